@@ -1,0 +1,33 @@
+"""FP64 CPU oracle for the hybrid LAD-GBR right-hand side (arxiv 2511.18042).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+execute this package: only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` use it.  It shares no code with the HIP
+library and does not import it.
+
+The oracle is a plain, slow, vectorised-numpy transcription of what the paper
+computes, in float64, step by step in the paper's order:
+
+* ``grid``         -- node layout, ghost layers and boundary images, grid metrics
+                      (governing equations, Sec. 2.1)
+* ``derivatives``  -- explicit E6 / E4 and compact (tridiagonal) C4 first
+                      derivatives of the primitives (Sec. 2.3, the MEG6 / MIG4
+                      gradients; Sec. 4.2 LAD-E4)
+* ``gbr``          -- characteristic transform, gradient-based linear interface
+                      states, centralised interpolation, MP5 limiter, the
+                      wave-appropriate selection rule, the Omega sensor and the
+                      curvilinear HLLC flux (Sec. 2.3)
+* ``lad``          -- localized artificial diffusivity coefficients, truncated
+                      Gaussian filter, central convective + viscous fluxes
+                      (Sec. 2.2, Eq. tauij)
+* ``rhs``          -- the three RHS forms (C-GBR, LAD, hybrid; Alg. 1-3), the
+                      CFL time step and SSP-RK3
+* ``riemann``      -- exact Riemann solver for the 1D shock-tube checks (Sec. 3.1)
+
+Where the paper is silent the oracle follows the numbered readings R1..R25 that
+are listed in the design notes; each function names the reading it relies on.
+
+Parity pins: every function is pinned by a ``-m "not gpu"`` test against a
+closed form, an invariant, brute force or a textbook value (tests/test_oracle_*.py).
+"""
+from . import grid, derivatives, gbr, lad, rhs, riemann  # noqa: F401

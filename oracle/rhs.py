@@ -1,0 +1,219 @@
+"""Stage right-hand sides, CFL time step and SSP-RK3 (oracle; test infrastructure only).
+
+Paper: Alg. 1 (LAD stage), Alg. 2 (C-GBR stage), Alg. 3 (hybrid: LAD unless
+troubled cells exist), Sec. 5 (the hybrid uses LAD-E4 with MEG6 and a density /
+pressure criterion for troubled cells; per-cell switching proposed as the
+efficient form), Sec. 2.3 (conservative finite difference: node derivative =
+difference of interface fluxes; third-order TVD Runge-Kutta).
+
+The stage RHS is  dQ/dt = -J sum_l (F_hat_{l,i+1/2} - F_hat_{l,i-1/2})  on interior
+nodes, with Q the physical conserved state (rho, rho u, rho v, rho w, E) and
+F_hat the contravariant fluxes of Eq. eq:3.1.1 (convective + viscous).
+
+Readings used here:
+  R8   dt = CFL / max_i sum_l (|xi_l . u| + c |xi_l|), xi_l = J l_hat, from U^n,
+       the last step clipped to t_end; no viscous limit.
+  R11  C-GBR viscous fluxes use the GBR gradients and the physical coefficients.
+  R12  per-cell hybrid: troubled flags f, dilated by a (2r+1)^ndim box (r = 3),
+       interface flag g_{i+1/2} = f~_i or f~_{i+1}; g selects the C-GBR interface
+       flux, otherwise the LAD flux.  The paper's global switch (any troubled
+       interior node -> C-GBR everywhere) is kept as mode 'global'.
+  R17  Shu-Osher SSP-RK3; flags re-evaluated every stage.
+  R18  no positivity fallback: rho <= 0, p <= 0 or a non-finite value after a
+       stage is reported (non-physical count).
+  R24  troubled if rho < rho_thr or p < p_thr (strict).
+"""
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import grid as gr
+from .derivatives import gradient
+from .gbr import gbr_interface_flux, omega_sensor, omega_bar
+from .lad import (lad_coefficients, lad_interface_flux, physical_gradients,
+                  physical_transport, viscous_node_flux)
+
+
+@dataclass
+class Gas:
+    gamma: float = 1.4
+    Re: float = 1.0
+    Pr: float = 0.72
+    Mref: float = 1.0
+    suth: float = 110.4 / 108.0
+    viscous: bool = False
+
+
+@dataclass
+class Opts:
+    grad: str = 'E6'              # 'E6' (MEG6) or 'C4' (MIG4)
+    cfl: float = 0.2
+    omega_thr: float = 0.01
+    mp_eps: float = 1e-20
+    mp_alpha: float = 4.0
+    C_mu: float = 0.0
+    C_beta: float = 1.75
+    C_kappa: float = 0.01
+    hybrid_mode: str = 'percell'  # 'percell' or 'global'
+    rho_thr: float = -1.0
+    p_thr: float = -1.0
+    dilate: int = 3
+
+
+def primitives(Q, gamma):
+    """(rho, u, v, w, p) from the conserved state (Sec. 2.1)."""
+    rho = Q[0]
+    u, v, w = Q[1] / rho, Q[2] / rho, Q[3] / rho
+    p = (gamma - 1.0) * (Q[4] - 0.5 * rho * (u * u + v * v + w * w))
+    return np.stack([rho, u, v, w, p])
+
+
+def troubled_flags(W, opts):
+    return (W[0] < opts.rho_thr) | (W[4] < opts.p_thr)
+
+
+def dilate(f, grid, r):
+    """Box dilation of a boolean field by r nodes in every active direction."""
+    out = f.copy()
+    for d in range(grid.ndim):
+        acc = out.copy()
+        for s in range(1, r + 1):
+            acc |= gr.shift(out, s, d, fill=False)
+            acc |= gr.shift(out, -s, d, fill=False)
+        out = acc
+    return out
+
+
+def interface_selectors(Q, W, grid, opts, scheme, force_flags=None):
+    """Per direction boolean arrays g (at node i for the interface i+1/2): True -> C-GBR.
+    ``force_flags`` (bool, field shape) replaces the troubled-cell criterion."""
+    shape = grid.shape
+    if scheme == 'cgbr':
+        return [np.ones(shape, bool) for _ in range(grid.ndim)], None
+    if scheme == 'lad':
+        return [np.zeros(shape, bool) for _ in range(grid.ndim)], None
+    f = troubled_flags(W, opts) if force_flags is None else force_flags.astype(bool)
+    if opts.hybrid_mode == 'global':
+        use = bool(f[grid.interior()].any())
+        return [np.full(shape, use) for _ in range(grid.ndim)], f
+    ft = dilate(f, grid, opts.dilate)
+    return [ft | gr.shift(ft, 1, d, fill=False) for d in range(grid.ndim)], f
+
+
+def rhs(Q, grid, gas, opts, scheme, M=None, info=None, force_flags=None):
+    """dQ/dt (5, Nz, Ny, Nx) on interior nodes (zero on ghosts) for scheme in
+    {'cgbr', 'lad', 'hybrid'}.  ``info`` (dict) receives diagnostics: the
+    troubled flags, the selectors and, for C-GBR interfaces, the smallest decision
+    margin per node (for excusing threshold flips)."""
+    gamma = gas.gamma
+    Q = Q.copy()
+    gr.fill_ghosts_conserved(Q, grid)
+    W = primitives(Q, gamma)
+    if M is None:
+        M = gr.node_metrics(grid)
+    sel, flags = interface_selectors(Q, W, grid, opts, scheme, force_flags)
+    need_gbr = any(s.any() for s in sel)
+    need_lad = any((~s).any() for s in sel)
+    mu_f, kappa_f = physical_transport(W, gas)
+
+    if need_gbr:
+        G = {l: np.stack([gradient(W[q], l, opts.grad, grid) for q in range(5)])
+             for l in range(grid.ndim)}
+        Dg = physical_gradients(G, M, grid)
+        Om = omega_sensor(W, Dg[1:4], grid)
+    if need_lad:
+        G4 = {l: np.stack([gradient(W[q], l, 'E4', grid) for q in range(5)])
+              for l in range(grid.ndim)}
+        coef = lad_coefficients(W, G4, M, grid, gas, opts)
+        if info is not None:
+            info['lad_coef'] = coef
+
+    L = np.zeros_like(Q)
+    inner = grid.interior()
+    margin = np.full(grid.shape, np.inf)
+    for d in range(grid.ndim):
+        F = np.zeros_like(Q)
+        if need_gbr:
+            rec = {} if info is not None else None
+            Fg = gbr_interface_flux(W, G[d], omega_bar(Om, d), M, d, gamma, opts.omega_thr,
+                                    opts.mp_eps, opts.mp_alpha, record=rec)
+            if gas.viscous:
+                Fv = viscous_node_flux(W, Dg, M, d, gas, mu_f, np.zeros_like(mu_f), kappa_f)
+                Fg = Fg + gr.i4(Fv, d)
+            if rec is not None:
+                m = np.where(sel[d], rec['margin'], np.inf)
+                margin = np.fmin(margin, np.fmin(m, gr.shift(m, -1, d, fill=np.inf)))
+            F = np.where(sel[d], Fg, F)
+        if need_lad:
+            Fl = lad_interface_flux(W, G4, M, d, grid, gas, coef, mu_f, kappa_f)
+            F = np.where(sel[d], F, Fl)
+        dF = F - gr.shift(F, -1, d)
+        L[(slice(None),) + inner] -= M[9][inner] * dF[(slice(None),) + inner]
+    if info is not None:
+        info['flags'] = flags
+        info['selectors'] = sel
+        info['margin'] = margin
+        info['W'] = W
+    return L
+
+
+def cfl_dt(Q, grid, gas, cfl, M=None):
+    """Convective CFL time step from the interior of Q (R8)."""
+    if M is None:
+        M = gr.node_metrics(grid)
+    inner = grid.interior()
+    W = primitives(Q[(slice(None),) + inner], gas.gamma)
+    Mi = M[(slice(None),) + inner]
+    c = np.sqrt(gas.gamma * W[4] / W[0])
+    s = np.zeros_like(c)
+    for l in range(grid.ndim):
+        xl = [Mi[9] * Mi[3 * l + j] for j in range(3)]
+        s = s + np.abs(xl[0] * W[1] + xl[1] * W[2] + xl[2] * W[3]) \
+            + c * np.sqrt(xl[0] ** 2 + xl[1] ** 2 + xl[2] ** 2)
+    return cfl / np.max(s)
+
+
+RK3_COEF = ((0.0, 1.0), (0.75, 0.25), (1.0 / 3.0, 2.0 / 3.0))
+
+
+def rk3_stage(Un, Us, dt, stage, grid, gas, opts, scheme, M=None, info=None, force_flags=None):
+    """U^{(s+1)} = a U^n + b (U^{(s)} + dt L(U^{(s)})) on interior nodes; ghosts copied from U^n."""
+    a, b = RK3_COEF[stage]
+    L = rhs(Us, grid, gas, opts, scheme, M, info, force_flags)
+    out = Un.copy()
+    inner = (slice(None),) + grid.interior()
+    out[inner] = a * Un[inner] + b * (Us[inner] + dt * L[inner])
+    return out
+
+
+def nonphysical_count(Q, grid, gamma):
+    inner = (slice(None),) + grid.interior()
+    W = primitives(Q[inner], gamma)
+    bad = (~np.isfinite(Q[inner]).all(axis=0)) | (W[0] <= 0.0) | (W[4] <= 0.0)
+    return int(bad.sum())
+
+
+def rk3_step(Q, t, t_end, grid, gas, opts, scheme, M=None):
+    """One SSP-RK3 step (R8, R17).  Returns (Q_new, t_new, dt, nonphysical_count)."""
+    if M is None:
+        M = gr.node_metrics(grid)
+    dt = min(cfl_dt(Q, grid, gas, opts.cfl, M), t_end - t)
+    bad = 0
+    U = Q
+    for s in range(3):
+        U = rk3_stage(Q, U, dt, s, grid, gas, opts, scheme, M)
+        bad += nonphysical_count(U, grid, gas.gamma)
+    return U, t + dt, dt, bad
+
+
+def run(Q, t_end, grid, gas, opts, scheme, max_steps=10 ** 9):
+    """March to t_end; returns (Q, steps, nonphysical_total)."""
+    M = gr.node_metrics(grid)
+    t = 0.0
+    steps = 0
+    bad = 0
+    while t < t_end and steps < max_steps:
+        Q, t, _, b = rk3_step(Q, t, t_end, grid, gas, opts, scheme, M)
+        bad += b
+        steps += 1
+    return Q, steps, bad

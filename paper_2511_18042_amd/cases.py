@@ -1,0 +1,250 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle checks.
+
+This module holds initial conditions and grids only -- none of the method's
+arithmetic -- and imports neither the HIP library nor the oracle.  States are the
+physical conserved variables Q = (rho, rho u, rho v, rho w, E) on the ghost-padded
+node layout (5, Nz, Ny, Nx), five ghost layers per active direction, cell-centred
+nodes.  Ghost values of boundaries marked FIXED are set here and never rewritten
+by either side; all other ghosts are left at the nearest interior value and are
+refilled by the boundary images at every stage.
+
+Workloads (shapes and value ranges of the paper's cases, Sec. 3):
+  sod            1D shock tube, Sec. 3.1
+  shu_osher      1D shock / entropy-wave interaction, Sec. 3.1
+  triple_point   2D three-state Riemann problem, Sec. 3.2
+  quadrants      2D four-quadrant Riemann problems with seeded random states
+  ramp3d         3D curvilinear compression-ramp grid with a turbulent-boundary-
+                 layer-like state (M 2.9, 24 degrees; Sec. 3.4 shapes)
+  wavy / random  smooth periodic test fields on sinusoidally perturbed grids
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+
+NG = 5
+PERIODIC, TRANSMISSIVE, REFLECTIVE, NOSLIP, FIXED = 0, 1, 2, 3, 4
+
+
+@dataclass
+class Case:
+    ndim: int
+    n: tuple                      # interior nodes (nx, ny, nz)
+    bc: list                      # [(lo, hi)] * 3
+    h: tuple = (1.0, 1.0, 1.0)    # Cartesian spacings
+    coords: object = None         # (3, Nz, Ny, Nx) for curvilinear grids
+    Q: object = None              # (5, Nz, Ny, Nx) conserved state incl. ghosts
+    gamma: float = 1.4
+    t_end: float = 0.0
+    x0: tuple = (0.0, 0.0, 0.0)
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def g(self):
+        return tuple(NG if d < self.ndim else 0 for d in range(3))
+
+    @property
+    def N(self):
+        return tuple(self.n[d] + 2 * self.g[d] for d in range(3))
+
+    @property
+    def shape(self):
+        N = self.N
+        return (N[2], N[1], N[0])
+
+    @property
+    def cells(self):
+        return int(self.n[0] * self.n[1] * self.n[2])
+
+
+def node_positions(n, g, x0, h):
+    """Cell-centred node coordinates including ghosts: x0 + (i + 1/2) h for i in [-g, n+g)."""
+    return x0 + (np.arange(-g, n + g) + 0.5) * h
+
+
+def cartesian_mesh(case):
+    """(x, y, z) node coordinates broadcast to the field shape."""
+    g = case.g
+    xs = [node_positions(case.n[d], g[d], case.x0[d], case.h[d]) for d in range(3)]
+    z, y, x = np.meshgrid(xs[2], xs[1], xs[0], indexing='ij')
+    return x, y, z
+
+
+def conserved(rho, u, v, w, p, gamma):
+    E = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
+    return np.stack([rho, rho * u, rho * v, rho * w, E]).astype(np.float64)
+
+
+def _pad3(n):
+    n = tuple(int(v) for v in n)
+    return n + (1,) * (3 - len(n))
+
+
+# ----------------------------------------------------------------- 1D cases
+def sod(n=400):
+    c = Case(1, _pad3((n,)), [(TRANSMISSIVE, TRANSMISSIVE)], h=(1.0 / n, 1.0, 1.0), t_end=0.2)
+    x, _, _ = cartesian_mesh(c)
+    left = x < 0.5
+    rho = np.where(left, 1.0, 0.125)
+    p = np.where(left, 1.0, 0.1)
+    z = np.zeros_like(x)
+    c.Q = conserved(rho, z, z, z, p, c.gamma)
+    c.extra = dict(left=(1.0, 0.0, 1.0), right=(0.125, 0.0, 0.1), x_interface=0.5)
+    return c
+
+
+SHU_OSHER_POST = (3.857143, 2.629369, 10.33333)
+
+
+def shu_osher(n=2000):
+    """Mach-3 shock at x = -4 entering rho = 1 + 0.2 sin(5x); left ghosts fixed at the post-shock state."""
+    c = Case(1, _pad3((n,)), [(FIXED, TRANSMISSIVE)], h=(10.0 / n, 1.0, 1.0),
+             x0=(-5.0, 0.0, 0.0), t_end=1.8)
+    x, _, _ = cartesian_mesh(c)
+    post = x < -4.0
+    rho = np.where(post, SHU_OSHER_POST[0], 1.0 + 0.2 * np.sin(5.0 * x))
+    u = np.where(post, SHU_OSHER_POST[1], 0.0)
+    p = np.where(post, SHU_OSHER_POST[2], 1.0)
+    z = np.zeros_like(x)
+    c.Q = conserved(rho, u, z, z, p, c.gamma)
+    return c
+
+
+# ----------------------------------------------------------------- 2D cases
+def triple_point(nx=1792, ny=768):
+    c = Case(2, _pad3((nx, ny)), [(REFLECTIVE, REFLECTIVE), (REFLECTIVE, REFLECTIVE)],
+             h=(7.0 / nx, 3.0 / ny, 1.0), t_end=5.0)
+    x, y, _ = cartesian_mesh(c)
+    rho = np.where(x < 1.0, 1.0, np.where(y < 1.5, 1.0, 0.125))
+    p = np.where(x < 1.0, 1.0, 0.1)
+    z = np.zeros_like(x)
+    c.Q = conserved(rho, z, z, z, p, c.gamma)
+    c.extra = dict(rho_thr=0.5 * 0.125, p_thr=-1.0)
+    return c
+
+
+def quadrant_states(rng):
+    """Four quadrant primitive states (rho, u, v, p) drawn from the configured ranges."""
+    st = []
+    for _ in range(4):
+        st.append((rng.uniform(0.1, 2.0), rng.uniform(-1.0, 1.0), rng.uniform(-1.0, 1.0),
+                   rng.uniform(0.1, 2.0)))
+    return st
+
+
+def quadrants(n, states, split=(0.5, 0.5)):
+    """2D four-quadrant Riemann problem on [0,1]^2, transmissive boundaries.
+    Quadrant order: (x>=sx, y>=sy), (x<sx, y>=sy), (x<sx, y<sy), (x>=sx, y<sy)."""
+    c = Case(2, _pad3((n, n)), [(TRANSMISSIVE, TRANSMISSIVE)] * 2, h=(1.0 / n, 1.0 / n, 1.0))
+    x, y, _ = cartesian_mesh(c)
+    sx, sy = split
+    q = np.where(x >= sx, np.where(y >= sy, 0, 3), np.where(y >= sy, 1, 2))
+    arr = np.array(states, dtype=np.float64)
+    rho, u, v, p = (arr[q, m] for m in range(4))
+    c.Q = conserved(rho, u, v, np.zeros_like(rho), p, c.gamma)
+    c.extra = dict(rho_thr=0.5 * arr[:, 0].min(), p_thr=0.5 * arr[:, 3].min())
+    return c
+
+
+BATCH_SEED = 18042
+
+
+def batch64(count=64, sizes=(128, 256, 512, 1024), seed=BATCH_SEED, scale=1):
+    """The batched serving workload: ``count`` four-quadrant problems with sizes drawn from
+    ``sizes`` and per-quadrant states from the same generator.  ``scale`` divides every size
+    (used for small test versions of the same draw)."""
+    rng = np.random.default_rng(seed)
+    ns = rng.choice(np.array(sizes), count)
+    out = []
+    for n in ns:
+        st = quadrant_states(rng)
+        out.append(quadrants(max(8, int(n) // scale), st))
+    return out
+
+
+# ----------------------------------------------------------------- test fields
+def wavy_coords(ndim, n, amp=0.1, g=NG):
+    """Sinusoidally perturbed periodic grid on the unit square/cube:
+    x_m = xi_m + amp prod_k sin(2 pi xi_k) (cell-centred xi)."""
+    gs = [g if d < ndim else 0 for d in range(3)]
+    n = _pad3(n)
+    xi = [node_positions(n[d], gs[d], 0.0, 1.0 / n[d]) if d < ndim else np.zeros(1) for d in range(3)]
+    Z, Y, X = np.meshgrid(xi[2], xi[1], xi[0], indexing='ij')
+    base = [X, Y, Z]
+    prod = np.ones_like(X)
+    for d in range(ndim):
+        prod = prod * np.sin(2.0 * np.pi * base[d])
+    coords = np.stack([base[d] + amp * prod if d < ndim else base[d] for d in range(3)])
+    return coords
+
+
+def periodic_case(ndim, n, curvilinear=False, amp=0.1):
+    n = _pad3(n)
+    bc = [(PERIODIC, PERIODIC)] * ndim
+    h = tuple(1.0 / n[d] if d < ndim else 1.0 for d in range(3))
+    c = Case(ndim, n, bc, h=h)
+    if curvilinear:
+        c.coords = wavy_coords(ndim, n, amp)
+    return c
+
+
+def uniform_state(case, rho=1.0, u=0.5, v=0.3, w=0.2, p=1.0 / 1.4):
+    shape = case.shape
+    f = lambda a: np.full(shape, float(a))  # noqa: E731
+    vv = v if case.ndim >= 2 else 0.0
+    ww = w if case.ndim >= 3 else 0.0
+    case.Q = conserved(f(rho), f(u), f(vv), f(ww), f(p), case.gamma)
+    return case
+
+
+def random_smooth_state(case, seed, amp=0.2, modes=3):
+    """Smooth periodic random primitives (positive rho, p) on a periodic case."""
+    rng = np.random.default_rng(seed)
+    if case.coords is not None:
+        X = [case.coords[d] for d in range(3)]
+    else:
+        X = list(cartesian_mesh(case))
+    def field_(base, a):
+        f = np.full(case.shape, base)
+        for _ in range(modes):
+            k = rng.integers(1, 4, size=3)
+            ph = rng.uniform(0, 2 * np.pi)
+            arg = ph + sum(2 * np.pi * k[d] * X[d] / (case.n[d] * case.h[d]) for d in range(case.ndim))
+            f = f + a * rng.uniform(-1, 1) * np.sin(arg)
+        return f
+    rho = field_(1.0, amp)
+    u = field_(0.3, amp)
+    v = field_(-0.2, amp) if case.ndim >= 2 else np.zeros(case.shape)
+    w = field_(0.1, amp) if case.ndim >= 3 else np.zeros(case.shape)
+    p = field_(1.0, amp)
+    case.Q = conserved(rho, u, v, w, p, case.gamma)
+    return case
+
+
+def random_rough_state(case, seed, jumps=True):
+    """Random piecewise-smooth data with discontinuities: exercises limiter branches."""
+    rng = np.random.default_rng(seed)
+    shape = case.shape
+    def fld(lo, hi):
+        f = rng.uniform(lo, hi, size=shape)
+        if jumps:
+            blocks = rng.uniform(lo, hi, size=(4,) * 3)
+            idx = [np.minimum((np.arange(s) * 4) // max(s, 1), 3) for s in shape]
+            f = 0.7 * blocks[np.ix_(*idx)] + 0.3 * f
+        return f
+    rho = fld(0.3, 2.0)
+    u = fld(-1.0, 1.0)
+    v = fld(-1.0, 1.0) if case.ndim >= 2 else np.zeros(shape)
+    w = fld(-1.0, 1.0) if case.ndim >= 3 else np.zeros(shape)
+    p = fld(0.3, 2.0)
+    case.Q = conserved(rho, u, v, w, p, case.gamma)
+    return case
+
+
+def entropy_wave(n, t=0.0):
+    """rho = 1 + 0.2 sin(2 pi (x - t)), u = 1, p = 1 on a periodic unit interval."""
+    c = Case(1, _pad3((n,)), [(PERIODIC, PERIODIC)], h=(1.0 / n, 1.0, 1.0))
+    x, _, _ = cartesian_mesh(c)
+    rho = 1.0 + 0.2 * np.sin(2 * np.pi * (x - t))
+    one = np.ones_like(x)
+    c.Q = conserved(rho, one, 0 * one, 0 * one, one, c.gamma)
+    return c
