@@ -19,9 +19,13 @@ Readings used here:
   R5  frozen state = arithmetic mean of nodes i and i+1; basis n = xi~/|xi~|,
       t1 = normalise(n x e_m) with m = argmin |n_m| (lowest index on ties),
       t2 = n x t1.
-  R7  Omega = (pressure switch) x (Ducros ratio with eps = 1e-32); the over-bar is
-      the maximum over the node and its two neighbours along the sweep; the left
-      state uses node i, the right state node i+1; strict "> 0.01".
+  R7  Omega = (pressure switch) x (Ducros ratio); the over-bar is the maximum over
+      the node and its two neighbours along the sweep; the left state uses node i,
+      the right state node i+1; strict "> 0.01".  The Ducros ratio is regularised
+      as (theta^2 + eps) / (theta^2 + |omega|^2 + eps), eps = 1e-32, so that where
+      the flow has neither dilatation nor vorticity (a pressure jump at rest) the
+      pressure switch alone decides; with eps only in the denominator such a jump
+      is never detected and the unlimited acoustic states go negative.
   R16 HLLC star flux F*_K = F_K + S_K (Q*_K - Q_K), |xi~| restored on the Roe
       wave speeds, E^K in the star state read as specific total energy.
 """
@@ -198,7 +202,7 @@ def omega_sensor(W, dudx, grid):
     w2 = dudx[0][2] - dudx[2][0]
     w3 = dudx[1][0] - dudx[0][1]
     om2 = w1 * w1 + w2 * w2 + w3 * w3
-    return phi * (theta * theta / (theta * theta + om2 + 1e-32))
+    return phi * ((theta * theta + 1e-32) / (theta * theta + om2 + 1e-32))
 
 
 def omega_bar(Om, d):
@@ -264,4 +268,6 @@ def gbr_interface_flux(W, G, Ob, M, d, gamma, omega_thr=0.01, mp_eps=1e-20, mp_a
 
     WL = from_characteristic(CL, n, t1, t2, rb, cb)
     WR = from_characteristic(CR, n, t1, t2, rb, cb)
+    if record is not None:
+        record['WL'], record['WR'] = WL, WR
     return hllc(WL, WR, xt, gamma)

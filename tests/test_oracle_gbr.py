@@ -187,3 +187,27 @@ def test_minmod_and_median():
     assert np.array_equal(gbr.minmod(a, b), [1.0, -1.0, 0.0, 0.0])
     assert gbr.minmod4(np.array(2.0), np.array(3.0), np.array(1.0), np.array(4.0)) == 1.0
     assert gbr.minmod4(np.array(2.0), np.array(-3.0), np.array(1.0), np.array(4.0)) == 0.0
+
+
+def test_sensor_detects_pressure_jump_at_rest_and_states_stay_positive():
+    """A pressure discontinuity in a fluid at rest (theta = omega = 0) is detected by the
+    Omega sensor (pressure switch alone), so the acoustic states are MP5-limited and the
+    interface pressures stay positive (Sod and triple-point initial data)."""
+    from oracle import grid as gr, rhs as R, derivatives as D
+    from paper_2511_18042_amd import cases
+    for c in (cases.sod(100), cases.triple_point(112, 48)):
+        g = gr.Grid(c.ndim, c.n, c.bc, c.h)
+        Q = c.Q.copy()
+        gr.fill_ghosts_conserved(Q, g)
+        W = R.primitives(Q, 1.4)
+        M = gr.node_metrics(g)
+        Gd = {l: np.stack([D.e6(W[q], l) for q in range(5)]) for l in range(g.ndim)}
+        Dg = __import__('oracle.lad', fromlist=['x']).physical_gradients(Gd, M, g)
+        Om = gbr.omega_sensor(W, Dg[1:4], g)
+        assert np.nanmax(Om[g.interior()]) > 0.1
+        for d in range(g.ndim):
+            rec = {}
+            F = gbr.gbr_interface_flux(W, Gd[d], gbr.omega_bar(Om, d), M, d, 1.4, record=rec)
+            band = g.band(-1, 0)
+            assert np.isfinite(F[(slice(None),) + band]).all()
+            assert rec['WL'][4][band].min() > 0 and rec['WR'][4][band].min() > 0
