@@ -1,0 +1,177 @@
+/*
+ * lgbr.h -- C ABI of the MI355X hybrid LAD-GBR right-hand-side library (liblgbr.so).
+ *
+ * Method: arxiv 2511.18042 (Kumar, Saini, Vadlamani, Chamarthi), "Assessment of
+ * gradient-based reconstruction and artificial diffusivity methods in simulating
+ * high-speed compressible flows".  The library evaluates the per-Runge-Kutta-stage
+ * right-hand side of the compressible Navier-Stokes equations in generalised
+ * curvilinear coordinates (Sec. 2.1, Eq. eq:3.1.1 and Eq. tauij) in three forms:
+ *   - C-GBR  (Sec. 2.3): centralised gradient-based reconstruction of the
+ *     characteristic primitives from explicit sixth-order (MEG6) or compact
+ *     fourth-order (MIG4) gradients, MP5 limiting with the wave-appropriate Omega
+ *     sensor, curvilinear HLLC fluxes;
+ *   - LAD    (Sec. 2.2, Sec. 5): fourth-order explicit central differences (LAD-E4)
+ *     with localized artificial shear / bulk viscosity and conductivity;
+ *   - hybrid (Alg. 3, Sec. 5): a troubled-cell flag selects the C-GBR interface flux,
+ *     the LAD flux elsewhere (per-cell form), or C-GBR for the whole field when any
+ *     interior cell is troubled (the paper's global form);
+ * and advances it with the third-order TVD (SSP) Runge-Kutta scheme.
+ *
+ * Conventions shared by every entry point
+ *  - All array arguments are DEVICE pointers owned by the caller; the library never
+ *    frees them and never keeps them beyond the call, except where stated (batches).
+ *  - Node layout: a field is stored on the ghost-padded node grid of one problem,
+ *    i fastest: index = i + N0 * (j + N1 * k) with N_d = n_d + 2 * 5 for the active
+ *    directions d < ndim and N_d = 1 for inactive ones.  Nodes are cell centres.
+ *    A stack of fields is field-major: field q at [q * N0 N1 N2 + index].
+ *  - Q is the physical conserved state (rho, rho u, rho v, rho w, E), FP64, [5][N].
+ *    Its ghost layers are rewritten by every call (boundary images), except on
+ *    boundaries marked LG_BC_FIXED, whose ghost values the caller owns.
+ *  - dQdt receives dQ/dt = -J sum_l (F_{l,i+1/2} - F_{l,i-1/2}) on interior nodes,
+ *    FP64, [5][N]; its ghost entries are not written.
+ *  - Work is enqueued on the context's HIP stream; no call synchronises the host
+ *    except lg_poll_status and lg_create / lg_destroy / lg_batch_create.
+ *  - Errors: invalid arguments return LG_EINVAL before anything is enqueued; HIP
+ *    launch or allocation failures return LG_EHIP / LG_ENOMEM.  Non-physical states
+ *    (rho <= 0, p <= 0 or not finite after an RK stage, the paper's "abrupt
+ *    divergence" of Sec. 3.4) are counted on the device and reported by
+ *    lg_poll_status as LG_ENONPHYS.
+ */
+#ifndef LGBR_H
+#define LGBR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LG_OK = 0,
+  LG_EINVAL = -1,
+  LG_ENOMEM = -2,
+  LG_EHIP = -3,
+  LG_ENONPHYS = -4,
+  LG_EUNSUPPORTED = -5
+} lg_status;
+
+/* boundary conditions (the per-case boundary treatments of Sec. 3) */
+enum {
+  LG_BC_PERIODIC = 0,          /* periodic images                                      */
+  LG_BC_TRANSMISSIVE = 1,      /* zeroth-order extrapolation ("extrapolated outflow")  */
+  LG_BC_REFLECTIVE = 2,        /* mirror, normal momentum negated (inviscid wall)      */
+  LG_BC_NOSLIP_ADIABATIC = 3,  /* mirror, all momentum negated (no-slip adiabatic wall)*/
+  LG_BC_FIXED = 4              /* ghosts owned by the caller (inflow at the IC state)  */
+};
+enum { LG_GRAD_E6 = 0, LG_GRAD_C4 = 1 };          /* MEG6 / MIG4 gradients (Sec. 2.3)   */
+enum { LG_FP64 = 0, LG_MIXED = 1 };               /* FP64 everywhere / FP32 bulk math   */
+enum { LG_HYB_PERCELL = 0, LG_HYB_GLOBAL = 1 };   /* hybrid selection (Sec. 5, Alg. 3)   */
+enum { LG_SCHEME_CGBR = 0, LG_SCHEME_LAD = 1, LG_SCHEME_HYBRID = 2 };
+
+typedef struct {
+  int ndim;            /* 1, 2 or 3 active directions                                 */
+  int n[3];            /* interior nodes per direction; 1 for inactive directions     */
+  int ng;              /* ghost layers per active direction; must be 5               */
+  int bc[3][2];        /* LG_BC_* for the low / high side of every active direction   */
+  int curvilinear;     /* 0: Cartesian, spacings h; 1: node metrics + coordinates    */
+  double h[3];         /* Cartesian node spacings (unused when curvilinear)          */
+} lg_grid;
+
+typedef struct {       /* non-dimensional gas model (Sec. 2.1)                        */
+  double gamma;        /* ratio of specific heats                                     */
+  double Re;           /* Reynolds number: mu_hat = mu / Re                           */
+  double Pr;           /* Prandtl number                                              */
+  double Mref;         /* reference Mach number: p = rho T / (gamma Mref^2)           */
+  double suth;         /* Sutherland constant S / T_ref                               */
+  int viscous;         /* 0: inviscid (no physical viscosity or conduction)           */
+} lg_gas;
+
+typedef struct {
+  int grad;            /* LG_GRAD_E6 or LG_GRAD_C4                                     */
+  int precision;       /* LG_FP64 or LG_MIXED (FP32 reconstruction, limiter, sensor,
+                          HLLC and LAD; FP64 state, RK combination, compact solves and
+                          flux differences)                                           */
+  double cfl;          /* CFL number of the time step (Sec. 3: 0.2)                   */
+  double omega_thr;    /* Omega sensor threshold (Sec. 2.3: 0.01)                     */
+  double mp_eps;       /* MP criterion threshold (Sec. 2.3: 1e-20)                    */
+  double mp_alpha;     /* MP5 alpha (4)                                               */
+  double C_mu, C_beta, C_kappa;  /* LAD constants (Sec. 2.2: 0.002, 1.75, 0.01; the
+                          paper's runs use C_mu = 0)                                   */
+  int hybrid_mode;     /* LG_HYB_PERCELL or LG_HYB_GLOBAL                              */
+  double rho_thr;      /* troubled if rho < rho_thr (Sec. 5; negative: never)         */
+  double p_thr;        /* troubled if p < p_thr (Sec. 5; negative: never)             */
+  int dilate;          /* troubled-flag dilation radius of the per-cell hybrid (3)    */
+  int seg;             /* nodes per lane in the strided sweeps (0: default)           */
+} lg_opts;
+
+typedef struct lg_ctx lg_ctx;
+typedef struct lg_batch lg_batch;
+
+/* Optional allocator for workspaces (e.g. a framework's caching allocator).
+ * alloc(bytes, user) returns device memory or NULL; free_(ptr, user) releases it.
+ * Passing NULL functions restores hipMalloc / hipFree.  Affects later lg_create calls. */
+lg_status lg_set_allocator(void* (*alloc)(size_t, void*), void (*free_)(void*, void*), void* user);
+
+/* Create a context for one grid.  node_metrics: device [10][N] FP64 metrics
+ * (xi_x, xi_y, xi_z, eta_x, .., zeta_z)/J and J (Sec. 2.1), required when
+ * grid->curvilinear, else NULL.  coords: device [3][N] FP64 node coordinates, required
+ * when curvilinear (LAD length scales, Sec. 2.2), else NULL.  Both must stay valid for
+ * the life of the context.  stream: a hipStream_t (NULL = default stream).
+ * Allocates the context's workspace. */
+lg_status lg_create(lg_ctx** ctx, const lg_grid* grid, const double* node_metrics, const double* coords,
+                    const lg_gas* gas, const lg_opts* opts, void* stream);
+void lg_destroy(lg_ctx* ctx);
+size_t lg_workspace_bytes(const lg_ctx* ctx);
+
+/* Conservative node metrics from node coordinates (Sec. 2.1; fourth-order central
+ * differences as the outer operator so that the discrete metric identities hold).
+ * coords [3][N] -> node_metrics [10][N]; values are defined on nodes at least two
+ * nodes inside the padded grid.  Allocates and frees a temporary [9][N] buffer. */
+lg_status lg_metrics_from_coords(const lg_grid* grid, const double* coords, double* node_metrics,
+                                 void* stream);
+
+/* dQdt = C-GBR right-hand side of Q (Sec. 2.3, Alg. 2). */
+lg_status cgbr_rhs(lg_ctx* ctx, double* Q, double* dQdt);
+/* dQdt = LAD-E4 right-hand side of Q (Sec. 2.2, Alg. 1 without the filter). */
+lg_status lad_rhs(lg_ctx* ctx, double* Q, double* dQdt);
+/* dQdt = hybrid right-hand side of Q (Alg. 3, Sec. 5).  flags_in (nullable, uint8 [N])
+ * replaces the troubled-cell criterion; flags_out (nullable, uint8 [N]) receives the
+ * troubled flags that were used. */
+lg_status hybrid_rhs(lg_ctx* ctx, double* Q, double* dQdt, const uint8_t* flags_in, uint8_t* flags_out);
+
+/* One SSP-RK3 step of scheme LG_SCHEME_* on Q in place.  The step size is
+ * dt = cfl / max_i sum_l (|xi_l . u| + c |xi_l|) from Q, clipped so that t does not
+ * pass t_end; t_inout is a device double that is advanced by dt.  dt stays on the
+ * device (no host synchronisation). */
+lg_status rk3_step(lg_ctx* ctx, int scheme, double* Q, double t_end, double* t_inout);
+
+/* One RK3 stage from given states (for per-stage checks):
+ * Us <- a Un + b (Us + dt L(Us)) on interior nodes, with (a, b) = (0, 1), (3/4, 1/4),
+ * (1/3, 2/3) for stage 0, 1, 2; ghosts of Us <- ghosts of Un. */
+lg_status lg_rk3_stage(lg_ctx* ctx, int scheme, int stage, const double* Un, double* Us, double dt);
+
+/* dt_out (device double) = cfl / max spectral radius of Q (no clipping). */
+lg_status lg_compute_dt(lg_ctx* ctx, const double* Q, double* dt_out);
+
+/* Batch of independent problems advanced together: every kernel of a step is one
+ * launch over all problems, and nsteps RK3 steps are captured into one HIP graph.
+ * All contexts must share ndim, precision, gradient kind, hybrid mode, viscosity and
+ * stream.  Q[i] / t[i] are device pointers (state and time of problem i) that must stay
+ * valid for the life of the batch; t_end[i] are the end times. */
+lg_status lg_batch_create(lg_batch** batch, lg_ctx* const* ctxs, double* const* Q, double* const* t,
+                          const double* t_end, int n, int nsteps, int scheme);
+lg_status lg_batch_run(lg_batch* batch);      /* one graph launch = nsteps RK3 steps     */
+void lg_batch_destroy(lg_batch* batch);
+
+/* Synchronises the context's stream and reads its non-physical node count since the
+ * last poll (then resets it).  Returns LG_ENONPHYS when the count is non-zero. */
+lg_status lg_poll_status(lg_ctx* ctx, int* nonphys_count);
+
+const char* lg_strerror(lg_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LGBR_H */

@@ -1,0 +1,401 @@
+// Ghost images, primitives, troubled flags, RK3 stage combination, CFL time step,
+// flag dilation and grid metrics.
+//
+// Paper: Sec. 2.1 (primitives, metrics xi_hat = xi_x / J), Alg. 1-2 (SET_BCS,
+// SET_PRIMITIVES, NETFLUX_LOOP), Alg. 3 / Sec. 5 (troubled cells: density or pressure
+// below a threshold), third-order TVD Runge-Kutta (Sec. 2.1, 2.3), CFL 0.2 (Sec. 3).
+#include "lgbr_dev.h"
+#include "lgbr_kernels.h"
+
+namespace lg {
+
+// ------------------------------------------------------------------ ghost images
+// Ghost layers of direction d: periodic images, zeroth-order copies, or mirrors
+// (normal momentum negated at reflective walls, all momentum at no-slip adiabatic
+// walls); FIXED ghosts belong to the caller.  Ghost layers are filled over the full
+// extent of the other two directions, direction by direction, so corners are set.
+__device__ __forceinline__ bool ghost_src(int bct, int side, int m, int g, int n, int& dst, int& src) {
+  if (bct == BC_FIXED) return false;
+  dst = side == 0 ? g - 1 - m : g + n + m;
+  if (bct == BC_PERIODIC) src = side == 0 ? dst + n : dst - n;
+  else if (bct == BC_TRANSMISSIVE) src = side == 0 ? g : g + n - 1;
+  else src = side == 0 ? g + m : g + n - 1 - m;
+  return true;
+}
+
+__global__ void __launch_bounds__(256) k_bc_cons(const Prob* probs, StateRef ref, int d) {
+  const Prob& P = probs[blockIdx.y];
+  if (d >= P.ndim) return;
+  double* Q = ref.state(P);
+  const int g = P.g[d], n = P.n[d];
+  const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+  const int N1 = P.N[o1], N2 = P.N[o2];
+  const int cnt = 2 * g * N1 * N2;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x) {
+    int a = t % N1, r = t / N1;
+    int b = r % N2;
+    r /= N2;
+    int m = r % g, side = r / g;
+    int bct = P.bc[d][side];
+    int dst, src;
+    if (!ghost_src(bct, side, m, g, n, dst, src)) continue;
+    int base = a * P.s[o1] + b * P.s[o2];
+    size_t id = base + dst * P.s[d], is = base + src * P.s[d];
+    for (int q = 0; q < 5; ++q) {
+      double v = Q[q * (size_t)P.total + is];
+      if (bct == BC_REFLECTIVE && q == 1 + d) v = -v;
+      if (bct == BC_NOSLIP && q >= 1 && q <= 3) v = -v;
+      Q[q * (size_t)P.total + id] = v;
+    }
+  }
+}
+
+// Scalar intermediate fields: same images with even parity; FIXED -> nearest copy.
+template <typename R>
+__global__ void __launch_bounds__(256) k_bc_scalar(const Prob* probs, int which, int nf, int d) {
+  const Prob& P = probs[blockIdx.y];
+  if (d >= P.ndim) return;
+  R* F = static_cast<R*>(which == 0 ? P.CA : P.CB);
+  const int g = P.g[d], n = P.n[d];
+  const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+  const int N1 = P.N[o1], N2 = P.N[o2];
+  const int cnt = 2 * g * N1 * N2;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x) {
+    int a = t % N1, r = t / N1;
+    int b = r % N2;
+    r /= N2;
+    int m = r % g, side = r / g;
+    int bct = P.bc[d][side];
+    if (bct == BC_FIXED) bct = BC_TRANSMISSIVE;
+    int dst, src;
+    ghost_src(bct, side, m, g, n, dst, src);
+    int base = a * P.s[o1] + b * P.s[o2];
+    size_t id = base + dst * P.s[d], is = base + src * P.s[d];
+    for (int q = 0; q < nf; ++q) F[q * (size_t)P.total + id] = F[q * (size_t)P.total + is];
+  }
+}
+
+// ------------------------------------------------------------------ primitives + flags
+template <typename R>
+__global__ void __launch_bounds__(256) k_prim(const Prob* probs, StateRef ref, int want_flags,
+                                              const uint8_t* force) {
+  const Prob& P = probs[blockIdx.y];
+  const double* Q = ref.state(P);
+  R* W = static_cast<R*>(P.W);
+  const size_t T = P.total;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < P.total; idx += gridDim.x * blockDim.x) {
+    double rho = Q[idx];
+    double u = Q[T + idx] / rho, v = Q[2 * T + idx] / rho, w = Q[3 * T + idx] / rho;
+    double p = (P.gamma - 1.0) * (Q[4 * T + idx] - 0.5 * rho * (u * u + v * v + w * w));
+    W[idx] = (R)rho;
+    W[T + idx] = (R)u;
+    W[2 * T + idx] = (R)v;
+    W[3 * T + idx] = (R)w;
+    W[4 * T + idx] = (R)p;
+    if (want_flags) {
+      uint8_t f = force ? (uint8_t)(force[idx] != 0) : (uint8_t)((rho < P.rho_thr) || (p < P.p_thr));
+      P.f[idx] = f;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ global hybrid switch
+__global__ void __launch_bounds__(256) k_any_flag(const Prob* probs) {
+  const Prob& P = probs[blockIdx.y];
+  const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
+  const int cnt = n0 * n1 * n2;
+  int found = 0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x) {
+    int i = t % n0, r = t / n0;
+    int j = r % n1, k = r / n1;
+    if (P.f[pos_to_idx(P, i + P.g[0], j + P.g[1], k + P.g[2])]) found = 1;
+  }
+  if (__any(found) && (threadIdx.x & 63) == 0) atomicOr(P.any_flag, 1);
+}
+
+// Separable box dilation by P.dilate nodes along direction d.
+// src/dst: 0 = f, 1 = ftmp, 2 = ft.
+__global__ void __launch_bounds__(256) k_dilate(const Prob* probs, int d, int src, int dst) {
+  const Prob& P = probs[blockIdx.y];
+  if (d >= P.ndim) return;
+  const uint8_t* in = src == 0 ? P.f : (src == 1 ? P.ftmp : P.ft);
+  uint8_t* out = dst == 0 ? P.f : (dst == 1 ? P.ftmp : P.ft);
+  const int r = P.dilate, Nd = P.N[d], sd = P.s[d];
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < P.total; idx += gridDim.x * blockDim.x) {
+    int c = (idx / sd) % Nd;
+    uint8_t acc = 0;
+    for (int s = -r; s <= r; ++s) {
+      int cc = c + s;
+      if (cc >= 0 && cc < Nd) acc |= in[idx + s * sd];
+    }
+    out[idx] = acc;
+  }
+}
+
+// ------------------------------------------------------------------ RK3 combination
+// out = a U^n + b (U^s + dt L) on interior nodes, out = U^n on ghost nodes; counts
+// non-physical interior results (rho <= 0, p <= 0 or not finite).
+__global__ void __launch_bounds__(256) k_combine(const Prob* probs, RKRef rr, int stage, double a, double b) {
+  const Prob& P = probs[blockIdx.y];
+  const double* Un = rr.Un ? rr.Un : P.Q;
+  const double* Us = rr.Us ? rr.Us : (stage == 0 ? Un : P.Us);
+  double* out = rr.out ? rr.out : (stage == 2 ? const_cast<double*>(Un) : P.Us);
+  const bool in_place_n = out == Un;
+  const double* L = P.dQ;
+  const double dt = *P.dt;
+  const size_t T = P.total;
+  int bad = 0;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < P.total; idx += gridDim.x * blockDim.x) {
+    int i = idx % P.N[0], r = idx / P.N[0];
+    int j = r % P.N[1], k = r / P.N[1];
+    bool inner = i >= P.g[0] && i < P.g[0] + P.n[0] && j >= P.g[1] && j < P.g[1] + P.n[1] &&
+                 k >= P.g[2] && k < P.g[2] + P.n[2];
+    double v[5];
+    for (int q = 0; q < 5; ++q) {
+      size_t o = q * T + idx;
+      v[q] = inner ? a * Un[o] + b * (Us[o] + dt * L[o]) : Un[o];
+      if (!in_place_n || inner) out[o] = v[q];
+    }
+    if (inner) {
+      double rho = v[0];
+      double ke = 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / rho;
+      double p = (P.gamma - 1.0) * (v[4] - ke);
+      bool ok = rho > 0.0 && p > 0.0 && isfinite(rho) && isfinite(p) && isfinite(v[1]) &&
+                isfinite(v[2]) && isfinite(v[3]);
+      if (!ok) ++bad;
+    }
+  }
+  // one atomic per wave
+  for (int off = 32; off > 0; off >>= 1) bad += __shfl_down(bad, off);
+  if ((threadIdx.x & 63) == 0 && bad) atomicAdd(P.status, bad);
+}
+
+// ------------------------------------------------------------------ CFL time step
+// Spectral radius sum_l (|xi_l . u| + c |xi_l|) with xi_l = J l_hat, max over the
+// interior; kept as the bit pattern of a positive double so that an integer max works.
+__global__ void __launch_bounds__(256) k_dt_reduce(const Prob* probs, const double* Qx) {
+  const Prob& P = probs[blockIdx.y];
+  const double* Q = Qx ? Qx : P.Q;
+  const size_t T = P.total;
+  const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
+  const int cnt = n0 * n1 * n2;
+  double smax = 0.0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x) {
+    int i = t % n0, r = t / n0;
+    int j = r % n1, k = r / n1;
+    int idx = pos_to_idx(P, i + P.g[0], j + P.g[1], k + P.g[2]);
+    double rho = Q[idx];
+    double u = Q[T + idx] / rho, v = Q[2 * T + idx] / rho, w = Q[3 * T + idx] / rho;
+    double p = (P.gamma - 1.0) * (Q[4 * T + idx] - 0.5 * rho * (u * u + v * v + w * w));
+    double c = sqrt(P.gamma * p / rho);
+    double J = met64(P, 9, idx);
+    double s = 0.0;
+    for (int l = 0; l < P.ndim; ++l) {
+      double x0 = J * met64(P, 3 * l, idx), x1 = J * met64(P, 3 * l + 1, idx),
+             x2 = J * met64(P, 3 * l + 2, idx);
+      s += fabs(x0 * u + x1 * v + x2 * w) + c * sqrt(x0 * x0 + x1 * x1 + x2 * x2);
+    }
+    if (!(s <= smax)) smax = s;  // NaN propagates as "larger"
+  }
+  for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_down(smax, off));
+  if ((threadIdx.x & 63) == 0)
+    atomicMax(P.smax, (unsigned long long)__double_as_longlong(smax));
+}
+
+__global__ void k_dt_reset(const Prob* probs) {
+  const Prob& P = probs[blockIdx.y];
+  if (threadIdx.x == 0) *P.smax = 0ull;
+}
+
+__global__ void k_dt_finalize(const Prob* probs, double* tx, double t_end, int advance_t) {
+  const Prob& P = probs[blockIdx.y];
+  if (threadIdx.x != 0) return;
+  double smax = __longlong_as_double((long long)*P.smax);
+  double dt = P.cfl / smax;
+  if (advance_t) {
+    double* t = tx ? tx : P.t;
+    double te = tx ? t_end : P.t_end;
+    double rem = te - *t;
+    if (dt > rem) dt = rem;
+    if (!(dt > 0.0)) dt = 0.0;
+    *t = *t + dt;
+  }
+  *P.dt = dt;
+}
+
+__global__ void k_set_dt(const Prob* probs, double dt) {
+  const Prob& P = probs[blockIdx.y];
+  if (threadIdx.x == 0) *P.dt = dt;
+}
+
+__global__ void k_zero_status(const Prob* probs) {
+  const Prob& P = probs[blockIdx.y];
+  if (threadIdx.x == 0) *P.status = 0;
+}
+
+__global__ void k_zero_any(const Prob* probs) {
+  const Prob& P = probs[blockIdx.y];
+  if (threadIdx.x == 0) *P.any_flag = 0;
+}
+
+// ------------------------------------------------------------------ metrics from coordinates
+// Conservative node metrics with the fourth-order central difference D4 as the outer
+// operator (2D: xi_hat = (y_eta, -x_eta), eta_hat = (-y_xi, x_xi); 3D: xi_hat_x =
+// (y_eta z)_zeta - (y_zeta z)_eta and cyclic), J = 1 / det of the D4 coordinate Jacobian.
+__device__ __forceinline__ double d4at(const double* f, int idx, int s) {
+  return (8.0 * (f[idx + s] - f[idx - s]) - (f[idx + 2 * s] - f[idx - 2 * s])) / 12.0;
+}
+
+__global__ void __launch_bounds__(256) k_metric_inner(int ndim, int N0, int N1, int N2, const double* X,
+                                                      double* D) {
+  // D[3*c + l] = D4_l(coord c) where the stencil fits, 0 elsewhere
+  const int total = N0 * N1 * N2;
+  const int Ns[3] = {N0, N1, N2}, ss[3] = {1, N0, N0 * N1};
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
+    int p[3] = {idx % N0, (idx / N0) % N1, idx / (N0 * N1)};
+    for (int c = 0; c < 3; ++c)
+      for (int l = 0; l < 3; ++l) {
+        double v = 0.0;
+        if (l < ndim && p[l] >= 2 && p[l] < Ns[l] - 2) v = d4at(X + (size_t)c * total, idx, ss[l]);
+        D[(size_t)(3 * c + l) * total + idx] = v;
+      }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_metric_outer(int ndim, int N0, int N1, int N2, const double* X,
+                                                      const double* D, double* M) {
+  const int total = N0 * N1 * N2;
+  const int Ns[3] = {N0, N1, N2}, ss[3] = {1, N0, N0 * N1};
+  const double* x = X;
+  const double* y = X + total;
+  const double* z = X + 2 * (size_t)total;
+#define DD(c, l) (D + (size_t)(3 * (c) + (l)) * total)
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
+    int p[3] = {idx % N0, (idx / N0) % N1, idx / (N0 * N1)};
+    bool ok = true;
+    for (int l = 0; l < ndim; ++l) ok = ok && p[l] >= 2 && p[l] < Ns[l] - 2;
+    double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (ok) {
+      if (ndim == 1) {
+        double xx = DD(0, 0)[idx];
+        m[0] = 1.0; m[4] = xx; m[8] = xx; m[9] = 1.0 / xx;
+      } else if (ndim == 2) {
+        double xxi = DD(0, 0)[idx], xet = DD(0, 1)[idx], yxi = DD(1, 0)[idx], yet = DD(1, 1)[idx];
+        m[0] = yet; m[1] = -xet; m[3] = -yxi; m[4] = xxi;
+        double det = xxi * yet - xet * yxi;
+        m[8] = det; m[9] = 1.0 / det;
+      } else {
+        // outer D4 of products of an inner derivative and a coordinate
+        auto od = [&](int c, int li, const double* w, int lo) {
+          const double* a = DD(c, li);
+          int s = ss[lo];
+          return (8.0 * (a[idx + s] * w[idx + s] - a[idx - s] * w[idx - s]) -
+                  (a[idx + 2 * s] * w[idx + 2 * s] - a[idx - 2 * s] * w[idx - 2 * s])) / 12.0;
+        };
+        m[0] = od(1, 1, z, 2) - od(1, 2, z, 1);
+        m[1] = od(2, 1, x, 2) - od(2, 2, x, 1);
+        m[2] = od(0, 1, y, 2) - od(0, 2, y, 1);
+        m[3] = od(1, 2, z, 0) - od(1, 0, z, 2);
+        m[4] = od(2, 2, x, 0) - od(2, 0, x, 2);
+        m[5] = od(0, 2, y, 0) - od(0, 0, y, 2);
+        m[6] = od(1, 0, z, 1) - od(1, 1, z, 0);
+        m[7] = od(2, 0, x, 1) - od(2, 1, x, 0);
+        m[8] = od(0, 0, y, 1) - od(0, 1, y, 0);
+        double xx = DD(0, 0)[idx], xe = DD(0, 1)[idx], xz = DD(0, 2)[idx];
+        double yx = DD(1, 0)[idx], ye = DD(1, 1)[idx], yz = DD(1, 2)[idx];
+        double zx = DD(2, 0)[idx], ze = DD(2, 1)[idx], zz = DD(2, 2)[idx];
+        double det = xx * (ye * zz - yz * ze) - xe * (yx * zz - yz * zx) + xz * (yx * ze - ye * zx);
+        m[9] = 1.0 / det;
+      }
+    }
+    for (int c = 0; c < 10; ++c) M[(size_t)c * total + idx] = m[c];
+  }
+#undef DD
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_convert(const double* src, R* dst, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = (R)src[i];
+}
+
+// ------------------------------------------------------------------ launchers
+static inline dim3 grid_for(long long work, int nprob, int block = 256, int cap = 8192) {
+  long long b = (work + block - 1) / block;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return dim3((unsigned)b, (unsigned)nprob);
+}
+
+void launch_bc_cons(const Launch& L, StateRef ref, int d) {
+  hipLaunchKernelGGL(k_bc_cons, grid_for(L.ghost_work[d], L.nprob), dim3(256), 0, L.stream, L.probs, ref, d);
+}
+
+template <typename R>
+void launch_bc_scalar(const Launch& L, int which, int nf, int d) {
+  hipLaunchKernelGGL(k_bc_scalar<R>, grid_for(L.ghost_work[d], L.nprob), dim3(256), 0, L.stream, L.probs,
+                     which, nf, d);
+}
+
+template <typename R>
+void launch_prim(const Launch& L, StateRef ref, int want_flags, const uint8_t* force) {
+  hipLaunchKernelGGL(k_prim<R>, grid_for(L.max_total, L.nprob), dim3(256), 0, L.stream, L.probs, ref,
+                     want_flags, force);
+}
+
+void launch_any_flag(const Launch& L) {
+  hipLaunchKernelGGL(k_zero_any, dim3(1, L.nprob), dim3(64), 0, L.stream, L.probs);
+  hipLaunchKernelGGL(k_any_flag, grid_for(L.max_cells, L.nprob), dim3(256), 0, L.stream, L.probs);
+}
+
+void launch_dilate(const Launch& L, int ndim) {
+  // f -> ... -> ft, alternating between ft and ftmp so that the last pass lands in ft
+  int src = 0;
+  for (int d = 0; d < ndim; ++d) {
+    int dst = ((ndim - 1 - d) % 2 == 0) ? 2 : 1;
+    hipLaunchKernelGGL(k_dilate, grid_for(L.max_total, L.nprob), dim3(256), 0, L.stream, L.probs, d, src, dst);
+    src = dst;
+  }
+}
+
+void launch_combine(const Launch& L, RKRef rr, int stage, double a, double b) {
+  hipLaunchKernelGGL(k_combine, grid_for(L.max_total, L.nprob), dim3(256), 0, L.stream, L.probs, rr, stage, a,
+                     b);
+}
+
+void launch_dt(const Launch& L, const double* Qx, double* tx, double t_end, int advance_t) {
+  hipLaunchKernelGGL(k_dt_reset, dim3(1, L.nprob), dim3(64), 0, L.stream, L.probs);
+  hipLaunchKernelGGL(k_dt_reduce, grid_for(L.max_cells, L.nprob), dim3(256), 0, L.stream, L.probs, Qx);
+  hipLaunchKernelGGL(k_dt_finalize, dim3(1, L.nprob), dim3(64), 0, L.stream, L.probs, tx, t_end, advance_t);
+}
+
+void launch_set_dt(const Launch& L, double dt) {
+  hipLaunchKernelGGL(k_set_dt, dim3(1, L.nprob), dim3(64), 0, L.stream, L.probs, dt);
+}
+
+void launch_zero_status(const Launch& L) {
+  hipLaunchKernelGGL(k_zero_status, dim3(1, L.nprob), dim3(64), 0, L.stream, L.probs);
+}
+
+void launch_metrics(int ndim, const int N[3], const double* coords, double* scratch9, double* metrics,
+                    hipStream_t s) {
+  long long total = (long long)N[0] * N[1] * N[2];
+  hipLaunchKernelGGL(k_metric_inner, grid_for(total, 1), dim3(256), 0, s, ndim, N[0], N[1], N[2], coords,
+                     scratch9);
+  hipLaunchKernelGGL(k_metric_outer, grid_for(total, 1), dim3(256), 0, s, ndim, N[0], N[1], N[2], coords,
+                     scratch9, metrics);
+}
+
+template <typename R>
+void launch_convert(const double* src, R* dst, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_convert<R>, grid_for((long long)n, 1), dim3(256), 0, s, src, dst, n);
+}
+
+template void launch_bc_scalar<float>(const Launch&, int, int, int);
+template void launch_bc_scalar<double>(const Launch&, int, int, int);
+template void launch_prim<float>(const Launch&, StateRef, int, const uint8_t*);
+template void launch_prim<double>(const Launch&, StateRef, int, const uint8_t*);
+template void launch_convert<float>(const double*, float*, size_t, hipStream_t);
+template void launch_convert<double>(const double*, double*, size_t, hipStream_t);
+
+}  // namespace lg

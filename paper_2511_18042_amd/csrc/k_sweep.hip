@@ -1,0 +1,392 @@
+// Omega sensor and the interface sweeps of the three right-hand-side forms.
+//
+// Paper: Sec. 2.3 -- conservative finite difference (fluxes at half nodes, node
+// derivative = flux difference); characteristic transformation of the primitives
+// with waves acoustic (1,5), entropy (2), shear (3,4); centralised interpolation
+// C^C = (C^{L,Lin} + C^{R,Lin}) / 2; selection rule: acoustic -> MP5 where the
+// over-barred sensor exceeds 0.01, else the linear (upwind GBR) state; entropy -> MP
+// criterion with threshold 1e-20 (central value when it holds, MP5 otherwise); shear
+// -> MP5 where the sensor exceeds 0.01, else the central value; curvilinear HLLC with
+// Roe-averaged wave speeds and interface metrics interpolated from the nodes.
+// Sec. 5 / Alg. 3 -- hybrid: the LAD-E4 interface flux unless the interface touches a
+// (dilated) troubled cell.
+//
+// GBR linear states (gradient-based reconstruction, unit spacing):
+//   C^{L,Lin} = C_i + C'_i/2 + C''_i/12,  C^{R,Lin} = C_{i+1} - C'_{i+1}/2 + C''_{i+1}/12,
+//   C''_j = 2 (C_{j+1} - 2 C_j + C_{j-1}) - (C'_{j+1} - C'_{j-1}) / 2.
+// MP5 = Suresh & Huynh (1997), alpha = 4, beta = 4/3.
+// Frozen characteristic state: arithmetic mean of nodes i, i+1; basis n = xi~/|xi~|,
+// t1 = normalise(n x e_m) with m = argmin |n_m| (lowest index on ties), t2 = n x t1.
+// Omega = pressure switch x Ducros ratio (theta^2 + eps) / (theta^2 + |omega|^2 + eps),
+// eps = 1e-32, so that a pressure jump in a flow at rest is still detected; over-bar =
+// max over the node and its two neighbours along the sweep; the left state uses node i,
+// the right node i+1.
+// Interface metrics: I4 of the node metrics.  The flux difference is formed in FP64.
+#include "lgbr_dev.h"
+#include "lgbr_kernels.h"
+
+namespace lg {
+
+__device__ __forceinline__ bool sw_skip(const Prob& P, int skip_if_any) {
+  return skip_if_any >= 0 && P.any_flag && (*P.any_flag != 0) == (skip_if_any != 0);
+}
+
+__device__ __forceinline__ bool band(const Prob& P, int idx, int lo, int hi) {
+  int p[3] = {idx % P.N[0], (idx / P.N[0]) % P.N[1], idx / (P.N[0] * P.N[1])};
+  for (int l = 0; l < P.ndim; ++l)
+    if (p[l] < P.g[l] + lo || p[l] >= P.g[l] + P.n[l] + hi) return false;
+  return true;
+}
+
+// ------------------------------------------------------------------ sensor
+template <typename R>
+__global__ void __launch_bounds__(256) k_sensor(const Prob* probs, int skip_if_any) {
+  const Prob& P = probs[blockIdx.y];
+  if (sw_skip(P, skip_if_any)) return;
+  const R* W = static_cast<const R*>(P.W);
+  R* Om = static_cast<R*>(P.Om);
+  const size_t T = P.total;
+  const R* p = W + 4 * T;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < P.total; idx += gridDim.x * blockDim.x) {
+    if (!band(P, idx, -2, 2)) continue;
+    R phi = R(0);
+    for (int l = 0; l < P.ndim; ++l) {
+      int s = P.s[l];
+      R pp = p[idx + s], p0 = p[idx], pm = p[idx - s];
+      R r = fabs(pp - R(2) * p0 + pm) / (pp + R(2) * p0 + pm);
+      phi = fmax(phi, r);
+    }
+    R du[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) du[i][j] = R(0);
+    R J = met<R>(P, 9, idx);
+    for (int l = 0; l < P.ndim; ++l) {
+      const R* G = static_cast<const R*>(P.G[l]);
+      for (int j = 0; j < 3; ++j) {
+        R m = J * met<R>(P, 3 * l + j, idx);
+        for (int i = 0; i < 3; ++i) du[i][j] += m * G[(1 + i) * T + idx];
+      }
+    }
+    R th = du[0][0] + du[1][1] + du[2][2];
+    R w1 = du[2][1] - du[1][2], w2 = du[0][2] - du[2][0], w3 = du[1][0] - du[0][1];
+    R om2 = w1 * w1 + w2 * w2 + w3 * w3;
+    Om[idx] = phi * ((th * th + R(1e-32)) / (th * th + om2 + R(1e-32)));
+  }
+}
+
+// ------------------------------------------------------------------ pieces of the GBR flux
+template <typename R>
+__host__ __device__ __forceinline__ R mp5(R vm2, R vm1, R v0, R vp1, R vp2, R alpha, R eps) {
+  R vor = (R(2) * vm2 - R(13) * vm1 + R(47) * v0 + R(27) * vp1 - R(3) * vp2) / R(60);
+  R vmp = v0 + minmod2(vp1 - v0, alpha * (v0 - vm1));
+  if ((vor - v0) * (vor - vmp) <= eps) return vor;
+  R djm1 = vm2 - R(2) * vm1 + v0;
+  R dj = vm1 - R(2) * v0 + vp1;
+  R djp1 = v0 - R(2) * vp1 + vp2;
+  R dm4p = minmod4(R(4) * dj - djp1, R(4) * djp1 - dj, dj, djp1);
+  R dm4m = minmod4(R(4) * dj - djm1, R(4) * djm1 - dj, dj, djm1);
+  R vul = v0 + alpha * (v0 - vm1);
+  R vav = R(0.5) * (v0 + vp1);
+  R vmd = vav - R(0.5) * dm4p;
+  R vlc = v0 + R(0.5) * (v0 - vm1) + R(4.0 / 3.0) * dm4m;
+  R vmin = fmax(fmin(fmin(v0, vp1), vmd), fmin(fmin(v0, vul), vlc));
+  R vmax = fmin(fmax(fmax(v0, vp1), vmd), fmax(fmax(v0, vul), vlc));
+  return vor + minmod2(vmin - vor, vmax - vor);
+}
+
+template <typename R>
+struct Frame {
+  R n[3], t1[3], t2[3];
+  R k, cb2inv, cb, rb;  // k = rb / (2 cb)
+};
+
+template <typename R>
+__host__ __device__ __forceinline__ void to_char(const Frame<R>& f, R r, R u, R v, R w, R p, R C[5]) {
+  R un = f.n[0] * u + f.n[1] * v + f.n[2] * w;
+  R pc = p / (R(2) * f.cb * f.cb);
+  C[0] = -f.k * un + pc;
+  C[1] = r - p / (f.cb * f.cb);
+  C[2] = f.t1[0] * u + f.t1[1] * v + f.t1[2] * w;
+  C[3] = f.t2[0] * u + f.t2[1] * v + f.t2[2] * w;
+  C[4] = f.k * un + pc;
+}
+
+template <typename R>
+__host__ __device__ __forceinline__ void from_char(const Frame<R>& f, const R C[5], R Wo[5]) {
+  R un = (f.cb / f.rb) * (C[4] - C[0]);
+  Wo[0] = C[0] + C[1] + C[4];
+  Wo[1] = f.n[0] * un + f.t1[0] * C[2] + f.t2[0] * C[3];
+  Wo[2] = f.n[1] * un + f.t1[1] * C[2] + f.t2[1] * C[3];
+  Wo[3] = f.n[2] * un + f.t1[2] * C[2] + f.t2[2] * C[3];
+  Wo[4] = f.cb * f.cb * (C[0] + C[4]);
+}
+
+template <typename R>
+__host__ __device__ __forceinline__ void hllc(const R WL[5], const R WR[5], const R xt[3], R gamma, R F[5]) {
+  R xn2 = xt[0] * xt[0] + xt[1] * xt[1] + xt[2] * xt[2];
+  R xn = sqrt(xn2);
+  R rL = WL[0], pL = WL[4], rR = WR[0], pR = WR[4];
+  R EL = pL / (gamma - R(1)) + R(0.5) * rL * (WL[1] * WL[1] + WL[2] * WL[2] + WL[3] * WL[3]);
+  R ER = pR / (gamma - R(1)) + R(0.5) * rR * (WR[1] * WR[1] + WR[2] * WR[2] + WR[3] * WR[3]);
+  R HL = (EL + pL) / rL, HR = (ER + pR) / rR;
+  R cL = sqrt(gamma * pL / rL), cR = sqrt(gamma * pR / rR);
+  R UL = xt[0] * WL[1] + xt[1] * WL[2] + xt[2] * WL[3];
+  R UR = xt[0] * WR[1] + xt[1] * WR[2] + xt[2] * WR[3];
+  R Rr = sqrt(rR / rL);
+  R ub[3];
+  for (int m = 0; m < 3; ++m) ub[m] = (WL[1 + m] + Rr * WR[1 + m]) / (R(1) + Rr);
+  R Hb = (HL + Rr * HR) / (R(1) + Rr);
+  R cb = sqrt((gamma - R(1)) * (Hb - R(0.5) * (ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2])));
+  R Ub = xt[0] * ub[0] + xt[1] * ub[1] + xt[2] * ub[2];
+  R SL = fmin(UL - cL * xn, Ub - cb * xn);
+  R SR = fmax(UR + cR * xn, Ub + cb * xn);
+  R Ss = (rR * UR * (SR - UR) - rL * UL * (SL - UL) + (pL - pR) * xn2) / (rR * (SR - UR) - rL * (SL - UL));
+  // pick the side whose flux (or star flux) is needed:
+  // S_L >= 0 -> F_L; S* >= 0 -> F*_L; S_R > 0 -> F*_R; else F_R
+  bool left = (SL >= R(0)) || (Ss >= R(0));
+  const R* Wk = left ? WL : WR;
+  R rho = left ? rL : rR, p = left ? pL : pR, E = left ? EL : ER, U = left ? UL : UR, S = left ? SL : SR;
+  F[0] = rho * U;
+  F[1] = rho * Wk[1] * U + xt[0] * p;
+  F[2] = rho * Wk[2] * U + xt[1] * p;
+  F[3] = rho * Wk[3] * U + xt[2] * p;
+  F[4] = (E + p) * U;
+  bool star = left ? !(SL >= R(0)) : (SR > R(0));
+  if (star) {
+    R fac = rho * (S - U) / (S - Ss);
+    R Qs[5], Qk[5];
+    Qs[0] = fac;
+    for (int m = 0; m < 3; ++m) Qs[1 + m] = fac * (Wk[1 + m] + xt[m] * (Ss - U) / xn2);
+    Qs[4] = fac * (E / rho + (Ss - U) * (Ss / xn2 + p / (rho * (S - U))));
+    Qk[0] = rho;
+    for (int m = 0; m < 3; ++m) Qk[1 + m] = rho * Wk[1 + m];
+    Qk[4] = E;
+    for (int q = 0; q < 5; ++q) F[q] = F[q] + S * (Qs[q] - Qk[q]);
+  }
+}
+
+// C-GBR convective flux at the interface between node idx and idx + s (direction d)
+template <typename R>
+__host__ __device__ __forceinline__ void gbr_flux(const Prob& P, int d, int idx, R F[5]) {
+  const size_t T = P.total;
+  const int s = P.s[d];
+  const R* W = static_cast<const R*>(P.W);
+  const R* G = static_cast<const R*>(P.G[d]);
+  const R* Om = static_cast<const R*>(P.Om);
+  // interface metrics (I4 of node metrics)
+  R xt[3];
+  for (int c = 0; c < 3; ++c) {
+    int comp = 3 * d + c;
+    R a0 = met<R>(P, comp, idx - s), a1 = met<R>(P, comp, idx), a2 = met<R>(P, comp, idx + s),
+      a3 = met<R>(P, comp, idx + 2 * s);
+    xt[c] = (R(7) * (a1 + a2) - (a0 + a3)) / R(12);
+  }
+  Frame<R> fr;
+  R xn = sqrt(xt[0] * xt[0] + xt[1] * xt[1] + xt[2] * xt[2]);
+  for (int c = 0; c < 3; ++c) fr.n[c] = xt[c] / xn;
+  {
+    R a0 = fabs(fr.n[0]), a1 = fabs(fr.n[1]), a2 = fabs(fr.n[2]);
+    int m = (a0 <= a1 && a0 <= a2) ? 0 : (a1 <= a2 ? 1 : 2);
+    R t[3];
+    if (m == 0) { t[0] = R(0); t[1] = fr.n[2]; t[2] = -fr.n[1]; }
+    else if (m == 1) { t[0] = -fr.n[2]; t[1] = R(0); t[2] = fr.n[0]; }
+    else { t[0] = fr.n[1]; t[1] = -fr.n[0]; t[2] = R(0); }
+    R tn = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    for (int c = 0; c < 3; ++c) fr.t1[c] = t[c] / tn;
+    fr.t2[0] = fr.n[1] * fr.t1[2] - fr.n[2] * fr.t1[1];
+    fr.t2[1] = fr.n[2] * fr.t1[0] - fr.n[0] * fr.t1[2];
+    fr.t2[2] = fr.n[0] * fr.t1[1] - fr.n[1] * fr.t1[0];
+  }
+  const R gamma = (R)P.gamma;
+  R r0 = W[idx], r1 = W[idx + s], p0 = W[4 * T + idx], p1 = W[4 * T + idx + s];
+  fr.rb = R(0.5) * (r0 + r1);
+  R pb = R(0.5) * (p0 + p1);
+  fr.cb = sqrt(gamma * pb / fr.rb);
+  fr.k = fr.rb / (R(2) * fr.cb);
+
+  R C[6][5], D[4][5];
+  for (int o = -2; o <= 3; ++o) {
+    int id = idx + o * s;
+    to_char(fr, W[id], W[T + id], W[2 * T + id], W[3 * T + id], W[4 * T + id], C[o + 2]);
+  }
+  for (int o = -1; o <= 2; ++o) {
+    int id = idx + o * s;
+    to_char(fr, G[id], G[T + id], G[2 * T + id], G[3 * T + id], G[4 * T + id], D[o + 1]);
+  }
+  const R thr = (R)P.omega_thr, eps = (R)P.mp_eps, alpha = (R)P.mp_alpha;
+  R om_m1 = Om[idx - s], om_0 = Om[idx], om_1 = Om[idx + s], om_2 = Om[idx + 2 * s];
+  bool shockL = fmax(fmax(om_m1, om_0), om_1) > thr;
+  bool shockR = fmax(fmax(om_0, om_1), om_2) > thr;
+
+  R CL[5], CR[5];
+  for (int b = 0; b < 5; ++b) {
+    // C[k] <-> offset k-2 ; D[k] <-> offset k-1
+    R cm2 = C[0][b], cm1 = C[1][b], c0 = C[2][b], c1 = C[3][b], c2 = C[4][b], c3 = C[5][b];
+    R dm1 = D[0][b], d0 = D[1][b], d1 = D[2][b], d2 = D[3][b];
+    R c2i = R(2) * (c1 - R(2) * c0 + cm1) - R(0.5) * (d1 - dm1);
+    R c2p = R(2) * (c2 - R(2) * c1 + c0) - R(0.5) * (d2 - d0);
+    R Llin = c0 + R(0.5) * d0 + c2i / R(12);
+    R Rlin = c1 - R(0.5) * d1 + c2p / R(12);
+    R cc = R(0.5) * (Llin + Rlin);
+    bool useL, useR;  // use MP5?
+    R Lalt, Ralt;     // value otherwise
+    if (b == 0 || b == 4) {
+      useL = shockL; useR = shockR; Lalt = Llin; Ralt = Rlin;
+    } else if (b == 1) {
+      R cmpL = c0 + minmod2(c1 - c0, alpha * (c0 - cm1));
+      R cmpR = c1 + minmod2(c0 - c1, alpha * (c1 - c2));
+      useL = !((Llin - c0) * (Llin - cmpL) <= eps);
+      useR = !((Rlin - c1) * (Rlin - cmpR) <= eps);
+      Lalt = cc; Ralt = cc;
+    } else {
+      useL = shockL; useR = shockR; Lalt = cc; Ralt = cc;
+    }
+    CL[b] = useL ? mp5(cm2, cm1, c0, c1, c2, alpha, eps) : Lalt;
+    CR[b] = useR ? mp5(c3, c2, c1, c0, cm1, alpha, eps) : Ralt;
+  }
+  R WL[5], WR[5];
+  from_char(fr, CL, WL);
+  from_char(fr, CR, WR);
+  hllc(WL, WR, xt, gamma, F);
+}
+
+template <typename R>
+__host__ __device__ __forceinline__ void i4_flux(const R* Fn, size_t T, int idx, int s, R F[5]) {
+  for (int q = 0; q < 5; ++q) {
+    const R* f = Fn + q * T + idx;
+    F[q] = (R(7) * (f[0] + f[s]) - (f[-s] + f[2 * s])) / R(12);
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void interface_flux(const Prob& P, int d, int idx, int sel, R F[5]) {
+  const int s = P.s[d];
+  const size_t T = P.total;
+  bool gbr;
+  if (sel == SEL_GBR) gbr = true;
+  else if (sel == SEL_LAD) gbr = false;
+  else if (sel == SEL_PERCELL) gbr = (P.ft[idx] | P.ft[idx + s]) != 0;
+  else gbr = *P.any_flag != 0;
+  if (gbr) {
+    gbr_flux(P, d, idx, F);
+    if (P.viscous) {
+      R Fv[5];
+      i4_flux(static_cast<const R*>(P.FV[d]), T, idx, s, Fv);
+      for (int q = 0; q < 5; ++q) F[q] = F[q] + Fv[q];
+    }
+  } else {
+    i4_flux(static_cast<const R*>(P.FL[d]), T, idx, s, F);
+  }
+}
+
+__device__ __forceinline__ double node_J(const Prob& P, int idx) {
+  return P.curvilinear ? P.M64[9 * (size_t)P.total + idx] : P.cm[9];
+}
+
+// ------------------------------------------------------------------ x sweep: one wave per
+// row segment of 63 nodes; lane t computes the interface left of node (seg*63 + t - 1) + 1
+// and the flux difference uses the neighbour lane's flux.
+template <typename R>
+__global__ void __launch_bounds__(256) k_sweep_x(const Prob* probs, StateRef ref, int sel, int accumulate) {
+  const Prob& P = probs[blockIdx.y];
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int n0 = P.n[0];
+  const int nseg = (n0 + 62) / 63;
+  const int rows = P.n[1] * P.n[2];
+  if (wave >= nseg * rows) return;
+  const int seg = wave % nseg, row = wave / nseg;
+  const int j = row % P.n[1], k = row / P.n[1];
+  const int il = seg * 63 - 1 + lane;  // interface il + 1/2
+  const bool valid = il <= n0 - 1;
+  const int idx = pos_to_idx(P, il + P.g[0], j + P.g[1], k + P.g[2]);
+  R F[5] = {R(0), R(0), R(0), R(0), R(0)};
+  if (valid) interface_flux(P, 0, idx, sel, F);
+  double* dQ = ref.deriv(P);
+  const size_t T = P.total;
+  double Fp[5];
+  for (int q = 0; q < 5; ++q) Fp[q] = (double)__shfl_up(F[q], 1);
+  if (lane >= 1 && valid) {
+    double J = node_J(P, idx);
+    for (int q = 0; q < 5; ++q) {
+      double v = -J * ((double)F[q] - Fp[q]);
+      size_t o = q * T + idx;
+      dQ[o] = accumulate ? dQ[o] + v : v;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ strided sweeps: one
+// lane per line segment of `seg` nodes, sliding along the line.
+template <typename R>
+__global__ void __launch_bounds__(256) k_sweep_s(const Prob* probs, StateRef ref, int d, int sel,
+                                                 int accumulate, int seg) {
+  const Prob& P = probs[blockIdx.y];
+  if (d >= P.ndim) return;
+  const int o2 = d == 1 ? 2 : 1;
+  const int na = P.n[0], nb = P.n[o2], nd = P.n[d];
+  const int nch = (nd + seg - 1) / seg;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= na * nb * nch) return;
+  const int a = t % na, r = t / na;
+  const int b = r % nb, ch = r / nb;
+  const int start = ch * seg, end = min(start + seg, nd);
+  int pos[3];
+  pos[0] = a + P.g[0];
+  pos[o2] = b + P.g[o2];
+  pos[d] = start - 1 + P.g[d];
+  int idx = pos_to_idx(P, pos[0], pos[1], pos[2]);
+  const int s = P.s[d];
+  const size_t T = P.total;
+  double* dQ = ref.deriv(P);
+  R F[5];
+  interface_flux(P, d, idx, sel, F);
+  double Fp[5];
+  for (int q = 0; q < 5; ++q) Fp[q] = (double)F[q];
+  for (int p = start; p < end; ++p) {
+    idx += s;
+    interface_flux(P, d, idx, sel, F);
+    double J = node_J(P, idx);
+    for (int q = 0; q < 5; ++q) {
+      double fq = (double)F[q];
+      double v = -J * (fq - Fp[q]);
+      size_t o = q * T + idx;
+      dQ[o] = accumulate ? dQ[o] + v : v;
+      Fp[q] = fq;
+    }
+  }
+}
+
+template <typename R>
+void launch_sensor(const Launch& L, int skip_if_any) {
+  long long b = (L.max_total + 255) / 256;
+  if (b > 8192) b = 8192;
+  hipLaunchKernelGGL(k_sensor<R>, dim3((unsigned)b, L.nprob), dim3(256), 0, L.stream, L.probs, skip_if_any);
+}
+
+template <typename R>
+void launch_sweep(const Launch& L, StateRef ref, int d, int sel, int accumulate) {
+  if (d == 0) {
+    long long nseg = (L.max_n[0] + 62) / 63;
+    long long waves = nseg * L.sweep_rows[0];
+    long long blocks = (waves + 3) / 4;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_sweep_x<R>, dim3((unsigned)blocks, L.nprob), dim3(256), 0, L.stream, L.probs, ref, sel,
+                       accumulate);
+  } else {
+    int seg = L.seg > 0 ? L.seg : 16;
+    long long nch = (L.max_n[d] + seg - 1) / seg;
+    long long work = nch * L.sweep_rows[d];
+    long long blocks = (work + 255) / 256;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_sweep_s<R>, dim3((unsigned)blocks, L.nprob), dim3(256), 0, L.stream, L.probs, ref, d,
+                       sel, accumulate, seg);
+  }
+}
+
+template void launch_sensor<float>(const Launch&, int);
+template void launch_sensor<double>(const Launch&, int);
+template void launch_sweep<float>(const Launch&, StateRef, int, int, int);
+template void launch_sweep<double>(const Launch&, StateRef, int, int, int);
+
+}  // namespace lg

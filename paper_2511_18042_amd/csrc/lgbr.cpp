@@ -1,0 +1,555 @@
+// Host side of liblgbr: contexts, workspaces, the stage pipeline of the three RHS forms,
+// SSP-RK3 and graph-captured multi-problem batches (C ABI declared in include/lgbr.h).
+//
+// Stage pipeline (Alg. 1-3 of the paper, in data-parallel form):
+//   ghost images -> primitives (+ troubled flags) ->
+//   [C-GBR] gradients per direction (E6 explicit or C4 line solves) -> Omega sensor
+//           (-> C-GBR viscous node fluxes when viscous)
+//   [LAD]   |S|, div u, e -> raw mu*, beta*, kappa* -> truncated Gaussian per direction
+//           -> node fluxes F^c + F^v per direction
+//   [hyb]   flag dilation (per-cell) or any-flag reduction (global)
+//   -> one interface sweep per direction (flux + FP64 difference into dQ/dt)
+// RK3: dt reduction from U^n, then three (stage RHS -> stage combination) passes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lgbr.h"
+#include "lgbr_kernels.h"
+
+using lg::Launch;
+using lg::Prob;
+using lg::RKRef;
+using lg::StateRef;
+
+namespace {
+
+void* (*g_alloc)(size_t, void*) = nullptr;
+void (*g_free)(void*, void*) = nullptr;
+void* g_user = nullptr;
+
+void* dev_alloc(size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (g_alloc) return g_alloc(bytes, g_user);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+
+void dev_free(void* p) {
+  if (!p) return;
+  if (g_free) g_free(p, g_user);
+  else (void)hipFree(p);
+}
+
+struct Cfg {
+  int ndim, precision, grad, hybrid_mode, viscous;
+};
+
+}  // namespace
+
+struct lg_ctx {
+  Prob hp;
+  Prob* dp = nullptr;
+  Launch L;
+  Cfg cfg;
+  hipStream_t stream = nullptr;
+  std::vector<void*> allocs;
+  size_t ws_bytes = 0;
+  void* alloc(size_t bytes) {
+    void* p = dev_alloc(bytes);
+    if (p) {
+      allocs.push_back(p);
+      ws_bytes += bytes;
+    }
+    return p;
+  }
+};
+
+struct lg_batch {
+  std::vector<Prob> hps;
+  Prob* dps = nullptr;
+  Launch L;
+  Cfg cfg;
+  hipStream_t stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int nsteps = 0, scheme = 0;
+};
+
+namespace {
+
+const double RK_A[3] = {0.0, 0.75, 1.0 / 3.0};
+const double RK_B[3] = {1.0, 0.25, 2.0 / 3.0};
+
+template <typename R>
+void enqueue_rhs(const Launch& L, const Cfg& c, int scheme, StateRef ref, const uint8_t* force) {
+  for (int d = 0; d < c.ndim; ++d) lg::launch_bc_cons(L, ref, d);
+  const bool hyb = scheme == LG_SCHEME_HYBRID;
+  lg::launch_prim<R>(L, ref, hyb ? 1 : 0, force);
+  int sel, skip_gbr = -1, skip_lad = -1;
+  if (scheme == LG_SCHEME_CGBR) {
+    sel = lg::SEL_GBR;
+  } else if (scheme == LG_SCHEME_LAD) {
+    sel = lg::SEL_LAD;
+  } else if (c.hybrid_mode == LG_HYB_GLOBAL) {
+    sel = lg::SEL_GLOBAL;
+    lg::launch_any_flag(L);
+    skip_gbr = 0;  // C-GBR inputs are skipped when no interior node is troubled
+    skip_lad = 1;  // LAD inputs are skipped when one is
+  } else {
+    sel = lg::SEL_PERCELL;
+    lg::launch_dilate(L, c.ndim);
+  }
+  if (sel != lg::SEL_LAD) {
+    for (int d = 0; d < c.ndim; ++d) {
+      if (c.grad == LG_GRAD_C4) lg::launch_grad_c4<R>(L, ref, d, skip_gbr);
+      else lg::launch_grad_explicit<R>(L, d, 6, skip_gbr);
+    }
+    lg::launch_sensor<R>(L, skip_gbr);
+    if (c.viscous) lg::launch_gbr_viscflux<R>(L, skip_gbr);
+  }
+  if (sel != lg::SEL_GBR) lg::launch_lad<R>(L, skip_lad);
+  for (int d = 0; d < c.ndim; ++d) lg::launch_sweep<R>(L, ref, d, sel, d > 0 ? 1 : 0);
+}
+
+template <typename R>
+void enqueue_rk3(const Launch& L, const Cfg& c, int scheme, double* Qx, double* tx, double t_end) {
+  lg::launch_dt(L, Qx, tx, t_end, 1);
+  for (int s = 0; s < 3; ++s) {
+    StateRef ref{s == 0 ? Qx : nullptr, nullptr, s == 0 ? 0 : 1};
+    enqueue_rhs<R>(L, c, scheme, ref, nullptr);
+    RKRef rr{Qx, nullptr, nullptr};
+    lg::launch_combine(L, rr, s, RK_A[s], RK_B[s]);
+  }
+}
+
+lg_status last_hip() { return hipGetLastError() == hipSuccess ? LG_OK : LG_EHIP; }
+
+bool valid_bc(int b) { return b >= LG_BC_PERIODIC && b <= LG_BC_FIXED; }
+
+// LU tables of the compact-gradient systems (see k_grad.hip for the layout)
+std::vector<double> tri_bounded(int N) {
+  std::vector<double> t(2 * N, 0.0);
+  double* cp = t.data();
+  double* inv = t.data() + N;
+  cp[0] = 0.0;
+  inv[0] = 1.0;
+  for (int i = 1; i < N - 1; ++i) {
+    double den = 1.0 - 0.25 * cp[i - 1];
+    inv[i] = 1.0 / den;
+    cp[i] = 0.25 / den;
+  }
+  cp[N - 1] = 0.0;
+  inv[N - 1] = 1.0;
+  return t;
+}
+
+std::vector<double> tri_periodic(int n) {
+  // cyclic [1/4, 1, 1/4] = B + u v^T with gamma = -1, u = (gamma, 0.., 1/4), v = (1, 0.., -1/4)
+  std::vector<double> t(3 * n + 1, 0.0);
+  double* cp = t.data();
+  double* inv = t.data() + n;
+  double* z = t.data() + 2 * n;
+  std::vector<double> b(n, 1.0);
+  b[0] = 2.0;
+  b[n - 1] = 1.0 + 0.25 * 0.25;
+  for (int i = 0; i < n; ++i) {
+    double den = b[i] - (i > 0 ? 0.25 * cp[i - 1] : 0.0);
+    inv[i] = 1.0 / den;
+    cp[i] = (i < n - 1 ? 0.25 : 0.0) / den;
+  }
+  std::vector<double> u(n, 0.0), dp(n);
+  u[0] = -1.0;
+  u[n - 1] = 0.25;
+  for (int i = 0; i < n; ++i) dp[i] = (u[i] - (i > 0 ? 0.25 * dp[i - 1] : 0.0)) * inv[i];
+  z[n - 1] = dp[n - 1];
+  for (int i = n - 2; i >= 0; --i) z[i] = dp[i] - cp[i] * z[i + 1];
+  t[3 * n] = 1.0 / (1.0 + z[0] - 0.25 * z[n - 1]);
+  return t;
+}
+
+void fill_launch(Launch& L, const Prob& P) {
+  L.max_total = std::max<long long>(L.max_total, P.total);
+  L.max_cells = std::max<long long>(L.max_cells, (long long)P.n[0] * P.n[1] * P.n[2]);
+  for (int d = 0; d < 3; ++d) {
+    int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+    L.ghost_work[d] = std::max<long long>(L.ghost_work[d], 2LL * P.g[d] * P.N[o1] * P.N[o2]);
+    L.lines[d] = std::max<long long>(L.lines[d], (long long)P.N[o1] * P.N[o2]);
+    L.max_N[d] = std::max<long long>(L.max_N[d], P.N[d]);
+    L.max_n[d] = std::max<long long>(L.max_n[d], P.n[d]);
+    L.sweep_rows[d] = std::max<long long>(L.sweep_rows[d], (long long)P.n[o1] * P.n[o2]);
+  }
+}
+
+template <typename F>
+lg_status dispatch(int precision, F&& f) {
+  if (precision == LG_MIXED) f(float(0));
+  else f(double(0));
+  return last_hip();
+}
+
+}  // namespace
+
+extern "C" {
+
+lg_status lg_set_allocator(void* (*alloc)(size_t, void*), void (*free_)(void*, void*), void* user) {
+  if ((alloc == nullptr) != (free_ == nullptr)) return LG_EINVAL;
+  g_alloc = alloc;
+  g_free = free_;
+  g_user = user;
+  return LG_OK;
+}
+
+const char* lg_strerror(lg_status s) {
+  switch (s) {
+    case LG_OK: return "ok";
+    case LG_EINVAL: return "invalid argument";
+    case LG_ENOMEM: return "out of device memory";
+    case LG_EHIP: return "HIP runtime error";
+    case LG_ENONPHYS: return "non-physical state (rho <= 0, p <= 0 or not finite)";
+    case LG_EUNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown status";
+}
+
+lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metrics, const double* coords,
+                    const lg_gas* gas, const lg_opts* opts, void* stream) {
+  if (!out || !grid || !gas || !opts) return LG_EINVAL;
+  *out = nullptr;
+  const lg_grid& G = *grid;
+  if (G.ndim < 1 || G.ndim > 3 || G.ng != lg::NG) return LG_EINVAL;
+  long long total = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (d < G.ndim) {
+      if (G.n[d] < 5) return LG_EINVAL;
+      if (!valid_bc(G.bc[d][0]) || !valid_bc(G.bc[d][1])) return LG_EINVAL;
+      if ((G.bc[d][0] == LG_BC_PERIODIC) != (G.bc[d][1] == LG_BC_PERIODIC)) return LG_EINVAL;
+      if (!G.curvilinear && !(G.h[d] > 0.0)) return LG_EINVAL;
+    } else if (G.n[d] != 1) {
+      return LG_EINVAL;
+    }
+    total *= G.n[d] + (d < G.ndim ? 2 * lg::NG : 0);
+  }
+  if (total * 5 >= (1LL << 31)) return LG_EUNSUPPORTED;
+  if (G.curvilinear && (!node_metrics || !coords)) return LG_EINVAL;
+  if (!(gas->gamma > 1.0)) return LG_EINVAL;
+  if (gas->viscous && !(gas->Re > 0.0 && gas->Pr > 0.0 && gas->Mref > 0.0)) return LG_EINVAL;
+  if (opts->grad != LG_GRAD_E6 && opts->grad != LG_GRAD_C4) return LG_EINVAL;
+  if (opts->precision != LG_FP64 && opts->precision != LG_MIXED) return LG_EINVAL;
+  if (opts->hybrid_mode != LG_HYB_PERCELL && opts->hybrid_mode != LG_HYB_GLOBAL) return LG_EINVAL;
+  if (opts->dilate < 0 || opts->dilate > 4 || opts->seg < 0) return LG_EINVAL;
+  if (!(opts->cfl > 0.0)) return LG_EINVAL;
+
+  lg_ctx* c = new (std::nothrow) lg_ctx();
+  if (!c) return LG_ENOMEM;
+  c->stream = static_cast<hipStream_t>(stream);
+  Prob& P = c->hp;
+  std::memset(&P, 0, sizeof(P));
+  P.ndim = G.ndim;
+  for (int d = 0; d < 3; ++d) {
+    P.n[d] = G.n[d];
+    P.g[d] = d < G.ndim ? lg::NG : 0;
+    P.N[d] = P.n[d] + 2 * P.g[d];
+    P.bc[d][0] = d < G.ndim ? G.bc[d][0] : LG_BC_TRANSMISSIVE;
+    P.bc[d][1] = d < G.ndim ? G.bc[d][1] : LG_BC_TRANSMISSIVE;
+    P.h[d] = G.h[d];
+  }
+  P.s[0] = 1;
+  P.s[1] = P.N[0];
+  P.s[2] = P.N[0] * P.N[1];
+  P.total = (int)total;
+  P.curvilinear = G.curvilinear;
+  P.cm[0] = G.h[1] * G.h[2];
+  P.cm[4] = G.h[0] * G.h[2];
+  P.cm[8] = G.h[0] * G.h[1];
+  P.cm[9] = 1.0 / (G.h[0] * G.h[1] * G.h[2]);
+  P.gamma = gas->gamma;
+  P.Re = gas->Re;
+  P.Pr = gas->Pr;
+  P.Mref = gas->Mref;
+  P.suth = gas->suth;
+  P.viscous = gas->viscous;
+  P.omega_thr = opts->omega_thr;
+  P.mp_eps = opts->mp_eps;
+  P.mp_alpha = opts->mp_alpha;
+  P.C_mu = opts->C_mu;
+  P.C_beta = opts->C_beta;
+  P.C_kappa = opts->C_kappa;
+  P.rho_thr = opts->rho_thr;
+  P.p_thr = opts->p_thr;
+  P.cfl = opts->cfl;
+  P.dilate = opts->dilate;
+  P.grad_c4 = opts->grad == LG_GRAD_C4;
+  c->cfg = Cfg{G.ndim, opts->precision, opts->grad, opts->hybrid_mode, gas->viscous};
+
+  const size_t T = (size_t)total;
+  const size_t rs = opts->precision == LG_MIXED ? sizeof(float) : sizeof(double);
+  bool ok = true;
+  auto A = [&](size_t bytes) {
+    void* p = c->alloc(bytes);
+    if (!p) ok = false;
+    return p;
+  };
+  P.W = A(5 * T * rs);
+  for (int d = 0; d < G.ndim; ++d) P.G[d] = A(5 * T * rs);
+  if (opts->grad == LG_GRAD_C4) P.T64 = static_cast<double*>(A(5 * T * sizeof(double)));
+  P.Om = A(T * rs);
+  P.f = static_cast<uint8_t*>(A(T));
+  P.ft = static_cast<uint8_t*>(A(T));
+  P.ftmp = static_cast<uint8_t*>(A(T));
+  P.S3 = A(3 * T * rs);
+  P.CA = A(3 * T * rs);
+  P.CB = A(3 * T * rs);
+  for (int d = 0; d < G.ndim; ++d) P.FL[d] = A(5 * T * rs);
+  if (gas->viscous)
+    for (int d = 0; d < G.ndim; ++d) P.FV[d] = A(5 * T * rs);
+  P.Us = static_cast<double*>(A(5 * T * sizeof(double)));
+  P.dQ = static_cast<double*>(A(5 * T * sizeof(double)));
+  double* scal = static_cast<double*>(A(8 * sizeof(double)));
+  if (!ok) {
+    lg_destroy(c);
+    return LG_ENOMEM;
+  }
+  P.dt = scal;
+  P.t = scal + 1;
+  P.smax = reinterpret_cast<unsigned long long*>(scal + 2);
+  P.status = reinterpret_cast<int*>(scal + 3);
+  P.any_flag = reinterpret_cast<int*>(scal + 4);
+  P.t_end = 0.0;
+  if (G.curvilinear) {
+    P.M64 = node_metrics;
+    P.coords = coords;
+    if (opts->precision == LG_MIXED) {
+      float* mr = static_cast<float*>(A(10 * T * sizeof(float)));
+      if (!ok) {
+        lg_destroy(c);
+        return LG_ENOMEM;
+      }
+      lg::launch_convert<float>(node_metrics, mr, 10 * T, c->stream);
+      P.MR = mr;
+    } else {
+      P.MR = node_metrics;
+    }
+  }
+  if (opts->grad == LG_GRAD_C4) {
+    for (int d = 0; d < G.ndim; ++d) {
+      std::vector<double> tab = P.bc[d][0] == LG_BC_PERIODIC ? tri_periodic(P.n[d]) : tri_bounded(P.N[d]);
+      double* dt = static_cast<double*>(A(tab.size() * sizeof(double)));
+      if (!ok) {
+        lg_destroy(c);
+        return LG_ENOMEM;
+      }
+      if (hipMemcpy(dt, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        lg_destroy(c);
+        return LG_EHIP;
+      }
+      P.tri[d] = dt;
+    }
+  }
+  c->dp = static_cast<Prob*>(A(sizeof(Prob)));
+  if (!ok) {
+    lg_destroy(c);
+    return LG_ENOMEM;
+  }
+  if (hipMemcpy(c->dp, &P, sizeof(Prob), hipMemcpyHostToDevice) != hipSuccess) {
+    lg_destroy(c);
+    return LG_EHIP;
+  }
+  // zero the device scalars with a kernel-free synchronous copy (setup only)
+  double zeros[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (hipMemcpy(scal, zeros, sizeof(zeros), hipMemcpyHostToDevice) != hipSuccess) {
+    lg_destroy(c);
+    return LG_EHIP;
+  }
+  std::memset(&c->L, 0, sizeof(Launch));
+  c->L.probs = c->dp;
+  c->L.nprob = 1;
+  c->L.stream = c->stream;
+  c->L.ndim = G.ndim;
+  c->L.seg = opts->seg;
+  fill_launch(c->L, P);
+  if (hipStreamSynchronize(c->stream) != hipSuccess) {
+    lg_destroy(c);
+    return LG_EHIP;
+  }
+  *out = c;
+  return LG_OK;
+}
+
+void lg_destroy(lg_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (void* p : c->allocs) dev_free(p);
+  delete c;
+}
+
+size_t lg_workspace_bytes(const lg_ctx* c) { return c ? c->ws_bytes : 0; }
+
+lg_status lg_metrics_from_coords(const lg_grid* grid, const double* coords, double* node_metrics, void* stream) {
+  if (!grid || !coords || !node_metrics) return LG_EINVAL;
+  if (grid->ndim < 1 || grid->ndim > 3 || grid->ng != lg::NG) return LG_EINVAL;
+  int N[3];
+  for (int d = 0; d < 3; ++d) {
+    if (d >= grid->ndim && grid->n[d] != 1) return LG_EINVAL;
+    if (d < grid->ndim && grid->n[d] < 5) return LG_EINVAL;
+    N[d] = grid->n[d] + (d < grid->ndim ? 2 * lg::NG : 0);
+  }
+  size_t total = (size_t)N[0] * N[1] * N[2];
+  double* scratch = nullptr;
+  if (hipMalloc(&scratch, 9 * total * sizeof(double)) != hipSuccess) return LG_ENOMEM;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  lg::launch_metrics(grid->ndim, N, coords, scratch, node_metrics, s);
+  lg_status st = last_hip();
+  if (hipStreamSynchronize(s) != hipSuccess) st = LG_EHIP;
+  (void)hipFree(scratch);
+  return st;
+}
+
+static lg_status rhs_common(lg_ctx* c, int scheme, double* Q, double* dQ, const uint8_t* fin, uint8_t* fout) {
+  if (!c || !Q || !dQ) return LG_EINVAL;
+  StateRef ref{Q, dQ, 0};
+  lg_status st = dispatch(c->cfg.precision, [&](auto r) {
+    using R = decltype(r);
+    enqueue_rhs<R>(c->L, c->cfg, scheme, ref, fin);
+  });
+  if (st == LG_OK && fout) {
+    if (hipMemcpyAsync(fout, c->hp.f, (size_t)c->hp.total, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+      return LG_EHIP;
+  }
+  return st;
+}
+
+lg_status cgbr_rhs(lg_ctx* c, double* Q, double* dQdt) { return rhs_common(c, LG_SCHEME_CGBR, Q, dQdt, nullptr, nullptr); }
+lg_status lad_rhs(lg_ctx* c, double* Q, double* dQdt) { return rhs_common(c, LG_SCHEME_LAD, Q, dQdt, nullptr, nullptr); }
+lg_status hybrid_rhs(lg_ctx* c, double* Q, double* dQdt, const uint8_t* flags_in, uint8_t* flags_out) {
+  return rhs_common(c, LG_SCHEME_HYBRID, Q, dQdt, flags_in, flags_out);
+}
+
+lg_status rk3_step(lg_ctx* c, int scheme, double* Q, double t_end, double* t_inout) {
+  if (!c || !Q || !t_inout) return LG_EINVAL;
+  if (scheme < LG_SCHEME_CGBR || scheme > LG_SCHEME_HYBRID) return LG_EINVAL;
+  return dispatch(c->cfg.precision, [&](auto r) {
+    using R = decltype(r);
+    enqueue_rk3<R>(c->L, c->cfg, scheme, Q, t_inout, t_end);
+  });
+}
+
+lg_status lg_rk3_stage(lg_ctx* c, int scheme, int stage, const double* Un, double* Us, double dt) {
+  if (!c || !Un || !Us || stage < 0 || stage > 2) return LG_EINVAL;
+  if (scheme < LG_SCHEME_CGBR || scheme > LG_SCHEME_HYBRID) return LG_EINVAL;
+  return dispatch(c->cfg.precision, [&](auto r) {
+    using R = decltype(r);
+    lg::launch_set_dt(c->L, dt);
+    enqueue_rhs<R>(c->L, c->cfg, scheme, StateRef{Us, nullptr, 0}, nullptr);
+    lg::launch_combine(c->L, RKRef{Un, Us, Us}, stage, RK_A[stage], RK_B[stage]);
+  });
+}
+
+lg_status lg_compute_dt(lg_ctx* c, const double* Q, double* dt_out) {
+  if (!c || !Q || !dt_out) return LG_EINVAL;
+  lg::launch_dt(c->L, Q, nullptr, 0.0, 0);
+  if (last_hip() != LG_OK) return LG_EHIP;
+  if (hipMemcpyAsync(dt_out, c->hp.dt, sizeof(double), hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return LG_EHIP;
+  return LG_OK;
+}
+
+lg_status lg_poll_status(lg_ctx* c, int* count) {
+  if (!c || !count) return LG_EINVAL;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return LG_EHIP;
+  int v = 0;
+  if (hipMemcpy(&v, c->hp.status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return LG_EHIP;
+  lg::launch_zero_status(c->L);
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return LG_EHIP;
+  *count = v;
+  return v ? LG_ENONPHYS : LG_OK;
+}
+
+lg_status lg_batch_create(lg_batch** out, lg_ctx* const* ctxs, double* const* Q, double* const* t,
+                          const double* t_end, int n, int nsteps, int scheme) {
+  if (!out || !ctxs || !Q || !t || !t_end || n < 1 || nsteps < 1) return LG_EINVAL;
+  if (scheme < LG_SCHEME_CGBR || scheme > LG_SCHEME_HYBRID) return LG_EINVAL;
+  *out = nullptr;
+  const Cfg& c0 = ctxs[0]->cfg;
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i] || !Q[i] || !t[i]) return LG_EINVAL;
+    const Cfg& ci = ctxs[i]->cfg;
+    if (ci.ndim != c0.ndim || ci.precision != c0.precision || ci.grad != c0.grad ||
+        ci.hybrid_mode != c0.hybrid_mode || ci.viscous != c0.viscous)
+      return LG_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return LG_EINVAL;  // workspaces must not be shared
+  }
+  lg_batch* b = new (std::nothrow) lg_batch();
+  if (!b) return LG_ENOMEM;
+  b->cfg = c0;
+  b->stream = ctxs[0]->stream;
+  b->nsteps = nsteps;
+  b->scheme = scheme;
+  std::memset(&b->L, 0, sizeof(Launch));
+  b->L.nprob = n;
+  b->L.ndim = c0.ndim;
+  b->L.seg = ctxs[0]->L.seg;
+  for (int i = 0; i < n; ++i) {
+    Prob P = ctxs[i]->hp;
+    P.Q = Q[i];
+    P.t = t[i];
+    P.t_end = t_end[i];
+    b->hps.push_back(P);
+    fill_launch(b->L, P);
+  }
+  if (hipMalloc(&b->dps, n * sizeof(Prob)) != hipSuccess) {
+    delete b;
+    return LG_ENOMEM;
+  }
+  if (hipMemcpy(b->dps, b->hps.data(), n * sizeof(Prob), hipMemcpyHostToDevice) != hipSuccess) {
+    lg_batch_destroy(b);
+    return LG_EHIP;
+  }
+  b->L.probs = b->dps;
+  hipStream_t cap;
+  if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+    lg_batch_destroy(b);
+    return LG_EHIP;
+  }
+  Launch Lc = b->L;
+  Lc.stream = cap;
+  lg_status st = LG_OK;
+  if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) st = LG_EHIP;
+  if (st == LG_OK) {
+    for (int s = 0; s < nsteps; ++s) {
+      if (c0.precision == LG_MIXED) enqueue_rk3<float>(Lc, c0, scheme, nullptr, nullptr, 0.0);
+      else enqueue_rk3<double>(Lc, c0, scheme, nullptr, nullptr, 0.0);
+    }
+    if (hipStreamEndCapture(cap, &b->graph) != hipSuccess) st = LG_EHIP;
+  }
+  if (st == LG_OK && hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) st = LG_EHIP;
+  (void)hipStreamDestroy(cap);
+  if (st != LG_OK) {
+    lg_batch_destroy(b);
+    return st;
+  }
+  *out = b;
+  return LG_OK;
+}
+
+lg_status lg_batch_run(lg_batch* b) {
+  if (!b || !b->exec) return LG_EINVAL;
+  return hipGraphLaunch(b->exec, b->stream) == hipSuccess ? LG_OK : LG_EHIP;
+}
+
+void lg_batch_destroy(lg_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->dps) (void)hipFree(b->dps);
+  delete b;
+}
+
+}  // extern "C"

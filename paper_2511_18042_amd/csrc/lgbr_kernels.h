@@ -1,0 +1,66 @@
+// Launch interface between the host library and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "lgbr_dev.h"
+
+namespace lg {
+
+// Which conserved state / derivative a launch works on.  Single-problem calls pass
+// caller pointers (Qx, dQx); batched launches pass null and each problem uses its own
+// buffers (src = 0: P.Q, src = 1: P.Us).
+struct StateRef {
+  double* Qx;
+  double* dQx;
+  int src;
+  __device__ __forceinline__ double* state(const Prob& P) const { return Qx ? Qx : (src ? P.Us : P.Q); }
+  __device__ __forceinline__ double* deriv(const Prob& P) const { return dQx ? dQx : P.dQ; }
+};
+
+// RK stage combination operands (null -> the problem's own buffers by stage).
+struct RKRef {
+  const double* Un;
+  const double* Us;
+  double* out;
+};
+
+// Launch geometry shared by all problems of one launch (maxima over the problems).
+struct Launch {
+  const Prob* probs;   // device array
+  int nprob;
+  hipStream_t stream;
+  long long max_total;     // ghost-padded nodes
+  long long max_cells;     // interior nodes
+  long long ghost_work[3]; // ghost nodes of one direction (2 g N_other1 N_other2)
+  long long lines[3];      // lines along each direction (all nodes of the other two dims)
+  long long max_N[3];      // ghost-padded extent per direction
+  long long max_n[3];      // interior extent per direction
+  long long sweep_rows[3]; // interior lines (interior of the other two dims) per direction
+  int ndim;
+  int seg;                 // nodes per thread in the strided sweeps
+};
+
+void launch_bc_cons(const Launch& L, StateRef ref, int d);
+template <typename R> void launch_bc_scalar(const Launch& L, int which, int nf, int d);
+template <typename R> void launch_prim(const Launch& L, StateRef ref, int want_flags, const uint8_t* force);
+void launch_any_flag(const Launch& L);
+void launch_dilate(const Launch& L, int ndim);
+void launch_combine(const Launch& L, RKRef rr, int stage, double a, double b);
+void launch_dt(const Launch& L, const double* Qx, double* tx, double t_end, int advance_t);
+void launch_set_dt(const Launch& L, double dt);
+void launch_zero_status(const Launch& L);
+void launch_metrics(int ndim, const int N[3], const double* coords, double* scratch9, double* metrics,
+                    hipStream_t s);
+template <typename R> void launch_convert(const double* src, R* dst, size_t n, hipStream_t s);
+
+// gradients
+template <typename R> void launch_grad_explicit(const Launch& L, int d, int order, int skip_if_any);
+template <typename R> void launch_grad_c4(const Launch& L, StateRef ref, int d, int skip_if_any);
+// sensor and C-GBR viscous node fluxes
+template <typename R> void launch_sensor(const Launch& L, int skip_if_any);
+template <typename R> void launch_gbr_viscflux(const Launch& L, int skip_if_any);
+// LAD
+template <typename R> void launch_lad(const Launch& L, int skip_if_any);
+// interface sweeps
+template <typename R> void launch_sweep(const Launch& L, StateRef ref, int d, int sel, int accumulate);
+
+}  // namespace lg
