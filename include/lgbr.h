@@ -164,6 +164,19 @@ lg_status lg_batch_create(lg_batch** batch, lg_ctx* const* ctxs, double* const* 
 lg_status lg_batch_run(lg_batch* batch);      /* one graph launch = nsteps RK3 steps     */
 void lg_batch_destroy(lg_batch* batch);
 
+/* Per-launch timing for measurement: while enabled, every launch of the selected kernel
+ * class (LG_KC_*, or -1 for all classes) issued through this context is bracketed by a
+ * pair of HIP events on the context's stream, up to max_launches launches.  lg_prof_stop
+ * synchronises the stream and returns, per class, the summed event time in ms and the
+ * number of timed launches (arrays of LG_KC_COUNT entries); it also releases the events. */
+enum {
+  LG_KC_BC = 0, LG_KC_PRIM, LG_KC_FLAGS, LG_KC_GRAD_E6, LG_KC_GRAD_C4, LG_KC_SENSOR, LG_KC_VISC,
+  LG_KC_LAD_NODE, LG_KC_LAD_RAW, LG_KC_GAUSS, LG_KC_LAD_FLUX, LG_KC_SWEEP_X, LG_KC_SWEEP_Y,
+  LG_KC_SWEEP_Z, LG_KC_COMBINE, LG_KC_DT, LG_KC_BC_SCALAR, LG_KC_COUNT
+};
+lg_status lg_prof_start(lg_ctx* ctx, int kernel_class, int max_launches);
+lg_status lg_prof_stop(lg_ctx* ctx, double* ms, int* launches);
+
 /* Synchronises the context's stream and reads its non-physical node count since the
  * last poll (then resets it).  Returns LG_ENONPHYS when the count is non-zero. */
 lg_status lg_poll_status(lg_ctx* ctx, int* nonphys_count);

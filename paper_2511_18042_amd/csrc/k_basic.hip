@@ -328,24 +328,26 @@ static inline dim3 grid_for(long long work, int nprob, int block = 256, int cap 
 }
 
 void launch_bc_cons(const Launch& L, StateRef ref, int d) {
-  hipLaunchKernelGGL(k_bc_cons, grid_for(L.ghost_work[d], L.nprob), dim3(256), 0, L.stream, L.probs, ref, d);
+  LG_TIMED(L, KC_BC, hipLaunchKernelGGL(k_bc_cons, grid_for(L.ghost_work[d], L.nprob), dim3(256), 0, L.stream,
+                                        L.probs, ref, d));
 }
 
 template <typename R>
 void launch_bc_scalar(const Launch& L, int which, int nf, int d) {
-  hipLaunchKernelGGL(k_bc_scalar<R>, grid_for(L.ghost_work[d], L.nprob), dim3(256), 0, L.stream, L.probs,
-                     which, nf, d);
+  LG_TIMED(L, KC_BC_SCALAR, hipLaunchKernelGGL(k_bc_scalar<R>, grid_for(L.ghost_work[d], L.nprob), dim3(256), 0,
+                                               L.stream, L.probs, which, nf, d));
 }
 
 template <typename R>
 void launch_prim(const Launch& L, StateRef ref, int want_flags, const uint8_t* force) {
-  hipLaunchKernelGGL(k_prim<R>, grid_for(L.max_total, L.nprob), dim3(256), 0, L.stream, L.probs, ref,
-                     want_flags, force);
+  LG_TIMED(L, KC_PRIM, hipLaunchKernelGGL(k_prim<R>, grid_for(L.max_total, L.nprob), dim3(256), 0, L.stream,
+                                          L.probs, ref, want_flags, force));
 }
 
 void launch_any_flag(const Launch& L) {
   hipLaunchKernelGGL(k_zero_any, dim3(1, L.nprob), dim3(64), 0, L.stream, L.probs);
-  hipLaunchKernelGGL(k_any_flag, grid_for(L.max_cells, L.nprob), dim3(256), 0, L.stream, L.probs);
+  LG_TIMED(L, KC_FLAGS, hipLaunchKernelGGL(k_any_flag, grid_for(L.max_cells, L.nprob), dim3(256), 0, L.stream,
+                                           L.probs));
 }
 
 void launch_dilate(const Launch& L, int ndim) {
@@ -353,19 +355,21 @@ void launch_dilate(const Launch& L, int ndim) {
   int src = 0;
   for (int d = 0; d < ndim; ++d) {
     int dst = ((ndim - 1 - d) % 2 == 0) ? 2 : 1;
-    hipLaunchKernelGGL(k_dilate, grid_for(L.max_total, L.nprob), dim3(256), 0, L.stream, L.probs, d, src, dst);
+    LG_TIMED(L, KC_FLAGS, hipLaunchKernelGGL(k_dilate, grid_for(L.max_total, L.nprob), dim3(256), 0, L.stream,
+                                             L.probs, d, src, dst));
     src = dst;
   }
 }
 
 void launch_combine(const Launch& L, RKRef rr, int stage, double a, double b) {
-  hipLaunchKernelGGL(k_combine, grid_for(L.max_total, L.nprob), dim3(256), 0, L.stream, L.probs, rr, stage, a,
-                     b);
+  LG_TIMED(L, KC_COMBINE, hipLaunchKernelGGL(k_combine, grid_for(L.max_total, L.nprob), dim3(256), 0, L.stream,
+                                             L.probs, rr, stage, a, b));
 }
 
 void launch_dt(const Launch& L, const double* Qx, double* tx, double t_end, int advance_t) {
   hipLaunchKernelGGL(k_dt_reset, dim3(1, L.nprob), dim3(64), 0, L.stream, L.probs);
-  hipLaunchKernelGGL(k_dt_reduce, grid_for(L.max_cells, L.nprob), dim3(256), 0, L.stream, L.probs, Qx);
+  LG_TIMED(L, KC_DT, hipLaunchKernelGGL(k_dt_reduce, grid_for(L.max_cells, L.nprob), dim3(256), 0, L.stream,
+                                        L.probs, Qx));
   hipLaunchKernelGGL(k_dt_finalize, dim3(1, L.nprob), dim3(64), 0, L.stream, L.probs, tx, t_end, advance_t);
 }
 

@@ -170,17 +170,19 @@ void launch_grad_explicit(const Launch& L, int d, int order, int skip_if_any) {
   if (b > 8192) b = 8192;
   dim3 grid((unsigned)b, L.nprob);
   if (order == 6)
-    hipLaunchKernelGGL((k_grad_explicit<R, 6>), grid, dim3(256), 0, L.stream, L.probs, d, skip_if_any);
+    LG_TIMED(L, KC_GRAD_E6,
+             hipLaunchKernelGGL((k_grad_explicit<R, 6>), grid, dim3(256), 0, L.stream, L.probs, d, skip_if_any));
   else
-    hipLaunchKernelGGL((k_grad_explicit<R, 4>), grid, dim3(256), 0, L.stream, L.probs, d, skip_if_any);
+    LG_TIMED(L, KC_GRAD_E6,
+             hipLaunchKernelGGL((k_grad_explicit<R, 4>), grid, dim3(256), 0, L.stream, L.probs, d, skip_if_any));
 }
 
 template <typename R>
 void launch_grad_c4(const Launch& L, StateRef ref, int d, int skip_if_any) {
   long long b = (L.lines[d] + 63) / 64;
   if (b < 1) b = 1;
-  hipLaunchKernelGGL(k_grad_c4<R>, dim3((unsigned)b, L.nprob), dim3(64), 0, L.stream, L.probs, ref, d,
-                     skip_if_any);
+  LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c4<R>, dim3((unsigned)b, L.nprob), dim3(64), 0, L.stream,
+                                             L.probs, ref, d, skip_if_any));
 }
 
 template void launch_grad_explicit<float>(const Launch&, int, int, int);

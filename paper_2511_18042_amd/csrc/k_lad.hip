@@ -283,24 +283,26 @@ static inline dim3 g1(long long work, int nprob) {
 
 template <typename R>
 void launch_lad(const Launch& L, int skip_if_any) {
-  hipLaunchKernelGGL(k_lad_node<R>, g1(L.max_total, L.nprob), dim3(256), 0, L.stream, L.probs, skip_if_any);
-  hipLaunchKernelGGL(k_lad_raw<R>, g1(L.max_total, L.nprob), dim3(256), 0, L.stream, L.probs, skip_if_any);
+  LG_TIMED(L, KC_LAD_NODE, hipLaunchKernelGGL(k_lad_node<R>, g1(L.max_total, L.nprob), dim3(256), 0, L.stream,
+                                              L.probs, skip_if_any));
+  LG_TIMED(L, KC_LAD_RAW, hipLaunchKernelGGL(k_lad_raw<R>, g1(L.max_total, L.nprob), dim3(256), 0, L.stream,
+                                             L.probs, skip_if_any));
   for (int d = 0; d < L.ndim; ++d) launch_bc_scalar<R>(L, 0, 3, d);
   int src = 0;
   for (int d = 0; d < L.ndim; ++d) {
-    hipLaunchKernelGGL(k_gauss<R>, g1(L.max_total, L.nprob), dim3(256), 0, L.stream, L.probs, d, src,
-                       skip_if_any);
+    LG_TIMED(L, KC_GAUSS, hipLaunchKernelGGL(k_gauss<R>, g1(L.max_total, L.nprob), dim3(256), 0, L.stream,
+                                             L.probs, d, src, skip_if_any));
     src ^= 1;
     for (int e = 0; e < L.ndim; ++e) launch_bc_scalar<R>(L, src, 3, e);
   }
-  hipLaunchKernelGGL(k_lad_nodeflux<R>, g1(L.max_total, L.nprob), dim3(256), 0, L.stream, L.probs, src,
-                     skip_if_any);
+  LG_TIMED(L, KC_LAD_FLUX, hipLaunchKernelGGL(k_lad_nodeflux<R>, g1(L.max_total, L.nprob), dim3(256), 0,
+                                              L.stream, L.probs, src, skip_if_any));
 }
 
 template <typename R>
 void launch_gbr_viscflux(const Launch& L, int skip_if_any) {
-  hipLaunchKernelGGL(k_gbr_viscflux<R>, g1(L.max_total, L.nprob), dim3(256), 0, L.stream, L.probs,
-                     skip_if_any);
+  LG_TIMED(L, KC_VISC, hipLaunchKernelGGL(k_gbr_viscflux<R>, g1(L.max_total, L.nprob), dim3(256), 0, L.stream,
+                                          L.probs, skip_if_any));
 }
 
 template void launch_lad<float>(const Launch&, int);

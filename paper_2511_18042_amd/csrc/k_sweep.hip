@@ -361,7 +361,8 @@ template <typename R>
 void launch_sensor(const Launch& L, int skip_if_any) {
   long long b = (L.max_total + 255) / 256;
   if (b > 8192) b = 8192;
-  hipLaunchKernelGGL(k_sensor<R>, dim3((unsigned)b, L.nprob), dim3(256), 0, L.stream, L.probs, skip_if_any);
+  LG_TIMED(L, KC_SENSOR, hipLaunchKernelGGL(k_sensor<R>, dim3((unsigned)b, L.nprob), dim3(256), 0, L.stream,
+                                            L.probs, skip_if_any));
 }
 
 template <typename R>
@@ -371,16 +372,17 @@ void launch_sweep(const Launch& L, StateRef ref, int d, int sel, int accumulate)
     long long waves = nseg * L.sweep_rows[0];
     long long blocks = (waves + 3) / 4;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_sweep_x<R>, dim3((unsigned)blocks, L.nprob), dim3(256), 0, L.stream, L.probs, ref, sel,
-                       accumulate);
+    LG_TIMED(L, KC_SWEEP_X, hipLaunchKernelGGL(k_sweep_x<R>, dim3((unsigned)blocks, L.nprob), dim3(256), 0,
+                                               L.stream, L.probs, ref, sel, accumulate));
   } else {
     int seg = L.seg > 0 ? L.seg : 16;
     long long nch = (L.max_n[d] + seg - 1) / seg;
     long long work = nch * L.sweep_rows[d];
     long long blocks = (work + 255) / 256;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_sweep_s<R>, dim3((unsigned)blocks, L.nprob), dim3(256), 0, L.stream, L.probs, ref, d,
-                       sel, accumulate, seg);
+    LG_TIMED(L, d == 1 ? KC_SWEEP_Y : KC_SWEEP_Z,
+             hipLaunchKernelGGL(k_sweep_s<R>, dim3((unsigned)blocks, L.nprob), dim3(256), 0, L.stream, L.probs, ref,
+                                d, sel, accumulate, seg));
   }
 }
 

@@ -56,6 +56,7 @@ struct lg_ctx {
   Prob hp;
   Prob* dp = nullptr;
   Launch L;
+  lg::Prof prof{};
   Cfg cfg;
   hipStream_t stream = nullptr;
   std::vector<void*> allocs;
@@ -381,9 +382,61 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
   return LG_OK;
 }
 
+static void prof_release(lg_ctx* c) {
+  if (c->prof.ev) {
+    for (int i = 0; i < 2 * c->prof.cap; ++i) (void)hipEventDestroy(c->prof.ev[i]);
+    delete[] c->prof.ev;
+    delete[] c->prof.cls;
+  }
+  c->prof = lg::Prof{};
+  c->L.prof = nullptr;
+}
+
+lg_status lg_prof_start(lg_ctx* c, int kernel_class, int max_launches) {
+  if (!c || max_launches < 1 || kernel_class < -1 || kernel_class >= lg::KC_COUNT) return LG_EINVAL;
+  prof_release(c);
+  c->prof.ev = new (std::nothrow) hipEvent_t[2 * max_launches];
+  c->prof.cls = new (std::nothrow) int[max_launches];
+  if (!c->prof.ev || !c->prof.cls) return LG_ENOMEM;
+  for (int i = 0; i < 2 * max_launches; ++i)
+    if (hipEventCreate(&c->prof.ev[i]) != hipSuccess) {
+      c->prof.cap = i / 2;
+      prof_release(c);
+      return LG_EHIP;
+    }
+  c->prof.cap = max_launches;
+  c->prof.n = 0;
+  c->prof.target = kernel_class;
+  c->prof.enabled = 1;
+  c->L.prof = &c->prof;
+  return LG_OK;
+}
+
+lg_status lg_prof_stop(lg_ctx* c, double* ms, int* launches) {
+  if (!c || !ms || !launches) return LG_EINVAL;
+  for (int k = 0; k < lg::KC_COUNT; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  if (!c->prof.ev) return LG_EINVAL;
+  lg_status st = hipStreamSynchronize(c->stream) == hipSuccess ? LG_OK : LG_EHIP;
+  for (int i = 0; i < c->prof.n && st == LG_OK; ++i) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, c->prof.ev[2 * i], c->prof.ev[2 * i + 1]) != hipSuccess) {
+      st = LG_EHIP;
+      break;
+    }
+    ms[c->prof.cls[i]] += t;
+    launches[c->prof.cls[i]] += 1;
+  }
+  prof_release(c);
+  return st;
+}
+
 void lg_destroy(lg_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  prof_release(c);
   for (void* p : c->allocs) dev_free(p);
   delete c;
 }

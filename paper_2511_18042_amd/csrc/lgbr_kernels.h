@@ -23,6 +23,21 @@ struct RKRef {
   double* out;
 };
 
+// Kernel classes for the optional per-launch event timing (lg_prof_start / lg_prof_stop).
+enum KClass {
+  KC_BC = 0, KC_PRIM, KC_FLAGS, KC_GRAD_E6, KC_GRAD_C4, KC_SENSOR, KC_VISC, KC_LAD_NODE, KC_LAD_RAW,
+  KC_GAUSS, KC_LAD_FLUX, KC_SWEEP_X, KC_SWEEP_Y, KC_SWEEP_Z, KC_COMBINE, KC_DT, KC_BC_SCALAR, KC_COUNT
+};
+
+// Event pairs recorded around launches while enabled (never during graph capture).
+struct Prof {
+  int enabled;
+  int target;       // KClass to time, or -1 for all
+  int n, cap;
+  hipEvent_t* ev;   // 2 * cap events
+  int* cls;         // class of each recorded launch
+};
+
 // Launch geometry shared by all problems of one launch (maxima over the problems).
 struct Launch {
   const Prob* probs;   // device array
@@ -37,7 +52,33 @@ struct Launch {
   long long sweep_rows[3]; // interior lines (interior of the other two dims) per direction
   int ndim;
   int seg;                 // nodes per thread in the strided sweeps
+  Prof* prof;              // optional launch timing (null: off)
 };
+
+inline bool prof_on(const Launch& L, int k) {
+  return L.prof && L.prof->enabled && (L.prof->target < 0 || L.prof->target == k) && L.prof->n < L.prof->cap;
+}
+inline void prof_begin(const Launch& L, int k) {
+  if (prof_on(L, k)) {
+    (void)hipEventRecord(L.prof->ev[2 * L.prof->n], L.stream);
+    L.prof->cls[L.prof->n] = k;
+  }
+}
+inline void prof_end(const Launch& L, int k) {
+  if (L.prof && L.prof->enabled && L.prof->n < L.prof->cap && L.prof->cls[L.prof->n] == k &&
+      (L.prof->target < 0 || L.prof->target == k)) {
+    (void)hipEventRecord(L.prof->ev[2 * L.prof->n + 1], L.stream);
+    L.prof->n++;
+  }
+}
+
+// RAII-free helper: time one launch statement
+#define LG_TIMED(L, k, stmt) \
+  do {                       \
+    prof_begin((L), (k));    \
+    stmt;                    \
+    prof_end((L), (k));      \
+  } while (0)
 
 void launch_bc_cons(const Launch& L, StateRef ref, int d);
 template <typename R> void launch_bc_scalar(const Launch& L, int which, int nf, int d);

@@ -20,7 +20,10 @@ SCHEMES = {'cgbr': SCHEME_CGBR, 'lad': SCHEME_LAD, 'hybrid': SCHEME_HYBRID}
 
 EXPORTS = ('lg_set_allocator', 'lg_strerror', 'lg_create', 'lg_destroy', 'lg_workspace_bytes',
            'lg_metrics_from_coords', 'cgbr_rhs', 'lad_rhs', 'hybrid_rhs', 'rk3_step', 'lg_rk3_stage',
-           'lg_compute_dt', 'lg_batch_create', 'lg_batch_run', 'lg_batch_destroy', 'lg_poll_status')
+           'lg_compute_dt', 'lg_batch_create', 'lg_batch_run', 'lg_batch_destroy', 'lg_poll_status',
+           'lg_prof_start', 'lg_prof_stop')
+KERNEL_CLASSES = ('bc', 'prim', 'flags', 'grad_e6', 'grad_c4', 'sensor', 'visc', 'lad_node', 'lad_raw', 'gauss',
+                  'lad_flux', 'sweep_x', 'sweep_y', 'sweep_z', 'combine', 'dt', 'bc_scalar')
 
 
 class LgGrid(ctypes.Structure):
@@ -71,6 +74,8 @@ def load():
         'lg_batch_run': (I, [P]),
         'lg_batch_destroy': (None, [P]),
         'lg_poll_status': (I, [P, ctypes.POINTER(I)]),
+        'lg_prof_start': (I, [P, I, I]),
+        'lg_prof_stop': (I, [P, ctypes.POINTER(D), ctypes.POINTER(I)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -189,6 +194,17 @@ class Context:
 
     def compute_dt(self, Q, dt_dev):
         _check(self._lib.lg_compute_dt(self.handle, _ptr(Q), _ptr(dt_dev)), 'lg_compute_dt')
+
+    def prof_start(self, kernel_class=-1, max_launches=100000):
+        k = kernel_class if isinstance(kernel_class, int) else KERNEL_CLASSES.index(kernel_class)
+        _check(self._lib.lg_prof_start(self.handle, k, int(max_launches)), 'lg_prof_start')
+
+    def prof_stop(self):
+        n = len(KERNEL_CLASSES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int * n)()
+        _check(self._lib.lg_prof_stop(self.handle, ms, cnt), 'lg_prof_stop')
+        return {KERNEL_CLASSES[k]: (ms[k], cnt[k]) for k in range(n) if cnt[k]}
 
     def poll_status(self):
         n = ctypes.c_int(0)

@@ -6,6 +6,9 @@ Tolerance rule (FP64 path):
   * right-hand side: max |L_gpu - L_oracle| <= 1e-10 * max |L_oracle| per conserved variable
     (the RHS is a flux difference scaled by J; rounding of O(1e-16 |F|) in the fluxes
     becomes O(1e-15) of the largest RHS on data with O(1) jumps, so 1e-10 leaves margin);
+  * every bound also carries an absolute floor of 1e-12 times the largest value over all
+    five variables, so that a component that vanishes identically (e.g. the y-momentum RHS
+    of a flow at rest) is not compared against its own round-off;
   * a node may exceed the bound only if the oracle recorded a threshold decision on one of
     its interfaces within 1e-10 of the threshold (R22); at most 0.1 % of nodes.
 """
@@ -77,6 +80,7 @@ def compare(gpu, ref, grid, rtol, excuse=None, label=''):
     inner = grid.interior()
     n_nodes = int(np.prod([s.stop - s.start for s in inner]))
     bad_any = np.zeros(grid.shape, bool)
+    floor = 1e-12 * max(np.max(np.abs(ref[q][inner])) for q in range(ref.shape[0]))
     for q in range(ref.shape[0]):
         r = ref[q][inner]
         gv = gpu[q][inner]
@@ -84,7 +88,7 @@ def compare(gpu, ref, grid, rtol, excuse=None, label=''):
         if scale == 0.0:
             scale = 1.0
         err = np.abs(gv - r)
-        bad = ~(err <= rtol * scale)
+        bad = ~(err <= rtol * scale + floor)
         full = np.zeros(grid.shape, bool)
         full[inner] = bad
         bad_any |= full
