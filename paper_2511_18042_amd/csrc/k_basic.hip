@@ -23,7 +23,7 @@ __device__ __forceinline__ bool ghost_src(int bct, int side, int m, int g, int n
   return true;
 }
 
-__global__ void __launch_bounds__(256) k_bc_cons(const Prob* probs, StateRef ref, int d) {
+__global__ void __launch_bounds__(256) k_bc_cons(const Prob* __restrict__ probs, StateRef ref, int d) {
   const Prob& P = probs[blockIdx.y];
   if (d >= P.ndim) return;
   double* Q = ref.state(P);
@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(256) k_bc_cons(const Prob* probs, StateRef ref
 
 // Scalar intermediate fields: same images with even parity; FIXED -> nearest copy.
 template <typename R>
-__global__ void __launch_bounds__(256) k_bc_scalar(const Prob* probs, int which, int nf, int d) {
+__global__ void __launch_bounds__(256) k_bc_scalar(const Prob* __restrict__ probs, int which, int nf, int d) {
   const Prob& P = probs[blockIdx.y];
   if (d >= P.ndim) return;
   R* F = static_cast<R*>(which == 0 ? P.CA : P.CB);
@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(256) k_bc_scalar(const Prob* probs, int which,
 
 // ------------------------------------------------------------------ primitives + flags
 template <typename R>
-__global__ void __launch_bounds__(256) k_prim(const Prob* probs, StateRef ref, int want_flags,
+__global__ void __launch_bounds__(256) k_prim(const Prob* __restrict__ probs, StateRef ref, int want_flags,
                                               const uint8_t* force) {
   const Prob& P = probs[blockIdx.y];
   const double* Q = ref.state(P);
@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(256) k_prim(const Prob* probs, StateRef ref, i
 }
 
 // ------------------------------------------------------------------ global hybrid switch
-__global__ void __launch_bounds__(256) k_any_flag(const Prob* probs) {
+__global__ void __launch_bounds__(256) k_any_flag(const Prob* __restrict__ probs) {
   const Prob& P = probs[blockIdx.y];
   const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
   const int cnt = n0 * n1 * n2;
@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(256) k_any_flag(const Prob* probs) {
 
 // Separable box dilation by P.dilate nodes along direction d.
 // src/dst: 0 = f, 1 = ftmp, 2 = ft.
-__global__ void __launch_bounds__(256) k_dilate(const Prob* probs, int d, int src, int dst) {
+__global__ void __launch_bounds__(256) k_dilate(const Prob* __restrict__ probs, int d, int src, int dst) {
   const Prob& P = probs[blockIdx.y];
   if (d >= P.ndim) return;
   const uint8_t* in = src == 0 ? P.f : (src == 1 ? P.ftmp : P.ft);
@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(256) k_dilate(const Prob* probs, int d, int sr
 // ------------------------------------------------------------------ RK3 combination
 // out = a U^n + b (U^s + dt L) on interior nodes, out = U^n on ghost nodes; counts
 // non-physical interior results (rho <= 0, p <= 0 or not finite).
-__global__ void __launch_bounds__(256) k_combine(const Prob* probs, RKRef rr, int stage, double a, double b) {
+__global__ void __launch_bounds__(256) k_combine(const Prob* __restrict__ probs, RKRef rr, int stage, double a, double b) {
   const Prob& P = probs[blockIdx.y];
   const double* Un = rr.Un ? rr.Un : P.Q;
   const double* Us = rr.Us ? rr.Us : (stage == 0 ? Un : P.Us);
@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(256) k_combine(const Prob* probs, RKRef rr, in
 // ------------------------------------------------------------------ CFL time step
 // Spectral radius sum_l (|xi_l . u| + c |xi_l|) with xi_l = J l_hat, max over the
 // interior; kept as the bit pattern of a positive double so that an integer max works.
-__global__ void __launch_bounds__(256) k_dt_reduce(const Prob* probs, const double* Qx) {
+__global__ void __launch_bounds__(256) k_dt_reduce(const Prob* __restrict__ probs, const double* Qx) {
   const Prob& P = probs[blockIdx.y];
   const double* Q = Qx ? Qx : P.Q;
   const size_t T = P.total;
@@ -197,17 +197,28 @@ __global__ void __launch_bounds__(256) k_dt_reduce(const Prob* probs, const doub
     }
     if (!(s <= smax)) smax = s;  // NaN propagates as "larger"
   }
-  for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_down(smax, off));
-  if ((threadIdx.x & 63) == 0)
-    atomicMax(P.smax, (unsigned long long)__double_as_longlong(smax));
+  // wave, then block reduction; one atomic per block
+  for (int off = 32; off > 0; off >>= 1) {
+    double o = __shfl_down(smax, off);
+    if (!(o <= smax)) smax = o;
+  }
+  __shared__ double part[4];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = smax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = part[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+      if (!(part[w] <= m)) m = part[w];
+    atomicMax(P.smax, (unsigned long long)__double_as_longlong(m));
+  }
 }
 
-__global__ void k_dt_reset(const Prob* probs) {
+__global__ void k_dt_reset(const Prob* __restrict__ probs) {
   const Prob& P = probs[blockIdx.y];
   if (threadIdx.x == 0) *P.smax = 0ull;
 }
 
-__global__ void k_dt_finalize(const Prob* probs, double* tx, double t_end, int advance_t) {
+__global__ void k_dt_finalize(const Prob* __restrict__ probs, double* tx, double t_end, int advance_t) {
   const Prob& P = probs[blockIdx.y];
   if (threadIdx.x != 0) return;
   double smax = __longlong_as_double((long long)*P.smax);
@@ -223,17 +234,17 @@ __global__ void k_dt_finalize(const Prob* probs, double* tx, double t_end, int a
   *P.dt = dt;
 }
 
-__global__ void k_set_dt(const Prob* probs, double dt) {
+__global__ void k_set_dt(const Prob* __restrict__ probs, double dt) {
   const Prob& P = probs[blockIdx.y];
   if (threadIdx.x == 0) *P.dt = dt;
 }
 
-__global__ void k_zero_status(const Prob* probs) {
+__global__ void k_zero_status(const Prob* __restrict__ probs) {
   const Prob& P = probs[blockIdx.y];
   if (threadIdx.x == 0) *P.status = 0;
 }
 
-__global__ void k_zero_any(const Prob* probs) {
+__global__ void k_zero_any(const Prob* __restrict__ probs) {
   const Prob& P = probs[blockIdx.y];
   if (threadIdx.x == 0) *P.any_flag = 0;
 }
@@ -368,8 +379,8 @@ void launch_combine(const Launch& L, RKRef rr, int stage, double a, double b) {
 
 void launch_dt(const Launch& L, const double* Qx, double* tx, double t_end, int advance_t) {
   hipLaunchKernelGGL(k_dt_reset, dim3(1, L.nprob), dim3(64), 0, L.stream, L.probs);
-  LG_TIMED(L, KC_DT, hipLaunchKernelGGL(k_dt_reduce, grid_for(L.max_cells, L.nprob), dim3(256), 0, L.stream,
-                                        L.probs, Qx));
+  LG_TIMED(L, KC_DT, hipLaunchKernelGGL(k_dt_reduce, grid_for(L.max_cells, L.nprob, 256, 1024), dim3(256), 0,
+                                        L.stream, L.probs, Qx));
   hipLaunchKernelGGL(k_dt_finalize, dim3(1, L.nprob), dim3(64), 0, L.stream, L.probs, tx, t_end, advance_t);
 }
 

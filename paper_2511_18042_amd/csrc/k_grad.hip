@@ -11,9 +11,9 @@
 // second-order one-sided end rows; a periodic line is solved cyclically over its
 // interior nodes (Sherman-Morrison on top of a bounded solve) and its ghost values are
 // the periodic images.  The solves run in FP64 from primitives formed in FP64 from the
-// conserved state, whatever the bulk precision.  Each thread owns one line; the LU
-// factors of the constant-coefficient matrices are precomputed on the host (tables
-// below), so a solve is one forward and one backward sweep.
+// conserved state, whatever the bulk precision.  Each lane owns one (line, primitive)
+// pair; the LU factors of the constant-coefficient matrices are precomputed on the host
+// (tables below), so a solve is one forward and one backward sweep.
 //
 // Table layout for direction d (double):
 //   bounded  line of N nodes: cp[0..N), inv[0..N)
@@ -28,7 +28,7 @@ __device__ __forceinline__ bool skip_launch(const Prob& P, int skip_if_any) {
 }
 
 template <typename R, int ORDER>
-__global__ void __launch_bounds__(256) k_grad_explicit(const Prob* probs, int d, int skip_if_any) {
+__global__ void __launch_bounds__(256) k_grad_explicit(const Prob* __restrict__ probs, int d, int skip_if_any) {
   const Prob& P = probs[blockIdx.y];
   if (d >= P.ndim || skip_launch(P, skip_if_any)) return;
   const R* W = static_cast<const R*>(P.W);
@@ -50,116 +50,87 @@ __global__ void __launch_bounds__(256) k_grad_explicit(const Prob* probs, int d,
   }
 }
 
-__device__ __forceinline__ void prim64(const double* Q, size_t T, size_t o, double gamma, double w[5]) {
+__device__ __forceinline__ double prim_q(int q, const double* Q, size_t T, size_t o, double gm1) {
   double rho = Q[o];
-  double u = Q[T + o] / rho, v = Q[2 * T + o] / rho, ww = Q[3 * T + o] / rho;
-  w[0] = rho;
-  w[1] = u;
-  w[2] = v;
-  w[3] = ww;
-  w[4] = (gamma - 1.0) * (Q[4 * T + o] - 0.5 * rho * (u * u + v * v + ww * ww));
+  if (q == 0) return rho;
+  if (q <= 3) return Q[q * T + o] / rho;
+  double u = Q[T + o] / rho, v = Q[2 * T + o] / rho, w = Q[3 * T + o] / rho;
+  return gm1 * (Q[4 * T + o] - 0.5 * rho * (u * u + v * v + w * w));
 }
 
+// One lane per (line, primitive variable): forward elimination stores d' in the FP64
+// scratch, back substitution writes the gradient.
 template <typename R>
-__global__ void __launch_bounds__(256) k_grad_c4(const Prob* probs, StateRef ref, int d, int skip_if_any) {
+__global__ void __launch_bounds__(256) k_grad_c4(const Prob* __restrict__ probs, StateRef ref, int d, int skip_if_any) {
   const Prob& P = probs[blockIdx.y];
   if (d >= P.ndim || skip_launch(P, skip_if_any)) return;
-  const double* Q = ref.state(P);
-  R* G = static_cast<R*>(P.G[d]);
-  double* S = P.T64;
-  const double* tab = P.tri[d];
-  const size_t T = P.total;
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   const int nlines = P.N[o1] * P.N[o2];
-  const int line = blockIdx.x * blockDim.x + threadIdx.x;
-  if (line >= nlines) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 5 * nlines) return;
+  const int line = t % nlines, q = t / nlines;
+  const double* Q = ref.state(P);
+  R* G = static_cast<R*>(P.G[d]) + (size_t)q * P.total;
+  const size_t T = P.total;
+  double* S = P.T64 + (size_t)q * T;
+  const double* tab = P.tri[d];
   const int a = line % P.N[o1], b = line / P.N[o1];
   const size_t base = (size_t)a * P.s[o1] + (size_t)b * P.s[o2];
   const int sd = P.s[d], g = P.g[d], n = P.n[d], N = P.N[d];
-  const double gam = P.gamma;
+  const double gm1 = P.gamma - 1.0;
+  auto f = [&](int pos) { return prim_q(q, Q, T, base + (size_t)pos * sd, gm1); };
 
   if (P.bc[d][0] != BC_PERIODIC) {
     const double* cp = tab;
     const double* inv = tab + N;
-    // forward sweep: d'_i stored in S
-    double wm[5], w0[5], wp[5], dprev[5];
-    prim64(Q, T, base, gam, w0);
-    prim64(Q, T, base + sd, gam, wp);
-    {
-      double w2[5];
-      prim64(Q, T, base + 2 * sd, gam, w2);
-      for (int q = 0; q < 5; ++q) {
-        double rhs = (-3.0 * w0[q] + 4.0 * wp[q] - w2[q]) / 2.0;
-        dprev[q] = rhs;
-        S[q * T + base] = rhs;
-      }
-    }
+    double fm = f(0), f0 = f(1), fp;
+    double dprev = (-3.0 * fm + 4.0 * f0 - f(2)) / 2.0;   // row 0 (one-sided, decoupled)
+    S[base] = dprev;
     for (int i = 1; i < N - 1; ++i) {
-      for (int q = 0; q < 5; ++q) { wm[q] = w0[q]; w0[q] = wp[q]; }
-      prim64(Q, T, base + (size_t)(i + 1) * sd, gam, wp);
-      for (int q = 0; q < 5; ++q) {
-        double rhs = 0.75 * (wp[q] - wm[q]);
-        double dd = (rhs - 0.25 * dprev[q]) * inv[i];
-        dprev[q] = dd;
-        S[q * T + base + (size_t)i * sd] = dd;
-      }
+      fp = f(i + 1);
+      double dd = (0.75 * (fp - fm) - 0.25 * dprev) * inv[i];
+      S[base + (size_t)i * sd] = dd;
+      dprev = dd;
+      fm = f0;
+      f0 = fp;
     }
-    // last row: one-sided, decoupled
-    double y[5];
-    {
-      double w3[5];
-      prim64(Q, T, base + (size_t)(N - 3) * sd, gam, w3);
-      for (int q = 0; q < 5; ++q) y[q] = (3.0 * wp[q] - 4.0 * w0[q] + w3[q]) / 2.0;
-    }
-    for (int q = 0; q < 5; ++q) G[q * T + base + (size_t)(N - 1) * sd] = (R)y[q];
+    // last row (one-sided, decoupled): f0 = f(N-1), fm = f(N-2)
+    double y = (3.0 * f0 - 4.0 * fm + f(N - 3)) / 2.0;
+    G[base + (size_t)(N - 1) * sd] = (R)y;
     for (int i = N - 2; i >= 0; --i) {
-      for (int q = 0; q < 5; ++q) {
-        y[q] = S[q * T + base + (size_t)i * sd] - cp[i] * y[q];
-        G[q * T + base + (size_t)i * sd] = (R)y[q];
-      }
+      y = S[base + (size_t)i * sd] - cp[i] * y;
+      G[base + (size_t)i * sd] = (R)y;
     }
   } else {
+    // cyclic system over the interior (the ghosts hold the periodic images):
+    // B y = r, x = y - (v.y) fac z with v.y = y_0 - y_{n-1}/4 (Sherman-Morrison)
     const double* cp = tab;
     const double* inv = tab + n;
     const double* z = tab + 2 * n;
     const double fac = tab[3 * n];
-    // B y = r over the interior; r_i = 3/4 (f_{i+1} - f_{i-1}) with periodic neighbours
-    // (the ghosts already hold the periodic images)
     const size_t b0 = base + (size_t)g * sd;
-    double wm[5], w0[5], wp[5], dprev[5];
-    prim64(Q, T, b0 - sd, gam, wm);
-    prim64(Q, T, b0, gam, w0);
+    double fm = f(g - 1), f0 = f(g), fp, dprev = 0.0;
     for (int i = 0; i < n; ++i) {
-      prim64(Q, T, b0 + (size_t)(i + 1) * sd, gam, wp);
-      for (int q = 0; q < 5; ++q) {
-        double rhs = 0.75 * (wp[q] - wm[q]);
-        double dd = (i == 0 ? rhs : rhs - 0.25 * dprev[q]) * inv[i];
-        dprev[q] = dd;
-        S[q * T + b0 + (size_t)i * sd] = dd;
-        wm[q] = w0[q];
-        w0[q] = wp[q];
-      }
+      fp = f(g + i + 1);
+      double rhs = 0.75 * (fp - fm);
+      double dd = (i == 0 ? rhs : rhs - 0.25 * dprev) * inv[i];
+      S[b0 + (size_t)i * sd] = dd;
+      dprev = dd;
+      fm = f0;
+      f0 = fp;
     }
-    double y[5], ylast[5];
-    for (int q = 0; q < 5; ++q) { y[q] = dprev[q]; ylast[q] = y[q]; }
-    for (int i = n - 2; i >= 0; --i)
-      for (int q = 0; q < 5; ++q) {
-        y[q] = S[q * T + b0 + (size_t)i * sd] - cp[i] * y[q];
-        S[q * T + b0 + (size_t)i * sd] = y[q];
-      }
-    // y now holds y_0; Sherman-Morrison correction x = y - (v.y) fac z, v.y = y_0 - y_{n-1}/4
-    double vy[5];
-    for (int q = 0; q < 5; ++q) vy[q] = (y[q] - 0.25 * ylast[q]) * fac;
-    S[0 * T + b0 + (size_t)(n - 1) * sd] = ylast[0];
-    for (int q = 1; q < 5; ++q) S[q * T + b0 + (size_t)(n - 1) * sd] = ylast[q];
+    double y = dprev, ylast = dprev;
+    for (int i = n - 2; i >= 0; --i) {
+      y = S[b0 + (size_t)i * sd] - cp[i] * y;
+      S[b0 + (size_t)i * sd] = y;
+    }
+    const double vy = (y - 0.25 * ylast) * fac;
     for (int i = 0; i < n; ++i) {
-      for (int q = 0; q < 5; ++q) {
-        double x = S[q * T + b0 + (size_t)i * sd] - vy[q] * z[i];
-        R xv = (R)x;
-        G[q * T + b0 + (size_t)i * sd] = xv;
-        if (i >= n - g) G[q * T + b0 + (size_t)(i - n) * sd] = xv;   // low ghosts
-        if (i < g) G[q * T + b0 + (size_t)(i + n) * sd] = xv;        // high ghosts
-      }
+      double yi = (i == n - 1) ? ylast : S[b0 + (size_t)i * sd];
+      R xv = (R)(yi - vy * z[i]);
+      G[b0 + (size_t)i * sd] = xv;
+      if (i >= n - g) G[b0 + (size_t)(i - n) * sd] = xv;   // low ghosts
+      if (i < g) G[b0 + (size_t)(i + n) * sd] = xv;        // high ghosts
     }
   }
 }
@@ -179,9 +150,9 @@ void launch_grad_explicit(const Launch& L, int d, int order, int skip_if_any) {
 
 template <typename R>
 void launch_grad_c4(const Launch& L, StateRef ref, int d, int skip_if_any) {
-  long long b = (L.lines[d] + 63) / 64;
+  long long b = (5 * L.lines[d] + 255) / 256;
   if (b < 1) b = 1;
-  LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c4<R>, dim3((unsigned)b, L.nprob), dim3(64), 0, L.stream,
+  LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c4<R>, dim3((unsigned)b, L.nprob), dim3(256), 0, L.stream,
                                              L.probs, ref, d, skip_if_any));
 }
 

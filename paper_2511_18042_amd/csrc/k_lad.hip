@@ -106,7 +106,7 @@ __device__ __forceinline__ bool is_interior(const Prob& P, int idx) { return in_
 
 // |S|, div u and e at every node where E4 fits (positions -3 .. n+2)
 template <typename R>
-__global__ void __launch_bounds__(256) k_lad_node(const Prob* probs, int skip_if_any) {
+__global__ void __launch_bounds__(256) k_lad_node(const Prob* __restrict__ probs, int skip_if_any) {
   const Prob& P = probs[blockIdx.y];
   if (lad_skip(P, skip_if_any)) return;
   const R* W = static_cast<const R*>(P.W);
@@ -137,7 +137,7 @@ __device__ __forceinline__ R delta4(const R* f, int idx, int s) {
 
 // raw (unfiltered) coefficients at interior nodes
 template <typename R>
-__global__ void __launch_bounds__(256) k_lad_raw(const Prob* probs, int skip_if_any) {
+__global__ void __launch_bounds__(256) k_lad_raw(const Prob* __restrict__ probs, int skip_if_any) {
   const Prob& P = probs[blockIdx.y];
   if (lad_skip(P, skip_if_any)) return;
   const R* W = static_cast<const R*>(P.W);
@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(256) k_lad_raw(const Prob* probs, int skip_if_
 
 // one truncated-Gaussian pass along d at interior nodes (3 fields)
 template <typename R>
-__global__ void __launch_bounds__(256) k_gauss(const Prob* probs, int d, int src, int skip_if_any) {
+__global__ void __launch_bounds__(256) k_gauss(const Prob* __restrict__ probs, int d, int src, int skip_if_any) {
   const Prob& P = probs[blockIdx.y];
   if (d >= P.ndim || lad_skip(P, skip_if_any)) return;
   const R* in = static_cast<const R*>(src == 0 ? P.CA : P.CB);
@@ -216,7 +216,7 @@ __global__ void __launch_bounds__(256) k_gauss(const Prob* probs, int d, int src
 
 // LAD node fluxes F^c + F^v for every active direction at positions -2 .. n+1
 template <typename R>
-__global__ void __launch_bounds__(256) k_lad_nodeflux(const Prob* probs, int coef_buf, int skip_if_any) {
+__global__ void __launch_bounds__(256) k_lad_nodeflux(const Prob* __restrict__ probs, int coef_buf, int skip_if_any) {
   const Prob& P = probs[blockIdx.y];
   if (lad_skip(P, skip_if_any)) return;
   const R* W = static_cast<const R*>(P.W);
@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(256) k_lad_nodeflux(const Prob* probs, int coe
 
 // C-GBR viscous node fluxes (physical coefficients, the scheme's gradients)
 template <typename R>
-__global__ void __launch_bounds__(256) k_gbr_viscflux(const Prob* probs, int skip_if_any) {
+__global__ void __launch_bounds__(256) k_gbr_viscflux(const Prob* __restrict__ probs, int skip_if_any) {
   const Prob& P = probs[blockIdx.y];
   if (lad_skip(P, skip_if_any)) return;
   const R* W = static_cast<const R*>(P.W);

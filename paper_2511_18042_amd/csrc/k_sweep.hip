@@ -40,7 +40,7 @@ __device__ __forceinline__ bool band(const Prob& P, int idx, int lo, int hi) {
 
 // ------------------------------------------------------------------ sensor
 template <typename R>
-__global__ void __launch_bounds__(256) k_sensor(const Prob* probs, int skip_if_any) {
+__global__ void __launch_bounds__(256) k_sensor(const Prob* __restrict__ probs, int skip_if_any) {
   const Prob& P = probs[blockIdx.y];
   if (sw_skip(P, skip_if_any)) return;
   const R* W = static_cast<const R*>(P.W);
@@ -287,7 +287,7 @@ __device__ __forceinline__ double node_J(const Prob& P, int idx) {
 // row segment of 63 nodes; lane t computes the interface left of node (seg*63 + t - 1) + 1
 // and the flux difference uses the neighbour lane's flux.
 template <typename R>
-__global__ void __launch_bounds__(256) k_sweep_x(const Prob* probs, StateRef ref, int sel, int accumulate) {
+__global__ void __launch_bounds__(256) k_sweep_x(const Prob* __restrict__ probs, StateRef ref, int sel, int accumulate) {
   const Prob& P = probs[blockIdx.y];
   const int lane = threadIdx.x & 63;
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -319,7 +319,7 @@ __global__ void __launch_bounds__(256) k_sweep_x(const Prob* probs, StateRef ref
 // ------------------------------------------------------------------ strided sweeps: one
 // lane per line segment of `seg` nodes, sliding along the line.
 template <typename R>
-__global__ void __launch_bounds__(256) k_sweep_s(const Prob* probs, StateRef ref, int d, int sel,
+__global__ void __launch_bounds__(256) k_sweep_s(const Prob* __restrict__ probs, StateRef ref, int d, int sel,
                                                  int accumulate, int seg) {
   const Prob& P = probs[blockIdx.y];
   if (d >= P.ndim) return;
@@ -375,7 +375,16 @@ void launch_sweep(const Launch& L, StateRef ref, int d, int sel, int accumulate)
     LG_TIMED(L, KC_SWEEP_X, hipLaunchKernelGGL(k_sweep_x<R>, dim3((unsigned)blocks, L.nprob), dim3(256), 0,
                                                L.stream, L.probs, ref, sel, accumulate));
   } else {
-    int seg = L.seg > 0 ? L.seg : 16;
+    // nodes per lane: the longest segment that still gives >= 8 waves per CU (256 CUs)
+    int seg = L.seg;
+    if (seg <= 0) {
+      seg = 4;
+      for (int c = 32; c >= 4; c >>= 1)
+        if (((L.max_n[d] + c - 1) / c) * L.sweep_rows[d] * L.nprob >= 256LL * 8 * 64) {
+          seg = c;
+          break;
+        }
+    }
     long long nch = (L.max_n[d] + seg - 1) / seg;
     long long work = nch * L.sweep_rows[d];
     long long blocks = (work + 255) / 256;
