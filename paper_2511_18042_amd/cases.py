@@ -248,3 +248,102 @@ def entropy_wave(n, t=0.0):
     one = np.ones_like(x)
     c.Q = conserved(rho, one, 0 * one, 0 * one, one, c.gamma)
     return c
+
+
+# ----------------------------------------------------------------- 3D ramp
+RAMP_SEED = 2511
+RAMP_MACH = 2.9
+
+
+def _stretch(eta, beta):
+    """Wall-normal tanh clustering: 0 at the wall (eta = 0), 1 at the top (eta = 1)."""
+    return 1.0 + np.tanh(beta * (eta - 1.0)) / np.tanh(beta)
+
+
+def ramp3d(nx=1024, ny=384, nz=128, seed=RAMP_SEED, Lx=26.2, Ly=7.9, Lz=3.0, angle_deg=24.0,
+           y1=0.002, delta=1.0, noise_rms=0.05, M=RAMP_MACH, gamma=1.4, Pr=0.72):
+    """Curvilinear compression-ramp grid and a turbulent-boundary-layer-like state.
+
+    Grid (lengths in units of the inflow boundary-layer thickness delta):
+      x_i uniform on [0, Lx]; wall y_w(x) = tan(angle) r log(1 + exp((x - x_c)/r)) with the
+      corner at x_c = Lx/2 rounded over r = 0.5; y = y_w + s(eta)(Ly - y_w) with tanh
+      clustering s chosen so the first cell centre sits at y1 above the wall; z uniform,
+      periodic.  Ghost nodes continue the same maps.
+    State (non-dimensional with the free stream: rho = u = T = 1, p = 1/(gamma M^2)):
+      u/U = min(1, y_n/delta)^(1/7) above 5 y1 and linear below (y_n = height above the wall),
+      directed along the wall tangent with the angle relaxing as exp(-y_n / 2 delta);
+      T from the adiabatic Crocco-Busemann relation T = T_aw - (T_aw - 1)(u/U)^2 with
+      T_aw = 1 + Pr^(1/3) (gamma - 1) M^2 / 2; uniform p; rho = gamma M^2 p / T.
+      Fluctuations: curl of a Gaussian-smoothed (4-cell) normal random vector potential in
+      index space, limited to y_n < delta, scaled to noise_rms of U (seeded).
+    Boundaries: fixed inflow ghosts (the initial profile), transmissive outflow and top,
+    no-slip adiabatic wall, periodic span.
+    """
+    from scipy.ndimage import gaussian_filter, zoom
+    n = (nx, ny, nz)
+    c = Case(3, n, [(FIXED, TRANSMISSIVE), (NOSLIP, TRANSMISSIVE), (PERIODIC, PERIODIC)],
+             h=(Lx / nx, Ly / ny, Lz / nz), gamma=gamma)
+    g = NG
+    xs = (np.arange(-g, nx + g) + 0.5) * (Lx / nx)
+    eta = (np.arange(-g, ny + g) + 0.5) / ny
+    zs = (np.arange(-g, nz + g) + 0.5) * (Lz / nz)
+    # tanh clustering parameter for the requested first-cell height
+    lo, hi = 1e-3, 20.0
+    for _ in range(100):
+        mid = 0.5 * (lo + hi)
+        if _stretch(0.5 / ny, mid) * Ly > y1:
+            lo = mid
+        else:
+            hi = mid
+    beta = 0.5 * (lo + hi)
+    ta = np.tan(np.radians(angle_deg))
+    r = 0.5
+    xc = 0.5 * Lx
+    yw = ta * r * np.logaddexp(0.0, (xs - xc) / r)
+    slope = ta / (1.0 + np.exp(-(xs - xc) / r))
+    s = _stretch(eta, beta)
+    Z, Sg, X = np.meshgrid(zs, s, xs, indexing='ij')
+    _, _, YW = np.meshgrid(zs, s, yw, indexing='ij')
+    _, _, SL = np.meshgrid(zs, s, slope, indexing='ij')
+    Y = YW + Sg * (Ly - YW)
+    c.coords = np.stack([X, Y, Z])
+    yn = Y - YW
+    # mean profile
+    ylin = 5.0 * y1
+    frac = np.clip(yn / delta, 0.0, 1.0)
+    ulog = frac ** (1.0 / 7.0)
+    ulin = (ylin / delta) ** (1.0 / 7.0) * np.clip(yn, 0.0, None) / ylin
+    U = np.where(yn >= ylin, ulog, ulin)
+    alpha = np.arctan(SL) * np.exp(-np.clip(yn, 0.0, None) / (2.0 * delta))
+    u = U * np.cos(alpha)
+    v = U * np.sin(alpha)
+    w = np.zeros_like(u)
+    # divergence-free fluctuations (curl of a smoothed vector potential, index space)
+    rng = np.random.default_rng(seed)
+    shape = X.shape
+    coarse = tuple(max(4, (sz + 3) // 4) for sz in shape)
+    psi = []
+    for _ in range(3):
+        a = gaussian_filter(rng.standard_normal(coarse), sigma=1.0, mode='wrap')
+        a = zoom(a, [shape[k] / coarse[k] for k in range(3)], order=1)[:shape[0], :shape[1], :shape[2]]
+        psi.append(a)
+    def dd(f, ax):
+        return 0.5 * (np.roll(f, -1, axis=ax) - np.roll(f, 1, axis=ax))
+    # axes: 0 = z, 1 = y, 2 = x
+    fx = dd(psi[2], 1) - dd(psi[1], 0)
+    fy = dd(psi[0], 0) - dd(psi[2], 2)
+    fz = dd(psi[1], 2) - dd(psi[0], 1)
+    mask = (yn > 0.0) & (yn < delta)
+    rms = np.sqrt(np.mean((fx ** 2 + fy ** 2 + fz ** 2)[mask]) / 3.0)
+    k = noise_rms / max(rms, 1e-300)
+    u = u + k * fx * mask
+    v = v + k * fy * mask
+    w = w + k * fz * mask
+    Taw = 1.0 + Pr ** (1.0 / 3.0) * 0.5 * (gamma - 1.0) * M * M
+    T = Taw - (Taw - 1.0) * np.clip(U, 0.0, 1.0) ** 2
+    p = np.full_like(T, 1.0 / (gamma * M * M))
+    rho = gamma * M * M * p / T
+    c.Q = conserved(rho, u, v, w, p, gamma)
+    c.extra = dict(p_thr=0.5 / (gamma * M * M), rho_thr=-1.0, Re=2.0e4, Pr=Pr, Mref=M,
+                   suth=110.4 / 108.0, beta_stretch=beta, T_aw=Taw)
+    return c

@@ -15,11 +15,13 @@
 // pair; the LU factors of the constant-coefficient matrices are precomputed on the host
 // (tables below), so a solve is one forward and one backward sweep.
 //
-// Table layout for direction d (double):
+// Table layout for direction d (double), after the PCR factors (see k_grad_c4_pcr):
 //   bounded  line of N nodes: cp[0..N), inv[0..N)
 //   periodic line of n nodes: cp[0..n), inv[0..n), z[0..n), fac   (B z = u, fac = 1/(1 + v.z))
 #include "lgbr_dev.h"
 #include "lgbr_kernels.h"
+
+#include <algorithm>
 
 namespace lg {
 
@@ -50,6 +52,22 @@ __global__ void __launch_bounds__(256) k_grad_explicit(const Prob* __restrict__ 
   }
 }
 
+constexpr int PCR_STEPS = LG_PCR_STEPS;
+constexpr int PCR_MAX_LINE = 4096;          // longest line held in LDS (2 x 32 KB)
+constexpr long long PCR_FEW_LINES = 131072; // below this many (line, variable) lanes, PCR for strided lines
+
+// Which kernel solves the lines of direction d of problem P: the PCR kernel takes the
+// contiguous direction, and strided directions with few lines; periodic lines need at
+// least 2^(PCR_STEPS+1) nodes so that no reduction step wraps onto itself.
+__device__ __forceinline__ bool use_pcr(const Prob& P, int d) {
+  const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+  const long long nlines = (long long)P.N[o1] * P.N[o2];
+  const bool periodic = P.bc[d][0] == BC_PERIODIC;
+  const int L = periodic ? P.n[d] : P.N[d];
+  if (P.N[d] > PCR_MAX_LINE || (periodic && L < (2 << PCR_STEPS))) return false;
+  return d == 0 || 5 * nlines < PCR_FEW_LINES;
+}
+
 __device__ __forceinline__ double prim_q(int q, const double* Q, size_t T, size_t o, double gm1) {
   double rho = Q[o];
   if (q == 0) return rho;
@@ -68,6 +86,7 @@ __global__ void __launch_bounds__(256) k_grad_c4(const Prob* __restrict__ probs,
   const int nlines = P.N[o1] * P.N[o2];
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 5 * nlines) return;
+  if (use_pcr(P, d)) return;   // done by the PCR kernel
   const int line = t % nlines, q = t / nlines;
   const double* Q = ref.state(P);
   R* G = static_cast<R*>(P.G[d]) + (size_t)q * P.total;
@@ -135,6 +154,100 @@ __global__ void __launch_bounds__(256) k_grad_c4(const Prob* __restrict__ probs,
   }
 }
 
+// ------------------------------------------------------------------ line solves by PCR
+// One workgroup per (line, primitive): the line's right-hand side is formed in LDS from
+// FP64 primitives and reduced by parallel cyclic reduction.  The matrix is the same for
+// every line of a direction, so the elimination factors k1 = a_i / b_{i-s} and
+// k2 = c_i / b_{i+s} of every step and the final 1/b_i are precomputed on the host
+// (table layout: k1[PCR_STEPS][L], k2[PCR_STEPS][L], binv[L]).  For the C4 matrix the
+// couplings shrink as (2 - sqrt 3)^(2^k), so after PCR_STEPS = 7 steps they are below
+// 1e-70 of the diagonal and x_i = d_i / b_i is the direct solution up to rounding.
+// Periodic lines reduce the cyclic system over the interior with wrapped indices.
+template <typename R>
+__global__ void __launch_bounds__(256) k_grad_c4_pcr(const Prob* __restrict__ probs, StateRef ref, int d,
+                                                     int skip_if_any) {
+  extern __shared__ double lds[];
+  const Prob& P = probs[blockIdx.y];
+  if (d >= P.ndim || skip_launch(P, skip_if_any)) return;
+  const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+  const int nlines = P.N[o1] * P.N[o2];
+  if (!use_pcr(P, d)) return;   // the lane-per-line kernel does these
+  const int blk = blockIdx.x;
+  if (blk >= 5 * nlines) return;
+  const int line = blk % nlines, q = blk / nlines;
+  const bool periodic = P.bc[d][0] == BC_PERIODIC;
+  const int g = P.g[d], N = P.N[d], n = P.n[d];
+  const int L = periodic ? n : N;
+  const int off0 = periodic ? g : 0;
+  const int a = line % P.N[o1], b = line / P.N[o1];
+  const size_t base = (size_t)a * P.s[o1] + (size_t)b * P.s[o2];
+  const int sd = P.s[d];
+  const double* Q = ref.state(P);
+  const size_t T = P.total;
+  const double gm1 = P.gamma - 1.0;
+  const double* tab = P.pcr[d];
+  double* f = lds;        // primitive along the line (all N nodes)
+  double* r = lds + N;    // right-hand side, reduced in place
+  for (int i = threadIdx.x; i < N; i += blockDim.x) f[i] = prim_q(q, Q, T, base + (size_t)i * sd, gm1);
+  __syncthreads();
+  for (int i = threadIdx.x; i < L; i += blockDim.x) {
+    double v;
+    if (periodic) {
+      v = 0.75 * (f[off0 + i + 1] - f[off0 + i - 1]);
+    } else if (i == 0) {
+      v = (-3.0 * f[0] + 4.0 * f[1] - f[2]) / 2.0;
+    } else if (i == L - 1) {
+      v = (3.0 * f[L - 1] - 4.0 * f[L - 2] + f[L - 3]) / 2.0;
+    } else {
+      v = 0.75 * (f[i + 1] - f[i - 1]);
+    }
+    r[i] = v;
+  }
+  __syncthreads();
+  constexpr int MAXPT = PCR_MAX_LINE / 256;
+  double nv[MAXPT];
+  for (int st = 0; st < PCR_STEPS; ++st) {
+    const int s = 1 << st;
+    const double* k1 = tab + (size_t)st * L;
+    const double* k2 = tab + (size_t)(PCR_STEPS + st) * L;
+#pragma unroll
+    for (int m = 0; m < MAXPT; ++m) {
+      int i = threadIdx.x + m * 256;
+      if (i < L) {
+        int im = i - s, ip = i + s;
+        double rm, rp;
+        if (periodic) {
+          im = ((im % L) + L) % L;
+          ip = ip % L;
+          rm = r[im];
+          rp = r[ip];
+        } else {
+          rm = im >= 0 ? r[im] : 0.0;
+          rp = ip < L ? r[ip] : 0.0;
+        }
+        nv[m] = r[i] - k1[i] * rm - k2[i] * rp;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < MAXPT; ++m) {
+      int i = threadIdx.x + m * 256;
+      if (i < L) r[i] = nv[m];
+    }
+    __syncthreads();
+  }
+  const double* binv = tab + (size_t)2 * PCR_STEPS * L;
+  R* G = static_cast<R*>(P.G[d]) + (size_t)q * T;
+  for (int i = threadIdx.x; i < L; i += blockDim.x) {
+    R y = (R)(r[i] * binv[i]);
+    G[base + (size_t)(i + off0) * sd] = y;
+    if (periodic) {
+      if (i >= n - g) G[base + (size_t)(i + off0 - n) * sd] = y;   // low ghosts
+      if (i < g) G[base + (size_t)(i + off0 + n) * sd] = y;        // high ghosts
+    }
+  }
+}
+
 template <typename R>
 void launch_grad_explicit(const Launch& L, int d, int order, int skip_if_any) {
   long long b = (L.max_total + 255) / 256;
@@ -150,10 +263,18 @@ void launch_grad_explicit(const Launch& L, int d, int order, int skip_if_any) {
 
 template <typename R>
 void launch_grad_c4(const Launch& L, StateRef ref, int d, int skip_if_any) {
-  long long b = (5 * L.lines[d] + 255) / 256;
-  if (b < 1) b = 1;
-  LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c4<R>, dim3((unsigned)b, L.nprob), dim3(256), 0, L.stream,
-                                             L.probs, ref, d, skip_if_any));
+  // both kernels are launched; each problem's direction is taken by exactly one of them
+  // (use_pcr): PCR in LDS, one workgroup per (line, primitive), or one lane per (line, primitive)
+  const long long N = std::min<long long>(L.max_N[d], PCR_MAX_LINE);
+  const unsigned lds = (unsigned)(2 * N * sizeof(double));
+  long long blocks = 5 * L.lines[d];
+  LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c4_pcr<R>, dim3((unsigned)blocks, L.nprob), dim3(256), lds,
+                                             L.stream, L.probs, ref, d, skip_if_any));
+  if (d != 0 || L.max_N[0] > PCR_MAX_LINE || L.has_short_periodic) {
+    long long b = (5 * L.lines[d] + 255) / 256;
+    LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c4<R>, dim3((unsigned)b, L.nprob), dim3(256), 0, L.stream,
+                                               L.probs, ref, d, skip_if_any));
+  }
 }
 
 template void launch_grad_explicit<float>(const Launch&, int, int, int);

@@ -174,7 +174,48 @@ std::vector<double> tri_periodic(int n) {
   return t;
 }
 
+// PCR elimination factors of the C4 matrix (see k_grad_c4_pcr): k1[steps][L], k2[steps][L],
+// binv[L]; periodic lines wrap their indices.
+std::vector<double> pcr_table(int L, bool periodic, int steps) {
+  std::vector<double> a(L), b(L), c(L), na(L), nb(L), nc(L);
+  for (int i = 0; i < L; ++i) {
+    bool end = !periodic && (i == 0 || i == L - 1);
+    a[i] = end ? 0.0 : 0.25;
+    c[i] = end ? 0.0 : 0.25;
+    b[i] = 1.0;
+  }
+  std::vector<double> t((size_t)(2 * steps + 1) * L, 0.0);
+  for (int st = 0; st < steps; ++st) {
+    const int s = 1 << st;
+    for (int i = 0; i < L; ++i) {
+      int im = i - s, ip = i + s;
+      bool hm = true, hp = true;
+      if (periodic) {
+        im = ((im % L) + L) % L;
+        ip = ip % L;
+      } else {
+        hm = im >= 0;
+        hp = ip < L;
+      }
+      double k1 = hm ? a[i] / b[im] : 0.0;
+      double k2 = hp ? c[i] / b[ip] : 0.0;
+      na[i] = hm ? -k1 * a[im] : 0.0;
+      nc[i] = hp ? -k2 * c[ip] : 0.0;
+      nb[i] = b[i] - (hm ? k1 * c[im] : 0.0) - (hp ? k2 * a[ip] : 0.0);
+      t[(size_t)st * L + i] = k1;
+      t[(size_t)(steps + st) * L + i] = k2;
+    }
+    a.swap(na);
+    b.swap(nb);
+    c.swap(nc);
+  }
+  for (int i = 0; i < L; ++i) t[(size_t)2 * steps * L + i] = 1.0 / b[i];
+  return t;
+}
+
 void fill_launch(Launch& L, const Prob& P) {
+  for (int d = 0; d < P.ndim; ++d)
+    if (P.bc[d][0] == LG_BC_PERIODIC && P.n[d] < 128) L.has_short_periodic = 1;
   L.max_total = std::max<long long>(L.max_total, P.total);
   L.max_cells = std::max<long long>(L.max_cells, (long long)P.n[0] * P.n[1] * P.n[2]);
   for (int d = 0; d < 3; ++d) {
@@ -350,6 +391,14 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
         return LG_EHIP;
       }
       P.tri[d] = dt;
+      std::vector<double> pt = pcr_table(P.bc[d][0] == LG_BC_PERIODIC ? P.n[d] : P.N[d],
+                                         P.bc[d][0] == LG_BC_PERIODIC, lg::LG_PCR_STEPS);
+      double* pd = static_cast<double*>(A(pt.size() * sizeof(double)));
+      if (!ok || hipMemcpy(pd, pt.data(), pt.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        lg_destroy(c);
+        return ok ? LG_EHIP : LG_ENOMEM;
+      }
+      P.pcr[d] = pd;
     }
   }
   c->dp = static_cast<Prob*>(A(sizeof(Prob)));

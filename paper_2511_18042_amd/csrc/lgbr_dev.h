@@ -56,7 +56,8 @@ struct Prob {
   const void* MR;    // node metrics in R                [10][total] (curvilinear only)
   const double* M64; // node metrics in FP64             [10][total] (curvilinear only)
   const double* coords;  // node coordinates             [3][total]  (curvilinear only)
-  const double* tri[3];  // compact-solve tables per direction (see k_grad.hip)
+  const double* tri[3];  // compact-solve LU tables per direction (see k_grad.hip)
+  const double* pcr[3];  // compact-solve PCR factors per direction (see k_grad.hip)
   // device scalars
   double* dt;
   double* t;

@@ -38,6 +38,9 @@ struct Prof {
   int* cls;         // class of each recorded launch
 };
 
+// Reduction steps of the PCR line solves (host tables and device kernel must agree).
+constexpr int LG_PCR_STEPS = 6;
+
 // Launch geometry shared by all problems of one launch (maxima over the problems).
 struct Launch {
   const Prob* probs;   // device array
@@ -50,6 +53,7 @@ struct Launch {
   long long max_N[3];      // ghost-padded extent per direction
   long long max_n[3];      // interior extent per direction
   long long sweep_rows[3]; // interior lines (interior of the other two dims) per direction
+  int has_short_periodic;  // some periodic direction has fewer than 128 interior nodes
   int ndim;
   int seg;                 // nodes per thread in the strided sweeps
   Prof* prof;              // optional launch timing (null: off)

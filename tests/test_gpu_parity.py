@@ -252,3 +252,50 @@ def test_full_size_triple_point_rhs(scheme):
     out = U.gpu_rhs(ctx, c, scheme)
     U.compare(out, ref, g, U.RHS_RTOL, U.excused_mask(info, g), label='triple point ' + scheme)
     ctx.close()
+
+
+def _ramp_case(nx=40, ny=32, nz=16):
+    c = cases.ramp3d(nx, ny, nz)
+    e = c.extra
+    gas = orhs.Gas(gamma=1.4, Re=e['Re'], Pr=e['Pr'], Mref=e['Mref'], suth=e['suth'], viscous=True)
+    return c, gas
+
+
+@pytest.mark.parametrize('scheme,grad', [('cgbr', 'C4'), ('cgbr', 'E6'), ('lad', 'E6'), ('hybrid', 'C4')])
+def test_ramp_crop_rhs_parity_fp64(scheme, grad):
+    """The compression-ramp workload (same generator, 40x32x16 crop): curvilinear metrics from
+    the GPU, fixed inflow ghosts, no-slip wall, periodic span, Sutherland viscosity; the
+    hybrid runs with 10 % random troubled cells so that both schemes and their seams are hit."""
+    print('ramp', scheme, grad, flush=True)
+    c, gas = _ramp_case()
+    g = U.oracle_grid(c)
+    opts = orhs.Opts(grad=grad, p_thr=c.extra['p_thr'])
+    flags = (np.random.default_rng(9).random(g.shape) < 0.1) if scheme == 'hybrid' else None
+    info = {}
+    ref = orhs.rhs(c.Q, g, gas, opts, scheme, info=info, force_flags=flags)
+    ctx, _ = U.gpu_context(c, gas, opts)
+    out = U.gpu_rhs(ctx, c, scheme, flags=flags)
+    U.compare(out, ref, g, U.RHS_RTOL, U.excused_mask(info, g), label='ramp %s %s' % (scheme, grad))
+    ctx.close()
+
+
+def test_ramp_crop_rk3_step_and_mixed_error():
+    """One full hybrid MIG4 RK3 step on the ramp crop (FP64 gate), and the mixed path's
+    state error after the step relative to the FP64 oracle (bound 1e-4 of each variable's
+    max norm: FP32 rounding amplified by the near-wall viscous cancellation)."""
+    torch = U.torch_mod()
+    c, gas = _ramp_case()
+    g = U.oracle_grid(c)
+    opts = orhs.Opts(grad='C4', p_thr=c.extra['p_thr'])
+    Qn, t1, dt1, bad = orhs.rk3_step(c.Q, 0.0, 1.0, g, gas, opts, 'hybrid')
+    assert bad == 0
+    for precision, tol in (('fp64', U.STAGE_RTOL), ('mixed', 1e-4)):
+        ctx, _ = U.gpu_context(c, gas, opts, precision=precision)
+        Qd = U.dev(c.Q)
+        td = torch.zeros(1, dtype=torch.float64, device='cuda')
+        ctx.rk3_step('hybrid', Qd, 1.0, td)
+        torch.cuda.synchronize()
+        assert abs(td.item() - t1) <= 1e-13 * t1
+        U.compare(Qd.cpu().numpy(), Qn, g, tol, label='ramp rk3 ' + precision)
+        assert ctx.poll_status() == 0
+        ctx.close()
