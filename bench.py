@@ -50,11 +50,11 @@ def algorithmic_bytes(kclass, nodes, rs, ndim, gbr_frac, viscous):
     elif kclass in ('sweep_y', 'sweep_z'):
         per = (1 - gbr_frac) * 5 * rs + gbr_frac * (11 * rs + vis) + 1 + 80
     elif kclass == 'lad_flux':
-        per = 5 * rs + 3 * rs + 5 * rs * ndim
+        per = 5 * rs + 15 * rs + 3 * rs + 5 * rs * ndim     # W, physical gradients, coefficients -> F_l
     elif kclass == 'lad_raw':
-        per = 11 * rs
+        per = 2 * rs + 15 * rs + 3 * rs + 3 * rs           # rho, p, gradients, |S| theta e -> raw
     elif kclass == 'lad_node':
-        per = 8 * rs
+        per = 5 * rs + 15 * rs + 3 * rs                     # W -> physical gradients, |S| theta e
     elif kclass == 'gauss':
         per = 6 * rs
     elif kclass == 'grad_e6':
@@ -127,7 +127,7 @@ def run_workload(name, K, W, variants, cpu):
             ctx.rk3_step(scheme, Q, 1e30, t)
         torch.cuda.synchronize()
         if prof_class is not None:
-            ctx.prof_start(prof_class, 80 * K + 80)
+            ctx.prof_start(prof_class, 400 * K + 400)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()

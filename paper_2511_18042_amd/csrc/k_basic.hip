@@ -100,36 +100,82 @@ __global__ void __launch_bounds__(256) k_prim(const Prob* __restrict__ probs, St
 }
 
 // ------------------------------------------------------------------ global hybrid switch
-__global__ void __launch_bounds__(256) k_any_flag(const Prob* __restrict__ probs) {
+__global__ void __launch_bounds__(256) k_any_flag(const Prob* __restrict__ probs, int interior_only) {
   const Prob& P = probs[blockIdx.y];
-  const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
-  const int cnt = n0 * n1 * n2;
   int found = 0;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x) {
-    int i = t % n0, r = t / n0;
-    int j = r % n1, k = r / n1;
-    if (P.f[pos_to_idx(P, i + P.g[0], j + P.g[1], k + P.g[2])]) found = 1;
+  if (interior_only) {
+    const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
+    const int cnt = n0 * n1 * n2;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x) {
+      int i = t % n0, r = t / n0;
+      int j = r % n1, k = r / n1;
+      if (P.f[pos_to_idx(P, i + P.g[0], j + P.g[1], k + P.g[2])]) found = 1;
+    }
+  } else {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < P.total; t += gridDim.x * blockDim.x)
+      if (P.f[t]) found = 1;
   }
   if (__any(found) && (threadIdx.x & 63) == 0) atomicOr(P.any_flag, 1);
 }
 
-// Separable box dilation by P.dilate nodes along direction d.
-// src/dst: 0 = f, 1 = ftmp, 2 = ft.
-__global__ void __launch_bounds__(256) k_dilate(const Prob* __restrict__ probs, int d, int src, int dst) {
+// Separable box dilation by r nodes along direction d.
+// src/dst: 0 = f, 1 = ftmp, 2 = ft, 3 = fg.
+__device__ __forceinline__ uint8_t* flag_buf(const Prob& P, int b) {
+  return b == 0 ? P.f : (b == 1 ? P.ftmp : (b == 2 ? P.ft : P.fg));
+}
+
+__global__ void __launch_bounds__(256) k_dilate(const Prob* __restrict__ probs, int d, int src, int dst, int radius) {
   const Prob& P = probs[blockIdx.y];
-  if (d >= P.ndim) return;
-  const uint8_t* in = src == 0 ? P.f : (src == 1 ? P.ftmp : P.ft);
-  uint8_t* out = dst == 0 ? P.f : (dst == 1 ? P.ftmp : P.ft);
-  const int r = P.dilate, Nd = P.N[d], sd = P.s[d];
+  if (d >= P.ndim || *P.any_flag == 0) return;   // nothing flagged: consumers check any_flag
+  const uint8_t* in = flag_buf(P, src);
+  uint8_t* out = flag_buf(P, dst);
+  const int r = radius, Nd = P.N[d], sd = P.s[d];
+  constexpr int RMAX = 7;
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < P.total; idx += gridDim.x * blockDim.x) {
-    int c = (idx / sd) % Nd;
+    const int c = (idx / sd) % Nd;
+    uint8_t v[2 * RMAX + 1];
+#pragma unroll
+    for (int s = -RMAX; s <= RMAX; ++s) {   // independent loads, clamped into the line
+      int cc = min(max(c + s, 0), Nd - 1);
+      v[s + RMAX] = in[idx + (cc - c) * sd];
+    }
     uint8_t acc = 0;
-    for (int s = -r; s <= r; ++s) {
+#pragma unroll
+    for (int s = -RMAX; s <= RMAX; ++s) {
       int cc = c + s;
-      if (cc >= 0 && cc < Nd) acc |= in[idx + s * sd];
+      if (s >= -r && s <= r && cc >= 0 && cc < Nd) acc |= v[s + RMAX];
     }
     out[idx] = acc;
   }
+}
+
+// Compacted list of the lines along d that cross the C-GBR input region fg (one lane
+// per line; wave-aggregated append).
+__global__ void __launch_bounds__(256) k_line_list(const Prob* __restrict__ probs, int d) {
+  const Prob& P = probs[blockIdx.y];
+  if (d >= P.ndim || *P.any_flag == 0) return;
+  const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+  const int nlines = P.N[o1] * P.N[o2];
+  const int line = blockIdx.x * blockDim.x + threadIdx.x;
+  bool act = false;
+  if (line < nlines) {
+    const int a = line % P.N[o1], b = line / P.N[o1];
+    const uint8_t* f = P.fg + a * P.s[o1] + b * P.s[o2];
+    const int Nd = P.N[d], sd = P.s[d];
+    for (int i = 0; i < Nd && !act; ++i) act = f[i * sd] != 0;
+  }
+  const unsigned long long m = __ballot(act);
+  if (m == 0ull) return;
+  const int lane = threadIdx.x & 63;
+  int base = 0;
+  if (lane == __ffsll((long long)m) - 1) base = atomicAdd(&P.lcount[d], __popcll(m));
+  base = __shfl(base, __ffsll((long long)m) - 1);
+  if (act) P.llist[d][base + __popcll(m & ((1ull << lane) - 1ull))] = line;
+}
+
+__global__ void k_zero_lcount(const Prob* __restrict__ probs) {
+  const Prob& P = probs[blockIdx.y];
+  if (threadIdx.x < 3) P.lcount[threadIdx.x] = 0;
 }
 
 // ------------------------------------------------------------------ RK3 combination
@@ -355,20 +401,29 @@ void launch_prim(const Launch& L, StateRef ref, int want_flags, const uint8_t* f
                                           L.probs, ref, want_flags, force));
 }
 
-void launch_any_flag(const Launch& L) {
+void launch_any_flag(const Launch& L, int interior_only) {
   hipLaunchKernelGGL(k_zero_any, dim3(1, L.nprob), dim3(64), 0, L.stream, L.probs);
-  LG_TIMED(L, KC_FLAGS, hipLaunchKernelGGL(k_any_flag, grid_for(L.max_cells, L.nprob), dim3(256), 0, L.stream,
-                                           L.probs));
+  LG_TIMED(L, KC_FLAGS, hipLaunchKernelGGL(k_any_flag, grid_for(interior_only ? L.max_cells : L.max_total, L.nprob),
+                                           dim3(256), 0, L.stream, L.probs, interior_only));
 }
 
-void launch_dilate(const Launch& L, int ndim) {
-  // f -> ... -> ft, alternating between ft and ftmp so that the last pass lands in ft
-  int src = 0;
+void launch_dilate(const Launch& L, int ndim, int radius, int first_src, int final_buf) {
+  // first_src -> ... -> final_buf, alternating with ftmp so that the last pass lands in final_buf
+  int src = first_src;
   for (int d = 0; d < ndim; ++d) {
-    int dst = ((ndim - 1 - d) % 2 == 0) ? 2 : 1;
+    int dst = ((ndim - 1 - d) % 2 == 0) ? final_buf : 1;
     LG_TIMED(L, KC_FLAGS, hipLaunchKernelGGL(k_dilate, grid_for(L.max_total, L.nprob), dim3(256), 0, L.stream,
-                                             L.probs, d, src, dst));
+                                             L.probs, d, src, dst, radius));
     src = dst;
+  }
+}
+
+void launch_line_lists(const Launch& L, int ndim) {
+  hipLaunchKernelGGL(k_zero_lcount, dim3(1, L.nprob), dim3(64), 0, L.stream, L.probs);
+  for (int d = 0; d < ndim; ++d) {
+    long long b = (L.lines[d] + 255) / 256;
+    LG_TIMED(L, KC_FLAGS, hipLaunchKernelGGL(k_line_list, dim3((unsigned)(b < 1 ? 1 : b), L.nprob), dim3(256), 0,
+                                             L.stream, L.probs, d));
   }
 }
 

@@ -30,7 +30,8 @@ __device__ __forceinline__ bool skip_launch(const Prob& P, int skip_if_any) {
 }
 
 template <typename R, int ORDER>
-__global__ void __launch_bounds__(256) k_grad_explicit(const Prob* __restrict__ probs, int d, int skip_if_any) {
+__global__ void __launch_bounds__(256) k_grad_explicit(const Prob* __restrict__ probs, int d, int skip_if_any,
+                                                       int region) {
   const Prob& P = probs[blockIdx.y];
   if (d >= P.ndim || skip_launch(P, skip_if_any)) return;
   const R* W = static_cast<const R*>(P.W);
@@ -40,6 +41,7 @@ __global__ void __launch_bounds__(256) k_grad_explicit(const Prob* __restrict__ 
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < P.total; idx += gridDim.x * blockDim.x) {
     int c = (idx / sd) % Nd;
     if (c < r || c >= Nd - r) continue;
+    if (region && !P.fg[idx]) continue;
     for (int q = 0; q < 5; ++q) {
       const R* f = W + q * T + idx;
       R v;
@@ -79,15 +81,17 @@ __device__ __forceinline__ double prim_q(int q, const double* Q, size_t T, size_
 // One lane per (line, primitive variable): forward elimination stores d' in the FP64
 // scratch, back substitution writes the gradient.
 template <typename R>
-__global__ void __launch_bounds__(256) k_grad_c4(const Prob* __restrict__ probs, StateRef ref, int d, int skip_if_any) {
+__global__ void __launch_bounds__(256) k_grad_c4(const Prob* __restrict__ probs, StateRef ref, int d, int skip_if_any,
+                                                 int region) {
   const Prob& P = probs[blockIdx.y];
   if (d >= P.ndim || skip_launch(P, skip_if_any)) return;
+  if (use_pcr(P, d)) return;   // done by the PCR kernel
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   const int nlines = P.N[o1] * P.N[o2];
+  const int cnt = region ? P.lcount[d] : nlines;   // compacted list of lines that need solving
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 5 * nlines) return;
-  if (use_pcr(P, d)) return;   // done by the PCR kernel
-  const int line = t % nlines, q = t / nlines;
+  if (t >= 5 * cnt) return;
+  const int line = region ? P.llist[d][t % cnt] : t % nlines, q = t / cnt;
   const double* Q = ref.state(P);
   R* G = static_cast<R*>(P.G[d]) + (size_t)q * P.total;
   const size_t T = P.total;
@@ -165,16 +169,17 @@ __global__ void __launch_bounds__(256) k_grad_c4(const Prob* __restrict__ probs,
 // Periodic lines reduce the cyclic system over the interior with wrapped indices.
 template <typename R>
 __global__ void __launch_bounds__(256) k_grad_c4_pcr(const Prob* __restrict__ probs, StateRef ref, int d,
-                                                     int skip_if_any) {
+                                                     int skip_if_any, int region) {
   extern __shared__ double lds[];
   const Prob& P = probs[blockIdx.y];
   if (d >= P.ndim || skip_launch(P, skip_if_any)) return;
+  if (!use_pcr(P, d)) return;   // the lane-per-line kernel does these
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   const int nlines = P.N[o1] * P.N[o2];
-  if (!use_pcr(P, d)) return;   // the lane-per-line kernel does these
-  const int blk = blockIdx.x;
-  if (blk >= 5 * nlines) return;
-  const int line = blk % nlines, q = blk / nlines;
+  const int cnt = region ? P.lcount[d] : nlines;   // compacted list of lines that need solving
+  // persistent workgroups walk the (line, primitive) items
+  for (int blk = blockIdx.x; blk < 5 * cnt; blk += gridDim.x) {
+  const int line = region ? P.llist[d][blk % cnt] : blk % nlines, q = blk / cnt;
   const bool periodic = P.bc[d][0] == BC_PERIODIC;
   const int g = P.g[d], N = P.N[d], n = P.n[d];
   const int L = periodic ? n : N;
@@ -246,40 +251,44 @@ __global__ void __launch_bounds__(256) k_grad_c4_pcr(const Prob* __restrict__ pr
       if (i < g) G[base + (size_t)(i + off0 + n) * sd] = y;        // high ghosts
     }
   }
+  __syncthreads();   // the next item reuses the LDS line
+  }
 }
 
 template <typename R>
-void launch_grad_explicit(const Launch& L, int d, int order, int skip_if_any) {
+void launch_grad_explicit(const Launch& L, int d, int order, int skip_if_any, int region) {
   long long b = (L.max_total + 255) / 256;
   if (b > 8192) b = 8192;
   dim3 grid((unsigned)b, L.nprob);
   if (order == 6)
-    LG_TIMED(L, KC_GRAD_E6,
-             hipLaunchKernelGGL((k_grad_explicit<R, 6>), grid, dim3(256), 0, L.stream, L.probs, d, skip_if_any));
+    LG_TIMED(L, KC_GRAD_E6, hipLaunchKernelGGL((k_grad_explicit<R, 6>), grid, dim3(256), 0, L.stream, L.probs, d,
+                                               skip_if_any, region));
   else
-    LG_TIMED(L, KC_GRAD_E6,
-             hipLaunchKernelGGL((k_grad_explicit<R, 4>), grid, dim3(256), 0, L.stream, L.probs, d, skip_if_any));
+    LG_TIMED(L, KC_GRAD_E6, hipLaunchKernelGGL((k_grad_explicit<R, 4>), grid, dim3(256), 0, L.stream, L.probs, d,
+                                               skip_if_any, region));
 }
 
 template <typename R>
-void launch_grad_c4(const Launch& L, StateRef ref, int d, int skip_if_any) {
-  // both kernels are launched; each problem's direction is taken by exactly one of them
-  // (use_pcr): PCR in LDS, one workgroup per (line, primitive), or one lane per (line, primitive)
-  const long long N = std::min<long long>(L.max_N[d], PCR_MAX_LINE);
-  const unsigned lds = (unsigned)(2 * N * sizeof(double));
-  long long blocks = 5 * L.lines[d];
-  LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c4_pcr<R>, dim3((unsigned)blocks, L.nprob), dim3(256), lds,
-                                             L.stream, L.probs, ref, d, skip_if_any));
-  if (d != 0 || L.max_N[0] > PCR_MAX_LINE || L.has_short_periodic) {
+void launch_grad_c4(const Launch& L, StateRef ref, int d, int skip_if_any, int region) {
+  // each problem's direction is taken by exactly one kernel (use_pcr): PCR in LDS with
+  // persistent workgroups over the (line, primitive) items, or one lane per item
+  if (L.pcr_dir[d]) {
+    const long long N = std::min<long long>(L.max_N[d], PCR_MAX_LINE);
+    const unsigned lds = (unsigned)(2 * N * sizeof(double));
+    long long blocks = std::min<long long>(5 * L.lines[d], 16384);
+    LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c4_pcr<R>, dim3((unsigned)blocks, L.nprob), dim3(256), lds,
+                                               L.stream, L.probs, ref, d, skip_if_any, region));
+  }
+  if (L.thomas_dir[d]) {
     long long b = (5 * L.lines[d] + 255) / 256;
     LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c4<R>, dim3((unsigned)b, L.nprob), dim3(256), 0, L.stream,
-                                               L.probs, ref, d, skip_if_any));
+                                               L.probs, ref, d, skip_if_any, region));
   }
 }
 
-template void launch_grad_explicit<float>(const Launch&, int, int, int);
-template void launch_grad_explicit<double>(const Launch&, int, int, int);
-template void launch_grad_c4<float>(const Launch&, StateRef, int, int);
-template void launch_grad_c4<double>(const Launch&, StateRef, int, int);
+template void launch_grad_explicit<float>(const Launch&, int, int, int, int);
+template void launch_grad_explicit<double>(const Launch&, int, int, int, int);
+template void launch_grad_c4<float>(const Launch&, StateRef, int, int, int);
+template void launch_grad_c4<double>(const Launch&, StateRef, int, int, int);
 
 }  // namespace lg

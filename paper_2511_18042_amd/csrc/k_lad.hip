@@ -104,19 +104,23 @@ __device__ __forceinline__ bool in_band(const Prob& P, int idx, int lo, int hi) 
 
 __device__ __forceinline__ bool is_interior(const Prob& P, int idx) { return in_band(P, idx, 0, 0); }
 
-// |S|, div u and e at every node where E4 fits (positions -3 .. n+2)
+// E4 physical gradients D (stored for the raw coefficients and the node fluxes) and
+// |S|, div u, e at every node where E4 fits (positions -3 .. n+2)
 template <typename R>
-__global__ void __launch_bounds__(256) k_lad_node(const Prob* __restrict__ probs, int skip_if_any) {
+__global__ void __launch_bounds__(256) k_lad_grad(const Prob* __restrict__ probs, int skip_if_any) {
   const Prob& P = probs[blockIdx.y];
   if (lad_skip(P, skip_if_any)) return;
   const R* W = static_cast<const R*>(P.W);
   R* S3 = static_cast<R*>(P.S3);
+  R* DD = static_cast<R*>(P.D4);
   const size_t T = P.total;
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < P.total; idx += gridDim.x * blockDim.x) {
     if (!in_band(P, idx, -3, 3)) continue;
     R gl[3][5], D[5][3];
     e4_grads(P, W, idx, gl);
     to_physical(P, idx, gl, D);
+    for (int q = 0; q < 5; ++q)
+      for (int j = 0; j < 3; ++j) DD[(size_t)(3 * q + j) * T + idx] = D[q][j];
     R S2 = R(0);
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) {
@@ -128,6 +132,14 @@ __global__ void __launch_bounds__(256) k_lad_node(const Prob* __restrict__ probs
     S3[T + idx] = D[1][0] + D[2][1] + D[3][2];
     S3[2 * T + idx] = p / (R(P.gamma - 1.0) * rho);
   }
+}
+
+template <typename R>
+__device__ __forceinline__ void load_D(const Prob& P, int idx, R D[5][3]) {
+  const R* DD = static_cast<const R*>(P.D4);
+  const size_t T = P.total;
+  for (int q = 0; q < 5; ++q)
+    for (int j = 0; j < 3; ++j) D[q][j] = DD[(size_t)(3 * q + j) * T + idx];
 }
 
 template <typename R>
@@ -147,9 +159,8 @@ __global__ void __launch_bounds__(256) k_lad_raw(const Prob* __restrict__ probs,
   const R gm1 = R(P.gamma - 1.0);
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < P.total; idx += gridDim.x * blockDim.x) {
     if (!is_interior(P, idx)) continue;
-    R gl[3][5], D[5][3];
-    e4_grads(P, W, idx, gl);
-    to_physical(P, idx, gl, D);
+    R D[5][3];
+    load_D(P, idx, D);
     R rho = W[idx], p = W[4 * T + idx];
     R theta = D[1][0] + D[2][1] + D[3][2];
     R w1 = D[3][1] - D[2][2], w2 = D[1][2] - D[3][0], w3 = D[2][0] - D[1][1];
@@ -226,9 +237,8 @@ __global__ void __launch_bounds__(256) k_lad_nodeflux(const Prob* __restrict__ p
     if (!in_band(P, idx, -2, 2)) continue;
     R w[5];
     for (int q = 0; q < 5; ++q) w[q] = W[q * T + idx];
-    R gl[3][5], D[5][3];
-    e4_grads(P, W, idx, gl);
-    to_physical(P, idx, gl, D);
+    R D[5][3];
+    load_D(P, idx, D);
     R muf, kapf;
     transport(P, w[0], w[4], muf, kapf);
     R mu = muf + C[idx], beta = C[T + idx], kappa = kapf + C[2 * T + idx];
@@ -250,13 +260,14 @@ __global__ void __launch_bounds__(256) k_lad_nodeflux(const Prob* __restrict__ p
 
 // C-GBR viscous node fluxes (physical coefficients, the scheme's gradients)
 template <typename R>
-__global__ void __launch_bounds__(256) k_gbr_viscflux(const Prob* __restrict__ probs, int skip_if_any) {
+__global__ void __launch_bounds__(256) k_gbr_viscflux(const Prob* __restrict__ probs, int skip_if_any, int region) {
   const Prob& P = probs[blockIdx.y];
   if (lad_skip(P, skip_if_any)) return;
   const R* W = static_cast<const R*>(P.W);
   const size_t T = P.total;
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < P.total; idx += gridDim.x * blockDim.x) {
     if (!in_band(P, idx, -2, 2)) continue;
+    if (region && !P.fg[idx]) continue;
     R w[5];
     for (int q = 0; q < 5; ++q) w[q] = W[q * T + idx];
     R gl[3][5], D[5][3];
@@ -283,7 +294,7 @@ static inline dim3 g1(long long work, int nprob) {
 
 template <typename R>
 void launch_lad(const Launch& L, int skip_if_any) {
-  LG_TIMED(L, KC_LAD_NODE, hipLaunchKernelGGL(k_lad_node<R>, g1(L.max_total, L.nprob), dim3(256), 0, L.stream,
+  LG_TIMED(L, KC_LAD_NODE, hipLaunchKernelGGL(k_lad_grad<R>, g1(L.max_total, L.nprob), dim3(256), 0, L.stream,
                                               L.probs, skip_if_any));
   LG_TIMED(L, KC_LAD_RAW, hipLaunchKernelGGL(k_lad_raw<R>, g1(L.max_total, L.nprob), dim3(256), 0, L.stream,
                                              L.probs, skip_if_any));
@@ -300,14 +311,14 @@ void launch_lad(const Launch& L, int skip_if_any) {
 }
 
 template <typename R>
-void launch_gbr_viscflux(const Launch& L, int skip_if_any) {
+void launch_gbr_viscflux(const Launch& L, int skip_if_any, int region) {
   LG_TIMED(L, KC_VISC, hipLaunchKernelGGL(k_gbr_viscflux<R>, g1(L.max_total, L.nprob), dim3(256), 0, L.stream,
-                                          L.probs, skip_if_any));
+                                          L.probs, skip_if_any, region));
 }
 
 template void launch_lad<float>(const Launch&, int);
 template void launch_lad<double>(const Launch&, int);
-template void launch_gbr_viscflux<float>(const Launch&, int);
-template void launch_gbr_viscflux<double>(const Launch&, int);
+template void launch_gbr_viscflux<float>(const Launch&, int, int);
+template void launch_gbr_viscflux<double>(const Launch&, int, int);
 
 }  // namespace lg

@@ -40,7 +40,7 @@ __device__ __forceinline__ bool band(const Prob& P, int idx, int lo, int hi) {
 
 // ------------------------------------------------------------------ sensor
 template <typename R>
-__global__ void __launch_bounds__(256) k_sensor(const Prob* __restrict__ probs, int skip_if_any) {
+__global__ void __launch_bounds__(256) k_sensor(const Prob* __restrict__ probs, int skip_if_any, int region) {
   const Prob& P = probs[blockIdx.y];
   if (sw_skip(P, skip_if_any)) return;
   const R* W = static_cast<const R*>(P.W);
@@ -49,6 +49,7 @@ __global__ void __launch_bounds__(256) k_sensor(const Prob* __restrict__ probs, 
   const R* p = W + 4 * T;
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < P.total; idx += gridDim.x * blockDim.x) {
     if (!band(P, idx, -2, 2)) continue;
+    if (region && !P.fg[idx]) continue;
     R phi = R(0);
     for (int l = 0; l < P.ndim; ++l) {
       int s = P.s[l];
@@ -265,7 +266,7 @@ __device__ __forceinline__ void interface_flux(const Prob& P, int d, int idx, in
   bool gbr;
   if (sel == SEL_GBR) gbr = true;
   else if (sel == SEL_LAD) gbr = false;
-  else if (sel == SEL_PERCELL) gbr = (P.ft[idx] | P.ft[idx + s]) != 0;
+  else if (sel == SEL_PERCELL) gbr = *P.any_flag != 0 && (P.ft[idx] | P.ft[idx + s]) != 0;
   else gbr = *P.any_flag != 0;
   if (gbr) {
     gbr_flux(P, d, idx, F);
@@ -358,11 +359,11 @@ __global__ void __launch_bounds__(256) k_sweep_s(const Prob* __restrict__ probs,
 }
 
 template <typename R>
-void launch_sensor(const Launch& L, int skip_if_any) {
+void launch_sensor(const Launch& L, int skip_if_any, int region) {
   long long b = (L.max_total + 255) / 256;
   if (b > 8192) b = 8192;
   LG_TIMED(L, KC_SENSOR, hipLaunchKernelGGL(k_sensor<R>, dim3((unsigned)b, L.nprob), dim3(256), 0, L.stream,
-                                            L.probs, skip_if_any));
+                                            L.probs, skip_if_any, region));
 }
 
 template <typename R>
@@ -395,8 +396,8 @@ void launch_sweep(const Launch& L, StateRef ref, int d, int sel, int accumulate)
   }
 }
 
-template void launch_sensor<float>(const Launch&, int);
-template void launch_sensor<double>(const Launch&, int);
+template void launch_sensor<float>(const Launch&, int, int);
+template void launch_sensor<double>(const Launch&, int, int);
 template void launch_sweep<float>(const Launch&, StateRef, int, int, int);
 template void launch_sweep<double>(const Launch&, StateRef, int, int, int);
 

@@ -47,7 +47,7 @@ void dev_free(void* p) {
 }
 
 struct Cfg {
-  int ndim, precision, grad, hybrid_mode, viscous;
+  int ndim, precision, grad, hybrid_mode, viscous, dilate;
 };
 
 }  // namespace
@@ -99,20 +99,32 @@ void enqueue_rhs(const Launch& L, const Cfg& c, int scheme, StateRef ref, const 
     sel = lg::SEL_LAD;
   } else if (c.hybrid_mode == LG_HYB_GLOBAL) {
     sel = lg::SEL_GLOBAL;
-    lg::launch_any_flag(L);
+    lg::launch_any_flag(L, 1);
     skip_gbr = 0;  // C-GBR inputs are skipped when no interior node is troubled
     skip_lad = 1;  // LAD inputs are skipped when one is
   } else {
     sel = lg::SEL_PERCELL;
-    lg::launch_dilate(L, c.ndim);
+  }
+  int region = 0;
+  if (sel == lg::SEL_PERCELL) {
+    // interface selection: flags dilated by the hybrid radius (-> ft); C-GBR inputs are
+    // only needed within three more nodes of those (-> fg), and only the compact lines
+    // that cross fg are solved.  With no troubled node at all (any_flag == 0) every
+    // interface is LAD and all of this, and the C-GBR inputs, are skipped on the device.
+    lg::launch_any_flag(L, 0);
+    lg::launch_dilate(L, c.ndim, c.dilate, 0, 2);
+    lg::launch_dilate(L, c.ndim, 3, 2, 3);
+    if (c.grad == LG_GRAD_C4) lg::launch_line_lists(L, c.ndim);
+    region = 1;
+    skip_gbr = 0;
   }
   if (sel != lg::SEL_LAD) {
     for (int d = 0; d < c.ndim; ++d) {
-      if (c.grad == LG_GRAD_C4) lg::launch_grad_c4<R>(L, ref, d, skip_gbr);
-      else lg::launch_grad_explicit<R>(L, d, 6, skip_gbr);
+      if (c.grad == LG_GRAD_C4) lg::launch_grad_c4<R>(L, ref, d, skip_gbr, region);
+      else lg::launch_grad_explicit<R>(L, d, 6, skip_gbr, region);
     }
-    lg::launch_sensor<R>(L, skip_gbr);
-    if (c.viscous) lg::launch_gbr_viscflux<R>(L, skip_gbr);
+    lg::launch_sensor<R>(L, skip_gbr, region);
+    if (c.viscous) lg::launch_gbr_viscflux<R>(L, skip_gbr, region);
   }
   if (sel != lg::SEL_GBR) lg::launch_lad<R>(L, skip_lad);
   for (int d = 0; d < c.ndim; ++d) lg::launch_sweep<R>(L, ref, d, sel, d > 0 ? 1 : 0);
@@ -214,8 +226,18 @@ std::vector<double> pcr_table(int L, bool periodic, int steps) {
 }
 
 void fill_launch(Launch& L, const Prob& P) {
-  for (int d = 0; d < P.ndim; ++d)
-    if (P.bc[d][0] == LG_BC_PERIODIC && P.n[d] < 128) L.has_short_periodic = 1;
+  for (int d = 0; d < P.ndim; ++d) {
+    // mirror of use_pcr() in k_grad.hip
+    int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+    long long nlines = (long long)P.N[o1] * P.N[o2];
+    bool periodic = P.bc[d][0] == LG_BC_PERIODIC;
+    int Lline = periodic ? P.n[d] : P.N[d];
+    bool pcr = !(P.N[d] > 4096 || (periodic && Lline < (2 << lg::LG_PCR_STEPS))) &&
+               (d == 0 || 5 * nlines < 131072);
+    if (pcr) L.pcr_dir[d] = 1;
+    else L.thomas_dir[d] = 1;
+    if (periodic && P.n[d] < 128) L.has_short_periodic = 1;
+  }
   L.max_total = std::max<long long>(L.max_total, P.total);
   L.max_cells = std::max<long long>(L.max_cells, (long long)P.n[0] * P.n[1] * P.n[2]);
   for (int d = 0; d < 3; ++d) {
@@ -327,7 +349,7 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
   P.cfl = opts->cfl;
   P.dilate = opts->dilate;
   P.grad_c4 = opts->grad == LG_GRAD_C4;
-  c->cfg = Cfg{G.ndim, opts->precision, opts->grad, opts->hybrid_mode, gas->viscous};
+  c->cfg = Cfg{G.ndim, opts->precision, opts->grad, opts->hybrid_mode, gas->viscous, opts->dilate};
 
   const size_t T = (size_t)total;
   const size_t rs = opts->precision == LG_MIXED ? sizeof(float) : sizeof(double);
@@ -344,7 +366,13 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
   P.f = static_cast<uint8_t*>(A(T));
   P.ft = static_cast<uint8_t*>(A(T));
   P.ftmp = static_cast<uint8_t*>(A(T));
+  P.fg = static_cast<uint8_t*>(A(T));
+  for (int d = 0; d < G.ndim; ++d) {
+    int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+    P.llist[d] = static_cast<int*>(A(sizeof(int) * (size_t)P.N[o1] * P.N[o2]));
+  }
   P.S3 = A(3 * T * rs);
+  P.D4 = A(15 * T * rs);
   P.CA = A(3 * T * rs);
   P.CB = A(3 * T * rs);
   for (int d = 0; d < G.ndim; ++d) P.FL[d] = A(5 * T * rs);
@@ -362,6 +390,7 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
   P.smax = reinterpret_cast<unsigned long long*>(scal + 2);
   P.status = reinterpret_cast<int*>(scal + 3);
   P.any_flag = reinterpret_cast<int*>(scal + 4);
+  P.lcount = reinterpret_cast<int*>(scal + 5);   // three ints
   P.t_end = 0.0;
   if (G.curvilinear) {
     P.M64 = node_metrics;
@@ -582,7 +611,7 @@ lg_status lg_batch_create(lg_batch** out, lg_ctx* const* ctxs, double* const* Q,
     if (!ctxs[i] || !Q[i] || !t[i]) return LG_EINVAL;
     const Cfg& ci = ctxs[i]->cfg;
     if (ci.ndim != c0.ndim || ci.precision != c0.precision || ci.grad != c0.grad ||
-        ci.hybrid_mode != c0.hybrid_mode || ci.viscous != c0.viscous)
+        ci.hybrid_mode != c0.hybrid_mode || ci.viscous != c0.viscous || ci.dilate != c0.dilate)
       return LG_EINVAL;
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == ctxs[i]) return LG_EINVAL;  // workspaces must not be shared

@@ -48,7 +48,11 @@ struct Prob {
   uint8_t* f;        // troubled flags                   [total]
   uint8_t* ft;       // dilated flags                    [total]
   uint8_t* ftmp;     // dilation scratch                 [total]
+  uint8_t* fg;       // nodes whose C-GBR inputs are needed (per-cell hybrid) [total]
+  int* llist[3];     // compacted lines of each direction that touch fg
+  int* lcount;       // [3] number of listed lines
   void* S3;          // |S|, theta, e                    [3][total]  R
+  void* D4;          // E4 physical gradients d(rho,u,v,w,p)/dx_j [15][total] R (q*3 + j)
   void* CA;          // LAD coefficients mu*,beta*,kappa* [3][total] R (result)
   void* CB;          // LAD filter scratch               [3][total]  R
   void* FL[3];       // LAD node fluxes per direction    [5][total]  R

@@ -54,6 +54,8 @@ struct Launch {
   long long max_n[3];      // interior extent per direction
   long long sweep_rows[3]; // interior lines (interior of the other two dims) per direction
   int has_short_periodic;  // some periodic direction has fewer than 128 interior nodes
+  int pcr_dir[3];          // some problem solves its lines along d by PCR
+  int thomas_dir[3];       // some problem solves its lines along d one lane per line
   int ndim;
   int seg;                 // nodes per thread in the strided sweeps
   Prof* prof;              // optional launch timing (null: off)
@@ -87,8 +89,9 @@ inline void prof_end(const Launch& L, int k) {
 void launch_bc_cons(const Launch& L, StateRef ref, int d);
 template <typename R> void launch_bc_scalar(const Launch& L, int which, int nf, int d);
 template <typename R> void launch_prim(const Launch& L, StateRef ref, int want_flags, const uint8_t* force);
-void launch_any_flag(const Launch& L);
-void launch_dilate(const Launch& L, int ndim);
+void launch_any_flag(const Launch& L, int interior_only);
+void launch_dilate(const Launch& L, int ndim, int radius, int first_src, int final_buf);
+void launch_line_lists(const Launch& L, int ndim);
 void launch_combine(const Launch& L, RKRef rr, int stage, double a, double b);
 void launch_dt(const Launch& L, const double* Qx, double* tx, double t_end, int advance_t);
 void launch_set_dt(const Launch& L, double dt);
@@ -97,12 +100,12 @@ void launch_metrics(int ndim, const int N[3], const double* coords, double* scra
                     hipStream_t s);
 template <typename R> void launch_convert(const double* src, R* dst, size_t n, hipStream_t s);
 
-// gradients
-template <typename R> void launch_grad_explicit(const Launch& L, int d, int order, int skip_if_any);
-template <typename R> void launch_grad_c4(const Launch& L, StateRef ref, int d, int skip_if_any);
+// gradients (region = 1: only where the per-cell hybrid needs C-GBR inputs)
+template <typename R> void launch_grad_explicit(const Launch& L, int d, int order, int skip_if_any, int region);
+template <typename R> void launch_grad_c4(const Launch& L, StateRef ref, int d, int skip_if_any, int region);
 // sensor and C-GBR viscous node fluxes
-template <typename R> void launch_sensor(const Launch& L, int skip_if_any);
-template <typename R> void launch_gbr_viscflux(const Launch& L, int skip_if_any);
+template <typename R> void launch_sensor(const Launch& L, int skip_if_any, int region);
+template <typename R> void launch_gbr_viscflux(const Launch& L, int skip_if_any, int region);
 // LAD
 template <typename R> void launch_lad(const Launch& L, int skip_if_any);
 // interface sweeps
