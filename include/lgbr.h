@@ -177,6 +177,14 @@ enum {
 lg_status lg_prof_start(lg_ctx* ctx, int kernel_class, int max_launches);
 lg_status lg_prof_stop(lg_ctx* ctx, double* ms, int* launches);
 
+/* Launch-shape tuning (no effect on results): seg = nodes per lane of the strided
+ * interface sweeps (0 = built-in heuristic, else 2..64); pcr_blocks = persistent
+ * workgroups of the PCR line solves (0 = built-in, else 256..65536).  Applies to later
+ * calls on the context and to batches created afterwards.  lg_get_tuning reports the
+ * values in effect (heuristic values resolved for the context's grid). */
+lg_status lg_set_tuning(lg_ctx* ctx, int seg, int pcr_blocks);
+lg_status lg_get_tuning(const lg_ctx* ctx, int* seg, int* pcr_blocks);
+
 /* Synchronises the context's stream and reads its non-physical node count since the
  * last poll (then resets it).  Returns LG_ENONPHYS when the count is non-zero. */
 lg_status lg_poll_status(lg_ctx* ctx, int* nonphys_count);

@@ -275,7 +275,7 @@ void launch_grad_c4(const Launch& L, StateRef ref, int d, int skip_if_any, int r
   if (L.pcr_dir[d]) {
     const long long N = std::min<long long>(L.max_N[d], PCR_MAX_LINE);
     const unsigned lds = (unsigned)(2 * N * sizeof(double));
-    long long blocks = std::min<long long>(5 * L.lines[d], 16384);
+    long long blocks = std::min<long long>(5 * L.lines[d], L.pcr_blocks > 0 ? L.pcr_blocks : 16384);
     LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c4_pcr<R>, dim3((unsigned)blocks, L.nprob), dim3(256), lds,
                                                L.stream, L.probs, ref, d, skip_if_any, region));
   }

@@ -366,6 +366,20 @@ void launch_sensor(const Launch& L, int skip_if_any, int region) {
                                             L.probs, skip_if_any, region));
 }
 
+int sweep_seg(const Launch& L, int d) {
+  // nodes per lane: the longest segment that still gives >= 8 waves per CU (256 CUs)
+  int seg = L.seg;
+  if (seg <= 0) {
+    seg = 4;
+    for (int c = 32; c >= 4; c >>= 1)
+      if (((L.max_n[d] + c - 1) / c) * L.sweep_rows[d] * L.nprob >= 256LL * 8 * 64) {
+        seg = c;
+        break;
+      }
+  }
+  return seg;
+}
+
 template <typename R>
 void launch_sweep(const Launch& L, StateRef ref, int d, int sel, int accumulate) {
   if (d == 0) {
@@ -376,16 +390,7 @@ void launch_sweep(const Launch& L, StateRef ref, int d, int sel, int accumulate)
     LG_TIMED(L, KC_SWEEP_X, hipLaunchKernelGGL(k_sweep_x<R>, dim3((unsigned)blocks, L.nprob), dim3(256), 0,
                                                L.stream, L.probs, ref, sel, accumulate));
   } else {
-    // nodes per lane: the longest segment that still gives >= 8 waves per CU (256 CUs)
-    int seg = L.seg;
-    if (seg <= 0) {
-      seg = 4;
-      for (int c = 32; c >= 4; c >>= 1)
-        if (((L.max_n[d] + c - 1) / c) * L.sweep_rows[d] * L.nprob >= 256LL * 8 * 64) {
-          seg = c;
-          break;
-        }
-    }
+    const int seg = sweep_seg(L, d);
     long long nch = (L.max_n[d] + seg - 1) / seg;
     long long work = nch * L.sweep_rows[d];
     long long blocks = (work + 255) / 256;

@@ -55,7 +55,7 @@ struct Cfg {
 struct lg_ctx {
   Prob hp;
   Prob* dp = nullptr;
-  Launch L;
+  Launch L{};
   lg::Prof prof{};
   Cfg cfg;
   hipStream_t stream = nullptr;
@@ -74,7 +74,7 @@ struct lg_ctx {
 struct lg_batch {
   std::vector<Prob> hps;
   Prob* dps = nullptr;
-  Launch L;
+  Launch L{};
   Cfg cfg;
   hipStream_t stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -590,6 +590,22 @@ lg_status lg_compute_dt(lg_ctx* c, const double* Q, double* dt_out) {
   return LG_OK;
 }
 
+lg_status lg_set_tuning(lg_ctx* c, int seg, int pcr_blocks) {
+  if (!c || seg < 0 || (seg > 0 && (seg < 2 || seg > 64)) || pcr_blocks < 0 ||
+      (pcr_blocks > 0 && (pcr_blocks < 256 || pcr_blocks > 65536)))
+    return LG_EINVAL;
+  c->L.seg = seg;
+  c->L.pcr_blocks = pcr_blocks;
+  return LG_OK;
+}
+
+lg_status lg_get_tuning(const lg_ctx* c, int* seg, int* pcr_blocks) {
+  if (!c || !seg || !pcr_blocks) return LG_EINVAL;
+  *seg = lg::sweep_seg(c->L, c->cfg.ndim > 1 ? 1 : 0);
+  *pcr_blocks = c->L.pcr_blocks > 0 ? c->L.pcr_blocks : 16384;
+  return LG_OK;
+}
+
 lg_status lg_poll_status(lg_ctx* c, int* count) {
   if (!c || !count) return LG_EINVAL;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return LG_EHIP;
@@ -626,6 +642,7 @@ lg_status lg_batch_create(lg_batch** out, lg_ctx* const* ctxs, double* const* Q,
   b->L.nprob = n;
   b->L.ndim = c0.ndim;
   b->L.seg = ctxs[0]->L.seg;
+  b->L.pcr_blocks = ctxs[0]->L.pcr_blocks;
   for (int i = 0; i < n; ++i) {
     Prob P = ctxs[i]->hp;
     P.Q = Q[i];

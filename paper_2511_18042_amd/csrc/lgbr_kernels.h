@@ -57,7 +57,8 @@ struct Launch {
   int pcr_dir[3];          // some problem solves its lines along d by PCR
   int thomas_dir[3];       // some problem solves its lines along d one lane per line
   int ndim;
-  int seg;                 // nodes per thread in the strided sweeps
+  int seg;                 // nodes per thread in the strided sweeps (0: heuristic)
+  int pcr_blocks;          // persistent workgroups of the PCR line solves (0: heuristic)
   Prof* prof;              // optional launch timing (null: off)
 };
 
@@ -99,6 +100,8 @@ void launch_zero_status(const Launch& L);
 void launch_metrics(int ndim, const int N[3], const double* coords, double* scratch9, double* metrics,
                     hipStream_t s);
 template <typename R> void launch_convert(const double* src, R* dst, size_t n, hipStream_t s);
+
+int sweep_seg(const Launch& L, int d);   // segment length in effect for direction d
 
 // gradients (region = 1: only where the per-cell hybrid needs C-GBR inputs)
 template <typename R> void launch_grad_explicit(const Launch& L, int d, int order, int skip_if_any, int region);

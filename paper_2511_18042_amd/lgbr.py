@@ -21,7 +21,7 @@ SCHEMES = {'cgbr': SCHEME_CGBR, 'lad': SCHEME_LAD, 'hybrid': SCHEME_HYBRID}
 EXPORTS = ('lg_set_allocator', 'lg_strerror', 'lg_create', 'lg_destroy', 'lg_workspace_bytes',
            'lg_metrics_from_coords', 'cgbr_rhs', 'lad_rhs', 'hybrid_rhs', 'rk3_step', 'lg_rk3_stage',
            'lg_compute_dt', 'lg_batch_create', 'lg_batch_run', 'lg_batch_destroy', 'lg_poll_status',
-           'lg_prof_start', 'lg_prof_stop')
+           'lg_prof_start', 'lg_prof_stop', 'lg_set_tuning', 'lg_get_tuning')
 KERNEL_CLASSES = ('bc', 'prim', 'flags', 'grad_e6', 'grad_c4', 'sensor', 'visc', 'lad_node', 'lad_raw', 'gauss',
                   'lad_flux', 'sweep_x', 'sweep_y', 'sweep_z', 'combine', 'dt', 'bc_scalar')
 
@@ -76,6 +76,8 @@ def load():
         'lg_poll_status': (I, [P, ctypes.POINTER(I)]),
         'lg_prof_start': (I, [P, I, I]),
         'lg_prof_stop': (I, [P, ctypes.POINTER(D), ctypes.POINTER(I)]),
+        'lg_set_tuning': (I, [P, I, I]),
+        'lg_get_tuning': (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -205,6 +207,14 @@ class Context:
         cnt = (ctypes.c_int * n)()
         _check(self._lib.lg_prof_stop(self.handle, ms, cnt), 'lg_prof_stop')
         return {KERNEL_CLASSES[k]: (ms[k], cnt[k]) for k in range(n) if cnt[k]}
+
+    def set_tuning(self, seg=0, pcr_blocks=0):
+        _check(self._lib.lg_set_tuning(self.handle, int(seg), int(pcr_blocks)), 'lg_set_tuning')
+
+    def get_tuning(self):
+        a, b = ctypes.c_int(0), ctypes.c_int(0)
+        _check(self._lib.lg_get_tuning(self.handle, ctypes.byref(a), ctypes.byref(b)), 'lg_get_tuning')
+        return a.value, b.value
 
     def poll_status(self):
         n = ctypes.c_int(0)

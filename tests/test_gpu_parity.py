@@ -299,3 +299,32 @@ def test_ramp_crop_rk3_step_and_mixed_error():
         U.compare(Qd.cpu().numpy(), Qn, g, tol, label='ramp rk3 ' + precision)
         assert ctx.poll_status() == 0
         ctx.close()
+
+
+def test_launch_tuning_leaves_results_bitwise_unchanged(tmp_path, monkeypatch):
+    """Segment length of the strided sweeps and the persistent PCR grid size only change
+    the launch shape: the RHS is bitwise identical for every setting, and the autotuner
+    picks one of its candidates and caches it."""
+    torch = U.torch_mod()
+    from paper_2511_18042_amd import autotune
+    c, gas = _ramp_case()
+    g = U.oracle_grid(c)
+    opts = orhs.Opts(grad='C4', p_thr=c.extra['p_thr'])
+    flags = np.random.default_rng(10).random(g.shape) < 0.1
+    ctx, _ = U.gpu_context(c, gas, opts)
+    outs = []
+    for seg, pcr in ((0, 0), (2, 256), (7, 1000), (64, 65536)):
+        print('tuning', seg, pcr, flush=True)
+        ctx.set_tuning(seg, pcr)
+        s, p = ctx.get_tuning()
+        assert (seg == 0 or s == seg) and p == (pcr or 16384)
+        outs.append(U.gpu_rhs(ctx, c, 'hybrid', flags=flags))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    monkeypatch.setenv('LGBR_TUNE_CACHE', str(tmp_path / 'tune.json'))
+    Q0 = U.dev(c.Q)
+    (seg, pcr), timings = autotune.tune(ctx, Q0, 'hybrid', steps=1)
+    assert seg in autotune.CANDIDATE_SEG and pcr in autotune.CANDIDATE_PCR and len(timings) == 15
+    assert autotune.tune(ctx, Q0, 'hybrid')[0] == (seg, pcr)          # served from the cache
+    ctx.close()
+    torch.cuda.synchronize()
