@@ -38,25 +38,31 @@ def parse():
     ap.add_argument('--workload', default='all', choices=['all', 'ramp3d', 'triple_point'])
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--variants', default='all', choices=['all', 'none'])
+    ap.add_argument('--copy-probe-mib', type=int, default=0,
+                    help='run one plain device copy of this many MiB first (calibrates HBM counters)')
     return ap.parse_args()
 
 
-def algorithmic_bytes(kclass, nodes, rs, ndim, gbr_frac, viscous):
+def algorithmic_bytes(kclass, nodes, rs, ndim, gbr_frac, viscous, curv):
     """Minimum bytes one launch of a kernel class moves (every input read once, every
-    output written once) for ``nodes`` interior nodes; rs = bytes of the bulk real type."""
+    output written once) for ``nodes`` interior nodes; rs = bytes of the bulk real type,
+    curv: node metrics (9 components + J) are fields rather than constants."""
     vis = 5 * rs if viscous else 0
+    met = 10 * rs if curv else 0
     if kclass == 'sweep_x':
         per = (1 - gbr_frac) * 5 * rs + gbr_frac * (11 * rs + vis) + 1 + 40
     elif kclass in ('sweep_y', 'sweep_z'):
         per = (1 - gbr_frac) * 5 * rs + gbr_frac * (11 * rs + vis) + 1 + 80
-    elif kclass == 'lad_flux':
-        per = 5 * rs + 15 * rs + 3 * rs + 5 * rs * ndim     # W, physical gradients, coefficients -> F_l
-    elif kclass == 'lad_raw':
-        per = 2 * rs + 15 * rs + 3 * rs + 3 * rs           # rho, p, gradients, |S| theta e -> raw
     elif kclass == 'lad_node':
-        per = 5 * rs + 15 * rs + 3 * rs                     # W -> physical gradients, |S| theta e
+        per = 5 * rs + met + 2 * rs                          # W, metrics -> |S|, theta
+    elif kclass == 'lad_raw':
+        per = 5 * rs + 2 * rs + met + (3 * ndim * rs if curv else 0) + 3 * rs   # + Delta x_l -> raw
     elif kclass == 'gauss':
-        per = 6 * rs
+        per = 6 * rs                                         # one launch: 3 fields in, 3 out
+    elif kclass == 'lad_flux':
+        per = 5 * rs + 3 * rs + met + 5 * ndim * rs          # W, coefficients, metrics -> F_l
+    elif kclass == 'lad_sweep':
+        per = 5 * ndim * rs + (8 if curv else 0) + 120       # F_l, J, U^n, U^s -> stage result
     elif kclass == 'grad_e6':
         per = 10 * rs
     elif kclass == 'grad_c4':
@@ -161,7 +167,7 @@ def run_workload(name, K, W, variants, cpu):
     gbr_frac = float(ft[inner].mean())
     dom_ms, dom_n = kern[dominant]
     dom_avg = dom_ms / max(dom_n, 1)
-    algo = algorithmic_bytes(dominant, cells, 4, c.ndim, gbr_frac, viscous)
+    algo = algorithmic_bytes(dominant, cells, 4, c.ndim, gbr_frac, viscous, curv)
     achieved = algo / (dom_avg * 1e-3) / 1e9
     res.update({
         'value': round(cells / (ms * 1e-3) / 1e6, 2), 'ms_per_step': round(ms, 4), 'nonphysical_nodes': bad,
@@ -230,6 +236,13 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
+    if args.copy_probe_mib > 0:
+        a = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device='cuda')
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        torch.cuda.empty_cache()
     names = ['ramp3d', 'triple_point'] if args.workload == 'all' else [args.workload]
     results = {}
     for nm in names:

@@ -172,18 +172,19 @@ void lg_batch_destroy(lg_batch* batch);
 enum {
   LG_KC_BC = 0, LG_KC_PRIM, LG_KC_FLAGS, LG_KC_GRAD_E6, LG_KC_GRAD_C4, LG_KC_SENSOR, LG_KC_VISC,
   LG_KC_LAD_NODE, LG_KC_LAD_RAW, LG_KC_GAUSS, LG_KC_LAD_FLUX, LG_KC_SWEEP_X, LG_KC_SWEEP_Y,
-  LG_KC_SWEEP_Z, LG_KC_COMBINE, LG_KC_DT, LG_KC_BC_SCALAR, LG_KC_COUNT
+  LG_KC_SWEEP_Z, LG_KC_COMBINE, LG_KC_DT, LG_KC_BC_SCALAR, LG_KC_LAD_SWEEP, LG_KC_COUNT
 };
 lg_status lg_prof_start(lg_ctx* ctx, int kernel_class, int max_launches);
 lg_status lg_prof_stop(lg_ctx* ctx, double* ms, int* launches);
 
 /* Launch-shape tuning (no effect on results): seg = nodes per lane of the strided
  * interface sweeps (0 = built-in heuristic, else 2..64); pcr_blocks = persistent
- * workgroups of the PCR line solves (0 = built-in, else 256..65536).  Applies to later
+ * workgroups of the PCR line solves (0 = built-in, else 256..65536); zc = planes per
+ * chunk of the z-marching stencil kernels (0 = built-in, else 1..1024).  Applies to later
  * calls on the context and to batches created afterwards.  lg_get_tuning reports the
  * values in effect (heuristic values resolved for the context's grid). */
-lg_status lg_set_tuning(lg_ctx* ctx, int seg, int pcr_blocks);
-lg_status lg_get_tuning(const lg_ctx* ctx, int* seg, int* pcr_blocks);
+lg_status lg_set_tuning(lg_ctx* ctx, int seg, int pcr_blocks, int zc);
+lg_status lg_get_tuning(const lg_ctx* ctx, int* seg, int* pcr_blocks, int* zc);
 
 /* Synchronises the context's stream and reads its non-physical node count since the
  * last poll (then resets it).  Returns LG_ENONPHYS when the count is non-zero. */

@@ -181,8 +181,10 @@ __global__ void k_zero_lcount(const Prob* __restrict__ probs) {
 // ------------------------------------------------------------------ RK3 combination
 // out = a U^n + b (U^s + dt L) on interior nodes, out = U^n on ghost nodes; counts
 // non-physical interior results (rho <= 0, p <= 0 or not finite).
-__global__ void __launch_bounds__(256) k_combine(const Prob* __restrict__ probs, RKRef rr, int stage, double a, double b) {
+__global__ void __launch_bounds__(256) k_combine(const Prob* __restrict__ probs, RKRef rr, int stage, double a, double b,
+                                                 int skip_if_any) {
   const Prob& P = probs[blockIdx.y];
+  if (gate_skip(P, skip_if_any)) return;
   const double* Un = rr.Un ? rr.Un : P.Q;
   const double* Us = rr.Us ? rr.Us : (stage == 0 ? Un : P.Us);
   double* out = rr.out ? rr.out : (stage == 2 ? const_cast<double*>(Un) : P.Us);
@@ -427,9 +429,9 @@ void launch_line_lists(const Launch& L, int ndim) {
   }
 }
 
-void launch_combine(const Launch& L, RKRef rr, int stage, double a, double b) {
+void launch_combine(const Launch& L, RKRef rr, int stage, double a, double b, int skip_if_any) {
   LG_TIMED(L, KC_COMBINE, hipLaunchKernelGGL(k_combine, grid_for(L.max_total, L.nprob), dim3(256), 0, L.stream,
-                                             L.probs, rr, stage, a, b));
+                                             L.probs, rr, stage, a, b, skip_if_any));
 }
 
 void launch_dt(const Launch& L, const double* Qx, double* tx, double t_end, int advance_t) {

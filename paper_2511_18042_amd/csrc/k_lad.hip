@@ -29,7 +29,7 @@ __device__ __forceinline__ bool lad_skip(const Prob& P, int skip_if_any) {
 
 template <typename R>
 __device__ __forceinline__ R e4_at(const R* f, int idx, int s) {
-  return (R(8) * (f[idx + s] - f[idx - s]) - (f[idx + 2 * s] - f[idx - 2 * s])) / R(12);
+  return (R(8) * (f[idx + s] - f[idx - s]) - (f[idx + 2 * s] - f[idx - 2 * s])) * R(1.0 / 12.0);
 }
 
 // physical gradients D[q][j] of the 5 primitives at node idx from computational
@@ -46,38 +46,30 @@ __device__ __forceinline__ void to_physical(const Prob& P, int idx, const R gl[3
     }
 }
 
+// Sutherland viscosity and conductivity from rho, p (ri = 1 / rho)
 template <typename R>
-__device__ __forceinline__ void e4_grads(const Prob& P, const R* W, int idx, R gl[3][5]) {
-  const size_t T = P.total;
-  for (int l = 0; l < 3; ++l)
-    for (int q = 0; q < 5; ++q) gl[l][q] = R(0);
-  for (int l = 0; l < P.ndim; ++l)
-    for (int q = 0; q < 5; ++q) gl[l][q] = e4_at(W + q * T, idx, P.s[l]);
-}
-
-template <typename R>
-__device__ __forceinline__ void transport(const Prob& P, R rho, R p, R& mu, R& kappa) {
+__device__ __forceinline__ void transport(const Prob& P, R ri, R p, R& mu, R& kappa) {
   if (!P.viscous) {
     mu = R(0);
     kappa = R(0);
     return;
   }
-  R T = R(P.gamma * P.Mref * P.Mref) * p / rho;
+  R T = R(P.gamma * P.Mref * P.Mref) * p * ri;
   R S = (R)P.suth;
-  mu = T * sqrt(T) * (R(1) + S) / (T + S) / R(P.Re);
-  kappa = mu / R((P.gamma - 1.0) * P.Pr * P.Mref * P.Mref);
+  mu = T * sqrt(T) * (R(1) + S) * rcp(T + S) * R(1.0 / P.Re);
+  kappa = mu * R(1.0 / ((P.gamma - 1.0) * P.Pr * P.Mref * P.Mref));
 }
 
-// -l_hat . [0, tau, phi] at node idx (Eq. tauij)
+// -l_hat . [0, tau, phi] at node idx (Eq. tauij); ri = 1 / rho
 template <typename R>
-__device__ __forceinline__ void viscous_flux(const Prob& P, int idx, int l, const R w[5], const R D[5][3],
+__device__ __forceinline__ void viscous_flux(const Prob& P, int idx, int l, const R w[5], R ri, const R D[5][3],
                                              R mu, R beta, R kappa, R F[5]) {
   R du[3][3];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) du[i][j] = D[1 + i][j];
   R theta = du[0][0] + du[1][1] + du[2][2];
   R g2 = R(P.gamma * P.Mref * P.Mref);
-  R rho = w[0], p = w[4];
+  R p = w[4];
   R tau[3][3];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {
@@ -86,7 +78,7 @@ __device__ __forceinline__ void viscous_flux(const Prob& P, int idx, int l, cons
     }
   R phi[3];
   for (int i = 0; i < 3; ++i) {
-    R dT = g2 * (D[4][i] / rho - p * D[0][i] / (rho * rho));
+    R dT = g2 * (D[4][i] * ri - p * D[0][i] * (ri * ri));
     phi[i] = w[1] * tau[i][0] + w[2] * tau[i][1] + w[3] * tau[i][2] + kappa * dT;
   }
   R m0 = met<R>(P, 3 * l, idx), m1 = met<R>(P, 3 * l + 1, idx), m2 = met<R>(P, 3 * l + 2, idx);
@@ -104,42 +96,17 @@ __device__ __forceinline__ bool in_band(const Prob& P, int idx, int lo, int hi) 
 
 __device__ __forceinline__ bool is_interior(const Prob& P, int idx) { return in_band(P, idx, 0, 0); }
 
-// E4 physical gradients D (stored for the raw coefficients and the node fluxes) and
-// |S|, div u, e at every node where E4 fits (positions -3 .. n+2)
+// ------------------------------------------------------------------ z-marching helpers
+// E4 derivative from the values at offsets -2, -1, +1, +2 (same rounding as e4_at).
 template <typename R>
-__global__ void __launch_bounds__(256) k_lad_grad(const Prob* __restrict__ probs, int skip_if_any) {
-  const Prob& P = probs[blockIdx.y];
-  if (lad_skip(P, skip_if_any)) return;
-  const R* W = static_cast<const R*>(P.W);
-  R* S3 = static_cast<R*>(P.S3);
-  R* DD = static_cast<R*>(P.D4);
-  const size_t T = P.total;
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < P.total; idx += gridDim.x * blockDim.x) {
-    if (!in_band(P, idx, -3, 3)) continue;
-    R gl[3][5], D[5][3];
-    e4_grads(P, W, idx, gl);
-    to_physical(P, idx, gl, D);
-    for (int q = 0; q < 5; ++q)
-      for (int j = 0; j < 3; ++j) DD[(size_t)(3 * q + j) * T + idx] = D[q][j];
-    R S2 = R(0);
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) {
-        R sij = R(0.5) * (D[1 + i][j] + D[1 + j][i]);
-        S2 += sij * sij;
-      }
-    R rho = W[idx], p = W[4 * T + idx];
-    S3[idx] = sqrt(S2);
-    S3[T + idx] = D[1][0] + D[2][1] + D[3][2];
-    S3[2 * T + idx] = p / (R(P.gamma - 1.0) * rho);
-  }
+__device__ __forceinline__ R e4v(R m2, R m1, R p1, R p2) {
+  return (R(8) * (p1 - m1) - (p2 - m2)) * R(1.0 / 12.0);
 }
 
+// fourth difference from the values at offsets -2 .. 2 (same rounding as delta4)
 template <typename R>
-__device__ __forceinline__ void load_D(const Prob& P, int idx, R D[5][3]) {
-  const R* DD = static_cast<const R*>(P.D4);
-  const size_t T = P.total;
-  for (int q = 0; q < 5; ++q)
-    for (int j = 0; j < 3; ++j) D[q][j] = DD[(size_t)(3 * q + j) * T + idx];
+__device__ __forceinline__ R d4v(R m2, R m1, R c0, R p1, R p2) {
+  return m2 - R(4) * m1 + R(6) * c0 - R(4) * p1 + p2;
 }
 
 template <typename R>
@@ -147,105 +114,331 @@ __device__ __forceinline__ R delta4(const R* f, int idx, int s) {
   return f[idx - 2 * s] - R(4) * f[idx - s] + R(6) * f[idx] - R(4) * f[idx + s] + f[idx + 2 * s];
 }
 
-// raw (unfiltered) coefficients at interior nodes
+// Register queue of NV fields at planes k-2 .. k+2 of one column (3D z-marching).
+template <typename R, int NV>
+struct ZQ5 {
+  R v[5][NV];
+  // before the first plane k0: planes k0-2 .. k0+1 into slots 1..4
+  __device__ __forceinline__ void prime(const R* f, size_t T, int idx, int sz) {
+    for (int p = 1; p < 5; ++p)
+      for (int q = 0; q < NV; ++q) v[p][q] = f[q * T + idx + (p - 3) * sz];
+  }
+  // advance to plane k (idx): slots 0..4 = planes k-2 .. k+2
+  __device__ __forceinline__ void step(const R* f, size_t T, int idx, int sz) {
+    for (int p = 0; p < 4; ++p)
+      for (int q = 0; q < NV; ++q) v[p][q] = v[p + 1][q];
+    for (int q = 0; q < NV; ++q) v[4][q] = f[q * T + idx + 2 * sz];
+  }
+};
+
+// computational E4 derivatives of the 5 primitives at idx; z from the queue (3D)
 template <typename R>
-__global__ void __launch_bounds__(256) k_lad_raw(const Prob* __restrict__ probs, int skip_if_any) {
-  const Prob& P = probs[blockIdx.y];
-  if (lad_skip(P, skip_if_any)) return;
-  const R* W = static_cast<const R*>(P.W);
-  const R* S3 = static_cast<const R*>(P.S3);
-  R* C = static_cast<R*>(P.CA);
+__device__ __forceinline__ void e4_grads_zm(const Prob& P, const R* W, int idx, const ZQ5<R, 5>& qz, R gl[3][5]) {
   const size_t T = P.total;
-  const R gm1 = R(P.gamma - 1.0);
+  for (int l = 0; l < 3; ++l)
+    for (int q = 0; q < 5; ++q) gl[l][q] = R(0);
+  for (int q = 0; q < 5; ++q) {
+    gl[0][q] = e4_at(W + q * T, idx, P.s[0]);
+    if (P.ndim > 1) gl[1][q] = e4_at(W + q * T, idx, P.s[1]);
+    if (P.ndim > 2) gl[2][q] = e4v(qz.v[0][q], qz.v[1][q], qz.v[3][q], qz.v[4][q]);
+  }
+}
+
+// ------------------------------------------------------------------ grid factors
+// Delta x_l at interior nodes (curvilinear grids; once per context)
+template <typename R>
+__global__ void __launch_bounds__(256) k_lad_dx(const Prob* __restrict__ probs) {
+  const Prob& P = probs[blockIdx.y];
+  if (!P.curvilinear) return;
+  R* GX = static_cast<R*>(P.GX);
+  const size_t T = P.total;
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < P.total; idx += gridDim.x * blockDim.x) {
     if (!is_interior(P, idx)) continue;
-    R D[5][3];
-    load_D(P, idx, D);
+    for (int l = 0; l < 3; ++l)
+      for (int cc = 0; cc < 3; ++cc) {
+        R v = R(0);
+        if (l < P.ndim) {
+          const double* X = P.coords + (size_t)cc * T;
+          v = (R)(0.5 * (X[idx + P.s[l]] - X[idx - P.s[l]]));
+        }
+        GX[(size_t)(3 * l + cc) * T + idx] = v;
+      }
+  }
+}
+
+// ------------------------------------------------------------------ |S| and theta
+// at positions -2 .. n+1 (the fourth differences of the raw coefficients reach two nodes
+// past the interior); E4 physical gradients recomputed from W
+template <typename R>
+__global__ void __launch_bounds__(256) k_lad_shear(const Prob* __restrict__ probs, int skip_if_any, int zc) {
+  const Prob& P = probs[blockIdx.y];
+  if (lad_skip(P, skip_if_any)) return;
+  ZCol c;
+  if (!zm_column(P, -2, 2, zc, c)) return;
+  const R* W = static_cast<const R*>(P.W);
+  R* S = static_cast<R*>(P.S3);
+  const size_t T = P.total;
+  const int sz = P.s[2];
+  const bool z3 = P.ndim == 3;
+  int idx = pos_to_idx(P, c.i, c.j, c.k0);
+  ZQ5<R, 5> qz;
+  if (z3) qz.prime(W, T, idx, sz);
+  for (int k = c.k0; k < c.k1; ++k, idx += sz) {
+    if (z3) qz.step(W, T, idx, sz);
+    R gl[3][5], D[5][3];
+    e4_grads_zm(P, W, idx, qz, gl);
+    to_physical(P, idx, gl, D);
+    R S2 = R(0);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        R sij = R(0.5) * (D[1 + i][j] + D[1 + j][i]);
+        S2 += sij * sij;
+      }
+    S[idx] = sqrt(S2);
+    S[T + idx] = D[1][0] + D[2][1] + D[3][2];
+  }
+}
+
+// ------------------------------------------------------------------ raw coefficients
+// at interior nodes; e = p / ((gamma - 1) rho) from W wherever needed
+template <typename R>
+__global__ void __launch_bounds__(256) k_lad_raw(const Prob* __restrict__ probs, int skip_if_any, int zc) {
+  const Prob& P = probs[blockIdx.y];
+  if (lad_skip(P, skip_if_any)) return;
+  ZCol c;
+  if (!zm_column(P, 0, 0, zc, c)) return;
+  const R* W = static_cast<const R*>(P.W);
+  const R* S = static_cast<const R*>(P.S3);
+  const R* GX = static_cast<const R*>(P.GX);
+  R* C = static_cast<R*>(P.CA);
+  const size_t T = P.total;
+  const int sz = P.s[2];
+  const bool z3 = P.ndim == 3;
+  const R gm1 = R(P.gamma - 1.0), igm1 = R(1.0 / (P.gamma - 1.0));
+  int idx = pos_to_idx(P, c.i, c.j, c.k0);
+  ZQ5<R, 5> qz;
+  ZQ5<R, 2> qs;
+  if (z3) {
+    qz.prime(W, T, idx, sz);
+    qs.prime(S, T, idx, sz);
+  }
+  for (int k = c.k0; k < c.k1; ++k, idx += sz) {
+    if (z3) {
+      qz.step(W, T, idx, sz);
+      qs.step(S, T, idx, sz);
+    }
+    R gl[3][5], D[5][3];
+    e4_grads_zm(P, W, idx, qz, gl);
+    to_physical(P, idx, gl, D);
     R rho = W[idx], p = W[4 * T + idx];
+    R ri = rcp(rho);
     R theta = D[1][0] + D[2][1] + D[3][2];
     R w1 = D[3][1] - D[2][2], w2 = D[1][2] - D[3][0], w3 = D[2][0] - D[1][1];
     R om2 = w1 * w1 + w2 * w2 + w3 * w3;
     R de[3], gr[3];
     for (int j = 0; j < 3; ++j) {
-      de[j] = (D[4][j] / rho - p * D[0][j] / (rho * rho)) / gm1;
+      de[j] = (D[4][j] * ri - p * D[0][j] * (ri * ri)) * igm1;
       gr[j] = D[0][j];
     }
-    R nr = sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]) + R(1e-32);
-    R ne = sqrt(de[0] * de[0] + de[1] * de[1] + de[2] * de[2]) + R(1e-32);
-    R Tt = R(P.gamma * P.Mref * P.Mref) * p / rho;
-    R c = sqrt(R(P.gamma) * p / rho);
-    R fsw = theta < R(0) ? theta * theta / (theta * theta + om2 + R(1e-32)) : R(0);
+    R inr = rcp(sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]) + R(1e-32));
+    R ine = rcp(sqrt(de[0] * de[0] + de[1] * de[1] + de[2] * de[2]) + R(1e-32));
+    R Tt = R(P.gamma * P.Mref * P.Mref) * p * ri;
+    R cs = sqrt(R(P.gamma) * p * ri);
+    R fsw = theta < R(0) ? theta * theta * rcp(theta * theta + om2 + R(1e-32)) : R(0);
     R smu = R(0), sbeta = R(0), skap = R(0);
     for (int l = 0; l < P.ndim; ++l) {
       R dx[3];
       if (P.curvilinear) {
-        for (int cc = 0; cc < 3; ++cc) {
-          const double* X = P.coords + (size_t)cc * T;
-          dx[cc] = (R)(0.5 * (X[idx + P.s[l]] - X[idx - P.s[l]]));
-        }
+        for (int cc = 0; cc < 3; ++cc) dx[cc] = GX[(size_t)(3 * l + cc) * T + idx];
       } else {
         dx[0] = dx[1] = dx[2] = R(0);
         dx[l] = (R)P.h[l];
       }
       R dmu2 = dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2];
-      R dbeta = (dx[0] * gr[0] + dx[1] * gr[1] + dx[2] * gr[2]) / nr;
-      R dkap = fabs(dx[0] * de[0] + dx[1] * de[1] + dx[2] * de[2]) / ne;
-      smu += delta4(S3, idx, P.s[l]) * dmu2;
-      sbeta += delta4(S3 + T, idx, P.s[l]) * dbeta * dbeta;
-      skap += delta4(S3 + 2 * T, idx, P.s[l]) * dkap;
+      R dbeta = (dx[0] * gr[0] + dx[1] * gr[1] + dx[2] * gr[2]) * inr;
+      R dkap = fabs(dx[0] * de[0] + dx[1] * de[1] + dx[2] * de[2]) * ine;
+      R f4S, f4t, f4e;
+      if (l < 2) {
+        const int s = P.s[l];
+        f4S = delta4(S, idx, s);
+        f4t = delta4(S + T, idx, s);
+        R e[5];
+        for (int o = -2; o <= 2; ++o) {
+          const int id = idx + o * s;
+          e[o + 2] = W[4 * T + id] * rcp(gm1 * W[id]);
+        }
+        f4e = d4v(e[0], e[1], e[2], e[3], e[4]);
+      } else {
+        f4S = d4v(qs.v[0][0], qs.v[1][0], qs.v[2][0], qs.v[3][0], qs.v[4][0]);
+        f4t = d4v(qs.v[0][1], qs.v[1][1], qs.v[2][1], qs.v[3][1], qs.v[4][1]);
+        R e[5];
+        for (int o = 0; o < 5; ++o) e[o] = qz.v[o][4] * rcp(gm1 * qz.v[o][0]);
+        f4e = d4v(e[0], e[1], e[2], e[3], e[4]);
+      }
+      smu += f4S * dmu2;
+      sbeta += f4t * dbeta * dbeta;
+      skap += f4e * dkap;
     }
     C[idx] = R(P.C_mu) * rho * fabs(smu);
     C[T + idx] = R(P.C_beta) * rho * fsw * fabs(sbeta);
-    C[2 * T + idx] = R(P.C_kappa) * rho * c / Tt * fabs(skap);
+    C[2 * T + idx] = R(P.C_kappa) * rho * cs * rcp(Tt) * fabs(skap);
   }
 }
 
-// one truncated-Gaussian pass along d at interior nodes (3 fields)
+// ------------------------------------------------------------------ truncated Gaussian
+// The three one-directional passes of the filter, each followed by ghost images, read
+// the previous pass at image positions: the xi and eta passes run together on LDS tiles
+// of one plane (rows mapped to their images, columns through the images of the raw
+// coefficients), the zeta pass z-marches with a nine-plane register queue.  No ghost
+// refill launches are needed; consumers read the result through scalar_image().
 template <typename R>
-__global__ void __launch_bounds__(256) k_gauss(const Prob* __restrict__ probs, int d, int src, int skip_if_any) {
+struct GaussW {
+  static constexpr R w0 = R(3565.0 / 10368.0), w1 = R(3091.0 / 12960.0), w2 = R(1997.0 / 25920.0),
+                     w3 = R(149.0 / 12960.0), w4 = R(107.0 / 103680.0);
+};
+
+// f[-4*s] .. f[4*s] around f (same rounding as one pass of the filter)
+template <typename R>
+__device__ __forceinline__ R gauss9(const R* f, int s) {
+  R v = GaussW<R>::w0 * f[0];
+  v = v + GaussW<R>::w1 * (f[s] + f[-s]);
+  v = v + GaussW<R>::w2 * (f[2 * s] + f[-2 * s]);
+  v = v + GaussW<R>::w3 * (f[3 * s] + f[-3 * s]);
+  v = v + GaussW<R>::w4 * (f[4 * s] + f[-4 * s]);
+  return v;
+}
+
+template <typename R, int TY>
+__global__ void __launch_bounds__(256) k_gauss_xy(const Prob* __restrict__ probs, int skip_if_any, int zc) {
+  constexpr int TX = 64, RX = TX + 8, RY = TY + 8;
+  constexpr int LR = (RY + 2) / 3;  // region rows per loading thread (216 threads: 72 columns x 3)
+  constexpr int XR = RY / 4;        // xi-pass rows per thread (64 columns x 4)
+  constexpr int YR = TY / 4;        // output rows per thread
+  __shared__ R sC[3][RY][RX];
+  __shared__ R sX[3][RY][TX];
   const Prob& P = probs[blockIdx.y];
-  if (d >= P.ndim || lad_skip(P, skip_if_any)) return;
-  const R* in = static_cast<const R*>(src == 0 ? P.CA : P.CB);
-  R* out = static_cast<R*>(src == 0 ? P.CB : P.CA);
+  if (lad_skip(P, skip_if_any)) return;
+  int org[3], ext[3];
+  zm_band(P, 0, 0, org, ext);
+  int ti0, tj0, k0, k1;
+  if (!zm_tile<TX, TY>(ext, zc, ti0, tj0, k0, k1)) return;
+  const R* C = static_cast<const R*>(P.CA);
+  R* out = static_cast<R*>(P.CB);
   const size_t T = P.total;
-  const R w0 = R(3565.0 / 10368.0), w1 = R(3091.0 / 12960.0), w2 = R(1997.0 / 25920.0),
-          w3 = R(149.0 / 12960.0), w4 = R(107.0 / 103680.0);
-  const int s = P.s[d];
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < P.total; idx += gridDim.x * blockDim.x) {
-    if (!is_interior(P, idx)) continue;
-    for (int q = 0; q < 3; ++q) {
-      const R* f = in + q * T + idx;
-      R v = w0 * f[0];
-      v = v + w1 * (f[s] + f[-s]);
-      v = v + w2 * (f[2 * s] + f[-2 * s]);
-      v = v + w3 * (f[3 * s] + f[-3 * s]);
-      v = v + w4 * (f[4 * s] + f[-4 * s]);
-      out[q * T + idx] = v;
+  const int tid = threadIdx.x;
+  const bool two = P.ndim > 1;
+  // region loads: column tid % 72 and rows tid / 72 + 3 m, through their ghost images;
+  // -1 marks columns / rows past what this tile's nodes reach (left unused)
+  const int lc = tid % RX, lr = tid / RX;
+  int lbase[LR];
+  {
+    const int pi = org[0] + ti0 - 4 + lc;
+    const bool okc = tid < 3 * RX && pi < org[0] + ext[0] + 4;
+    const int gi = okc ? scalar_image(P, 0, pi) : 0;
+    for (int m = 0; m < LR; ++m) {
+      const int r = lr + 3 * m;
+      const int pj = org[1] + tj0 - 4 + r;
+      const bool ok = okc && r < RY && (!two || pj < org[1] + ext[1] + 4);
+      lbase[m] = ok ? gi + P.s[1] * (two ? scalar_image(P, 1, pj) : 0) : -1;
+    }
+  }
+  const int cx = tid % TX, rg = tid / TX;
+  int obase[YR];
+  for (int m = 0; m < YR; ++m) {
+    const int ti = ti0 + cx, tj = tj0 + rg + 4 * m;
+    obase[m] = (ti < ext[0] && tj < ext[1]) ? pos_to_idx(P, org[0] + ti, org[1] + tj, 0) : -1;
+  }
+  for (int kk = k0; kk < k1; ++kk) {
+    const int koff = P.s[2] * (org[2] + kk);
+    for (int m = 0; m < LR; ++m) {
+      const int r = lr + 3 * m;
+      if (r < RY && tid < 3 * RX)
+        for (int q = 0; q < 3; ++q) sC[q][r][lc] = lbase[m] >= 0 ? C[q * T + lbase[m] + koff] : R(0);
+    }
+    __syncthreads();
+    for (int m = 0; m < XR; ++m)
+      for (int q = 0; q < 3; ++q) sX[q][rg + 4 * m][cx] = gauss9(&sC[q][rg + 4 * m][cx + 4], 1);
+    __syncthreads();
+    // the next plane's loads touch sC only, and its xi pass (which rewrites sX) starts
+    // after a barrier that every read below precedes
+    for (int m = 0; m < YR; ++m) {
+      if (obase[m] < 0) continue;
+      const int r = rg + 4 * m;
+      for (int q = 0; q < 3; ++q) {
+        const R v = two ? gauss9(&sX[q][r + 4][cx], TX) : sX[q][r + 4][cx];
+        out[q * T + obase[m] + koff] = v;
+      }
     }
   }
 }
 
-// LAD node fluxes F^c + F^v for every active direction at positions -2 .. n+1
 template <typename R>
-__global__ void __launch_bounds__(256) k_lad_nodeflux(const Prob* __restrict__ probs, int coef_buf, int skip_if_any) {
+__global__ void __launch_bounds__(256) k_gauss_z(const Prob* __restrict__ probs, int skip_if_any, int zc) {
+  const Prob& P = probs[blockIdx.y];
+  if (P.ndim < 3 || lad_skip(P, skip_if_any)) return;
+  ZCol c;
+  if (!zm_column(P, 0, 0, zc, c)) return;
+  const R* in = static_cast<const R*>(P.CB);
+  R* out = static_cast<R*>(P.CA);
+  const size_t T = P.total;
+  const int col = pos_to_idx(P, c.i, c.j, 0);
+  R qz[9][3];  // planes k-4 .. k+4 (ghost planes through their images)
+  for (int p = 1; p < 9; ++p) {
+    const int id = col + P.s[2] * scalar_image(P, 2, c.k0 - 5 + p);
+    for (int q = 0; q < 3; ++q) qz[p][q] = in[q * T + id];
+  }
+  for (int k = c.k0; k < c.k1; ++k) {
+    for (int p = 0; p < 8; ++p)
+      for (int q = 0; q < 3; ++q) qz[p][q] = qz[p + 1][q];
+    const int id = col + P.s[2] * scalar_image(P, 2, k + 4);
+    for (int q = 0; q < 3; ++q) qz[8][q] = in[q * T + id];
+    for (int q = 0; q < 3; ++q) {
+      R v = GaussW<R>::w0 * qz[4][q];
+      v = v + GaussW<R>::w1 * (qz[5][q] + qz[3][q]);
+      v = v + GaussW<R>::w2 * (qz[6][q] + qz[2][q]);
+      v = v + GaussW<R>::w3 * (qz[7][q] + qz[1][q]);
+      v = v + GaussW<R>::w4 * (qz[8][q] + qz[0][q]);
+      out[q * T + col + P.s[2] * k] = v;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ LAD node fluxes
+// F^c + F^v for every active direction at positions -2 .. n+1; gradients recomputed from
+// W, coefficients read at the image of the node
+template <typename R>
+__global__ void __launch_bounds__(256) k_lad_nodeflux(const Prob* __restrict__ probs, int coef_buf, int skip_if_any,
+                                                      int zc) {
   const Prob& P = probs[blockIdx.y];
   if (lad_skip(P, skip_if_any)) return;
+  ZCol c;
+  if (!zm_column(P, -2, 2, zc, c)) return;
   const R* W = static_cast<const R*>(P.W);
   const R* C = static_cast<const R*>(coef_buf == 0 ? P.CA : P.CB);
   const size_t T = P.total;
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < P.total; idx += gridDim.x * blockDim.x) {
-    if (!in_band(P, idx, -2, 2)) continue;
+  const int sz = P.s[2];
+  const bool z3 = P.ndim == 3;
+  const int ci = scalar_image(P, 0, c.i);
+  const int cj = P.ndim > 1 ? scalar_image(P, 1, c.j) : c.j;
+  int idx = pos_to_idx(P, c.i, c.j, c.k0);
+  ZQ5<R, 5> qz;
+  if (z3) qz.prime(W, T, idx, sz);
+  for (int k = c.k0; k < c.k1; ++k, idx += sz) {
+    if (z3) qz.step(W, T, idx, sz);
     R w[5];
     for (int q = 0; q < 5; ++q) w[q] = W[q * T + idx];
-    R D[5][3];
-    load_D(P, idx, D);
+    R gl[3][5], D[5][3];
+    e4_grads_zm(P, W, idx, qz, gl);
+    to_physical(P, idx, gl, D);
+    const int cidx = pos_to_idx(P, ci, cj, z3 ? scalar_image(P, 2, k) : k);
+    const R ri = rcp(w[0]);
     R muf, kapf;
-    transport(P, w[0], w[4], muf, kapf);
-    R mu = muf + C[idx], beta = C[T + idx], kappa = kapf + C[2 * T + idx];
-    R E = w[4] / R(P.gamma - 1.0) + R(0.5) * w[0] * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
+    transport(P, ri, w[4], muf, kapf);
+    R mu = muf + C[cidx], beta = C[T + cidx], kappa = kapf + C[2 * T + cidx];
+    R E = w[4] * R(1.0 / (P.gamma - 1.0)) + R(0.5) * w[0] * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
     for (int l = 0; l < P.ndim; ++l) {
       R F[5];
-      viscous_flux(P, idx, l, w, D, mu, beta, kappa, F);
+      viscous_flux(P, idx, l, w, ri, D, mu, beta, kappa, F);
       R m0 = met<R>(P, 3 * l, idx), m1 = met<R>(P, 3 * l + 1, idx), m2 = met<R>(P, 3 * l + 2, idx);
       R U = m0 * w[1] + m1 * w[2] + m2 * w[3];
       R* out = static_cast<R*>(P.FL[l]);
@@ -255,6 +448,97 @@ __global__ void __launch_bounds__(256) k_lad_nodeflux(const Prob* __restrict__ p
       out[3 * T + idx] = w[0] * w[3] * U + m2 * w[4] + F[3];
       out[4 * T + idx] = (E + w[4]) * U + F[4];
     }
+  }
+}
+
+// ------------------------------------------------------------------ all-LAD interfaces
+// dQ/dt = -J sum_l (F_{l,+1/2} - F_{l,-1/2}) with F = I4 of the node fluxes (fourth-order
+// midpoint interpolation), the differences in FP64 in the order xi, eta, zeta; mode 0
+// stores it, mode 1 forms the RK stage a U^n + b (U^s + dt L) in place of the combination
+// kernel (interior nodes; non-physical results are counted).
+template <typename R>
+__device__ __forceinline__ R i4v(R m1, R c0, R p1, R p2) {
+  return (R(7) * (c0 + p1) - (m1 + p2)) * R(1.0 / 12.0);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_lad_sweep(const Prob* __restrict__ probs, StateRef ref, RKRef rr, int mode,
+                                                   int stage, double a, double b, int skip_if_any, int zc) {
+  const Prob& P = probs[blockIdx.y];
+  if (lad_skip(P, skip_if_any)) return;
+  ZCol c;
+  if (!zm_column(P, 0, 0, zc, c)) return;
+  const size_t T = P.total;
+  const int sz = P.s[2];
+  const bool z3 = P.ndim == 3;
+  const R* Fx = static_cast<const R*>(P.FL[0]);
+  const R* Fy = P.ndim > 1 ? static_cast<const R*>(P.FL[1]) : nullptr;
+  const R* Fz = z3 ? static_cast<const R*>(P.FL[2]) : nullptr;
+  double* dQ = ref.deriv(P);
+  const double* Un = rr.Un ? rr.Un : P.Q;
+  const double* Us = rr.Us ? rr.Us : (stage == 0 ? Un : P.Us);
+  double* out = rr.out ? rr.out : (stage == 2 ? const_cast<double*>(Un) : P.Us);
+  const double dt = mode ? *P.dt : 0.0;
+  int bad = 0;
+  int idx = pos_to_idx(P, c.i, c.j, c.k0);
+  ZQ5<R, 5> qz;
+  if (z3) qz.prime(Fz, T, idx, sz);
+  for (int k = c.k0; k < c.k1; ++k, idx += sz) {
+    if (z3) qz.step(Fz, T, idx, sz);
+    const double J = P.curvilinear ? P.M64[9 * T + idx] : P.cm[9];
+    double Lq[5];
+    for (int q = 0; q < 5; ++q) {
+      const R* f = Fx + q * T + idx;
+      R fp = i4v(f[-1], f[0], f[1], f[2]), fm = i4v(f[-2], f[-1], f[0], f[1]);
+      Lq[q] = -J * ((double)fp - (double)fm);
+    }
+    if (P.ndim > 1) {
+      const int s = P.s[1];
+      for (int q = 0; q < 5; ++q) {
+        const R* f = Fy + q * T + idx;
+        R fp = i4v(f[-s], f[0], f[s], f[2 * s]), fm = i4v(f[-2 * s], f[-s], f[0], f[s]);
+        Lq[q] = Lq[q] + -J * ((double)fp - (double)fm);
+      }
+    }
+    if (z3) {
+      for (int q = 0; q < 5; ++q) {
+        R fp = i4v(qz.v[1][q], qz.v[2][q], qz.v[3][q], qz.v[4][q]);
+        R fm = i4v(qz.v[0][q], qz.v[1][q], qz.v[2][q], qz.v[3][q]);
+        Lq[q] = Lq[q] + -J * ((double)fp - (double)fm);
+      }
+    }
+    if (mode == 0) {
+      for (int q = 0; q < 5; ++q) dQ[q * T + idx] = Lq[q];
+    } else {
+      double v[5];
+      for (int q = 0; q < 5; ++q) {
+        const size_t o = q * T + idx;
+        v[q] = a * Un[o] + b * (Us[o] + dt * Lq[q]);
+        out[o] = v[q];
+      }
+      const double rho = v[0];
+      const double ke = 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / rho;
+      const double pr = (P.gamma - 1.0) * (v[4] - ke);
+      const bool ok = rho > 0.0 && pr > 0.0 && isfinite(rho) && isfinite(pr) && isfinite(v[1]) &&
+                      isfinite(v[2]) && isfinite(v[3]);
+      if (!ok) ++bad;
+    }
+  }
+  if (bad) atomicAdd(P.status, bad);
+}
+
+// ghost nodes of the stage result = U^n (what the combination kernel does off the interior)
+__global__ void __launch_bounds__(256) k_stage_ghosts(const Prob* __restrict__ probs, RKRef rr, int stage,
+                                                      int skip_if_any) {
+  const Prob& P = probs[blockIdx.y];
+  if (lad_skip(P, skip_if_any)) return;
+  const double* Un = rr.Un ? rr.Un : P.Q;
+  double* out = rr.out ? rr.out : (stage == 2 ? const_cast<double*>(Un) : P.Us);
+  if (out == Un) return;
+  const size_t T = P.total;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < P.total; idx += gridDim.x * blockDim.x) {
+    if (is_interior(P, idx)) continue;
+    for (int q = 0; q < 5; ++q) out[q * T + idx] = Un[q * T + idx];
   }
 }
 
@@ -274,50 +558,73 @@ __global__ void __launch_bounds__(256) k_gbr_viscflux(const Prob* __restrict__ p
     for (int l = 0; l < 3; ++l)
       for (int q = 0; q < 5; ++q) gl[l][q] = l < P.ndim ? static_cast<const R*>(P.G[l])[q * T + idx] : R(0);
     to_physical(P, idx, gl, D);
+    const R ri = rcp(w[0]);
     R mu, kappa;
-    transport(P, w[0], w[4], mu, kappa);
+    transport(P, ri, w[4], mu, kappa);
     for (int l = 0; l < P.ndim; ++l) {
       R F[5];
-      viscous_flux(P, idx, l, w, D, mu, R(0), kappa, F);
+      viscous_flux(P, idx, l, w, ri, D, mu, R(0), kappa, F);
       R* out = static_cast<R*>(P.FV[l]);
       for (int q = 0; q < 5; ++q) out[q * T + idx] = F[q];
     }
   }
 }
 
-static inline dim3 g1(long long work, int nprob) {
+static inline dim3 g1(long long work, int nprob, long long cap = 1LL << 30) {
   long long b = (work + 255) / 256;
-  if (b > 8192) b = 8192;
+  if (b > cap) b = cap;
   if (b < 1) b = 1;
   return dim3((unsigned)b, nprob);
 }
 
 template <typename R>
 void launch_lad(const Launch& L, int skip_if_any) {
-  LG_TIMED(L, KC_LAD_NODE, hipLaunchKernelGGL(k_lad_grad<R>, g1(L.max_total, L.nprob), dim3(256), 0, L.stream,
-                                              L.probs, skip_if_any));
-  LG_TIMED(L, KC_LAD_RAW, hipLaunchKernelGGL(k_lad_raw<R>, g1(L.max_total, L.nprob), dim3(256), 0, L.stream,
-                                             L.probs, skip_if_any));
-  for (int d = 0; d < L.ndim; ++d) launch_bc_scalar<R>(L, 0, 3, d);
-  int src = 0;
-  for (int d = 0; d < L.ndim; ++d) {
-    LG_TIMED(L, KC_GAUSS, hipLaunchKernelGGL(k_gauss<R>, g1(L.max_total, L.nprob), dim3(256), 0, L.stream,
-                                             L.probs, d, src, skip_if_any));
-    src ^= 1;
-    for (int e = 0; e < L.ndim; ++e) launch_bc_scalar<R>(L, src, 3, e);
+  const int zb = zm_chunk(L, -2, 2), zi = zm_chunk(L, 0, 0);
+  LG_TIMED(L, KC_LAD_NODE, hipLaunchKernelGGL(k_lad_shear<R>, zm_grid(L, -2, 2, ZM_TX, ZM_TY), dim3(256), 0,
+                                              L.stream, L.probs, skip_if_any, zb));
+  LG_TIMED(L, KC_LAD_RAW, hipLaunchKernelGGL(k_lad_raw<R>, zm_grid(L, 0, 0, ZM_TX, ZM_TY), dim3(256), 0, L.stream,
+                                             L.probs, skip_if_any, zi));
+  constexpr int GTY = sizeof(R) == 4 ? 16 : 8;
+  LG_TIMED(L, KC_GAUSS, hipLaunchKernelGGL((k_gauss_xy<R, GTY>), zm_grid(L, 0, 0, 64, GTY), dim3(256), 0, L.stream,
+                                           L.probs, skip_if_any, zi));
+  int coef = 1;
+  if (L.ndim > 2) {
+    LG_TIMED(L, KC_GAUSS, hipLaunchKernelGGL(k_gauss_z<R>, zm_grid(L, 0, 0, ZM_TX, ZM_TY), dim3(256), 0, L.stream,
+                                             L.probs, skip_if_any, zi));
+    coef = 0;
   }
-  LG_TIMED(L, KC_LAD_FLUX, hipLaunchKernelGGL(k_lad_nodeflux<R>, g1(L.max_total, L.nprob), dim3(256), 0,
-                                              L.stream, L.probs, src, skip_if_any));
+  LG_TIMED(L, KC_LAD_FLUX, hipLaunchKernelGGL(k_lad_nodeflux<R>, zm_grid(L, -2, 2, ZM_TX, ZM_TY), dim3(256), 0,
+                                              L.stream, L.probs, coef, skip_if_any, zb));
+}
+
+template <typename R>
+void launch_lad_geometry(const Launch& L) {
+  hipLaunchKernelGGL(k_lad_dx<R>, g1(L.max_total, L.nprob), dim3(256), 0, L.stream, L.probs);
+}
+
+template <typename R>
+void launch_lad_sweep(const Launch& L, StateRef ref, const RKRef* rr, int stage, double a, double b, int skip_if_any) {
+  RKRef r = rr ? *rr : RKRef{nullptr, nullptr, nullptr};
+  LG_TIMED(L, KC_LAD_SWEEP, hipLaunchKernelGGL(k_lad_sweep<R>, zm_grid(L, 0, 0, ZM_TX, ZM_TY), dim3(256), 0,
+                                               L.stream, L.probs, ref, r, rr ? 1 : 0, stage, a, b, skip_if_any,
+                                               zm_chunk(L, 0, 0)));
+  if (rr)
+    LG_TIMED(L, KC_COMBINE, hipLaunchKernelGGL(k_stage_ghosts, g1(L.max_total, L.nprob), dim3(256), 0, L.stream,
+                                               L.probs, r, stage, skip_if_any));
 }
 
 template <typename R>
 void launch_gbr_viscflux(const Launch& L, int skip_if_any, int region) {
-  LG_TIMED(L, KC_VISC, hipLaunchKernelGGL(k_gbr_viscflux<R>, g1(L.max_total, L.nprob), dim3(256), 0, L.stream,
+  LG_TIMED(L, KC_VISC, hipLaunchKernelGGL(k_gbr_viscflux<R>, g1(L.max_total, L.nprob, 16384), dim3(256), 0, L.stream,
                                           L.probs, skip_if_any, region));
 }
 
 template void launch_lad<float>(const Launch&, int);
 template void launch_lad<double>(const Launch&, int);
+template void launch_lad_geometry<float>(const Launch&);
+template void launch_lad_geometry<double>(const Launch&);
+template void launch_lad_sweep<float>(const Launch&, StateRef, const RKRef*, int, double, double, int);
+template void launch_lad_sweep<double>(const Launch&, StateRef, const RKRef*, int, double, double, int);
 template void launch_gbr_viscflux<float>(const Launch&, int, int);
 template void launch_gbr_viscflux<double>(const Launch&, int, int);
 

@@ -255,7 +255,7 @@ template <typename R>
 __host__ __device__ __forceinline__ void i4_flux(const R* Fn, size_t T, int idx, int s, R F[5]) {
   for (int q = 0; q < 5; ++q) {
     const R* f = Fn + q * T + idx;
-    F[q] = (R(7) * (f[0] + f[s]) - (f[-s] + f[2 * s])) / R(12);
+    F[q] = (R(7) * (f[0] + f[s]) - (f[-s] + f[2 * s])) * R(1.0 / 12.0);
   }
 }
 
@@ -288,8 +288,10 @@ __device__ __forceinline__ double node_J(const Prob& P, int idx) {
 // row segment of 63 nodes; lane t computes the interface left of node (seg*63 + t - 1) + 1
 // and the flux difference uses the neighbour lane's flux.
 template <typename R>
-__global__ void __launch_bounds__(256) k_sweep_x(const Prob* __restrict__ probs, StateRef ref, int sel, int accumulate) {
+__global__ void __launch_bounds__(256) k_sweep_x(const Prob* __restrict__ probs, StateRef ref, int sel, int accumulate,
+                                                 int skip_if_any) {
   const Prob& P = probs[blockIdx.y];
+  if (gate_skip(P, skip_if_any)) return;
   const int lane = threadIdx.x & 63;
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int n0 = P.n[0];
@@ -321,9 +323,9 @@ __global__ void __launch_bounds__(256) k_sweep_x(const Prob* __restrict__ probs,
 // lane per line segment of `seg` nodes, sliding along the line.
 template <typename R>
 __global__ void __launch_bounds__(256) k_sweep_s(const Prob* __restrict__ probs, StateRef ref, int d, int sel,
-                                                 int accumulate, int seg) {
+                                                 int accumulate, int seg, int skip_if_any) {
   const Prob& P = probs[blockIdx.y];
-  if (d >= P.ndim) return;
+  if (d >= P.ndim || gate_skip(P, skip_if_any)) return;
   const int o2 = d == 1 ? 2 : 1;
   const int na = P.n[0], nb = P.n[o2], nd = P.n[d];
   const int nch = (nd + seg - 1) / seg;
@@ -381,14 +383,14 @@ int sweep_seg(const Launch& L, int d) {
 }
 
 template <typename R>
-void launch_sweep(const Launch& L, StateRef ref, int d, int sel, int accumulate) {
+void launch_sweep(const Launch& L, StateRef ref, int d, int sel, int accumulate, int skip_if_any) {
   if (d == 0) {
     long long nseg = (L.max_n[0] + 62) / 63;
     long long waves = nseg * L.sweep_rows[0];
     long long blocks = (waves + 3) / 4;
     if (blocks < 1) blocks = 1;
     LG_TIMED(L, KC_SWEEP_X, hipLaunchKernelGGL(k_sweep_x<R>, dim3((unsigned)blocks, L.nprob), dim3(256), 0,
-                                               L.stream, L.probs, ref, sel, accumulate));
+                                               L.stream, L.probs, ref, sel, accumulate, skip_if_any));
   } else {
     const int seg = sweep_seg(L, d);
     long long nch = (L.max_n[d] + seg - 1) / seg;
@@ -397,13 +399,13 @@ void launch_sweep(const Launch& L, StateRef ref, int d, int sel, int accumulate)
     if (blocks < 1) blocks = 1;
     LG_TIMED(L, d == 1 ? KC_SWEEP_Y : KC_SWEEP_Z,
              hipLaunchKernelGGL(k_sweep_s<R>, dim3((unsigned)blocks, L.nprob), dim3(256), 0, L.stream, L.probs, ref,
-                                d, sel, accumulate, seg));
+                                d, sel, accumulate, seg, skip_if_any));
   }
 }
 
 template void launch_sensor<float>(const Launch&, int, int);
 template void launch_sensor<double>(const Launch&, int, int);
-template void launch_sweep<float>(const Launch&, StateRef, int, int, int);
-template void launch_sweep<double>(const Launch&, StateRef, int, int, int);
+template void launch_sweep<float>(const Launch&, StateRef, int, int, int, int);
+template void launch_sweep<double>(const Launch&, StateRef, int, int, int, int);
 
 }  // namespace lg

@@ -87,8 +87,12 @@ namespace {
 const double RK_A[3] = {0.0, 0.75, 1.0 / 3.0};
 const double RK_B[3] = {1.0, 0.25, 2.0 / 3.0};
 
+// One right-hand side evaluation of the state `ref`.  With rk set, the RK stage
+// combination follows: inside the all-LAD interface pass where that pass runs, as its own
+// kernel after the per-direction sweeps otherwise.
 template <typename R>
-void enqueue_rhs(const Launch& L, const Cfg& c, int scheme, StateRef ref, const uint8_t* force) {
+void enqueue_rhs(const Launch& L, const Cfg& c, int scheme, StateRef ref, const uint8_t* force,
+                 const RKRef* rk = nullptr, int stage = 0) {
   for (int d = 0; d < c.ndim; ++d) lg::launch_bc_cons(L, ref, d);
   const bool hyb = scheme == LG_SCHEME_HYBRID;
   lg::launch_prim<R>(L, ref, hyb ? 1 : 0, force);
@@ -127,7 +131,17 @@ void enqueue_rhs(const Launch& L, const Cfg& c, int scheme, StateRef ref, const 
     if (c.viscous) lg::launch_gbr_viscflux<R>(L, skip_gbr, region);
   }
   if (sel != lg::SEL_GBR) lg::launch_lad<R>(L, skip_lad);
-  for (int d = 0; d < c.ndim; ++d) lg::launch_sweep<R>(L, ref, d, sel, d > 0 ? 1 : 0);
+  // interfaces: the all-LAD pass (LAD scheme; hybrid with no troubled node), else the
+  // per-direction sweeps that pick C-GBR or LAD per interface; the hybrid decides on the
+  // device, so both are launched and each returns at once when the other applies
+  const double a = rk ? RK_A[stage] : 0.0, b = rk ? RK_B[stage] : 0.0;
+  const int skip_fused = sel == lg::SEL_LAD ? -1 : 1;
+  const int skip_dir = sel == lg::SEL_GBR ? -1 : 0;
+  if (sel != lg::SEL_GBR) lg::launch_lad_sweep<R>(L, ref, rk, stage, a, b, skip_fused);
+  if (sel != lg::SEL_LAD) {
+    for (int d = 0; d < c.ndim; ++d) lg::launch_sweep<R>(L, ref, d, sel, d > 0 ? 1 : 0, skip_dir);
+    if (rk) lg::launch_combine(L, *rk, stage, a, b, skip_dir);
+  }
 }
 
 template <typename R>
@@ -135,9 +149,8 @@ void enqueue_rk3(const Launch& L, const Cfg& c, int scheme, double* Qx, double* 
   lg::launch_dt(L, Qx, tx, t_end, 1);
   for (int s = 0; s < 3; ++s) {
     StateRef ref{s == 0 ? Qx : nullptr, nullptr, s == 0 ? 0 : 1};
-    enqueue_rhs<R>(L, c, scheme, ref, nullptr);
     RKRef rr{Qx, nullptr, nullptr};
-    lg::launch_combine(L, rr, s, RK_A[s], RK_B[s]);
+    enqueue_rhs<R>(L, c, scheme, ref, nullptr, &rr, s);
   }
 }
 
@@ -371,8 +384,8 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
     int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
     P.llist[d] = static_cast<int*>(A(sizeof(int) * (size_t)P.N[o1] * P.N[o2]));
   }
-  P.S3 = A(3 * T * rs);
-  P.D4 = A(15 * T * rs);
+  P.S3 = A(2 * T * rs);
+  if (G.curvilinear) P.GX = A(9 * T * rs);
   P.CA = A(3 * T * rs);
   P.CB = A(3 * T * rs);
   for (int d = 0; d < G.ndim; ++d) P.FL[d] = A(5 * T * rs);
@@ -452,6 +465,12 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
   c->L.ndim = G.ndim;
   c->L.seg = opts->seg;
   fill_launch(c->L, P);
+  if (G.curvilinear) {
+    if (dispatch(opts->precision, [&](auto r) { lg::launch_lad_geometry<decltype(r)>(c->L); }) != LG_OK) {
+      lg_destroy(c);
+      return LG_EHIP;
+    }
+  }
   if (hipStreamSynchronize(c->stream) != hipSuccess) {
     lg_destroy(c);
     return LG_EHIP;
@@ -576,8 +595,8 @@ lg_status lg_rk3_stage(lg_ctx* c, int scheme, int stage, const double* Un, doubl
   return dispatch(c->cfg.precision, [&](auto r) {
     using R = decltype(r);
     lg::launch_set_dt(c->L, dt);
-    enqueue_rhs<R>(c->L, c->cfg, scheme, StateRef{Us, nullptr, 0}, nullptr);
-    lg::launch_combine(c->L, RKRef{Un, Us, Us}, stage, RK_A[stage], RK_B[stage]);
+    RKRef rr{Un, Us, Us};
+    enqueue_rhs<R>(c->L, c->cfg, scheme, StateRef{Us, nullptr, 0}, nullptr, &rr, stage);
   });
 }
 
@@ -590,19 +609,21 @@ lg_status lg_compute_dt(lg_ctx* c, const double* Q, double* dt_out) {
   return LG_OK;
 }
 
-lg_status lg_set_tuning(lg_ctx* c, int seg, int pcr_blocks) {
+lg_status lg_set_tuning(lg_ctx* c, int seg, int pcr_blocks, int zc) {
   if (!c || seg < 0 || (seg > 0 && (seg < 2 || seg > 64)) || pcr_blocks < 0 ||
-      (pcr_blocks > 0 && (pcr_blocks < 256 || pcr_blocks > 65536)))
+      (pcr_blocks > 0 && (pcr_blocks < 256 || pcr_blocks > 65536)) || zc < 0 || zc > 1024)
     return LG_EINVAL;
   c->L.seg = seg;
   c->L.pcr_blocks = pcr_blocks;
+  c->L.zc = zc;
   return LG_OK;
 }
 
-lg_status lg_get_tuning(const lg_ctx* c, int* seg, int* pcr_blocks) {
-  if (!c || !seg || !pcr_blocks) return LG_EINVAL;
+lg_status lg_get_tuning(const lg_ctx* c, int* seg, int* pcr_blocks, int* zc) {
+  if (!c || !seg || !pcr_blocks || !zc) return LG_EINVAL;
   *seg = lg::sweep_seg(c->L, c->cfg.ndim > 1 ? 1 : 0);
   *pcr_blocks = c->L.pcr_blocks > 0 ? c->L.pcr_blocks : 16384;
+  *zc = lg::zm_chunk(c->L, 0, 0);
   return LG_OK;
 }
 
@@ -643,6 +664,7 @@ lg_status lg_batch_create(lg_batch** out, lg_ctx* const* ctxs, double* const* Q,
   b->L.ndim = c0.ndim;
   b->L.seg = ctxs[0]->L.seg;
   b->L.pcr_blocks = ctxs[0]->L.pcr_blocks;
+  b->L.zc = ctxs[0]->L.zc;
   for (int i = 0; i < n; ++i) {
     Prob P = ctxs[i]->hp;
     P.Q = Q[i];

@@ -51,8 +51,8 @@ struct Prob {
   uint8_t* fg;       // nodes whose C-GBR inputs are needed (per-cell hybrid) [total]
   int* llist[3];     // compacted lines of each direction that touch fg
   int* lcount;       // [3] number of listed lines
-  void* S3;          // |S|, theta, e                    [3][total]  R
-  void* D4;          // E4 physical gradients d(rho,u,v,w,p)/dx_j [15][total] R (q*3 + j)
+  void* S3;          // |S|, theta (LAD)                 [2][total]  R
+  void* GX;          // Delta x_l = (x_{+1} - x_{-1}) / 2 [3 l + c][total] R (curvilinear only)
   void* CA;          // LAD coefficients mu*,beta*,kappa* [3][total] R (result)
   void* CB;          // LAD filter scratch               [3][total]  R
   void* FL[3];       // LAD node fluxes per direction    [5][total]  R
@@ -85,6 +85,96 @@ __host__ __device__ __forceinline__ R met(const Prob& P, int c, int idx) {
 __host__ __device__ __forceinline__ double met64(const Prob& P, int c, int idx) {
   if (P.curvilinear) return P.M64[(size_t)c * P.total + idx];
   return P.cm[c];
+}
+
+// Device-side switch of the hybrid (any_flag = some troubled node): skip = -1 never skips,
+// 1 skips when a troubled node exists, 0 skips when none does.
+__device__ __forceinline__ bool gate_skip(const Prob& P, int skip) {
+  return skip >= 0 && (*P.any_flag != 0) == (skip != 0);
+}
+
+// Ghost image of position p along d for scalar intermediate fields (even parity; FIXED
+// faces behave as transmissive): the interior position whose value the ghost holds.
+__device__ __forceinline__ int scalar_image(const Prob& P, int d, int p) {
+  const int g = P.g[d], n = P.n[d];
+  if (p >= g && p < g + n) return p;
+  const int side = p < g ? 0 : 1;
+  int bct = P.bc[d][side];
+  if (bct == BC_PERIODIC) {
+    int r = (p - g) % n;
+    return g + (r < 0 ? r + n : r);
+  }
+  if (bct == BC_TRANSMISSIVE || bct == BC_FIXED) return side == 0 ? g : g + n - 1;
+  // mirror; within the ghost depth (n >= 5) the image is interior, the clamp only keeps
+  // positions farther out in bounds
+  const int m = side == 0 ? 2 * g - 1 - p : 2 * (g + n) - 1 - p;
+  return m < g ? g : (m > g + n - 1 ? g + n - 1 : m);
+}
+
+// ------------------------------------------------------------------ z-marching tiles
+// A z-marching launch covers the band [g + lo, g + n + hi) of every active direction
+// (node 0 of inactive ones) with tiles of TX x TY columns (i, j); a workgroup walks its
+// columns through one chunk of zc planes, so values along z are reused from registers.
+// Hardware workgroups are dealt round-robin to the eight XCDs (workgroup b runs on XCD
+// b mod 8, gridDim.x is a multiple of 8): the logical order hands each XCD one
+// contiguous range of tiles -- whole z-chunks -- so that neighbouring rows meet in the
+// same L2.  The decode is uniform over the workgroup.
+__device__ __forceinline__ void zm_band(const Prob& P, int lo, int hi, int org[3], int ext[3]) {
+  for (int d = 0; d < 3; ++d) {
+    const bool a = d < P.ndim;
+    org[d] = a ? P.g[d] + lo : 0;
+    ext[d] = a ? P.n[d] + hi - lo : 1;
+  }
+}
+
+template <int TX, int TY>
+__device__ __forceinline__ bool zm_tile(const int ext[3], int zc, int& ti0, int& tj0, int& k0, int& k1) {
+  const int ntx = (ext[0] + TX - 1) / TX, nty = (ext[1] + TY - 1) / TY, nch = (ext[2] + zc - 1) / zc;
+  const int nblk = ntx * nty * nch;
+  const int per = (nblk + 7) >> 3;
+  if ((int)(blockIdx.x >> 3) >= per) return false;
+  const int L = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (L >= nblk) return false;
+  const int t = L % (ntx * nty), ch = L / (ntx * nty);
+  ti0 = (t % ntx) * TX;
+  tj0 = (t / ntx) * TY;
+  k0 = ch * zc;
+  k1 = min(ext[2], k0 + zc);
+  return true;
+}
+
+constexpr int ZM_TX = 64, ZM_TY = 4;
+
+struct ZCol {
+  int i, j, k0, k1;  // padded positions of the column; planes [k0, k1)
+};
+
+// This thread's column of a 64 x 4 z-marching launch; false if it has none.
+__device__ __forceinline__ bool zm_column(const Prob& P, int lo, int hi, int zc, ZCol& c) {
+  int org[3], ext[3];
+  zm_band(P, lo, hi, org, ext);
+  int ti0, tj0, k0, k1;
+  if (!zm_tile<ZM_TX, ZM_TY>(ext, zc, ti0, tj0, k0, k1)) return false;
+  const int ti = ti0 + (int)(threadIdx.x % ZM_TX), tj = tj0 + (int)(threadIdx.x / ZM_TX);
+  if (ti >= ext[0] || tj >= ext[1]) return false;
+  c.i = org[0] + ti;
+  c.j = org[1] + tj;
+  c.k0 = org[2] + k0;
+  c.k1 = org[2] + k1;
+  return true;
+}
+
+// Reciprocal in the bulk arithmetic: the hardware estimate (within 1 ulp) in FP32, the
+// correctly rounded quotient in FP64.
+template <typename R>
+__device__ __forceinline__ R rcp(R x);
+template <>
+__device__ __forceinline__ float rcp<float>(float x) {
+  return __builtin_amdgcn_rcpf(x);
+}
+template <>
+__device__ __forceinline__ double rcp<double>(double x) {
+  return 1.0 / x;
 }
 
 template <typename R>

@@ -26,7 +26,8 @@ struct RKRef {
 // Kernel classes for the optional per-launch event timing (lg_prof_start / lg_prof_stop).
 enum KClass {
   KC_BC = 0, KC_PRIM, KC_FLAGS, KC_GRAD_E6, KC_GRAD_C4, KC_SENSOR, KC_VISC, KC_LAD_NODE, KC_LAD_RAW,
-  KC_GAUSS, KC_LAD_FLUX, KC_SWEEP_X, KC_SWEEP_Y, KC_SWEEP_Z, KC_COMBINE, KC_DT, KC_BC_SCALAR, KC_COUNT
+  KC_GAUSS, KC_LAD_FLUX, KC_SWEEP_X, KC_SWEEP_Y, KC_SWEEP_Z, KC_COMBINE, KC_DT, KC_BC_SCALAR, KC_LAD_SWEEP,
+  KC_COUNT
 };
 
 // Event pairs recorded around launches while enabled (never during graph capture).
@@ -59,6 +60,7 @@ struct Launch {
   int ndim;
   int seg;                 // nodes per thread in the strided sweeps (0: heuristic)
   int pcr_blocks;          // persistent workgroups of the PCR line solves (0: heuristic)
+  int zc;                  // planes per chunk of the z-marching kernels (0: heuristic)
   Prof* prof;              // optional launch timing (null: off)
 };
 
@@ -93,7 +95,7 @@ template <typename R> void launch_prim(const Launch& L, StateRef ref, int want_f
 void launch_any_flag(const Launch& L, int interior_only);
 void launch_dilate(const Launch& L, int ndim, int radius, int first_src, int final_buf);
 void launch_line_lists(const Launch& L, int ndim);
-void launch_combine(const Launch& L, RKRef rr, int stage, double a, double b);
+void launch_combine(const Launch& L, RKRef rr, int stage, double a, double b, int skip_if_any);
 void launch_dt(const Launch& L, const double* Qx, double* tx, double t_end, int advance_t);
 void launch_set_dt(const Launch& L, double dt);
 void launch_zero_status(const Launch& L);
@@ -103,15 +105,35 @@ template <typename R> void launch_convert(const double* src, R* dst, size_t n, h
 
 int sweep_seg(const Launch& L, int d);   // segment length in effect for direction d
 
+// z-marching launches (see zm_tile): planes per chunk and grid over the band [lo, hi)
+inline int zm_chunk(const Launch& L, int lo, int hi) {
+  if (L.zc > 0) return L.zc;
+  long long e2 = L.ndim > 2 ? L.max_n[2] + hi - lo : 1;
+  long long c = (e2 + 7) / 8;
+  return (int)(c < 8 ? 8 : c);
+}
+inline dim3 zm_grid(const Launch& L, int lo, int hi, int TX, int TY) {
+  long long e[3];
+  for (int d = 0; d < 3; ++d) e[d] = d < L.ndim ? L.max_n[d] + hi - lo : 1;
+  const int zc = zm_chunk(L, lo, hi);
+  long long nblk = ((e[0] + TX - 1) / TX) * ((e[1] + TY - 1) / TY) * ((e[2] + zc - 1) / zc);
+  return dim3((unsigned)(8 * ((nblk + 7) / 8)), L.nprob);
+}
+
 // gradients (region = 1: only where the per-cell hybrid needs C-GBR inputs)
 template <typename R> void launch_grad_explicit(const Launch& L, int d, int order, int skip_if_any, int region);
 template <typename R> void launch_grad_c4(const Launch& L, StateRef ref, int d, int skip_if_any, int region);
 // sensor and C-GBR viscous node fluxes
 template <typename R> void launch_sensor(const Launch& L, int skip_if_any, int region);
 template <typename R> void launch_gbr_viscflux(const Launch& L, int skip_if_any, int region);
-// LAD
+// LAD: coefficients and node fluxes; the grid factors Delta x_l once per context
 template <typename R> void launch_lad(const Launch& L, int skip_if_any);
+template <typename R> void launch_lad_geometry(const Launch& L);
+// all-LAD interfaces of every direction in one pass; rr == nullptr writes the time
+// derivative, else the RK stage combination (and the ghost copy of the stage result)
+template <typename R>
+void launch_lad_sweep(const Launch& L, StateRef ref, const RKRef* rr, int stage, double a, double b, int skip_if_any);
 // interface sweeps
-template <typename R> void launch_sweep(const Launch& L, StateRef ref, int d, int sel, int accumulate);
+template <typename R> void launch_sweep(const Launch& L, StateRef ref, int d, int sel, int accumulate, int skip_if_any);
 
 }  // namespace lg

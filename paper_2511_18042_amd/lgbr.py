@@ -23,7 +23,7 @@ EXPORTS = ('lg_set_allocator', 'lg_strerror', 'lg_create', 'lg_destroy', 'lg_wor
            'lg_compute_dt', 'lg_batch_create', 'lg_batch_run', 'lg_batch_destroy', 'lg_poll_status',
            'lg_prof_start', 'lg_prof_stop', 'lg_set_tuning', 'lg_get_tuning')
 KERNEL_CLASSES = ('bc', 'prim', 'flags', 'grad_e6', 'grad_c4', 'sensor', 'visc', 'lad_node', 'lad_raw', 'gauss',
-                  'lad_flux', 'sweep_x', 'sweep_y', 'sweep_z', 'combine', 'dt', 'bc_scalar')
+                  'lad_flux', 'sweep_x', 'sweep_y', 'sweep_z', 'combine', 'dt', 'bc_scalar', 'lad_sweep')
 
 
 class LgGrid(ctypes.Structure):
@@ -76,8 +76,8 @@ def load():
         'lg_poll_status': (I, [P, ctypes.POINTER(I)]),
         'lg_prof_start': (I, [P, I, I]),
         'lg_prof_stop': (I, [P, ctypes.POINTER(D), ctypes.POINTER(I)]),
-        'lg_set_tuning': (I, [P, I, I]),
-        'lg_get_tuning': (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
+        'lg_set_tuning': (I, [P, I, I, I]),
+        'lg_get_tuning': (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -208,13 +208,14 @@ class Context:
         _check(self._lib.lg_prof_stop(self.handle, ms, cnt), 'lg_prof_stop')
         return {KERNEL_CLASSES[k]: (ms[k], cnt[k]) for k in range(n) if cnt[k]}
 
-    def set_tuning(self, seg=0, pcr_blocks=0):
-        _check(self._lib.lg_set_tuning(self.handle, int(seg), int(pcr_blocks)), 'lg_set_tuning')
+    def set_tuning(self, seg=0, pcr_blocks=0, zc=0):
+        _check(self._lib.lg_set_tuning(self.handle, int(seg), int(pcr_blocks), int(zc)), 'lg_set_tuning')
 
     def get_tuning(self):
-        a, b = ctypes.c_int(0), ctypes.c_int(0)
-        _check(self._lib.lg_get_tuning(self.handle, ctypes.byref(a), ctypes.byref(b)), 'lg_get_tuning')
-        return a.value, b.value
+        a, b, z = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+        _check(self._lib.lg_get_tuning(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(z)),
+               'lg_get_tuning')
+        return a.value, b.value, z.value
 
     def poll_status(self):
         n = ctypes.c_int(0)

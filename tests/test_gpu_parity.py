@@ -313,18 +313,21 @@ def test_launch_tuning_leaves_results_bitwise_unchanged(tmp_path, monkeypatch):
     flags = np.random.default_rng(10).random(g.shape) < 0.1
     ctx, _ = U.gpu_context(c, gas, opts)
     outs = []
-    for seg, pcr in ((0, 0), (2, 256), (7, 1000), (64, 65536)):
-        print('tuning', seg, pcr, flush=True)
-        ctx.set_tuning(seg, pcr)
-        s, p = ctx.get_tuning()
-        assert (seg == 0 or s == seg) and p == (pcr or 16384)
-        outs.append(U.gpu_rhs(ctx, c, 'hybrid', flags=flags))
-    for o in outs[1:]:
-        assert np.array_equal(o, outs[0])
+    for seg, pcr, zc in ((0, 0, 0), (2, 256, 1), (7, 1000, 5), (64, 65536, 1024)):
+        print('tuning', seg, pcr, zc, flush=True)
+        ctx.set_tuning(seg, pcr, zc)
+        s, p, z = ctx.get_tuning()
+        assert (seg == 0 or s == seg) and p == (pcr or 16384) and (zc == 0 or z == zc)
+        for scheme, fl in (('hybrid', flags), ('lad', None)):
+            outs.append(U.gpu_rhs(ctx, c, scheme, flags=fl))
+    for i, o in enumerate(outs[2:]):
+        assert np.array_equal(o, outs[i % 2])
     monkeypatch.setenv('LGBR_TUNE_CACHE', str(tmp_path / 'tune.json'))
     Q0 = U.dev(c.Q)
-    (seg, pcr), timings = autotune.tune(ctx, Q0, 'hybrid', steps=1)
-    assert seg in autotune.CANDIDATE_SEG and pcr in autotune.CANDIDATE_PCR and len(timings) == 15
-    assert autotune.tune(ctx, Q0, 'hybrid')[0] == (seg, pcr)          # served from the cache
+    best, timings = autotune.tune(ctx, Q0, 'hybrid', steps=1)
+    zc, seg, pcr = best
+    assert zc in autotune.CANDIDATE_ZC and seg in autotune.CANDIDATE_SEG and pcr in autotune.CANDIDATE_PCR
+    assert len(timings) >= len(autotune.CANDIDATE_ZC)
+    assert autotune.tune(ctx, Q0, 'hybrid')[0] == best          # served from the cache
     ctx.close()
     torch.cuda.synchronize()
