@@ -35,13 +35,13 @@ __device__ __forceinline__ R e4_at(const R* f, int idx, int s) {
 // physical gradients D[q][j] of the 5 primitives at node idx from computational
 // derivatives gl[l][q] (l < ndim)
 template <typename R>
-__device__ __forceinline__ void to_physical(const Prob& P, int idx, const R gl[3][5], R D[5][3]) {
-  R J = met<R>(P, 9, idx);
+__device__ __forceinline__ void to_physical(int ndim, const R mt[10], const R gl[3][5], R D[5][3]) {
+  R J = mt[9];
   for (int q = 0; q < 5; ++q)
     for (int j = 0; j < 3; ++j) D[q][j] = R(0);
-  for (int l = 0; l < P.ndim; ++l)
+  for (int l = 0; l < ndim; ++l)
     for (int j = 0; j < 3; ++j) {
-      R m = J * met<R>(P, 3 * l + j, idx);
+      R m = J * mt[3 * l + j];
       for (int q = 0; q < 5; ++q) D[q][j] += m * gl[l][q];
     }
 }
@@ -60,9 +60,9 @@ __device__ __forceinline__ void transport(const Prob& P, R ri, R p, R& mu, R& ka
   kappa = mu * R(1.0 / ((P.gamma - 1.0) * P.Pr * P.Mref * P.Mref));
 }
 
-// -l_hat . [0, tau, phi] at node idx (Eq. tauij); ri = 1 / rho
+// -l_hat . [0, tau, phi] with l_hat = (m0, m1, m2) (Eq. tauij); ri = 1 / rho
 template <typename R>
-__device__ __forceinline__ void viscous_flux(const Prob& P, int idx, int l, const R w[5], R ri, const R D[5][3],
+__device__ __forceinline__ void viscous_flux(const Prob& P, R m0, R m1, R m2, const R w[5], R ri, const R D[5][3],
                                              R mu, R beta, R kappa, R F[5]) {
   R du[3][3];
   for (int i = 0; i < 3; ++i)
@@ -81,7 +81,6 @@ __device__ __forceinline__ void viscous_flux(const Prob& P, int idx, int l, cons
     R dT = g2 * (D[4][i] * ri - p * D[0][i] * (ri * ri));
     phi[i] = w[1] * tau[i][0] + w[2] * tau[i][1] + w[3] * tau[i][2] + kappa * dT;
   }
-  R m0 = met<R>(P, 3 * l, idx), m1 = met<R>(P, 3 * l + 1, idx), m2 = met<R>(P, 3 * l + 2, idx);
   F[0] = R(0);
   for (int i = 0; i < 3; ++i) F[1 + i] = -(m0 * tau[i][0] + m1 * tau[i][1] + m2 * tau[i][2]);
   F[4] = -(m0 * phi[0] + m1 * phi[1] + m2 * phi[2]);
@@ -185,9 +184,10 @@ __global__ void __launch_bounds__(256) k_lad_shear(const Prob* __restrict__ prob
   if (z3) qz.prime(W, T, idx, sz);
   for (int k = c.k0; k < c.k1; ++k, idx += sz) {
     if (z3) qz.step(W, T, idx, sz);
-    R gl[3][5], D[5][3];
+    R gl[3][5], D[5][3], mt[10];
+    load_met(P, idx, mt);
     e4_grads_zm(P, W, idx, qz, gl);
-    to_physical(P, idx, gl, D);
+    to_physical(P.ndim, mt, gl, D);
     R S2 = R(0);
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) {
@@ -227,9 +227,10 @@ __global__ void __launch_bounds__(256) k_lad_raw(const Prob* __restrict__ probs,
       qz.step(W, T, idx, sz);
       qs.step(S, T, idx, sz);
     }
-    R gl[3][5], D[5][3];
+    R gl[3][5], D[5][3], mt[10];
+    load_met(P, idx, mt);
     e4_grads_zm(P, W, idx, qz, gl);
-    to_physical(P, idx, gl, D);
+    to_physical(P.ndim, mt, gl, D);
     R rho = W[idx], p = W[4 * T + idx];
     R ri = rcp(rho);
     R theta = D[1][0] + D[2][1] + D[3][2];
@@ -427,9 +428,10 @@ __global__ void __launch_bounds__(256) k_lad_nodeflux(const Prob* __restrict__ p
     if (z3) qz.step(W, T, idx, sz);
     R w[5];
     for (int q = 0; q < 5; ++q) w[q] = W[q * T + idx];
-    R gl[3][5], D[5][3];
+    R gl[3][5], D[5][3], mt[10];
+    load_met(P, idx, mt);
     e4_grads_zm(P, W, idx, qz, gl);
-    to_physical(P, idx, gl, D);
+    to_physical(P.ndim, mt, gl, D);
     const int cidx = pos_to_idx(P, ci, cj, z3 ? scalar_image(P, 2, k) : k);
     const R ri = rcp(w[0]);
     R muf, kapf;
@@ -437,9 +439,9 @@ __global__ void __launch_bounds__(256) k_lad_nodeflux(const Prob* __restrict__ p
     R mu = muf + C[cidx], beta = C[T + cidx], kappa = kapf + C[2 * T + cidx];
     R E = w[4] * R(1.0 / (P.gamma - 1.0)) + R(0.5) * w[0] * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
     for (int l = 0; l < P.ndim; ++l) {
+      const R m0 = mt[3 * l], m1 = mt[3 * l + 1], m2 = mt[3 * l + 2];
       R F[5];
-      viscous_flux(P, idx, l, w, ri, D, mu, beta, kappa, F);
-      R m0 = met<R>(P, 3 * l, idx), m1 = met<R>(P, 3 * l + 1, idx), m2 = met<R>(P, 3 * l + 2, idx);
+      viscous_flux(P, m0, m1, m2, w, ri, D, mu, beta, kappa, F);
       R U = m0 * w[1] + m1 * w[2] + m2 * w[3];
       R* out = static_cast<R*>(P.FL[l]);
       out[idx] = w[0] * U + F[0];
@@ -554,16 +556,17 @@ __global__ void __launch_bounds__(256) k_gbr_viscflux(const Prob* __restrict__ p
     if (region && !P.fg[idx]) continue;
     R w[5];
     for (int q = 0; q < 5; ++q) w[q] = W[q * T + idx];
-    R gl[3][5], D[5][3];
+    R gl[3][5], D[5][3], mt[10];
     for (int l = 0; l < 3; ++l)
       for (int q = 0; q < 5; ++q) gl[l][q] = l < P.ndim ? static_cast<const R*>(P.G[l])[q * T + idx] : R(0);
-    to_physical(P, idx, gl, D);
+    load_met(P, idx, mt);
+    to_physical(P.ndim, mt, gl, D);
     const R ri = rcp(w[0]);
     R mu, kappa;
     transport(P, ri, w[4], mu, kappa);
     for (int l = 0; l < P.ndim; ++l) {
       R F[5];
-      viscous_flux(P, idx, l, w, ri, D, mu, R(0), kappa, F);
+      viscous_flux(P, mt[3 * l], mt[3 * l + 1], mt[3 * l + 2], w, ri, D, mu, R(0), kappa, F);
       R* out = static_cast<R*>(P.FV[l]);
       for (int q = 0; q < 5; ++q) out[q * T + idx] = F[q];
     }

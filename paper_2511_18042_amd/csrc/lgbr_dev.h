@@ -82,6 +82,17 @@ __host__ __device__ __forceinline__ R met(const Prob& P, int c, int idx) {
   return (R)P.cm[c];
 }
 
+// all node metrics at idx: m[3 l + j] = l_hat_j of direction l, m[9] = J
+template <typename R>
+__device__ __forceinline__ void load_met(const Prob& P, int idx, R m[10]) {
+  if (P.curvilinear) {
+    const R* M = static_cast<const R*>(P.MR);
+    for (int c = 0; c < 10; ++c) m[c] = M[(size_t)c * P.total + idx];
+  } else {
+    for (int c = 0; c < 10; ++c) m[c] = (R)P.cm[c];
+  }
+}
+
 __host__ __device__ __forceinline__ double met64(const Prob& P, int c, int idx) {
   if (P.curvilinear) return P.M64[(size_t)c * P.total + idx];
   return P.cm[c];
