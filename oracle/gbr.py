@@ -215,7 +215,11 @@ def gbr_interface_flux(W, G, Ob, M, d, gamma, omega_thr=0.01, mp_eps=1e-20, mp_a
     """C-GBR convective flux at every interface i+1/2 along d, stored at node i.
 
     W  : primitives (5, ...);  G : their derivatives along d (5, ...);
-    Ob : Omega-bar along d;    M : node metrics (10, ...).
+    Ob : Omega-bar along d, or None for inviscid flow, where Sec. 2.3 limits with the MP
+         criterion alone: every field takes its linear state (upwind for the acoustic
+         fields, central for the others) where the MP test of the entropy rule passes,
+         MP5 where it fails (R26);
+    M  : node metrics (10, ...).
     If ``record`` is a dict, the smallest decision margin per interface is stored
     under record['margin'] (used to excuse threshold flips, R22).
     """
@@ -243,28 +247,39 @@ def gbr_interface_flux(W, G, Ob, M, d, gamma, omega_thr=0.01, mp_eps=1e-20, mp_a
     passL = (CL_lin - C[0]) * (CL_lin - cmpL) <= mp_eps
     passR = (CR_lin - C[1]) * (CR_lin - cmpR) <= mp_eps
 
-    ObL = Ob
-    ObR = shift(Ob, 1, d)
-    shockL = ObL > omega_thr
-    shockR = ObR > omega_thr
-
     CL = np.empty_like(CL_lin)
     CR = np.empty_like(CR_lin)
-    for b in (0, 4):                       # acoustic waves
-        CL[b] = np.where(shockL, mpL[b], CL_lin[b])
-        CR[b] = np.where(shockR, mpR[b], CR_lin[b])
-    CL[1] = np.where(passL[1], CC[1], mpL[1])   # entropy wave (R3)
-    CR[1] = np.where(passR[1], CC[1], mpR[1])
-    for b in (2, 3):                       # shear waves
-        CL[b] = np.where(shockL, mpL[b], CC[b])
-        CR[b] = np.where(shockR, mpR[b], CC[b])
+    if Ob is None:                         # inviscid: MP criterion for every field (R26)
+        for b in range(5):
+            linL = CL_lin[b] if b in (0, 4) else CC[b]
+            linR = CR_lin[b] if b in (0, 4) else CC[b]
+            CL[b] = np.where(passL[b], linL, mpL[b])
+            CR[b] = np.where(passR[b], linR, mpR[b])
+        tested = range(5)
+        om = np.inf
+    else:
+        ObL = Ob
+        ObR = shift(Ob, 1, d)
+        shockL = ObL > omega_thr
+        shockR = ObR > omega_thr
+        for b in (0, 4):                       # acoustic waves
+            CL[b] = np.where(shockL, mpL[b], CL_lin[b])
+            CR[b] = np.where(shockR, mpR[b], CR_lin[b])
+        CL[1] = np.where(passL[1], CC[1], mpL[1])   # entropy wave (R3)
+        CR[1] = np.where(passR[1], CC[1], mpR[1])
+        for b in (2, 3):                       # shear waves
+            CL[b] = np.where(shockL, mpL[b], CC[b])
+            CR[b] = np.where(shockR, mpR[b], CC[b])
+        tested = (1,)
+        om = np.minimum(np.abs(ObL - omega_thr), np.abs(ObR - omega_thr)) / omega_thr
 
     if record is not None:
-        om = np.minimum(np.abs(ObL - omega_thr), np.abs(ObR - omega_thr)) / omega_thr
-        t2L = product_test_margin(CL_lin[1], C[0][1], CL_lin[1], cmpL[1], mp_eps)
-        t2R = product_test_margin(CR_lin[1], C[1][1], CR_lin[1], cmpR[1], mp_eps)
+        t = np.inf
+        for b in tested:
+            t = np.minimum(t, product_test_margin(CL_lin[b], C[0][b], CL_lin[b], cmpL[b], mp_eps))
+            t = np.minimum(t, product_test_margin(CR_lin[b], C[1][b], CR_lin[b], cmpR[b], mp_eps))
         mm = np.minimum(np.min(mL, axis=0), np.min(mR, axis=0))
-        record['margin'] = np.minimum(np.minimum(om, mm), np.minimum(t2L, t2R))
+        record['margin'] = np.minimum(np.minimum(om, mm), t)
 
     WL = from_characteristic(CL, n, t1, t2, rb, cb)
     WR = from_characteristic(CR, n, t1, t2, rb, cb)

@@ -120,7 +120,7 @@ def rhs(Q, grid, gas, opts, scheme, M=None, info=None, force_flags=None):
         G = {l: np.stack([gradient(W[q], l, opts.grad, grid) for q in range(5)])
              for l in range(grid.ndim)}
         Dg = physical_gradients(G, M, grid)
-        Om = omega_sensor(W, Dg[1:4], grid)
+        Om = omega_sensor(W, Dg[1:4], grid) if gas.viscous else None   # R26
     if need_lad:
         G4 = {l: np.stack([gradient(W[q], l, 'E4', grid) for q in range(5)])
               for l in range(grid.ndim)}
@@ -135,7 +135,8 @@ def rhs(Q, grid, gas, opts, scheme, M=None, info=None, force_flags=None):
         F = np.zeros_like(Q)
         if need_gbr:
             rec = {} if info is not None else None
-            Fg = gbr_interface_flux(W, G[d], omega_bar(Om, d), M, d, gamma, opts.omega_thr,
+            Ob = omega_bar(Om, d) if Om is not None else None
+            Fg = gbr_interface_flux(W, G[d], Ob, M, d, gamma, opts.omega_thr,
                                     opts.mp_eps, opts.mp_alpha, record=rec)
             if gas.viscous:
                 Fv = viscous_node_flux(W, Dg, M, d, gas, mu_f, np.zeros_like(mu_f), kappa_f)

@@ -211,3 +211,39 @@ def test_sensor_detects_pressure_jump_at_rest_and_states_stay_positive():
             band = g.band(-1, 0)
             assert np.isfinite(F[(slice(None),) + band]).all()
             assert rec['WL'][4][band].min() > 0 and rec['WR'][4][band].min() > 0
+
+
+def test_inviscid_rule_limits_every_field_by_the_mp_test():
+    """Sec. 2.3 limits inviscid flow with the MP criterion alone (R26).  On the Sod and
+    triple-point initial data (a pressure jump at rest) every field is then MP5-limited at
+    the jump, so the interface pressures stay positive without the Omega sensor; on smooth
+    monotone data, where every MP test passes and the sensor stays below its threshold, the
+    inviscid rule and the wave-appropriate rule give the same flux."""
+    from oracle import grid as gr, rhs as R, derivatives as D
+    from oracle.lad import physical_gradients
+    from paper_2511_18042_amd import cases
+    for c in (cases.sod(100), cases.triple_point(112, 48)):
+        g = gr.Grid(c.ndim, c.n, c.bc, c.h)
+        Q = c.Q.copy()
+        gr.fill_ghosts_conserved(Q, g)
+        W = R.primitives(Q, 1.4)
+        M = gr.node_metrics(g)
+        Gd = {l: np.stack([D.e6(W[q], l) for q in range(5)]) for l in range(g.ndim)}
+        for d in range(g.ndim):
+            rec = {}
+            F = gbr.gbr_interface_flux(W, Gd[d], None, M, d, 1.4, record=rec)
+            band = g.band(-1, 0)
+            assert np.isfinite(F[(slice(None),) + band]).all()
+            assert rec['WL'][4][band].min() > 0 and rec['WR'][4][band].min() > 0
+    # smooth monotone ramp in x: MP tests pass, Omega-bar small
+    c = cases.Case(1, (40, 1, 1), [(cases.TRANSMISSIVE,) * 2], h=(1 / 40, 1, 1))
+    x, _, _ = cases.cartesian_mesh(c)
+    W = np.stack([1 + 0.1 * x, 0.2 + 0.05 * x, 0 * x, 0 * x, 1 + 0.05 * x])
+    g = gr.Grid(1, c.n, c.bc, c.h)
+    M = gr.node_metrics(g)
+    G0 = np.stack([D.e6(W[q], 0) for q in range(5)])
+    Ob = np.zeros_like(W[0])
+    band = g.band(-1, 0)
+    Fi = gbr.gbr_interface_flux(W, G0, None, M, 0, 1.4)
+    Fv = gbr.gbr_interface_flux(W, G0, Ob, M, 0, 1.4)
+    assert np.allclose(Fi[(slice(None),) + band], Fv[(slice(None),) + band], rtol=0, atol=1e-14)
