@@ -215,9 +215,15 @@ __host__ __device__ __forceinline__ void gbr_flux(const Prob& P, int d, int idx,
     to_char(fr, G[id], G[T + id], G[2 * T + id], G[3 * T + id], G[4 * T + id], D[o + 1]);
   }
   const R thr = (R)P.omega_thr, eps = (R)P.mp_eps, alpha = (R)P.mp_alpha;
-  R om_m1 = Om[idx - s], om_0 = Om[idx], om_1 = Om[idx + s], om_2 = Om[idx + 2 * s];
-  bool shockL = fmax(fmax(om_m1, om_0), om_1) > thr;
-  bool shockR = fmax(fmax(om_0, om_1), om_2) > thr;
+  // inviscid flow: the MP criterion alone governs every field and the Omega sensor is not
+  // evaluated (Sec. 2.3); viscous flow: the wave-appropriate rule
+  const bool mp_only = !P.viscous;
+  bool shockL = false, shockR = false;
+  if (!mp_only) {
+    R om_m1 = Om[idx - s], om_0 = Om[idx], om_1 = Om[idx + s], om_2 = Om[idx + 2 * s];
+    shockL = fmax(fmax(om_m1, om_0), om_1) > thr;
+    shockR = fmax(fmax(om_0, om_1), om_2) > thr;
+  }
 
   R CL[5], CR[5];
   for (int b = 0; b < 5; ++b) {
@@ -231,14 +237,16 @@ __host__ __device__ __forceinline__ void gbr_flux(const Prob& P, int d, int idx,
     R cc = R(0.5) * (Llin + Rlin);
     bool useL, useR;  // use MP5?
     R Lalt, Ralt;     // value otherwise
-    if (b == 0 || b == 4) {
-      useL = shockL; useR = shockR; Lalt = Llin; Ralt = Rlin;
-    } else if (b == 1) {
+    if (mp_only || b == 1) {
       R cmpL = c0 + minmod2(c1 - c0, alpha * (c0 - cm1));
       R cmpR = c1 + minmod2(c0 - c1, alpha * (c1 - c2));
       useL = !((Llin - c0) * (Llin - cmpL) <= eps);
       useR = !((Rlin - c1) * (Rlin - cmpR) <= eps);
-      Lalt = cc; Ralt = cc;
+      const bool acoustic = b == 0 || b == 4;
+      Lalt = acoustic ? Llin : cc;
+      Ralt = acoustic ? Rlin : cc;
+    } else if (b == 0 || b == 4) {
+      useL = shockL; useR = shockR; Lalt = Llin; Ralt = Rlin;
     } else {
       useL = shockL; useR = shockR; Lalt = cc; Ralt = cc;
     }

@@ -127,8 +127,10 @@ void enqueue_rhs(const Launch& L, const Cfg& c, int scheme, StateRef ref, const 
       if (c.grad == LG_GRAD_C4) lg::launch_grad_c4<R>(L, ref, d, skip_gbr, region);
       else lg::launch_grad_explicit<R>(L, d, 6, skip_gbr, region);
     }
-    lg::launch_sensor<R>(L, skip_gbr, region);
-    if (c.viscous) lg::launch_gbr_viscflux<R>(L, skip_gbr, region);
+    if (c.viscous) {  // the Omega sensor drives the selection in viscous flow only (Sec. 2.3)
+      lg::launch_sensor<R>(L, skip_gbr, region);
+      lg::launch_gbr_viscflux<R>(L, skip_gbr, region);
+    }
   }
   if (sel != lg::SEL_GBR) lg::launch_lad<R>(L, skip_lad);
   // interfaces: the all-LAD pass (LAD scheme; hybrid with no troubled node), else the
