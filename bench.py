@@ -58,12 +58,14 @@ def log(msg):
     print('[bench] ' + msg, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kclass, nodes, rs, ndim, gbr_frac, viscous, curv):
+def algorithmic_bytes(kclass, nodes, rs, ndim, gbr_frac, viscous, curv, planar=False):
     """Minimum bytes one launch of a kernel class moves (every input read once, every
     output written once) for ``nodes`` interior nodes; rs = bytes of the bulk real type,
-    curv: node metrics (9 components + J) are fields rather than constants."""
+    curv: node metrics (9 components + J) are fields rather than constants; planar: they
+    (and the LAD grid factors) are stored for one plane only, so they add nothing per node."""
     vis = 5 * rs if viscous else 0
-    met = 10 * rs if curv else 0
+    per_node_geom = curv and not planar
+    met = 10 * rs if per_node_geom else 0
     if kclass == 'sweep_x':
         per = (1 - gbr_frac) * 5 * rs + gbr_frac * (11 * rs + vis) + 1 + 40
     elif kclass in ('sweep_y', 'sweep_z'):
@@ -71,13 +73,13 @@ def algorithmic_bytes(kclass, nodes, rs, ndim, gbr_frac, viscous, curv):
     elif kclass == 'lad_node':
         per = 5 * rs + met + 2 * rs                          # W, metrics -> |S|, theta
     elif kclass == 'lad_raw':
-        per = 5 * rs + 2 * rs + met + (3 * ndim * rs if curv else 0) + 3 * rs   # + Delta x_l -> raw
+        per = 5 * rs + 2 * rs + met + (3 * ndim * rs if per_node_geom else 0) + 3 * rs   # + Delta x_l -> raw
     elif kclass == 'gauss':
         per = 6 * rs                                         # one launch: 3 fields in, 3 out
     elif kclass == 'lad_flux':
         per = 5 * rs + 3 * rs + met + 5 * ndim * rs          # W, coefficients, metrics -> F_l
     elif kclass == 'lad_sweep':
-        per = 5 * ndim * rs + (8 if curv else 0) + 120       # F_l, J, U^n, U^s -> stage result
+        per = 5 * ndim * rs + (8 if per_node_geom else 0) + 120   # F_l, J, U^n, U^s -> stage result
     elif kclass == 'grad_e6':
         per = 10 * rs
     elif kclass == 'grad_c4':
@@ -91,7 +93,7 @@ def algorithmic_bytes(kclass, nodes, rs, ndim, gbr_frac, viscous, curv):
     elif kclass == 'combine':
         per = 160
     elif kclass == 'dt':
-        per = 40 + (72 if curv else 0)
+        per = 40 + (72 if per_node_geom else 0)
     else:
         per = 0.0
     return per * nodes
@@ -143,13 +145,14 @@ class Runner:
         return ms, kern, bad, Q, float(t.item())
 
     def roofline(self, ctx, scheme, Q0, cells, ndim, gbr_frac, viscous, curv, K=20):
+        planar = ctx.metrics_planar()
         """Per-class breakdown, then the dominant class timed alone."""
         _, breakdown, _, _, _ = self.steps(ctx, scheme, Q0, K=K, W=2, prof_class=-1)
         dominant = max(breakdown, key=lambda k: breakdown[k][0])
         _, kern, _, _, _ = self.steps(ctx, scheme, Q0, K=K, W=2, prof_class=dominant)
         dom_ms, dom_n = kern[dominant]
         dom_avg = dom_ms / max(dom_n, 1)
-        algo = algorithmic_bytes(dominant, cells, 4, ndim, gbr_frac, viscous, curv)
+        algo = algorithmic_bytes(dominant, cells, 4, ndim, gbr_frac, viscous, curv, planar)
         achieved = algo / (dom_avg * 1e-3) / 1e9
         roof = {'bound': 'hbm', 'kernel': dominant, 'achieved': round(achieved, 1), 'peak': HBM_PEAK_GBS,
                 'unit': 'GB/s', 'frac': round(achieved / HBM_PEAK_GBS, 4), 'avg_launch_ms': round(dom_avg, 5),

@@ -124,6 +124,11 @@ lg_status lg_create(lg_ctx** ctx, const lg_grid* grid, const double* node_metric
 void lg_destroy(lg_ctx* ctx);
 size_t lg_workspace_bytes(const lg_ctx* ctx);
 
+/* 1 if the context stores one plane of node metrics and LAD grid factors because they do
+ * not vary along zeta (a 2D section extruded spanwise, detected at lg_create to 1e-12 of
+ * the plane's values), 0 if it stores them at every node, -1 for a null context. */
+int lg_metrics_planar(const lg_ctx* ctx);
+
 /* Conservative node metrics from node coordinates (Sec. 2.1; fourth-order central
  * differences as the outer operator so that the discrete metric identities hold).
  * coords [3][N] -> node_metrics [10][N]; values are defined on nodes at least two

@@ -232,10 +232,10 @@ __global__ void __launch_bounds__(256) k_dt_reduce(const Prob* __restrict__ prob
     int i = t % n0, r = t / n0;
     int j = r % n1, k = r / n1;
     int idx = pos_to_idx(P, i + P.g[0], j + P.g[1], k + P.g[2]);
-    double rho = Q[idx];
-    double u = Q[T + idx] / rho, v = Q[2 * T + idx] / rho, w = Q[3 * T + idx] / rho;
+    double rho = Q[idx], ri = 1.0 / rho;
+    double u = Q[T + idx] * ri, v = Q[2 * T + idx] * ri, w = Q[3 * T + idx] * ri;
     double p = (P.gamma - 1.0) * (Q[4 * T + idx] - 0.5 * rho * (u * u + v * v + w * w));
-    double c = sqrt(P.gamma * p / rho);
+    double c = sqrt(P.gamma * p * ri);
     double J = met64(P, 9, idx);
     double s = 0.0;
     for (int l = 0; l < P.ndim; ++l) {
@@ -378,6 +378,44 @@ __global__ void __launch_bounds__(256) k_convert(const double* src, R* dst, size
     dst[i] = (R)src[i];
 }
 
+// ------------------------------------------------------------------ planar grids
+// Largest deviation, over planes 2 <= k < N2 - 2 (where node metrics are defined), of the
+// node metrics and, at interior nodes, of Delta x_l from their values on the first interior
+// plane, relative to the largest metric component (resp. component of Delta x_l) there.
+// Stored as the bit pattern of a non-negative double (integer max orders them).
+__global__ void __launch_bounds__(256) k_planar_dev(int N0, int N1, int N2, int g, const double* __restrict__ M,
+                                                    const double* __restrict__ X, unsigned long long* out) {
+  const size_t s2 = (size_t)N0 * N1, T = s2 * N2;
+  double dev = 0.0;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < T; idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t k = idx / s2, col = idx % s2;
+    const int i = (int)(col % N0), j = (int)(col / N0);
+    if (k < 2 || k >= (size_t)N2 - 2 || i < 2 || i >= N0 - 2 || j < 2 || j >= N1 - 2) continue;
+    const size_t ref = (size_t)g * s2 + col;
+    double sc = 0.0;
+    for (int c = 0; c < 9; ++c) sc = fmax(sc, fabs(M[c * T + ref]));
+    if (sc > 0.0)
+      for (int c = 0; c < 9; ++c) dev = fmax(dev, fabs(M[c * T + idx] - M[c * T + ref]) / sc);
+    const double J0 = fabs(M[9 * T + ref]);
+    if (J0 > 0.0) dev = fmax(dev, fabs(M[9 * T + idx] - M[9 * T + ref]) / J0);
+    if (i >= g && i < N0 - g && j >= g && j < N1 - g && k >= (size_t)g && k < (size_t)(N2 - g)) {
+      const size_t st[3] = {1, (size_t)N0, s2};
+      for (int l = 0; l < 3; ++l) {
+        double a[3], b[3], nb = 0.0;
+        for (int c = 0; c < 3; ++c) {
+          a[c] = 0.5 * (X[c * T + idx + st[l]] - X[c * T + idx - st[l]]);
+          b[c] = 0.5 * (X[c * T + ref + st[l]] - X[c * T + ref - st[l]]);
+          nb = fmax(nb, fabs(b[c]));
+        }
+        if (nb > 0.0)
+          for (int c = 0; c < 3; ++c) dev = fmax(dev, fabs(a[c] - b[c]) / nb);
+      }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) dev = fmax(dev, __shfl_down(dev, off));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(dev));
+}
+
 // ------------------------------------------------------------------ launchers
 static inline dim3 grid_for(long long work, int nprob, int block = 256, int cap = 8192) {
   long long b = (work + block - 1) / block;
@@ -436,7 +474,7 @@ void launch_combine(const Launch& L, RKRef rr, int stage, double a, double b, in
 
 void launch_dt(const Launch& L, const double* Qx, double* tx, double t_end, int advance_t) {
   hipLaunchKernelGGL(k_dt_reset, dim3(1, L.nprob), dim3(64), 0, L.stream, L.probs);
-  LG_TIMED(L, KC_DT, hipLaunchKernelGGL(k_dt_reduce, grid_for(L.max_cells, L.nprob, 256, 1024), dim3(256), 0,
+  LG_TIMED(L, KC_DT, hipLaunchKernelGGL(k_dt_reduce, grid_for(L.max_cells, L.nprob, 256, 8192), dim3(256), 0,
                                         L.stream, L.probs, Qx));
   hipLaunchKernelGGL(k_dt_finalize, dim3(1, L.nprob), dim3(64), 0, L.stream, L.probs, tx, t_end, advance_t);
 }
@@ -456,6 +494,11 @@ void launch_metrics(int ndim, const int N[3], const double* coords, double* scra
                      scratch9);
   hipLaunchKernelGGL(k_metric_outer, grid_for(total, 1), dim3(256), 0, s, ndim, N[0], N[1], N[2], coords,
                      scratch9, metrics);
+}
+
+void launch_planar_dev(int N0, int N1, int N2, int g, const double* M, const double* X, unsigned long long* out,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_planar_dev, grid_for((long long)N0 * N1 * N2, 1), dim3(256), 0, s, N0, N1, N2, g, M, X, out);
 }
 
 template <typename R>

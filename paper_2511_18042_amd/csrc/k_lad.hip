@@ -144,7 +144,8 @@ __device__ __forceinline__ void e4_grads_zm(const Prob& P, const R* W, int idx, 
 }
 
 // ------------------------------------------------------------------ grid factors
-// Delta x_l at interior nodes (curvilinear grids; once per context)
+// Delta x_l at interior nodes (curvilinear grids; once per context); when the grid is
+// planar along zeta, only the first interior plane is stored
 template <typename R>
 __global__ void __launch_bounds__(256) k_lad_dx(const Prob* __restrict__ probs) {
   const Prob& P = probs[blockIdx.y];
@@ -153,6 +154,7 @@ __global__ void __launch_bounds__(256) k_lad_dx(const Prob* __restrict__ probs) 
   const size_t T = P.total;
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < P.total; idx += gridDim.x * blockDim.x) {
     if (!is_interior(P, idx)) continue;
+    if (P.met_planar && idx / P.s[2] != P.g[2]) continue;
     for (int l = 0; l < 3; ++l)
       for (int cc = 0; cc < 3; ++cc) {
         R v = R(0);
@@ -160,7 +162,7 @@ __global__ void __launch_bounds__(256) k_lad_dx(const Prob* __restrict__ probs) 
           const double* X = P.coords + (size_t)cc * T;
           v = (R)(0.5 * (X[idx + P.s[l]] - X[idx - P.s[l]]));
         }
-        GX[(size_t)(3 * l + cc) * T + idx] = v;
+        GX[(size_t)(3 * l + cc) * P.met_T + met_idx(P, idx)] = v;
       }
   }
 }
@@ -182,10 +184,13 @@ __global__ void __launch_bounds__(256) k_lad_shear(const Prob* __restrict__ prob
   int idx = pos_to_idx(P, c.i, c.j, c.k0);
   ZQ5<R, 5> qz;
   if (z3) qz.prime(W, T, idx, sz);
+  R mt[10];
+  const bool mplane = P.met_planar;
+  if (mplane) load_met(P, idx, mt);   // one plane of metrics serves the whole column
   for (int k = c.k0; k < c.k1; ++k, idx += sz) {
     if (z3) qz.step(W, T, idx, sz);
-    R gl[3][5], D[5][3], mt[10];
-    load_met(P, idx, mt);
+    if (!mplane) load_met(P, idx, mt);
+    R gl[3][5], D[5][3];
     e4_grads_zm(P, W, idx, qz, gl);
     to_physical(P.ndim, mt, gl, D);
     R S2 = R(0);
@@ -222,13 +227,25 @@ __global__ void __launch_bounds__(256) k_lad_raw(const Prob* __restrict__ probs,
     qz.prime(W, T, idx, sz);
     qs.prime(S, T, idx, sz);
   }
+  R mt[10], gx[9];
+  const bool mplane = P.met_planar;
+  auto load_gx = [&](int id) {
+    for (int m = 0; m < 9; ++m) gx[m] = P.curvilinear ? GX[(size_t)m * P.met_T + met_idx(P, id)] : R(0);
+  };
+  if (mplane) {   // one plane of metrics and grid factors serves the whole column
+    load_met(P, idx, mt);
+    load_gx(idx);
+  }
   for (int k = c.k0; k < c.k1; ++k, idx += sz) {
     if (z3) {
       qz.step(W, T, idx, sz);
       qs.step(S, T, idx, sz);
     }
-    R gl[3][5], D[5][3], mt[10];
-    load_met(P, idx, mt);
+    if (!mplane) {
+      load_met(P, idx, mt);
+      load_gx(idx);
+    }
+    R gl[3][5], D[5][3];
     e4_grads_zm(P, W, idx, qz, gl);
     to_physical(P.ndim, mt, gl, D);
     R rho = W[idx], p = W[4 * T + idx];
@@ -250,7 +267,7 @@ __global__ void __launch_bounds__(256) k_lad_raw(const Prob* __restrict__ probs,
     for (int l = 0; l < P.ndim; ++l) {
       R dx[3];
       if (P.curvilinear) {
-        for (int cc = 0; cc < 3; ++cc) dx[cc] = GX[(size_t)(3 * l + cc) * T + idx];
+        for (int cc = 0; cc < 3; ++cc) dx[cc] = gx[3 * l + cc];
       } else {
         dx[0] = dx[1] = dx[2] = R(0);
         dx[l] = (R)P.h[l];
@@ -424,12 +441,15 @@ __global__ void __launch_bounds__(256) k_lad_nodeflux(const Prob* __restrict__ p
   int idx = pos_to_idx(P, c.i, c.j, c.k0);
   ZQ5<R, 5> qz;
   if (z3) qz.prime(W, T, idx, sz);
+  R mt[10];
+  const bool mplane = P.met_planar;
+  if (mplane) load_met(P, idx, mt);   // one plane of metrics serves the whole column
   for (int k = c.k0; k < c.k1; ++k, idx += sz) {
     if (z3) qz.step(W, T, idx, sz);
+    if (!mplane) load_met(P, idx, mt);
     R w[5];
     for (int q = 0; q < 5; ++q) w[q] = W[q * T + idx];
-    R gl[3][5], D[5][3], mt[10];
-    load_met(P, idx, mt);
+    R gl[3][5], D[5][3];
     e4_grads_zm(P, W, idx, qz, gl);
     to_physical(P.ndim, mt, gl, D);
     const int cidx = pos_to_idx(P, ci, cj, z3 ? scalar_image(P, 2, k) : k);
@@ -485,9 +505,11 @@ __global__ void __launch_bounds__(256) k_lad_sweep(const Prob* __restrict__ prob
   int idx = pos_to_idx(P, c.i, c.j, c.k0);
   ZQ5<R, 5> qz;
   if (z3) qz.prime(Fz, T, idx, sz);
+  const bool mplane = P.met_planar;
+  const double Jcol = met64(P, 9, idx);
   for (int k = c.k0; k < c.k1; ++k, idx += sz) {
     if (z3) qz.step(Fz, T, idx, sz);
-    const double J = P.curvilinear ? P.M64[9 * T + idx] : P.cm[9];
+    const double J = mplane ? Jcol : met64(P, 9, idx);
     double Lq[5];
     for (int q = 0; q < 5; ++q) {
       const R* f = Fx + q * T + idx;
@@ -529,7 +551,9 @@ __global__ void __launch_bounds__(256) k_lad_sweep(const Prob* __restrict__ prob
   if (bad) atomicAdd(P.status, bad);
 }
 
-// ghost nodes of the stage result = U^n (what the combination kernel does off the interior)
+// Ghost nodes of the stage result = U^n, as the combination kernel does off the interior.
+// Inside rk3_step (no explicit output) only the ghosts of FIXED faces are copied: every
+// other ghost is rewritten from the interior before the next stage reads it.
 __global__ void __launch_bounds__(256) k_stage_ghosts(const Prob* __restrict__ probs, RKRef rr, int stage,
                                                       int skip_if_any) {
   const Prob& P = probs[blockIdx.y];
@@ -537,9 +561,17 @@ __global__ void __launch_bounds__(256) k_stage_ghosts(const Prob* __restrict__ p
   const double* Un = rr.Un ? rr.Un : P.Q;
   double* out = rr.out ? rr.out : (stage == 2 ? const_cast<double*>(Un) : P.Us);
   if (out == Un) return;
+  const bool all = rr.out != nullptr;
   const size_t T = P.total;
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < P.total; idx += gridDim.x * blockDim.x) {
-    if (is_interior(P, idx)) continue;
+    const int p[3] = {idx % P.N[0], (idx / P.N[0]) % P.N[1], idx / (P.N[0] * P.N[1])};
+    bool ghost = false, fixed = false;
+    for (int d = 0; d < P.ndim; ++d) {
+      const bool lo = p[d] < P.g[d], hi = p[d] >= P.g[d] + P.n[d];
+      ghost |= lo || hi;
+      fixed |= (lo && P.bc[d][0] == BC_FIXED) || (hi && P.bc[d][1] == BC_FIXED);
+    }
+    if (!ghost || !(all || fixed)) continue;
     for (int q = 0; q < 5; ++q) out[q * T + idx] = Un[q * T + idx];
   }
 }
@@ -611,7 +643,7 @@ void launch_lad_sweep(const Launch& L, StateRef ref, const RKRef* rr, int stage,
   LG_TIMED(L, KC_LAD_SWEEP, hipLaunchKernelGGL(k_lad_sweep<R>, zm_grid(L, 0, 0, ZM_TX, ZM_TY), dim3(256), 0,
                                                L.stream, L.probs, ref, r, rr ? 1 : 0, stage, a, b, skip_if_any,
                                                zm_chunk(L, 0, 0)));
-  if (rr)
+  if (rr && (rr->out || L.has_fixed))
     LG_TIMED(L, KC_COMBINE, hipLaunchKernelGGL(k_stage_ghosts, g1(L.max_total, L.nprob), dim3(256), 0, L.stream,
                                                L.probs, r, stage, skip_if_any));
 }

@@ -288,9 +288,7 @@ __device__ __forceinline__ void interface_flux(const Prob& P, int d, int idx, in
   }
 }
 
-__device__ __forceinline__ double node_J(const Prob& P, int idx) {
-  return P.curvilinear ? P.M64[9 * (size_t)P.total + idx] : P.cm[9];
-}
+__device__ __forceinline__ double node_J(const Prob& P, int idx) { return met64(P, 9, idx); }
 
 // ------------------------------------------------------------------ x sweep: one wave per
 // row segment of 63 nodes; lane t computes the interface left of node (seg*63 + t - 1) + 1

@@ -252,6 +252,7 @@ void fill_launch(Launch& L, const Prob& P) {
     if (pcr) L.pcr_dir[d] = 1;
     else L.thomas_dir[d] = 1;
     if (periodic && P.n[d] < 128) L.has_short_periodic = 1;
+    if (P.bc[d][0] == LG_BC_FIXED || P.bc[d][1] == LG_BC_FIXED) L.has_fixed = 1;
   }
   L.max_total = std::max<long long>(L.max_total, P.total);
   L.max_cells = std::max<long long>(L.max_cells, (long long)P.n[0] * P.n[1] * P.n[2]);
@@ -387,7 +388,6 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
     P.llist[d] = static_cast<int*>(A(sizeof(int) * (size_t)P.N[o1] * P.N[o2]));
   }
   P.S3 = A(2 * T * rs);
-  if (G.curvilinear) P.GX = A(9 * T * rs);
   P.CA = A(3 * T * rs);
   P.CB = A(3 * T * rs);
   for (int d = 0; d < G.ndim; ++d) P.FL[d] = A(5 * T * rs);
@@ -407,19 +407,63 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
   P.any_flag = reinterpret_cast<int*>(scal + 4);
   P.lcount = reinterpret_cast<int*>(scal + 5);   // three ints
   P.t_end = 0.0;
+  P.met_T = P.total;
   if (G.curvilinear) {
-    P.M64 = node_metrics;
     P.coords = coords;
-    if (opts->precision == LG_MIXED) {
-      float* mr = static_cast<float*>(A(10 * T * sizeof(float)));
+    // A grid whose metrics and grid factors do not vary along zeta (a 2D section extruded
+    // spanwise) keeps one plane of them: the stencil kernels then read no metric bytes per
+    // node.  Deviations up to 1e-12 of the plane's values (rounding of the extrusion) are
+    // accepted.
+    if (G.ndim == 3) {
+      unsigned long long* dbits = reinterpret_cast<unsigned long long*>(scal + 7);
+      unsigned long long bits = 0;
+      if (hipMemcpy(dbits, &bits, sizeof(bits), hipMemcpyHostToDevice) != hipSuccess) {
+        lg_destroy(c);
+        return LG_EHIP;
+      }
+      lg::launch_planar_dev(P.N[0], P.N[1], P.N[2], lg::NG, node_metrics, coords, dbits, c->stream);
+      if (hipMemcpyAsync(&bits, dbits, sizeof(bits), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+          hipStreamSynchronize(c->stream) != hipSuccess) {
+        lg_destroy(c);
+        return LG_EHIP;
+      }
+      double dev;
+      std::memcpy(&dev, &bits, sizeof(dev));
+      P.met_planar = dev <= 1e-12 ? 1 : 0;
+    }
+    const size_t MT = P.met_planar ? (size_t)P.s[2] : T;
+    P.met_T = (int)MT;
+    if (P.met_planar) {
+      double* m64 = static_cast<double*>(A(10 * MT * sizeof(double)));
       if (!ok) {
         lg_destroy(c);
         return LG_ENOMEM;
       }
-      lg::launch_convert<float>(node_metrics, mr, 10 * T, c->stream);
+      for (int cc = 0; cc < 10; ++cc)
+        if (hipMemcpyAsync(m64 + cc * MT, node_metrics + cc * T + (size_t)lg::NG * MT, MT * sizeof(double),
+                           hipMemcpyDeviceToDevice, c->stream) != hipSuccess) {
+          lg_destroy(c);
+          return LG_EHIP;
+        }
+      P.M64 = m64;
+    } else {
+      P.M64 = node_metrics;
+    }
+    if (opts->precision == LG_MIXED) {
+      float* mr = static_cast<float*>(A(10 * MT * sizeof(float)));
+      if (!ok) {
+        lg_destroy(c);
+        return LG_ENOMEM;
+      }
+      lg::launch_convert<float>(P.M64, mr, 10 * MT, c->stream);
       P.MR = mr;
     } else {
-      P.MR = node_metrics;
+      P.MR = P.M64;
+    }
+    P.GX = A(9 * MT * rs);
+    if (!ok) {
+      lg_destroy(c);
+      return LG_ENOMEM;
     }
   }
   if (opts->grad == LG_GRAD_C4) {
@@ -541,6 +585,8 @@ void lg_destroy(lg_ctx* c) {
 }
 
 size_t lg_workspace_bytes(const lg_ctx* c) { return c ? c->ws_bytes : 0; }
+
+int lg_metrics_planar(const lg_ctx* c) { return c ? c->hp.met_planar : -1; }
 
 lg_status lg_metrics_from_coords(const lg_grid* grid, const double* coords, double* node_metrics, void* stream) {
   if (!grid || !coords || !node_metrics) return LG_EINVAL;

@@ -52,13 +52,15 @@ struct Prob {
   int* llist[3];     // compacted lines of each direction that touch fg
   int* lcount;       // [3] number of listed lines
   void* S3;          // |S|, theta (LAD)                 [2][total]  R
-  void* GX;          // Delta x_l = (x_{+1} - x_{-1}) / 2 [3 l + c][total] R (curvilinear only)
+  void* GX;          // Delta x_l = (x_{+1} - x_{-1}) / 2 [3 l + c][met_T] R (curvilinear only)
   void* CA;          // LAD coefficients mu*,beta*,kappa* [3][total] R (result)
   void* CB;          // LAD filter scratch               [3][total]  R
   void* FL[3];       // LAD node fluxes per direction    [5][total]  R
   void* FV[3];       // C-GBR viscous node fluxes        [5][total]  R
-  const void* MR;    // node metrics in R                [10][total] (curvilinear only)
-  const double* M64; // node metrics in FP64             [10][total] (curvilinear only)
+  const void* MR;    // node metrics in R                [10][met_T] (curvilinear only)
+  const double* M64; // node metrics in FP64             [10][met_T] (curvilinear only)
+  int met_planar;    // 1: metrics and Delta x_l do not vary along zeta; MR, M64, GX hold one plane
+  int met_T;         // field stride of MR, M64 and GX: total, or N0 N1 when planar
   const double* coords;  // node coordinates             [3][total]  (curvilinear only)
   const double* tri[3];  // compact-solve LU tables per direction (see k_grad.hip)
   const double* pcr[3];  // compact-solve PCR factors per direction (see k_grad.hip)
@@ -75,10 +77,15 @@ __host__ __device__ __forceinline__ int pos_to_idx(const Prob& P, int i, int j, 
   return i + P.s[1] * j + P.s[2] * k;
 }
 
+// Position of node idx in the metric arrays (its (i, j) column when they hold one plane).
+__host__ __device__ __forceinline__ int met_idx(const Prob& P, int idx) {
+  return P.met_planar ? idx % P.s[2] : idx;
+}
+
 // Node metric component c (0..8: l_hat_j for l = c/3, j = c%3; 9: J) at node idx.
 template <typename R>
 __host__ __device__ __forceinline__ R met(const Prob& P, int c, int idx) {
-  if (P.curvilinear) return static_cast<const R*>(P.MR)[(size_t)c * P.total + idx];
+  if (P.curvilinear) return static_cast<const R*>(P.MR)[(size_t)c * P.met_T + met_idx(P, idx)];
   return (R)P.cm[c];
 }
 
@@ -87,14 +94,15 @@ template <typename R>
 __device__ __forceinline__ void load_met(const Prob& P, int idx, R m[10]) {
   if (P.curvilinear) {
     const R* M = static_cast<const R*>(P.MR);
-    for (int c = 0; c < 10; ++c) m[c] = M[(size_t)c * P.total + idx];
+    const int mi = met_idx(P, idx);
+    for (int c = 0; c < 10; ++c) m[c] = M[(size_t)c * P.met_T + mi];
   } else {
     for (int c = 0; c < 10; ++c) m[c] = (R)P.cm[c];
   }
 }
 
 __host__ __device__ __forceinline__ double met64(const Prob& P, int c, int idx) {
-  if (P.curvilinear) return P.M64[(size_t)c * P.total + idx];
+  if (P.curvilinear) return P.M64[(size_t)c * P.met_T + met_idx(P, idx)];
   return P.cm[c];
 }
 

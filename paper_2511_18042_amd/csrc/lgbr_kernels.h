@@ -55,6 +55,7 @@ struct Launch {
   long long max_n[3];      // interior extent per direction
   long long sweep_rows[3]; // interior lines (interior of the other two dims) per direction
   int has_short_periodic;  // some periodic direction has fewer than 128 interior nodes
+  int has_fixed;           // some problem has a FIXED face (caller-owned ghosts)
   int pcr_dir[3];          // some problem solves its lines along d by PCR
   int thomas_dir[3];       // some problem solves its lines along d one lane per line
   int ndim;
@@ -102,6 +103,9 @@ void launch_zero_status(const Launch& L);
 void launch_metrics(int ndim, const int N[3], const double* coords, double* scratch9, double* metrics,
                     hipStream_t s);
 template <typename R> void launch_convert(const double* src, R* dst, size_t n, hipStream_t s);
+// deviation of a 3D grid from planarity along zeta (see k_planar_dev); *out must be 0 first
+void launch_planar_dev(int N0, int N1, int N2, int g, const double* M, const double* X, unsigned long long* out,
+                       hipStream_t s);
 
 int sweep_seg(const Launch& L, int d);   // segment length in effect for direction d
 

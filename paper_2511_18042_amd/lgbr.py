@@ -21,7 +21,7 @@ SCHEMES = {'cgbr': SCHEME_CGBR, 'lad': SCHEME_LAD, 'hybrid': SCHEME_HYBRID}
 EXPORTS = ('lg_set_allocator', 'lg_strerror', 'lg_create', 'lg_destroy', 'lg_workspace_bytes',
            'lg_metrics_from_coords', 'cgbr_rhs', 'lad_rhs', 'hybrid_rhs', 'rk3_step', 'lg_rk3_stage',
            'lg_compute_dt', 'lg_batch_create', 'lg_batch_run', 'lg_batch_destroy', 'lg_poll_status',
-           'lg_prof_start', 'lg_prof_stop', 'lg_set_tuning', 'lg_get_tuning')
+           'lg_prof_start', 'lg_prof_stop', 'lg_set_tuning', 'lg_get_tuning', 'lg_metrics_planar')
 KERNEL_CLASSES = ('bc', 'prim', 'flags', 'grad_e6', 'grad_c4', 'sensor', 'visc', 'lad_node', 'lad_raw', 'gauss',
                   'lad_flux', 'sweep_x', 'sweep_y', 'sweep_z', 'combine', 'dt', 'bc_scalar', 'lad_sweep')
 
@@ -63,6 +63,7 @@ def load():
                           ctypes.POINTER(LgOpts), P]),
         'lg_destroy': (None, [P]),
         'lg_workspace_bytes': (S, [P]),
+        'lg_metrics_planar': (I, [P]),
         'lg_metrics_from_coords': (I, [ctypes.POINTER(LgGrid), P, P, P]),
         'cgbr_rhs': (I, [P, P, P]),
         'lad_rhs': (I, [P, P, P]),
@@ -168,6 +169,9 @@ class Context:
 
     def workspace_bytes(self):
         return int(self._lib.lg_workspace_bytes(self.handle))
+
+    def metrics_planar(self):
+        return bool(self._lib.lg_metrics_planar(self.handle) == 1)
 
     def cgbr_rhs(self, Q, dQ):
         _check(self._lib.cgbr_rhs(self.handle, _ptr(Q), _ptr(dQ)), 'cgbr_rhs')

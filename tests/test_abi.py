@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     src = open(os.path.join(ROOT, 'include', 'lgbr.h')).read()
     src = re.sub(r'/\*.*?\*/', '', src, flags=re.S)
-    names = re.findall(r'^\s*(?:lg_status|void|size_t|const char\*)\s+\**\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(',
+    names = re.findall(r'^\s*(?:lg_status|void|size_t|int|const char\*)\s+\**\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(',
                        src, flags=re.M)
     return sorted(set(names))
 

@@ -331,3 +331,32 @@ def test_launch_tuning_leaves_results_bitwise_unchanged(tmp_path, monkeypatch):
     assert autotune.tune(ctx, Q0, 'hybrid')[0] == best          # served from the cache
     ctx.close()
     torch.cuda.synchronize()
+
+
+def test_planar_metric_storage_matches_full_storage():
+    """The ramp grid is a 2D section extruded spanwise: the library keeps one plane of
+    metrics and grid factors for it.  A copy whose coordinates are perturbed along zeta
+    (1e-6 of the spacing, so the metrics vary with k) is stored in full.  Both right-hand
+    sides meet the oracle's on their own grids, the planar context holds less workspace,
+    and the two agree where the grids agree to 1e-6."""
+    torch = U.torch_mod()
+    c, gas = _ramp_case()
+    opts = orhs.Opts(grad='C4', p_thr=c.extra['p_thr'], hybrid_mode='global')
+    c2 = cases.ramp3d(40, 32, 16)
+    kk = np.arange(c2.coords.shape[1])[:, None, None]
+    c2.coords = c2.coords.copy()
+    c2.coords[0] += 1e-6 * c2.h[0] * np.sin(0.7 * kk) * np.ones_like(c2.coords[0])
+    outs, sizes = [], []
+    for cc in (c, c2):
+        g = U.oracle_grid(cc)
+        ref = orhs.rhs(cc.Q, g, gas, opts, 'hybrid')
+        ctx, _ = U.gpu_context(cc, gas, opts)
+        sizes.append(ctx.workspace_bytes())
+        assert ctx.metrics_planar() == (cc is c)
+        out = U.gpu_rhs(ctx, cc, 'hybrid')
+        U.compare(out, ref, g, U.RHS_RTOL, label='planar' if cc is c else 'full')
+        outs.append(out)
+        ctx.close()
+    assert sizes[0] < sizes[1]
+    g = U.oracle_grid(c)
+    U.compare(outs[1], outs[0], g, 1e-4, label='planar vs perturbed')
