@@ -422,6 +422,44 @@ __global__ void __launch_bounds__(256) k_gauss_z(const Prob* __restrict__ probs,
 }
 
 // ------------------------------------------------------------------ LAD node fluxes
+// What the node flux of any direction needs at one node.
+template <typename R>
+struct LadNode {
+  R w[5], D[5][3];
+  R ri, mu, beta, kappa, E;
+};
+
+// gl: computational E4 derivatives at idx; mt: metrics there; cidx: the image of idx at
+// which the (ghost-imaged) coefficients are read
+template <typename R>
+__device__ __forceinline__ void lad_node_state(const Prob& P, const R* W, const R* C, int idx, int cidx,
+                                               const R mt[10], const R gl[3][5], LadNode<R>& s) {
+  const size_t T = P.total;
+  for (int q = 0; q < 5; ++q) s.w[q] = W[q * T + idx];
+  to_physical(P.ndim, mt, gl, s.D);
+  s.ri = rcp(s.w[0]);
+  R muf, kapf;
+  transport(P, s.ri, s.w[4], muf, kapf);
+  s.mu = muf + C[cidx];
+  s.beta = C[T + cidx];
+  s.kappa = kapf + C[2 * T + cidx];
+  s.E = s.w[4] * R(1.0 / (P.gamma - 1.0)) + R(0.5) * s.w[0] * (s.w[1] * s.w[1] + s.w[2] * s.w[2] + s.w[3] * s.w[3]);
+}
+
+// F^c_l + F^v_l at the node
+template <typename R>
+__device__ __forceinline__ void lad_node_flux(const Prob& P, const LadNode<R>& s, const R mt[10], int l, R out[5]) {
+  const R m0 = mt[3 * l], m1 = mt[3 * l + 1], m2 = mt[3 * l + 2];
+  R F[5];
+  viscous_flux(P, m0, m1, m2, s.w, s.ri, s.D, s.mu, s.beta, s.kappa, F);
+  const R U = m0 * s.w[1] + m1 * s.w[2] + m2 * s.w[3];
+  out[0] = s.w[0] * U + F[0];
+  out[1] = s.w[0] * s.w[1] * U + m0 * s.w[4] + F[1];
+  out[2] = s.w[0] * s.w[2] * U + m1 * s.w[4] + F[2];
+  out[3] = s.w[0] * s.w[3] * U + m2 * s.w[4] + F[3];
+  out[4] = (s.E + s.w[4]) * U + F[4];
+}
+
 // F^c + F^v for every active direction at positions -2 .. n+1; gradients recomputed from
 // W, coefficients read at the image of the node
 template <typename R>
@@ -447,28 +485,15 @@ __global__ void __launch_bounds__(256) k_lad_nodeflux(const Prob* __restrict__ p
   for (int k = c.k0; k < c.k1; ++k, idx += sz) {
     if (z3) qz.step(W, T, idx, sz);
     if (!mplane) load_met(P, idx, mt);
-    R w[5];
-    for (int q = 0; q < 5; ++q) w[q] = W[q * T + idx];
-    R gl[3][5], D[5][3];
+    R gl[3][5];
     e4_grads_zm(P, W, idx, qz, gl);
-    to_physical(P.ndim, mt, gl, D);
-    const int cidx = pos_to_idx(P, ci, cj, z3 ? scalar_image(P, 2, k) : k);
-    const R ri = rcp(w[0]);
-    R muf, kapf;
-    transport(P, ri, w[4], muf, kapf);
-    R mu = muf + C[cidx], beta = C[T + cidx], kappa = kapf + C[2 * T + cidx];
-    R E = w[4] * R(1.0 / (P.gamma - 1.0)) + R(0.5) * w[0] * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
+    LadNode<R> s;
+    lad_node_state(P, W, C, idx, pos_to_idx(P, ci, cj, z3 ? scalar_image(P, 2, k) : k), mt, gl, s);
     for (int l = 0; l < P.ndim; ++l) {
-      const R m0 = mt[3 * l], m1 = mt[3 * l + 1], m2 = mt[3 * l + 2];
       R F[5];
-      viscous_flux(P, m0, m1, m2, w, ri, D, mu, beta, kappa, F);
-      R U = m0 * w[1] + m1 * w[2] + m2 * w[3];
+      lad_node_flux(P, s, mt, l, F);
       R* out = static_cast<R*>(P.FL[l]);
-      out[idx] = w[0] * U + F[0];
-      out[T + idx] = w[0] * w[1] * U + m0 * w[4] + F[1];
-      out[2 * T + idx] = w[0] * w[2] * U + m1 * w[4] + F[2];
-      out[3 * T + idx] = w[0] * w[3] * U + m2 * w[4] + F[3];
-      out[4 * T + idx] = (E + w[4]) * U + F[4];
+      for (int q = 0; q < 5; ++q) out[q * T + idx] = F[q];
     }
   }
 }
@@ -622,14 +647,18 @@ void launch_lad(const Launch& L, int skip_if_any) {
   constexpr int GTY = sizeof(R) == 4 ? 16 : 8;
   LG_TIMED(L, KC_GAUSS, hipLaunchKernelGGL((k_gauss_xy<R, GTY>), zm_grid(L, 0, 0, 64, GTY), dim3(256), 0, L.stream,
                                            L.probs, skip_if_any, zi));
-  int coef = 1;
-  if (L.ndim > 2) {
+  if (L.ndim > 2)
     LG_TIMED(L, KC_GAUSS, hipLaunchKernelGGL(k_gauss_z<R>, zm_grid(L, 0, 0, ZM_TX, ZM_TY), dim3(256), 0, L.stream,
                                              L.probs, skip_if_any, zi));
-    coef = 0;
-  }
+}
+
+// the filtered coefficients end in CA after the zeta pass (3D), in CB otherwise
+static inline int lad_coef_buf(const Launch& L) { return L.ndim > 2 ? 0 : 1; }
+
+template <typename R>
+void launch_lad_nodeflux(const Launch& L, int skip_if_any) {
   LG_TIMED(L, KC_LAD_FLUX, hipLaunchKernelGGL(k_lad_nodeflux<R>, zm_grid(L, -2, 2, ZM_TX, ZM_TY), dim3(256), 0,
-                                              L.stream, L.probs, coef, skip_if_any, zb));
+                                              L.stream, L.probs, lad_coef_buf(L), skip_if_any, zm_chunk(L, -2, 2)));
 }
 
 template <typename R>
@@ -660,6 +689,8 @@ template void launch_lad_geometry<float>(const Launch&);
 template void launch_lad_geometry<double>(const Launch&);
 template void launch_lad_sweep<float>(const Launch&, StateRef, const RKRef*, int, double, double, int);
 template void launch_lad_sweep<double>(const Launch&, StateRef, const RKRef*, int, double, double, int);
+template void launch_lad_nodeflux<float>(const Launch&, int);
+template void launch_lad_nodeflux<double>(const Launch&, int);
 template void launch_gbr_viscflux<float>(const Launch&, int, int);
 template void launch_gbr_viscflux<double>(const Launch&, int, int);
 

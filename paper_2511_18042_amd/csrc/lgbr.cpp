@@ -132,7 +132,10 @@ void enqueue_rhs(const Launch& L, const Cfg& c, int scheme, StateRef ref, const 
       lg::launch_gbr_viscflux<R>(L, skip_gbr, region);
     }
   }
-  if (sel != lg::SEL_GBR) lg::launch_lad<R>(L, skip_lad);
+  if (sel != lg::SEL_GBR) {
+    lg::launch_lad<R>(L, skip_lad);
+    lg::launch_lad_nodeflux<R>(L, skip_lad);
+  }
   // interfaces: the all-LAD pass (LAD scheme; hybrid with no troubled node), else the
   // per-direction sweeps that pick C-GBR or LAD per interface; the hybrid decides on the
   // device, so both are launched and each returns at once when the other applies

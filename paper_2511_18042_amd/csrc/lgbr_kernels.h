@@ -130,8 +130,9 @@ template <typename R> void launch_grad_c4(const Launch& L, StateRef ref, int d, 
 // sensor and C-GBR viscous node fluxes
 template <typename R> void launch_sensor(const Launch& L, int skip_if_any, int region);
 template <typename R> void launch_gbr_viscflux(const Launch& L, int skip_if_any, int region);
-// LAD: coefficients and node fluxes; the grid factors Delta x_l once per context
+// LAD: filtered coefficients; node fluxes; the grid factors Delta x_l once per context
 template <typename R> void launch_lad(const Launch& L, int skip_if_any);
+template <typename R> void launch_lad_nodeflux(const Launch& L, int skip_if_any);
 template <typename R> void launch_lad_geometry(const Launch& L);
 // all-LAD interfaces of every direction in one pass; rr == nullptr writes the time
 // derivative, else the RK stage combination (and the ghost copy of the stage result)
