@@ -178,46 +178,6 @@ __global__ void k_zero_lcount(const Prob* __restrict__ probs) {
   if (threadIdx.x < 3) P.lcount[threadIdx.x] = 0;
 }
 
-// ------------------------------------------------------------------ RK3 combination
-// out = a U^n + b (U^s + dt L) on interior nodes, out = U^n on ghost nodes; counts
-// non-physical interior results (rho <= 0, p <= 0 or not finite).
-__global__ void __launch_bounds__(256) k_combine(const Prob* __restrict__ probs, RKRef rr, int stage, double a, double b,
-                                                 int skip_if_any) {
-  const Prob& P = probs[blockIdx.y];
-  if (gate_skip(P, skip_if_any)) return;
-  const double* Un = rr.Un ? rr.Un : P.Q;
-  const double* Us = rr.Us ? rr.Us : (stage == 0 ? Un : P.Us);
-  double* out = rr.out ? rr.out : (stage == 2 ? const_cast<double*>(Un) : P.Us);
-  const bool in_place_n = out == Un;
-  const double* L = P.dQ;
-  const double dt = *P.dt;
-  const size_t T = P.total;
-  int bad = 0;
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < P.total; idx += gridDim.x * blockDim.x) {
-    int i = idx % P.N[0], r = idx / P.N[0];
-    int j = r % P.N[1], k = r / P.N[1];
-    bool inner = i >= P.g[0] && i < P.g[0] + P.n[0] && j >= P.g[1] && j < P.g[1] + P.n[1] &&
-                 k >= P.g[2] && k < P.g[2] + P.n[2];
-    double v[5];
-    for (int q = 0; q < 5; ++q) {
-      size_t o = q * T + idx;
-      v[q] = inner ? a * Un[o] + b * (Us[o] + dt * L[o]) : Un[o];
-      if (!in_place_n || inner) out[o] = v[q];
-    }
-    if (inner) {
-      double rho = v[0];
-      double ke = 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / rho;
-      double p = (P.gamma - 1.0) * (v[4] - ke);
-      bool ok = rho > 0.0 && p > 0.0 && isfinite(rho) && isfinite(p) && isfinite(v[1]) &&
-                isfinite(v[2]) && isfinite(v[3]);
-      if (!ok) ++bad;
-    }
-  }
-  // one atomic per wave
-  for (int off = 32; off > 0; off >>= 1) bad += __shfl_down(bad, off);
-  if ((threadIdx.x & 63) == 0 && bad) atomicAdd(P.status, bad);
-}
-
 // ------------------------------------------------------------------ CFL time step
 // Spectral radius sum_l (|xi_l . u| + c |xi_l|) with xi_l = J l_hat, max over the
 // interior; kept as the bit pattern of a positive double so that an integer max works.
@@ -465,11 +425,6 @@ void launch_line_lists(const Launch& L, int ndim) {
     LG_TIMED(L, KC_FLAGS, hipLaunchKernelGGL(k_line_list, dim3((unsigned)(b < 1 ? 1 : b), L.nprob), dim3(256), 0,
                                              L.stream, L.probs, d));
   }
-}
-
-void launch_combine(const Launch& L, RKRef rr, int stage, double a, double b, int skip_if_any) {
-  LG_TIMED(L, KC_COMBINE, hipLaunchKernelGGL(k_combine, grid_for(L.max_total, L.nprob), dim3(256), 0, L.stream,
-                                             L.probs, rr, stage, a, b, skip_if_any));
 }
 
 void launch_dt(const Launch& L, const double* Qx, double* tx, double t_end, int advance_t) {

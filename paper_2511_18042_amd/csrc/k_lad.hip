@@ -522,9 +522,6 @@ __global__ void __launch_bounds__(256) k_lad_sweep(const Prob* __restrict__ prob
   const R* Fy = P.ndim > 1 ? static_cast<const R*>(P.FL[1]) : nullptr;
   const R* Fz = z3 ? static_cast<const R*>(P.FL[2]) : nullptr;
   double* dQ = ref.deriv(P);
-  const double* Un = rr.Un ? rr.Un : P.Q;
-  const double* Us = rr.Us ? rr.Us : (stage == 0 ? Un : P.Us);
-  double* out = rr.out ? rr.out : (stage == 2 ? const_cast<double*>(Un) : P.Us);
   const double dt = mode ? *P.dt : 0.0;
   int bad = 0;
   int idx = pos_to_idx(P, c.i, c.j, c.k0);
@@ -558,19 +555,8 @@ __global__ void __launch_bounds__(256) k_lad_sweep(const Prob* __restrict__ prob
     }
     if (mode == 0) {
       for (int q = 0; q < 5; ++q) dQ[q * T + idx] = Lq[q];
-    } else {
-      double v[5];
-      for (int q = 0; q < 5; ++q) {
-        const size_t o = q * T + idx;
-        v[q] = a * Un[o] + b * (Us[o] + dt * Lq[q]);
-        out[o] = v[q];
-      }
-      const double rho = v[0];
-      const double ke = 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / rho;
-      const double pr = (P.gamma - 1.0) * (v[4] - ke);
-      const bool ok = rho > 0.0 && pr > 0.0 && isfinite(rho) && isfinite(pr) && isfinite(v[1]) &&
-                      isfinite(v[2]) && isfinite(v[3]);
-      if (!ok) ++bad;
+    } else if (rk_combine_node(P, rr, stage, a, b, dt, idx, Lq)) {
+      ++bad;
     }
   }
   if (bad) atomicAdd(P.status, bad);
@@ -672,9 +658,13 @@ void launch_lad_sweep(const Launch& L, StateRef ref, const RKRef* rr, int stage,
   LG_TIMED(L, KC_LAD_SWEEP, hipLaunchKernelGGL(k_lad_sweep<R>, zm_grid(L, 0, 0, ZM_TX, ZM_TY), dim3(256), 0,
                                                L.stream, L.probs, ref, r, rr ? 1 : 0, stage, a, b, skip_if_any,
                                                zm_chunk(L, 0, 0)));
-  if (rr && (rr->out || L.has_fixed))
-    LG_TIMED(L, KC_COMBINE, hipLaunchKernelGGL(k_stage_ghosts, g1(L.max_total, L.nprob), dim3(256), 0, L.stream,
-                                               L.probs, r, stage, skip_if_any));
+  if (rr) launch_stage_ghosts(L, *rr, stage, skip_if_any);
+}
+
+void launch_stage_ghosts(const Launch& L, const RKRef& rr, int stage, int skip_if_any) {
+  if (!rr.out && !L.has_fixed) return;
+  LG_TIMED(L, KC_COMBINE, hipLaunchKernelGGL(k_stage_ghosts, g1(L.max_total, L.nprob), dim3(256), 0, L.stream,
+                                             L.probs, rr, stage, skip_if_any));
 }
 
 template <typename R>

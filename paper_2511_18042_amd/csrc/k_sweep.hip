@@ -293,9 +293,11 @@ __device__ __forceinline__ double node_J(const Prob& P, int idx) { return met64(
 // ------------------------------------------------------------------ x sweep: one wave per
 // row segment of 63 nodes; lane t computes the interface left of node (seg*63 + t - 1) + 1
 // and the flux difference uses the neighbour lane's flux.
+// With rk = 1 the sweep is the last direction's: it adds its differences to the partial
+// derivative and forms the RK stage result at once (the combination kernel's work).
 template <typename R>
 __global__ void __launch_bounds__(256) k_sweep_x(const Prob* __restrict__ probs, StateRef ref, int sel, int accumulate,
-                                                 int skip_if_any) {
+                                                 int skip_if_any, int rk, RKRef rr, int stage, double ca, double cb) {
   const Prob& P = probs[blockIdx.y];
   if (gate_skip(P, skip_if_any)) return;
   const int lane = threadIdx.x & 63;
@@ -317,11 +319,14 @@ __global__ void __launch_bounds__(256) k_sweep_x(const Prob* __restrict__ probs,
   for (int q = 0; q < 5; ++q) Fp[q] = (double)__shfl_up(F[q], 1);
   if (lane >= 1 && valid) {
     double J = node_J(P, idx);
+    double Lq[5];
     for (int q = 0; q < 5; ++q) {
       double v = -J * ((double)F[q] - Fp[q]);
       size_t o = q * T + idx;
-      dQ[o] = accumulate ? dQ[o] + v : v;
+      Lq[q] = accumulate ? dQ[o] + v : v;
+      if (!rk) dQ[o] = Lq[q];
     }
+    if (rk && rk_combine_node(P, rr, stage, ca, cb, *P.dt, idx, Lq)) atomicAdd(P.status, 1);
   }
 }
 
@@ -329,7 +334,8 @@ __global__ void __launch_bounds__(256) k_sweep_x(const Prob* __restrict__ probs,
 // lane per line segment of `seg` nodes, sliding along the line.
 template <typename R>
 __global__ void __launch_bounds__(256) k_sweep_s(const Prob* __restrict__ probs, StateRef ref, int d, int sel,
-                                                 int accumulate, int seg, int skip_if_any) {
+                                                 int accumulate, int seg, int skip_if_any, int rk, RKRef rr, int stage,
+                                                 double ca, double cb) {
   const Prob& P = probs[blockIdx.y];
   if (d >= P.ndim || gate_skip(P, skip_if_any)) return;
   const int o2 = d == 1 ? 2 : 1;
@@ -348,22 +354,27 @@ __global__ void __launch_bounds__(256) k_sweep_s(const Prob* __restrict__ probs,
   const int s = P.s[d];
   const size_t T = P.total;
   double* dQ = ref.deriv(P);
-  R F[5];
-  interface_flux(P, d, idx, sel, F);
+  const double dt = rk ? *P.dt : 0.0;
+  int bad = 0;
+  // one flux evaluation site: interface p + 1/2 at node p, for p = start - 1 .. end - 1
   double Fp[5];
-  for (int q = 0; q < 5; ++q) Fp[q] = (double)F[q];
-  for (int p = start; p < end; ++p) {
-    idx += s;
+  for (int p = start - 1; p < end; ++p, idx += s) {
+    R F[5];
     interface_flux(P, d, idx, sel, F);
-    double J = node_J(P, idx);
-    for (int q = 0; q < 5; ++q) {
-      double fq = (double)F[q];
-      double v = -J * (fq - Fp[q]);
-      size_t o = q * T + idx;
-      dQ[o] = accumulate ? dQ[o] + v : v;
-      Fp[q] = fq;
+    if (p >= start) {
+      const double J = node_J(P, idx);
+      double Lq[5];
+      for (int q = 0; q < 5; ++q) {
+        const double v = -J * ((double)F[q] - Fp[q]);
+        const size_t o = q * T + idx;
+        Lq[q] = accumulate ? dQ[o] + v : v;
+        if (!rk) dQ[o] = Lq[q];
+      }
+      if (rk && rk_combine_node(P, rr, stage, ca, cb, dt, idx, Lq)) ++bad;
     }
+    for (int q = 0; q < 5; ++q) Fp[q] = (double)F[q];
   }
+  if (bad) atomicAdd(P.status, bad);
 }
 
 template <typename R>
@@ -389,14 +400,17 @@ int sweep_seg(const Launch& L, int d) {
 }
 
 template <typename R>
-void launch_sweep(const Launch& L, StateRef ref, int d, int sel, int accumulate, int skip_if_any) {
+void launch_sweep(const Launch& L, StateRef ref, int d, int sel, int accumulate, int skip_if_any, const RKRef* rr,
+                  int stage, double a, double b) {
+  const RKRef r = rr ? *rr : RKRef{nullptr, nullptr, nullptr};
+  const int rk = rr ? 1 : 0;
   if (d == 0) {
     long long nseg = (L.max_n[0] + 62) / 63;
     long long waves = nseg * L.sweep_rows[0];
     long long blocks = (waves + 3) / 4;
     if (blocks < 1) blocks = 1;
     LG_TIMED(L, KC_SWEEP_X, hipLaunchKernelGGL(k_sweep_x<R>, dim3((unsigned)blocks, L.nprob), dim3(256), 0,
-                                               L.stream, L.probs, ref, sel, accumulate, skip_if_any));
+                                               L.stream, L.probs, ref, sel, accumulate, skip_if_any, rk, r, stage, a, b));
   } else {
     const int seg = sweep_seg(L, d);
     long long nch = (L.max_n[d] + seg - 1) / seg;
@@ -405,13 +419,13 @@ void launch_sweep(const Launch& L, StateRef ref, int d, int sel, int accumulate,
     if (blocks < 1) blocks = 1;
     LG_TIMED(L, d == 1 ? KC_SWEEP_Y : KC_SWEEP_Z,
              hipLaunchKernelGGL(k_sweep_s<R>, dim3((unsigned)blocks, L.nprob), dim3(256), 0, L.stream, L.probs, ref,
-                                d, sel, accumulate, seg, skip_if_any));
+                                d, sel, accumulate, seg, skip_if_any, rk, r, stage, a, b));
   }
 }
 
 template void launch_sensor<float>(const Launch&, int, int);
 template void launch_sensor<double>(const Launch&, int, int);
-template void launch_sweep<float>(const Launch&, StateRef, int, int, int, int);
-template void launch_sweep<double>(const Launch&, StateRef, int, int, int, int);
+template void launch_sweep<float>(const Launch&, StateRef, int, int, int, int, const RKRef*, int, double, double);
+template void launch_sweep<double>(const Launch&, StateRef, int, int, int, int, const RKRef*, int, double, double);
 
 }  // namespace lg

@@ -144,8 +144,10 @@ void enqueue_rhs(const Launch& L, const Cfg& c, int scheme, StateRef ref, const 
   const int skip_dir = sel == lg::SEL_GBR ? -1 : 0;
   if (sel != lg::SEL_GBR) lg::launch_lad_sweep<R>(L, ref, rk, stage, a, b, skip_fused);
   if (sel != lg::SEL_LAD) {
-    for (int d = 0; d < c.ndim; ++d) lg::launch_sweep<R>(L, ref, d, sel, d > 0 ? 1 : 0, skip_dir);
-    if (rk) lg::launch_combine(L, *rk, stage, a, b, skip_dir);
+    // the last direction's sweep forms the RK stage itself
+    for (int d = 0; d < c.ndim; ++d)
+      lg::launch_sweep<R>(L, ref, d, sel, d > 0 ? 1 : 0, skip_dir, d == c.ndim - 1 ? rk : nullptr, stage, a, b);
+    if (rk) lg::launch_stage_ghosts(L, *rk, stage, skip_dir);
   }
 }
 

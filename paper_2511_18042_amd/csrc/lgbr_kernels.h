@@ -23,6 +23,28 @@ struct RKRef {
   double* out;
 };
 
+// Stage result at interior node idx: out = a U^n + b (U^s + dt L); true if non-physical
+// (rho <= 0, p <= 0 or not finite).  U^s may alias out (each node reads before it writes).
+__device__ __forceinline__ bool rk_combine_node(const Prob& P, const RKRef& rr, int stage, double a, double b,
+                                                double dt, int idx, const double L[5]) {
+  const double* Un = rr.Un ? rr.Un : P.Q;
+  const double* Us = rr.Us ? rr.Us : (stage == 0 ? Un : P.Us);
+  double* out = rr.out ? rr.out : (stage == 2 ? const_cast<double*>(Un) : P.Us);
+  const size_t T = P.total;
+  double v[5];
+  for (int q = 0; q < 5; ++q) {
+    const size_t o = q * T + idx;
+    v[q] = a * Un[o] + b * (Us[o] + dt * L[q]);
+    out[o] = v[q];
+  }
+  const double rho = v[0];
+  const double ke = 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / rho;
+  const double p = (P.gamma - 1.0) * (v[4] - ke);
+  const bool ok = rho > 0.0 && p > 0.0 && isfinite(rho) && isfinite(p) && isfinite(v[1]) && isfinite(v[2]) &&
+                  isfinite(v[3]);
+  return !ok;
+}
+
 // Kernel classes for the optional per-launch event timing (lg_prof_start / lg_prof_stop).
 enum KClass {
   KC_BC = 0, KC_PRIM, KC_FLAGS, KC_GRAD_E6, KC_GRAD_C4, KC_SENSOR, KC_VISC, KC_LAD_NODE, KC_LAD_RAW,
@@ -96,7 +118,6 @@ template <typename R> void launch_prim(const Launch& L, StateRef ref, int want_f
 void launch_any_flag(const Launch& L, int interior_only);
 void launch_dilate(const Launch& L, int ndim, int radius, int first_src, int final_buf);
 void launch_line_lists(const Launch& L, int ndim);
-void launch_combine(const Launch& L, RKRef rr, int stage, double a, double b, int skip_if_any);
 void launch_dt(const Launch& L, const double* Qx, double* tx, double t_end, int advance_t);
 void launch_set_dt(const Launch& L, double dt);
 void launch_zero_status(const Launch& L);
@@ -139,6 +160,11 @@ template <typename R> void launch_lad_geometry(const Launch& L);
 template <typename R>
 void launch_lad_sweep(const Launch& L, StateRef ref, const RKRef* rr, int stage, double a, double b, int skip_if_any);
 // interface sweeps
-template <typename R> void launch_sweep(const Launch& L, StateRef ref, int d, int sel, int accumulate, int skip_if_any);
+// rr != nullptr: this is the last direction and the sweep also forms the RK stage (and the
+// ghost copy of the stage result)
+template <typename R>
+void launch_sweep(const Launch& L, StateRef ref, int d, int sel, int accumulate, int skip_if_any,
+                  const RKRef* rr = nullptr, int stage = 0, double a = 0.0, double b = 0.0);
+void launch_stage_ghosts(const Launch& L, const RKRef& rr, int stage, int skip_if_any);
 
 }  // namespace lg
