@@ -78,8 +78,20 @@ __device__ __forceinline__ double prim_q(int q, const double* Q, size_t T, size_
   return gm1 * (Q[4 * T + o] - 0.5 * rho * (u * u + v * v + w * w));
 }
 
-// One lane per (line, primitive variable): forward elimination stores d' in the FP64
-// scratch, back substitution writes the gradient.
+// all five FP64 primitives at offset o (one reciprocal of rho)
+__device__ __forceinline__ void prims5(const double* Q, size_t T, size_t o, double gm1, double w[5]) {
+  const double rho = Q[o], ri = 1.0 / rho;
+  const double u = Q[T + o] * ri, v = Q[2 * T + o] * ri, x = Q[3 * T + o] * ri;
+  w[0] = rho;
+  w[1] = u;
+  w[2] = v;
+  w[3] = x;
+  w[4] = gm1 * (Q[4 * T + o] - 0.5 * rho * (u * u + v * v + x * x));
+}
+
+// One lane per line, all five primitives at once (the state is read once per node):
+// forward elimination stores d' in the FP64 scratch, back substitution writes the
+// gradients.
 template <typename R>
 __global__ void __launch_bounds__(256) k_grad_c4(const Prob* __restrict__ probs, StateRef ref, int d, int skip_if_any,
                                                  int region) {
@@ -90,40 +102,53 @@ __global__ void __launch_bounds__(256) k_grad_c4(const Prob* __restrict__ probs,
   const int nlines = P.N[o1] * P.N[o2];
   const int cnt = region ? P.lcount[d] : nlines;   // compacted list of lines that need solving
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 5 * cnt) return;
-  const int line = region ? P.llist[d][t % cnt] : t % nlines, q = t / cnt;
+  if (t >= cnt) return;
+  const int line = region ? P.llist[d][t] : t;
   const double* Q = ref.state(P);
-  R* G = static_cast<R*>(P.G[d]) + (size_t)q * P.total;
+  R* G = static_cast<R*>(P.G[d]);
   const size_t T = P.total;
-  double* S = P.T64 + (size_t)q * T;
+  double* S = P.T64;
   const double* tab = P.tri[d];
   const int a = line % P.N[o1], b = line / P.N[o1];
   const size_t base = (size_t)a * P.s[o1] + (size_t)b * P.s[o2];
   const int sd = P.s[d], g = P.g[d], n = P.n[d], N = P.N[d];
   const double gm1 = P.gamma - 1.0;
-  auto f = [&](int pos) { return prim_q(q, Q, T, base + (size_t)pos * sd, gm1); };
+  auto f = [&](int pos, double w[5]) { prims5(Q, T, base + (size_t)pos * sd, gm1, w); };
 
   if (P.bc[d][0] != BC_PERIODIC) {
     const double* cp = tab;
     const double* inv = tab + N;
-    double fm = f(0), f0 = f(1), fp;
-    double dprev = (-3.0 * fm + 4.0 * f0 - f(2)) / 2.0;   // row 0 (one-sided, decoupled)
-    S[base] = dprev;
+    double fm[5], f0[5], fp[5], dprev[5];
+    f(0, fm);
+    f(1, f0);
+    f(2, fp);
+    for (int q = 0; q < 5; ++q) {
+      dprev[q] = (-3.0 * fm[q] + 4.0 * f0[q] - fp[q]) / 2.0;   // row 0 (one-sided, decoupled)
+      S[q * T + base] = dprev[q];
+    }
+    double fmm[5];   // f(N-3) once the sweep ends
     for (int i = 1; i < N - 1; ++i) {
-      fp = f(i + 1);
-      double dd = (0.75 * (fp - fm) - 0.25 * dprev) * inv[i];
-      S[base + (size_t)i * sd] = dd;
-      dprev = dd;
-      fm = f0;
-      f0 = fp;
+      if (i > 1) f(i + 1, fp);
+      for (int q = 0; q < 5; ++q) {
+        const double dd = (0.75 * (fp[q] - fm[q]) - 0.25 * dprev[q]) * inv[i];
+        S[q * T + base + (size_t)i * sd] = dd;
+        dprev[q] = dd;
+        fmm[q] = fm[q];
+        fm[q] = f0[q];
+        f0[q] = fp[q];
+      }
     }
-    // last row (one-sided, decoupled): f0 = f(N-1), fm = f(N-2)
-    double y = (3.0 * f0 - 4.0 * fm + f(N - 3)) / 2.0;
-    G[base + (size_t)(N - 1) * sd] = (R)y;
-    for (int i = N - 2; i >= 0; --i) {
-      y = S[base + (size_t)i * sd] - cp[i] * y;
-      G[base + (size_t)i * sd] = (R)y;
+    // last row (one-sided, decoupled): f0 = f(N-1), fm = f(N-2), fmm = f(N-3)
+    double y[5];
+    for (int q = 0; q < 5; ++q) {
+      y[q] = (3.0 * f0[q] - 4.0 * fm[q] + fmm[q]) / 2.0;
+      G[q * T + base + (size_t)(N - 1) * sd] = (R)y[q];
     }
+    for (int i = N - 2; i >= 0; --i)
+      for (int q = 0; q < 5; ++q) {
+        y[q] = S[q * T + base + (size_t)i * sd] - cp[i] * y[q];
+        G[q * T + base + (size_t)i * sd] = (R)y[q];
+      }
   } else {
     // cyclic system over the interior (the ghosts hold the periodic images):
     // B y = r, x = y - (v.y) fac z with v.y = y_0 - y_{n-1}/4 (Sherman-Morrison)
@@ -132,29 +157,37 @@ __global__ void __launch_bounds__(256) k_grad_c4(const Prob* __restrict__ probs,
     const double* z = tab + 2 * n;
     const double fac = tab[3 * n];
     const size_t b0 = base + (size_t)g * sd;
-    double fm = f(g - 1), f0 = f(g), fp, dprev = 0.0;
+    double fm[5], f0[5], fp[5], dprev[5];
+    f(g - 1, fm);
+    f(g, f0);
     for (int i = 0; i < n; ++i) {
-      fp = f(g + i + 1);
-      double rhs = 0.75 * (fp - fm);
-      double dd = (i == 0 ? rhs : rhs - 0.25 * dprev) * inv[i];
-      S[b0 + (size_t)i * sd] = dd;
-      dprev = dd;
-      fm = f0;
-      f0 = fp;
+      f(g + i + 1, fp);
+      for (int q = 0; q < 5; ++q) {
+        const double rhs = 0.75 * (fp[q] - fm[q]);
+        const double dd = (i == 0 ? rhs : rhs - 0.25 * dprev[q]) * inv[i];
+        S[q * T + b0 + (size_t)i * sd] = dd;
+        dprev[q] = dd;
+        fm[q] = f0[q];
+        f0[q] = fp[q];
+      }
     }
-    double y = dprev, ylast = dprev;
-    for (int i = n - 2; i >= 0; --i) {
-      y = S[b0 + (size_t)i * sd] - cp[i] * y;
-      S[b0 + (size_t)i * sd] = y;
-    }
-    const double vy = (y - 0.25 * ylast) * fac;
-    for (int i = 0; i < n; ++i) {
-      double yi = (i == n - 1) ? ylast : S[b0 + (size_t)i * sd];
-      R xv = (R)(yi - vy * z[i]);
-      G[b0 + (size_t)i * sd] = xv;
-      if (i >= n - g) G[b0 + (size_t)(i - n) * sd] = xv;   // low ghosts
-      if (i < g) G[b0 + (size_t)(i + n) * sd] = xv;        // high ghosts
-    }
+    double y[5], ylast[5];
+    for (int q = 0; q < 5; ++q) y[q] = ylast[q] = dprev[q];
+    for (int i = n - 2; i >= 0; --i)
+      for (int q = 0; q < 5; ++q) {
+        y[q] = S[q * T + b0 + (size_t)i * sd] - cp[i] * y[q];
+        S[q * T + b0 + (size_t)i * sd] = y[q];
+      }
+    double vy[5];
+    for (int q = 0; q < 5; ++q) vy[q] = (y[q] - 0.25 * ylast[q]) * fac;
+    for (int i = 0; i < n; ++i)
+      for (int q = 0; q < 5; ++q) {
+        const double yi = (i == n - 1) ? ylast[q] : S[q * T + b0 + (size_t)i * sd];
+        const R xv = (R)(yi - vy[q] * z[i]);
+        G[q * T + b0 + (size_t)i * sd] = xv;
+        if (i >= n - g) G[q * T + b0 + (size_t)(i - n) * sd] = xv;   // low ghosts
+        if (i < g) G[q * T + b0 + (size_t)(i + n) * sd] = xv;        // high ghosts
+      }
   }
 }
 
@@ -280,7 +313,7 @@ void launch_grad_c4(const Launch& L, StateRef ref, int d, int skip_if_any, int r
                                                L.stream, L.probs, ref, d, skip_if_any, region));
   }
   if (L.thomas_dir[d]) {
-    long long b = (5 * L.lines[d] + 255) / 256;
+    long long b = (L.lines[d] + 255) / 256;
     LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c4<R>, dim3((unsigned)b, L.nprob), dim3(256), 0, L.stream,
                                                L.probs, ref, d, skip_if_any, region));
   }
