@@ -10,24 +10,26 @@ computes, in float64, step by step in the paper's order:
 
 * ``grid``         -- node layout, ghost layers and boundary images, grid metrics
                       (governing equations, Sec. 2.1)
-* ``derivatives``  -- explicit E6 / E4 and compact (tridiagonal) C4 first
+* ``derivatives``  -- explicit E6 / E4 and compact (tridiagonal) C4 / C6 first
                       derivatives of the primitives (Sec. 2.3, the MEG6 / MIG4
-                      gradients; Sec. 4.2 LAD-E4)
+                      gradients; Sec. 4.2 LAD-E4; Sec. 3 LAD-C6)
 * ``gbr``          -- characteristic transform, gradient-based linear interface
                       states, centralised interpolation, MP5 limiter, the
                       wave-appropriate selection rule, the Omega sensor and the
                       curvilinear HLLC flux (Sec. 2.3)
 * ``lad``          -- localized artificial diffusivity coefficients, truncated
-                      Gaussian filter, central convective + viscous fluxes
-                      (Sec. 2.2, Eq. tauij)
+                      Gaussian filter, central convective + viscous fluxes in
+                      E4 or compact C6 flux form (Sec. 2.2, Eq. tauij)
+* ``implicit_filter`` -- the implicit Pade-type filter of LAD-C6 steps (Sec. 2.1,
+                      Alg. 1 FILTER_CALLS)
 * ``rhs``          -- the three RHS forms (C-GBR, LAD, hybrid; Alg. 1-3), the
                       CFL time step and SSP-RK3
 * ``riemann``      -- exact Riemann solver for the 1D shock-tube checks (Sec. 3.1)
 
-Where the paper is silent the oracle follows the numbered readings R1..R25 that
+Where the paper is silent the oracle follows the numbered readings R1..R29 that
 are listed in the design notes; each function names the reading it relies on.
 
 Parity pins: every function is pinned by a ``-m "not gpu"`` test against a
 closed form, an invariant, brute force or a textbook value (tests/test_oracle_*.py).
 """
-from . import grid, derivatives, gbr, lad, rhs, riemann  # noqa: F401
+from . import grid, derivatives, gbr, lad, implicit_filter, rhs, riemann  # noqa: F401

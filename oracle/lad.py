@@ -8,7 +8,9 @@ coordinates) and Sec. 2.1 (viscous flux vectors, Sutherland law, Stokes
 hypothesis, kappa_hat = mu_hat / ((gamma-1) Pr M^2), p = rho T / (gamma M^2)).
 The LAD form of the hybrid uses explicit fourth-order central differences (E4,
 Sec. 5); written in flux form, the E4 derivative of a node flux is the difference
-of its fourth-order interface interpolation I4.
+of its fourth-order interface interpolation I4.  The paper's stand-alone LAD scheme
+uses sixth-order compact central differences (LAD-C6, Sec. 3 and Alg. 1), whose flux
+form is a tridiagonal system for the interface fluxes (R28).
 
 Readings used here:
   R9   5-point fourth difference for d^4/dxi^4 Delta xi^4; |S| = sqrt(S_ij S_ij);
@@ -21,12 +23,21 @@ Readings used here:
        gradients, I4 to the interface, then differenced.
   R13  ghost images of intermediate scalar fields (even parity).
   R15  T = gamma M^2 p / rho with M = 1 for inviscid runs.
+  R28  LAD-C6: the primitives' gradients are C6 (R27); the interface fluxes F_{i+1/2}
+       of a line solve
+         (1/3) F_{i-1/2} + F_{i+1/2} + (1/3) F_{i+3/2}
+             = (29/36) (F_i + F_{i+1}) + (1/36) (F_{i-1} + F_{i+2}),
+       whose differences satisfy the C6 relation for the node derivative exactly
+       (subtract the rows of i+1/2 and i-1/2).  A bounded line takes the two
+       boundary faces -1/2 and n-1/2 from I4 (known values of the system), so the
+       scheme stays conservative; a periodic line is cyclic over its n faces.
 """
 from fractions import Fraction
 
 import numpy as np
+import scipy.linalg
 
-from .grid import shift, fill_ghosts_scalar, delta_x, i4
+from .grid import shift, fill_ghosts_scalar, delta_x, i4, axis_of
 
 # Truncated-Gaussian weights for offsets 0, +-1, ..., +-4 (Kawai & Lele 2008).
 GAUSS_FRAC = (Fraction(3565, 10368), Fraction(3091, 12960), Fraction(1997, 25920),
@@ -170,13 +181,61 @@ def lad_coefficients(W, G4, M, grid, gas, opts, raw_only=False):
     return out
 
 
-def lad_interface_flux(W, G4, M, d, grid, gas, coef, mu_f, kappa_f):
-    """LAD-E4 interface flux along d at i+1/2 (stored at node i):
-    I4 of the node convective + viscous flux with mu = mu_f + mu*, beta = beta*,
-    kappa = kappa_f + kappa*."""
-    D = physical_gradients(G4, M, grid)
+C6F_ALPHA = 1.0 / 3.0
+C6F_A = 29.0 / 36.0   # weight of (F_i + F_{i+1})
+C6F_B = 1.0 / 36.0    # weight of (F_{i-1} + F_{i+2})
+
+
+def c6_faces(Fn, d, grid):
+    """Compact sixth-order interface fluxes along d (R28), stored at node i for the face
+    i+1/2; defined on faces -1/2 .. n-1/2 (NaN elsewhere).  Fn: (m, ...) node fluxes,
+    needed at positions -2 .. n+1 along d."""
+    ax = axis_of(Fn, d)
+    g, n = grid.g[d], grid.n[d]
+    Fm = np.moveaxis(Fn, ax, 0)
+    N = Fm.shape[0]
+    cols = Fm.reshape(N, -1)
+    out = np.full_like(cols, np.nan)
+    F = lambda i: cols[g + i]  # noqa: E731  (position i of the line)
+    if grid.periodic(d):
+        inner = cols[g:g + n]
+        rhs = C6F_A * (inner + np.roll(inner, -1, axis=0)) \
+            + C6F_B * (np.roll(inner, 1, axis=0) + np.roll(inner, -2, axis=0))
+        c = np.zeros(n)
+        c[0] = 1.0
+        c[1] = C6F_ALPHA
+        c[n - 1] += C6F_ALPHA
+        faces = np.real(scipy.linalg.solve_circulant(c, rhs, singular='raise'))
+        out[g:g + n] = faces
+        out[g - 1] = faces[n - 1]
+    else:
+        i4f = lambda i: (7.0 * (F(i) + F(i + 1)) - (F(i - 1) + F(i + 2))) / 12.0  # noqa: E731
+        lo, hi = i4f(-1), i4f(n - 1)
+        m = n - 1
+        idx = np.arange(m)
+        rhs = C6F_A * (cols[g + idx] + cols[g + idx + 1]) + C6F_B * (cols[g + idx - 1] + cols[g + idx + 2])
+        rhs[0] -= C6F_ALPHA * lo
+        rhs[m - 1] -= C6F_ALPHA * hi
+        ab = np.zeros((3, m))
+        ab[1, :] = 1.0
+        ab[0, 1:] = C6F_ALPHA
+        ab[2, :m - 1] = C6F_ALPHA
+        out[g:g + m] = scipy.linalg.solve_banded((1, 1), ab, rhs)
+        out[g - 1] = lo
+        out[g + n - 1] = hi
+    return np.moveaxis(out.reshape(Fm.shape), 0, ax)
+
+
+def lad_interface_flux(W, Gl, M, d, grid, gas, coef, mu_f, kappa_f, order='E4'):
+    """LAD interface flux along d at i+1/2 (stored at node i): I4 (LAD-E4) or the compact
+    C6 faces (LAD-C6, R28) of the node convective + viscous flux with mu = mu_f + mu*,
+    beta = beta*, kappa = kappa_f + kappa*.  Gl: the scheme's computational gradients
+    of the primitives (E4 or C6)."""
+    D = physical_gradients(Gl, M, grid)
     mu = mu_f + coef[0]
     beta = coef[1]
     kappa = kappa_f + coef[2]
     Fn = convective_node_flux(W, M, d, gas.gamma) + viscous_node_flux(W, D, M, d, gas, mu, beta, kappa)
+    if order == 'C6':
+        return c6_faces(Fn, d, grid)
     return i4(Fn, d)

@@ -1,6 +1,7 @@
 """Stage right-hand sides, CFL time step and SSP-RK3 (oracle; test infrastructure only).
 
-Paper: Alg. 1 (LAD stage), Alg. 2 (C-GBR stage), Alg. 3 (hybrid: LAD unless
+Paper: Alg. 1 (LAD stage, with the implicit filter after the last stage of a
+LAD-C6 step), Alg. 2 (C-GBR stage), Alg. 3 (hybrid: LAD unless
 troubled cells exist), Sec. 5 (the hybrid uses LAD-E4 with MEG6 and a density /
 pressure criterion for troubled cells; per-cell switching proposed as the
 efficient form), Sec. 2.3 (conservative finite difference: node derivative =
@@ -22,6 +23,9 @@ Readings used here:
   R18  no positivity fallback: rho <= 0, p <= 0 or a non-finite value after a
        stage is reported (non-physical count).
   R24  troubled if rho < rho_thr or p < p_thr (strict).
+  R27-R29  LAD-C6: C6 gradients, compact interface fluxes, tenth-order implicit
+       filter after the third stage (``Opts.lad = 'C6'``; derivatives, lad and
+       implicit_filter modules).
 """
 from dataclasses import dataclass
 
@@ -29,6 +33,7 @@ import numpy as np
 
 from . import grid as gr
 from .derivatives import gradient
+from .implicit_filter import filter_state
 from .gbr import gbr_interface_flux, omega_sensor, omega_bar
 from .lad import (lad_coefficients, lad_interface_flux, physical_gradients,
                   physical_transport, viscous_node_flux)
@@ -58,6 +63,8 @@ class Opts:
     rho_thr: float = -1.0
     p_thr: float = -1.0
     dilate: int = 3
+    lad: str = 'E4'               # LAD central scheme: 'E4' or 'C6'
+    filter_alpha: float = 0.49    # alpha_f of the LAD-C6 filter (0.5: no filter)
 
 
 def primitives(Q, gamma):
@@ -122,7 +129,7 @@ def rhs(Q, grid, gas, opts, scheme, M=None, info=None, force_flags=None):
         Dg = physical_gradients(G, M, grid)
         Om = omega_sensor(W, Dg[1:4], grid) if gas.viscous else None   # R26
     if need_lad:
-        G4 = {l: np.stack([gradient(W[q], l, 'E4', grid) for q in range(5)])
+        G4 = {l: np.stack([gradient(W[q], l, opts.lad, grid) for q in range(5)])
               for l in range(grid.ndim)}
         coef = lad_coefficients(W, G4, M, grid, gas, opts)
         if info is not None:
@@ -146,7 +153,7 @@ def rhs(Q, grid, gas, opts, scheme, M=None, info=None, force_flags=None):
                 margin = np.fmin(margin, np.fmin(m, gr.shift(m, -1, d, fill=np.inf)))
             F = np.where(sel[d], Fg, F)
         if need_lad:
-            Fl = lad_interface_flux(W, G4, M, d, grid, gas, coef, mu_f, kappa_f)
+            Fl = lad_interface_flux(W, G4, M, d, grid, gas, coef, mu_f, kappa_f, opts.lad)
             F = np.where(sel[d], F, Fl)
         dF = F - gr.shift(F, -1, d)
         L[(slice(None),) + inner] -= M[9][inner] * dF[(slice(None),) + inner]
@@ -194,8 +201,14 @@ def nonphysical_count(Q, grid, gamma):
     return int(bad.sum())
 
 
+def uses_filter(opts, scheme):
+    """LAD-C6 steps end with the implicit filter (Alg. 1, R29)."""
+    return scheme == 'lad' and opts.lad == 'C6' and opts.filter_alpha < 0.5
+
+
 def rk3_step(Q, t, t_end, grid, gas, opts, scheme, M=None):
-    """One SSP-RK3 step (R8, R17).  Returns (Q_new, t_new, dt, nonphysical_count)."""
+    """One SSP-RK3 step (R8, R17), filtered after the third stage for LAD-C6 (R29).
+    Returns (Q_new, t_new, dt, nonphysical_count)."""
     if M is None:
         M = gr.node_metrics(grid)
     dt = min(cfl_dt(Q, grid, gas, opts.cfl, M), t_end - t)
@@ -203,6 +216,8 @@ def rk3_step(Q, t, t_end, grid, gas, opts, scheme, M=None):
     U = Q
     for s in range(3):
         U = rk3_stage(Q, U, dt, s, grid, gas, opts, scheme, M)
+        if s == 2 and uses_filter(opts, scheme):
+            U = filter_state(U, grid, opts.filter_alpha)
         bad += nonphysical_count(U, grid, gas.gamma)
     return U, t + dt, dt, bad
 
