@@ -187,9 +187,9 @@ def ramp3d(args, variants, cpu):
     cells = c.cells
     c.Q = c.coords = None
 
-    def context(precision, grad='C4', mode='global'):
+    def context(precision, grad='C4', mode='global', lad='E4'):
         return lgbr.Context(grid, gas, lgbr.make_opts(precision=precision, cfl=0.2, grad=grad, hybrid_mode=mode,
-                                                      p_thr=e['p_thr']), metrics, coords)
+                                                      p_thr=e['p_thr'], lad=lad), metrics, coords)
 
     desc = ('M2.9 24-deg ramp stand-in 1024x384x128 curvilinear, viscous, hybrid LAD-E4/MIG4 (global switch), '
             'p_thr 0.5 p_inf, CFL 0.2')
@@ -212,7 +212,7 @@ def ramp3d(args, variants, cpu):
     torch.cuda.empty_cache()
     if variants:
         var = {}
-        for vname, prec, scheme, grad, mode in (
+        for vname, prec, scheme, grad, mode, *vv in (
                 ('hybrid_fp64', 'fp64', 'hybrid', 'C4', 'global'),
                 ('hybrid_percell_mixed', 'mixed', 'hybrid', 'C4', 'percell'),
                 ('hybrid_percell_fp64', 'fp64', 'hybrid', 'C4', 'percell'),
@@ -221,14 +221,27 @@ def ramp3d(args, variants, cpu):
                 ('cgbr_meg6_fp64', 'fp64', 'cgbr', 'E6', 'global'),
                 ('cgbr_meg6_mixed', 'mixed', 'cgbr', 'E6', 'global'),
                 ('lad_e4_fp64', 'fp64', 'lad', 'C4', 'global'),
-                ('lad_e4_mixed', 'mixed', 'lad', 'C4', 'global')):
+                ('lad_e4_mixed', 'mixed', 'lad', 'C4', 'global'),
+                ('lad_c6_fp64', 'fp64', 'lad', 'C4', 'global', 'C6'),
+                ('lad_c6_mixed', 'mixed', 'lad', 'C4', 'global', 'C6')):
             log('ramp3d: variant ' + vname)
-            ctx = context(prec, grad, mode)
+            ctx = context(prec, grad, mode, *vv)
             vms, _, vbad, _, _ = R.steps(ctx, scheme, Q0, K=min(args.steps, 20), W=3)
+            var[vname] = {'ms_per_step': round(vms, 4), 'mcell_per_s': mcell(cells, vms), 'nonphysical_nodes': vbad}
+            if vname.startswith('lad_c6'):
+                _, kern, _, _, _ = R.steps(ctx, scheme, Q0, K=5, W=1, prof_class=-1)
+                var[vname]['kernel_breakdown_ms_per_step'] = {
+                    k: round(v[0] / 5, 4) for k, v in sorted(kern.items(), key=lambda kv: -kv[1][0])}
             ctx.close()
             torch.cuda.empty_cache()
-            var[vname] = {'ms_per_step': round(vms, 4), 'mcell_per_s': mcell(cells, vms), 'nonphysical_nodes': vbad}
+        # the paper's per-stage speed-up study: LAD-C6 against MEG6 / MIG4 C-GBR (FP64 there)
         res['variants'] = var
+        res['lad_c6_speedup'] = {
+            p: {'over_meg6': round(var['cgbr_meg6_' + p]['ms_per_step'] / var['lad_c6_' + p]['ms_per_step'], 3),
+                'over_mig4': round(var['cgbr_mig4_' + p]['ms_per_step'] / var['lad_c6_' + p]['ms_per_step'], 3),
+                'lad_e4_over_meg6': round(var['cgbr_meg6_' + p]['ms_per_step'] / var['lad_e4_' + p]['ms_per_step'], 3),
+                'lad_e4_over_mig4': round(var['cgbr_mig4_' + p]['ms_per_step'] / var['lad_e4_' + p]['ms_per_step'], 3)}
+            for p in ('fp64', 'mixed')}
     if cpu:
         res['cpu_baseline'] = cpu_baseline_ramp()
     return res
@@ -306,9 +319,9 @@ def triple_point(args, variants, cpu):
     cells = c.cells
     Q0 = torch.from_numpy(c.Q).cuda()
 
-    def context(precision, grad='E6', mode='global'):
+    def context(precision, grad='E6', mode='global', lad='E4'):
         return lgbr.Context(grid, gas, lgbr.make_opts(precision=precision, cfl=0.2, grad=grad, hybrid_mode=mode,
-                                                      rho_thr=c.extra['rho_thr']))
+                                                      rho_thr=c.extra['rho_thr'], lad=lad))
 
     desc = 'triple point 1792x768, hybrid LAD-E4/MEG6 (global switch), rho_thr 0.0625, CFL 0.2'
     res = {'workload': desc, 'cells': cells}
@@ -341,21 +354,22 @@ def triple_point(args, variants, cpu):
         fl3 = flags_of(head, Q3)
         w3['troubled_interface_fraction'] = {'global': interface_fraction(fl3, 'global'),
                                              'percell': round(interface_fraction(fl3), 5)}
-        for vname, prec, scheme, grad, mode in (
+        for vname, prec, scheme, grad, mode, *vv in (
                 ('hybrid_mixed', 'mixed', 'hybrid', 'E6', 'global'),
                 ('hybrid_fp64', 'fp64', 'hybrid', 'E6', 'global'),
                 ('hybrid_percell_mixed', 'mixed', 'hybrid', 'E6', 'percell'),
                 ('cgbr_meg6_mixed', 'mixed', 'cgbr', 'E6', 'global'),
                 ('cgbr_meg6_fp64', 'fp64', 'cgbr', 'E6', 'global'),
                 ('cgbr_mig4_mixed', 'mixed', 'cgbr', 'C4', 'global'),
-                ('lad_e4_mixed', 'mixed', 'lad', 'E6', 'global')):
-            ctx = context(prec, grad, mode)
+                ('lad_e4_mixed', 'mixed', 'lad', 'E6', 'global'),
+                ('lad_c6_mixed', 'mixed', 'lad', 'E6', 'global', 'C6')):
+            ctx = context(prec, grad, mode, *vv)
             vms, _, vbad, _, _ = R.steps(ctx, scheme, Q3, K=min(args.steps, 50), W=3)
             ctx.close()
             w3[vname] = {'ms_per_step': round(vms, 4), 'mcell_per_s': mcell(cells, vms), 'nonphysical_nodes': vbad}
         res['window_t3'] = w3
         var = {}
-        for vname, prec, scheme, grad, mode in (
+        for vname, prec, scheme, grad, mode, *vv in (
                 ('hybrid_fp64', 'fp64', 'hybrid', 'E6', 'global'),
                 ('hybrid_percell_mixed', 'mixed', 'hybrid', 'E6', 'percell'),
                 ('hybrid_percell_fp64', 'fp64', 'hybrid', 'E6', 'percell'),
@@ -364,8 +378,10 @@ def triple_point(args, variants, cpu):
                 ('cgbr_mig4_fp64', 'fp64', 'cgbr', 'C4', 'global'),
                 ('cgbr_mig4_mixed', 'mixed', 'cgbr', 'C4', 'global'),
                 ('lad_e4_fp64', 'fp64', 'lad', 'E6', 'global'),
-                ('lad_e4_mixed', 'mixed', 'lad', 'E6', 'global')):
-            ctx = context(prec, grad, mode)
+                ('lad_e4_mixed', 'mixed', 'lad', 'E6', 'global'),
+                ('lad_c6_fp64', 'fp64', 'lad', 'E6', 'global', 'C6'),
+                ('lad_c6_mixed', 'mixed', 'lad', 'E6', 'global', 'C6')):
+            ctx = context(prec, grad, mode, *vv)
             vms, _, vbad, _, _ = R.steps(ctx, scheme, Q0, K=min(args.steps, 50), W=3)
             ctx.close()
             var[vname] = {'ms_per_step': round(vms, 4), 'mcell_per_s': mcell(cells, vms), 'nonphysical_nodes': vbad}

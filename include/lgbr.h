@@ -11,7 +11,9 @@
  *     fourth-order (MIG4) gradients, MP5 limiting with the wave-appropriate Omega
  *     sensor, curvilinear HLLC fluxes;
  *   - LAD    (Sec. 2.2, Sec. 5): fourth-order explicit central differences (LAD-E4)
- *     with localized artificial shear / bulk viscosity and conductivity;
+ *     with localized artificial shear / bulk viscosity and conductivity, or the
+ *     stand-alone sixth-order compact form LAD-C6 with its implicit filter (Sec. 3,
+ *     Alg. 1);
  *   - hybrid (Alg. 3, Sec. 5): a troubled-cell flag selects the C-GBR interface flux,
  *     the LAD flux elsewhere (per-cell form), or C-GBR for the whole field when any
  *     interior cell is troubled (the paper's global form);
@@ -68,6 +70,7 @@ enum { LG_GRAD_E6 = 0, LG_GRAD_C4 = 1 };          /* MEG6 / MIG4 gradients (Sec.
 enum { LG_FP64 = 0, LG_MIXED = 1 };               /* FP64 everywhere / FP32 bulk math   */
 enum { LG_HYB_PERCELL = 0, LG_HYB_GLOBAL = 1 };   /* hybrid selection (Sec. 5, Alg. 3)   */
 enum { LG_SCHEME_CGBR = 0, LG_SCHEME_LAD = 1, LG_SCHEME_HYBRID = 2 };
+enum { LG_LAD_E4 = 0, LG_LAD_C6 = 1 };            /* central scheme of LG_SCHEME_LAD        */
 
 typedef struct {
   int ndim;            /* 1, 2 or 3 active directions                                 */
@@ -103,6 +106,12 @@ typedef struct {
   double p_thr;        /* troubled if p < p_thr (Sec. 5; negative: never)             */
   int dilate;          /* troubled-flag dilation radius of the per-cell hybrid (3)    */
   int seg;             /* nodes per lane in the strided sweeps (0: default)           */
+  int lad_scheme;      /* LG_LAD_E4 (the hybrid's LAD, Sec. 5) or LG_LAD_C6 (the
+                          stand-alone LAD scheme of Sec. 3: compact sixth-order
+                          gradients and interface fluxes; LG_SCHEME_LAD only)          */
+  double filter_alpha; /* alpha_f of the tenth-order implicit filter that ends every
+                          rk3_step of a LG_LAD_C6 context (Alg. 1); 0 <= alpha_f <= 0.5,
+                          0.5 = no filter.  Ignored for LG_LAD_E4.                     */
 } lg_opts;
 
 typedef struct lg_ctx lg_ctx;
@@ -138,17 +147,31 @@ lg_status lg_metrics_from_coords(const lg_grid* grid, const double* coords, doub
 
 /* dQdt = C-GBR right-hand side of Q (Sec. 2.3, Alg. 2). */
 lg_status cgbr_rhs(lg_ctx* ctx, double* Q, double* dQdt);
-/* dQdt = LAD-E4 right-hand side of Q (Sec. 2.2, Alg. 1 without the filter). */
+/* dQdt = LAD right-hand side of Q (Sec. 2.2, Alg. 1 without the filter): LAD-E4, or
+ * LAD-C6 on a context created with lad_scheme = LG_LAD_C6. */
 lg_status lad_rhs(lg_ctx* ctx, double* Q, double* dQdt);
+/* FILTER_CALLS of Alg. 1: the implicit low-pass filter (Sec. 2.1; Gaitonde-Visbal,
+ * tenth order, alpha_f = opts->filter_alpha)
+ *   alpha_f phi^_{i-1} + phi^_i + alpha_f phi^_{i+1} = sum_{k=0}^{5} a_k/2 (phi_{i+k} + phi_{i-k})
+ * applied to the conserved state Q in place along xi, eta, zeta in turn.  Before each
+ * direction the ghost layers of that direction are refilled with the boundary images;
+ * bounded lines filter their interior nodes with the ghost values as known neighbours,
+ * periodic lines are cyclic.  Interior nodes and the ghosts of FIXED faces hold the
+ * result; other ghosts hold images of intermediate fields.  rk3_step calls it after the
+ * third stage on LG_LAD_C6 contexts; lg_rk3_stage does not.  LG_EUNSUPPORTED unless the
+ * context is LG_LAD_C6 with alpha_f < 0.5. */
+lg_status lad_filter(lg_ctx* ctx, double* Q);
 /* dQdt = hybrid right-hand side of Q (Alg. 3, Sec. 5).  flags_in (nullable, uint8 [N])
  * replaces the troubled-cell criterion; flags_out (nullable, uint8 [N]) receives the
- * troubled flags that were used. */
+ * troubled flags that were used.  LG_EUNSUPPORTED on LG_LAD_C6 contexts (the hybrid's
+ * LAD is LAD-E4). */
 lg_status hybrid_rhs(lg_ctx* ctx, double* Q, double* dQdt, const uint8_t* flags_in, uint8_t* flags_out);
 
 /* One SSP-RK3 step of scheme LG_SCHEME_* on Q in place.  The step size is
  * dt = cfl / max_i sum_l (|xi_l . u| + c |xi_l|) from Q, clipped so that t does not
  * pass t_end; t_inout is a device double that is advanced by dt.  dt stays on the
- * device (no host synchronisation). */
+ * device (no host synchronisation).  LG_SCHEME_LAD on a LG_LAD_C6 context ends the step
+ * with lad_filter (Alg. 1) unless filter_alpha = 0.5. */
 lg_status rk3_step(lg_ctx* ctx, int scheme, double* Q, double t_end, double* t_inout);
 
 /* One RK3 stage from given states (for per-stage checks):
@@ -177,7 +200,8 @@ void lg_batch_destroy(lg_batch* batch);
 enum {
   LG_KC_BC = 0, LG_KC_PRIM, LG_KC_FLAGS, LG_KC_GRAD_E6, LG_KC_GRAD_C4, LG_KC_SENSOR, LG_KC_VISC,
   LG_KC_LAD_NODE, LG_KC_LAD_RAW, LG_KC_GAUSS, LG_KC_LAD_FLUX, LG_KC_SWEEP_X, LG_KC_SWEEP_Y,
-  LG_KC_SWEEP_Z, LG_KC_COMBINE, LG_KC_DT, LG_KC_BC_SCALAR, LG_KC_LAD_SWEEP, LG_KC_COUNT
+  LG_KC_SWEEP_Z, LG_KC_COMBINE, LG_KC_DT, LG_KC_BC_SCALAR, LG_KC_LAD_SWEEP, LG_KC_C6_FACES, LG_KC_FILTER,
+  LG_KC_COUNT
 };
 lg_status lg_prof_start(lg_ctx* ctx, int kernel_class, int max_launches);
 lg_status lg_prof_stop(lg_ctx* ctx, double* ms, int* launches);

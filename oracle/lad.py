@@ -220,7 +220,9 @@ def c6_faces(Fn, d, grid):
         ab[1, :] = 1.0
         ab[0, 1:] = C6F_ALPHA
         ab[2, :m - 1] = C6F_ALPHA
-        out[g:g + m] = scipy.linalg.solve_banded((1, 1), ab, rhs)
+        # lines through ghost positions of the other directions may hold NaN node fluxes
+        # (metrics undefined there); they are solved too but never used
+        out[g:g + m] = scipy.linalg.solve_banded((1, 1), ab, rhs, check_finite=False)
         out[g - 1] = lo
         out[g + n - 1] = hi
     return np.moveaxis(out.reshape(Fm.shape), 0, ax)

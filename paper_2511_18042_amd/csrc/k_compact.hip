@@ -1,0 +1,619 @@
+// LAD-C6: compact sixth-order differences and the low-pass implicit filter.
+//
+// Paper: Sec. 3 and Alg. 1 -- the stand-alone LAD scheme differences its fluxes with a
+// sixth-order compact central scheme, and after the solution update of the last
+// Runge-Kutta stage it filters the solution along i, j and k with the implicit filter
+// of Gaitonde & Visbal (Sec. 2.1).  Unit computational spacing.
+//
+//   C6 gradient  (1/3) f'_{i-1} + f'_i + (1/3) f'_{i+1} = (7/9)(f_{i+1} - f_{i-1}) + (1/36)(f_{i+2} - f_{i-2})
+//   C6 faces     (1/3) F_{i-1/2} + F_{i+1/2} + (1/3) F_{i+3/2}
+//                    = (29/36)(F_i + F_{i+1}) + (1/36)(F_{i-1} + F_{i+2})
+//                (subtracting the rows of i+1/2 and i-1/2 gives the C6 relation for the node
+//                derivative F_{i+1/2} - F_{i-1/2}: the flux form of the scheme)
+//   filter       a_f phi^_{i-1} + phi^_i + a_f phi^_{i+1} = sum_{k=0}^{5} (a_k / 2)(phi_{i+k} + phi_{i-k})
+//                (tenth order; a_k from the maximal-order conditions, computed on the host)
+//
+// Closures of bounded lines: the gradient line spans all nodes with second-order
+// one-sided end rows and C4 rows next to them; the face system's unknowns are the
+// interior faces, the boundary faces -1/2 and n-1/2 being the fourth-order I4 values of
+// the node fluxes; the filter's unknowns are the interior nodes, their neighbours across
+// the boundary entering with the ghost values.  Periodic lines are cyclic over the
+// interior.  All solves run in FP64.
+//
+// Each system has constant coefficients, so its factors are tables built on the host:
+//   bounded, m unknowns (Thomas):  cp[m], inv[m], a[m]      (a = sub-diagonal of each row)
+//   cyclic, n unknowns:            cp[n], inv[n], z[n], fac, alpha
+//       (A = B + u v^T with u = (-1, 0.., alpha), v = (1, 0.., -alpha); B z = u,
+//        x = y - (y_0 - alpha y_{n-1}) fac z with B y = r, fac = 1 / (1 + v.z))
+//   PCR factors:                   k1[steps][L], k2[steps][L], binv[L]
+// Lines along the contiguous direction are solved by parallel cyclic reduction in LDS, one
+// workgroup per (line, variable); strided lines one lane per line, coalesced across lanes.
+#include "lgbr_dev.h"
+#include "lgbr_kernels.h"
+
+#include <algorithm>
+
+namespace lg {
+
+constexpr double C6_A = 7.0 / 9.0, C6_B = 1.0 / 36.0;
+constexpr double C6F_A = 29.0 / 36.0, C6F_B = 1.0 / 36.0, C6_ALPHA = 1.0 / 3.0;
+constexpr int CPCR_MAXPT = 4096 / 256;
+
+// Parallel cyclic reduction of r[0..L) in LDS by the whole (256-lane) workgroup; the
+// solution x_i = r_i / b_i is left in r.  Periodic lines wrap their indices (L must be at
+// least 2^(steps+1)); the couplings left after `steps` steps are below rounding.
+__device__ void pcr_lds(double* r, int L, bool periodic, const double* tab, int steps) {
+  double nv[CPCR_MAXPT];
+  for (int st = 0; st < steps; ++st) {
+    const int s = 1 << st;
+    const double* k1 = tab + (size_t)st * L;
+    const double* k2 = tab + (size_t)(steps + st) * L;
+#pragma unroll
+    for (int m = 0; m < CPCR_MAXPT; ++m) {
+      const int i = threadIdx.x + m * 256;
+      if (i < L) {
+        int im = i - s, ip = i + s;
+        double rm, rp;
+        if (periodic) {
+          im = im < 0 ? im + L : im;
+          ip = ip >= L ? ip - L : ip;
+          rm = r[im];
+          rp = r[ip];
+        } else {
+          rm = im >= 0 ? r[im] : 0.0;
+          rp = ip < L ? r[ip] : 0.0;
+        }
+        nv[m] = r[i] - k1[i] * rm - k2[i] * rp;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < CPCR_MAXPT; ++m) {
+      const int i = threadIdx.x + m * 256;
+      if (i < L) r[i] = nv[m];
+    }
+    __syncthreads();
+  }
+  const double* binv = tab + (size_t)2 * steps * L;
+  for (int i = threadIdx.x; i < L; i += blockDim.x) r[i] *= binv[i];
+  __syncthreads();
+}
+
+// interior line t of direction d (positions of the other two directions inside the grid)
+__device__ __forceinline__ size_t interior_line_base(const Prob& P, int d, int t) {
+  const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+  const int a = t % P.n[o1], b = t / P.n[o1];
+  return (size_t)(P.g[o1] + a) * P.s[o1] + (size_t)(P.g[o2] + b) * P.s[o2];
+}
+
+__device__ __forceinline__ int interior_lines(const Prob& P, int d) {
+  const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+  return P.n[o1] * P.n[o2];
+}
+
+__device__ __forceinline__ int wrap(int p, int n) { return p < 0 ? p + n : (p >= n ? p - n : p); }
+
+__device__ __forceinline__ void prims5c(const double* Q, size_t T, size_t o, double gm1, double w[5]) {
+  const double rho = Q[o], ri = 1.0 / rho;
+  const double u = Q[T + o] * ri, v = Q[2 * T + o] * ri, x = Q[3 * T + o] * ri;
+  w[0] = rho;
+  w[1] = u;
+  w[2] = v;
+  w[3] = x;
+  w[4] = gm1 * (Q[4 * T + o] - 0.5 * rho * (u * u + v * v + x * x));
+}
+
+// ------------------------------------------------------------------ C6 gradients
+// right-hand side of row i of a bounded gradient line of N nodes from the values at
+// i-2 .. i+2 (entries outside the line unused)
+__device__ __forceinline__ double c6_grad_rhs(int i, int N, double m2, double m1, double c0, double p1, double p2) {
+  if (i == 0) return (-3.0 * c0 + 4.0 * p1 - p2) / 2.0;
+  if (i == N - 1) return (3.0 * c0 - 4.0 * m1 + m2) / 2.0;
+  if (i == 1 || i == N - 2) return 0.75 * (p1 - m1);
+  return C6_A * (p1 - m1) + C6_B * (p2 - m2);
+}
+
+// One lane per line (all nodes of the other two directions), all five primitives formed
+// in FP64 from the conserved state; forward elimination into the FP64 scratch, back
+// substitution into the gradient array.
+template <typename R>
+__global__ void __launch_bounds__(256) k_grad_c6(const Prob* __restrict__ probs, StateRef ref, int d) {
+  const Prob& P = probs[blockIdx.y];
+  if (d >= P.ndim || c6_grad_pcr(P, d)) return;
+  const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= P.N[o1] * P.N[o2]) return;
+  const double* Q = ref.state(P);
+  R* G = static_cast<R*>(P.G[d]);
+  const size_t T = P.total;
+  double* S = P.T64;
+  const double* tab = P.tri6[d];
+  const int a = t % P.N[o1], b = t / P.N[o1];
+  const size_t base = (size_t)a * P.s[o1] + (size_t)b * P.s[o2];
+  const int sd = P.s[d], g = P.g[d], n = P.n[d], N = P.N[d];
+  const double gm1 = P.gamma - 1.0;
+  double w[5][5];   // window: positions i-2 .. i+2
+  if (P.bc[d][0] != BC_PERIODIC) {
+    const double* cp = tab;
+    const double* inv = tab + N;
+    const double* sub = tab + 2 * N;
+    for (int q = 0; q < 5; ++q) w[0][q] = w[1][q] = 0.0;
+    prims5c(Q, T, base, gm1, w[2]);
+    prims5c(Q, T, base + (size_t)sd, gm1, w[3]);
+    prims5c(Q, T, base + (size_t)2 * sd, gm1, w[4]);
+    double dprev[5] = {0, 0, 0, 0, 0};
+    for (int i = 0; i < N; ++i) {
+      for (int q = 0; q < 5; ++q) {
+        const double r = c6_grad_rhs(i, N, w[0][q], w[1][q], w[2][q], w[3][q], w[4][q]);
+        const double dd = (r - sub[i] * dprev[q]) * inv[i];
+        S[q * T + base + (size_t)i * sd] = dd;
+        dprev[q] = dd;
+      }
+      for (int p = 0; p < 4; ++p)
+        for (int q = 0; q < 5; ++q) w[p][q] = w[p + 1][q];
+      if (i + 3 < N) prims5c(Q, T, base + (size_t)(i + 3) * sd, gm1, w[4]);
+      else
+        for (int q = 0; q < 5; ++q) w[4][q] = 0.0;
+    }
+    double y[5];
+    for (int q = 0; q < 5; ++q) {
+      y[q] = dprev[q];
+      G[q * T + base + (size_t)(N - 1) * sd] = (R)y[q];
+    }
+    for (int i = N - 2; i >= 0; --i)
+      for (int q = 0; q < 5; ++q) {
+        y[q] = S[q * T + base + (size_t)i * sd] - cp[i] * y[q];
+        G[q * T + base + (size_t)i * sd] = (R)y[q];
+      }
+  } else {
+    const double* cp = tab;
+    const double* inv = tab + n;
+    const double* z = tab + 2 * n;
+    const double fac = tab[3 * n], al = tab[3 * n + 1];
+    const size_t b0 = base + (size_t)g * sd;
+    for (int p = 0; p < 4; ++p) prims5c(Q, T, base + (size_t)(g + wrap(p - 2, n)) * sd, gm1, w[p]);
+    double dprev[5] = {0, 0, 0, 0, 0};
+    for (int i = 0; i < n; ++i) {
+      prims5c(Q, T, base + (size_t)(g + wrap(i + 2, n)) * sd, gm1, w[4]);
+      for (int q = 0; q < 5; ++q) {
+        const double r = C6_A * (w[3][q] - w[1][q]) + C6_B * (w[4][q] - w[0][q]);
+        const double dd = (i == 0 ? r : r - al * dprev[q]) * inv[i];
+        S[q * T + b0 + (size_t)i * sd] = dd;
+        dprev[q] = dd;
+      }
+      for (int p = 0; p < 4; ++p)
+        for (int q = 0; q < 5; ++q) w[p][q] = w[p + 1][q];
+    }
+    double y[5], ylast[5];
+    for (int q = 0; q < 5; ++q) y[q] = ylast[q] = dprev[q];
+    for (int i = n - 2; i >= 0; --i)
+      for (int q = 0; q < 5; ++q) {
+        y[q] = S[q * T + b0 + (size_t)i * sd] - cp[i] * y[q];
+        S[q * T + b0 + (size_t)i * sd] = y[q];
+      }
+    double vy[5];
+    for (int q = 0; q < 5; ++q) vy[q] = (y[q] - al * ylast[q]) * fac;
+    for (int i = 0; i < n; ++i)
+      for (int q = 0; q < 5; ++q) {
+        const double yi = (i == n - 1) ? ylast[q] : S[q * T + b0 + (size_t)i * sd];
+        const R xv = (R)(yi - vy[q] * z[i]);
+        G[q * T + b0 + (size_t)i * sd] = xv;
+        if (i >= n - g) G[q * T + b0 + (size_t)(i - n) * sd] = xv;   // low ghosts
+        if (i < g) G[q * T + b0 + (size_t)(i + n) * sd] = xv;        // high ghosts
+      }
+  }
+}
+
+// One workgroup per (line, primitive), persistent over the items; the primitive along the
+// line in LDS, the right-hand side reduced by PCR.
+template <typename R>
+__global__ void __launch_bounds__(256) k_grad_c6_pcr(const Prob* __restrict__ probs, StateRef ref, int d) {
+  extern __shared__ double lds[];
+  const Prob& P = probs[blockIdx.y];
+  if (d >= P.ndim || !c6_grad_pcr(P, d)) return;
+  const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+  const int nlines = P.N[o1] * P.N[o2];
+  const bool periodic = P.bc[d][0] == BC_PERIODIC;
+  const int g = P.g[d], N = P.N[d], n = P.n[d];
+  const int L = periodic ? n : N;
+  const int off0 = periodic ? g : 0;
+  const int sd = P.s[d];
+  const double* Q = ref.state(P);
+  const size_t T = P.total;
+  const double gm1 = P.gamma - 1.0;
+  double* f = lds;
+  double* r = lds + N;
+  for (int blk = blockIdx.x; blk < 5 * nlines; blk += gridDim.x) {
+    const int line = blk % nlines, q = blk / nlines;
+    const int a = line % P.N[o1], b = line / P.N[o1];
+    const size_t base = (size_t)a * P.s[o1] + (size_t)b * P.s[o2];
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+      const size_t o = base + (size_t)i * sd;
+      const double rho = Q[o];
+      double v;
+      if (q == 0) {
+        v = rho;
+      } else {
+        const double ri = 1.0 / rho;
+        if (q <= 3) {
+          v = Q[q * T + o] * ri;
+        } else {
+          const double u = Q[T + o] * ri, vv = Q[2 * T + o] * ri, w = Q[3 * T + o] * ri;
+          v = gm1 * (Q[4 * T + o] - 0.5 * rho * (u * u + vv * vv + w * w));
+        }
+      }
+      f[i] = v;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < L; i += blockDim.x) {
+      double v;
+      if (periodic) {
+        v = C6_A * (f[off0 + wrap(i + 1, n)] - f[off0 + wrap(i - 1, n)]) +
+            C6_B * (f[off0 + wrap(i + 2, n)] - f[off0 + wrap(i - 2, n)]);
+      } else {
+        v = c6_grad_rhs(i, N, i >= 2 ? f[i - 2] : 0.0, i >= 1 ? f[i - 1] : 0.0, f[i], i + 1 < N ? f[i + 1] : 0.0,
+                        i + 2 < N ? f[i + 2] : 0.0);
+      }
+      r[i] = v;
+    }
+    __syncthreads();
+    pcr_lds(r, L, periodic, P.pcr6[d], LG_PCR_STEPS);
+    R* G = static_cast<R*>(P.G[d]) + (size_t)q * T;
+    for (int i = threadIdx.x; i < L; i += blockDim.x) {
+      const R y = (R)r[i];
+      G[base + (size_t)(i + off0) * sd] = y;
+      if (periodic) {
+        if (i >= n - g) G[base + (size_t)(i + off0 - n) * sd] = y;   // low ghosts
+        if (i < g) G[base + (size_t)(i + off0 + n) * sd] = y;        // high ghosts
+      }
+    }
+    __syncthreads();   // the next item reuses the LDS line
+  }
+}
+
+// ------------------------------------------------------------------ C6 interface fluxes
+// What one node's derivative does: -J D (first direction), added to dQ/dt (later ones),
+// or, in the last direction of an RK stage, the stage combination.
+struct FaceOut {
+  StateRef ref;
+  RKRef rr;
+  int accumulate, rk, stage;
+  double a, b;
+};
+
+__device__ __forceinline__ bool face_emit(const Prob& P, const FaceOut& o, double* dQ, double dt, size_t idx,
+                                          const double D[5]) {
+  const size_t T = P.total;
+  const double J = met64(P, 9, (int)idx);
+  double Lq[5];
+  for (int q = 0; q < 5; ++q) {
+    Lq[q] = -J * D[q];
+    if (o.accumulate) Lq[q] = dQ[q * T + idx] + Lq[q];
+  }
+  if (o.rk) return rk_combine_node(P, o.rr, o.stage, o.a, o.b, dt, (int)idx, Lq);
+  for (int q = 0; q < 5; ++q) dQ[q * T + idx] = Lq[q];
+  return false;
+}
+
+// One lane per interior line, all five flux components; forward elimination into the
+// FP64 scratch, back substitution emitting the node derivatives.
+template <typename R>
+__global__ void __launch_bounds__(256) k_c6_faces(const Prob* __restrict__ probs, FaceOut o, int d) {
+  const Prob& P = probs[blockIdx.y];
+  if (d >= P.ndim || c6_face_pcr(P, d)) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= interior_lines(P, d)) return;
+  const R* F = static_cast<const R*>(P.FL[d]);
+  const size_t T = P.total;
+  double* S = P.T64;
+  double* dQ = o.ref.deriv(P);
+  const double dt = o.rk ? *P.dt : 0.0;
+  const double* tab = P.trc[d];
+  const size_t base = interior_line_base(P, d, t);
+  const int sd = P.s[d], g = P.g[d], n = P.n[d];
+  int bad = 0;
+  auto at = [&](int q, int p) { return (double)F[q * T + base + (size_t)(g + p) * sd]; };
+  if (P.bc[d][0] != BC_PERIODIC) {
+    const int m = n - 1;
+    const double* cp = tab;
+    const double* inv = tab + m;
+    const double* sub = tab + 2 * m;
+    double lo[5], hi[5], w[4][5], dprev[5];
+    for (int q = 0; q < 5; ++q) {
+      lo[q] = (7.0 * (at(q, -1) + at(q, 0)) - (at(q, -2) + at(q, 1))) / 12.0;
+      hi[q] = (7.0 * (at(q, n - 1) + at(q, n)) - (at(q, n - 2) + at(q, n + 1))) / 12.0;
+      for (int p = 0; p < 3; ++p) w[p][q] = at(q, p - 1);
+      dprev[q] = 0.0;
+    }
+    for (int k = 0; k < m; ++k) {
+      for (int q = 0; q < 5; ++q) {
+        w[3][q] = at(q, k + 2);
+        double r = C6F_A * (w[1][q] + w[2][q]) + C6F_B * (w[0][q] + w[3][q]);
+        if (k == 0) r = r - C6_ALPHA * lo[q];
+        if (k == m - 1) r = r - C6_ALPHA * hi[q];
+        const double dd = (r - sub[k] * dprev[q]) * inv[k];
+        S[q * T + base + (size_t)(g + k) * sd] = dd;
+        dprev[q] = dd;
+        w[0][q] = w[1][q];
+        w[1][q] = w[2][q];
+        w[2][q] = w[3][q];
+      }
+    }
+    double prev[5], D[5];
+    for (int q = 0; q < 5; ++q) prev[q] = hi[q];
+    for (int k = m - 1; k >= 0; --k) {
+      for (int q = 0; q < 5; ++q) {
+        const double x = S[q * T + base + (size_t)(g + k) * sd] - cp[k] * (k == m - 1 ? 0.0 : prev[q]);
+        D[q] = prev[q] - x;
+        prev[q] = x;
+      }
+      if (face_emit(P, o, dQ, dt, base + (size_t)(g + k + 1) * sd, D)) ++bad;
+    }
+    for (int q = 0; q < 5; ++q) D[q] = prev[q] - lo[q];
+    if (face_emit(P, o, dQ, dt, base + (size_t)g * sd, D)) ++bad;
+  } else {
+    const double* cp = tab;
+    const double* inv = tab + n;
+    const double* z = tab + 2 * n;
+    const double fac = tab[3 * n], al = tab[3 * n + 1];
+    auto atw = [&](int q, int p) { return at(q, wrap(p, n)); };
+    double w[4][5], dprev[5];
+    for (int q = 0; q < 5; ++q) {
+      for (int p = 0; p < 3; ++p) w[p][q] = atw(q, p - 1);
+      dprev[q] = 0.0;
+    }
+    for (int k = 0; k < n; ++k) {
+      for (int q = 0; q < 5; ++q) {
+        w[3][q] = atw(q, k + 2);
+        const double r = C6F_A * (w[1][q] + w[2][q]) + C6F_B * (w[0][q] + w[3][q]);
+        const double dd = (k == 0 ? r : r - al * dprev[q]) * inv[k];
+        S[q * T + base + (size_t)(g + k) * sd] = dd;
+        dprev[q] = dd;
+        w[0][q] = w[1][q];
+        w[1][q] = w[2][q];
+        w[2][q] = w[3][q];
+      }
+    }
+    double y[5], ylast[5];
+    for (int q = 0; q < 5; ++q) y[q] = ylast[q] = dprev[q];
+    for (int k = n - 2; k >= 0; --k)
+      for (int q = 0; q < 5; ++q) {
+        y[q] = S[q * T + base + (size_t)(g + k) * sd] - cp[k] * y[q];
+        S[q * T + base + (size_t)(g + k) * sd] = y[q];
+      }
+    double vy[5], xprev[5], D[5];
+    for (int q = 0; q < 5; ++q) {
+      vy[q] = (y[q] - al * ylast[q]) * fac;
+      xprev[q] = ylast[q] - vy[q] * z[n - 1];
+    }
+    for (int i = 0; i < n; ++i) {
+      for (int q = 0; q < 5; ++q) {
+        const double yi = (i == n - 1) ? ylast[q] : S[q * T + base + (size_t)(g + i) * sd];
+        const double x = yi - vy[q] * z[i];
+        D[q] = x - xprev[q];
+        xprev[q] = x;
+      }
+      if (face_emit(P, o, dQ, dt, base + (size_t)(g + i) * sd, D)) ++bad;
+    }
+  }
+  if (bad) atomicAdd(P.status, bad);
+}
+
+// Contiguous lines (the first direction of a 2D / 3D grid): one workgroup per (interior
+// line, component); node fluxes at positions -2 .. n+1 and the face right-hand sides in
+// LDS; writes -J D into dQ/dt.
+template <typename R>
+__global__ void __launch_bounds__(256) k_c6_faces_pcr(const Prob* __restrict__ probs, StateRef ref, int d) {
+  extern __shared__ double lds[];
+  const Prob& P = probs[blockIdx.y];
+  if (d >= P.ndim || !c6_face_pcr(P, d)) return;
+  const int nlines = interior_lines(P, d);
+  const bool periodic = P.bc[d][0] == BC_PERIODIC;
+  const int g = P.g[d], n = P.n[d], sd = P.s[d];
+  const int m = periodic ? n : n - 1;
+  const R* F = static_cast<const R*>(P.FL[d]);
+  double* dQ = ref.deriv(P);
+  const size_t T = P.total;
+  double* f = lds;          // positions -2 .. n+1
+  double* r = lds + n + 4;  // faces
+  for (int blk = blockIdx.x; blk < 5 * nlines; blk += gridDim.x) {
+    const int line = blk % nlines, q = blk / nlines;
+    const size_t base = interior_line_base(P, d, line);
+    for (int p = threadIdx.x; p < n + 4; p += blockDim.x) f[p] = (double)F[q * T + base + (size_t)(g - 2 + p) * sd];
+    __syncthreads();
+    // boundary faces (bounded lines): I4 of the node fluxes
+    const double lo = (7.0 * (f[1] + f[2]) - (f[0] + f[3])) / 12.0;
+    const double hi = (7.0 * (f[n + 1] + f[n + 2]) - (f[n] + f[n + 3])) / 12.0;
+    for (int k = threadIdx.x; k < m; k += blockDim.x) {
+      double v;
+      if (periodic) {
+        v = C6F_A * (f[2 + k] + f[2 + wrap(k + 1, n)]) + C6F_B * (f[2 + wrap(k - 1, n)] + f[2 + wrap(k + 2, n)]);
+      } else {
+        v = C6F_A * (f[2 + k] + f[3 + k]) + C6F_B * (f[1 + k] + f[4 + k]);
+        if (k == 0) v = v - C6_ALPHA * lo;
+        if (k == m - 1) v = v - C6_ALPHA * hi;
+      }
+      r[k] = v;
+    }
+    __syncthreads();
+    pcr_lds(r, m, periodic, P.pcrc[d], LG_PCR_STEPS);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      double fp, fm;
+      if (periodic) {
+        fp = r[i];
+        fm = r[wrap(i - 1, n)];
+      } else {
+        fp = i < m ? r[i] : hi;
+        fm = i > 0 ? r[i - 1] : lo;
+      }
+      const size_t idx = base + (size_t)(g + i) * sd;
+      dQ[q * T + idx] = -met64(P, 9, (int)idx) * (fp - fm);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ implicit filter
+// right-hand side of row i from the window w[0..10] = phi_{i-5} .. phi_{i+5}
+__device__ __forceinline__ double filt_rhs(const Prob& P, const double w[11]) {
+  double v = P.fcoef[0] * w[5];
+  for (int k = 1; k <= 5; ++k) v = v + (0.5 * P.fcoef[k]) * (w[5 + k] + w[5 - k]);
+  return v;
+}
+
+// One lane per interior line, the five conserved variables in turn; in place on the state.
+__global__ void __launch_bounds__(256) k_filter(const Prob* __restrict__ probs, StateRef ref, int d) {
+  const Prob& P = probs[blockIdx.y];
+  if (d >= P.ndim || !(P.falpha < 0.5) || filt_pcr(P, d)) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= interior_lines(P, d)) return;
+  double* Q = ref.state(P);
+  const size_t T = P.total;
+  double* S = P.T64;
+  const double* tab = P.trf[d];
+  const size_t base = interior_line_base(P, d, t);
+  const int sd = P.s[d], g = P.g[d], n = P.n[d];
+  const double al = P.falpha;
+  const bool periodic = P.bc[d][0] == BC_PERIODIC;
+  for (int q = 0; q < 5; ++q) {
+    double* phi = Q + (size_t)q * T + base;
+    double* Sq = S + (size_t)q * T + base;
+    auto at = [&](int p) { return phi[(size_t)(g + (periodic ? wrap(p, n) : p)) * sd]; };
+    const double* cp = tab;
+    const double* inv = tab + n;
+    double w[11];
+    for (int p = 0; p < 10; ++p) w[p] = at(p - 5);
+    double dprev = 0.0;
+    if (!periodic) {
+      const double* sub = tab + 2 * n;
+      const double gl = at(-1), gh = at(n);
+      for (int i = 0; i < n; ++i) {
+        w[10] = at(i + 5);
+        double r = filt_rhs(P, w);
+        if (i == 0) r = r - al * gl;
+        if (i == n - 1) r = r - al * gh;
+        const double dd = (r - sub[i] * dprev) * inv[i];
+        Sq[(size_t)(g + i) * sd] = dd;
+        dprev = dd;
+        for (int p = 0; p < 10; ++p) w[p] = w[p + 1];
+      }
+      double y = dprev;
+      phi[(size_t)(g + n - 1) * sd] = y;
+      for (int i = n - 2; i >= 0; --i) {
+        y = Sq[(size_t)(g + i) * sd] - cp[i] * y;
+        phi[(size_t)(g + i) * sd] = y;
+      }
+    } else {
+      const double* z = tab + 2 * n;
+      const double fac = tab[3 * n];
+      for (int i = 0; i < n; ++i) {
+        w[10] = at(i + 5);
+        const double r = filt_rhs(P, w);
+        const double dd = (i == 0 ? r : r - al * dprev) * inv[i];
+        Sq[(size_t)(g + i) * sd] = dd;
+        dprev = dd;
+        for (int p = 0; p < 10; ++p) w[p] = w[p + 1];
+      }
+      double y = dprev;
+      const double ylast = dprev;
+      for (int i = n - 2; i >= 0; --i) {
+        y = Sq[(size_t)(g + i) * sd] - cp[i] * y;
+        Sq[(size_t)(g + i) * sd] = y;
+      }
+      const double vy = (y - al * ylast) * fac;
+      for (int i = 0; i < n; ++i) {
+        const double yi = (i == n - 1) ? ylast : Sq[(size_t)(g + i) * sd];
+        phi[(size_t)(g + i) * sd] = yi - vy * z[i];
+      }
+    }
+  }
+}
+
+// Contiguous lines: one workgroup per (interior line, variable); the line in LDS, the
+// interior unknowns reduced by PCR, written back in place.
+__global__ void __launch_bounds__(256) k_filter_pcr(const Prob* __restrict__ probs, StateRef ref, int d) {
+  extern __shared__ double lds[];
+  const Prob& P = probs[blockIdx.y];
+  if (d >= P.ndim || !(P.falpha < 0.5) || !filt_pcr(P, d)) return;
+  const int nlines = interior_lines(P, d);
+  const bool periodic = P.bc[d][0] == BC_PERIODIC;
+  const int g = P.g[d], n = P.n[d], N = P.N[d], sd = P.s[d];
+  const double al = P.falpha;
+  double* Q = ref.state(P);
+  const size_t T = P.total;
+  double* f = lds;       // the whole line
+  double* r = lds + N;   // interior unknowns
+  for (int blk = blockIdx.x; blk < 5 * nlines; blk += gridDim.x) {
+    const int line = blk % nlines, q = blk / nlines;
+    double* phi = Q + (size_t)q * T + interior_line_base(P, d, line);
+    for (int p = threadIdx.x; p < N; p += blockDim.x) f[p] = phi[(size_t)p * sd];
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      double w[11];
+      for (int k = -5; k <= 5; ++k) w[k + 5] = f[g + (periodic ? wrap(i + k, n) : i + k)];
+      double v = filt_rhs(P, w);
+      if (!periodic) {
+        if (i == 0) v = v - al * f[g - 1];
+        if (i == n - 1) v = v - al * f[g + n];
+      }
+      r[i] = v;
+    }
+    __syncthreads();
+    pcr_lds(r, n, periodic, P.pcrf[d], P.fsteps);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) phi[(size_t)(g + i) * sd] = r[i];
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ launches
+static inline unsigned blocks_for(long long work) { return (unsigned)std::max<long long>(1, (work + 255) / 256); }
+
+static inline unsigned pcr_grid(const Launch& L, long long items) {
+  return (unsigned)std::max<long long>(1, std::min<long long>(items, L.pcr_blocks > 0 ? L.pcr_blocks : 16384));
+}
+
+template <typename R>
+void launch_grad_c6(const Launch& L, StateRef ref, int d) {
+  if (L.pcr_dir[d]) {
+    const unsigned lds = (unsigned)(2 * L.max_N[d] * sizeof(double));
+    LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c6_pcr<R>, dim3(pcr_grid(L, 5 * L.lines[d]), L.nprob),
+                                               dim3(256), lds, L.stream, L.probs, ref, d));
+  }
+  if (L.thomas_dir[d])
+    LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c6<R>, dim3(blocks_for(L.lines[d]), L.nprob), dim3(256), 0,
+                                               L.stream, L.probs, ref, d));
+}
+
+template <typename R>
+void launch_c6_faces(const Launch& L, StateRef ref, int d, int accumulate, const RKRef* rr, int stage, double a,
+                     double b) {
+  if (L.face_pcr[d]) {
+    const unsigned lds = (unsigned)((2 * L.max_n[d] + 4) * sizeof(double));
+    LG_TIMED(L, KC_C6_FACES, hipLaunchKernelGGL(k_c6_faces_pcr<R>, dim3(pcr_grid(L, 5 * L.sweep_rows[d]), L.nprob),
+                                                dim3(256), lds, L.stream, L.probs, ref, d));
+  }
+  if (L.face_thomas[d]) {
+    FaceOut o{ref, rr ? *rr : RKRef{nullptr, nullptr, nullptr}, accumulate, rr ? 1 : 0, stage, a, b};
+    LG_TIMED(L, KC_C6_FACES, hipLaunchKernelGGL(k_c6_faces<R>, dim3(blocks_for(L.sweep_rows[d]), L.nprob),
+                                                dim3(256), 0, L.stream, L.probs, o, d));
+  }
+}
+
+void launch_filter(const Launch& L, StateRef ref, int d) {
+  launch_bc_cons(L, ref, d);
+  if (L.filt_pcr[d]) {
+    const unsigned lds = (unsigned)((L.max_N[d] + L.max_n[d]) * sizeof(double));
+    LG_TIMED(L, KC_FILTER, hipLaunchKernelGGL(k_filter_pcr, dim3(pcr_grid(L, 5 * L.sweep_rows[d]), L.nprob),
+                                              dim3(256), lds, L.stream, L.probs, ref, d));
+  }
+  if (L.filt_thomas[d])
+    LG_TIMED(L, KC_FILTER, hipLaunchKernelGGL(k_filter, dim3(blocks_for(L.sweep_rows[d]), L.nprob), dim3(256), 0,
+                                              L.stream, L.probs, ref, d));
+}
+
+template void launch_grad_c6<float>(const Launch&, StateRef, int);
+template void launch_grad_c6<double>(const Launch&, StateRef, int);
+template void launch_c6_faces<float>(const Launch&, StateRef, int, int, const RKRef*, int, double, double);
+template void launch_c6_faces<double>(const Launch&, StateRef, int, int, const RKRef*, int, double, double);
+
+}  // namespace lg

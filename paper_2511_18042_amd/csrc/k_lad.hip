@@ -16,7 +16,9 @@
 //
 // The central convective flux of LAD-E4 is written in flux form: the E4 derivative of a
 // node flux equals the difference of its fourth-order interface interpolation, so the
-// node fluxes F^c + F^v are stored here and interpolated in the interface sweep.
+// node fluxes F^c + F^v are stored here and interpolated in the interface sweep.  LAD-C6
+// (Sec. 3, Alg. 1) runs the same kernels on compact sixth-order gradients solved
+// beforehand (k_compact.hip), and its interface fluxes are tridiagonal solves there.
 // Fourth differences use five points; all derivatives use unit computational spacing.
 #include "lgbr_dev.h"
 #include "lgbr_kernels.h"
@@ -143,6 +145,15 @@ __device__ __forceinline__ void e4_grads_zm(const Prob& P, const R* W, int idx, 
   }
 }
 
+// computational derivatives of the 5 primitives at idx read from the gradient arrays
+// (LAD-C6: compact sixth-order gradients solved beforehand)
+template <typename R>
+__device__ __forceinline__ void stored_grads(const Prob& P, int idx, R gl[3][5]) {
+  const size_t T = P.total;
+  for (int l = 0; l < 3; ++l)
+    for (int q = 0; q < 5; ++q) gl[l][q] = l < P.ndim ? static_cast<const R*>(P.G[l])[q * T + idx] : R(0);
+}
+
 // ------------------------------------------------------------------ grid factors
 // Delta x_l at interior nodes (curvilinear grids; once per context); when the grid is
 // planar along zeta, only the first interior plane is stored
@@ -169,8 +180,8 @@ __global__ void __launch_bounds__(256) k_lad_dx(const Prob* __restrict__ probs) 
 
 // ------------------------------------------------------------------ |S| and theta
 // at positions -2 .. n+1 (the fourth differences of the raw coefficients reach two nodes
-// past the interior); E4 physical gradients recomputed from W
-template <typename R>
+// past the interior); E4 physical gradients recomputed from W (CG: stored gradients)
+template <typename R, bool CG>
 __global__ void __launch_bounds__(256) k_lad_shear(const Prob* __restrict__ probs, int skip_if_any, int zc) {
   const Prob& P = probs[blockIdx.y];
   if (lad_skip(P, skip_if_any)) return;
@@ -180,7 +191,7 @@ __global__ void __launch_bounds__(256) k_lad_shear(const Prob* __restrict__ prob
   R* S = static_cast<R*>(P.S3);
   const size_t T = P.total;
   const int sz = P.s[2];
-  const bool z3 = P.ndim == 3;
+  const bool z3 = P.ndim == 3 && !CG;
   int idx = pos_to_idx(P, c.i, c.j, c.k0);
   ZQ5<R, 5> qz;
   if (z3) qz.prime(W, T, idx, sz);
@@ -191,7 +202,8 @@ __global__ void __launch_bounds__(256) k_lad_shear(const Prob* __restrict__ prob
     if (z3) qz.step(W, T, idx, sz);
     if (!mplane) load_met(P, idx, mt);
     R gl[3][5], D[5][3];
-    e4_grads_zm(P, W, idx, qz, gl);
+    if (CG) stored_grads(P, idx, gl);
+    else e4_grads_zm(P, W, idx, qz, gl);
     to_physical(P.ndim, mt, gl, D);
     R S2 = R(0);
     for (int i = 0; i < 3; ++i)
@@ -206,7 +218,7 @@ __global__ void __launch_bounds__(256) k_lad_shear(const Prob* __restrict__ prob
 
 // ------------------------------------------------------------------ raw coefficients
 // at interior nodes; e = p / ((gamma - 1) rho) from W wherever needed
-template <typename R>
+template <typename R, bool CG>
 __global__ void __launch_bounds__(256) k_lad_raw(const Prob* __restrict__ probs, int skip_if_any, int zc) {
   const Prob& P = probs[blockIdx.y];
   if (lad_skip(P, skip_if_any)) return;
@@ -246,7 +258,8 @@ __global__ void __launch_bounds__(256) k_lad_raw(const Prob* __restrict__ probs,
       load_gx(idx);
     }
     R gl[3][5], D[5][3];
-    e4_grads_zm(P, W, idx, qz, gl);
+    if (CG) stored_grads(P, idx, gl);
+    else e4_grads_zm(P, W, idx, qz, gl);
     to_physical(P.ndim, mt, gl, D);
     R rho = W[idx], p = W[4 * T + idx];
     R ri = rcp(rho);
@@ -258,8 +271,11 @@ __global__ void __launch_bounds__(256) k_lad_raw(const Prob* __restrict__ probs,
       de[j] = (D[4][j] * ri - p * D[0][j] * (ri * ri)) * igm1;
       gr[j] = D[0][j];
     }
-    R inr = rcp(sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]) + R(1e-32));
-    R ine = rcp(sqrt(de[0] * de[0] + de[1] * de[1] + de[2] * de[2]) + R(1e-32));
+    // regularised unit vectors g / (|g| + 1e-32), formed in FP64: in FP32 the squares of
+    // tiny gradient components underflow (1e-32 is below the square root of its normal
+    // range) and would leave an unbounded projection
+    const double inr = 1.0 / (sqrt((double)gr[0] * gr[0] + (double)gr[1] * gr[1] + (double)gr[2] * gr[2]) + 1e-32);
+    const double ine = 1.0 / (sqrt((double)de[0] * de[0] + (double)de[1] * de[1] + (double)de[2] * de[2]) + 1e-32);
     R Tt = R(P.gamma * P.Mref * P.Mref) * p * ri;
     R cs = sqrt(R(P.gamma) * p * ri);
     R fsw = theta < R(0) ? theta * theta * rcp(theta * theta + om2 + R(1e-32)) : R(0);
@@ -273,8 +289,8 @@ __global__ void __launch_bounds__(256) k_lad_raw(const Prob* __restrict__ probs,
         dx[l] = (R)P.h[l];
       }
       R dmu2 = dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2];
-      R dbeta = (dx[0] * gr[0] + dx[1] * gr[1] + dx[2] * gr[2]) * inr;
-      R dkap = fabs(dx[0] * de[0] + dx[1] * de[1] + dx[2] * de[2]) * ine;
+      R dbeta = (R)(((double)dx[0] * gr[0] + (double)dx[1] * gr[1] + (double)dx[2] * gr[2]) * inr);
+      R dkap = (R)(fabs((double)dx[0] * de[0] + (double)dx[1] * de[1] + (double)dx[2] * de[2]) * ine);
       R f4S, f4t, f4e;
       if (l < 2) {
         const int s = P.s[l];
@@ -461,8 +477,8 @@ __device__ __forceinline__ void lad_node_flux(const Prob& P, const LadNode<R>& s
 }
 
 // F^c + F^v for every active direction at positions -2 .. n+1; gradients recomputed from
-// W, coefficients read at the image of the node
-template <typename R>
+// W (CG: stored gradients), coefficients read at the image of the node
+template <typename R, bool CG>
 __global__ void __launch_bounds__(256) k_lad_nodeflux(const Prob* __restrict__ probs, int coef_buf, int skip_if_any,
                                                       int zc) {
   const Prob& P = probs[blockIdx.y];
@@ -474,19 +490,21 @@ __global__ void __launch_bounds__(256) k_lad_nodeflux(const Prob* __restrict__ p
   const size_t T = P.total;
   const int sz = P.s[2];
   const bool z3 = P.ndim == 3;
+  const bool zq = z3 && !CG;
   const int ci = scalar_image(P, 0, c.i);
   const int cj = P.ndim > 1 ? scalar_image(P, 1, c.j) : c.j;
   int idx = pos_to_idx(P, c.i, c.j, c.k0);
   ZQ5<R, 5> qz;
-  if (z3) qz.prime(W, T, idx, sz);
+  if (zq) qz.prime(W, T, idx, sz);
   R mt[10];
   const bool mplane = P.met_planar;
   if (mplane) load_met(P, idx, mt);   // one plane of metrics serves the whole column
   for (int k = c.k0; k < c.k1; ++k, idx += sz) {
-    if (z3) qz.step(W, T, idx, sz);
+    if (zq) qz.step(W, T, idx, sz);
     if (!mplane) load_met(P, idx, mt);
     R gl[3][5];
-    e4_grads_zm(P, W, idx, qz, gl);
+    if (CG) stored_grads(P, idx, gl);
+    else e4_grads_zm(P, W, idx, qz, gl);
     LadNode<R> s;
     lad_node_state(P, W, C, idx, pos_to_idx(P, ci, cj, z3 ? scalar_image(P, 2, k) : k), mt, gl, s);
     for (int l = 0; l < P.ndim; ++l) {
@@ -624,12 +642,19 @@ static inline dim3 g1(long long work, int nprob, long long cap = 1LL << 30) {
 }
 
 template <typename R>
-void launch_lad(const Launch& L, int skip_if_any) {
+void launch_lad(const Launch& L, int skip_if_any, int cg) {
   const int zb = zm_chunk(L, -2, 2), zi = zm_chunk(L, 0, 0);
-  LG_TIMED(L, KC_LAD_NODE, hipLaunchKernelGGL(k_lad_shear<R>, zm_grid(L, -2, 2, ZM_TX, ZM_TY), dim3(256), 0,
-                                              L.stream, L.probs, skip_if_any, zb));
-  LG_TIMED(L, KC_LAD_RAW, hipLaunchKernelGGL(k_lad_raw<R>, zm_grid(L, 0, 0, ZM_TX, ZM_TY), dim3(256), 0, L.stream,
-                                             L.probs, skip_if_any, zi));
+  if (cg) {
+    LG_TIMED(L, KC_LAD_NODE, hipLaunchKernelGGL((k_lad_shear<R, true>), zm_grid(L, -2, 2, ZM_TX, ZM_TY), dim3(256),
+                                                0, L.stream, L.probs, skip_if_any, zb));
+    LG_TIMED(L, KC_LAD_RAW, hipLaunchKernelGGL((k_lad_raw<R, true>), zm_grid(L, 0, 0, ZM_TX, ZM_TY), dim3(256), 0,
+                                               L.stream, L.probs, skip_if_any, zi));
+  } else {
+    LG_TIMED(L, KC_LAD_NODE, hipLaunchKernelGGL((k_lad_shear<R, false>), zm_grid(L, -2, 2, ZM_TX, ZM_TY), dim3(256),
+                                                0, L.stream, L.probs, skip_if_any, zb));
+    LG_TIMED(L, KC_LAD_RAW, hipLaunchKernelGGL((k_lad_raw<R, false>), zm_grid(L, 0, 0, ZM_TX, ZM_TY), dim3(256), 0,
+                                               L.stream, L.probs, skip_if_any, zi));
+  }
   constexpr int GTY = sizeof(R) == 4 ? 16 : 8;
   LG_TIMED(L, KC_GAUSS, hipLaunchKernelGGL((k_gauss_xy<R, GTY>), zm_grid(L, 0, 0, 64, GTY), dim3(256), 0, L.stream,
                                            L.probs, skip_if_any, zi));
@@ -642,9 +667,15 @@ void launch_lad(const Launch& L, int skip_if_any) {
 static inline int lad_coef_buf(const Launch& L) { return L.ndim > 2 ? 0 : 1; }
 
 template <typename R>
-void launch_lad_nodeflux(const Launch& L, int skip_if_any) {
-  LG_TIMED(L, KC_LAD_FLUX, hipLaunchKernelGGL(k_lad_nodeflux<R>, zm_grid(L, -2, 2, ZM_TX, ZM_TY), dim3(256), 0,
-                                              L.stream, L.probs, lad_coef_buf(L), skip_if_any, zm_chunk(L, -2, 2)));
+void launch_lad_nodeflux(const Launch& L, int skip_if_any, int cg) {
+  const dim3 grid = zm_grid(L, -2, 2, ZM_TX, ZM_TY);
+  const int zb = zm_chunk(L, -2, 2);
+  if (cg)
+    LG_TIMED(L, KC_LAD_FLUX, hipLaunchKernelGGL((k_lad_nodeflux<R, true>), grid, dim3(256), 0, L.stream, L.probs,
+                                                lad_coef_buf(L), skip_if_any, zb));
+  else
+    LG_TIMED(L, KC_LAD_FLUX, hipLaunchKernelGGL((k_lad_nodeflux<R, false>), grid, dim3(256), 0, L.stream, L.probs,
+                                                lad_coef_buf(L), skip_if_any, zb));
 }
 
 template <typename R>
@@ -673,14 +704,14 @@ void launch_gbr_viscflux(const Launch& L, int skip_if_any, int region) {
                                           L.probs, skip_if_any, region));
 }
 
-template void launch_lad<float>(const Launch&, int);
-template void launch_lad<double>(const Launch&, int);
+template void launch_lad<float>(const Launch&, int, int);
+template void launch_lad<double>(const Launch&, int, int);
 template void launch_lad_geometry<float>(const Launch&);
 template void launch_lad_geometry<double>(const Launch&);
 template void launch_lad_sweep<float>(const Launch&, StateRef, const RKRef*, int, double, double, int);
 template void launch_lad_sweep<double>(const Launch&, StateRef, const RKRef*, int, double, double, int);
-template void launch_lad_nodeflux<float>(const Launch&, int);
-template void launch_lad_nodeflux<double>(const Launch&, int);
+template void launch_lad_nodeflux<float>(const Launch&, int, int);
+template void launch_lad_nodeflux<double>(const Launch&, int, int);
 template void launch_gbr_viscflux<float>(const Launch&, int, int);
 template void launch_gbr_viscflux<double>(const Launch&, int, int);
 

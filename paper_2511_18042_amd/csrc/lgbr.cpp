@@ -9,7 +9,10 @@
 //           -> node fluxes F^c + F^v per direction
 //   [hyb]   flag dilation (per-cell) or any-flag reduction (global)
 //   -> one interface sweep per direction (flux + FP64 difference into dQ/dt)
-// RK3: dt reduction from U^n, then three (stage RHS -> stage combination) passes.
+//   [LAD-C6] compact gradients -> LAD coefficients and node fluxes from them -> compact
+//           interface-flux solves per direction
+// RK3: dt reduction from U^n, then three (stage RHS -> stage combination) passes; LAD-C6
+// steps end with the implicit filter along each direction.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -48,6 +51,8 @@ void dev_free(void* p) {
 
 struct Cfg {
   int ndim, precision, grad, hybrid_mode, viscous, dilate;
+  int lad_c6, filter;   // LAD-C6 context; its steps end with the implicit filter
+  double falpha;
 };
 
 }  // namespace
@@ -90,9 +95,29 @@ const double RK_B[3] = {1.0, 0.25, 2.0 / 3.0};
 // One right-hand side evaluation of the state `ref`.  With rk set, the RK stage
 // combination follows: inside the all-LAD interface pass where that pass runs, as its own
 // kernel after the per-direction sweeps otherwise.
+// LAD-C6 stage (Alg. 1): compact gradients of the primitives, the LAD coefficients and
+// node fluxes from them, then the compact interface fluxes differenced per direction (the
+// last direction forms the RK stage).
+template <typename R>
+void enqueue_rhs_c6(const Launch& L, const Cfg& c, StateRef ref, const RKRef* rk, int stage) {
+  for (int d = 0; d < c.ndim; ++d) lg::launch_bc_cons(L, ref, d);
+  lg::launch_prim<R>(L, ref, 0, nullptr);
+  for (int d = 0; d < c.ndim; ++d) lg::launch_grad_c6<R>(L, ref, d);
+  lg::launch_lad<R>(L, -1, 1);
+  lg::launch_lad_nodeflux<R>(L, -1, 1);
+  const double a = rk ? RK_A[stage] : 0.0, b = rk ? RK_B[stage] : 0.0;
+  for (int d = 0; d < c.ndim; ++d)
+    lg::launch_c6_faces<R>(L, ref, d, d > 0 ? 1 : 0, d == c.ndim - 1 ? rk : nullptr, stage, a, b);
+  if (rk) lg::launch_stage_ghosts(L, *rk, stage, -1);
+}
+
 template <typename R>
 void enqueue_rhs(const Launch& L, const Cfg& c, int scheme, StateRef ref, const uint8_t* force,
                  const RKRef* rk = nullptr, int stage = 0) {
+  if (scheme == LG_SCHEME_LAD && c.lad_c6) {
+    enqueue_rhs_c6<R>(L, c, ref, rk, stage);
+    return;
+  }
   for (int d = 0; d < c.ndim; ++d) lg::launch_bc_cons(L, ref, d);
   const bool hyb = scheme == LG_SCHEME_HYBRID;
   lg::launch_prim<R>(L, ref, hyb ? 1 : 0, force);
@@ -159,6 +184,8 @@ void enqueue_rk3(const Launch& L, const Cfg& c, int scheme, double* Qx, double* 
     RKRef rr{Qx, nullptr, nullptr};
     enqueue_rhs<R>(L, c, scheme, ref, nullptr, &rr, s);
   }
+  if (scheme == LG_SCHEME_LAD && c.lad_c6 && c.filter)   // FILTER_CALLS after the last stage
+    for (int d = 0; d < c.ndim; ++d) lg::launch_filter(L, StateRef{Qx, nullptr, 0}, d);
 }
 
 lg_status last_hip() { return hipGetLastError() == hipSuccess ? LG_OK : LG_EHIP; }
@@ -245,6 +272,105 @@ std::vector<double> pcr_table(int L, bool periodic, int steps) {
   return t;
 }
 
+// Thomas tables (cp[m], inv[m], a[m]; see k_compact.hip) of the unit-diagonal tridiagonal
+// system with sub-diagonal a[i] and super-diagonal c[i] (a[0] = c[m-1] = 0)
+std::vector<double> thomas_table(const std::vector<double>& a, const std::vector<double>& c) {
+  const int m = (int)a.size();
+  std::vector<double> t(3 * (size_t)m, 0.0);
+  double* cp = t.data();
+  double* inv = t.data() + m;
+  for (int i = 0; i < m; ++i) {
+    const double den = 1.0 - (i > 0 ? a[i] * cp[i - 1] : 0.0);
+    inv[i] = 1.0 / den;
+    cp[i] = c[i] / den;
+    t[2 * (size_t)m + i] = a[i];
+  }
+  return t;
+}
+
+// cyclic [alpha, 1, alpha] of n unknowns: cp[n], inv[n], z[n], fac, alpha (see k_compact.hip)
+std::vector<double> cyclic_table(int n, double al) {
+  std::vector<double> t(3 * (size_t)n + 2, 0.0);
+  double* cp = t.data();
+  double* inv = t.data() + n;
+  double* z = t.data() + 2 * n;
+  std::vector<double> b(n, 1.0);
+  b[0] = 2.0;
+  b[n - 1] = 1.0 + al * al;
+  for (int i = 0; i < n; ++i) {
+    const double den = b[i] - (i > 0 ? al * cp[i - 1] : 0.0);
+    inv[i] = 1.0 / den;
+    cp[i] = (i < n - 1 ? al : 0.0) / den;
+  }
+  std::vector<double> u(n, 0.0), dp(n);
+  u[0] = -1.0;
+  u[n - 1] = al;
+  for (int i = 0; i < n; ++i) dp[i] = (u[i] - (i > 0 ? al * dp[i - 1] : 0.0)) * inv[i];
+  z[n - 1] = dp[n - 1];
+  for (int i = n - 2; i >= 0; --i) z[i] = dp[i] - cp[i] * z[i + 1];
+  t[3 * (size_t)n] = 1.0 / (1.0 + z[0] - al * z[n - 1]);
+  t[3 * (size_t)n + 1] = al;
+  return t;
+}
+
+// PCR elimination factors k1[steps][L], k2[steps][L], binv[L] of the unit-diagonal system
+// with sub / super-diagonals a, c (periodic: cyclic, indices wrapped)
+std::vector<double> pcr_table_ac(std::vector<double> a, std::vector<double> c, bool periodic, int steps) {
+  const int L = (int)a.size();
+  std::vector<double> b(L, 1.0), na(L), nb(L), nc(L);
+  std::vector<double> t((size_t)(2 * steps + 1) * L, 0.0);
+  for (int st = 0; st < steps; ++st) {
+    const int s = 1 << st;
+    for (int i = 0; i < L; ++i) {
+      int im = i - s, ip = i + s;
+      bool hm = true, hp = true;
+      if (periodic) {
+        im = ((im % L) + L) % L;
+        ip = ip % L;
+      } else {
+        hm = im >= 0;
+        hp = ip < L;
+      }
+      const double k1 = hm ? a[i] / b[im] : 0.0;
+      const double k2 = hp ? c[i] / b[ip] : 0.0;
+      na[i] = hm ? -k1 * a[im] : 0.0;
+      nc[i] = hp ? -k2 * c[ip] : 0.0;
+      nb[i] = b[i] - (hm ? k1 * c[im] : 0.0) - (hp ? k2 * a[ip] : 0.0);
+      t[(size_t)st * L + i] = k1;
+      t[(size_t)(steps + st) * L + i] = k2;
+    }
+    a.swap(na);
+    b.swap(nb);
+    c.swap(nc);
+  }
+  for (int i = 0; i < L; ++i) t[(size_t)2 * steps * L + i] = 1.0 / b[i];
+  return t;
+}
+
+// Right-hand-side weights of the tenth-order implicit filter: the maximal-order member has
+// T(w) = 1 - (1 - 2 alpha) sin^10(w/2) / (1 + 2 alpha cos w); with
+// sin^10(w/2) = (252 - 420 cos w + 240 cos 2w - 90 cos 3w + 20 cos 4w - 2 cos 5w) / 1024
+// the numerator sum_k a_k cos(k w) gives a_k directly.
+void filter_weights(double al, double a[6]) {
+  const double e = (1.0 - 2.0 * al) / 1024.0;
+  a[0] = 1.0 - 252.0 * e;
+  a[1] = 2.0 * al + 420.0 * e;
+  a[2] = -240.0 * e;
+  a[3] = 90.0 * e;
+  a[4] = -20.0 * e;
+  a[5] = 2.0 * e;
+}
+
+// PCR steps that leave couplings below 1e-22 of the diagonal: the eliminated couplings of
+// [alpha, 1, alpha] shrink as r^(2^k), r = (1 - sqrt(1 - 4 alpha^2)) / (2 alpha)
+int filter_pcr_steps(double al) {
+  if (!(al > 0.0)) return 1;
+  const double r = (1.0 - std::sqrt(1.0 - 4.0 * al * al)) / (2.0 * al);
+  int k = 1;
+  while (k < 12 && std::pow(r, std::ldexp(1.0, k)) > 1e-22) ++k;
+  return k;
+}
+
 void fill_launch(Launch& L, const Prob& P) {
   for (int d = 0; d < P.ndim; ++d) {
     // mirror of use_pcr() in k_grad.hip
@@ -258,7 +384,16 @@ void fill_launch(Launch& L, const Prob& P) {
     else L.thomas_dir[d] = 1;
     if (periodic && P.n[d] < 128) L.has_short_periodic = 1;
     if (P.bc[d][0] == LG_BC_FIXED || P.bc[d][1] == LG_BC_FIXED) L.has_fixed = 1;
+    if (P.lad_c6) {
+      if (lg::c6_face_pcr(P, d)) L.face_pcr[d] = 1;
+      else L.face_thomas[d] = 1;
+      if (P.falpha < 0.5) {
+        if (lg::filt_pcr(P, d)) L.filt_pcr[d] = 1;
+        else L.filt_thomas[d] = 1;
+      }
+    }
   }
+  L.max_fsteps = std::max(L.max_fsteps, P.fsteps);
   L.max_total = std::max<long long>(L.max_total, P.total);
   L.max_cells = std::max<long long>(L.max_cells, (long long)P.n[0] * P.n[1] * P.n[2]);
   for (int d = 0; d < 3; ++d) {
@@ -329,6 +464,8 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
   if (opts->hybrid_mode != LG_HYB_PERCELL && opts->hybrid_mode != LG_HYB_GLOBAL) return LG_EINVAL;
   if (opts->dilate < 0 || opts->dilate > 4 || opts->seg < 0) return LG_EINVAL;
   if (!(opts->cfl > 0.0)) return LG_EINVAL;
+  if (opts->lad_scheme != LG_LAD_E4 && opts->lad_scheme != LG_LAD_C6) return LG_EINVAL;
+  if (opts->lad_scheme == LG_LAD_C6 && !(opts->filter_alpha >= 0.0 && opts->filter_alpha <= 0.5)) return LG_EINVAL;
 
   lg_ctx* c = new (std::nothrow) lg_ctx();
   if (!c) return LG_ENOMEM;
@@ -370,7 +507,14 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
   P.cfl = opts->cfl;
   P.dilate = opts->dilate;
   P.grad_c4 = opts->grad == LG_GRAD_C4;
-  c->cfg = Cfg{G.ndim, opts->precision, opts->grad, opts->hybrid_mode, gas->viscous, opts->dilate};
+  const int c6 = opts->lad_scheme == LG_LAD_C6;
+  P.lad_c6 = c6;
+  P.falpha = c6 ? opts->filter_alpha : 0.5;
+  const int filt = c6 && P.falpha < 0.5;
+  filter_weights(P.falpha, P.fcoef);
+  P.fsteps = filt ? filter_pcr_steps(P.falpha) : 0;
+  c->cfg = Cfg{G.ndim, opts->precision, opts->grad, opts->hybrid_mode, gas->viscous, opts->dilate, c6, filt,
+               P.falpha};
 
   const size_t T = (size_t)total;
   const size_t rs = opts->precision == LG_MIXED ? sizeof(float) : sizeof(double);
@@ -382,7 +526,7 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
   };
   P.W = A(5 * T * rs);
   for (int d = 0; d < G.ndim; ++d) P.G[d] = A(5 * T * rs);
-  if (opts->grad == LG_GRAD_C4) P.T64 = static_cast<double*>(A(5 * T * sizeof(double)));
+  if (opts->grad == LG_GRAD_C4 || c6) P.T64 = static_cast<double*>(A(5 * T * sizeof(double)));
   P.Om = A(T * rs);
   P.f = static_cast<uint8_t*>(A(T));
   P.ft = static_cast<uint8_t*>(A(T));
@@ -492,6 +636,51 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
         return ok ? LG_EHIP : LG_ENOMEM;
       }
       P.pcr[d] = pd;
+    }
+  }
+  if (c6) {
+    // factor tables of the LAD-C6 systems (layouts in k_compact.hip)
+    auto upload = [&](const std::vector<double>& v) -> const double* {
+      double* p = static_cast<double*>(A(v.size() * sizeof(double)));
+      if (!ok) return nullptr;
+      if (hipMemcpy(p, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        ok = false;
+        return nullptr;
+      }
+      return p;
+    };
+    const double a3 = 1.0 / 3.0;
+    for (int d = 0; d < G.ndim && ok; ++d) {
+      const bool periodic = P.bc[d][0] == LG_BC_PERIODIC;
+      const int n = P.n[d], N = P.N[d];
+      // gradients: all N nodes, one-sided end rows, C4 rows next to them
+      std::vector<double> ga(N, a3), gc(N, a3);
+      ga[0] = gc[0] = ga[N - 1] = gc[N - 1] = 0.0;
+      ga[1] = gc[1] = ga[N - 2] = gc[N - 2] = 0.25;
+      std::vector<double> pa(n, a3), pc(n, a3);   // cyclic rows
+      P.tri6[d] = upload(periodic ? cyclic_table(n, a3) : thomas_table(ga, gc));
+      P.pcr6[d] = upload(periodic ? pcr_table_ac(pa, pc, true, lg::LG_PCR_STEPS)
+                                  : pcr_table_ac(ga, gc, false, lg::LG_PCR_STEPS));
+      // interface fluxes: n - 1 interior faces between I4 boundary faces, or n cyclic faces
+      std::vector<double> fa(n - 1, a3), fc(n - 1, a3);
+      fa[0] = 0.0;
+      fc[n - 2] = 0.0;
+      P.trc[d] = upload(periodic ? cyclic_table(n, a3) : thomas_table(fa, fc));
+      P.pcrc[d] = upload(periodic ? pcr_table_ac(pa, pc, true, lg::LG_PCR_STEPS)
+                                  : pcr_table_ac(fa, fc, false, lg::LG_PCR_STEPS));
+      if (filt) {
+        const double al = P.falpha;
+        std::vector<double> ka(n, al), kc(n, al);
+        std::vector<double> qa(n, al), qc(n, al);
+        ka[0] = 0.0;
+        kc[n - 1] = 0.0;
+        P.trf[d] = upload(periodic ? cyclic_table(n, al) : thomas_table(ka, kc));
+        P.pcrf[d] = upload(pcr_table_ac(periodic ? qa : ka, periodic ? qc : kc, periodic, P.fsteps));
+      }
+    }
+    if (!ok) {
+      lg_destroy(c);
+      return LG_ENOMEM;
     }
   }
   c->dp = static_cast<Prob*>(A(sizeof(Prob)));
@@ -630,12 +819,21 @@ static lg_status rhs_common(lg_ctx* c, int scheme, double* Q, double* dQ, const 
 lg_status cgbr_rhs(lg_ctx* c, double* Q, double* dQdt) { return rhs_common(c, LG_SCHEME_CGBR, Q, dQdt, nullptr, nullptr); }
 lg_status lad_rhs(lg_ctx* c, double* Q, double* dQdt) { return rhs_common(c, LG_SCHEME_LAD, Q, dQdt, nullptr, nullptr); }
 lg_status hybrid_rhs(lg_ctx* c, double* Q, double* dQdt, const uint8_t* flags_in, uint8_t* flags_out) {
+  if (c && c->cfg.lad_c6) return LG_EUNSUPPORTED;
   return rhs_common(c, LG_SCHEME_HYBRID, Q, dQdt, flags_in, flags_out);
+}
+
+lg_status lad_filter(lg_ctx* c, double* Q) {
+  if (!c || !Q) return LG_EINVAL;
+  if (!c->cfg.filter) return LG_EUNSUPPORTED;
+  for (int d = 0; d < c->cfg.ndim; ++d) lg::launch_filter(c->L, StateRef{Q, nullptr, 0}, d);
+  return last_hip();
 }
 
 lg_status rk3_step(lg_ctx* c, int scheme, double* Q, double t_end, double* t_inout) {
   if (!c || !Q || !t_inout) return LG_EINVAL;
   if (scheme < LG_SCHEME_CGBR || scheme > LG_SCHEME_HYBRID) return LG_EINVAL;
+  if (scheme == LG_SCHEME_HYBRID && c->cfg.lad_c6) return LG_EUNSUPPORTED;
   return dispatch(c->cfg.precision, [&](auto r) {
     using R = decltype(r);
     enqueue_rk3<R>(c->L, c->cfg, scheme, Q, t_inout, t_end);
@@ -645,6 +843,7 @@ lg_status rk3_step(lg_ctx* c, int scheme, double* Q, double t_end, double* t_ino
 lg_status lg_rk3_stage(lg_ctx* c, int scheme, int stage, const double* Un, double* Us, double dt) {
   if (!c || !Un || !Us || stage < 0 || stage > 2) return LG_EINVAL;
   if (scheme < LG_SCHEME_CGBR || scheme > LG_SCHEME_HYBRID) return LG_EINVAL;
+  if (scheme == LG_SCHEME_HYBRID && c->cfg.lad_c6) return LG_EUNSUPPORTED;
   return dispatch(c->cfg.precision, [&](auto r) {
     using R = decltype(r);
     lg::launch_set_dt(c->L, dt);
@@ -696,12 +895,16 @@ lg_status lg_batch_create(lg_batch** out, lg_ctx* const* ctxs, double* const* Q,
   if (!out || !ctxs || !Q || !t || !t_end || n < 1 || nsteps < 1) return LG_EINVAL;
   if (scheme < LG_SCHEME_CGBR || scheme > LG_SCHEME_HYBRID) return LG_EINVAL;
   *out = nullptr;
+  for (int i = 0; i < n; ++i)
+    if (!ctxs[i]) return LG_EINVAL;
   const Cfg& c0 = ctxs[0]->cfg;
+  if (scheme == LG_SCHEME_HYBRID && c0.lad_c6) return LG_EUNSUPPORTED;
   for (int i = 0; i < n; ++i) {
     if (!ctxs[i] || !Q[i] || !t[i]) return LG_EINVAL;
     const Cfg& ci = ctxs[i]->cfg;
     if (ci.ndim != c0.ndim || ci.precision != c0.precision || ci.grad != c0.grad ||
-        ci.hybrid_mode != c0.hybrid_mode || ci.viscous != c0.viscous || ci.dilate != c0.dilate)
+        ci.hybrid_mode != c0.hybrid_mode || ci.viscous != c0.viscous || ci.dilate != c0.dilate ||
+        ci.lad_c6 != c0.lad_c6 || ci.filter != c0.filter)
       return LG_EINVAL;
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == ctxs[i]) return LG_EINVAL;  // workspaces must not be shared

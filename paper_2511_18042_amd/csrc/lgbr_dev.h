@@ -64,6 +64,17 @@ struct Prob {
   const double* coords;  // node coordinates             [3][total]  (curvilinear only)
   const double* tri[3];  // compact-solve LU tables per direction (see k_grad.hip)
   const double* pcr[3];  // compact-solve PCR factors per direction (see k_grad.hip)
+  // LAD-C6 (see k_compact.hip for the table layouts)
+  int lad_c6;            // the LAD scheme uses compact sixth-order differences
+  double falpha;         // alpha_f of the implicit filter (0.5: no filter)
+  double fcoef[6];       // filter right-hand-side weights a_0 .. a_5
+  int fsteps;            // PCR reduction steps of the filter systems
+  const double* tri6[3]; // C6 gradient systems: Thomas / cyclic tables
+  const double* pcr6[3]; //   and PCR factors
+  const double* trc[3];  // C6 interface-flux systems
+  const double* pcrc[3];
+  const double* trf[3];  // filter systems
+  const double* pcrf[3];
   // device scalars
   double* dt;
   double* t;

@@ -49,7 +49,7 @@ __device__ __forceinline__ bool rk_combine_node(const Prob& P, const RKRef& rr, 
 enum KClass {
   KC_BC = 0, KC_PRIM, KC_FLAGS, KC_GRAD_E6, KC_GRAD_C4, KC_SENSOR, KC_VISC, KC_LAD_NODE, KC_LAD_RAW,
   KC_GAUSS, KC_LAD_FLUX, KC_SWEEP_X, KC_SWEEP_Y, KC_SWEEP_Z, KC_COMBINE, KC_DT, KC_BC_SCALAR, KC_LAD_SWEEP,
-  KC_COUNT
+  KC_C6_FACES, KC_FILTER, KC_COUNT
 };
 
 // Event pairs recorded around launches while enabled (never during graph capture).
@@ -80,6 +80,9 @@ struct Launch {
   int has_fixed;           // some problem has a FIXED face (caller-owned ghosts)
   int pcr_dir[3];          // some problem solves its lines along d by PCR
   int thomas_dir[3];       // some problem solves its lines along d one lane per line
+  int face_pcr[3], face_thomas[3];   // the same for the LAD-C6 interface-flux systems
+  int filt_pcr[3], filt_thomas[3];   // and for the implicit-filter systems
+  int max_fsteps;          // most PCR steps of any problem's filter systems
   int ndim;
   int seg;                 // nodes per thread in the strided sweeps (0: heuristic)
   int pcr_blocks;          // persistent workgroups of the PCR line solves (0: heuristic)
@@ -152,8 +155,9 @@ template <typename R> void launch_grad_c4(const Launch& L, StateRef ref, int d, 
 template <typename R> void launch_sensor(const Launch& L, int skip_if_any, int region);
 template <typename R> void launch_gbr_viscflux(const Launch& L, int skip_if_any, int region);
 // LAD: filtered coefficients; node fluxes; the grid factors Delta x_l once per context
-template <typename R> void launch_lad(const Launch& L, int skip_if_any);
-template <typename R> void launch_lad_nodeflux(const Launch& L, int skip_if_any);
+// (cg = 1: gradients read from the gradient arrays instead of E4 from the primitives)
+template <typename R> void launch_lad(const Launch& L, int skip_if_any, int cg = 0);
+template <typename R> void launch_lad_nodeflux(const Launch& L, int skip_if_any, int cg = 0);
 template <typename R> void launch_lad_geometry(const Launch& L);
 // all-LAD interfaces of every direction in one pass; rr == nullptr writes the time
 // derivative, else the RK stage combination (and the ghost copy of the stage result)
@@ -166,5 +170,30 @@ template <typename R>
 void launch_sweep(const Launch& L, StateRef ref, int d, int sel, int accumulate, int skip_if_any,
                   const RKRef* rr = nullptr, int stage = 0, double a = 0.0, double b = 0.0);
 void launch_stage_ghosts(const Launch& L, const RKRef& rr, int stage, int skip_if_any);
+// LAD-C6: compact sixth-order gradients of the primitives along d; compact interface
+// fluxes along d differenced into dQ/dt (accumulate: add to what earlier directions
+// wrote; rr != nullptr: this is the last direction and it forms the RK stage); one pass
+// of the implicit filter along d on the state of ref (ghosts of d refilled first)
+template <typename R> void launch_grad_c6(const Launch& L, StateRef ref, int d);
+template <typename R>
+void launch_c6_faces(const Launch& L, StateRef ref, int d, int accumulate, const RKRef* rr, int stage, double a,
+                     double b);
+void launch_filter(const Launch& L, StateRef ref, int d);
+// which kernel solves the lines of each system (shared by the host and the kernels)
+__host__ __device__ inline bool c6_grad_pcr(const Prob& P, int d) {
+  const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+  const long long nlines = (long long)P.N[o1] * P.N[o2];
+  const bool periodic = P.bc[d][0] == BC_PERIODIC;
+  if (P.N[d] > 4096 || (periodic && P.n[d] < (2 << LG_PCR_STEPS))) return false;   // as the C4 solves
+  return d == 0 || 5 * nlines < 131072;
+}
+__host__ __device__ inline bool c6_face_pcr(const Prob& P, int d) {
+  const bool periodic = P.bc[d][0] == BC_PERIODIC;
+  return d == 0 && P.ndim > 1 && P.n[d] <= 3990 && !(periodic && P.n[d] < (2 << LG_PCR_STEPS));
+}
+__host__ __device__ inline bool filt_pcr(const Prob& P, int d) {
+  const bool periodic = P.bc[d][0] == BC_PERIODIC;
+  return d == 0 && P.N[d] <= 4000 && !(periodic && P.n[d] < (2 << P.fsteps));
+}
 
 }  // namespace lg

@@ -21,9 +21,11 @@ SCHEMES = {'cgbr': SCHEME_CGBR, 'lad': SCHEME_LAD, 'hybrid': SCHEME_HYBRID}
 EXPORTS = ('lg_set_allocator', 'lg_strerror', 'lg_create', 'lg_destroy', 'lg_workspace_bytes',
            'lg_metrics_from_coords', 'cgbr_rhs', 'lad_rhs', 'hybrid_rhs', 'rk3_step', 'lg_rk3_stage',
            'lg_compute_dt', 'lg_batch_create', 'lg_batch_run', 'lg_batch_destroy', 'lg_poll_status',
-           'lg_prof_start', 'lg_prof_stop', 'lg_set_tuning', 'lg_get_tuning', 'lg_metrics_planar')
+           'lg_prof_start', 'lg_prof_stop', 'lg_set_tuning', 'lg_get_tuning', 'lg_metrics_planar', 'lad_filter')
 KERNEL_CLASSES = ('bc', 'prim', 'flags', 'grad_e6', 'grad_c4', 'sensor', 'visc', 'lad_node', 'lad_raw', 'gauss',
-                  'lad_flux', 'sweep_x', 'sweep_y', 'sweep_z', 'combine', 'dt', 'bc_scalar', 'lad_sweep')
+                  'lad_flux', 'sweep_x', 'sweep_y', 'sweep_z', 'combine', 'dt', 'bc_scalar', 'lad_sweep',
+                  'c6_faces', 'filter')
+LAD_E4, LAD_C6 = 0, 1
 
 
 class LgGrid(ctypes.Structure):
@@ -41,7 +43,8 @@ class LgOpts(ctypes.Structure):
                 ('omega_thr', ctypes.c_double), ('mp_eps', ctypes.c_double), ('mp_alpha', ctypes.c_double),
                 ('C_mu', ctypes.c_double), ('C_beta', ctypes.c_double), ('C_kappa', ctypes.c_double),
                 ('hybrid_mode', ctypes.c_int), ('rho_thr', ctypes.c_double), ('p_thr', ctypes.c_double),
-                ('dilate', ctypes.c_int), ('seg', ctypes.c_int)]
+                ('dilate', ctypes.c_int), ('seg', ctypes.c_int), ('lad_scheme', ctypes.c_int),
+                ('filter_alpha', ctypes.c_double)]
 
 
 _lib = None
@@ -67,6 +70,7 @@ def load():
         'lg_metrics_from_coords': (I, [ctypes.POINTER(LgGrid), P, P, P]),
         'cgbr_rhs': (I, [P, P, P]),
         'lad_rhs': (I, [P, P, P]),
+        'lad_filter': (I, [P, P]),
         'hybrid_rhs': (I, [P, P, P, P, P]),
         'rk3_step': (I, [P, I, P, D, P]),
         'lg_rk3_stage': (I, [P, I, I, P, P, D]),
@@ -132,10 +136,11 @@ def make_gas(gamma=1.4, Re=1.0, Pr=0.72, Mref=1.0, suth=110.4 / 108.0, viscous=F
 
 def make_opts(grad='E6', precision='fp64', cfl=0.2, omega_thr=0.01, mp_eps=1e-20, mp_alpha=4.0,
               C_mu=0.0, C_beta=1.75, C_kappa=0.01, hybrid_mode='percell', rho_thr=-1.0, p_thr=-1.0,
-              dilate=3, seg=0):
+              dilate=3, seg=0, lad='E4', filter_alpha=0.49):
     return LgOpts(GRAD_C4 if grad == 'C4' else GRAD_E6, MIXED if precision == 'mixed' else FP64, cfl,
                   omega_thr, mp_eps, mp_alpha, C_mu, C_beta, C_kappa,
-                  HYB_GLOBAL if hybrid_mode == 'global' else HYB_PERCELL, rho_thr, p_thr, dilate, seg)
+                  HYB_GLOBAL if hybrid_mode == 'global' else HYB_PERCELL, rho_thr, p_thr, dilate, seg,
+                  LAD_C6 if lad == 'C6' else LAD_E4, float(filter_alpha))
 
 
 def metrics_from_coords(grid, coords, metrics, stream=None):
@@ -178,6 +183,9 @@ class Context:
 
     def lad_rhs(self, Q, dQ):
         _check(self._lib.lad_rhs(self.handle, _ptr(Q), _ptr(dQ)), 'lad_rhs')
+
+    def lad_filter(self, Q):
+        _check(self._lib.lad_filter(self.handle, _ptr(Q)), 'lad_filter')
 
     def hybrid_rhs(self, Q, dQ, flags_in=None, flags_out=None):
         _check(self._lib.hybrid_rhs(self.handle, _ptr(Q), _ptr(dQ), _ptr(flags_in), _ptr(flags_out)),

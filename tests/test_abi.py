@@ -34,11 +34,36 @@ def test_library_exports_every_declared_symbol():
     assert set(declared_functions()) == set(lgbr.EXPORTS)
 
 
-def test_binding_struct_layout_matches_header():
-    # lg_grid: 4 + 12 + 4 + 24 + 4 (+4 pad) + 24 bytes
-    assert ctypes.sizeof(lgbr.LgGrid) == 72
-    assert ctypes.sizeof(lgbr.LgGas) == 48
-    assert ctypes.sizeof(lgbr.LgOpts) == 96
+def test_binding_struct_layout_matches_header(tmp_path):
+    """Field offsets and sizes of the ctypes structs equal those the C compiler gives the
+    header's structs."""
+    import shutil
+    import subprocess
+    cc = shutil.which('gcc') or shutil.which('cc')
+    if cc is None:
+        pytest.skip('no C compiler')
+    structs = {'lg_grid': lgbr.LgGrid, 'lg_gas': lgbr.LgGas, 'lg_opts': lgbr.LgOpts}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lgbr.h"', 'int main(void) {']
+    for cname, cls in structs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f in cls._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f[0], cname, f[0]))
+    lines.append('return 0; }')
+    src = tmp_path / 'layout.c'
+    src.write_text('\n'.join(lines))
+    exe = tmp_path / 'layout'
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), 'include')
+    subprocess.run([cc, '-I', inc, str(src), '-o', str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split('\n')
+    got = {}
+    for line in out:
+        if line.strip():
+            a, b, c = line.split()
+            got[(a, b)] = int(c)
+    for cname, cls in structs.items():
+        assert got[(cname, 'size')] == ctypes.sizeof(cls), cname
+        for f in cls._fields_:
+            assert got[(cname, f[0])] == getattr(cls, f[0]).offset, (cname, f[0])
 
 
 def test_strerror_and_argument_errors_without_gpu():
