@@ -20,9 +20,11 @@ Readings used here:
        alpha_f = 0.49 (the paper gives neither); the conserved state Q is filtered,
        once per time step, after the third stage of SSP-RK3, along xi, eta, zeta in
        turn.  Before each direction the ghost layers are refilled with the boundary
-       images of the current field; the unknowns of a bounded line are its interior
-       nodes, whose neighbours across the boundary enter unfiltered (ghost values);
-       a periodic line is cyclic over its interior nodes.
+       images of the current field; the filtered lines are those through interior
+       nodes, and the unknowns of a bounded line are its interior nodes, whose
+       neighbours across the boundary enter unfiltered (ghost values, never written:
+       FIXED ghosts stay the caller's); a periodic line is cyclic over its interior
+       nodes.
 """
 from fractions import Fraction
 
@@ -99,15 +101,19 @@ def filter_lines(cols, g, n, periodic, alpha, coef):
 
 
 def filter_direction(Q, d, grid, alpha, coef):
-    """One pass along d of the filter over every line of Q (5, Nz, Ny, Nx) (interior nodes
-    along d are replaced; ghosts are read, not written)."""
+    """One pass along d of the filter over the lines of Q (5, Nz, Ny, Nx) through interior
+    nodes: their interior nodes are replaced; ghost values, the caller's FIXED ghosts
+    included (R13), are read and never written."""
     ax = gr.axis_of(Q, d)
     g, n = grid.g[d], grid.n[d]
+    inner = np.zeros(grid.shape, bool)
+    inner[grid.interior()] = True
+    lines = np.moveaxis(np.broadcast_to(inner, Q.shape), ax, 0)[g].reshape(-1)
     Qm = np.moveaxis(Q, ax, 0)
     N = Qm.shape[0]
     cols = Qm.reshape(N, -1)
     out = cols.copy()
-    out[g:g + n] = filter_lines(cols, g, n, grid.periodic(d), alpha, coef)
+    out[g:g + n, lines] = filter_lines(cols[:, lines], g, n, grid.periodic(d), alpha, coef)
     return np.moveaxis(out.reshape(Qm.shape), 0, ax)
 
 

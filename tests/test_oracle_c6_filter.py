@@ -297,3 +297,18 @@ def test_lad_c6_step_applies_the_filter_once_after_the_last_stage():
     ref = IF.filter_state(Qn, g, 0.49)
     assert np.max(np.abs(Qf[inner] - ref[inner])) < 1e-15
     assert np.max(np.abs(Qf[inner] - Qn[inner])) > 0.0
+
+
+def test_filter_leaves_fixed_ghosts_to_the_caller():
+    """FIXED ghost values are never rewritten (R13): a pass along x does not touch the
+    FIXED ghost rows of y, whose values enter the y pass as given."""
+    T, NS, FX = cases.TRANSMISSIVE, cases.NOSLIP, cases.FIXED
+    c = cases.random_rough_state(cases.Case(2, (6, 40, 1), [(T, T), (NS, FX)], h=(0.05 / 6, 1 / 40, 1)), seed=24)
+    g = Grid(2, c.n, c.bc, h=c.h)
+    out = IF.filter_state(c.Q, g, 0.49)
+    assert np.array_equal(out[:, :, 45:, 5:11], c.Q[:, :, 45:, 5:11])
+    # and the y pass sees them: changing a FIXED ghost changes the filtered interior next to it
+    Q2 = c.Q.copy()
+    Q2[0, 0, 45, 5:11] += 0.1
+    out2 = IF.filter_state(Q2, g, 0.49)
+    assert np.max(np.abs(out2[0, 0, 44, 5:11] - out[0, 0, 44, 5:11])) > 1e-3
