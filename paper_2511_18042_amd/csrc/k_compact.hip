@@ -117,9 +117,9 @@ __device__ __forceinline__ double c6_grad_rhs(int i, int N, double m2, double m1
 // in FP64 from the conserved state; forward elimination into the FP64 scratch, back
 // substitution into the gradient array.
 template <typename R>
-__global__ void __launch_bounds__(256) k_grad_c6(const Prob* __restrict__ probs, StateRef ref, int d) {
+__global__ void __launch_bounds__(256) k_grad_c6(const Prob* __restrict__ probs, StateRef ref, int d, int mask) {
   const Prob& P = probs[blockIdx.y];
-  if (d >= P.ndim || c6_grad_pcr(P, d)) return;
+  if (d >= P.ndim || tile_use(P, d, TK_GRAD6, mask) || c6_grad_pcr(P, d)) return;
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= P.N[o1] * P.N[o2]) return;
@@ -207,10 +207,11 @@ __global__ void __launch_bounds__(256) k_grad_c6(const Prob* __restrict__ probs,
 // One workgroup per (line, primitive), persistent over the items; the primitive along the
 // line in LDS, the right-hand side reduced by PCR.
 template <typename R>
-__global__ void __launch_bounds__(256) k_grad_c6_pcr(const Prob* __restrict__ probs, StateRef ref, int d) {
+__global__ void __launch_bounds__(256) k_grad_c6_pcr(const Prob* __restrict__ probs, StateRef ref, int d,
+                                                     int mask) {
   extern __shared__ double lds[];
   const Prob& P = probs[blockIdx.y];
-  if (d >= P.ndim || !c6_grad_pcr(P, d)) return;
+  if (d >= P.ndim || tile_use(P, d, TK_GRAD6, mask) || !c6_grad_pcr(P, d)) return;
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   const int nlines = P.N[o1] * P.N[o2];
   const bool periodic = P.bc[d][0] == BC_PERIODIC;
@@ -298,9 +299,9 @@ __device__ __forceinline__ bool face_emit(const Prob& P, const FaceOut& o, doubl
 // One lane per interior line, all five flux components; forward elimination into the
 // FP64 scratch, back substitution emitting the node derivatives.
 template <typename R>
-__global__ void __launch_bounds__(256) k_c6_faces(const Prob* __restrict__ probs, FaceOut o, int d) {
+__global__ void __launch_bounds__(256) k_c6_faces(const Prob* __restrict__ probs, FaceOut o, int d, int mask) {
   const Prob& P = probs[blockIdx.y];
-  if (d >= P.ndim || c6_face_pcr(P, d)) return;
+  if (d >= P.ndim || tile_use(P, d, TK_FACES, mask) || c6_face_pcr(P, d)) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= interior_lines(P, d)) return;
   const R* F = static_cast<const R*>(P.FL[d]);
@@ -403,10 +404,11 @@ __global__ void __launch_bounds__(256) k_c6_faces(const Prob* __restrict__ probs
 // line, component); node fluxes at positions -2 .. n+1 and the face right-hand sides in
 // LDS; writes -J D into dQ/dt.
 template <typename R>
-__global__ void __launch_bounds__(256) k_c6_faces_pcr(const Prob* __restrict__ probs, StateRef ref, int d) {
+__global__ void __launch_bounds__(256) k_c6_faces_pcr(const Prob* __restrict__ probs, StateRef ref, int d,
+                                                      int mask) {
   extern __shared__ double lds[];
   const Prob& P = probs[blockIdx.y];
-  if (d >= P.ndim || !c6_face_pcr(P, d)) return;
+  if (d >= P.ndim || tile_use(P, d, TK_FACES, mask) || !c6_face_pcr(P, d)) return;
   const int nlines = interior_lines(P, d);
   const bool periodic = P.bc[d][0] == BC_PERIODIC;
   const int g = P.g[d], n = P.n[d], sd = P.s[d];
@@ -462,9 +464,9 @@ __device__ __forceinline__ double filt_rhs(const Prob& P, const double w[11]) {
 }
 
 // One lane per interior line, the five conserved variables in turn; in place on the state.
-__global__ void __launch_bounds__(256) k_filter(const Prob* __restrict__ probs, StateRef ref, int d) {
+__global__ void __launch_bounds__(256) k_filter(const Prob* __restrict__ probs, StateRef ref, int d, int mask) {
   const Prob& P = probs[blockIdx.y];
-  if (d >= P.ndim || !(P.falpha < 0.5) || filt_pcr(P, d)) return;
+  if (d >= P.ndim || !(P.falpha < 0.5) || tile_use(P, d, TK_FILTER, mask) || filt_pcr(P, d)) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= interior_lines(P, d)) return;
   double* Q = ref.state(P);
@@ -531,10 +533,11 @@ __global__ void __launch_bounds__(256) k_filter(const Prob* __restrict__ probs, 
 
 // Contiguous lines: one workgroup per (interior line, variable); the line in LDS, the
 // interior unknowns reduced by PCR, written back in place.
-__global__ void __launch_bounds__(256) k_filter_pcr(const Prob* __restrict__ probs, StateRef ref, int d) {
+__global__ void __launch_bounds__(256) k_filter_pcr(const Prob* __restrict__ probs, StateRef ref, int d,
+                                                    int mask) {
   extern __shared__ double lds[];
   const Prob& P = probs[blockIdx.y];
-  if (d >= P.ndim || !(P.falpha < 0.5) || !filt_pcr(P, d)) return;
+  if (d >= P.ndim || !(P.falpha < 0.5) || tile_use(P, d, TK_FILTER, mask) || !filt_pcr(P, d)) return;
   const int nlines = interior_lines(P, d);
   const bool periodic = P.bc[d][0] == BC_PERIODIC;
   const int g = P.g[d], n = P.n[d], N = P.N[d], sd = P.s[d];
@@ -565,6 +568,313 @@ __global__ void __launch_bounds__(256) k_filter_pcr(const Prob* __restrict__ pro
   }
 }
 
+// ------------------------------------------------------------------ line tiles
+// One workgroup holds all five variables of TX neighbouring lines of one direction in LDS
+// (TX * 5 * positions <= TILE_ELEMS doubles), forms the right-hand sides there, reduces
+// them by PCR and writes the outputs: no FP64 scratch round trip, and many workgroups in
+// flight whatever the direction.  Neighbouring lines are adjacent along the contiguous
+// other direction (x for eta / zeta lines), so a tile reads and writes TX consecutive
+// values per line position; tiles of neighbouring columns run on the same XCD (L2).
+//   TK_GRAD6   C6 gradients: FP64 primitives of all nodes in, G out
+//   TK_FACES   C6 interface fluxes: node fluxes at -2 .. n+1 in, -J D into dQ/dt (or the
+//              RK stage in the last direction)
+//   TK_FILTER  implicit filter: the state in, its interior filtered in place
+struct TileArgs {
+  StateRef ref;
+  RKRef rr;
+  int d, TX, accumulate, rk, stage, mask;
+  double a, b;
+};
+
+// the LDS index of (variable q, column c, position p) is (q * TX + c) * Lin + p
+__device__ __forceinline__ void tile_geom(const Prob& P, int d, int kind, int& Lin, int& off, int& U, int& la,
+                                          int& lb, int& ba, int& bb) {
+  const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+  const bool periodic = P.bc[d][0] == BC_PERIODIC;
+  const int n = P.n[d], g = P.g[d];
+  if (kind == TK_GRAD6) {
+    Lin = P.N[d];
+    off = -g;
+    U = periodic ? n : P.N[d];
+    la = P.N[o1];
+    lb = P.N[o2];
+    ba = bb = 0;
+  } else {
+    Lin = kind == TK_FACES ? n + 4 : P.N[d];
+    off = kind == TK_FACES ? -2 : -g;
+    U = kind == TK_FACES ? (periodic ? n : n - 1) : n;
+    la = P.n[o1];
+    lb = P.n[o2];
+    ba = P.g[o1];
+    bb = P.g[o2];
+  }
+}
+
+template <typename R, int KIND>
+__global__ void __launch_bounds__(256) k_line_tiles(const Prob* __restrict__ probs, TileArgs A) {
+  __shared__ double buf[TILE_ELEMS];
+  __shared__ double lohi[2 * 5 * TILE_MAX_TX];
+  const Prob& P = probs[blockIdx.y];
+  const int d = A.d, TX = A.TX;
+  if (d >= P.ndim || !tile_use(P, d, KIND, A.mask)) return;
+  int Lin, off, U, la, lb, ba, bb;
+  tile_geom(P, d, KIND, Lin, off, U, la, lb, ba, bb);
+  if (5 * TX * Lin > TILE_ELEMS || TX > TILE_MAX_TX) return;   // the host sizes TX so that this never holds
+  const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+  const int ta = (la + TX - 1) / TX;
+  const int ntiles = ta * lb;
+  const int per = (ntiles + 7) >> 3;
+  if ((int)(blockIdx.x >> 3) >= per) return;
+  const int tile = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (tile >= ntiles) return;
+  const int a0 = (tile % ta) * TX, bpos = tile / ta;
+  const int ncol = min(TX, la - a0);
+  const int g = P.g[d], n = P.n[d], sd = P.s[d];
+  const bool periodic = P.bc[d][0] == BC_PERIODIC;
+  const size_t T = P.total;
+  const size_t lbase = (size_t)(ba + a0) * P.s[o1] + (size_t)(bb + bpos) * P.s[o2];
+  const int tid = threadIdx.x;
+  const int ncp = TX * Lin;   // (column, position) pairs
+  // element e of a (column, position) sweep: positions fastest on contiguous lines,
+  // columns fastest on strided ones (coalesced either way)
+  auto cp_of = [&](int e, int& c, int& p) {
+    if (d == 0) {
+      p = e % Lin;
+      c = e / Lin;
+    } else {
+      c = e % TX;
+      p = e / TX;
+    }
+  };
+  // ---- load
+  for (int e = tid; e < ncp; e += 256) {
+    int c, p;
+    cp_of(e, c, p);
+    double v[5] = {0, 0, 0, 0, 0};
+    if (c < ncol) {
+      const size_t node = lbase + (size_t)c * P.s[o1] + (size_t)(g + off + p) * sd;
+      if (KIND == TK_GRAD6) {
+        prims5c(A.ref.state(P), T, node, P.gamma - 1.0, v);
+      } else if (KIND == TK_FACES) {
+        const R* F = static_cast<const R*>(P.FL[d]);
+        for (int q = 0; q < 5; ++q) v[q] = (double)F[q * T + node];
+      } else {
+        const double* Q = A.ref.state(P);
+        for (int q = 0; q < 5; ++q) v[q] = Q[q * T + node];
+      }
+    }
+    for (int q = 0; q < 5; ++q) buf[(q * TX + c) * Lin + p] = v[q];
+  }
+  __syncthreads();
+  // ---- right-hand sides (registers, then over the inputs)
+  const int nel = 5 * TX * Lin;
+  double nv[TILE_PT];
+#pragma unroll
+  for (int m = 0; m < TILE_PT; ++m) {
+    const int e = tid + m * 256;
+    nv[m] = 0.0;
+    if (e < nel) {
+      const int line = e / Lin, k = e % Lin;
+      const double* f = buf + line * Lin;
+      if (k < U) {
+        double r;
+        if (KIND == TK_GRAD6) {
+          if (periodic)
+            r = C6_A * (f[g + wrap(k + 1, n)] - f[g + wrap(k - 1, n)]) +
+                C6_B * (f[g + wrap(k + 2, n)] - f[g + wrap(k - 2, n)]);
+          else
+            r = c6_grad_rhs(k, U, k >= 2 ? f[k - 2] : 0.0, k >= 1 ? f[k - 1] : 0.0, f[k], k + 1 < U ? f[k + 1] : 0.0,
+                            k + 2 < U ? f[k + 2] : 0.0);
+        } else if (KIND == TK_FACES) {
+          // node position p sits at f[p + 2]
+          if (periodic) {
+            r = C6F_A * (f[2 + k] + f[2 + wrap(k + 1, n)]) + C6F_B * (f[2 + wrap(k - 1, n)] + f[2 + wrap(k + 2, n)]);
+          } else {
+            r = C6F_A * (f[2 + k] + f[3 + k]) + C6F_B * (f[1 + k] + f[4 + k]);
+            if (k == 0 || k == U - 1) {
+              const double lo = (7.0 * (f[1] + f[2]) - (f[0] + f[3])) / 12.0;
+              const double hi = (7.0 * (f[n + 1] + f[n + 2]) - (f[n] + f[n + 3])) / 12.0;
+              if (k == 0) {
+                r = r - C6_ALPHA * lo;
+                lohi[2 * line] = lo;
+              }
+              if (k == U - 1) {
+                r = r - C6_ALPHA * hi;
+                lohi[2 * line + 1] = hi;
+              }
+            }
+          }
+        } else {
+          double w[11];
+          for (int j = -5; j <= 5; ++j) w[j + 5] = f[g + (periodic ? wrap(k + j, n) : k + j)];
+          r = filt_rhs(P, w);
+          if (!periodic) {
+            if (k == 0) r = r - P.falpha * f[g - 1];
+            if (k == n - 1) r = r - P.falpha * f[g + n];
+          }
+        }
+        nv[m] = r;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < TILE_PT; ++m) {
+    const int e = tid + m * 256;
+    if (e < nel) buf[e] = nv[m];
+  }
+  __syncthreads();
+  // ---- PCR over all 5 TX lines at once.  Each element keeps its (line start, row); the
+  // factors of rows inside a step's band are two constants (see the table header), so only
+  // rows near the line ends read the table.
+  const double* tab = KIND == TK_GRAD6 ? P.pcr6[d] : (KIND == TK_FACES ? P.pcrc[d] : P.pcrf[d]);
+  const int steps = KIND == TK_FILTER ? P.fsteps : LG_PCR_STEPS;
+  const double* hdr = tab + (size_t)(2 * steps + 1) * U;
+  int eln[TILE_PT], erow[TILE_PT];
+#pragma unroll
+  for (int m = 0; m < TILE_PT; ++m) {
+    const int e = tid + m * 256;
+    const int k = e % Lin;
+    const bool ok = e < nel && k < U;
+    eln[m] = e - k;
+    erow[m] = ok ? k : -1;
+  }
+  for (int st = 0; st < steps; ++st) {
+    const int s = 1 << st;
+    const double* k1 = tab + (size_t)st * U;
+    const double* k2 = tab + (size_t)(steps + st) * U;
+    const double c1 = hdr[4 * st], c2 = hdr[4 * st + 1];
+    const int blo = (int)hdr[4 * st + 2], bhi = (int)hdr[4 * st + 3];
+#pragma unroll
+    for (int m = 0; m < TILE_PT; ++m) {
+      const int k = erow[m];
+      if (k >= 0) {
+        const double* r = buf + eln[m];
+        int km = k - s, kp = k + s;
+        double rm, rp;
+        if (periodic) {
+          km = km < 0 ? km + U : km;
+          kp = kp >= U ? kp - U : kp;
+          rm = r[km];
+          rp = r[kp];
+        } else {
+          rm = km >= 0 ? r[km] : 0.0;
+          rp = kp < U ? r[kp] : 0.0;
+        }
+        double f1 = c1, f2 = c2;
+        if (k < blo || k > bhi) {
+          f1 = k1[k];
+          f2 = k2[k];
+        }
+        nv[m] = r[k] - f1 * rm - f2 * rp;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < TILE_PT; ++m)
+      if (erow[m] >= 0) buf[eln[m] + erow[m]] = nv[m];
+    __syncthreads();
+  }
+  {
+    const double* binv = tab + (size_t)2 * steps * U;
+    const double cb = hdr[4 * steps];
+    const int blo = (int)hdr[4 * steps + 2], bhi = (int)hdr[4 * steps + 3];
+#pragma unroll
+    for (int m = 0; m < TILE_PT; ++m) {
+      const int k = erow[m];
+      if (k >= 0) buf[eln[m] + k] *= (k < blo || k > bhi) ? binv[k] : cb;
+    }
+  }
+  __syncthreads();
+  // ---- outputs
+  if (KIND == TK_GRAD6) {
+    R* G = static_cast<R*>(P.G[d]);
+    const int pos0 = periodic ? g : 0;   // position of unknown 0
+    for (int e = tid; e < TX * U; e += 256) {
+      int c, k;
+      if (d == 0) {
+        k = e % U;
+        c = e / U;
+      } else {
+        c = e % TX;
+        k = e / TX;
+      }
+      if (c >= ncol) continue;
+      const size_t col = lbase + (size_t)c * P.s[o1];
+      for (int q = 0; q < 5; ++q) {
+        const R y = (R)buf[(q * TX + c) * Lin + k];
+        G[q * T + col + (size_t)(pos0 + k) * sd] = y;
+        if (periodic) {
+          if (k >= n - g) G[q * T + col + (size_t)(g + k - n) * sd] = y;   // low ghosts
+          if (k < g) G[q * T + col + (size_t)(g + k + n) * sd] = y;        // high ghosts
+        }
+      }
+    }
+  } else if (KIND == TK_FACES) {
+    double* dQ = A.ref.deriv(P);
+    FaceOut o{A.ref, A.rr, A.accumulate, A.rk, A.stage, A.a, A.b};
+    const double dt = A.rk ? *P.dt : 0.0;
+    int bad = 0;
+    for (int e = tid; e < TX * n; e += 256) {
+      int c, i;
+      if (d == 0) {
+        i = e % n;
+        c = e / n;
+      } else {
+        c = e % TX;
+        i = e / TX;
+      }
+      if (c >= ncol) continue;
+      double D[5];
+      for (int q = 0; q < 5; ++q) {
+        const int line = q * TX + c;
+        const double* r = buf + line * Lin;
+        double fp, fm;
+        if (periodic) {
+          fp = r[i];
+          fm = r[wrap(i - 1, n)];
+        } else {
+          fp = i < U ? r[i] : lohi[2 * line + 1];
+          fm = i > 0 ? r[i - 1] : lohi[2 * line];
+        }
+        D[q] = fp - fm;
+      }
+      if (face_emit(P, o, dQ, dt, lbase + (size_t)c * P.s[o1] + (size_t)(g + i) * sd, D)) ++bad;
+    }
+    if (bad) atomicAdd(P.status, bad);
+  } else {
+    double* Q = A.ref.state(P);
+    for (int e = tid; e < TX * n; e += 256) {
+      int c, k;
+      if (d == 0) {
+        k = e % n;
+        c = e / n;
+      } else {
+        c = e % TX;
+        k = e / TX;
+      }
+      if (c >= ncol) continue;
+      const size_t node = lbase + (size_t)c * P.s[o1] + (size_t)(g + k) * sd;
+      for (int q = 0; q < 5; ++q) Q[q * T + node] = buf[(q * TX + c) * Lin + k];
+    }
+  }
+}
+
+// columns per tile so that 5 TX positions fit the LDS tile
+static inline int tile_tx(long long Lmax) {
+  long long tx = TILE_ELEMS / (5 * std::max<long long>(Lmax, 1));
+  return (int)std::max<long long>(1, std::min<long long>(tx, TILE_MAX_TX));
+}
+
+template <typename R, int KIND>
+static void launch_tiles(const Launch& L, int kc, long long Lmax, long long lines_a, long long lines_b, TileArgs A) {
+  A.TX = tile_tx(Lmax);
+  const long long nt = ((lines_a + A.TX - 1) / A.TX) * lines_b;
+  const unsigned grid = (unsigned)(8 * ((nt + 7) / 8));
+  LG_TIMED(L, kc, hipLaunchKernelGGL((k_line_tiles<R, KIND>), dim3(grid, L.nprob), dim3(256), 0, L.stream,
+                                     L.probs, A));
+}
+
 // ------------------------------------------------------------------ launches
 static inline unsigned blocks_for(long long work) { return (unsigned)std::max<long long>(1, (work + 255) / 256); }
 
@@ -572,43 +882,68 @@ static inline unsigned pcr_grid(const Launch& L, long long items) {
   return (unsigned)std::max<long long>(1, std::min<long long>(items, L.pcr_blocks > 0 ? L.pcr_blocks : 16384));
 }
 
+// which kernels a system's direction takes: LDS tiles when enabled (for the problems that
+// fit them), the fallback kernels for the others (or for all when tiles are off)
+struct SysLaunch {
+  int tiles, pcr, thomas;
+};
+static inline SysLaunch sys_launch(const Launch& L, int kind, int d) {
+  return SysLaunch{L.ctile[kind][d], L.cpcr[kind][d], L.cthomas[kind][d]};
+}
+
 template <typename R>
 void launch_grad_c6(const Launch& L, StateRef ref, int d) {
-  if (L.pcr_dir[d]) {
-    const unsigned lds = (unsigned)(2 * L.max_N[d] * sizeof(double));
+  const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+  const SysLaunch sl = sys_launch(L, TK_GRAD6, d);
+  if (sl.tiles)
+    launch_tiles<R, TK_GRAD6>(L, KC_GRAD_C4, L.max_N[d], L.max_N[o1], L.max_N[o2],
+                              TileArgs{ref, RKRef{nullptr, nullptr, nullptr}, d, 1, 0, 0, 0, L.tile_mask, 0.0, 0.0});
+  if (sl.pcr) {
+    const unsigned lds = (unsigned)(2 * std::min<long long>(L.max_N[d], 4096) * sizeof(double));
     LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c6_pcr<R>, dim3(pcr_grid(L, 5 * L.lines[d]), L.nprob),
-                                               dim3(256), lds, L.stream, L.probs, ref, d));
+                                               dim3(256), lds, L.stream, L.probs, ref, d, L.tile_mask));
   }
-  if (L.thomas_dir[d])
+  if (sl.thomas)
     LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c6<R>, dim3(blocks_for(L.lines[d]), L.nprob), dim3(256), 0,
-                                               L.stream, L.probs, ref, d));
+                                               L.stream, L.probs, ref, d, L.tile_mask));
 }
 
 template <typename R>
 void launch_c6_faces(const Launch& L, StateRef ref, int d, int accumulate, const RKRef* rr, int stage, double a,
                      double b) {
-  if (L.face_pcr[d]) {
-    const unsigned lds = (unsigned)((2 * L.max_n[d] + 4) * sizeof(double));
+  const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+  const SysLaunch sl = sys_launch(L, TK_FACES, d);
+  if (sl.tiles)
+    launch_tiles<R, TK_FACES>(L, KC_C6_FACES, L.max_n[d] + 4, L.max_n[o1], L.max_n[o2],
+                              TileArgs{ref, rr ? *rr : RKRef{nullptr, nullptr, nullptr}, d, 1, accumulate, rr ? 1 : 0,
+                                       stage, L.tile_mask, a, b});
+  if (sl.pcr) {
+    const unsigned lds = (unsigned)((2 * std::min<long long>(L.max_n[d], 3990) + 4) * sizeof(double));
     LG_TIMED(L, KC_C6_FACES, hipLaunchKernelGGL(k_c6_faces_pcr<R>, dim3(pcr_grid(L, 5 * L.sweep_rows[d]), L.nprob),
-                                                dim3(256), lds, L.stream, L.probs, ref, d));
+                                                dim3(256), lds, L.stream, L.probs, ref, d, L.tile_mask));
   }
-  if (L.face_thomas[d]) {
+  if (sl.thomas) {
     FaceOut o{ref, rr ? *rr : RKRef{nullptr, nullptr, nullptr}, accumulate, rr ? 1 : 0, stage, a, b};
     LG_TIMED(L, KC_C6_FACES, hipLaunchKernelGGL(k_c6_faces<R>, dim3(blocks_for(L.sweep_rows[d]), L.nprob),
-                                                dim3(256), 0, L.stream, L.probs, o, d));
+                                                dim3(256), 0, L.stream, L.probs, o, d, L.tile_mask));
   }
 }
 
 void launch_filter(const Launch& L, StateRef ref, int d) {
   launch_bc_cons(L, ref, d);
-  if (L.filt_pcr[d]) {
-    const unsigned lds = (unsigned)((L.max_N[d] + L.max_n[d]) * sizeof(double));
+  const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+  const SysLaunch sl = sys_launch(L, TK_FILTER, d);
+  if (sl.tiles)
+    launch_tiles<double, TK_FILTER>(L, KC_FILTER, L.max_N[d], L.max_n[o1], L.max_n[o2],
+                                    TileArgs{ref, RKRef{nullptr, nullptr, nullptr}, d, 1, 0, 0, 0, L.tile_mask, 0.0, 0.0});
+  if (sl.pcr) {
+    const unsigned lds = (unsigned)(std::min<long long>(L.max_N[d] + L.max_n[d], 7990) * sizeof(double));
     LG_TIMED(L, KC_FILTER, hipLaunchKernelGGL(k_filter_pcr, dim3(pcr_grid(L, 5 * L.sweep_rows[d]), L.nprob),
-                                              dim3(256), lds, L.stream, L.probs, ref, d));
+                                              dim3(256), lds, L.stream, L.probs, ref, d, L.tile_mask));
   }
-  if (L.filt_thomas[d])
+  if (sl.thomas)
     LG_TIMED(L, KC_FILTER, hipLaunchKernelGGL(k_filter, dim3(blocks_for(L.sweep_rows[d]), L.nprob), dim3(256), 0,
-                                              L.stream, L.probs, ref, d));
+                                              L.stream, L.probs, ref, d, L.tile_mask));
 }
 
 template void launch_grad_c6<float>(const Launch&, StateRef, int);

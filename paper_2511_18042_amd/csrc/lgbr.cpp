@@ -344,6 +344,25 @@ std::vector<double> pcr_table_ac(std::vector<double> a, std::vector<double> c, b
     c.swap(nc);
   }
   for (int i = 0; i < L; ++i) t[(size_t)2 * steps * L + i] = 1.0 / b[i];
+  // band header (read by the LDS line tiles): for every step the factors of rows away from
+  // the line ends are bit-identical, so kernels use two constants there; per step st:
+  // {k1, k2, first row, last row} of the band around the middle row, then {binv, 0, lo, hi}
+  const size_t h0 = t.size();
+  t.resize(h0 + 4 * (size_t)(steps + 1), 0.0);
+  const int mid = L / 2;
+  for (int st = 0; st <= steps; ++st) {
+    const double* r1 = t.data() + (st < steps ? (size_t)st * L : (size_t)2 * steps * L);
+    const double* r2 = st < steps ? t.data() + (size_t)(steps + st) * L : nullptr;
+    auto same = [&](int i) { return r1[i] == r1[mid] && (!r2 || r2[i] == r2[mid]); };
+    int lo = mid, hi = mid;
+    while (lo > 0 && same(lo - 1)) --lo;
+    while (hi < L - 1 && same(hi + 1)) ++hi;
+    double* hd = t.data() + h0 + 4 * (size_t)st;
+    hd[0] = r1[mid];
+    hd[1] = r2 ? r2[mid] : 0.0;
+    hd[2] = lo;
+    hd[3] = hi;
+  }
   return t;
 }
 
@@ -385,11 +404,12 @@ void fill_launch(Launch& L, const Prob& P) {
     if (periodic && P.n[d] < 128) L.has_short_periodic = 1;
     if (P.bc[d][0] == LG_BC_FIXED || P.bc[d][1] == LG_BC_FIXED) L.has_fixed = 1;
     if (P.lad_c6) {
-      if (lg::c6_face_pcr(P, d)) L.face_pcr[d] = 1;
-      else L.face_thomas[d] = 1;
-      if (P.falpha < 0.5) {
-        if (lg::filt_pcr(P, d)) L.filt_pcr[d] = 1;
-        else L.filt_thomas[d] = 1;
+      for (int k = 0; k < 3; ++k) {
+        if (k == lg::TK_FILTER && !(P.falpha < 0.5)) continue;
+        const bool pcr = k == lg::TK_GRAD6 ? lg::c6_grad_pcr(P, d)
+                                           : (k == lg::TK_FACES ? lg::c6_face_pcr(P, d) : lg::filt_pcr(P, d));
+        if (lg::tile_use(P, d, k, L.tile_mask)) L.ctile[k][d] = 1;
+        else (pcr ? L.cpcr : L.cthomas)[k][d] = 1;
       }
     }
   }
@@ -704,6 +724,7 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
   c->L.stream = c->stream;
   c->L.ndim = G.ndim;
   c->L.seg = opts->seg;
+  c->L.tile_mask = lg::TILE_MASK_DEFAULT;
   fill_launch(c->L, P);
   if (G.curvilinear) {
     if (dispatch(opts->precision, [&](auto r) { lg::launch_lad_geometry<decltype(r)>(c->L); }) != LG_OK) {
@@ -871,6 +892,17 @@ lg_status lg_set_tuning(lg_ctx* c, int seg, int pcr_blocks, int zc) {
   return LG_OK;
 }
 
+lg_status lg_set_line_tiles(lg_ctx* c, int mask) {
+  if (!c || mask < -1 || mask > lg::TILE_MASK_ALL) return LG_EINVAL;
+  c->L.tile_mask = mask < 0 ? lg::TILE_MASK_DEFAULT : mask;
+  for (int k = 0; k < 3; ++k)
+    for (int d = 0; d < 3; ++d) c->L.ctile[k][d] = c->L.cpcr[k][d] = c->L.cthomas[k][d] = 0;
+  fill_launch(c->L, c->hp);
+  return LG_OK;
+}
+
+int lg_get_line_tiles(const lg_ctx* c) { return c ? c->L.tile_mask : -1; }
+
 lg_status lg_get_tuning(const lg_ctx* c, int* seg, int* pcr_blocks, int* zc) {
   if (!c || !seg || !pcr_blocks || !zc) return LG_EINVAL;
   *seg = lg::sweep_seg(c->L, c->cfg.ndim > 1 ? 1 : 0);
@@ -921,6 +953,7 @@ lg_status lg_batch_create(lg_batch** out, lg_ctx* const* ctxs, double* const* Q,
   b->L.seg = ctxs[0]->L.seg;
   b->L.pcr_blocks = ctxs[0]->L.pcr_blocks;
   b->L.zc = ctxs[0]->L.zc;
+  b->L.tile_mask = ctxs[0]->L.tile_mask;
   for (int i = 0; i < n; ++i) {
     Prob P = ctxs[i]->hp;
     P.Q = Q[i];

@@ -80,8 +80,10 @@ struct Launch {
   int has_fixed;           // some problem has a FIXED face (caller-owned ghosts)
   int pcr_dir[3];          // some problem solves its lines along d by PCR
   int thomas_dir[3];       // some problem solves its lines along d one lane per line
-  int face_pcr[3], face_thomas[3];   // the same for the LAD-C6 interface-flux systems
-  int filt_pcr[3], filt_thomas[3];   // and for the implicit-filter systems
+  // LAD-C6 line systems [TK_*][d]: which kernels some problem needs (tile_use with this
+  // launch's tile_mask): LDS line tiles, PCR per (line, variable), one lane per line
+  int ctile[3][3], cpcr[3][3], cthomas[3][3];
+  int tile_mask;           // bit 3 TK_* + d: LDS tiles allowed for that system and direction
   int max_fsteps;          // most PCR steps of any problem's filter systems
   int ndim;
   int seg;                 // nodes per thread in the strided sweeps (0: heuristic)
@@ -179,7 +181,37 @@ template <typename R>
 void launch_c6_faces(const Launch& L, StateRef ref, int d, int accumulate, const RKRef* rr, int stage, double a,
                      double b);
 void launch_filter(const Launch& L, StateRef ref, int d);
-// which kernel solves the lines of each system (shared by the host and the kernels)
+// which kernel solves the lines of each system (shared by the host and the kernels):
+// LDS line tiles when all five variables of one line fit the tile and a periodic line is
+// long enough for the PCR steps; otherwise the policies below
+enum { TK_GRAD6 = 0, TK_FACES = 1, TK_FILTER = 2 };
+constexpr int TILE_MASK_ALL = 0x1FF;
+constexpr int TILE_MASK_DEFAULT = TILE_MASK_ALL;
+constexpr int TILE_ELEMS = 6144;   // doubles per tile (48 KB of LDS)
+constexpr int TILE_PT = TILE_ELEMS / 256;
+constexpr int TILE_MAX_TX = 16;
+__host__ __device__ inline bool tile_ok(const Prob& P, int d, int kind) {
+  const bool periodic = P.bc[d][0] == BC_PERIODIC;
+  const int n = P.n[d];
+  const int Lin = kind == TK_FACES ? n + 4 : P.N[d];
+  if (5 * Lin > TILE_ELEMS) return false;
+  const int steps = kind == TK_FILTER ? P.fsteps : LG_PCR_STEPS;
+  return !(periodic && n < (2 << steps));
+}
+// Where tiles are allowed (tile_mask), they are used for the contiguous direction, and for
+// strided directions with few lines: strided lines solved one lane per line are coalesced
+// across neighbouring lines and faster once there are enough of them to fill the chip
+// (1024 x 384 x 128 ramp: 4.3 ms vs 11 ms for the C6 gradients along xi; along eta,
+// 142 k lines, 2.5 ms one lane per line vs 4.4 ms in tiles; a 1792 x 768 plane has only
+// 1802 eta lines, far too few lanes)
+constexpr long long TILE_FEW_LINES = 32768;
+__host__ __device__ inline bool tile_use(const Prob& P, int d, int kind, int mask) {
+  if (!((mask >> (3 * kind + d)) & 1) || !tile_ok(P, d, kind)) return false;
+  if (d == 0) return true;
+  const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+  const long long lines = kind == TK_GRAD6 ? (long long)P.N[o1] * P.N[o2] : (long long)P.n[o1] * P.n[o2];
+  return lines < TILE_FEW_LINES;
+}
 __host__ __device__ inline bool c6_grad_pcr(const Prob& P, int d) {
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   const long long nlines = (long long)P.N[o1] * P.N[o2];

@@ -21,7 +21,8 @@ SCHEMES = {'cgbr': SCHEME_CGBR, 'lad': SCHEME_LAD, 'hybrid': SCHEME_HYBRID}
 EXPORTS = ('lg_set_allocator', 'lg_strerror', 'lg_create', 'lg_destroy', 'lg_workspace_bytes',
            'lg_metrics_from_coords', 'cgbr_rhs', 'lad_rhs', 'hybrid_rhs', 'rk3_step', 'lg_rk3_stage',
            'lg_compute_dt', 'lg_batch_create', 'lg_batch_run', 'lg_batch_destroy', 'lg_poll_status',
-           'lg_prof_start', 'lg_prof_stop', 'lg_set_tuning', 'lg_get_tuning', 'lg_metrics_planar', 'lad_filter')
+           'lg_prof_start', 'lg_prof_stop', 'lg_set_tuning', 'lg_get_tuning', 'lg_metrics_planar', 'lad_filter',
+           'lg_set_line_tiles', 'lg_get_line_tiles')
 KERNEL_CLASSES = ('bc', 'prim', 'flags', 'grad_e6', 'grad_c4', 'sensor', 'visc', 'lad_node', 'lad_raw', 'gauss',
                   'lad_flux', 'sweep_x', 'sweep_y', 'sweep_z', 'combine', 'dt', 'bc_scalar', 'lad_sweep',
                   'c6_faces', 'filter')
@@ -82,6 +83,8 @@ def load():
         'lg_prof_start': (I, [P, I, I]),
         'lg_prof_stop': (I, [P, ctypes.POINTER(D), ctypes.POINTER(I)]),
         'lg_set_tuning': (I, [P, I, I, I]),
+        'lg_set_line_tiles': (I, [P, I]),
+        'lg_get_line_tiles': (I, [P]),
         'lg_get_tuning': (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
     }
     for name, (res, args) in sig.items():
@@ -222,6 +225,12 @@ class Context:
 
     def set_tuning(self, seg=0, pcr_blocks=0, zc=0):
         _check(self._lib.lg_set_tuning(self.handle, int(seg), int(pcr_blocks), int(zc)), 'lg_set_tuning')
+
+    def set_line_tiles(self, mask=-1):
+        _check(self._lib.lg_set_line_tiles(self.handle, int(mask)), 'lg_set_line_tiles')
+
+    def get_line_tiles(self):
+        return int(self._lib.lg_get_line_tiles(self.handle))
 
     def get_tuning(self):
         a, b, z = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)

@@ -2,9 +2,10 @@
 gradients and interface fluxes (lad_rhs, RK stages) and the tenth-order implicit filter
 (lad_filter, the end of every rk3_step).
 
-The cases cover every line-solve kernel: contiguous lines by PCR (bounded, and periodic
-with enough nodes), strided and short periodic lines one lane per line, FIXED, reflective,
-no-slip and transmissive faces, curvilinear grids with full and planar metric storage.
+The cases cover every line-solve kernel: LDS line tiles (all five variables of a few
+lines), lines too long for a tile by PCR per (line, variable) or one lane per line, short
+periodic lines one lane per line; FIXED, reflective, no-slip and transmissive faces;
+curvilinear grids with full and planar metric storage.
 Tolerances: RHS 1e-10 and states 1e-12 of each variable's max norm (FP64; the two sides
 solve the same tridiagonal systems with different elimination orders).
 """
@@ -56,9 +57,21 @@ def case_ramp():
     return cases.ramp3d(40, 32, 16)
 
 
+def case_2d_long_x():
+    """x lines longer than an LDS line tile holds (PCR per line and variable)."""
+    c = cases.Case(2, (1300, 6, 1), [(RF, T), (T, RF)], h=(1.0 / 1300, 0.05 / 6, 1))
+    return cases.random_rough_state(c, seed=23)
+
+
+def case_2d_long_y():
+    """y lines longer than a tile: PCR gradients, one lane per line for fluxes and filter."""
+    c = cases.Case(2, (6, 1300, 1), [(T, T), (NS, FX)], h=(0.05 / 6, 1.0 / 1300, 1))
+    return cases.random_rough_state(c, seed=24)
+
+
 CASES = {'1d_fixed': case_1d_fixed, '1d_periodic': case_1d_periodic, '2d_walls': case_2d_walls,
          '2d_periodic_wide': case_2d_periodic_wide, '2d_curv': case_2d_curv, '3d_curv': case_3d_curv,
-         'ramp': case_ramp}
+         'ramp': case_ramp, '2d_long_x': case_2d_long_x, '2d_long_y': case_2d_long_y}
 
 
 def _gas(name, c):
@@ -74,29 +87,39 @@ def _opts(alpha=0.49):
     return orhs.Opts(lad='C6', filter_alpha=alpha, C_mu=0.002)
 
 
+# line-solve kernels: LDS line tiles everywhere, or the PCR / lane-per-line kernels only
+TILES = {'default': -1, 'tiles': 0x1FF, 'no_tiles': 0}
+
+
 @pytest.mark.parametrize('name', list(CASES))
-def test_lad_c6_rhs_parity_fp64(name):
-    print('case', name, flush=True)
+@pytest.mark.parametrize('tiles', list(TILES))
+def test_lad_c6_rhs_parity_fp64(name, tiles):
+    print('case', name, tiles, flush=True)
     c = CASES[name]()
     gas, opts = _gas(name, c), _opts()
     g = U.oracle_grid(c)
     ref = orhs.rhs(c.Q, g, gas, opts, 'lad')
     ctx, _ = U.gpu_context(c, gas, opts)
+    ctx.set_line_tiles(TILES[tiles])
+    assert ctx.get_line_tiles() == (TILES[tiles] if TILES[tiles] >= 0 else 0x1FF)
     out = U.gpu_rhs(ctx, c, 'lad')
-    U.compare(out, ref, g, U.RHS_RTOL, label='lad-c6 ' + name)
+    U.compare(out, ref, g, U.RHS_RTOL, label='lad-c6 %s %s' % (name, tiles))
     ctx.close()
 
 
-@pytest.mark.parametrize('name', ['1d_fixed', '1d_periodic', '2d_walls', '2d_periodic_wide', '3d_curv', 'ramp'])
+@pytest.mark.parametrize('name', ['1d_fixed', '1d_periodic', '2d_walls', '2d_periodic_wide', '3d_curv', 'ramp',
+                                  '2d_long_x', '2d_long_y'])
 @pytest.mark.parametrize('alpha', [0.49, 0.3])
-def test_filter_parity_fp64(name, alpha):
-    print('filter', name, alpha, flush=True)
+@pytest.mark.parametrize('tiles', list(TILES))
+def test_filter_parity_fp64(name, alpha, tiles):
+    print('filter', name, alpha, tiles, flush=True)
     torch = U.torch_mod()
     c = CASES[name]()
     gas, opts = _gas(name, c), _opts(alpha)
     g = U.oracle_grid(c)
     ref = oflt.filter_state(c.Q, g, alpha)
     ctx, _ = U.gpu_context(c, gas, opts)
+    ctx.set_line_tiles(TILES[tiles])
     Qd = U.dev(c.Q)
     ctx.lad_filter(Qd)
     torch.cuda.synchronize()
