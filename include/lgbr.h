@@ -214,14 +214,15 @@ lg_status lg_prof_stop(lg_ctx* ctx, double* ms, int* launches);
  * values in effect (heuristic values resolved for the context's grid). */
 lg_status lg_set_tuning(lg_ctx* ctx, int seg, int pcr_blocks, int zc);
 lg_status lg_get_tuning(const lg_ctx* ctx, int* seg, int* pcr_blocks, int* zc);
-/* Line-solve kernels of LAD-C6 contexts (no effect on results beyond rounding): bit 3 s + d
- * of mask allows LDS line tiles (all five variables of a few lines in one workgroup) for
- * system s (0 = C6 gradients, 1 = C6 interface fluxes, 2 = implicit filter) along
- * direction d.  Where allowed, tiles are used for the contiguous direction and for strided
- * directions with fewer than 32768 lines; other lines are solved by PCR per (line,
- * variable) or one lane per line.  mask in [0, 511]; -1 restores the default (511, all
- * allowed).  lg_get_line_tiles returns the mask in effect (-1 for a null context).
- * Applies to later calls and to batches created afterwards. */
+/* Line-solve kernels of the compact schemes (no effect on results beyond rounding): bit
+ * 3 s + d of mask allows LDS line tiles (all five variables of a few lines in one
+ * workgroup) for system s (0 = LAD-C6 gradients, 1 = LAD-C6 interface fluxes, 2 = implicit
+ * filter, 3 = MIG4 gradients outside per-cell hybrid stages) along direction d.  Where
+ * allowed, tiles are used for the contiguous direction and for strided directions with
+ * fewer than 32768 lines; other lines are solved by PCR per (line, variable) or one lane
+ * per line.  mask in [0, 4095]; -1 restores the default (4095, all allowed).
+ * lg_get_line_tiles returns the mask in effect (-1 for a null context).  Applies to later
+ * calls and to batches created afterwards. */
 lg_status lg_set_line_tiles(lg_ctx* ctx, int mask);
 int lg_get_line_tiles(const lg_ctx* ctx);
 

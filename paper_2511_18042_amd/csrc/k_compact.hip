@@ -579,10 +579,11 @@ __global__ void __launch_bounds__(256) k_filter_pcr(const Prob* __restrict__ pro
 //   TK_FACES   C6 interface fluxes: node fluxes at -2 .. n+1 in, -J D into dQ/dt (or the
 //              RK stage in the last direction)
 //   TK_FILTER  implicit filter: the state in, its interior filtered in place
+//   TK_GRAD4   C4 gradients (MIG4 of C-GBR): as TK_GRAD6 with the C4 rows and tables
 struct TileArgs {
   StateRef ref;
   RKRef rr;
-  int d, TX, accumulate, rk, stage, mask;
+  int d, TX, accumulate, rk, stage, mask, skip_if_any;
   double a, b;
 };
 
@@ -592,7 +593,7 @@ __device__ __forceinline__ void tile_geom(const Prob& P, int d, int kind, int& L
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   const bool periodic = P.bc[d][0] == BC_PERIODIC;
   const int n = P.n[d], g = P.g[d];
-  if (kind == TK_GRAD6) {
+  if (kind == TK_GRAD6 || kind == TK_GRAD4) {
     Lin = P.N[d];
     off = -g;
     U = periodic ? n : P.N[d];
@@ -617,6 +618,7 @@ __global__ void __launch_bounds__(256) k_line_tiles(const Prob* __restrict__ pro
   const Prob& P = probs[blockIdx.y];
   const int d = A.d, TX = A.TX;
   if (d >= P.ndim || !tile_use(P, d, KIND, A.mask)) return;
+  if (A.skip_if_any >= 0 && P.any_flag && (*P.any_flag != 0) == (A.skip_if_any != 0)) return;
   int Lin, off, U, la, lb, ba, bb;
   tile_geom(P, d, KIND, Lin, off, U, la, lb, ba, bb);
   if (5 * TX * Lin > TILE_ELEMS || TX > TILE_MAX_TX) return;   // the host sizes TX so that this never holds
@@ -653,7 +655,7 @@ __global__ void __launch_bounds__(256) k_line_tiles(const Prob* __restrict__ pro
     double v[5] = {0, 0, 0, 0, 0};
     if (c < ncol) {
       const size_t node = lbase + (size_t)c * P.s[o1] + (size_t)(g + off + p) * sd;
-      if (KIND == TK_GRAD6) {
+      if (KIND == TK_GRAD6 || KIND == TK_GRAD4) {
         prims5c(A.ref.state(P), T, node, P.gamma - 1.0, v);
       } else if (KIND == TK_FACES) {
         const R* F = static_cast<const R*>(P.FL[d]);
@@ -678,7 +680,16 @@ __global__ void __launch_bounds__(256) k_line_tiles(const Prob* __restrict__ pro
       const double* f = buf + line * Lin;
       if (k < U) {
         double r;
-        if (KIND == TK_GRAD6) {
+        if (KIND == TK_GRAD4) {
+          if (periodic)
+            r = 0.75 * (f[g + wrap(k + 1, n)] - f[g + wrap(k - 1, n)]);
+          else if (k == 0)
+            r = (-3.0 * f[0] + 4.0 * f[1] - f[2]) / 2.0;
+          else if (k == U - 1)
+            r = (3.0 * f[U - 1] - 4.0 * f[U - 2] + f[U - 3]) / 2.0;
+          else
+            r = 0.75 * (f[k + 1] - f[k - 1]);
+        } else if (KIND == TK_GRAD6) {
           if (periodic)
             r = C6_A * (f[g + wrap(k + 1, n)] - f[g + wrap(k - 1, n)]) +
                 C6_B * (f[g + wrap(k + 2, n)] - f[g + wrap(k - 2, n)]);
@@ -727,7 +738,8 @@ __global__ void __launch_bounds__(256) k_line_tiles(const Prob* __restrict__ pro
   // ---- PCR over all 5 TX lines at once.  Each element keeps its (line start, row); the
   // factors of rows inside a step's band are two constants (see the table header), so only
   // rows near the line ends read the table.
-  const double* tab = KIND == TK_GRAD6 ? P.pcr6[d] : (KIND == TK_FACES ? P.pcrc[d] : P.pcrf[d]);
+  const double* tab =
+      KIND == TK_GRAD4 ? P.pcr[d] : (KIND == TK_GRAD6 ? P.pcr6[d] : (KIND == TK_FACES ? P.pcrc[d] : P.pcrf[d]));
   const int steps = KIND == TK_FILTER ? P.fsteps : LG_PCR_STEPS;
   const double* hdr = tab + (size_t)(2 * steps + 1) * U;
   int eln[TILE_PT], erow[TILE_PT];
@@ -787,7 +799,7 @@ __global__ void __launch_bounds__(256) k_line_tiles(const Prob* __restrict__ pro
   }
   __syncthreads();
   // ---- outputs
-  if (KIND == TK_GRAD6) {
+  if (KIND == TK_GRAD6 || KIND == TK_GRAD4) {
     R* G = static_cast<R*>(P.G[d]);
     const int pos0 = periodic ? g : 0;   // position of unknown 0
     for (int e = tid; e < TX * U; e += 256) {
@@ -897,7 +909,7 @@ void launch_grad_c6(const Launch& L, StateRef ref, int d) {
   const SysLaunch sl = sys_launch(L, TK_GRAD6, d);
   if (sl.tiles)
     launch_tiles<R, TK_GRAD6>(L, KC_GRAD_C4, L.max_N[d], L.max_N[o1], L.max_N[o2],
-                              TileArgs{ref, RKRef{nullptr, nullptr, nullptr}, d, 1, 0, 0, 0, L.tile_mask, 0.0, 0.0});
+                              TileArgs{ref, RKRef{nullptr, nullptr, nullptr}, d, 1, 0, 0, 0, L.tile_mask, -1, 0.0, 0.0});
   if (sl.pcr) {
     const unsigned lds = (unsigned)(2 * std::min<long long>(L.max_N[d], 4096) * sizeof(double));
     LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c6_pcr<R>, dim3(pcr_grid(L, 5 * L.lines[d]), L.nprob),
@@ -916,7 +928,7 @@ void launch_c6_faces(const Launch& L, StateRef ref, int d, int accumulate, const
   if (sl.tiles)
     launch_tiles<R, TK_FACES>(L, KC_C6_FACES, L.max_n[d] + 4, L.max_n[o1], L.max_n[o2],
                               TileArgs{ref, rr ? *rr : RKRef{nullptr, nullptr, nullptr}, d, 1, accumulate, rr ? 1 : 0,
-                                       stage, L.tile_mask, a, b});
+                                       stage, L.tile_mask, -1, a, b});
   if (sl.pcr) {
     const unsigned lds = (unsigned)((2 * std::min<long long>(L.max_n[d], 3990) + 4) * sizeof(double));
     LG_TIMED(L, KC_C6_FACES, hipLaunchKernelGGL(k_c6_faces_pcr<R>, dim3(pcr_grid(L, 5 * L.sweep_rows[d]), L.nprob),
@@ -935,7 +947,7 @@ void launch_filter(const Launch& L, StateRef ref, int d) {
   const SysLaunch sl = sys_launch(L, TK_FILTER, d);
   if (sl.tiles)
     launch_tiles<double, TK_FILTER>(L, KC_FILTER, L.max_N[d], L.max_n[o1], L.max_n[o2],
-                                    TileArgs{ref, RKRef{nullptr, nullptr, nullptr}, d, 1, 0, 0, 0, L.tile_mask, 0.0, 0.0});
+                                    TileArgs{ref, RKRef{nullptr, nullptr, nullptr}, d, 1, 0, 0, 0, L.tile_mask, -1, 0.0, 0.0});
   if (sl.pcr) {
     const unsigned lds = (unsigned)(std::min<long long>(L.max_N[d] + L.max_n[d], 7990) * sizeof(double));
     LG_TIMED(L, KC_FILTER, hipLaunchKernelGGL(k_filter_pcr, dim3(pcr_grid(L, 5 * L.sweep_rows[d]), L.nprob),
@@ -946,6 +958,17 @@ void launch_filter(const Launch& L, StateRef ref, int d) {
                                               L.stream, L.probs, ref, d, L.tile_mask));
 }
 
+template <typename R>
+void launch_grad_c4_tiles(const Launch& L, StateRef ref, int d, int skip_if_any) {
+  const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+  if (L.ctile[TK_GRAD4][d])
+    launch_tiles<R, TK_GRAD4>(L, KC_GRAD_C4, L.max_N[d], L.max_N[o1], L.max_N[o2],
+                              TileArgs{ref, RKRef{nullptr, nullptr, nullptr}, d, 1, 0, 0, 0, L.tile_mask, skip_if_any,
+                                       0.0, 0.0});
+}
+
+template void launch_grad_c4_tiles<float>(const Launch&, StateRef, int, int);
+template void launch_grad_c4_tiles<double>(const Launch&, StateRef, int, int);
 template void launch_grad_c6<float>(const Launch&, StateRef, int);
 template void launch_grad_c6<double>(const Launch&, StateRef, int);
 template void launch_c6_faces<float>(const Launch&, StateRef, int, int, const RKRef*, int, double, double);

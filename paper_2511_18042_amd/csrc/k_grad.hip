@@ -94,10 +94,11 @@ __device__ __forceinline__ void prims5(const double* Q, size_t T, size_t o, doub
 // gradients.
 template <typename R>
 __global__ void __launch_bounds__(256) k_grad_c4(const Prob* __restrict__ probs, StateRef ref, int d, int skip_if_any,
-                                                 int region) {
+                                                 int region, int mask) {
   const Prob& P = probs[blockIdx.y];
   if (d >= P.ndim || skip_launch(P, skip_if_any)) return;
   if (use_pcr(P, d)) return;   // done by the PCR kernel
+  if (!region && tile_use(P, d, TK_GRAD4, mask)) return;   // done in LDS tiles
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   const int nlines = P.N[o1] * P.N[o2];
   const int cnt = region ? P.lcount[d] : nlines;   // compacted list of lines that need solving
@@ -202,11 +203,12 @@ __global__ void __launch_bounds__(256) k_grad_c4(const Prob* __restrict__ probs,
 // Periodic lines reduce the cyclic system over the interior with wrapped indices.
 template <typename R>
 __global__ void __launch_bounds__(256) k_grad_c4_pcr(const Prob* __restrict__ probs, StateRef ref, int d,
-                                                     int skip_if_any, int region) {
+                                                     int skip_if_any, int region, int mask) {
   extern __shared__ double lds[];
   const Prob& P = probs[blockIdx.y];
   if (d >= P.ndim || skip_launch(P, skip_if_any)) return;
   if (!use_pcr(P, d)) return;   // the lane-per-line kernel does these
+  if (!region && tile_use(P, d, TK_GRAD4, mask)) return;   // done in LDS tiles
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   const int nlines = P.N[o1] * P.N[o2];
   const int cnt = region ? P.lcount[d] : nlines;   // compacted list of lines that need solving
@@ -303,19 +305,22 @@ void launch_grad_explicit(const Launch& L, int d, int order, int skip_if_any, in
 
 template <typename R>
 void launch_grad_c4(const Launch& L, StateRef ref, int d, int skip_if_any, int region) {
-  // each problem's direction is taken by exactly one kernel (use_pcr): PCR in LDS with
-  // persistent workgroups over the (line, primitive) items, or one lane per item
-  if (L.pcr_dir[d]) {
+  // each problem's direction is taken by exactly one kernel: LDS line tiles (region-free
+  // launches, tile_use), PCR in LDS with persistent workgroups over the (line, primitive)
+  // items, or one lane per line
+  if (!region) launch_grad_c4_tiles<R>(L, ref, d, skip_if_any);
+  const int mask = region ? 0 : L.tile_mask;
+  if (L.c4_rest_pcr[d] || (region && L.pcr_dir[d])) {
     const long long N = std::min<long long>(L.max_N[d], PCR_MAX_LINE);
     const unsigned lds = (unsigned)(2 * N * sizeof(double));
     long long blocks = std::min<long long>(5 * L.lines[d], L.pcr_blocks > 0 ? L.pcr_blocks : 16384);
     LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c4_pcr<R>, dim3((unsigned)blocks, L.nprob), dim3(256), lds,
-                                               L.stream, L.probs, ref, d, skip_if_any, region));
+                                               L.stream, L.probs, ref, d, skip_if_any, region, mask));
   }
-  if (L.thomas_dir[d]) {
+  if (L.c4_rest_thomas[d] || (region && L.thomas_dir[d])) {
     long long b = (L.lines[d] + 255) / 256;
     LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c4<R>, dim3((unsigned)b, L.nprob), dim3(256), 0, L.stream,
-                                               L.probs, ref, d, skip_if_any, region));
+                                               L.probs, ref, d, skip_if_any, region, mask));
   }
 }
 

@@ -233,8 +233,10 @@ std::vector<double> tri_periodic(int n) {
   return t;
 }
 
+void append_band_header(std::vector<double>& t, int L, int steps);
+
 // PCR elimination factors of the C4 matrix (see k_grad_c4_pcr): k1[steps][L], k2[steps][L],
-// binv[L]; periodic lines wrap their indices.
+// binv[L], then the band header; periodic lines wrap their indices.
 std::vector<double> pcr_table(int L, bool periodic, int steps) {
   std::vector<double> a(L), b(L), c(L), na(L), nb(L), nc(L);
   for (int i = 0; i < L; ++i) {
@@ -269,6 +271,7 @@ std::vector<double> pcr_table(int L, bool periodic, int steps) {
     c.swap(nc);
   }
   for (int i = 0; i < L; ++i) t[(size_t)2 * steps * L + i] = 1.0 / b[i];
+  append_band_header(t, L, steps);
   return t;
 }
 
@@ -344,9 +347,15 @@ std::vector<double> pcr_table_ac(std::vector<double> a, std::vector<double> c, b
     c.swap(nc);
   }
   for (int i = 0; i < L; ++i) t[(size_t)2 * steps * L + i] = 1.0 / b[i];
-  // band header (read by the LDS line tiles): for every step the factors of rows away from
-  // the line ends are bit-identical, so kernels use two constants there; per step st:
-  // {k1, k2, first row, last row} of the band around the middle row, then {binv, 0, lo, hi}
+  append_band_header(t, L, steps);
+  return t;
+}
+
+// Band header of a PCR table (read by the LDS line tiles): for every step the factors of
+// rows away from the line ends are bit-identical, so kernels use two constants there; per
+// step st: {k1, k2, first row, last row} of the band around the middle row, then
+// {binv, 0, lo, hi}
+void append_band_header(std::vector<double>& t, int L, int steps) {
   const size_t h0 = t.size();
   t.resize(h0 + 4 * (size_t)(steps + 1), 0.0);
   const int mid = L / 2;
@@ -363,7 +372,6 @@ std::vector<double> pcr_table_ac(std::vector<double> a, std::vector<double> c, b
     hd[2] = lo;
     hd[3] = hi;
   }
-  return t;
 }
 
 // Right-hand-side weights of the tenth-order implicit filter: the maximal-order member has
@@ -401,6 +409,11 @@ void fill_launch(Launch& L, const Prob& P) {
                (d == 0 || 5 * nlines < 131072);
     if (pcr) L.pcr_dir[d] = 1;
     else L.thomas_dir[d] = 1;
+    if (P.grad_c4) {
+      if (lg::tile_use(P, d, lg::TK_GRAD4, L.tile_mask)) L.ctile[lg::TK_GRAD4][d] = 1;
+      else if (pcr) L.c4_rest_pcr[d] = 1;
+      else L.c4_rest_thomas[d] = 1;
+    }
     if (periodic && P.n[d] < 128) L.has_short_periodic = 1;
     if (P.bc[d][0] == LG_BC_FIXED || P.bc[d][1] == LG_BC_FIXED) L.has_fixed = 1;
     if (P.lad_c6) {
@@ -895,8 +908,11 @@ lg_status lg_set_tuning(lg_ctx* c, int seg, int pcr_blocks, int zc) {
 lg_status lg_set_line_tiles(lg_ctx* c, int mask) {
   if (!c || mask < -1 || mask > lg::TILE_MASK_ALL) return LG_EINVAL;
   c->L.tile_mask = mask < 0 ? lg::TILE_MASK_DEFAULT : mask;
-  for (int k = 0; k < 3; ++k)
-    for (int d = 0; d < 3; ++d) c->L.ctile[k][d] = c->L.cpcr[k][d] = c->L.cthomas[k][d] = 0;
+  for (int d = 0; d < 3; ++d) {
+    for (int k = 0; k < 3; ++k) c->L.cpcr[k][d] = c->L.cthomas[k][d] = 0;
+    for (int k = 0; k < 4; ++k) c->L.ctile[k][d] = 0;
+    c->L.c4_rest_pcr[d] = c->L.c4_rest_thomas[d] = 0;
+  }
   fill_launch(c->L, c->hp);
   return LG_OK;
 }

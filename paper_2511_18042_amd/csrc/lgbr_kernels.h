@@ -82,7 +82,8 @@ struct Launch {
   int thomas_dir[3];       // some problem solves its lines along d one lane per line
   // LAD-C6 line systems [TK_*][d]: which kernels some problem needs (tile_use with this
   // launch's tile_mask): LDS line tiles, PCR per (line, variable), one lane per line
-  int ctile[3][3], cpcr[3][3], cthomas[3][3];
+  int ctile[4][3], cpcr[3][3], cthomas[3][3];
+  int c4_rest_pcr[3], c4_rest_thomas[3];   // C4 gradients of region-free launches not in tiles
   int tile_mask;           // bit 3 TK_* + d: LDS tiles allowed for that system and direction
   int max_fsteps;          // most PCR steps of any problem's filter systems
   int ndim;
@@ -153,6 +154,8 @@ inline dim3 zm_grid(const Launch& L, int lo, int hi, int TX, int TY) {
 // gradients (region = 1: only where the per-cell hybrid needs C-GBR inputs)
 template <typename R> void launch_grad_explicit(const Launch& L, int d, int order, int skip_if_any, int region);
 template <typename R> void launch_grad_c4(const Launch& L, StateRef ref, int d, int skip_if_any, int region);
+// C4 gradients of whole lines in LDS tiles (region-free launches; see tile_use)
+template <typename R> void launch_grad_c4_tiles(const Launch& L, StateRef ref, int d, int skip_if_any);
 // sensor and C-GBR viscous node fluxes
 template <typename R> void launch_sensor(const Launch& L, int skip_if_any, int region);
 template <typename R> void launch_gbr_viscflux(const Launch& L, int skip_if_any, int region);
@@ -184,8 +187,8 @@ void launch_filter(const Launch& L, StateRef ref, int d);
 // which kernel solves the lines of each system (shared by the host and the kernels):
 // LDS line tiles when all five variables of one line fit the tile and a periodic line is
 // long enough for the PCR steps; otherwise the policies below
-enum { TK_GRAD6 = 0, TK_FACES = 1, TK_FILTER = 2 };
-constexpr int TILE_MASK_ALL = 0x1FF;
+enum { TK_GRAD6 = 0, TK_FACES = 1, TK_FILTER = 2, TK_GRAD4 = 3 };
+constexpr int TILE_MASK_ALL = 0xFFF;
 constexpr int TILE_MASK_DEFAULT = TILE_MASK_ALL;
 constexpr int TILE_ELEMS = 6144;   // doubles per tile (48 KB of LDS)
 constexpr int TILE_PT = TILE_ELEMS / 256;
@@ -195,7 +198,7 @@ __host__ __device__ inline bool tile_ok(const Prob& P, int d, int kind) {
   const int n = P.n[d];
   const int Lin = kind == TK_FACES ? n + 4 : P.N[d];
   if (5 * Lin > TILE_ELEMS) return false;
-  const int steps = kind == TK_FILTER ? P.fsteps : LG_PCR_STEPS;
+  const int steps = kind == TK_FILTER ? P.fsteps : LG_PCR_STEPS;   // TK_GRAD4: the C4 tables
   return !(periodic && n < (2 << steps));
 }
 // Where tiles are allowed (tile_mask), they are used for the contiguous direction, and for
@@ -209,7 +212,8 @@ __host__ __device__ inline bool tile_use(const Prob& P, int d, int kind, int mas
   if (!((mask >> (3 * kind + d)) & 1) || !tile_ok(P, d, kind)) return false;
   if (d == 0) return true;
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
-  const long long lines = kind == TK_GRAD6 ? (long long)P.N[o1] * P.N[o2] : (long long)P.n[o1] * P.n[o2];
+  const bool all_nodes = kind == TK_GRAD6 || kind == TK_GRAD4;
+  const long long lines = all_nodes ? (long long)P.N[o1] * P.N[o2] : (long long)P.n[o1] * P.n[o2];
   return lines < TILE_FEW_LINES;
 }
 __host__ __device__ inline bool c6_grad_pcr(const Prob& P, int d) {

@@ -88,7 +88,7 @@ def _opts(alpha=0.49):
 
 
 # line-solve kernels: LDS line tiles everywhere, or the PCR / lane-per-line kernels only
-TILES = {'default': -1, 'tiles': 0x1FF, 'no_tiles': 0}
+TILES = {'default': -1, 'tiles': 0xFFF, 'no_tiles': 0}
 
 
 @pytest.mark.parametrize('name', list(CASES))
@@ -101,7 +101,7 @@ def test_lad_c6_rhs_parity_fp64(name, tiles):
     ref = orhs.rhs(c.Q, g, gas, opts, 'lad')
     ctx, _ = U.gpu_context(c, gas, opts)
     ctx.set_line_tiles(TILES[tiles])
-    assert ctx.get_line_tiles() == (TILES[tiles] if TILES[tiles] >= 0 else 0x1FF)
+    assert ctx.get_line_tiles() == (TILES[tiles] if TILES[tiles] >= 0 else 0xFFF)
     out = U.gpu_rhs(ctx, c, 'lad')
     U.compare(out, ref, g, U.RHS_RTOL, label='lad-c6 %s %s' % (name, tiles))
     ctx.close()

@@ -66,6 +66,24 @@ def test_rhs_parity_fp64(name, scheme, grad, mode):
     ctx.close()
 
 
+@pytest.mark.parametrize('name', list(CASES))
+@pytest.mark.parametrize('mask', [0, 0xFFF])
+def test_mig4_line_kernels_parity_fp64(name, mask):
+    """MIG4 gradients solved in LDS line tiles (mask 0xFFF; small problems use them in every
+    direction) or by the PCR / lane-per-line kernels only (mask 0): both against the oracle."""
+    print('mig4 lines', name, mask, flush=True)
+    c = CASES[name]()
+    gas, opts = _gas(name), _opts('C4', 'global')
+    g = U.oracle_grid(c)
+    info = {}
+    ref = orhs.rhs(c.Q, g, gas, opts, 'cgbr', info=info)
+    ctx, _ = U.gpu_context(c, gas, opts)
+    ctx.set_line_tiles(mask)
+    out = U.gpu_rhs(ctx, c, 'cgbr')
+    U.compare(out, ref, g, U.RHS_RTOL, U.excused_mask(info, g), label='mig4 %s mask %x' % (name, mask))
+    ctx.close()
+
+
 @pytest.mark.parametrize('scheme,grad', [('cgbr', 'E6'), ('cgbr', 'C4'), ('lad', 'E6'), ('hybrid', 'E6')])
 def test_stage_parity_fp64(scheme, grad):
     """Each stage starts from the oracle's own stage input; the stage output must agree to
