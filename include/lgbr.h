@@ -112,6 +112,8 @@ typedef struct {
   double filter_alpha; /* alpha_f of the tenth-order implicit filter that ends every
                           rk3_step of a LG_LAD_C6 context (Alg. 1); 0 <= alpha_f <= 0.5,
                           0.5 = no filter.  Ignored for LG_LAD_E4.                     */
+  int filter_every_stage; /* 0: filter after the third stage (Alg. 1); 1: after every
+                          stage of rk3_step (an alternative reading)                   */
 } lg_opts;
 
 typedef struct lg_ctx lg_ctx;
@@ -171,7 +173,8 @@ lg_status hybrid_rhs(lg_ctx* ctx, double* Q, double* dQdt, const uint8_t* flags_
  * dt = cfl / max_i sum_l (|xi_l . u| + c |xi_l|) from Q, clipped so that t does not
  * pass t_end; t_inout is a device double that is advanced by dt.  dt stays on the
  * device (no host synchronisation).  LG_SCHEME_LAD on a LG_LAD_C6 context ends the step
- * with lad_filter (Alg. 1) unless filter_alpha = 0.5. */
+ * with lad_filter (Alg. 1) unless filter_alpha = 0.5 (with filter_every_stage, every
+ * stage). */
 lg_status rk3_step(lg_ctx* ctx, int scheme, double* Q, double t_end, double* t_inout);
 
 /* One RK3 stage from given states (for per-stage checks):

@@ -24,7 +24,7 @@ Readings used here:
        nodes, and the unknowns of a bounded line are its interior nodes, whose
        neighbours across the boundary enter unfiltered (ghost values, never written:
        FIXED ghosts stay the caller's); a periodic line is cyclic over its interior
-       nodes.
+       nodes.  Alternative placement (option): after every stage.
 """
 from fractions import Fraction
 

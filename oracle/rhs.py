@@ -65,6 +65,7 @@ class Opts:
     dilate: int = 3
     lad: str = 'E4'               # LAD central scheme: 'E4' or 'C6'
     filter_alpha: float = 0.49    # alpha_f of the LAD-C6 filter (0.5: no filter)
+    filter_every_stage: bool = False   # R29 alternative: filter after every RK stage
 
 
 def primitives(Q, gamma):
@@ -207,7 +208,8 @@ def uses_filter(opts, scheme):
 
 
 def rk3_step(Q, t, t_end, grid, gas, opts, scheme, M=None):
-    """One SSP-RK3 step (R8, R17), filtered after the third stage for LAD-C6 (R29).
+    """One SSP-RK3 step (R8, R17), filtered after the third stage for LAD-C6 (R29; after
+    every stage with ``opts.filter_every_stage``).
     Returns (Q_new, t_new, dt, nonphysical_count)."""
     if M is None:
         M = gr.node_metrics(grid)
@@ -216,7 +218,7 @@ def rk3_step(Q, t, t_end, grid, gas, opts, scheme, M=None):
     U = Q
     for s in range(3):
         U = rk3_stage(Q, U, dt, s, grid, gas, opts, scheme, M)
-        if s == 2 and uses_filter(opts, scheme):
+        if (s == 2 or opts.filter_every_stage) and uses_filter(opts, scheme):
             U = filter_state(U, grid, opts.filter_alpha)
         bad += nonphysical_count(U, grid, gas.gamma)
     return U, t + dt, dt, bad

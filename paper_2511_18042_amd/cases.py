@@ -10,8 +10,12 @@ refilled by the boundary images at every stage.
 
 Workloads (shapes and value ranges of the paper's cases, Sec. 3):
   sod            1D shock tube, Sec. 3.1
+  lax, le_blanc  1D shock tubes with the printed states, Sec. 3.1
   shu_osher      1D shock / entropy-wave interaction, Sec. 3.1
+  khi            2D Kelvin-Helmholtz instability, Sec. 3.2
+  riemann_c3, riemann_c12   2D four-quadrant Riemann problems, Sec. 3.2
   triple_point   2D three-state Riemann problem, Sec. 3.2
+  shock_bubble   2D shock / light-cylinder interaction, Sec. 3.2
   quadrants      2D four-quadrant Riemann problems with seeded random states
   ramp3d         3D curvilinear compression-ramp grid with a turbulent-boundary-
                  layer-like state (M 2.9, 24 degrees; Sec. 3.4 shapes)
@@ -92,6 +96,31 @@ def sod(n=400):
     return c
 
 
+def shock_tube(n, length, x_face, left, right, t_end, gamma=1.4):
+    """1D Riemann problem on [0, length]: (rho, u, p) left / right of x_face; the inflow
+    (left) ghosts hold the initial left state (FIXED), the outflow extrapolates."""
+    c = Case(1, _pad3((n,)), [(FIXED, TRANSMISSIVE)], h=(length / n, 1.0, 1.0), t_end=t_end, gamma=gamma)
+    x, _, _ = cartesian_mesh(c)
+    lft = x < x_face
+    rho = np.where(lft, left[0], right[0])
+    u = np.where(lft, left[1], right[1])
+    p = np.where(lft, left[2], right[2])
+    z = np.zeros_like(x)
+    c.Q = conserved(rho, u, z, z, p, gamma)
+    c.extra = dict(left=tuple(left), right=tuple(right), x_interface=x_face)
+    return c
+
+
+def lax(n=200):
+    return shock_tube(n, 1.0, 0.5, (0.445, 0.698, 3.528), (0.5, 0.0, 0.571), 0.14)
+
+
+def le_blanc(n=900):
+    """Density and pressure jumps of 1e3 and 1e9, gamma = 5/3, t = 6."""
+    return shock_tube(n, 9.0, 3.0, (1.0, 0.0, 2.0 / 3.0 * 1e-1), (1e-3, 0.0, 2.0 / 3.0 * 1e-10), 6.0,
+                      gamma=5.0 / 3.0)
+
+
 SHU_OSHER_POST = (3.857143, 2.629369, 10.33333)
 
 
@@ -142,6 +171,63 @@ def quadrants(n, states, split=(0.5, 0.5)):
     rho, u, v, p = (arr[q, m] for m in range(4))
     c.Q = conserved(rho, u, v, np.zeros_like(rho), p, c.gamma)
     c.extra = dict(rho_thr=0.5 * arr[:, 0].min(), p_thr=0.5 * arr[:, 3].min())
+    return c
+
+
+def riemann_c3(n=400):
+    """Strong four-quadrant problem (Schulz-Rinne configuration 3): split at 0.8,
+    pressure ratio about 51, t = 0.8."""
+    s11 = 4.0 / np.sqrt(11.0)
+    st = [(1.5, 0.0, 0.0, 1.5), (33.0 / 62.0, s11, 0.0, 0.3), (77.0 / 558.0, s11, s11, 9.0 / 310.0),
+          (33.0 / 62.0, 0.0, s11, 0.3)]
+    c = quadrants(n, st, split=(0.8, 0.8))
+    c.t_end = 0.8
+    return c
+
+
+def riemann_c12(n=800):
+    """Weak four-quadrant problem (the paper's configuration F): split at 0.5, t = 0.25."""
+    st = [(0.5313, 0.0, 0.0, 0.4), (1.0, 0.7276, 0.0, 1.0), (0.8, 0.0, 0.0, 1.0), (1.0, 0.0, 0.7276, 1.0)]
+    c = quadrants(n, st, split=(0.5, 0.5))
+    c.t_end = 0.25
+    return c
+
+
+def khi(n=512):
+    """Kelvin-Helmholtz instability on the periodic unit square, t = 0.8: p = 2.5, a
+    heavy (rho 2, u 0.5) band 0.25 < y <= 0.75 in light fluid (rho 1, u -0.5), and a
+    sin(4 pi x) v perturbation on both interfaces (Gaussian width 0.05 / sqrt 2)."""
+    c = Case(2, _pad3((n, n)), [(PERIODIC, PERIODIC)] * 2, h=(1.0 / n, 1.0 / n, 1.0), t_end=0.8)
+    x, y, _ = cartesian_mesh(c)
+    band = (y > 0.25) & (y <= 0.75)
+    rho = np.where(band, 2.0, 1.0)
+    u = np.where(band, 0.5, -0.5)
+    sig = 0.05 / np.sqrt(2.0)
+    v = 0.1 * np.sin(4 * np.pi * x) * (np.exp(-(y - 0.75) ** 2 / (2 * sig ** 2)) +
+                                       np.exp(-(y - 0.25) ** 2 / (2 * sig ** 2)))
+    p = np.full_like(x, 2.5)
+    c.Q = conserved(rho, u, v, np.zeros_like(x), p, c.gamma)
+    c.extra = dict(rho_thr=-1.0, p_thr=-1.0)
+    return c
+
+
+SHOCK_BUBBLE_POST = (1.3764, -0.3336, 1.5698 / 1.4)
+
+
+def shock_bubble(nx=1300, ny=356):
+    """Mach 1.22 shock at x/D = 4.5 moving into still air (rho 1, p 1/1.4) towards a light
+    cylinder (rho 0.1819, same pressure) of diameter D = 1 centred at (3.5, 0.89), on
+    [0, 6.5] x [0, 1.78]; outflow left and right, inviscid walls top and bottom, t = 6."""
+    c = Case(2, _pad3((nx, ny)), [(TRANSMISSIVE, TRANSMISSIVE), (REFLECTIVE, REFLECTIVE)],
+             h=(6.5 / nx, 1.78 / ny, 1.0), t_end=6.0)
+    x, y, _ = cartesian_mesh(c)
+    post = x > 4.5
+    bubble = (x - 3.5) ** 2 + (y - 0.89) ** 2 < 0.25
+    rho = np.where(post, SHOCK_BUBBLE_POST[0], np.where(bubble, 0.1819, 1.0))
+    u = np.where(post, SHOCK_BUBBLE_POST[1], 0.0)
+    p = np.where(post, SHOCK_BUBBLE_POST[2], 1.0 / 1.4)
+    c.Q = conserved(rho, u, np.zeros_like(x), np.zeros_like(x), p, c.gamma)
+    c.extra = dict(rho_thr=0.5 * 0.1819, p_thr=-1.0)
     return c
 
 

@@ -53,6 +53,7 @@ struct Cfg {
   int ndim, precision, grad, hybrid_mode, viscous, dilate;
   int lad_c6, filter;   // LAD-C6 context; its steps end with the implicit filter
   double falpha;
+  int filter_all;       // ... or filter after every stage
 };
 
 }  // namespace
@@ -179,13 +180,16 @@ void enqueue_rhs(const Launch& L, const Cfg& c, int scheme, StateRef ref, const 
 template <typename R>
 void enqueue_rk3(const Launch& L, const Cfg& c, int scheme, double* Qx, double* tx, double t_end) {
   lg::launch_dt(L, Qx, tx, t_end, 1);
+  const bool filt = scheme == LG_SCHEME_LAD && c.lad_c6 && c.filter;
   for (int s = 0; s < 3; ++s) {
     StateRef ref{s == 0 ? Qx : nullptr, nullptr, s == 0 ? 0 : 1};
     RKRef rr{Qx, nullptr, nullptr};
     enqueue_rhs<R>(L, c, scheme, ref, nullptr, &rr, s);
+    if (filt && (s == 2 || c.filter_all)) {   // FILTER_CALLS (after the last stage, Alg. 1)
+      const StateRef out{s == 2 ? Qx : nullptr, nullptr, s == 2 ? 0 : 1};   // the stage result
+      for (int d = 0; d < c.ndim; ++d) lg::launch_filter(L, out, d);
+    }
   }
-  if (scheme == LG_SCHEME_LAD && c.lad_c6 && c.filter)   // FILTER_CALLS after the last stage
-    for (int d = 0; d < c.ndim; ++d) lg::launch_filter(L, StateRef{Qx, nullptr, 0}, d);
 }
 
 lg_status last_hip() { return hipGetLastError() == hipSuccess ? LG_OK : LG_EHIP; }
@@ -547,7 +551,7 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
   filter_weights(P.falpha, P.fcoef);
   P.fsteps = filt ? filter_pcr_steps(P.falpha) : 0;
   c->cfg = Cfg{G.ndim, opts->precision, opts->grad, opts->hybrid_mode, gas->viscous, opts->dilate, c6, filt,
-               P.falpha};
+               P.falpha, opts->filter_every_stage ? 1 : 0};
 
   const size_t T = (size_t)total;
   const size_t rs = opts->precision == LG_MIXED ? sizeof(float) : sizeof(double);
@@ -952,7 +956,7 @@ lg_status lg_batch_create(lg_batch** out, lg_ctx* const* ctxs, double* const* Q,
     const Cfg& ci = ctxs[i]->cfg;
     if (ci.ndim != c0.ndim || ci.precision != c0.precision || ci.grad != c0.grad ||
         ci.hybrid_mode != c0.hybrid_mode || ci.viscous != c0.viscous || ci.dilate != c0.dilate ||
-        ci.lad_c6 != c0.lad_c6 || ci.filter != c0.filter)
+        ci.lad_c6 != c0.lad_c6 || ci.filter != c0.filter || ci.filter_all != c0.filter_all)
       return LG_EINVAL;
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == ctxs[i]) return LG_EINVAL;  // workspaces must not be shared

@@ -83,8 +83,8 @@ def _gas(name, c):
     return orhs.Gas(gamma=c.gamma)
 
 
-def _opts(alpha=0.49):
-    return orhs.Opts(lad='C6', filter_alpha=alpha, C_mu=0.002)
+def _opts(alpha=0.49, every=False):
+    return orhs.Opts(lad='C6', filter_alpha=alpha, C_mu=0.002, filter_every_stage=every)
 
 
 # line-solve kernels: LDS line tiles everywhere, or the PCR / lane-per-line kernels only
@@ -131,15 +131,17 @@ def test_filter_parity_fp64(name, alpha, tiles):
     ctx.close()
 
 
-@pytest.mark.parametrize('name', ['2d_walls', '1d_fixed', '3d_curv', '2d_periodic_wide'])
-def test_lad_c6_rk3_step_parity_fp64(name):
-    """Three stages and the filter; two steps in a row.  (The 40x32x16 ramp crop is left
-    out: without the C-GBR fluxes, LAD alone -- E4 or C6 -- loses positivity on it within
-    the first step, in the oracle as on the GPU.)"""
-    print('rk3', name, flush=True)
+@pytest.mark.parametrize('name,every', [(n, False) for n in ('2d_walls', '1d_fixed', '3d_curv', '2d_periodic_wide')] +
+                         [(n, True) for n in ('2d_walls', '3d_curv', '2d_periodic_wide')])
+def test_lad_c6_rk3_step_parity_fp64(name, every):
+    """Three stages and the filter (after the last stage, or after every stage); two steps in
+    a row.  Left out, because LAD alone loses positivity on them within two steps in the
+    oracle as on the GPU: the 40x32x16 ramp crop (E4 or C6), and the 96-cell Shu-Osher
+    tube with the filter after every stage."""
+    print('rk3', name, every, flush=True)
     torch = U.torch_mod()
     c = CASES[name]()
-    gas, opts = _gas(name, c), _opts()
+    gas, opts = _gas(name, c), _opts(every=every)
     g = U.oracle_grid(c)
     M = ogrid.node_metrics(g)
     ctx, _ = U.gpu_context(c, gas, opts)
@@ -200,12 +202,13 @@ def test_lad_c6_mixed_precision_on_smooth_data():
     ctx.close()
 
 
-def test_lad_c6_batch_graph_matches_the_oracle():
+@pytest.mark.parametrize('every', [False, True])
+def test_lad_c6_batch_graph_matches_the_oracle(every):
     """Two problems of different sizes, two steps per captured graph, replayed twice."""
     torch = U.torch_mod()
     cs = [case_2d_walls(), cases.random_rough_state(cases.Case(2, (40, 52, 1), [(T, T), (RF, RF)],
                                                               h=(1.0 / 40, 1.0 / 52, 1)), seed=31)]
-    gas, opts = orhs.Gas(), _opts()
+    gas, opts = orhs.Gas(), _opts(every=every)
     ctxs, Qs, ts = [], [], []
     for c in cs:
         ctx, _ = U.gpu_context(c, gas, opts)

@@ -1,0 +1,163 @@
+"""The paper's stability table (Sec. 4.1, Table tbl:scheme_comparison) rerun on the GPU for
+the cases whose initial conditions the paper prints (Sec. 3.1-3.2), with this library's
+schemes: LAD-C6 (with its implicit filter), MEG6 and MIG4 C-GBR, the LAD-E4/MEG6 hybrid
+(global switch) and LAD-E4 alone, all in FP64 at CFL 0.2.
+
+A run advances with graph-captured RK3 steps until t_end and counts non-physical nodes
+(rho <= 0, p <= 0 or not finite) after every stage; it is reported "converged" when it
+reaches t_end with none, "diverged at t" otherwise.  The 1D shock tubes also report the
+L1 density error against the exact Riemann solution (oracle/riemann.py).
+
+    python tests/validation_runs.py [--out FILE]      # the full table (GPU, a few minutes)
+
+``tests/test_gpu_validation.py`` runs a subset as a GPU test.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+sys.path.insert(0, HERE)
+
+from paper_2511_18042_amd import cases, lgbr  # noqa: E402
+
+# (name, builder, paper cells, paper LAD-C6, paper C-GBR); the paper's Shu-Osher row uses 300 cells
+CASES = [
+    ('sod', lambda: cases.sod(200), '200x1', True, True),
+    ('lax', lambda: cases.lax(200), '200x1', True, True),
+    ('le_blanc', lambda: cases.le_blanc(900), '900x1', False, True),
+    ('shu_osher', lambda: cases.shu_osher(300), '300x1', True, True),
+    ('khi', lambda: cases.khi(512), '512x512', True, True),
+    ('riemann_c3', lambda: cases.riemann_c3(400), '400x400', False, True),
+    ('riemann_c12', lambda: cases.riemann_c12(800), '800x800', True, True),
+    ('triple_point', lambda: cases.triple_point(1792, 768), '1792x768', False, True),
+    ('triple_point_extrapolated', lambda: _extrapolated(cases.triple_point(1792, 768)), '1792x768', False, True),
+    ('shock_bubble', lambda: cases.shock_bubble(1300, 356), '1300x356', True, True),
+]
+
+def _extrapolated(c):
+    """The paper's boundary treatment for the triple point: extrapolation on all walls (the
+    workload above keeps reflective walls, reading R21)."""
+    c.bc = [(cases.TRANSMISSIVE, cases.TRANSMISSIVE)] * 2
+    return c
+
+
+# (label, scheme, MEG6 / MIG4 gradients, LAD central scheme[, filter alpha_f, filter every stage])
+SCHEMES = [
+    ('lad_c6', 'lad', 'E6', 'C6'),
+    ('lad_c6_every_stage_0.40', 'lad', 'E6', 'C6', 0.40, True),
+    ('cgbr_meg6', 'cgbr', 'E6', 'E4'),
+    ('cgbr_mig4', 'cgbr', 'C4', 'E4'),
+    ('hybrid_meg6', 'hybrid', 'E6', 'E4'),
+    ('lad_e4', 'lad', 'E6', 'E4'),
+]
+
+
+def exact_l1(c, Q):
+    """L1 density error of a 1D shock tube against the exact Riemann solution."""
+    from oracle import riemann
+    e = c.extra
+    n = c.n[0]
+    x = (np.arange(n) + 0.5) * c.h[0]
+    ex = riemann.sample(e['left'], e['right'], c.gamma, (x - e['x_interface']) / c.t_end)
+    rho = Q[0, 0, 0, 5:5 + n]
+    return float(np.abs(rho - ex[0]).mean())
+
+
+def run(c, scheme, grad, lad, alpha=0.49, every=False, precision='fp64', wall=120.0, chunk=200):
+    """Advance case c to t_end (or until the first non-physical stage, or `wall` seconds)."""
+    import torch
+    g = lgbr.make_grid(c.ndim, c.n, c.bc, c.h)
+    gas = lgbr.make_gas(gamma=c.gamma)
+    e = c.extra or {}
+    opts = lgbr.make_opts(grad=grad, precision=precision, cfl=0.2, hybrid_mode='global', lad=lad,
+                          rho_thr=e.get('rho_thr', -1.0), p_thr=e.get('p_thr', -1.0), filter_alpha=alpha,
+                          filter_every_stage=every)
+    ctx = lgbr.Context(g, gas, opts)
+    Q = torch.from_numpy(np.ascontiguousarray(c.Q)).cuda()
+    t = torch.zeros(1, dtype=torch.float64, device='cuda')
+    b = lgbr.Batch([ctx], [Q], [t], [c.t_end], chunk, scheme)
+    t0 = time.perf_counter()
+    t_prev, bad, steps = 0.0, 0, 0
+    while True:
+        b.run()
+        torch.cuda.synchronize()
+        steps += chunk
+        bad = ctx.poll_status()
+        tv = float(t.item())
+        if bad or tv >= c.t_end or time.perf_counter() - t0 > wall:
+            break
+        t_prev = tv
+    out = Q.cpu().numpy()
+    b.close()
+    ctx.close()
+    res = {'status': 'converged' if (bad == 0 and tv >= c.t_end) else ('diverged' if bad else 'timeout'),
+           't_end': c.t_end, 't': round(tv, 6), 'seconds': round(time.perf_counter() - t0, 2)}
+    if bad:
+        res['t_fail_within'] = [round(t_prev, 6), round(tv, 6)]
+        res['nonphysical'] = bad
+    if c.ndim == 1 and 'left' in (c.extra or {}) and res['status'] == 'converged':
+        res['L1_rho_exact'] = exact_l1(c, out)
+    return res
+
+
+def table(names=None, schemes=None, wall=120.0):
+    rows = []
+    for name, build, cells, p_lad, p_gbr in CASES:
+        if names and name not in names:
+            continue
+        row = {'case': name, 'cells': cells, 'paper': {'lad_c6': p_lad, 'c_gbr': p_gbr}, 'runs': {}}
+        for label, scheme, grad, lad, *filt in SCHEMES:
+            if schemes and label not in schemes:
+                continue
+            c = build()
+            row['runs'][label] = run(c, scheme, grad, lad, *filt, wall=wall)
+            print('VALIDATION ' + json.dumps({'case': name, 'scheme': label, **row['runs'][label]}), flush=True)
+        rows.append(row)
+    return rows
+
+
+def markdown(rows):
+    labels = [s[0] for s in SCHEMES]
+    out = ['| case | cells | paper LAD-C6 | paper C-GBR | ' + ' | '.join(labels) + ' |',
+           '|' + '---|' * (4 + len(labels))]
+    for r in rows:
+        cells = []
+        for lb in labels:
+            v = r['runs'].get(lb)
+            if v is None:
+                cells.append('')
+            elif v['status'] == 'converged':
+                cells.append('yes' + (' (L1 %.2e)' % v['L1_rho_exact'] if 'L1_rho_exact' in v else ''))
+            elif v['status'] == 'diverged':
+                cells.append('no (t %.3g)' % v['t_fail_within'][1])
+            else:
+                cells.append('t %.3g of %g' % (v['t'], v['t_end']))
+        out.append('| %s | %s | %s | %s | %s |' % (r['case'], r['cells'], 'yes' if r['paper']['lad_c6'] else 'no',
+                                                  'yes' if r['paper']['c_gbr'] else 'no', ' | '.join(cells)))
+    return '\n'.join(out)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument('--out', default=None)
+    ap.add_argument('--cases', nargs='*', default=None)
+    ap.add_argument('--schemes', nargs='*', default=None)
+    ap.add_argument('--wall', type=float, default=120.0)
+    a = ap.parse_args()
+    rows = table(a.cases, a.schemes, a.wall)
+    md = markdown(rows)
+    print(md)
+    if a.out:
+        with open(a.out, 'w') as f:
+            json.dump(rows, f, indent=1)
+            f.write('\n')
+
+
+if __name__ == '__main__':
+    main()
