@@ -49,6 +49,8 @@ def parse():
     ap.add_argument('--workload', default='all', choices=['all', 'ramp3d', 'triple_point', 'batch64'])
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--variants', default='all', choices=['all', 'none'])
+    ap.add_argument('--only-variant', default=None,
+                    help='with --workload ramp3d: of the config-4 variants run only this one (profiling)')
     ap.add_argument('--copy-probe-mib', type=int, default=0,
                     help='run one plain device copy of this many MiB first (calibrates HBM counters)')
     return ap.parse_args()
@@ -204,7 +206,7 @@ def ramp3d(args, variants, cpu):
                 'sim_time_end': round(t_end, 6), 'troubled_interface_fraction': round(gbr_frac, 5),
                 'roofline': roof, 'kernel_breakdown_ms_per_step': brk})
     head.close()
-    if variants:
+    if variants and not args.only_variant:
         log('ramp3d: forced-flag sweep')
         pc = context('mixed', mode='percell')
         res['forced_flag_sweep'] = forced_sweep(pc, Q0, tuple(c.shape))
@@ -224,6 +226,8 @@ def ramp3d(args, variants, cpu):
                 ('lad_e4_mixed', 'mixed', 'lad', 'C4', 'global'),
                 ('lad_c6_fp64', 'fp64', 'lad', 'C4', 'global', 'C6'),
                 ('lad_c6_mixed', 'mixed', 'lad', 'C4', 'global', 'C6')):
+            if args.only_variant and vname != args.only_variant:
+                continue
             log('ramp3d: variant ' + vname)
             ctx = context(prec, grad, mode, *vv)
             vms, _, vbad, _, _ = R.steps(ctx, scheme, Q0, K=min(args.steps, 20), W=3)
@@ -236,6 +240,8 @@ def ramp3d(args, variants, cpu):
             torch.cuda.empty_cache()
         # the paper's per-stage speed-up study: LAD-C6 against MEG6 / MIG4 C-GBR (FP64 there)
         res['variants'] = var
+        if args.only_variant:
+            return res
         res['lad_c6_speedup'] = {
             p: {'over_meg6': round(var['cgbr_meg6_' + p]['ms_per_step'] / var['lad_c6_' + p]['ms_per_step'], 3),
                 'over_mig4': round(var['cgbr_mig4_' + p]['ms_per_step'] / var['lad_c6_' + p]['ms_per_step'], 3),
