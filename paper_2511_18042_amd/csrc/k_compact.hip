@@ -44,10 +44,13 @@ constexpr int CPCR_MAXPT = 4096 / 256;
 // least 2^(steps+1)); the couplings left after `steps` steps are below rounding.
 __device__ void pcr_lds(double* r, int L, bool periodic, const double* tab, int steps) {
   double nv[CPCR_MAXPT];
+  const double* hdr = tab + (size_t)(2 * steps + 1) * L;   // band header (see the line tiles)
   for (int st = 0; st < steps; ++st) {
     const int s = 1 << st;
     const double* k1 = tab + (size_t)st * L;
     const double* k2 = tab + (size_t)(steps + st) * L;
+    const double c1 = hdr[4 * st], c2 = hdr[4 * st + 1];
+    const int blo = (int)hdr[4 * st + 2], bhi = (int)hdr[4 * st + 3];
 #pragma unroll
     for (int m = 0; m < CPCR_MAXPT; ++m) {
       const int i = threadIdx.x + m * 256;
@@ -63,7 +66,12 @@ __device__ void pcr_lds(double* r, int L, bool periodic, const double* tab, int 
           rm = im >= 0 ? r[im] : 0.0;
           rp = ip < L ? r[ip] : 0.0;
         }
-        nv[m] = r[i] - k1[i] * rm - k2[i] * rp;
+        double f1 = c1, f2 = c2;
+        if (i < blo || i > bhi) {
+          f1 = k1[i];
+          f2 = k2[i];
+        }
+        nv[m] = r[i] - f1 * rm - f2 * rp;
       }
     }
     __syncthreads();
@@ -75,7 +83,9 @@ __device__ void pcr_lds(double* r, int L, bool periodic, const double* tab, int 
     __syncthreads();
   }
   const double* binv = tab + (size_t)2 * steps * L;
-  for (int i = threadIdx.x; i < L; i += blockDim.x) r[i] *= binv[i];
+  const double cb = hdr[4 * steps];
+  const int blo = (int)hdr[4 * steps + 2], bhi = (int)hdr[4 * steps + 3];
+  for (int i = threadIdx.x; i < L; i += blockDim.x) r[i] *= (i < blo || i > bhi) ? binv[i] : cb;
   __syncthreads();
 }
 

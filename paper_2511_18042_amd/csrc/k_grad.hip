@@ -197,9 +197,10 @@ __global__ void __launch_bounds__(256) k_grad_c4(const Prob* __restrict__ probs,
 // FP64 primitives and reduced by parallel cyclic reduction.  The matrix is the same for
 // every line of a direction, so the elimination factors k1 = a_i / b_{i-s} and
 // k2 = c_i / b_{i+s} of every step and the final 1/b_i are precomputed on the host
-// (table layout: k1[PCR_STEPS][L], k2[PCR_STEPS][L], binv[L]).  For the C4 matrix the
-// couplings shrink as (2 - sqrt 3)^(2^k), so after PCR_STEPS = 7 steps they are below
-// 1e-70 of the diagonal and x_i = d_i / b_i is the direct solution up to rounding.
+// (table layout: k1[PCR_STEPS][L], k2[PCR_STEPS][L], binv[L], then per step the band of
+// rows sharing one pair of factors).  For the C4 matrix the couplings shrink as
+// (2 - sqrt 3)^(2^k), so after PCR_STEPS = 6 steps they are below 1e-36 of the diagonal
+// and x_i = d_i / b_i is the direct solution up to rounding.
 // Periodic lines reduce the cyclic system over the interior with wrapped indices.
 template <typename R>
 __global__ void __launch_bounds__(256) k_grad_c4_pcr(const Prob* __restrict__ probs, StateRef ref, int d,
@@ -246,10 +247,15 @@ __global__ void __launch_bounds__(256) k_grad_c4_pcr(const Prob* __restrict__ pr
   __syncthreads();
   constexpr int MAXPT = PCR_MAX_LINE / 256;
   double nv[MAXPT];
+  // rows inside a step's band share two factors (band header after the table), so only
+  // rows near the line ends read the table
+  const double* hdr = tab + (size_t)(2 * PCR_STEPS + 1) * L;
   for (int st = 0; st < PCR_STEPS; ++st) {
     const int s = 1 << st;
     const double* k1 = tab + (size_t)st * L;
     const double* k2 = tab + (size_t)(PCR_STEPS + st) * L;
+    const double c1 = hdr[4 * st], c2 = hdr[4 * st + 1];
+    const int blo = (int)hdr[4 * st + 2], bhi = (int)hdr[4 * st + 3];
 #pragma unroll
     for (int m = 0; m < MAXPT; ++m) {
       int i = threadIdx.x + m * 256;
@@ -265,7 +271,12 @@ __global__ void __launch_bounds__(256) k_grad_c4_pcr(const Prob* __restrict__ pr
           rm = im >= 0 ? r[im] : 0.0;
           rp = ip < L ? r[ip] : 0.0;
         }
-        nv[m] = r[i] - k1[i] * rm - k2[i] * rp;
+        double f1 = c1, f2 = c2;
+        if (i < blo || i > bhi) {
+          f1 = k1[i];
+          f2 = k2[i];
+        }
+        nv[m] = r[i] - f1 * rm - f2 * rp;
       }
     }
     __syncthreads();
@@ -277,9 +288,11 @@ __global__ void __launch_bounds__(256) k_grad_c4_pcr(const Prob* __restrict__ pr
     __syncthreads();
   }
   const double* binv = tab + (size_t)2 * PCR_STEPS * L;
+  const double cb = hdr[4 * PCR_STEPS];
+  const int blo = (int)hdr[4 * PCR_STEPS + 2], bhi = (int)hdr[4 * PCR_STEPS + 3];
   R* G = static_cast<R*>(P.G[d]) + (size_t)q * T;
   for (int i = threadIdx.x; i < L; i += blockDim.x) {
-    R y = (R)(r[i] * binv[i]);
+    R y = (R)(r[i] * ((i < blo || i > bhi) ? binv[i] : cb));
     G[base + (size_t)(i + off0) * sd] = y;
     if (periodic) {
       if (i >= n - g) G[base + (size_t)(i + off0 - n) * sd] = y;   // low ghosts
