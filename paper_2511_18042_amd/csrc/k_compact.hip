@@ -37,9 +37,10 @@ namespace lg {
 
 constexpr double C6_A = 7.0 / 9.0, C6_B = 1.0 / 36.0;
 constexpr double C6F_A = 29.0 / 36.0, C6F_B = 1.0 / 36.0, C6_ALPHA = 1.0 / 3.0;
-constexpr int CPCR_MAXPT = 4096 / 256;
+constexpr int CPCR_THREADS = 512;   // lanes per workgroup of the one-line PCR kernels
+constexpr int CPCR_MAXPT = 4096 / CPCR_THREADS;
 
-// Parallel cyclic reduction of r[0..L) in LDS by the whole (256-lane) workgroup; the
+// Parallel cyclic reduction of r[0..L) in LDS by the whole (CPCR_THREADS-lane) workgroup; the
 // solution x_i = r_i / b_i is left in r.  Periodic lines wrap their indices (L must be at
 // least 2^(steps+1)); the couplings left after `steps` steps are below rounding.
 __device__ void pcr_lds(double* r, int L, bool periodic, const double* tab, int steps) {
@@ -53,7 +54,7 @@ __device__ void pcr_lds(double* r, int L, bool periodic, const double* tab, int 
     const int blo = (int)hdr[4 * st + 2], bhi = (int)hdr[4 * st + 3];
 #pragma unroll
     for (int m = 0; m < CPCR_MAXPT; ++m) {
-      const int i = threadIdx.x + m * 256;
+      const int i = threadIdx.x + m * CPCR_THREADS;
       if (i < L) {
         int im = i - s, ip = i + s;
         double rm, rp;
@@ -77,7 +78,7 @@ __device__ void pcr_lds(double* r, int L, bool periodic, const double* tab, int 
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < CPCR_MAXPT; ++m) {
-      const int i = threadIdx.x + m * 256;
+      const int i = threadIdx.x + m * CPCR_THREADS;
       if (i < L) r[i] = nv[m];
     }
     __syncthreads();
@@ -217,7 +218,7 @@ __global__ void __launch_bounds__(256) k_grad_c6(const Prob* __restrict__ probs,
 // One workgroup per (line, primitive), persistent over the items; the primitive along the
 // line in LDS, the right-hand side reduced by PCR.
 template <typename R>
-__global__ void __launch_bounds__(256) k_grad_c6_pcr(const Prob* __restrict__ probs, StateRef ref, int d,
+__global__ void __launch_bounds__(CPCR_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_grad_c6_pcr(const Prob* __restrict__ probs, StateRef ref, int d,
                                                      int mask) {
   extern __shared__ double lds[];
   const Prob& P = probs[blockIdx.y];
@@ -414,7 +415,7 @@ __global__ void __launch_bounds__(256) k_c6_faces(const Prob* __restrict__ probs
 // line, component); node fluxes at positions -2 .. n+1 and the face right-hand sides in
 // LDS; writes -J D into dQ/dt.
 template <typename R>
-__global__ void __launch_bounds__(256) k_c6_faces_pcr(const Prob* __restrict__ probs, StateRef ref, int d,
+__global__ void __launch_bounds__(CPCR_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_c6_faces_pcr(const Prob* __restrict__ probs, StateRef ref, int d,
                                                       int mask) {
   extern __shared__ double lds[];
   const Prob& P = probs[blockIdx.y];
@@ -543,7 +544,7 @@ __global__ void __launch_bounds__(256) k_filter(const Prob* __restrict__ probs, 
 
 // Contiguous lines: one workgroup per (interior line, variable); the line in LDS, the
 // interior unknowns reduced by PCR, written back in place.
-__global__ void __launch_bounds__(256) k_filter_pcr(const Prob* __restrict__ probs, StateRef ref, int d,
+__global__ void __launch_bounds__(CPCR_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_filter_pcr(const Prob* __restrict__ probs, StateRef ref, int d,
                                                     int mask) {
   extern __shared__ double lds[];
   const Prob& P = probs[blockIdx.y];
@@ -621,8 +622,10 @@ __device__ __forceinline__ void tile_geom(const Prob& P, int d, int kind, int& L
   }
 }
 
-template <typename R, int KIND>
-__global__ void __launch_bounds__(256) k_line_tiles(const Prob* __restrict__ probs, TileArgs A) {
+template <typename R, int KIND, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 4 : 1)))
+k_line_tiles(const Prob* __restrict__ probs, TileArgs A) {
+  constexpr int PT = TILE_ELEMS / NT;   // slots per lane
   __shared__ double buf[TILE_ELEMS];
   __shared__ double lohi[2 * 5 * TILE_MAX_TX];
   const Prob& P = probs[blockIdx.y];
@@ -659,7 +662,7 @@ __global__ void __launch_bounds__(256) k_line_tiles(const Prob* __restrict__ pro
     }
   };
   // ---- load
-  for (int e = tid; e < ncp; e += 256) {
+  for (int e = tid; e < ncp; e += NT) {
     int c, p;
     cp_of(e, c, p);
     double v[5] = {0, 0, 0, 0, 0};
@@ -680,10 +683,10 @@ __global__ void __launch_bounds__(256) k_line_tiles(const Prob* __restrict__ pro
   __syncthreads();
   // ---- right-hand sides (registers, then over the inputs)
   const int nel = 5 * TX * Lin;
-  double nv[TILE_PT];
+  double nv[PT];
 #pragma unroll
-  for (int m = 0; m < TILE_PT; ++m) {
-    const int e = tid + m * 256;
+  for (int m = 0; m < PT; ++m) {
+    const int e = tid + m * NT;
     nv[m] = 0.0;
     if (e < nel) {
       const int line = e / Lin, k = e % Lin;
@@ -740,26 +743,24 @@ __global__ void __launch_bounds__(256) k_line_tiles(const Prob* __restrict__ pro
   }
   __syncthreads();
 #pragma unroll
-  for (int m = 0; m < TILE_PT; ++m) {
-    const int e = tid + m * 256;
+  for (int m = 0; m < PT; ++m) {
+    const int e = tid + m * NT;
     if (e < nel) buf[e] = nv[m];
   }
   __syncthreads();
-  // ---- PCR over all 5 TX lines at once.  Each element keeps its (line start, row); the
-  // factors of rows inside a step's band are two constants (see the table header), so only
+  // ---- PCR over all 5 TX lines at once.  Each slot keeps its row (its line starts at
+  // its LDS index minus the row); the factors of rows inside a step's band are two constants (see the table header), so only
   // rows near the line ends read the table.
   const double* tab =
       KIND == TK_GRAD4 ? P.pcr[d] : (KIND == TK_GRAD6 ? P.pcr6[d] : (KIND == TK_FACES ? P.pcrc[d] : P.pcrf[d]));
   const int steps = KIND == TK_FILTER ? P.fsteps : LG_PCR_STEPS;
   const double* hdr = tab + (size_t)(2 * steps + 1) * U;
-  int eln[TILE_PT], erow[TILE_PT];
+  int erow[PT];
 #pragma unroll
-  for (int m = 0; m < TILE_PT; ++m) {
-    const int e = tid + m * 256;
+  for (int m = 0; m < PT; ++m) {
+    const int e = tid + m * NT;
     const int k = e % Lin;
-    const bool ok = e < nel && k < U;
-    eln[m] = e - k;
-    erow[m] = ok ? k : -1;
+    erow[m] = (e < nel && k < U) ? k : -1;
   }
   for (int st = 0; st < steps; ++st) {
     const int s = 1 << st;
@@ -768,10 +769,10 @@ __global__ void __launch_bounds__(256) k_line_tiles(const Prob* __restrict__ pro
     const double c1 = hdr[4 * st], c2 = hdr[4 * st + 1];
     const int blo = (int)hdr[4 * st + 2], bhi = (int)hdr[4 * st + 3];
 #pragma unroll
-    for (int m = 0; m < TILE_PT; ++m) {
+    for (int m = 0; m < PT; ++m) {
       const int k = erow[m];
       if (k >= 0) {
-        const double* r = buf + eln[m];
+        const double* r = buf + (tid + m * NT - k);
         int km = k - s, kp = k + s;
         double rm, rp;
         if (periodic) {
@@ -793,8 +794,8 @@ __global__ void __launch_bounds__(256) k_line_tiles(const Prob* __restrict__ pro
     }
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < TILE_PT; ++m)
-      if (erow[m] >= 0) buf[eln[m] + erow[m]] = nv[m];
+    for (int m = 0; m < PT; ++m)
+      if (erow[m] >= 0) buf[tid + m * NT] = nv[m];
     __syncthreads();
   }
   {
@@ -802,9 +803,9 @@ __global__ void __launch_bounds__(256) k_line_tiles(const Prob* __restrict__ pro
     const double cb = hdr[4 * steps];
     const int blo = (int)hdr[4 * steps + 2], bhi = (int)hdr[4 * steps + 3];
 #pragma unroll
-    for (int m = 0; m < TILE_PT; ++m) {
+    for (int m = 0; m < PT; ++m) {
       const int k = erow[m];
-      if (k >= 0) buf[eln[m] + k] *= (k < blo || k > bhi) ? binv[k] : cb;
+      if (k >= 0) buf[tid + m * NT] *= (k < blo || k > bhi) ? binv[k] : cb;
     }
   }
   __syncthreads();
@@ -812,7 +813,7 @@ __global__ void __launch_bounds__(256) k_line_tiles(const Prob* __restrict__ pro
   if (KIND == TK_GRAD6 || KIND == TK_GRAD4) {
     R* G = static_cast<R*>(P.G[d]);
     const int pos0 = periodic ? g : 0;   // position of unknown 0
-    for (int e = tid; e < TX * U; e += 256) {
+    for (int e = tid; e < TX * U; e += NT) {
       int c, k;
       if (d == 0) {
         k = e % U;
@@ -837,7 +838,7 @@ __global__ void __launch_bounds__(256) k_line_tiles(const Prob* __restrict__ pro
     FaceOut o{A.ref, A.rr, A.accumulate, A.rk, A.stage, A.a, A.b};
     const double dt = A.rk ? *P.dt : 0.0;
     int bad = 0;
-    for (int e = tid; e < TX * n; e += 256) {
+    for (int e = tid; e < TX * n; e += NT) {
       int c, i;
       if (d == 0) {
         i = e % n;
@@ -866,7 +867,7 @@ __global__ void __launch_bounds__(256) k_line_tiles(const Prob* __restrict__ pro
     if (bad) atomicAdd(P.status, bad);
   } else {
     double* Q = A.ref.state(P);
-    for (int e = tid; e < TX * n; e += 256) {
+    for (int e = tid; e < TX * n; e += NT) {
       int c, k;
       if (d == 0) {
         k = e % n;
@@ -893,8 +894,12 @@ static void launch_tiles(const Launch& L, int kc, long long Lmax, long long line
   A.TX = tile_tx(Lmax);
   const long long nt = ((lines_a + A.TX - 1) / A.TX) * lines_b;
   const unsigned grid = (unsigned)(8 * ((nt + 7) / 8));
-  LG_TIMED(L, kc, hipLaunchKernelGGL((k_line_tiles<R, KIND>), dim3(grid, L.nprob), dim3(256), 0, L.stream,
-                                     L.probs, A));
+  if (A.d == 0)
+    LG_TIMED(L, kc, hipLaunchKernelGGL((k_line_tiles<R, KIND, TILE_THREADS_CONTIG>), dim3(grid, L.nprob),
+                                       dim3(TILE_THREADS_CONTIG), 0, L.stream, L.probs, A));
+  else
+    LG_TIMED(L, kc, hipLaunchKernelGGL((k_line_tiles<R, KIND, TILE_THREADS_STRIDED>), dim3(grid, L.nprob),
+                                       dim3(TILE_THREADS_STRIDED), 0, L.stream, L.probs, A));
 }
 
 // ------------------------------------------------------------------ launches
@@ -923,7 +928,7 @@ void launch_grad_c6(const Launch& L, StateRef ref, int d) {
   if (sl.pcr) {
     const unsigned lds = (unsigned)(2 * std::min<long long>(L.max_N[d], 4096) * sizeof(double));
     LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c6_pcr<R>, dim3(pcr_grid(L, 5 * L.lines[d]), L.nprob),
-                                               dim3(256), lds, L.stream, L.probs, ref, d, L.tile_mask));
+                                               dim3(CPCR_THREADS), lds, L.stream, L.probs, ref, d, L.tile_mask));
   }
   if (sl.thomas)
     LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c6<R>, dim3(blocks_for(L.lines[d]), L.nprob), dim3(256), 0,
@@ -942,7 +947,7 @@ void launch_c6_faces(const Launch& L, StateRef ref, int d, int accumulate, const
   if (sl.pcr) {
     const unsigned lds = (unsigned)((2 * std::min<long long>(L.max_n[d], 3990) + 4) * sizeof(double));
     LG_TIMED(L, KC_C6_FACES, hipLaunchKernelGGL(k_c6_faces_pcr<R>, dim3(pcr_grid(L, 5 * L.sweep_rows[d]), L.nprob),
-                                                dim3(256), lds, L.stream, L.probs, ref, d, L.tile_mask));
+                                                dim3(CPCR_THREADS), lds, L.stream, L.probs, ref, d, L.tile_mask));
   }
   if (sl.thomas) {
     FaceOut o{ref, rr ? *rr : RKRef{nullptr, nullptr, nullptr}, accumulate, rr ? 1 : 0, stage, a, b};
@@ -961,7 +966,7 @@ void launch_filter(const Launch& L, StateRef ref, int d) {
   if (sl.pcr) {
     const unsigned lds = (unsigned)(std::min<long long>(L.max_N[d] + L.max_n[d], 7990) * sizeof(double));
     LG_TIMED(L, KC_FILTER, hipLaunchKernelGGL(k_filter_pcr, dim3(pcr_grid(L, 5 * L.sweep_rows[d]), L.nprob),
-                                              dim3(256), lds, L.stream, L.probs, ref, d, L.tile_mask));
+                                              dim3(CPCR_THREADS), lds, L.stream, L.probs, ref, d, L.tile_mask));
   }
   if (sl.thomas)
     LG_TIMED(L, KC_FILTER, hipLaunchKernelGGL(k_filter, dim3(blocks_for(L.sweep_rows[d]), L.nprob), dim3(256), 0,

@@ -191,7 +191,10 @@ enum { TK_GRAD6 = 0, TK_FACES = 1, TK_FILTER = 2, TK_GRAD4 = 3 };
 constexpr int TILE_MASK_ALL = 0xFFF;
 constexpr int TILE_MASK_DEFAULT = TILE_MASK_ALL;
 constexpr int TILE_ELEMS = 6144;   // doubles per tile (48 KB of LDS)
-constexpr int TILE_PT = TILE_ELEMS / 256;
+// lanes per tile workgroup: contiguous lines take 512 (128 VGPRs, four waves per SIMD);
+// strided tiles of long lines hold one or few columns, whose strided reads stay in L2 only
+// while few workgroups are in flight: 256 lanes and no register cap
+constexpr int TILE_THREADS_CONTIG = 512, TILE_THREADS_STRIDED = 256;
 constexpr int TILE_MAX_TX = 16;
 __host__ __device__ inline bool tile_ok(const Prob& P, int d, int kind) {
   const bool periodic = P.bc[d][0] == BC_PERIODIC;
