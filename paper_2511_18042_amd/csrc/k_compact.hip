@@ -894,7 +894,7 @@ static void launch_tiles(const Launch& L, int kc, long long Lmax, long long line
   A.TX = tile_tx(Lmax);
   const long long nt = ((lines_a + A.TX - 1) / A.TX) * lines_b;
   const unsigned grid = (unsigned)(8 * ((nt + 7) / 8));
-  if (A.d == 0)
+  if (A.d == 0 || A.TX >= 8)
     LG_TIMED(L, kc, hipLaunchKernelGGL((k_line_tiles<R, KIND, TILE_THREADS_CONTIG>), dim3(grid, L.nprob),
                                        dim3(TILE_THREADS_CONTIG), 0, L.stream, L.probs, A));
   else

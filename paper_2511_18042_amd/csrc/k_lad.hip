@@ -182,7 +182,8 @@ __global__ void __launch_bounds__(256) k_lad_dx(const Prob* __restrict__ probs) 
 // at positions -2 .. n+1 (the fourth differences of the raw coefficients reach two nodes
 // past the interior); E4 physical gradients recomputed from W (CG: stored gradients)
 template <typename R, bool CG>
-__global__ void __launch_bounds__(256) k_lad_shear(const Prob* __restrict__ probs, int skip_if_any, int zc) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 6 : 4)))
+k_lad_shear(const Prob* __restrict__ probs, int skip_if_any, int zc) {
   const Prob& P = probs[blockIdx.y];
   if (lad_skip(P, skip_if_any)) return;
   ZCol c;

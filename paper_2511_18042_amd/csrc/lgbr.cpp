@@ -910,7 +910,7 @@ lg_status lg_set_tuning(lg_ctx* c, int seg, int pcr_blocks, int zc) {
 }
 
 lg_status lg_set_line_tiles(lg_ctx* c, int mask) {
-  if (!c || mask < -1 || mask > lg::TILE_MASK_ALL) return LG_EINVAL;
+  if (!c || mask < -1 || mask > (lg::TILE_MASK_ALL | lg::TILE_MASK_FORCE_STRIDED)) return LG_EINVAL;
   c->L.tile_mask = mask < 0 ? lg::TILE_MASK_DEFAULT : mask;
   for (int d = 0; d < 3; ++d) {
     for (int k = 0; k < 3; ++k) c->L.cpcr[k][d] = c->L.cthomas[k][d] = 0;

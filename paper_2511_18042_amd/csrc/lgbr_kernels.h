@@ -189,6 +189,7 @@ void launch_filter(const Launch& L, StateRef ref, int d);
 // long enough for the PCR steps; otherwise the policies below
 enum { TK_GRAD6 = 0, TK_FACES = 1, TK_FILTER = 2, TK_GRAD4 = 3 };
 constexpr int TILE_MASK_ALL = 0xFFF;
+constexpr int TILE_MASK_FORCE_STRIDED = 0x1000;   // tiles on strided directions whatever their line count
 constexpr int TILE_MASK_DEFAULT = TILE_MASK_ALL;
 constexpr int TILE_ELEMS = 6144;   // doubles per tile (48 KB of LDS)
 // lanes per tile workgroup: contiguous lines take 512 (128 VGPRs, four waves per SIMD);
@@ -213,7 +214,7 @@ __host__ __device__ inline bool tile_ok(const Prob& P, int d, int kind) {
 constexpr long long TILE_FEW_LINES = 32768;
 __host__ __device__ inline bool tile_use(const Prob& P, int d, int kind, int mask) {
   if (!((mask >> (3 * kind + d)) & 1) || !tile_ok(P, d, kind)) return false;
-  if (d == 0) return true;
+  if (d == 0 || (mask & TILE_MASK_FORCE_STRIDED)) return true;
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   const bool all_nodes = kind == TK_GRAD6 || kind == TK_GRAD4;
   const long long lines = all_nodes ? (long long)P.N[o1] * P.N[o2] : (long long)P.n[o1] * P.n[o2];
