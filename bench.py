@@ -146,9 +146,9 @@ class Runner:
         bad = ctx.poll_status()
         return ms, kern, bad, Q, float(t.item())
 
-    def roofline(self, ctx, scheme, Q0, cells, ndim, gbr_frac, viscous, curv, K=20):
-        planar = ctx.metrics_planar()
+    def roofline(self, ctx, scheme, Q0, cells, ndim, gbr_frac, viscous, curv, K=20, traffic_file=None):
         """Per-class breakdown, then the dominant class timed alone."""
+        planar = ctx.metrics_planar()
         _, breakdown, _, _, _ = self.steps(ctx, scheme, Q0, K=K, W=2, prof_class=-1)
         dominant = max(breakdown, key=lambda k: breakdown[k][0])
         _, kern, _, _, _ = self.steps(ctx, scheme, Q0, K=K, W=2, prof_class=dominant)
@@ -159,8 +159,37 @@ class Runner:
         roof = {'bound': 'hbm', 'kernel': dominant, 'achieved': round(achieved, 1), 'peak': HBM_PEAK_GBS,
                 'unit': 'GB/s', 'frac': round(achieved / HBM_PEAK_GBS, 4), 'avg_launch_ms': round(dom_avg, 5),
                 'launches': dom_n, 'algorithmic_bytes_per_launch': int(algo), 'traffic': None}
+        if traffic_file:
+            tr, why = profiled_traffic(traffic_file, dominant)
+            roof['traffic'] = tr
+            roof['traffic_source'] = os.path.relpath(traffic_file, ROOT) + ('' if tr else ' (%s)' % why)
+            if tr:
+                roof['traffic_over_algorithmic'] = round(tr / algo, 3)
         brk = {k: round(v[0] / K, 4) for k, v in sorted(breakdown.items(), key=lambda kv: -kv[1][0])}
         return roof, brk
+
+
+def profiled_traffic(path, kclass):
+    """HBM bytes per launch of kernel class kclass from a committed rocprofv3 counter summary
+    (its TRAFFIC line: FETCH_SIZE and WRITE_SIZE in KiB per dispatch and their scales from a
+    copy of known size), or None with the reason: no such line, or the kernel sources no
+    longer hash to what was profiled."""
+    import hashlib
+    if not os.path.exists(path):
+        return None, 'no profile'
+    for line in open(path):
+        f = line.split()
+        if len(f) < 3 or f[0] != 'TRAFFIC' or f[1] != kclass:
+            continue
+        kv = dict(x.split('=', 1) for x in f[2:])
+        h = hashlib.sha256()
+        for src in kv['sources'].split(','):
+            h.update(open(os.path.join(ROOT, src), 'rb').read())
+        if h.hexdigest() != kv['sha256']:
+            return None, 'kernel sources changed since the counters were taken'
+        kib = float(kv['fetch_kib']) * float(kv['fetch_scale']) + float(kv['write_kib']) * float(kv['write_scale'])
+        return int(kib * 1024), ''
+    return None, 'no counters for this kernel'
 
 
 def flags_of(ctx, Q):
@@ -201,7 +230,8 @@ def ramp3d(args, variants, cpu):
     ms, _, bad, Q, t_end = R.steps(head, 'hybrid', Q0)
     gbr_frac = interface_fraction(flags_of(head, Q), 'global')
     del Q
-    roof, brk = R.roofline(head, 'hybrid', Q0, cells, 3, gbr_frac, True, True)
+    roof, brk = R.roofline(head, 'hybrid', Q0, cells, 3, gbr_frac, True, True,
+                           traffic_file=os.path.join(ROOT, 'profiles', 'ramp3d_hybrid_mig4_mixed_hbm_traffic.txt'))
     res.update({'value': mcell(cells, ms), 'ms_per_step': round(ms, 4), 'nonphysical_nodes': bad,
                 'sim_time_end': round(t_end, 6), 'troubled_interface_fraction': round(gbr_frac, 5),
                 'roofline': roof, 'kernel_breakdown_ms_per_step': brk})

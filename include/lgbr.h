@@ -222,8 +222,9 @@ lg_status lg_get_tuning(const lg_ctx* ctx, int* seg, int* pcr_blocks, int* zc);
  * workgroup) for system s (0 = LAD-C6 gradients, 1 = LAD-C6 interface fluxes, 2 = implicit
  * filter, 3 = MIG4 gradients outside per-cell hybrid stages) along direction d.  Where
  * allowed, tiles are used for the contiguous direction and for strided directions with
- * fewer than 32768 lines; other lines are solved by PCR per (line, variable) or one lane
- * per line.  mask in [0, 4095]; -1 restores the default (4095, all allowed).
+ * fewer than 32768 lines (bit 12 set: for strided directions whatever their line count);
+ * other lines are solved by PCR per (line, variable) or one lane per line.  mask in
+ * [0, 8191]; -1 restores the default (4095, all allowed, bit 12 clear).
  * lg_get_line_tiles returns the mask in effect (-1 for a null context).  Applies to later
  * calls and to batches created afterwards. */
 lg_status lg_set_line_tiles(lg_ctx* ctx, int mask);

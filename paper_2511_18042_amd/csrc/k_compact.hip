@@ -22,9 +22,11 @@
 //
 // Each system has constant coefficients, so its factors are tables built on the host:
 //   bounded, m unknowns (Thomas):  cp[m], inv[m], a[m]      (a = sub-diagonal of each row)
-//   cyclic, n unknowns:            cp[n], inv[n], z[n], fac, alpha
+//   cyclic, n unknowns:            cp[n], inv[n], z[n], fac, alpha, c[n]
 //       (A = B + u v^T with u = (-1, 0.., alpha), v = (1, 0.., -alpha); B z = u,
-//        x = y - (y_0 - alpha y_{n-1}) fac z with B y = r, fac = 1 / (1 + v.z))
+//        x = y - (y_0 - alpha y_{n-1}) fac z with B y = r, fac = 1 / (1 + v.z);
+//        y_0 = sum_k c_k d_k over the forward-eliminated d, so one back substitution
+//        emits x)
 //   PCR factors:                   k1[steps][L], k2[steps][L], binv[L]
 // Lines along the contiguous direction are solved by parallel cyclic reduction in LDS, one
 // workgroup per (line, variable); strided lines one lane per line, coalesced across lanes.
@@ -181,9 +183,10 @@ __global__ void __launch_bounds__(256) k_grad_c6(const Prob* __restrict__ probs,
     const double* inv = tab + n;
     const double* z = tab + 2 * n;
     const double fac = tab[3 * n], al = tab[3 * n + 1];
+    const double* y0c = tab + 3 * n + 2;
     const size_t b0 = base + (size_t)g * sd;
     for (int p = 0; p < 4; ++p) prims5c(Q, T, base + (size_t)(g + wrap(p - 2, n)) * sd, gm1, w[p]);
-    double dprev[5] = {0, 0, 0, 0, 0};
+    double dprev[5] = {0, 0, 0, 0, 0}, y0[5] = {0, 0, 0, 0, 0};
     for (int i = 0; i < n; ++i) {
       prims5c(Q, T, base + (size_t)(g + wrap(i + 2, n)) * sd, gm1, w[4]);
       for (int q = 0; q < 5; ++q) {
@@ -191,23 +194,21 @@ __global__ void __launch_bounds__(256) k_grad_c6(const Prob* __restrict__ probs,
         const double dd = (i == 0 ? r : r - al * dprev[q]) * inv[i];
         S[q * T + b0 + (size_t)i * sd] = dd;
         dprev[q] = dd;
+        y0[q] = y0[q] + y0c[i] * dd;
       }
       for (int p = 0; p < 4; ++p)
         for (int q = 0; q < 5; ++q) w[p][q] = w[p + 1][q];
     }
-    double y[5], ylast[5];
-    for (int q = 0; q < 5; ++q) y[q] = ylast[q] = dprev[q];
-    for (int i = n - 2; i >= 0; --i)
+    // one back substitution emitting x = y - (y_0 - al y_{n-1}) fac z
+    double y[5], vy[5];
+    for (int q = 0; q < 5; ++q) {
+      y[q] = dprev[q];
+      vy[q] = (y0[q] - al * dprev[q]) * fac;
+    }
+    for (int i = n - 1; i >= 0; --i)
       for (int q = 0; q < 5; ++q) {
-        y[q] = S[q * T + b0 + (size_t)i * sd] - cp[i] * y[q];
-        S[q * T + b0 + (size_t)i * sd] = y[q];
-      }
-    double vy[5];
-    for (int q = 0; q < 5; ++q) vy[q] = (y[q] - al * ylast[q]) * fac;
-    for (int i = 0; i < n; ++i)
-      for (int q = 0; q < 5; ++q) {
-        const double yi = (i == n - 1) ? ylast[q] : S[q * T + b0 + (size_t)i * sd];
-        const R xv = (R)(yi - vy[q] * z[i]);
+        if (i < n - 1) y[q] = S[q * T + b0 + (size_t)i * sd] - cp[i] * y[q];
+        const R xv = (R)(y[q] - vy[q] * z[i]);
         G[q * T + b0 + (size_t)i * sd] = xv;
         if (i >= n - g) G[q * T + b0 + (size_t)(i - n) * sd] = xv;   // low ghosts
         if (i < g) G[q * T + b0 + (size_t)(i + n) * sd] = xv;        // high ghosts
@@ -368,11 +369,12 @@ __global__ void __launch_bounds__(256) k_c6_faces(const Prob* __restrict__ probs
     const double* inv = tab + n;
     const double* z = tab + 2 * n;
     const double fac = tab[3 * n], al = tab[3 * n + 1];
+    const double* y0c = tab + 3 * n + 2;
     auto atw = [&](int q, int p) { return at(q, wrap(p, n)); };
-    double w[4][5], dprev[5];
+    double w[4][5], dprev[5], y0[5];
     for (int q = 0; q < 5; ++q) {
       for (int p = 0; p < 3; ++p) w[p][q] = atw(q, p - 1);
-      dprev[q] = 0.0;
+      dprev[q] = y0[q] = 0.0;
     }
     for (int k = 0; k < n; ++k) {
       for (int q = 0; q < 5; ++q) {
@@ -381,32 +383,31 @@ __global__ void __launch_bounds__(256) k_c6_faces(const Prob* __restrict__ probs
         const double dd = (k == 0 ? r : r - al * dprev[q]) * inv[k];
         S[q * T + base + (size_t)(g + k) * sd] = dd;
         dprev[q] = dd;
+        y0[q] = y0[q] + y0c[k] * dd;
         w[0][q] = w[1][q];
         w[1][q] = w[2][q];
         w[2][q] = w[3][q];
       }
     }
-    double y[5], ylast[5];
-    for (int q = 0; q < 5; ++q) y[q] = ylast[q] = dprev[q];
-    for (int k = n - 2; k >= 0; --k)
+    // one back substitution emitting the faces x = y - (y_0 - al y_{n-1}) fac z and, from
+    // each pair of neighbouring faces, the node difference D_{k+1} = x_{k+1} - x_k
+    double y[5], vy[5], xlast[5], xnext[5], D[5];
+    for (int q = 0; q < 5; ++q) {
+      y[q] = dprev[q];
+      vy[q] = (y0[q] - al * dprev[q]) * fac;
+      xlast[q] = xnext[q] = y[q] - vy[q] * z[n - 1];
+    }
+    for (int k = n - 2; k >= 0; --k) {
       for (int q = 0; q < 5; ++q) {
         y[q] = S[q * T + base + (size_t)(g + k) * sd] - cp[k] * y[q];
-        S[q * T + base + (size_t)(g + k) * sd] = y[q];
+        const double x = y[q] - vy[q] * z[k];
+        D[q] = xnext[q] - x;
+        xnext[q] = x;
       }
-    double vy[5], xprev[5], D[5];
-    for (int q = 0; q < 5; ++q) {
-      vy[q] = (y[q] - al * ylast[q]) * fac;
-      xprev[q] = ylast[q] - vy[q] * z[n - 1];
+      if (face_emit(P, o, dQ, dt, base + (size_t)(g + k + 1) * sd, D)) ++bad;
     }
-    for (int i = 0; i < n; ++i) {
-      for (int q = 0; q < 5; ++q) {
-        const double yi = (i == n - 1) ? ylast[q] : S[q * T + base + (size_t)(g + i) * sd];
-        const double x = yi - vy[q] * z[i];
-        D[q] = x - xprev[q];
-        xprev[q] = x;
-      }
-      if (face_emit(P, o, dQ, dt, base + (size_t)(g + i) * sd, D)) ++bad;
-    }
+    for (int q = 0; q < 5; ++q) D[q] = xnext[q] - xlast[q];   // node 0: x_0 - x_{n-1}
+    if (face_emit(P, o, dQ, dt, base + (size_t)g * sd, D)) ++bad;
   }
   if (bad) atomicAdd(P.status, bad);
 }
@@ -519,24 +520,25 @@ __global__ void __launch_bounds__(256) k_filter(const Prob* __restrict__ probs, 
     } else {
       const double* z = tab + 2 * n;
       const double fac = tab[3 * n];
+      const double* y0c = tab + 3 * n + 2;
+      double y0 = 0.0;
       for (int i = 0; i < n; ++i) {
         w[10] = at(i + 5);
         const double r = filt_rhs(P, w);
         const double dd = (i == 0 ? r : r - al * dprev) * inv[i];
         Sq[(size_t)(g + i) * sd] = dd;
         dprev = dd;
+        y0 = y0 + y0c[i] * dd;
         for (int p = 0; p < 10; ++p) w[p] = w[p + 1];
       }
+      // one back substitution writing x = y - (y_0 - al y_{n-1}) fac z (the forward pass
+      // has read every input it needs)
+      const double vy = (y0 - al * dprev) * fac;
       double y = dprev;
-      const double ylast = dprev;
+      phi[(size_t)(g + n - 1) * sd] = y - vy * z[n - 1];
       for (int i = n - 2; i >= 0; --i) {
         y = Sq[(size_t)(g + i) * sd] - cp[i] * y;
-        Sq[(size_t)(g + i) * sd] = y;
-      }
-      const double vy = (y - al * ylast) * fac;
-      for (int i = 0; i < n; ++i) {
-        const double yi = (i == n - 1) ? ylast : Sq[(size_t)(g + i) * sd];
-        phi[(size_t)(g + i) * sd] = yi - vy * z[i];
+        phi[(size_t)(g + i) * sd] = y - vy * z[i];
       }
     }
   }

@@ -157,8 +157,9 @@ __global__ void __launch_bounds__(256) k_grad_c4(const Prob* __restrict__ probs,
     const double* inv = tab + n;
     const double* z = tab + 2 * n;
     const double fac = tab[3 * n];
+    const double* y0c = tab + 3 * n + 2;   // y_0 = sum_k c_k d_k (see the host table)
     const size_t b0 = base + (size_t)g * sd;
-    double fm[5], f0[5], fp[5], dprev[5];
+    double fm[5], f0[5], fp[5], dprev[5], y0[5] = {0, 0, 0, 0, 0};
     f(g - 1, fm);
     f(g, f0);
     for (int i = 0; i < n; ++i) {
@@ -168,23 +169,21 @@ __global__ void __launch_bounds__(256) k_grad_c4(const Prob* __restrict__ probs,
         const double dd = (i == 0 ? rhs : rhs - 0.25 * dprev[q]) * inv[i];
         S[q * T + b0 + (size_t)i * sd] = dd;
         dprev[q] = dd;
+        y0[q] = y0[q] + y0c[i] * dd;
         fm[q] = f0[q];
         f0[q] = fp[q];
       }
     }
-    double y[5], ylast[5];
-    for (int q = 0; q < 5; ++q) y[q] = ylast[q] = dprev[q];
-    for (int i = n - 2; i >= 0; --i)
+    // one back substitution emitting x = y - (y_0 - y_{n-1}/4) fac z
+    double y[5], vy[5];
+    for (int q = 0; q < 5; ++q) {
+      y[q] = dprev[q];
+      vy[q] = (y0[q] - 0.25 * dprev[q]) * fac;
+    }
+    for (int i = n - 1; i >= 0; --i)
       for (int q = 0; q < 5; ++q) {
-        y[q] = S[q * T + b0 + (size_t)i * sd] - cp[i] * y[q];
-        S[q * T + b0 + (size_t)i * sd] = y[q];
-      }
-    double vy[5];
-    for (int q = 0; q < 5; ++q) vy[q] = (y[q] - 0.25 * ylast[q]) * fac;
-    for (int i = 0; i < n; ++i)
-      for (int q = 0; q < 5; ++q) {
-        const double yi = (i == n - 1) ? ylast[q] : S[q * T + b0 + (size_t)i * sd];
-        const R xv = (R)(yi - vy[q] * z[i]);
+        if (i < n - 1) y[q] = S[q * T + b0 + (size_t)i * sd] - cp[i] * y[q];
+        const R xv = (R)(y[q] - vy[q] * z[i]);
         G[q * T + b0 + (size_t)i * sd] = xv;
         if (i >= n - g) G[q * T + b0 + (size_t)(i - n) * sd] = xv;   // low ghosts
         if (i < g) G[q * T + b0 + (size_t)(i + n) * sd] = xv;        // high ghosts

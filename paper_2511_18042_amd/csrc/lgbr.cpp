@@ -213,30 +213,6 @@ std::vector<double> tri_bounded(int N) {
   return t;
 }
 
-std::vector<double> tri_periodic(int n) {
-  // cyclic [1/4, 1, 1/4] = B + u v^T with gamma = -1, u = (gamma, 0.., 1/4), v = (1, 0.., -1/4)
-  std::vector<double> t(3 * n + 1, 0.0);
-  double* cp = t.data();
-  double* inv = t.data() + n;
-  double* z = t.data() + 2 * n;
-  std::vector<double> b(n, 1.0);
-  b[0] = 2.0;
-  b[n - 1] = 1.0 + 0.25 * 0.25;
-  for (int i = 0; i < n; ++i) {
-    double den = b[i] - (i > 0 ? 0.25 * cp[i - 1] : 0.0);
-    inv[i] = 1.0 / den;
-    cp[i] = (i < n - 1 ? 0.25 : 0.0) / den;
-  }
-  std::vector<double> u(n, 0.0), dp(n);
-  u[0] = -1.0;
-  u[n - 1] = 0.25;
-  for (int i = 0; i < n; ++i) dp[i] = (u[i] - (i > 0 ? 0.25 * dp[i - 1] : 0.0)) * inv[i];
-  z[n - 1] = dp[n - 1];
-  for (int i = n - 2; i >= 0; --i) z[i] = dp[i] - cp[i] * z[i + 1];
-  t[3 * n] = 1.0 / (1.0 + z[0] - 0.25 * z[n - 1]);
-  return t;
-}
-
 void append_band_header(std::vector<double>& t, int L, int steps);
 
 // PCR elimination factors of the C4 matrix (see k_grad_c4_pcr): k1[steps][L], k2[steps][L],
@@ -296,8 +272,12 @@ std::vector<double> thomas_table(const std::vector<double>& a, const std::vector
 }
 
 // cyclic [alpha, 1, alpha] of n unknowns: cp[n], inv[n], z[n], fac, alpha (see k_compact.hip)
+// Cyclic factors of the system with unit diagonal and off-diagonals al (n unknowns):
+// cp[n], inv[n], z[n], fac, al, then c[n] with y_0 = sum_k c_k d_k for the forward
+// values d_k (c_0 = 1, c_k = -c_{k-1} cp_{k-1}), so that the one back substitution can
+// emit x = y - (y_0 - al y_{n-1}) fac z directly.
 std::vector<double> cyclic_table(int n, double al) {
-  std::vector<double> t(3 * (size_t)n + 2, 0.0);
+  std::vector<double> t(4 * (size_t)n + 2, 0.0);
   double* cp = t.data();
   double* inv = t.data() + n;
   double* z = t.data() + 2 * n;
@@ -317,6 +297,9 @@ std::vector<double> cyclic_table(int n, double al) {
   for (int i = n - 2; i >= 0; --i) z[i] = dp[i] - cp[i] * z[i + 1];
   t[3 * (size_t)n] = 1.0 / (1.0 + z[0] - al * z[n - 1]);
   t[3 * (size_t)n + 1] = al;
+  double* c = t.data() + 3 * (size_t)n + 2;
+  c[0] = 1.0;
+  for (int k = 1; k < n; ++k) c[k] = -c[k - 1] * cp[k - 1];
   return t;
 }
 
@@ -654,7 +637,7 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
   }
   if (opts->grad == LG_GRAD_C4) {
     for (int d = 0; d < G.ndim; ++d) {
-      std::vector<double> tab = P.bc[d][0] == LG_BC_PERIODIC ? tri_periodic(P.n[d]) : tri_bounded(P.N[d]);
+      std::vector<double> tab = P.bc[d][0] == LG_BC_PERIODIC ? cyclic_table(P.n[d], 0.25) : tri_bounded(P.N[d]);
       double* dt = static_cast<double*>(A(tab.size() * sizeof(double)));
       if (!ok) {
         lg_destroy(c);

@@ -87,8 +87,9 @@ def _opts(alpha=0.49, every=False):
     return orhs.Opts(lad='C6', filter_alpha=alpha, C_mu=0.002, filter_every_stage=every)
 
 
-# line-solve kernels: LDS line tiles everywhere, or the PCR / lane-per-line kernels only
-TILES = {'default': -1, 'tiles': 0xFFF, 'no_tiles': 0}
+# line-solve kernels: LDS line tiles everywhere (also on strided directions whatever their
+# line count: bit 12), or the PCR / lane-per-line kernels only
+TILES = {'default': -1, 'tiles': 0xFFF, 'strided_tiles': 0x1FFF, 'no_tiles': 0}
 
 
 @pytest.mark.parametrize('name', list(CASES))
@@ -101,6 +102,9 @@ def test_lad_c6_rhs_parity_fp64(name, tiles):
     ref = orhs.rhs(c.Q, g, gas, opts, 'lad')
     ctx, _ = U.gpu_context(c, gas, opts)
     ctx.set_line_tiles(TILES[tiles])
+    assert ctx.get_line_tiles() == (TILES[tiles] if TILES[tiles] >= 0 else 0xFFF)
+    with pytest.raises(lgbr.LgError):
+        ctx.set_line_tiles(0x2000)
     assert ctx.get_line_tiles() == (TILES[tiles] if TILES[tiles] >= 0 else 0xFFF)
     out = U.gpu_rhs(ctx, c, 'lad')
     U.compare(out, ref, g, U.RHS_RTOL, label='lad-c6 %s %s' % (name, tiles))
