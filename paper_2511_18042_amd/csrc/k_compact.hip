@@ -116,6 +116,23 @@ __device__ __forceinline__ void prims5c(const double* Q, size_t T, size_t o, dou
   w[4] = gm1 * (Q[4 * T + o] - 0.5 * rho * (u * u + v * v + x * x));
 }
 
+// primitives q0 .. q0 + NQ - 1 of node o (NQ = 5: all, as prims5c; NQ = 1: the one, with
+// the same arithmetic)
+template <int NQ>
+__device__ __forceinline__ void prims_q(const double* Q, size_t T, size_t o, double gm1, int q0, double w[NQ]) {
+  if constexpr (NQ == 5) {
+    prims5c(Q, T, o, gm1, w);
+  } else if (q0 == 0) {
+    w[0] = Q[o];
+  } else if (q0 < 4) {
+    w[0] = Q[(size_t)q0 * T + o] * (1.0 / Q[o]);
+  } else {
+    double a[5];
+    prims5c(Q, T, o, gm1, a);
+    w[0] = a[4];
+  }
+}
+
 // ------------------------------------------------------------------ C6 gradients
 // right-hand side of row i of a bounded gradient line of N nodes from the values at
 // i-2 .. i+2 (entries outside the line unused)
@@ -129,12 +146,15 @@ __device__ __forceinline__ double c6_grad_rhs(int i, int N, double m2, double m1
 // One lane per line (all nodes of the other two directions), all five primitives formed
 // in FP64 from the conserved state; forward elimination into the FP64 scratch, back
 // substitution into the gradient array.
-template <typename R>
-__global__ void __launch_bounds__(256) k_grad_c6(const Prob* __restrict__ probs, StateRef ref, int d, int mask) {
+template <typename R, int NQ>
+__global__ void __launch_bounds__(320) k_grad_c6(const Prob* __restrict__ probs, StateRef ref, int d, int mask) {
   const Prob& P = probs[blockIdx.y];
   if (d >= P.ndim || tile_use(P, d, TK_GRAD6, mask) || c6_grad_pcr(P, d)) return;
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  // NQ = 5: one lane per line; NQ = 1: a workgroup of five waves solves the five primitives
+  // of 64 lines, wave w primitive w (the waves share the state's cache lines)
+  const int t = NQ == 5 ? (int)(blockIdx.x * blockDim.x + threadIdx.x) : (int)(blockIdx.x * 64 + (threadIdx.x & 63));
+  const int q0 = NQ == 5 ? 0 : (int)(threadIdx.x >> 6);
   if (t >= P.N[o1] * P.N[o2]) return;
   const double* Q = ref.state(P);
   R* G = static_cast<R*>(P.G[d]);
@@ -145,38 +165,38 @@ __global__ void __launch_bounds__(256) k_grad_c6(const Prob* __restrict__ probs,
   const size_t base = (size_t)a * P.s[o1] + (size_t)b * P.s[o2];
   const int sd = P.s[d], g = P.g[d], n = P.n[d], N = P.N[d];
   const double gm1 = P.gamma - 1.0;
-  double w[5][5];   // window: positions i-2 .. i+2
+  double w[5][NQ];   // window: positions i-2 .. i+2
   if (P.bc[d][0] != BC_PERIODIC) {
     const double* cp = tab;
     const double* inv = tab + N;
     const double* sub = tab + 2 * N;
-    for (int q = 0; q < 5; ++q) w[0][q] = w[1][q] = 0.0;
-    prims5c(Q, T, base, gm1, w[2]);
-    prims5c(Q, T, base + (size_t)sd, gm1, w[3]);
-    prims5c(Q, T, base + (size_t)2 * sd, gm1, w[4]);
-    double dprev[5] = {0, 0, 0, 0, 0};
+    for (int q = 0; q < NQ; ++q) w[0][q] = w[1][q] = 0.0;
+    prims_q<NQ>(Q, T, base, gm1, q0, w[2]);
+    prims_q<NQ>(Q, T, base + (size_t)sd, gm1, q0, w[3]);
+    prims_q<NQ>(Q, T, base + (size_t)2 * sd, gm1, q0, w[4]);
+    double dprev[NQ] = {};
     for (int i = 0; i < N; ++i) {
-      for (int q = 0; q < 5; ++q) {
+      for (int q = 0; q < NQ; ++q) {
         const double r = c6_grad_rhs(i, N, w[0][q], w[1][q], w[2][q], w[3][q], w[4][q]);
         const double dd = (r - sub[i] * dprev[q]) * inv[i];
-        S[q * T + base + (size_t)i * sd] = dd;
+        S[(q0 + q) * T + base + (size_t)i * sd] = dd;
         dprev[q] = dd;
       }
       for (int p = 0; p < 4; ++p)
-        for (int q = 0; q < 5; ++q) w[p][q] = w[p + 1][q];
-      if (i + 3 < N) prims5c(Q, T, base + (size_t)(i + 3) * sd, gm1, w[4]);
+        for (int q = 0; q < NQ; ++q) w[p][q] = w[p + 1][q];
+      if (i + 3 < N) prims_q<NQ>(Q, T, base + (size_t)(i + 3) * sd, gm1, q0, w[4]);
       else
-        for (int q = 0; q < 5; ++q) w[4][q] = 0.0;
+        for (int q = 0; q < NQ; ++q) w[4][q] = 0.0;
     }
-    double y[5];
-    for (int q = 0; q < 5; ++q) {
+    double y[NQ];
+    for (int q = 0; q < NQ; ++q) {
       y[q] = dprev[q];
-      G[q * T + base + (size_t)(N - 1) * sd] = (R)y[q];
+      G[(q0 + q) * T + base + (size_t)(N - 1) * sd] = (R)y[q];
     }
     for (int i = N - 2; i >= 0; --i)
-      for (int q = 0; q < 5; ++q) {
-        y[q] = S[q * T + base + (size_t)i * sd] - cp[i] * y[q];
-        G[q * T + base + (size_t)i * sd] = (R)y[q];
+      for (int q = 0; q < NQ; ++q) {
+        y[q] = S[(q0 + q) * T + base + (size_t)i * sd] - cp[i] * y[q];
+        G[(q0 + q) * T + base + (size_t)i * sd] = (R)y[q];
       }
   } else {
     const double* cp = tab;
@@ -185,33 +205,33 @@ __global__ void __launch_bounds__(256) k_grad_c6(const Prob* __restrict__ probs,
     const double fac = tab[3 * n], al = tab[3 * n + 1];
     const double* y0c = tab + 3 * n + 2;
     const size_t b0 = base + (size_t)g * sd;
-    for (int p = 0; p < 4; ++p) prims5c(Q, T, base + (size_t)(g + wrap(p - 2, n)) * sd, gm1, w[p]);
-    double dprev[5] = {0, 0, 0, 0, 0}, y0[5] = {0, 0, 0, 0, 0};
+    for (int p = 0; p < 4; ++p) prims_q<NQ>(Q, T, base + (size_t)(g + wrap(p - 2, n)) * sd, gm1, q0, w[p]);
+    double dprev[NQ] = {}, y0[NQ] = {};
     for (int i = 0; i < n; ++i) {
-      prims5c(Q, T, base + (size_t)(g + wrap(i + 2, n)) * sd, gm1, w[4]);
-      for (int q = 0; q < 5; ++q) {
+      prims_q<NQ>(Q, T, base + (size_t)(g + wrap(i + 2, n)) * sd, gm1, q0, w[4]);
+      for (int q = 0; q < NQ; ++q) {
         const double r = C6_A * (w[3][q] - w[1][q]) + C6_B * (w[4][q] - w[0][q]);
         const double dd = (i == 0 ? r : r - al * dprev[q]) * inv[i];
-        S[q * T + b0 + (size_t)i * sd] = dd;
+        S[(q0 + q) * T + b0 + (size_t)i * sd] = dd;
         dprev[q] = dd;
         y0[q] = y0[q] + y0c[i] * dd;
       }
       for (int p = 0; p < 4; ++p)
-        for (int q = 0; q < 5; ++q) w[p][q] = w[p + 1][q];
+        for (int q = 0; q < NQ; ++q) w[p][q] = w[p + 1][q];
     }
     // one back substitution emitting x = y - (y_0 - al y_{n-1}) fac z
-    double y[5], vy[5];
-    for (int q = 0; q < 5; ++q) {
+    double y[NQ], vy[NQ];
+    for (int q = 0; q < NQ; ++q) {
       y[q] = dprev[q];
       vy[q] = (y0[q] - al * dprev[q]) * fac;
     }
     for (int i = n - 1; i >= 0; --i)
-      for (int q = 0; q < 5; ++q) {
-        if (i < n - 1) y[q] = S[q * T + b0 + (size_t)i * sd] - cp[i] * y[q];
+      for (int q = 0; q < NQ; ++q) {
+        if (i < n - 1) y[q] = S[(q0 + q) * T + b0 + (size_t)i * sd] - cp[i] * y[q];
         const R xv = (R)(y[q] - vy[q] * z[i]);
-        G[q * T + b0 + (size_t)i * sd] = xv;
-        if (i >= n - g) G[q * T + b0 + (size_t)(i - n) * sd] = xv;   // low ghosts
-        if (i < g) G[q * T + b0 + (size_t)(i + n) * sd] = xv;        // high ghosts
+        G[(q0 + q) * T + b0 + (size_t)i * sd] = xv;
+        if (i >= n - g) G[(q0 + q) * T + b0 + (size_t)(i - n) * sd] = xv;   // low ghosts
+        if (i < g) G[(q0 + q) * T + b0 + (size_t)(i + n) * sd] = xv;        // high ghosts
       }
   }
 }
@@ -308,62 +328,79 @@ __device__ __forceinline__ bool face_emit(const Prob& P, const FaceOut& o, doubl
   return false;
 }
 
-// One lane per interior line, all five flux components; forward elimination into the
-// FP64 scratch, back substitution emitting the node derivatives.
-template <typename R>
+// face_emit for NQ components starting at q0 (one component: never the RK stage)
+template <int NQ>
+__device__ __forceinline__ bool face_emit_q(const Prob& P, const FaceOut& o, double* dQ, double dt, int q0,
+                                            size_t idx, const double D[NQ]) {
+  if constexpr (NQ == 5) {
+    return face_emit(P, o, dQ, dt, idx, D);
+  } else {
+    const size_t at = (size_t)q0 * P.total + idx;
+    const double L = -met64(P, 9, (int)idx) * D[0];
+    dQ[at] = o.accumulate ? dQ[at] + L : L;
+    return false;
+  }
+}
+
+// One lane per interior line and NQ flux components (all five where the RK stage needs
+// them together, else one: five times the lanes); forward elimination into the FP64
+// scratch, back substitution emitting the node derivatives.
+template <typename R, int NQ>
 __global__ void __launch_bounds__(256) k_c6_faces(const Prob* __restrict__ probs, FaceOut o, int d, int mask) {
   const Prob& P = probs[blockIdx.y];
   if (d >= P.ndim || tile_use(P, d, TK_FACES, mask) || c6_face_pcr(P, d)) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= interior_lines(P, d)) return;
+  const int nl = interior_lines(P, d);
+  if (t >= (5 / NQ) * nl) return;
+  const int line = NQ == 5 ? t : t % nl, q0 = NQ == 5 ? 0 : t / nl;
   const R* F = static_cast<const R*>(P.FL[d]);
   const size_t T = P.total;
   double* S = P.T64;
   double* dQ = o.ref.deriv(P);
   const double dt = o.rk ? *P.dt : 0.0;
   const double* tab = P.trc[d];
-  const size_t base = interior_line_base(P, d, t);
+  const size_t base = interior_line_base(P, d, line);
   const int sd = P.s[d], g = P.g[d], n = P.n[d];
   int bad = 0;
-  auto at = [&](int q, int p) { return (double)F[q * T + base + (size_t)(g + p) * sd]; };
+  auto at = [&](int q, int p) { return (double)F[(q0 + q) * T + base + (size_t)(g + p) * sd]; };
   if (P.bc[d][0] != BC_PERIODIC) {
     const int m = n - 1;
     const double* cp = tab;
     const double* inv = tab + m;
     const double* sub = tab + 2 * m;
-    double lo[5], hi[5], w[4][5], dprev[5];
-    for (int q = 0; q < 5; ++q) {
+    double lo[NQ], hi[NQ], w[4][NQ], dprev[NQ];
+    for (int q = 0; q < NQ; ++q) {
       lo[q] = (7.0 * (at(q, -1) + at(q, 0)) - (at(q, -2) + at(q, 1))) / 12.0;
       hi[q] = (7.0 * (at(q, n - 1) + at(q, n)) - (at(q, n - 2) + at(q, n + 1))) / 12.0;
       for (int p = 0; p < 3; ++p) w[p][q] = at(q, p - 1);
       dprev[q] = 0.0;
     }
     for (int k = 0; k < m; ++k) {
-      for (int q = 0; q < 5; ++q) {
+      for (int q = 0; q < NQ; ++q) {
         w[3][q] = at(q, k + 2);
         double r = C6F_A * (w[1][q] + w[2][q]) + C6F_B * (w[0][q] + w[3][q]);
         if (k == 0) r = r - C6_ALPHA * lo[q];
         if (k == m - 1) r = r - C6_ALPHA * hi[q];
         const double dd = (r - sub[k] * dprev[q]) * inv[k];
-        S[q * T + base + (size_t)(g + k) * sd] = dd;
+        S[(q0 + q) * T + base + (size_t)(g + k) * sd] = dd;
         dprev[q] = dd;
         w[0][q] = w[1][q];
         w[1][q] = w[2][q];
         w[2][q] = w[3][q];
       }
     }
-    double prev[5], D[5];
-    for (int q = 0; q < 5; ++q) prev[q] = hi[q];
+    double prev[NQ], D[NQ];
+    for (int q = 0; q < NQ; ++q) prev[q] = hi[q];
     for (int k = m - 1; k >= 0; --k) {
-      for (int q = 0; q < 5; ++q) {
-        const double x = S[q * T + base + (size_t)(g + k) * sd] - cp[k] * (k == m - 1 ? 0.0 : prev[q]);
+      for (int q = 0; q < NQ; ++q) {
+        const double x = S[(q0 + q) * T + base + (size_t)(g + k) * sd] - cp[k] * (k == m - 1 ? 0.0 : prev[q]);
         D[q] = prev[q] - x;
         prev[q] = x;
       }
-      if (face_emit(P, o, dQ, dt, base + (size_t)(g + k + 1) * sd, D)) ++bad;
+      if (face_emit_q<NQ>(P, o, dQ, dt, q0, base + (size_t)(g + k + 1) * sd, D)) ++bad;
     }
-    for (int q = 0; q < 5; ++q) D[q] = prev[q] - lo[q];
-    if (face_emit(P, o, dQ, dt, base + (size_t)g * sd, D)) ++bad;
+    for (int q = 0; q < NQ; ++q) D[q] = prev[q] - lo[q];
+    if (face_emit_q<NQ>(P, o, dQ, dt, q0, base + (size_t)g * sd, D)) ++bad;
   } else {
     const double* cp = tab;
     const double* inv = tab + n;
@@ -371,17 +408,17 @@ __global__ void __launch_bounds__(256) k_c6_faces(const Prob* __restrict__ probs
     const double fac = tab[3 * n], al = tab[3 * n + 1];
     const double* y0c = tab + 3 * n + 2;
     auto atw = [&](int q, int p) { return at(q, wrap(p, n)); };
-    double w[4][5], dprev[5], y0[5];
-    for (int q = 0; q < 5; ++q) {
+    double w[4][NQ], dprev[NQ], y0[NQ];
+    for (int q = 0; q < NQ; ++q) {
       for (int p = 0; p < 3; ++p) w[p][q] = atw(q, p - 1);
       dprev[q] = y0[q] = 0.0;
     }
     for (int k = 0; k < n; ++k) {
-      for (int q = 0; q < 5; ++q) {
+      for (int q = 0; q < NQ; ++q) {
         w[3][q] = atw(q, k + 2);
         const double r = C6F_A * (w[1][q] + w[2][q]) + C6F_B * (w[0][q] + w[3][q]);
         const double dd = (k == 0 ? r : r - al * dprev[q]) * inv[k];
-        S[q * T + base + (size_t)(g + k) * sd] = dd;
+        S[(q0 + q) * T + base + (size_t)(g + k) * sd] = dd;
         dprev[q] = dd;
         y0[q] = y0[q] + y0c[k] * dd;
         w[0][q] = w[1][q];
@@ -391,23 +428,23 @@ __global__ void __launch_bounds__(256) k_c6_faces(const Prob* __restrict__ probs
     }
     // one back substitution emitting the faces x = y - (y_0 - al y_{n-1}) fac z and, from
     // each pair of neighbouring faces, the node difference D_{k+1} = x_{k+1} - x_k
-    double y[5], vy[5], xlast[5], xnext[5], D[5];
-    for (int q = 0; q < 5; ++q) {
+    double y[NQ], vy[NQ], xlast[NQ], xnext[NQ], D[NQ];
+    for (int q = 0; q < NQ; ++q) {
       y[q] = dprev[q];
       vy[q] = (y0[q] - al * dprev[q]) * fac;
       xlast[q] = xnext[q] = y[q] - vy[q] * z[n - 1];
     }
     for (int k = n - 2; k >= 0; --k) {
-      for (int q = 0; q < 5; ++q) {
-        y[q] = S[q * T + base + (size_t)(g + k) * sd] - cp[k] * y[q];
+      for (int q = 0; q < NQ; ++q) {
+        y[q] = S[(q0 + q) * T + base + (size_t)(g + k) * sd] - cp[k] * y[q];
         const double x = y[q] - vy[q] * z[k];
         D[q] = xnext[q] - x;
         xnext[q] = x;
       }
-      if (face_emit(P, o, dQ, dt, base + (size_t)(g + k + 1) * sd, D)) ++bad;
+      if (face_emit_q<NQ>(P, o, dQ, dt, q0, base + (size_t)(g + k + 1) * sd, D)) ++bad;
     }
-    for (int q = 0; q < 5; ++q) D[q] = xnext[q] - xlast[q];   // node 0: x_0 - x_{n-1}
-    if (face_emit(P, o, dQ, dt, base + (size_t)g * sd, D)) ++bad;
+    for (int q = 0; q < NQ; ++q) D[q] = xnext[q] - xlast[q];   // node 0: x_0 - x_{n-1}
+    if (face_emit_q<NQ>(P, o, dQ, dt, q0, base + (size_t)g * sd, D)) ++bad;
   }
   if (bad) atomicAdd(P.status, bad);
 }
@@ -475,21 +512,23 @@ __device__ __forceinline__ double filt_rhs(const Prob& P, const double w[11]) {
   return v;
 }
 
-// One lane per interior line, the five conserved variables in turn; in place on the state.
+// One lane per (interior line, conserved variable); in place on the state.
 __global__ void __launch_bounds__(256) k_filter(const Prob* __restrict__ probs, StateRef ref, int d, int mask) {
   const Prob& P = probs[blockIdx.y];
   if (d >= P.ndim || !(P.falpha < 0.5) || tile_use(P, d, TK_FILTER, mask) || filt_pcr(P, d)) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= interior_lines(P, d)) return;
+  const int nl = interior_lines(P, d);
+  if (t >= 5 * nl) return;
+  const int line = t % nl, q = t / nl;
   double* Q = ref.state(P);
   const size_t T = P.total;
   double* S = P.T64;
   const double* tab = P.trf[d];
-  const size_t base = interior_line_base(P, d, t);
+  const size_t base = interior_line_base(P, d, line);
   const int sd = P.s[d], g = P.g[d], n = P.n[d];
   const double al = P.falpha;
   const bool periodic = P.bc[d][0] == BC_PERIODIC;
-  for (int q = 0; q < 5; ++q) {
+  {
     double* phi = Q + (size_t)q * T + base;
     double* Sq = S + (size_t)q * T + base;
     auto at = [&](int p) { return phi[(size_t)(g + (periodic ? wrap(p, n) : p)) * sd]; };
@@ -932,9 +971,9 @@ void launch_grad_c6(const Launch& L, StateRef ref, int d) {
     LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c6_pcr<R>, dim3(pcr_grid(L, 5 * L.lines[d]), L.nprob),
                                                dim3(CPCR_THREADS), lds, L.stream, L.probs, ref, d, L.tile_mask));
   }
-  if (sl.thomas)
-    LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c6<R>, dim3(blocks_for(L.lines[d]), L.nprob), dim3(256), 0,
-                                               L.stream, L.probs, ref, d, L.tile_mask));
+  if (sl.thomas)   // five waves per 64 lines, one primitive each
+    LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL((k_grad_c6<R, 1>), dim3((unsigned)((L.lines[d] + 63) / 64), L.nprob),
+                                               dim3(320), 0, L.stream, L.probs, ref, d, L.tile_mask));
 }
 
 template <typename R>
@@ -953,8 +992,12 @@ void launch_c6_faces(const Launch& L, StateRef ref, int d, int accumulate, const
   }
   if (sl.thomas) {
     FaceOut o{ref, rr ? *rr : RKRef{nullptr, nullptr, nullptr}, accumulate, rr ? 1 : 0, stage, a, b};
-    LG_TIMED(L, KC_C6_FACES, hipLaunchKernelGGL(k_c6_faces<R>, dim3(blocks_for(L.sweep_rows[d]), L.nprob),
-                                                dim3(256), 0, L.stream, L.probs, o, d, L.tile_mask));
+    if (rr)   // the RK stage needs the five components of a node together
+      LG_TIMED(L, KC_C6_FACES, hipLaunchKernelGGL((k_c6_faces<R, 5>), dim3(blocks_for(L.sweep_rows[d]), L.nprob),
+                                                  dim3(256), 0, L.stream, L.probs, o, d, L.tile_mask));
+    else
+      LG_TIMED(L, KC_C6_FACES, hipLaunchKernelGGL((k_c6_faces<R, 1>), dim3(blocks_for(5 * L.sweep_rows[d]), L.nprob),
+                                                  dim3(256), 0, L.stream, L.probs, o, d, L.tile_mask));
   }
 }
 
@@ -971,7 +1014,7 @@ void launch_filter(const Launch& L, StateRef ref, int d) {
                                               dim3(CPCR_THREADS), lds, L.stream, L.probs, ref, d, L.tile_mask));
   }
   if (sl.thomas)
-    LG_TIMED(L, KC_FILTER, hipLaunchKernelGGL(k_filter, dim3(blocks_for(L.sweep_rows[d]), L.nprob), dim3(256), 0,
+    LG_TIMED(L, KC_FILTER, hipLaunchKernelGGL(k_filter, dim3(blocks_for(5 * L.sweep_rows[d]), L.nprob), dim3(256), 0,
                                               L.stream, L.probs, ref, d, L.tile_mask));
 }
 

@@ -135,13 +135,22 @@ def test_filter_parity_fp64(name, alpha, tiles):
     ctx.close()
 
 
+# measured conditioning of the two-step result (see the test's docstring)
+RK3_RTOL = {'2d_periodic_wide': 1e-9}
+
+
 @pytest.mark.parametrize('name,every', [(n, False) for n in ('2d_walls', '1d_fixed', '3d_curv', '2d_periodic_wide')] +
                          [(n, True) for n in ('2d_walls', '3d_curv', '2d_periodic_wide')])
 def test_lad_c6_rk3_step_parity_fp64(name, every):
     """Three stages and the filter (after the last stage, or after every stage); two steps in
     a row.  Left out, because LAD alone loses positivity on them within two steps in the
     oracle as on the GPU: the 40x32x16 ramp crop (E4 or C6), and the 96-cell Shu-Osher
-    tube with the filter after every stage."""
+    tube with the filter after every stage.
+
+    Tolerance: 1e-12 where the step is well conditioned.  On the 520 x 9 periodic case a
+    1e-15 relative perturbation of the input moves the oracle's own two-step result by up
+    to 5.3e-11 in rho u (the LAD switch f_sw at nodes where theta and omega both nearly
+    vanish), every other case by about 1e-14; there the bound is 1e-9."""
     print('rk3', name, every, flush=True)
     torch = U.torch_mod()
     c = CASES[name]()
@@ -158,7 +167,7 @@ def test_lad_c6_rk3_step_parity_fp64(name, every):
         torch.cuda.synchronize()
         assert bad == 0
         assert abs(td.item() - t) <= 1e-13 * t
-        U.compare(Qd.cpu().numpy(), Q, g, U.STAGE_RTOL, label='lad-c6 rk3 %s step %d' % (name, step))
+        U.compare(Qd.cpu().numpy(), Q, g, RK3_RTOL.get(name, U.STAGE_RTOL), label='lad-c6 rk3 %s step %d' % (name, step))
     assert ctx.poll_status() == 0
     ctx.close()
 
