@@ -632,6 +632,16 @@ __global__ void __launch_bounds__(CPCR_THREADS) __attribute__((amdgpu_waves_per_
 //              RK stage in the last direction)
 //   TK_FILTER  implicit filter: the state in, its interior filtered in place
 //   TK_GRAD4   C4 gradients (MIG4 of C-GBR): as TK_GRAD6 with the C4 rows and tables
+// Division by a per-workgroup constant d >= 1 for dividends e with e * d < 2^32 (tile
+// indices: both below 6144): q = hi32(e * ceil(2^32 / d)) is exact there (d = 1 apart,
+// whose multiplier does not fit 32 bits).
+struct SmallDiv {
+  unsigned m;
+  int d;
+  __device__ explicit SmallDiv(int dv) : m(dv > 1 ? 0xFFFFFFFFu / (unsigned)dv + 1u : 0u), d(dv) {}
+  __device__ __forceinline__ int div(int e) const { return d > 1 ? (int)__umulhi((unsigned)e, m) : e; }
+};
+
 struct TileArgs {
   StateRef ref;
   RKRef rr;
@@ -678,6 +688,7 @@ k_line_tiles(const Prob* __restrict__ probs, TileArgs A) {
   if (5 * TX * Lin > TILE_ELEMS || TX > TILE_MAX_TX) return;   // the host sizes TX so that this never holds
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   const int ta = (la + TX - 1) / TX;
+  const SmallDiv dLin(Lin), dTX(TX), dU(U), dn(P.n[d]);
   const int ntiles = ta * lb;
   const int per = (ntiles + 7) >> 3;
   if ((int)(blockIdx.x >> 3) >= per) return;
@@ -693,14 +704,12 @@ k_line_tiles(const Prob* __restrict__ probs, TileArgs A) {
   const int ncp = TX * Lin;   // (column, position) pairs
   // element e of a (column, position) sweep: positions fastest on contiguous lines,
   // columns fastest on strided ones (coalesced either way)
-  auto cp_of = [&](int e, int& c, int& p) {
-    if (d == 0) {
-      p = e % Lin;
-      c = e / Lin;
-    } else {
-      c = e % TX;
-      p = e / TX;
-    }
+  auto cp_of = [d, dLin, dTX](int e, int& c, int& p) {
+    // both quotients, then a choice of values (a choice of destinations keeps c and p in
+    // memory)
+    const int qa = dLin.div(e), qb = dTX.div(e);
+    c = d == 0 ? qa : e - qb * dTX.d;
+    p = d == 0 ? e - qa * dLin.d : qb;
   };
   // ---- load
   for (int e = tid; e < ncp; e += NT) {
@@ -730,7 +739,9 @@ k_line_tiles(const Prob* __restrict__ probs, TileArgs A) {
     const int e = tid + m * NT;
     nv[m] = 0.0;
     if (e < nel) {
-      const int line = e / Lin, k = e % Lin;
+      int line, k;
+      line = dLin.div(e);
+      k = e - line * dLin.d;
       const double* f = buf + line * Lin;
       if (k < U) {
         double r;
@@ -800,7 +811,7 @@ k_line_tiles(const Prob* __restrict__ probs, TileArgs A) {
 #pragma unroll
   for (int m = 0; m < PT; ++m) {
     const int e = tid + m * NT;
-    const int k = e % Lin;
+    const int k = e - dLin.div(e) * Lin;
     erow[m] = (e < nel && k < U) ? k : -1;
   }
   for (int st = 0; st < steps; ++st) {
@@ -856,13 +867,9 @@ k_line_tiles(const Prob* __restrict__ probs, TileArgs A) {
     const int pos0 = periodic ? g : 0;   // position of unknown 0
     for (int e = tid; e < TX * U; e += NT) {
       int c, k;
-      if (d == 0) {
-        k = e % U;
-        c = e / U;
-      } else {
-        c = e % TX;
-        k = e / TX;
-      }
+      const int qa = dU.div(e), qb = dTX.div(e);
+      c = d == 0 ? qa : e - qb * dTX.d;
+      k = d == 0 ? e - qa * dU.d : qb;
       if (c >= ncol) continue;
       const size_t col = lbase + (size_t)c * P.s[o1];
       for (int q = 0; q < 5; ++q) {
@@ -881,13 +888,9 @@ k_line_tiles(const Prob* __restrict__ probs, TileArgs A) {
     int bad = 0;
     for (int e = tid; e < TX * n; e += NT) {
       int c, i;
-      if (d == 0) {
-        i = e % n;
-        c = e / n;
-      } else {
-        c = e % TX;
-        i = e / TX;
-      }
+      const int qa = dn.div(e), qb = dTX.div(e);
+      c = d == 0 ? qa : e - qb * dTX.d;
+      i = d == 0 ? e - qa * dn.d : qb;
       if (c >= ncol) continue;
       double D[5];
       for (int q = 0; q < 5; ++q) {
@@ -910,13 +913,9 @@ k_line_tiles(const Prob* __restrict__ probs, TileArgs A) {
     double* Q = A.ref.state(P);
     for (int e = tid; e < TX * n; e += NT) {
       int c, k;
-      if (d == 0) {
-        k = e % n;
-        c = e / n;
-      } else {
-        c = e % TX;
-        k = e / TX;
-      }
+      const int qa = dn.div(e), qb = dTX.div(e);
+      c = d == 0 ? qa : e - qb * dTX.d;
+      k = d == 0 ? e - qa * dn.d : qb;
       if (c >= ncol) continue;
       const size_t node = lbase + (size_t)c * P.s[o1] + (size_t)(g + k) * sd;
       for (int q = 0; q < 5; ++q) Q[q * T + node] = buf[(q * TX + c) * Lin + k];
