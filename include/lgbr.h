@@ -64,7 +64,10 @@ enum {
   LG_BC_TRANSMISSIVE = 1,      /* zeroth-order extrapolation ("extrapolated outflow")  */
   LG_BC_REFLECTIVE = 2,        /* mirror, normal momentum negated (inviscid wall)      */
   LG_BC_NOSLIP_ADIABATIC = 3,  /* mirror, all momentum negated (no-slip adiabatic wall)*/
-  LG_BC_FIXED = 4              /* ghosts owned by the caller (inflow at the IC state)  */
+  LG_BC_FIXED = 4,             /* ghosts owned by the caller (inflow at the IC state)  */
+  LG_BC_NOSLIP_ISOTHERMAL = 5  /* no-slip wall held at wall_T (Sec. 4, M2.9 ramp): mirror
+                                  with velocity negated, pressure even, temperature odd
+                                  about wall_T, density from the equation of state     */
 };
 enum { LG_GRAD_E6 = 0, LG_GRAD_C4 = 1 };          /* MEG6 / MIG4 gradients (Sec. 2.3)   */
 enum { LG_FP64 = 0, LG_MIXED = 1 };               /* FP64 everywhere / FP32 bulk math   */
@@ -79,6 +82,8 @@ typedef struct {
   int bc[3][2];        /* LG_BC_* for the low / high side of every active direction   */
   int curvilinear;     /* 0: Cartesian, spacings h; 1: node metrics + coordinates    */
   double h[3];         /* Cartesian node spacings (unused when curvilinear)          */
+  double wall_T[3][2]; /* wall temperature (T_ref = 1) of LG_BC_NOSLIP_ISOTHERMAL
+                          faces, > 0; ignored on other faces                        */
 } lg_grid;
 
 typedef struct {       /* non-dimensional gas model (Sec. 2.1)                        */

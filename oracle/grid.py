@@ -24,7 +24,7 @@ axis ``ndim_of_array - 1 - d``.  Inactive directions have one node and no ghosts
 import numpy as np
 
 NG = 5
-BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE, BC_NOSLIP, BC_FIXED = 0, 1, 2, 3, 4
+BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE, BC_NOSLIP, BC_FIXED, BC_NOSLIP_T = 0, 1, 2, 3, 4, 5
 
 
 class Grid:
@@ -35,9 +35,11 @@ class Grid:
     h      : Cartesian spacings (hx, hy, hz) when ``coords`` is None.
     coords : (3, Nz, Ny, Nx) node coordinates including ghost nodes, for a
              curvilinear grid (None for Cartesian).
+    wall_T : wall_T[d][side], the wall temperature (T_ref = 1) of a no-slip isothermal
+             face (BC_NOSLIP_T); unused elsewhere.
     """
 
-    def __init__(self, ndim, n, bc, h=(1.0, 1.0, 1.0), coords=None):
+    def __init__(self, ndim, n, bc, h=(1.0, 1.0, 1.0), coords=None, wall_T=None):
         n = tuple(int(v) for v in n) + (1,) * (3 - len(n))
         assert 1 <= ndim <= 3
         for d in range(ndim, 3):
@@ -50,6 +52,8 @@ class Grid:
         self.bc = bc[:3]
         self.h = tuple(float(v) for v in h) + (1.0,) * (3 - len(h))
         self.coords = coords
+        wt = [tuple(float(v) for v in w) for w in (wall_T or [])]
+        self.wall_T = (wt + [(0.0, 0.0)] * 3)[:3]
 
     @property
     def shape(self):
@@ -115,7 +119,7 @@ def _ghost_pairs(grid, d, side):
             pairs.append((dst, src, False))
         elif t == BC_TRANSMISSIVE:
             pairs.append((dst, g if side == 0 else g + n - 1, False))
-        elif t in (BC_REFLECTIVE, BC_NOSLIP):
+        elif t in (BC_REFLECTIVE, BC_NOSLIP, BC_NOSLIP_T):
             pairs.append((dst, g + m if side == 0 else g + n - 1 - m, True))
         elif t == BC_FIXED:
             pass
@@ -124,19 +128,46 @@ def _ghost_pairs(grid, d, side):
     return pairs
 
 
-def fill_ghosts_conserved(Q, grid):
+def _isothermal_image(Qs, T_w, gas):
+    """Ghost state mirroring the conserved state Qs across a no-slip wall held at T_w
+    (R32): velocity odd (zero at the wall), pressure even (no normal gradient),
+    temperature odd about T_w (the pair's mean is T_w), density from p = rho T /
+    (gamma Mref^2)."""
+    gamma = gas.gamma
+    gM2 = gamma * gas.Mref ** 2
+    rho = Qs[0]
+    u = Qs[1:4] / rho
+    ke = 0.5 * rho * (u ** 2).sum(axis=0)
+    p = (gamma - 1.0) * (Qs[4] - ke)
+    T_g = 2.0 * T_w - gM2 * p / rho
+    rho_g = gM2 * p / T_g
+    out = np.empty_like(Qs)
+    out[0] = rho_g
+    out[1:4] = -rho_g * u
+    out[4] = p / (gamma - 1.0) + 0.5 * rho_g * (u ** 2).sum(axis=0)
+    return out
+
+
+def fill_ghosts_conserved(Q, grid, gas=None):
     """Fill the ghost layers of the conserved state Q (5, Nz, Ny, Nx) in place (R13).
 
     Reflective walls negate the momentum component normal to the wall (the
     Cartesian component of the sweep direction; walls are grid lines aligned
     with that axis).  No-slip adiabatic walls negate all momentum, so the wall
     velocity is zero while density and energy (hence temperature) are even.
+    No-slip isothermal walls (R32) need the gas (gamma, Mref) for the equation of
+    state.
     """
     for d in range(grid.ndim):
         ax = axis_of(Q, d)
         for side in (0, 1):
             t = grid.bc[d][side]
+            if t == BC_NOSLIP_T and gas is None:
+                raise ValueError('an isothermal wall needs the gas model')
             for dst, src, mirrored in _ghost_pairs(grid, d, side):
+                if t == BC_NOSLIP_T:
+                    Q[_take(Q, ax, dst)] = _isothermal_image(Q[_take(Q, ax, src)], grid.wall_T[d][side], gas)
+                    continue
                 Q[_take(Q, ax, dst)] = Q[_take(Q, ax, src)]
                 if mirrored:
                     comps = [1 + d] if t == BC_REFLECTIVE else [1, 2, 3]

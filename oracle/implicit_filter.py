@@ -117,13 +117,13 @@ def filter_direction(Q, d, grid, alpha, coef):
     return np.moveaxis(out.reshape(Qm.shape), 0, ax)
 
 
-def filter_state(Q, grid, alpha=FILTER_ALPHA, order=FILTER_ORDER):
+def filter_state(Q, grid, alpha=FILTER_ALPHA, order=FILTER_ORDER, gas=None):
     """FILTER_CALLS of Alg. 1 on the conserved state (R29); returns the filtered copy with
-    its ghost layers refilled."""
+    its ghost layers refilled (isothermal walls need the gas model)."""
     coef = gv_coefficients(alpha, order)
     Q = Q.copy()
     for d in range(grid.ndim):
-        gr.fill_ghosts_conserved(Q, grid)
+        gr.fill_ghosts_conserved(Q, grid, gas)
         Q = filter_direction(Q, d, grid, alpha, coef)
-    gr.fill_ghosts_conserved(Q, grid)
+    gr.fill_ghosts_conserved(Q, grid, gas)
     return Q

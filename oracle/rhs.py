@@ -115,7 +115,7 @@ def rhs(Q, grid, gas, opts, scheme, M=None, info=None, force_flags=None):
     margin per node (for excusing threshold flips)."""
     gamma = gas.gamma
     Q = Q.copy()
-    gr.fill_ghosts_conserved(Q, grid)
+    gr.fill_ghosts_conserved(Q, grid, gas)
     W = primitives(Q, gamma)
     if M is None:
         M = gr.node_metrics(grid)
@@ -219,7 +219,7 @@ def rk3_step(Q, t, t_end, grid, gas, opts, scheme, M=None):
     for s in range(3):
         U = rk3_stage(Q, U, dt, s, grid, gas, opts, scheme, M)
         if (s == 2 or opts.filter_every_stage) and uses_filter(opts, scheme):
-            U = filter_state(U, grid, opts.filter_alpha)
+            U = filter_state(U, grid, opts.filter_alpha, gas=gas)
         bad += nonphysical_count(U, grid, gas.gamma)
     return U, t + dt, dt, bad
 

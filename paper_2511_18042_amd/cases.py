@@ -26,7 +26,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 NG = 5
-PERIODIC, TRANSMISSIVE, REFLECTIVE, NOSLIP, FIXED = 0, 1, 2, 3, 4
+PERIODIC, TRANSMISSIVE, REFLECTIVE, NOSLIP, FIXED, NOSLIP_ISOTHERMAL = 0, 1, 2, 3, 4, 5
 
 
 @dataclass
@@ -41,6 +41,7 @@ class Case:
     t_end: float = 0.0
     x0: tuple = (0.0, 0.0, 0.0)
     extra: dict = field(default_factory=dict)
+    wall_T: object = None         # [(lo, hi)] * 3: temperatures of NOSLIP_ISOTHERMAL faces
 
     @property
     def g(self):

@@ -12,7 +12,9 @@ namespace lg {
 // ------------------------------------------------------------------ ghost images
 // Ghost layers of direction d: periodic images, zeroth-order copies, or mirrors
 // (normal momentum negated at reflective walls, all momentum at no-slip adiabatic
-// walls); FIXED ghosts belong to the caller.  Ghost layers are filled over the full
+// walls; at no-slip isothermal walls velocity odd, pressure even and temperature odd
+// about the wall temperature, density from the equation of state); FIXED ghosts belong
+// to the caller.  Ghost layers are filled over the full
 // extent of the other two directions, direction by direction, so corners are set.
 __device__ __forceinline__ bool ghost_src(int bct, int side, int m, int g, int n, int& dst, int& src) {
   if (bct == BC_FIXED) return false;
@@ -41,11 +43,26 @@ __global__ void __launch_bounds__(256) k_bc_cons(const Prob* __restrict__ probs,
     if (!ghost_src(bct, side, m, g, n, dst, src)) continue;
     int base = a * P.s[o1] + b * P.s[o2];
     size_t id = base + dst * P.s[d], is = base + src * P.s[d];
+    const size_t T = P.total;
+    if (bct == BC_NOSLIP_T) {
+      const double rs = Q[is], u = Q[T + is] / rs, v = Q[2 * T + is] / rs, w = Q[3 * T + is] / rs;
+      const double u2 = u * u + v * v + w * w;
+      const double ps = (P.gamma - 1.0) * (Q[4 * T + is] - 0.5 * rs * u2);
+      const double gM2 = P.gamma * P.Mref * P.Mref;
+      const double Tg = 2.0 * P.wall_T[d][side] - gM2 * ps / rs;
+      const double rg = gM2 * ps / Tg;
+      Q[id] = rg;
+      Q[T + id] = -rg * u;
+      Q[2 * T + id] = -rg * v;
+      Q[3 * T + id] = -rg * w;
+      Q[4 * T + id] = ps / (P.gamma - 1.0) + 0.5 * rg * u2;
+      continue;
+    }
     for (int q = 0; q < 5; ++q) {
-      double v = Q[q * (size_t)P.total + is];
+      double v = Q[q * T + is];
       if (bct == BC_REFLECTIVE && q == 1 + d) v = -v;
       if (bct == BC_NOSLIP && q >= 1 && q <= 3) v = -v;
-      Q[q * (size_t)P.total + id] = v;
+      Q[q * T + id] = v;
     }
   }
 }

@@ -194,7 +194,7 @@ void enqueue_rk3(const Launch& L, const Cfg& c, int scheme, double* Qx, double* 
 
 lg_status last_hip() { return hipGetLastError() == hipSuccess ? LG_OK : LG_EHIP; }
 
-bool valid_bc(int b) { return b >= LG_BC_PERIODIC && b <= LG_BC_FIXED; }
+bool valid_bc(int b) { return b >= LG_BC_PERIODIC && b <= LG_BC_NOSLIP_ISOTHERMAL; }
 
 // LU tables of the compact-gradient systems (see k_grad.hip for the layout)
 std::vector<double> tri_bounded(int N) {
@@ -469,6 +469,9 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
       if (G.n[d] < 5) return LG_EINVAL;
       if (!valid_bc(G.bc[d][0]) || !valid_bc(G.bc[d][1])) return LG_EINVAL;
       if ((G.bc[d][0] == LG_BC_PERIODIC) != (G.bc[d][1] == LG_BC_PERIODIC)) return LG_EINVAL;
+      for (int sd = 0; sd < 2; ++sd)
+        if (G.bc[d][sd] == LG_BC_NOSLIP_ISOTHERMAL && !(G.wall_T[d][sd] > 0.0 && std::isfinite(G.wall_T[d][sd])))
+          return LG_EINVAL;
       if (!G.curvilinear && !(G.h[d] > 0.0)) return LG_EINVAL;
     } else if (G.n[d] != 1) {
       return LG_EINVAL;
@@ -499,6 +502,8 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
     P.N[d] = P.n[d] + 2 * P.g[d];
     P.bc[d][0] = d < G.ndim ? G.bc[d][0] : LG_BC_TRANSMISSIVE;
     P.bc[d][1] = d < G.ndim ? G.bc[d][1] : LG_BC_TRANSMISSIVE;
+    P.wall_T[d][0] = G.wall_T[d][0];
+    P.wall_T[d][1] = G.wall_T[d][1];
     P.h[d] = G.h[d];
   }
   P.s[0] = 1;

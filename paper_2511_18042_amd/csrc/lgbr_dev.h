@@ -13,7 +13,7 @@
 
 namespace lg {
 
-enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2, BC_NOSLIP = 3, BC_FIXED = 4 };
+enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2, BC_NOSLIP = 3, BC_FIXED = 4, BC_NOSLIP_T = 5 };
 // Interface flux selection of one sweep.
 enum { SEL_GBR = 0, SEL_LAD = 1, SEL_PERCELL = 2, SEL_GLOBAL = 3 };
 
@@ -30,6 +30,7 @@ struct Prob {
   int curvilinear;
   double h[3];
   double cm[10];     // Cartesian metrics (xi_x .. zeta_z)/J and J
+  double wall_T[3][2];   // wall temperature of isothermal no-slip faces (BC_NOSLIP_T)
   // gas (Sec. 2.1)
   double gamma, Re, Pr, Mref, suth;
   int viscous;

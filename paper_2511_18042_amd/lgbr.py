@@ -11,7 +11,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, 'liblgbr.so')
 
 LG_OK, LG_EINVAL, LG_ENOMEM, LG_EHIP, LG_ENONPHYS, LG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE, BC_NOSLIP_ADIABATIC, BC_FIXED = 0, 1, 2, 3, 4
+BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE, BC_NOSLIP_ADIABATIC, BC_FIXED, BC_NOSLIP_ISOTHERMAL = 0, 1, 2, 3, 4, 5
 GRAD_E6, GRAD_C4 = 0, 1
 FP64, MIXED = 0, 1
 HYB_PERCELL, HYB_GLOBAL = 0, 1
@@ -31,7 +31,8 @@ LAD_E4, LAD_C6 = 0, 1
 
 class LgGrid(ctypes.Structure):
     _fields_ = [('ndim', ctypes.c_int), ('n', ctypes.c_int * 3), ('ng', ctypes.c_int),
-                ('bc', (ctypes.c_int * 2) * 3), ('curvilinear', ctypes.c_int), ('h', ctypes.c_double * 3)]
+                ('bc', (ctypes.c_int * 2) * 3), ('curvilinear', ctypes.c_int), ('h', ctypes.c_double * 3),
+                ('wall_T', (ctypes.c_double * 2) * 3)]
 
 
 class LgGas(ctypes.Structure):
@@ -118,8 +119,11 @@ def _stream(stream):
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def make_grid(ndim, n, bc, h=(1.0, 1.0, 1.0), curvilinear=False):
+def make_grid(ndim, n, bc, h=(1.0, 1.0, 1.0), curvilinear=False, wall_T=None):
+    """wall_T[d] = (lo, hi): wall temperatures of BC_NOSLIP_ISOTHERMAL faces."""
     g = LgGrid()
+    for d, w in enumerate(wall_T or []):
+        g.wall_T[d][0], g.wall_T[d][1] = float(w[0]), float(w[1])
     g.ndim = ndim
     n = tuple(n) + (1,) * (3 - len(n))
     for d in range(3):

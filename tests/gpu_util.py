@@ -36,14 +36,14 @@ def dev(a, dtype=None):
 
 
 def oracle_grid(c):
-    return ogrid.Grid(c.ndim, c.n, c.bc, c.h, c.coords)
+    return ogrid.Grid(c.ndim, c.n, c.bc, c.h, c.coords, wall_T=c.wall_T)
 
 
 def gpu_context(c, gas, opts, precision='fp64', stream=None):
     """Context for case c; curvilinear metrics are computed on the GPU from the coordinates."""
     torch = torch_mod()
     curv = c.coords is not None
-    g = lgbr.make_grid(c.ndim, c.n, c.bc, c.h, curvilinear=curv)
+    g = lgbr.make_grid(c.ndim, c.n, c.bc, c.h, curvilinear=curv, wall_T=c.wall_T)
     metrics = coords = None
     if curv:
         coords = dev(c.coords)
