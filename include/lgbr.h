@@ -238,6 +238,13 @@ int lg_get_line_tiles(const lg_ctx* ctx);
 /* Synchronises the context's stream and reads its non-physical node count since the
  * last poll (then resets it).  Returns LG_ENONPHYS when the count is non-zero. */
 lg_status lg_poll_status(lg_ctx* ctx, int* nonphys_count);
+/* Switching record of the hybrid (Sec. 5: the share of the run spent on each scheme):
+ * every hybrid stage of the context (hybrid_rhs, rk3_step, lg_rk3_stage, batches) counts
+ * one, and one more in *troubled_stages when a node was troubled at its start (global
+ * switch: the stage ran on C-GBR; per-cell switch: some interfaces did).  Synchronises
+ * the context's stream; reset != 0 zeroes both counters after reading.  Counters wrap
+ * after 2^32 stages. */
+lg_status lg_switch_stats(lg_ctx* ctx, int* hybrid_stages, int* troubled_stages, int reset);
 
 const char* lg_strerror(lg_status s);
 

@@ -348,7 +348,7 @@ def _stretch(eta, beta):
 
 
 def ramp3d(nx=1024, ny=384, nz=128, seed=RAMP_SEED, Lx=26.2, Ly=7.9, Lz=3.0, angle_deg=24.0,
-           y1=0.002, delta=1.0, noise_rms=0.05, M=RAMP_MACH, gamma=1.4, Pr=0.72):
+           y1=0.002, delta=1.0, noise_rms=0.05, M=RAMP_MACH, gamma=1.4, Pr=0.72, wall='adiabatic'):
     """Curvilinear compression-ramp grid and a turbulent-boundary-layer-like state.
 
     Grid (lengths in units of the inflow boundary-layer thickness delta):
@@ -363,13 +363,20 @@ def ramp3d(nx=1024, ny=384, nz=128, seed=RAMP_SEED, Lx=26.2, Ly=7.9, Lz=3.0, ang
       T_aw = 1 + Pr^(1/3) (gamma - 1) M^2 / 2; uniform p; rho = gamma M^2 p / T.
       Fluctuations: curl of a Gaussian-smoothed (4-cell) normal random vector potential in
       index space, limited to y_n < delta, scaled to noise_rms of U (seeded).
-    Boundaries: fixed inflow ghosts (the initial profile), transmissive outflow and top,
-    no-slip adiabatic wall, periodic span.
+    Boundaries: fixed inflow ghosts (the initial profile), transmissive (supersonic)
+    outflow and top, periodic span, and a no-slip wall: adiabatic, or with
+    wall='isothermal' held at 1.14 times the recovery temperature T_aw (Sec. 4, M2.9 ramp).
     """
     from scipy.ndimage import gaussian_filter, zoom
     n = (nx, ny, nz)
     c = Case(3, n, [(FIXED, TRANSMISSIVE), (NOSLIP, TRANSMISSIVE), (PERIODIC, PERIODIC)],
              h=(Lx / nx, Ly / ny, Lz / nz), gamma=gamma)
+    Taw = 1.0 + Pr ** (1.0 / 3.0) * 0.5 * (gamma - 1.0) * M * M
+    if wall == 'isothermal':
+        c.bc[1] = (NOSLIP_ISOTHERMAL, TRANSMISSIVE)
+        c.wall_T = [(0.0, 0.0), (1.14 * Taw, 0.0), (0.0, 0.0)]
+    elif wall != 'adiabatic':
+        raise ValueError('wall: adiabatic or isothermal')
     g = NG
     xs = (np.arange(-g, nx + g) + 0.5) * (Lx / nx)
     eta = (np.arange(-g, ny + g) + 0.5) / ny
@@ -426,7 +433,6 @@ def ramp3d(nx=1024, ny=384, nz=128, seed=RAMP_SEED, Lx=26.2, Ly=7.9, Lz=3.0, ang
     u = u + k * fx * mask
     v = v + k * fy * mask
     w = w + k * fz * mask
-    Taw = 1.0 + Pr ** (1.0 / 3.0) * 0.5 * (gamma - 1.0) * M * M
     T = Taw - (Taw - 1.0) * np.clip(U, 0.0, 1.0) ** 2
     p = np.full_like(T, 1.0 / (gamma * M * M))
     rho = gamma * M * M * p / T

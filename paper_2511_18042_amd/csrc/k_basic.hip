@@ -269,6 +269,16 @@ __global__ void k_zero_status(const Prob* __restrict__ probs) {
   if (threadIdx.x == 0) *P.status = 0;
 }
 
+// one hybrid stage done: count it, and whether it had a troubled node (the global switch
+// then runs it on C-GBR)
+__global__ void k_switch_count(const Prob* __restrict__ probs) {
+  const Prob& P = probs[blockIdx.y];
+  if (threadIdx.x == 0) {
+    P.sw[0] += 1u;
+    if (*P.any_flag != 0) P.sw[1] += 1u;
+  }
+}
+
 __global__ void k_zero_any(const Prob* __restrict__ probs) {
   const Prob& P = probs[blockIdx.y];
   if (threadIdx.x == 0) *P.any_flag = 0;
@@ -453,6 +463,10 @@ void launch_dt(const Launch& L, const double* Qx, double* tx, double t_end, int 
 
 void launch_set_dt(const Launch& L, double dt) {
   hipLaunchKernelGGL(k_set_dt, dim3(1, L.nprob), dim3(64), 0, L.stream, L.probs, dt);
+}
+
+void launch_switch_count(const Launch& L) {
+  hipLaunchKernelGGL(k_switch_count, dim3(1, L.nprob), dim3(64), 0, L.stream, L.probs);
 }
 
 void launch_zero_status(const Launch& L) {

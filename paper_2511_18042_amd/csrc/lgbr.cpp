@@ -130,6 +130,7 @@ void enqueue_rhs(const Launch& L, const Cfg& c, int scheme, StateRef ref, const 
   } else if (c.hybrid_mode == LG_HYB_GLOBAL) {
     sel = lg::SEL_GLOBAL;
     lg::launch_any_flag(L, 1);
+    lg::launch_switch_count(L);
     skip_gbr = 0;  // C-GBR inputs are skipped when no interior node is troubled
     skip_lad = 1;  // LAD inputs are skipped when one is
   } else {
@@ -142,6 +143,7 @@ void enqueue_rhs(const Launch& L, const Cfg& c, int scheme, StateRef ref, const 
     // that cross fg are solved.  With no troubled node at all (any_flag == 0) every
     // interface is LAD and all of this, and the C-GBR inputs, are skipped on the device.
     lg::launch_any_flag(L, 0);
+    lg::launch_switch_count(L);
     lg::launch_dilate(L, c.ndim, c.dilate, 0, 2);
     lg::launch_dilate(L, c.ndim, 3, 2, 3);
     if (c.grad == LG_GRAD_C4) lg::launch_line_lists(L, c.ndim);
@@ -580,6 +582,7 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
   P.status = reinterpret_cast<int*>(scal + 3);
   P.any_flag = reinterpret_cast<int*>(scal + 4);
   P.lcount = reinterpret_cast<int*>(scal + 5);   // three ints
+  P.sw = reinterpret_cast<unsigned*>(scal + 7);   // two counters
   P.t_end = 0.0;
   P.met_T = P.total;
   if (G.curvilinear) {
@@ -928,6 +931,20 @@ lg_status lg_poll_status(lg_ctx* c, int* count) {
   if (hipStreamSynchronize(c->stream) != hipSuccess) return LG_EHIP;
   *count = v;
   return v ? LG_ENONPHYS : LG_OK;
+}
+
+lg_status lg_switch_stats(lg_ctx* c, int* hybrid_stages, int* troubled_stages, int reset) {
+  if (!c || !hybrid_stages || !troubled_stages) return LG_EINVAL;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return LG_EHIP;
+  unsigned v[2] = {0u, 0u};
+  if (hipMemcpy(v, c->hp.sw, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return LG_EHIP;
+  if (reset) {
+    const unsigned z[2] = {0u, 0u};
+    if (hipMemcpy(c->hp.sw, z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess) return LG_EHIP;
+  }
+  *hybrid_stages = (int)v[0];
+  *troubled_stages = (int)v[1];
+  return LG_OK;
 }
 
 lg_status lg_batch_create(lg_batch** out, lg_ctx* const* ctxs, double* const* Q, double* const* t,

@@ -83,6 +83,7 @@ struct Prob {
   unsigned long long* smax;  // max spectral radius (bit pattern of a positive double)
   int* status;               // non-physical node count
   int* any_flag;             // global hybrid switch: any troubled interior node
+  unsigned* sw;              // switching record: [0] hybrid stages, [1] those with a troubled node
 };
 
 __host__ __device__ __forceinline__ int pos_to_idx(const Prob& P, int i, int j, int k) {

@@ -127,6 +127,7 @@ void launch_line_lists(const Launch& L, int ndim);
 void launch_dt(const Launch& L, const double* Qx, double* tx, double t_end, int advance_t);
 void launch_set_dt(const Launch& L, double dt);
 void launch_zero_status(const Launch& L);
+void launch_switch_count(const Launch& L);
 void launch_metrics(int ndim, const int N[3], const double* coords, double* scratch9, double* metrics,
                     hipStream_t s);
 template <typename R> void launch_convert(const double* src, R* dst, size_t n, hipStream_t s);

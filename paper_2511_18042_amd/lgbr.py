@@ -22,7 +22,7 @@ EXPORTS = ('lg_set_allocator', 'lg_strerror', 'lg_create', 'lg_destroy', 'lg_wor
            'lg_metrics_from_coords', 'cgbr_rhs', 'lad_rhs', 'hybrid_rhs', 'rk3_step', 'lg_rk3_stage',
            'lg_compute_dt', 'lg_batch_create', 'lg_batch_run', 'lg_batch_destroy', 'lg_poll_status',
            'lg_prof_start', 'lg_prof_stop', 'lg_set_tuning', 'lg_get_tuning', 'lg_metrics_planar', 'lad_filter',
-           'lg_set_line_tiles', 'lg_get_line_tiles')
+           'lg_set_line_tiles', 'lg_get_line_tiles', 'lg_switch_stats')
 KERNEL_CLASSES = ('bc', 'prim', 'flags', 'grad_e6', 'grad_c4', 'sensor', 'visc', 'lad_node', 'lad_raw', 'gauss',
                   'lad_flux', 'sweep_x', 'sweep_y', 'sweep_z', 'combine', 'dt', 'bc_scalar', 'lad_sweep',
                   'c6_faces', 'filter')
@@ -81,6 +81,7 @@ def load():
         'lg_batch_run': (I, [P]),
         'lg_batch_destroy': (None, [P]),
         'lg_poll_status': (I, [P, ctypes.POINTER(I)]),
+        'lg_switch_stats': (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), I]),
         'lg_prof_start': (I, [P, I, I]),
         'lg_prof_stop': (I, [P, ctypes.POINTER(D), ctypes.POINTER(I)]),
         'lg_set_tuning': (I, [P, I, I, I]),
@@ -241,6 +242,13 @@ class Context:
         _check(self._lib.lg_get_tuning(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(z)),
                'lg_get_tuning')
         return a.value, b.value, z.value
+
+    def switch_stats(self, reset=False):
+        """(hybrid stages, stages with a troubled node) since creation or the last reset."""
+        a, b = ctypes.c_int(0), ctypes.c_int(0)
+        _check(self._lib.lg_switch_stats(self.handle, ctypes.byref(a), ctypes.byref(b), 1 if reset else 0),
+               'lg_switch_stats')
+        return a.value, b.value
 
     def poll_status(self):
         n = ctypes.c_int(0)
