@@ -238,6 +238,47 @@ int lg_get_line_tiles(const lg_ctx* ctx);
 /* Synchronises the context's stream and reads its non-physical node count since the
  * last poll (then resets it).  Returns LG_ENONPHYS when the count is non-zero. */
 lg_status lg_poll_status(lg_ctx* ctx, int* nonphys_count);
+/* Digital-filter inflow turbulence (Sec. 4: the 3D cases' inflow, with per-component integral
+ * length scales in two wall-normal zones and the strong Reynolds analogy for temperature
+ * and density).  One generator per context writes the FIXED ghost layers of the low-xi
+ * face; each update:
+ *   1. filters a plane of standard normal numbers (supplied by the caller, rnd, device,
+ *      [3][ny + 2 pad][nz], pad = the largest filter support along eta, see
+ *      lg_df_random_count) along zeta (periodic) and eta with the coefficients
+ *      b_i = exp(-pi |i| / n) / norm, |i| <= ceil(2 n), n = length scale / spacing (eta:
+ *      the row's spacing and zone, inner where y <= y_lim);
+ *   2. correlates it in time: psi <- psi exp(-pi dt / 2T) + new sqrt(1 - exp(-pi dt / T)),
+ *      T = Ix / U_ref (first update: psi = new);
+ *   3. forms u' = a11 psi_u, v' = a21 psi_u + a22 psi_v, w' = a33 psi_w (a: Cholesky
+ *      factor of R11, R21, R22, R33), T'/T = -(gamma - 1) M_sra^2 u' / U_ref,
+ *      rho = rho_mean (1 - T'/T), p unchanged, and writes (rho, U + u', V + v', w', p) as
+ *      conserved values into every ghost layer of the low-xi face (interior eta, zeta).
+ * The context needs ndim >= 2 and LG_BC_FIXED on the low-xi face; ny = n[1], nz = n[2]
+ * (1 in 2D).  Profile arrays are host memory, copied at creation. */
+typedef struct {
+  int ny, nz;              /* inflow plane: interior eta rows and zeta columns           */
+  const double* dy;        /* [ny] row spacings along eta (> 0)                          */
+  const double* y;         /* [ny] wall distance of each row (zone selection)           */
+  double dz;               /* spanwise spacing (> 0; unused in 2D)                       */
+  double y_lim;            /* inner zone: y <= y_lim                                     */
+  double Iy[3][2];         /* eta length scales of u, v, w: inner, outer (> 0)           */
+  double Iz[3], Ix[3];     /* zeta and streamwise length scales of u, v, w (> 0)         */
+  double U_ref;            /* Taylor convection velocity and analogy velocity (> 0)      */
+  const double* mean;      /* [4][ny] mean rho (> 0), U, V, T                           */
+  const double* rey;       /* [4][ny] Reynolds stresses R11, R21, R22, R33 (R_ii >= 0)  */
+  double M_sra;            /* Mach number of the strong Reynolds analogy                  */
+  double p;                /* inflow pressure (> 0)                                      */
+} lg_df_spec;
+typedef struct lg_df lg_df;
+lg_status lg_df_create(lg_ctx* ctx, const lg_df_spec* spec, lg_df** out);
+/* doubles of rnd one update consumes: 3 (ny + 2 pad) nz */
+lg_status lg_df_random_count(const lg_df* df, long long* count);
+/* One update on the context's stream; dt < 0 takes the context's device time step (the
+ * last step's), else dt; first != 0 starts the time correlation.  Q: the state whose
+ * inflow ghosts are written (device). */
+lg_status lg_df_update(lg_df* df, const double* rnd, double* Q, double dt, int first);
+void lg_df_destroy(lg_df* df);
+
 /* Switching record of the hybrid (Sec. 5: the share of the run spent on each scheme):
  * every hybrid stage of the context (hybrid_rhs, rk3_step, lg_rk3_stage, batches) counts
  * one, and one more in *troubled_stages when a node was troubled at its start (global

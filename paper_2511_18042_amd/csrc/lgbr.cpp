@@ -933,6 +933,150 @@ lg_status lg_poll_status(lg_ctx* c, int* count) {
   return v ? LG_ENONPHYS : LG_OK;
 }
 
+// ------------------------------------------------------------------ digital-filter inflow
+struct lg_df {
+  lg_ctx* ctx = nullptr;
+  lg::DFDev D{};
+  std::vector<void*> allocs;
+  long long nrand = 0;
+};
+
+void lg_df_destroy(lg_df* f) {
+  if (!f) return;
+  if (f->ctx) (void)hipStreamSynchronize(f->ctx->stream);
+  for (void* p : f->allocs) dev_free(p);
+  delete f;
+}
+
+namespace {
+// b_i = exp(-pi |i| / n) / sqrt(sum b^2), |i| <= ceil(2 n)
+std::vector<double> df_coef(double n) {
+  n = std::max(n, 1e-12);
+  const int N = (int)std::ceil(2.0 * n);
+  std::vector<double> b(2 * N + 1);
+  double ss = 0.0;
+  for (int i = -N; i <= N; ++i) {
+    b[i + N] = std::exp(-M_PI * std::abs(i) / n);
+    ss += b[i + N] * b[i + N];
+  }
+  const double inv = 1.0 / std::sqrt(ss);
+  for (double& v : b) v *= inv;
+  return b;
+}
+bool pos_finite(double v) { return v > 0.0 && std::isfinite(v); }
+}  // namespace
+
+lg_status lg_df_create(lg_ctx* c, const lg_df_spec* s, lg_df** out) {
+  if (!c || !s || !out) return LG_EINVAL;
+  *out = nullptr;
+  const Prob& P = c->hp;
+  if (P.ndim < 2 || P.bc[0][0] != LG_BC_FIXED) return LG_EINVAL;
+  if (s->ny != P.n[1] || s->nz != (P.ndim == 3 ? P.n[2] : 1)) return LG_EINVAL;
+  if (!s->dy || !s->y || !s->mean || !s->rey) return LG_EINVAL;
+  if (!pos_finite(s->U_ref) || !pos_finite(s->p) || !std::isfinite(s->M_sra) || !std::isfinite(s->y_lim)) return LG_EINVAL;
+  if (P.ndim == 3 && !pos_finite(s->dz)) return LG_EINVAL;
+  const int ny = s->ny, nz = s->nz;
+  for (int q = 0; q < 3; ++q) {
+    if (!pos_finite(s->Iy[q][0]) || !pos_finite(s->Iy[q][1]) || !pos_finite(s->Iz[q]) || !pos_finite(s->Ix[q]))
+      return LG_EINVAL;
+  }
+  for (int j = 0; j < ny; ++j) {
+    if (!pos_finite(s->dy[j]) || !std::isfinite(s->y[j]) || !pos_finite(s->mean[j])) return LG_EINVAL;
+    for (int q = 1; q < 4; ++q)
+      if (!std::isfinite(s->mean[q * ny + j])) return LG_EINVAL;
+    const double R11 = s->rey[j], R21 = s->rey[ny + j], R22 = s->rey[2 * ny + j], R33 = s->rey[3 * ny + j];
+    if (!(R11 >= 0.0) || !(R22 >= 0.0) || !(R33 >= 0.0) || !std::isfinite(R21) || !std::isfinite(R11 + R22 + R33))
+      return LG_EINVAL;
+  }
+  lg_df* f = new (std::nothrow) lg_df();
+  if (!f) return LG_ENOMEM;
+  f->ctx = c;
+  lg::DFDev& D = f->D;
+  D.ny = ny;
+  D.nz = nz;
+  // eta coefficients per component and row (zone by wall distance, local spacing)
+  std::vector<std::vector<double>> rowc(3 * (size_t)ny);
+  int pad = 0;
+  for (int q = 0; q < 3; ++q)
+    for (int j = 0; j < ny; ++j) {
+      const double I = s->Iy[q][s->y[j] <= s->y_lim ? 0 : 1];
+      rowc[(size_t)q * ny + j] = df_coef(I / s->dy[j]);
+      pad = std::max(pad, (int)(rowc[(size_t)q * ny + j].size() - 1) / 2);
+    }
+  D.pad = pad;
+  std::vector<double> by(3 * (size_t)ny * (2 * pad + 1), 0.0);
+  std::vector<int> nyh(3 * (size_t)ny);
+  for (size_t r = 0; r < rowc.size(); ++r) {
+    const int h = (int)(rowc[r].size() - 1) / 2;
+    nyh[r] = h;
+    for (int i = -h; i <= h; ++i) by[r * (2 * pad + 1) + pad + i] = rowc[r][i + h];
+  }
+  std::vector<std::vector<double>> zc(3);
+  int nzmax = 0;
+  for (int q = 0; q < 3; ++q) {
+    zc[q] = df_coef(s->Iz[q] / (P.ndim == 3 ? s->dz : 1.0));
+    D.nzh[q] = (int)(zc[q].size() - 1) / 2;
+    nzmax = std::max(nzmax, D.nzh[q]);
+  }
+  D.nzmax = nzmax;
+  std::vector<double> bz(3 * (size_t)(2 * nzmax + 1), 0.0);
+  for (int q = 0; q < 3; ++q)
+    for (int l = -D.nzh[q]; l <= D.nzh[q]; ++l) bz[(size_t)q * (2 * nzmax + 1) + nzmax + l] = zc[q][l + D.nzh[q]];
+  // Cholesky factor of the Reynolds stresses
+  std::vector<double> a(4 * (size_t)ny);
+  for (int j = 0; j < ny; ++j) {
+    const double a11 = std::sqrt(s->rey[j]);
+    const double a21 = a11 > 0.0 ? s->rey[ny + j] / a11 : 0.0;
+    a[j] = a11;
+    a[ny + j] = a21;
+    a[2 * ny + j] = std::sqrt(std::max(s->rey[2 * ny + j] - a21 * a21, 0.0));
+    a[3 * ny + j] = std::sqrt(s->rey[3 * ny + j]);
+  }
+  for (int q = 0; q < 3; ++q) D.Tc[q] = s->Ix[q] / s->U_ref;
+  D.gm1 = P.gamma - 1.0;
+  D.M2 = s->M_sra * s->M_sra;
+  D.U_ref = s->U_ref;
+  D.p = s->p;
+  bool ok = true;
+  auto up = [&](const void* src, size_t bytes) -> void* {
+    void* d = dev_alloc(bytes);
+    if (!d) {
+      ok = false;
+      return nullptr;
+    }
+    f->allocs.push_back(d);
+    if (src && hipMemcpy(d, src, bytes, hipMemcpyHostToDevice) != hipSuccess) ok = false;
+    return d;
+  };
+  D.by = static_cast<const double*>(up(by.data(), by.size() * sizeof(double)));
+  D.nyh = static_cast<const int*>(up(nyh.data(), nyh.size() * sizeof(int)));
+  D.bz = static_cast<const double*>(up(bz.data(), bz.size() * sizeof(double)));
+  D.a = static_cast<const double*>(up(a.data(), a.size() * sizeof(double)));
+  D.mean = static_cast<const double*>(up(s->mean, 4 * (size_t)ny * sizeof(double)));
+  const long long rows = ny + 2LL * pad;
+  D.rz = static_cast<double*>(up(nullptr, 3 * rows * nz * sizeof(double)));
+  D.psi = static_cast<double*>(up(nullptr, 3 * (size_t)ny * nz * sizeof(double)));
+  f->nrand = 3 * rows * nz;
+  if (!ok) {
+    lg_df_destroy(f);
+    return LG_ENOMEM;
+  }
+  *out = f;
+  return LG_OK;
+}
+
+lg_status lg_df_random_count(const lg_df* f, long long* count) {
+  if (!f || !count) return LG_EINVAL;
+  *count = f->nrand;
+  return LG_OK;
+}
+
+lg_status lg_df_update(lg_df* f, const double* rnd, double* Q, double dt, int first) {
+  if (!f || !rnd || !Q || !std::isfinite(dt)) return LG_EINVAL;
+  lg::launch_df_update(f->D, f->ctx->dp, rnd, Q, dt, first, f->ctx->stream);
+  return last_hip();
+}
+
 lg_status lg_switch_stats(lg_ctx* c, int* hybrid_stages, int* troubled_stages, int reset) {
   if (!c || !hybrid_stages || !troubled_stages) return LG_EINVAL;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return LG_EHIP;

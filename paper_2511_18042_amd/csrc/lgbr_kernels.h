@@ -128,6 +128,23 @@ void launch_dt(const Launch& L, const double* Qx, double* tx, double t_end, int 
 void launch_set_dt(const Launch& L, double dt);
 void launch_zero_status(const Launch& L);
 void launch_switch_count(const Launch& L);
+// digital-filter inflow: device tables and state of one generator (host code builds the
+// tables; see k_inflow.hip)
+struct DFDev {
+  int ny, nz, pad, nzmax;
+  int nzh[3];           // half-width of the zeta filter per component
+  const int* nyh;       // [3][ny] half-width of the eta filter per component and row
+  const double* by;     // [3][ny][2 pad + 1] eta coefficients, centred at pad
+  const double* bz;     // [3][2 nzmax + 1] zeta coefficients, centred at nzmax
+  const double* a;      // [4][ny] a11, a21, a22, a33
+  const double* mean;   // [4][ny] rho, U, V, T
+  double Tc[3];         // Ix / U_ref
+  double gm1, M2, U_ref, p;
+  double* rz;           // [3][ny + 2 pad][nz] zeta-filtered numbers
+  double* psi;          // [3][ny][nz] time-correlated field
+};
+void launch_df_update(const DFDev& D, const Prob* prob, const double* rnd, double* Q, double dt, int first,
+                      hipStream_t s);
 void launch_metrics(int ndim, const int N[3], const double* coords, double* scratch9, double* metrics,
                     hipStream_t s);
 template <typename R> void launch_convert(const double* src, R* dst, size_t n, hipStream_t s);

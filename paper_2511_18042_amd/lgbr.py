@@ -22,7 +22,8 @@ EXPORTS = ('lg_set_allocator', 'lg_strerror', 'lg_create', 'lg_destroy', 'lg_wor
            'lg_metrics_from_coords', 'cgbr_rhs', 'lad_rhs', 'hybrid_rhs', 'rk3_step', 'lg_rk3_stage',
            'lg_compute_dt', 'lg_batch_create', 'lg_batch_run', 'lg_batch_destroy', 'lg_poll_status',
            'lg_prof_start', 'lg_prof_stop', 'lg_set_tuning', 'lg_get_tuning', 'lg_metrics_planar', 'lad_filter',
-           'lg_set_line_tiles', 'lg_get_line_tiles', 'lg_switch_stats')
+           'lg_set_line_tiles', 'lg_get_line_tiles', 'lg_switch_stats', 'lg_df_create', 'lg_df_random_count',
+           'lg_df_update', 'lg_df_destroy')
 KERNEL_CLASSES = ('bc', 'prim', 'flags', 'grad_e6', 'grad_c4', 'sensor', 'visc', 'lad_node', 'lad_raw', 'gauss',
                   'lad_flux', 'sweep_x', 'sweep_y', 'sweep_z', 'combine', 'dt', 'bc_scalar', 'lad_sweep',
                   'c6_faces', 'filter')
@@ -80,6 +81,10 @@ def load():
         'lg_batch_create': (I, [ctypes.POINTER(P), P, P, P, P, I, I, I]),
         'lg_batch_run': (I, [P]),
         'lg_batch_destroy': (None, [P]),
+        'lg_df_create': (I, [P, P, ctypes.POINTER(P)]),
+        'lg_df_random_count': (I, [P, ctypes.POINTER(ctypes.c_longlong)]),
+        'lg_df_update': (I, [P, P, P, D, I]),
+        'lg_df_destroy': (None, [P]),
         'lg_poll_status': (I, [P, ctypes.POINTER(I)]),
         'lg_switch_stats': (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), I]),
         'lg_prof_start': (I, [P, I, I]),
@@ -256,6 +261,61 @@ class Context:
         if code not in (LG_OK, LG_ENONPHYS):
             _check(code, 'lg_poll_status')
         return n.value
+
+
+class LgDFSpec(ctypes.Structure):
+    _fields_ = [('ny', ctypes.c_int), ('nz', ctypes.c_int), ('dy', ctypes.c_void_p), ('y', ctypes.c_void_p),
+                ('dz', ctypes.c_double), ('y_lim', ctypes.c_double), ('Iy', (ctypes.c_double * 2) * 3),
+                ('Iz', ctypes.c_double * 3), ('Ix', ctypes.c_double * 3), ('U_ref', ctypes.c_double),
+                ('mean', ctypes.c_void_p), ('rey', ctypes.c_void_p), ('M_sra', ctypes.c_double),
+                ('p', ctypes.c_double)]
+
+
+class DFInflow:
+    """Digital-filter inflow generator of a context (lg_df_*): the profile arrays are numpy
+    FP64 arrays over the ny inflow rows (mean: rho, U, V, T; rey: R11, R21, R22, R33)."""
+
+    def __init__(self, ctx, dy, y, dz, y_lim, Iy, Iz, Ix, U_ref, mean, rey, M_sra, p):
+        import numpy as np
+        lib = load()
+        self._lib = lib
+        self.ctx = ctx
+        arrs = [np.ascontiguousarray(v, dtype=np.float64) for v in (dy, y, mean, rey)]
+        self._arrs = arrs
+        spec = LgDFSpec()
+        spec.ny = int(arrs[0].size)
+        spec.nz = int(ctx.grid.n[2]) if ctx.grid.ndim == 3 else 1
+        spec.dy, spec.y = arrs[0].ctypes.data, arrs[1].ctypes.data
+        spec.dz, spec.y_lim = float(dz), float(y_lim)
+        for c in range(3):
+            spec.Iy[c][0], spec.Iy[c][1] = float(Iy[c][0]), float(Iy[c][1])
+            spec.Iz[c], spec.Ix[c] = float(Iz[c]), float(Ix[c])
+        spec.U_ref = float(U_ref)
+        spec.mean, spec.rey = arrs[2].ctypes.data, arrs[3].ctypes.data
+        spec.M_sra, spec.p = float(M_sra), float(p)
+        h = ctypes.c_void_p()
+        _check(lib.lg_df_create(ctx.handle, ctypes.byref(spec), ctypes.byref(h)), 'lg_df_create')
+        self.handle = h
+
+    def random_count(self):
+        n = ctypes.c_longlong(0)
+        _check(self._lib.lg_df_random_count(self.handle, ctypes.byref(n)), 'lg_df_random_count')
+        return n.value
+
+    def update(self, rnd, Q, dt=-1.0, first=False):
+        _check(self._lib.lg_df_update(self.handle, _ptr(rnd), _ptr(Q), float(dt), 1 if first else 0),
+               'lg_df_update')
+
+    def close(self):
+        if self.handle:
+            self._lib.lg_df_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:

@@ -42,7 +42,7 @@ def test_binding_struct_layout_matches_header(tmp_path):
     cc = shutil.which('gcc') or shutil.which('cc')
     if cc is None:
         pytest.skip('no C compiler')
-    structs = {'lg_grid': lgbr.LgGrid, 'lg_gas': lgbr.LgGas, 'lg_opts': lgbr.LgOpts}
+    structs = {'lg_grid': lgbr.LgGrid, 'lg_gas': lgbr.LgGas, 'lg_opts': lgbr.LgOpts, 'lg_df_spec': lgbr.LgDFSpec}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lgbr.h"', 'int main(void) {']
     for cname, cls in structs.items():
         lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
