@@ -250,8 +250,10 @@ lg_status lg_poll_status(lg_ctx* ctx, int* nonphys_count);
  *   2. correlates it in time: psi <- psi exp(-pi dt / 2T) + new sqrt(1 - exp(-pi dt / T)),
  *      T = Ix / U_ref (first update: psi = new);
  *   3. forms u' = a11 psi_u, v' = a21 psi_u + a22 psi_v, w' = a33 psi_w (a: Cholesky
- *      factor of R11, R21, R22, R33), T'/T = -(gamma - 1) M_sra^2 u' / U_ref,
- *      rho = rho_mean (1 - T'/T), p unchanged, and writes (rho, U + u', V + v', w', p) as
+ *      factor of R11, R21, R22, R33), T'/T = -(gamma - 1) M_sra^2 U u' / (U_ref^2 T) (the
+ *      strong Reynolds analogy at the local mean Mach number; T in units of the
+ *      reference temperature), rho = rho_mean (1 - T'/T), p unchanged, and writes
+ *      (rho, U + u', V + v', w', p) as
  *      conserved values into every ghost layer of the low-xi face (interior eta, zeta).
  * The context needs ndim >= 2 and LG_BC_FIXED on the low-xi face; ny = n[1], nz = n[2]
  * (1 in 2D).  Profile arrays are host memory, copied at creation. */
@@ -266,7 +268,7 @@ typedef struct {
   double U_ref;            /* Taylor convection velocity and analogy velocity (> 0)      */
   const double* mean;      /* [4][ny] mean rho (> 0), U, V, T                           */
   const double* rey;       /* [4][ny] Reynolds stresses R11, R21, R22, R33 (R_ii >= 0)  */
-  double M_sra;            /* Mach number of the strong Reynolds analogy                  */
+  double M_sra;            /* reference Mach number of the strong Reynolds analogy        */
   double p;                /* inflow pressure (> 0)                                      */
 } lg_df_spec;
 typedef struct lg_df lg_df;

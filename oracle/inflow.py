@@ -20,8 +20,9 @@ none of its formulas; R33 takes the exponential-filter form with time correlatio
   4. velocity fluctuations by the Cholesky factor of the Reynolds stresses (Lund):
      u' = a11 psi_u, v' = a21 psi_u + a22 psi_v, w' = a33 psi_w with a11 = sqrt(R11),
      a21 = R21 / a11, a22 = sqrt(R22 - a21^2), a33 = sqrt(R33) (zero where R11 = 0);
-  5. strong Reynolds analogy: T'/T = -(gamma - 1) M_sra^2 u'/U_ref, rho'/rho = -T'/T,
-     pressure unchanged;
+  5. strong Reynolds analogy with the local mean Mach number M^2 = M_sra^2 U^2 / (U_ref^2 T)
+     (T in units of the reference temperature): T'/T = -(gamma - 1) M^2 u'/U
+     = -(gamma - 1) M_sra^2 U u' / (U_ref^2 T); rho'/rho = -T'/T, pressure unchanged;
   6. every ghost layer of the low-xi face (FIXED) takes the plane's state
      (rho(1 + rho'/rho), U + u', V + v', w', p).
 """
@@ -114,8 +115,8 @@ def inflow_plane(spec, psi):
     up = a11[:, None] * psi[0]
     vp = a21[:, None] * psi[0] + a22[:, None] * psi[1]
     wp = a33[:, None] * psi[2]
-    rho, U, V, _ = spec.mean
-    tr = -(spec.gamma - 1.0) * spec.M_sra ** 2 * up / spec.U_ref      # T'/T
+    rho, U, V, Tm = spec.mean
+    tr = -(spec.gamma - 1.0) * spec.M_sra ** 2 * U[:, None] * up / (spec.U_ref ** 2 * Tm[:, None])   # T'/T
     out = np.empty((5,) + psi.shape[1:])
     out[0] = rho[:, None] * (1.0 - tr)
     out[1] = U[:, None] + up

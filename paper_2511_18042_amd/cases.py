@@ -342,6 +342,45 @@ RAMP_SEED = 2511
 RAMP_MACH = 2.9
 
 
+# integral length scales of the digital-filter inflow in units of the inflow boundary-layer
+# thickness (Sec. 4, table of length scales): u, v, w
+DF_IX = (0.7, 0.28, 0.28)
+DF_IY = ((0.13, 0.23), (0.17, 0.3), (0.1, 0.13))     # (inner, outer)
+DF_IZ = (0.15, 0.15, 0.3)
+
+
+def ramp_df_inflow(c, delta=1.0, M=RAMP_MACH, gamma=1.4):
+    """Inputs of the digital-filter inflow generator for a ramp3d case (keyword arguments of
+    lgbr.DFInflow / oracle.inflow.DFSpec): the first interior xi column's rows; mean
+    rho, U, V, T averaged over the span; Reynolds stresses from a model boundary layer
+    (u, v, w rms 0.10, 0.06, 0.08 U_inf times (1 - y/delta)(1 - exp(-y / 0.05 delta)) below
+    delta, R21 = -0.4 u_rms v_rms); inner zone up to the displacement thickness of the mean
+    profile; the length-scale table in units of delta; the analogy at the free-stream Mach
+    number; the free-stream pressure."""
+    g = NG
+    X, Y = c.coords[0], c.coords[1]
+    ny = c.n[1]
+    col = Y[g, :, g]                                   # first interior xi column, one z plane
+    wall = 0.5 * (col[g - 1] + col[g])                 # the wall face
+    y = col[g:g + ny] - wall
+    dy = 0.5 * (col[g + 1:g + ny + 1] - col[g - 1:g + ny - 1])
+    Q = c.Q[:, g:g + c.n[2], g:g + ny, g]              # (5, nz, ny)
+    rho = Q[0].mean(axis=0)
+    U = (Q[1] / Q[0]).mean(axis=0)
+    V = (Q[2] / Q[0]).mean(axis=0)
+    ke = 0.5 * (Q[1] ** 2 + Q[2] ** 2 + Q[3] ** 2) / Q[0]
+    p = ((gamma - 1.0) * (Q[4] - ke)).mean(axis=0)
+    T = gamma * M * M * p / rho
+    f = np.where(y < delta, (1.0 - y / delta) * (1.0 - np.exp(-y / (0.05 * delta))), 0.0)
+    urms, vrms, wrms = 0.10 * f, 0.06 * f, 0.08 * f
+    rey = np.stack([urms ** 2, -0.4 * urms * vrms, vrms ** 2, wrms ** 2])
+    inside = y < delta
+    y_lim = float(np.sum(((1.0 - np.clip(U, 0.0, 1.0)) * dy)[inside]))
+    return dict(dy=dy, y=y, dz=c.h[2], y_lim=y_lim, Iy=[tuple(v) for v in DF_IY], Iz=list(DF_IZ),
+                Ix=list(DF_IX), U_ref=1.0, mean=np.stack([rho, U, V, T]), rey=rey, M_sra=M,
+                p=1.0 / (gamma * M * M))
+
+
 def _stretch(eta, beta):
     """Wall-normal tanh clustering: 0 at the wall (eta = 0), 1 at the top (eta = 1)."""
     return 1.0 + np.tanh(beta * (eta - 1.0)) / np.tanh(beta)

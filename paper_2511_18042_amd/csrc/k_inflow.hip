@@ -68,9 +68,11 @@ __global__ void __launch_bounds__(256) k_df_ghosts(DFDev D, const Prob* __restri
     const double a11 = D.a[j], a21 = D.a[D.ny + j], a22 = D.a[2 * D.ny + j], a33 = D.a[3 * D.ny + j];
     const double pu = D.psi[t], pv = D.psi[pl + t], pw = D.psi[2 * pl + t];
     const double up = a11 * pu, vp = a21 * pu + a22 * pv, wp = a33 * pw;
-    const double tr = -D.gm1 * D.M2 * up / D.U_ref;   // T'/T
+    // T'/T by the strong Reynolds analogy at the local mean Mach number
+    const double Um = D.mean[D.ny + j], Tm = D.mean[3 * D.ny + j];
+    const double tr = -D.gm1 * D.M2 * Um * up / (D.U_ref * D.U_ref * Tm);
     const double rho = D.mean[j] * (1.0 - tr);
-    const double u = D.mean[D.ny + j] + up, v = D.mean[2 * D.ny + j] + vp, w = wp;
+    const double u = Um + up, v = D.mean[2 * D.ny + j] + vp, w = wp;
     const double cons[5] = {rho, rho * u, rho * v, rho * w, D.p / D.gm1 + 0.5 * rho * (u * u + v * v + w * w)};
     const size_t col = (size_t)(P.g[1] + j) * P.s[1] + (size_t)(P.g[2] + k) * P.s[2];
     for (int m = 0; m < NG; ++m)

@@ -5,9 +5,10 @@ on the GPU, for the two cases the paper reports:
   * the triple point (1792 x 768, MEG6 / LAD-E4, troubled where rho < 0.0625, FP64) until
     t = 5, the first non-physical stage, or the wall-time cap (paper: LAD 13.6 % of the run);
   * the M2.9 ramp stand-in (1024 x 384 x 128, MIG4 / LAD-E4, troubled where p < p_inf / 2,
-    FP32 bulk) for a fixed number of steps, with the adiabatic wall of the headline workload
-    and with the isothermal wall at 1.14 T_aw (paper: LAD 82.4 % of one flow-through,
-    1.67x faster than MEG6 C-GBR).
+    FP32 bulk) for a fixed number of steps, with the adiabatic wall of the headline workload,
+    with the isothermal wall at 1.14 T_aw, and with that wall and the digital-filter inflow
+    (a new time-correlated plane before every step, cases.ramp_df_inflow) (paper: LAD 82.4 %
+    of one flow-through, 1.67x faster than MEG6 C-GBR).
 
 Every RK3 step reads the context's switching record (lg_switch_stats: hybrid stages and
 those with a troubled node).  A step counts as LAD or C-GBR by its stages; a step whose
@@ -37,9 +38,10 @@ def _triple_point():
     return c, gas, grid, opts, None, None, None
 
 
-def _ramp(wall):
+def _ramp(wall, df=False):
     import torch
     c = cases.ramp3d(wall=wall)
+    inflow = cases.ramp_df_inflow(c) if df else None
     e = c.extra
     gas = lgbr.make_gas(gamma=1.4, Re=e['Re'], Pr=e['Pr'], Mref=e['Mref'], suth=e['suth'], viscous=True)
     grid = lgbr.make_grid(3, c.n, c.bc, c.h, curvilinear=True, wall_T=c.wall_T)
@@ -48,6 +50,7 @@ def _ramp(wall):
     lgbr.metrics_from_coords(grid, coords, metrics)
     c.coords = None
     opts = dict(grad='C4', precision='mixed', rho_thr=-1.0, p_thr=e['p_thr'])
+    c.extra['df_inflow'] = inflow
     return c, gas, grid, opts, metrics, coords, 1e30
 
 
@@ -55,6 +58,8 @@ CASES = {
     'triple_point': (_triple_point, 'MEG6 / LAD-E4, FP64', 13.6),
     'ramp_adiabatic': (lambda: _ramp('adiabatic'), 'MIG4 / LAD-E4, FP32 bulk, adiabatic wall', 82.4),
     'ramp_isothermal': (lambda: _ramp('isothermal'), 'MIG4 / LAD-E4, FP32 bulk, wall at 1.14 T_aw', 82.4),
+    'ramp_isothermal_df': (lambda: _ramp('isothermal', df=True),
+                           'MIG4 / LAD-E4, FP32 bulk, wall at 1.14 T_aw, digital-filter inflow', 82.4),
 }
 
 
@@ -83,8 +88,17 @@ def run(name, wall=120.0, ramp_steps=2000):
     t = torch.zeros(1, dtype=torch.float64, device='cuda')
     per_step = []
     status, bad, steps = 'steps', 0, 0
+    df = None
+    if (c.extra or {}).get('df_inflow') is not None:
+        df = lgbr.DFInflow(ctx, **c.extra['df_inflow'])
+        gen = torch.Generator(device='cuda')
+        gen.manual_seed(18042)
+        count = df.random_count()
     t0 = time.perf_counter()
     while True:
+        if df is not None:   # a new inflow plane for the step (time-correlated with the last)
+            df.update(torch.randn(count, generator=gen, dtype=torch.float64, device='cuda'), Q, dt=-1.0,
+                      first=steps == 0)
         ctx.rk3_step('hybrid', Q, t_end, t)
         n_st, n_tr = ctx.switch_stats(reset=True)
         per_step.append(n_tr)
@@ -114,6 +128,8 @@ def run(name, wall=120.0, ramp_steps=2000):
     switches = int((mode == -1).sum()) + int(np.sum((mode[1:] != mode[:-1]) & (mode[1:] >= 0) & (mode[:-1] >= 0)))
     first_gbr = int(np.argmax(tr > 0)) if gbr else None
     hyb_ms = _step_time(ctx, 'hybrid', Q0)
+    if df is not None:
+        df.close()
     ctx.close()
     ctx = lgbr.Context(grid, gas, lgbr.make_opts(cfl=0.2, hybrid_mode='global', **dict(o, grad='E6')), metrics, coords)
     meg6_ms = _step_time(ctx, 'cgbr', Q0)

@@ -100,13 +100,18 @@ def test_lund_transform_reproduces_the_reynolds_stresses():
 
 
 def test_strong_reynolds_analogy_and_uniform_pressure():
+    """T'/T = -(gamma - 1) Mbar^2 u'/U with the local mean Mach number
+    Mbar^2 = U^2 / c^2, c^2 = T / M_sra^2 (T in units of the reference temperature, the
+    reference speed of sound U_ref / M_sra); density opposite at constant pressure."""
     s = _spec(nz=3)
     rng = np.random.default_rng(4)
     psi = rng.standard_normal((3, s.ny, 3))
     pl = DF.inflow_plane(s, psi)
-    up = pl[1] - s.mean[1][:, None]
-    tr = -(s.gamma - 1.0) * s.M_sra ** 2 * up / s.U_ref
-    np.testing.assert_allclose(pl[0], s.mean[0][:, None] * (1.0 - tr), rtol=1e-14)
+    U, T = s.mean[1][:, None], s.mean[3][:, None]
+    up = pl[1] - U
+    c2 = T * (s.U_ref / s.M_sra) ** 2
+    tr = -(s.gamma - 1.0) * (U ** 2 / c2) * up / U
+    np.testing.assert_allclose(pl[0], s.mean[0][:, None] * (1.0 - tr), rtol=1e-13)
     assert np.all(pl[4] == s.p)
 
 
