@@ -266,7 +266,7 @@ __global__ void k_set_dt(const Prob* __restrict__ probs, double dt) {
 
 __global__ void k_zero_status(const Prob* __restrict__ probs) {
   const Prob& P = probs[blockIdx.y];
-  if (threadIdx.x == 0) *P.status = 0;
+  if (threadIdx.x < STATUS_SLOTS) P.status[STATUS_STRIDE * threadIdx.x] = 0;
 }
 
 // one hybrid stage done: count it, and whether it had a troubled node (the global switch

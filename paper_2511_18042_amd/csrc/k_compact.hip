@@ -446,7 +446,7 @@ __global__ void __launch_bounds__(256) k_c6_faces(const Prob* __restrict__ probs
     for (int q = 0; q < NQ; ++q) D[q] = xnext[q] - xlast[q];   // node 0: x_0 - x_{n-1}
     if (face_emit_q<NQ>(P, o, dQ, dt, q0, base + (size_t)g * sd, D)) ++bad;
   }
-  if (bad) atomicAdd(P.status, bad);
+  add_bad(P, bad);
 }
 
 // Contiguous lines (the first direction of a 2D / 3D grid): one workgroup per (interior
@@ -908,7 +908,7 @@ k_line_tiles(const Prob* __restrict__ probs, TileArgs A) {
       }
       if (face_emit(P, o, dQ, dt, lbase + (size_t)c * P.s[o1] + (size_t)(g + i) * sd, D)) ++bad;
     }
-    if (bad) atomicAdd(P.status, bad);
+    add_bad(P, bad);
   } else {
     double* Q = A.ref.state(P);
     for (int e = tid; e < TX * n; e += NT) {

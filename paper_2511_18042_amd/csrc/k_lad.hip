@@ -578,7 +578,7 @@ __global__ void __launch_bounds__(256) k_lad_sweep(const Prob* __restrict__ prob
       ++bad;
     }
   }
-  if (bad) atomicAdd(P.status, bad);
+  add_bad(P, bad);
 }
 
 // Ghost nodes of the stage result = U^n, as the combination kernel does off the interior.

@@ -317,6 +317,7 @@ __global__ void __launch_bounds__(256) k_sweep_x(const Prob* __restrict__ probs,
   const size_t T = P.total;
   double Fp[5];
   for (int q = 0; q < 5; ++q) Fp[q] = (double)__shfl_up(F[q], 1);
+  int bad = 0;
   if (lane >= 1 && valid) {
     double J = node_J(P, idx);
     double Lq[5];
@@ -326,8 +327,9 @@ __global__ void __launch_bounds__(256) k_sweep_x(const Prob* __restrict__ probs,
       Lq[q] = accumulate ? dQ[o] + v : v;
       if (!rk) dQ[o] = Lq[q];
     }
-    if (rk && rk_combine_node(P, rr, stage, ca, cb, *P.dt, idx, Lq)) atomicAdd(P.status, 1);
+    if (rk && rk_combine_node(P, rr, stage, ca, cb, *P.dt, idx, Lq)) bad = 1;
   }
+  add_bad(P, bad);
 }
 
 // ------------------------------------------------------------------ strided sweeps: one
@@ -374,7 +376,7 @@ __global__ void __launch_bounds__(256) k_sweep_s(const Prob* __restrict__ probs,
     }
     for (int q = 0; q < 5; ++q) Fp[q] = (double)F[q];
   }
-  if (bad) atomicAdd(P.status, bad);
+  add_bad(P, bad);
 }
 
 template <typename R>

@@ -437,6 +437,25 @@ lg_status dispatch(int precision, F&& f) {
 
 }  // namespace
 
+// digital-filter inflow helpers
+namespace {
+// b_i = exp(-pi |i| / n) / sqrt(sum b^2), |i| <= ceil(2 n)
+std::vector<double> df_coef(double n) {
+  n = std::max(n, 1e-12);
+  const int N = (int)std::ceil(2.0 * n);
+  std::vector<double> b(2 * N + 1);
+  double ss = 0.0;
+  for (int i = -N; i <= N; ++i) {
+    b[i + N] = std::exp(-M_PI * std::abs(i) / n);
+    ss += b[i + N] * b[i + N];
+  }
+  const double inv = 1.0 / std::sqrt(ss);
+  for (double& v : b) v *= inv;
+  return b;
+}
+bool pos_finite(double v) { return v > 0.0 && std::isfinite(v); }
+}  // namespace
+
 extern "C" {
 
 lg_status lg_set_allocator(void* (*alloc)(size_t, void*), void (*free_)(void*, void*), void* user) {
@@ -579,7 +598,11 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
   P.dt = scal;
   P.t = scal + 1;
   P.smax = reinterpret_cast<unsigned long long*>(scal + 2);
-  P.status = reinterpret_cast<int*>(scal + 3);
+  P.status = static_cast<int*>(A(lg::STATUS_SLOTS * lg::STATUS_STRIDE * sizeof(int)));
+  if (!ok) {
+    lg_destroy(c);
+    return LG_ENOMEM;
+  }
   P.any_flag = reinterpret_cast<int*>(scal + 4);
   P.lcount = reinterpret_cast<int*>(scal + 5);   // three ints
   P.sw = reinterpret_cast<unsigned*>(scal + 7);   // two counters
@@ -720,9 +743,11 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
     lg_destroy(c);
     return LG_EHIP;
   }
-  // zero the device scalars with a kernel-free synchronous copy (setup only)
+  // zero the device scalars and status slots with kernel-free synchronous copies (setup only)
   double zeros[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  if (hipMemcpy(scal, zeros, sizeof(zeros), hipMemcpyHostToDevice) != hipSuccess) {
+  std::vector<int> zslots(lg::STATUS_SLOTS * lg::STATUS_STRIDE, 0);
+  if (hipMemcpy(scal, zeros, sizeof(zeros), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(P.status, zslots.data(), zslots.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
     lg_destroy(c);
     return LG_EHIP;
   }
@@ -925,8 +950,12 @@ lg_status lg_get_tuning(const lg_ctx* c, int* seg, int* pcr_blocks, int* zc) {
 lg_status lg_poll_status(lg_ctx* c, int* count) {
   if (!c || !count) return LG_EINVAL;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return LG_EHIP;
-  int v = 0;
-  if (hipMemcpy(&v, c->hp.status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return LG_EHIP;
+  std::vector<int> slots(lg::STATUS_SLOTS * lg::STATUS_STRIDE);
+  if (hipMemcpy(slots.data(), c->hp.status, slots.size() * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+    return LG_EHIP;
+  long long sum = 0;
+  for (int i = 0; i < lg::STATUS_SLOTS; ++i) sum += slots[(size_t)i * lg::STATUS_STRIDE];
+  const int v = (int)std::min<long long>(sum, 2147483647LL);
   lg::launch_zero_status(c->L);
   if (hipStreamSynchronize(c->stream) != hipSuccess) return LG_EHIP;
   *count = v;
@@ -948,23 +977,6 @@ void lg_df_destroy(lg_df* f) {
   delete f;
 }
 
-namespace {
-// b_i = exp(-pi |i| / n) / sqrt(sum b^2), |i| <= ceil(2 n)
-std::vector<double> df_coef(double n) {
-  n = std::max(n, 1e-12);
-  const int N = (int)std::ceil(2.0 * n);
-  std::vector<double> b(2 * N + 1);
-  double ss = 0.0;
-  for (int i = -N; i <= N; ++i) {
-    b[i + N] = std::exp(-M_PI * std::abs(i) / n);
-    ss += b[i + N] * b[i + N];
-  }
-  const double inv = 1.0 / std::sqrt(ss);
-  for (double& v : b) v *= inv;
-  return b;
-}
-bool pos_finite(double v) { return v > 0.0 && std::isfinite(v); }
-}  // namespace
 
 lg_status lg_df_create(lg_ctx* c, const lg_df_spec* s, lg_df** out) {
   if (!c || !s || !out) return LG_EINVAL;

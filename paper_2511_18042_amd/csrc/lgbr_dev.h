@@ -81,7 +81,7 @@ struct Prob {
   double* t;
   double t_end;
   unsigned long long* smax;  // max spectral radius (bit pattern of a positive double)
-  int* status;               // non-physical node count
+  int* status;               // non-physical node counts (STATUS_SLOTS slots, see add_bad)
   int* any_flag;             // global hybrid switch: any troubled interior node
   unsigned* sw;              // switching record: [0] hybrid stages, [1] those with a troubled node
 };
@@ -194,6 +194,15 @@ __device__ __forceinline__ bool zm_column(const Prob& P, int lo, int hi, int zc,
   c.k0 = org[2] + k0;
   c.k1 = org[2] + k1;
   return true;
+}
+
+// Non-physical node counts: STATUS_SLOTS counters STATUS_STRIDE ints (one 128-byte line)
+// apart, workgroup b adding to slot b mod STATUS_SLOTS (an address uniform in the wave).
+// One shared counter serialises when a whole field goes bad (every wave adding to one
+// address); the host sums the slots.
+constexpr int STATUS_SLOTS = 64, STATUS_STRIDE = 32;
+__device__ __forceinline__ void add_bad(const Prob& P, int bad) {
+  if (bad) atomicAdd(P.status + STATUS_STRIDE * (blockIdx.x & (STATUS_SLOTS - 1)), bad);
 }
 
 // Reciprocal in the bulk arithmetic: the hardware estimate (within 1 ulp) in FP32, the
