@@ -192,6 +192,28 @@ def profiled_traffic(path, kclass):
     return None, 'no counters for this kernel'
 
 
+def profiled_step(path):
+    """Whole-step HBM bytes and VALU-busy % of the workload from a committed counter summary
+    (its STEP line: every kernel of a step, FETCH_SIZE and WRITE_SIZE scaled by the copy of
+    known size), or (None, reason) once any library source no longer hashes to what was
+    profiled."""
+    import hashlib
+    if not os.path.exists(path):
+        return None, 'no profile'
+    for line in open(path):
+        f = line.split()
+        if len(f) < 2 or f[0] != 'STEP':
+            continue
+        kv = dict(x.split('=', 1) for x in f[1:])
+        h = hashlib.sha256()
+        for src in kv['sources'].split(','):
+            h.update(open(os.path.join(ROOT, src), 'rb').read())
+        if h.hexdigest() != kv['sha256']:
+            return None, 'library sources changed since the counters were taken'
+        return {'bytes_per_step': int(float(kv['bytes_per_step'])), 'valu_busy_pct': float(kv['valu_busy_pct'])}, ''
+    return None, 'no STEP line'
+
+
 def flags_of(ctx, Q):
     import torch
     fl = torch.zeros(tuple(Q.shape[1:]), dtype=torch.uint8, device='cuda')
@@ -232,6 +254,15 @@ def ramp3d(args, variants, cpu):
     del Q
     roof, brk = R.roofline(head, 'hybrid', Q0, cells, 3, gbr_frac, True, True,
                            traffic_file=os.path.join(ROOT, 'profiles', 'ramp3d_hybrid_mig4_mixed_hbm_traffic.txt'))
+    prof = os.path.join(ROOT, 'profiles', 'ramp3d_hybrid_mig4_mixed_hbm_traffic.txt')
+    st, why = profiled_step(prof)
+    if st:   # SURVEY-style whole-step figure: all kernels' HBM bytes over the measured step time
+        gbs = st['bytes_per_step'] / (ms * 1e-3) / 1e9
+        res['hbm_step'] = {'bytes_per_step': st['bytes_per_step'], 'achieved': round(gbs, 1), 'unit': 'GB/s',
+                           'frac_of_peak': round(gbs / HBM_PEAK_GBS, 4), 'valu_busy_pct': st['valu_busy_pct'],
+                           'source': os.path.relpath(prof, ROOT)}
+    else:
+        res['hbm_step'] = {'source': os.path.relpath(prof, ROOT) + ' (%s)' % why}
     res.update({'value': mcell(cells, ms), 'ms_per_step': round(ms, 4), 'nonphysical_nodes': bad,
                 'sim_time_end': round(t_end, 6), 'troubled_interface_fraction': round(gbr_frac, 5),
                 'roofline': roof, 'kernel_breakdown_ms_per_step': brk})
@@ -585,6 +616,7 @@ def main():
         'data': 'synthetic: seeded generator states',
         'config': {'workload': head['workload'], 'cells': head['cells'], 'parallelism': 'single GPU'},
         'roofline': head.get('roofline'),
+        'hbm_step': head.get('hbm_step'),
         'cpu_baseline': head.get('cpu_baseline'),
         'nonphysical_nodes': head.get('nonphysical_nodes'),
         'workloads': results,
