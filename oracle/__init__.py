@@ -20,16 +20,17 @@ computes, in float64, step by step in the paper's order:
 * ``lad``          -- localized artificial diffusivity coefficients, truncated
                       Gaussian filter, central convective + viscous fluxes in
                       E4 or compact C6 flux form (Sec. 2.2, Eq. tauij)
-* ``implicit_filter`` -- the implicit Pade-type filter of LAD-C6 steps (Sec. 2.1,
-                      Alg. 1 FILTER_CALLS)
+* ``implicit_filter`` -- the implicit Pade-type filter of LAD-C6 steps (Sec. 2.1;
+                      where Alg. 1 applies it)
 * ``rhs``          -- the three RHS forms (C-GBR, LAD, hybrid; Alg. 1-3), the
                       CFL time step and SSP-RK3
 * ``riemann``      -- exact Riemann solver for the 1D shock-tube checks (Sec. 3.1)
+* ``inflow``       -- digital-filter inflow turbulence of the 3D cases (Sec. 4)
 
-Where the paper is silent the oracle follows the numbered readings R1..R29 that
-are listed in the design notes; each function names the reading it relies on.
+Where the paper is silent the oracle follows the numbered readings R1..R34 that
+are listed with the design; each function names the reading it relies on.
 
 Parity pins: every function is pinned by a ``-m "not gpu"`` test against a
 closed form, an invariant, brute force or a textbook value (tests/test_oracle_*.py).
 """
-from . import grid, derivatives, gbr, lad, implicit_filter, rhs, riemann  # noqa: F401
+from . import grid, derivatives, gbr, lad, implicit_filter, rhs, riemann, inflow  # noqa: F401
