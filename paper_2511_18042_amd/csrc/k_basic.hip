@@ -198,29 +198,35 @@ __global__ void k_zero_lcount(const Prob* __restrict__ probs) {
 // ------------------------------------------------------------------ CFL time step
 // Spectral radius sum_l (|xi_l . u| + c |xi_l|) with xi_l = J l_hat, max over the
 // interior; kept as the bit pattern of a positive double so that an integer max works.
-__global__ void __launch_bounds__(256) k_dt_reduce(const Prob* __restrict__ probs, const double* Qx) {
+__global__ void __launch_bounds__(256) k_dt_reduce(const Prob* __restrict__ probs, const double* Qx, int zc) {
   const Prob& P = probs[blockIdx.y];
   const double* Q = Qx ? Qx : P.Q;
   const size_t T = P.total;
-  const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
-  const int cnt = n0 * n1 * n2;
   double smax = 0.0;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x) {
-    int i = t % n0, r = t / n0;
-    int j = r % n1, k = r / n1;
-    int idx = pos_to_idx(P, i + P.g[0], j + P.g[1], k + P.g[2]);
-    double rho = Q[idx], ri = 1.0 / rho;
-    double u = Q[T + idx] * ri, v = Q[2 * T + idx] * ri, w = Q[3 * T + idx] * ri;
-    double p = (P.gamma - 1.0) * (Q[4 * T + idx] - 0.5 * rho * (u * u + v * v + w * w));
-    double c = sqrt(P.gamma * p * ri);
-    double J = met64(P, 9, idx);
-    double s = 0.0;
-    for (int l = 0; l < P.ndim; ++l) {
-      double x0 = J * met64(P, 3 * l, idx), x1 = J * met64(P, 3 * l + 1, idx),
-             x2 = J * met64(P, 3 * l + 2, idx);
-      s += fabs(x0 * u + x1 * v + x2 * w) + c * sqrt(x0 * x0 + x1 * x1 + x2 * x2);
+  // z-marching columns: the metrics of a grid planar along zeta are read once per column
+  ZCol c;
+  if (zm_column(P, 0, 0, zc, c)) {
+    const int sz = P.s[2];
+    int idx = pos_to_idx(P, c.i, c.j, c.k0);
+    const bool mplane = P.met_planar || !P.curvilinear;
+    double m[10];
+    if (mplane)
+      for (int q = 0; q < 10; ++q) m[q] = met64(P, q, idx);
+    for (int k = c.k0; k < c.k1; ++k, idx += sz) {
+      if (!mplane)
+        for (int q = 0; q < 10; ++q) m[q] = met64(P, q, idx);
+      double rho = Q[idx], ri = 1.0 / rho;
+      double u = Q[T + idx] * ri, v = Q[2 * T + idx] * ri, w = Q[3 * T + idx] * ri;
+      double p = (P.gamma - 1.0) * (Q[4 * T + idx] - 0.5 * rho * (u * u + v * v + w * w));
+      double cs = sqrt(P.gamma * p * ri);
+      double J = m[9];
+      double s = 0.0;
+      for (int l = 0; l < P.ndim; ++l) {
+        double x0 = J * m[3 * l], x1 = J * m[3 * l + 1], x2 = J * m[3 * l + 2];
+        s += fabs(x0 * u + x1 * v + x2 * w) + cs * sqrt(x0 * x0 + x1 * x1 + x2 * x2);
+      }
+      if (!(s <= smax)) smax = s;  // NaN propagates as "larger"
     }
-    if (!(s <= smax)) smax = s;  // NaN propagates as "larger"
   }
   // wave, then block reduction; one atomic per block
   for (int off = 32; off > 0; off >>= 1) {
@@ -456,8 +462,8 @@ void launch_line_lists(const Launch& L, int ndim) {
 
 void launch_dt(const Launch& L, const double* Qx, double* tx, double t_end, int advance_t) {
   hipLaunchKernelGGL(k_dt_reset, dim3(1, L.nprob), dim3(64), 0, L.stream, L.probs);
-  LG_TIMED(L, KC_DT, hipLaunchKernelGGL(k_dt_reduce, grid_for(L.max_cells, L.nprob, 256, 8192), dim3(256), 0,
-                                        L.stream, L.probs, Qx));
+  LG_TIMED(L, KC_DT, hipLaunchKernelGGL(k_dt_reduce, zm_grid(L, 0, 0, ZM_TX, ZM_TY), dim3(256), 0, L.stream,
+                                        L.probs, Qx, zm_chunk(L, 0, 0)));
   hipLaunchKernelGGL(k_dt_finalize, dim3(1, L.nprob), dim3(64), 0, L.stream, L.probs, tx, t_end, advance_t);
 }
 

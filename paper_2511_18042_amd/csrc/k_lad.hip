@@ -21,37 +21,12 @@
 // beforehand (k_compact.hip), and its interface fluxes are tridiagonal solves there.
 // Fourth differences use five points; all derivatives use unit computational spacing.
 #include "lgbr_dev.h"
-#include <type_traits>
-
 #include "lgbr_kernels.h"
 
 namespace lg {
 
 __device__ __forceinline__ bool lad_skip(const Prob& P, int skip_if_any) {
   return skip_if_any >= 0 && P.any_flag && (*P.any_flag != 0) == (skip_if_any != 0);
-}
-
-// Fields addressed as global memory (the descriptor's pointers are otherwise generic) by
-// 32-bit element offsets from a scalar base when O32 (every field below 2^32 bytes; chosen
-// on the host): per-lane addresses then take one register instead of two, and the loads
-// wait on the vector-memory counter only.
-#define LG_GLOBAL __attribute__((address_space(1)))
-template <bool O32>
-using sidx_t = typename std::conditional<O32, unsigned, size_t>::type;
-
-template <typename T, bool O32>
-__device__ __forceinline__ T gld(const T* base, sidx_t<O32> e) {
-  if constexpr (O32)
-    return *(const LG_GLOBAL T*)((const LG_GLOBAL char*)base + e * (unsigned)sizeof(T));
-  else
-    return base[e];
-}
-template <typename T, bool O32>
-__device__ __forceinline__ void gst(T* base, sidx_t<O32> e, T v) {
-  if constexpr (O32)
-    *(LG_GLOBAL T*)((LG_GLOBAL char*)base + e * (unsigned)sizeof(T)) = v;
-  else
-    base[e] = v;
 }
 
 template <typename R>
@@ -757,7 +732,7 @@ template <typename R>
 void launch_lad_nodeflux(const Launch& L, int skip_if_any, int cg) {
   const dim3 grid = zm_grid(L, -2, 2, ZM_TX, ZM_TY);
   const int zb = zm_chunk(L, -2, 2);
-  const bool o32 = sizeof(R) == 4 && L.sweep_o32;
+  const bool o32 = sizeof(R) == 4 && !L.o64;
   if (cg && o32)
     LG_TIMED(L, KC_LAD_FLUX, hipLaunchKernelGGL((k_lad_nodeflux<R, true, true>), grid, dim3(256), 0, L.stream,
                                                 L.probs, lad_coef_buf(L), skip_if_any, zb));
@@ -783,7 +758,7 @@ void launch_lad_sweep(const Launch& L, StateRef ref, const RKRef* rr, int stage,
   const dim3 grid = zm_grid(L, 0, 0, ZM_TX, ZM_TY);
   // FP32 fluxes: 115 registers with 32-bit offsets (4 waves per SIMD), 7 % faster on the
   // ramp; FP64 needs 164 that way (3 waves) and runs faster with generic addressing
-  if (sizeof(R) == 4 && L.sweep_o32)
+  if (sizeof(R) == 4 && !L.o64)
     LG_TIMED(L, KC_LAD_SWEEP, hipLaunchKernelGGL((k_lad_sweep<R, true>), grid, dim3(256), 0, L.stream, L.probs, ref,
                                                  r, rr ? 1 : 0, stage, a, b, skip_if_any, zm_chunk(L, 0, 0)));
   else

@@ -9,6 +9,8 @@
 // float for the mixed path).
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <stdint.h>
 
 namespace lg {
@@ -194,6 +196,29 @@ __device__ __forceinline__ bool zm_column(const Prob& P, int lo, int hi, int zc,
   c.k0 = org[2] + k0;
   c.k1 = org[2] + k1;
   return true;
+}
+
+// Fields addressed as global memory (the descriptor's pointers are otherwise generic) by
+// 32-bit element offsets from a scalar base when O32 (every field below 2^32 bytes; chosen
+// on the host): per-lane addresses then take one register instead of two, and the loads
+// wait on the vector-memory counter only.
+#define LG_GLOBAL __attribute__((address_space(1)))
+template <bool O32>
+using sidx_t = typename std::conditional<O32, unsigned, size_t>::type;
+
+template <typename T, bool O32>
+__device__ __forceinline__ T gld(const T* base, sidx_t<O32> e) {
+  if constexpr (O32)
+    return *(const LG_GLOBAL T*)((const LG_GLOBAL char*)base + e * (unsigned)sizeof(T));
+  else
+    return base[e];
+}
+template <typename T, bool O32>
+__device__ __forceinline__ void gst(T* base, sidx_t<O32> e, T v) {
+  if constexpr (O32)
+    *(LG_GLOBAL T*)((LG_GLOBAL char*)base + e * (unsigned)sizeof(T)) = v;
+  else
+    base[e] = v;
 }
 
 // Non-physical node counts: STATUS_SLOTS counters STATUS_STRIDE ints (one 128-byte line)

@@ -78,8 +78,7 @@ struct Launch {
   long long sweep_rows[3]; // interior lines (interior of the other two dims) per direction
   int has_short_periodic;  // some periodic direction has fewer than 128 interior nodes
   int has_fixed;           // some problem has a FIXED face (caller-owned ghosts)
-  int sweep_o64;           // some problem's fields need 64-bit offsets (5 FP64 planes >= 2^32 B)
-  int sweep_o32;           // every problem's fields take 32-bit offsets (!sweep_o64)
+  int o64;                 // some problem's fields need 64-bit offsets (5 FP64 planes >= 2^32 B)
   int pcr_dir[3];          // some problem solves its lines along d by PCR
   int thomas_dir[3];       // some problem solves its lines along d one lane per line
   // LAD-C6 line systems [TK_*][d]: which kernels some problem needs (tile_use with this
