@@ -117,16 +117,14 @@ __global__ void __launch_bounds__(256) k_prim(const Prob* __restrict__ probs, St
 }
 
 // ------------------------------------------------------------------ global hybrid switch
-__global__ void __launch_bounds__(256) k_any_flag(const Prob* __restrict__ probs, int interior_only) {
+__global__ void __launch_bounds__(256) k_any_flag(const Prob* __restrict__ probs, int interior_only, int zc) {
   const Prob& P = probs[blockIdx.y];
   int found = 0;
-  if (interior_only) {
-    const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
-    const int cnt = n0 * n1 * n2;
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x) {
-      int i = t % n0, r = t / n0;
-      int j = r % n1, k = r / n1;
-      if (P.f[pos_to_idx(P, i + P.g[0], j + P.g[1], k + P.g[2])]) found = 1;
+  if (interior_only) {   // z-marching columns of the interior (launched with zm_grid)
+    ZCol c;
+    if (zm_column(P, 0, 0, zc, c)) {
+      int idx = pos_to_idx(P, c.i, c.j, c.k0);
+      for (int k = c.k0; k < c.k1; ++k, idx += P.s[2]) found |= P.f[idx];
     }
   } else {
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < P.total; t += gridDim.x * blockDim.x)
@@ -436,8 +434,9 @@ void launch_prim(const Launch& L, StateRef ref, int want_flags, const uint8_t* f
 
 void launch_any_flag(const Launch& L, int interior_only) {
   hipLaunchKernelGGL(k_zero_any, dim3(1, L.nprob), dim3(64), 0, L.stream, L.probs);
-  LG_TIMED(L, KC_FLAGS, hipLaunchKernelGGL(k_any_flag, grid_for(interior_only ? L.max_cells : L.max_total, L.nprob),
-                                           dim3(256), 0, L.stream, L.probs, interior_only));
+  const dim3 grid = interior_only ? zm_grid(L, 0, 0, ZM_TX, ZM_TY) : grid_for(L.max_total, L.nprob);
+  LG_TIMED(L, KC_FLAGS, hipLaunchKernelGGL(k_any_flag, grid, dim3(256), 0, L.stream, L.probs, interior_only,
+                                           zm_chunk(L, 0, 0)));
 }
 
 void launch_dilate(const Launch& L, int ndim, int radius, int first_src, int final_buf) {

@@ -667,6 +667,36 @@ __global__ void __launch_bounds__(256) k_stage_ghosts(const Prob* __restrict__ p
   }
 }
 
+// The ghost layers of the FIXED faces along d (all positions of the other directions):
+// the only ghosts a stage inside rk3_step must carry over from U^n.
+// (rr.out null: the stage's own result buffer.)
+__global__ void __launch_bounds__(256) k_fixed_ghosts(const Prob* __restrict__ probs, RKRef rr, int stage,
+                                                      int skip_if_any, int d) {
+  const Prob& P = probs[blockIdx.y];
+  if (lad_skip(P, skip_if_any) || d >= P.ndim) return;
+  const double* Un = rr.Un ? rr.Un : P.Q;
+  double* out = stage == 2 ? const_cast<double*>(Un) : P.Us;
+  if (out == Un) return;
+  const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+  const int g = P.g[d], n1 = P.N[o1], n2 = P.N[o2];
+  const long long slab = (long long)g * n1 * n2;
+  const size_t T = P.total;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < 2 * slab;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int side = t >= slab;
+    if (P.bc[d][side] != BC_FIXED) continue;
+    const long long r = t - side * slab;
+    const int a = (int)(r % g), b = (int)((r / g) % n1), c = (int)(r / ((long long)g * n1));
+    const int pd = side ? g + P.n[d] + a : a;
+    int pos[3];
+    pos[d] = pd;
+    pos[o1] = b;
+    pos[o2] = c;
+    const size_t idx = (size_t)pos[0] * P.s[0] + (size_t)pos[1] * P.s[1] + (size_t)pos[2] * P.s[2];
+    for (int q = 0; q < 5; ++q) out[q * T + idx] = Un[q * T + idx];
+  }
+}
+
 // C-GBR viscous node fluxes (physical coefficients, the scheme's gradients)
 template <typename R>
 __global__ void __launch_bounds__(256) k_gbr_viscflux(const Prob* __restrict__ probs, int skip_if_any, int region) {
@@ -768,9 +798,15 @@ void launch_lad_sweep(const Launch& L, StateRef ref, const RKRef* rr, int stage,
 }
 
 void launch_stage_ghosts(const Launch& L, const RKRef& rr, int stage, int skip_if_any) {
-  if (!rr.out && !L.has_fixed) return;
-  LG_TIMED(L, KC_COMBINE, hipLaunchKernelGGL(k_stage_ghosts, g1(L.max_total, L.nprob), dim3(256), 0, L.stream,
-                                             L.probs, rr, stage, skip_if_any));
+  if (rr.out) {   // an explicit output: every ghost of the result
+    LG_TIMED(L, KC_COMBINE, hipLaunchKernelGGL(k_stage_ghosts, g1(L.max_total, L.nprob), dim3(256), 0, L.stream,
+                                               L.probs, rr, stage, skip_if_any));
+    return;
+  }
+  if (!L.has_fixed) return;
+  for (int d = 0; d < L.ndim; ++d)   // the FIXED faces' layers only
+    LG_TIMED(L, KC_COMBINE, hipLaunchKernelGGL(k_fixed_ghosts, g1(L.ghost_work[d], L.nprob), dim3(256), 0, L.stream,
+                                               L.probs, rr, stage, skip_if_any, d));
 }
 
 template <typename R>
