@@ -36,16 +36,30 @@ __device__ __forceinline__ R e4_at(const R* f, int idx, int s) {
 
 // physical gradients D[q][j] of the 5 primitives at node idx from computational
 // derivatives gl[l][q] (l < ndim)
-template <typename R>
+// Direction loops run over the three directions with a uniform exit, so that every
+// register array index is a constant (a runtime bound indexes registers indirectly).  The
+// shear kernel keeps the runtime bound (UNROLL false): it is faster that way.
+template <typename R, bool UNROLL = true>
 __device__ __forceinline__ void to_physical(int ndim, const R mt[10], const R gl[3][5], R D[5][3]) {
   R J = mt[9];
   for (int q = 0; q < 5; ++q)
     for (int j = 0; j < 3; ++j) D[q][j] = R(0);
-  for (int l = 0; l < ndim; ++l)
-    for (int j = 0; j < 3; ++j) {
-      R m = J * mt[3 * l + j];
-      for (int q = 0; q < 5; ++q) D[q][j] += m * gl[l][q];
+  if constexpr (UNROLL) {
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      if (l >= ndim) break;
+      for (int j = 0; j < 3; ++j) {
+        R m = J * mt[3 * l + j];
+        for (int q = 0; q < 5; ++q) D[q][j] += m * gl[l][q];
+      }
     }
+  } else {
+    for (int l = 0; l < ndim; ++l)
+      for (int j = 0; j < 3; ++j) {
+        R m = J * mt[3 * l + j];
+        for (int q = 0; q < 5; ++q) D[q][j] += m * gl[l][q];
+      }
+  }
 }
 
 // Sutherland viscosity and conductivity from rho, p (ri = 1 / rho)
@@ -90,8 +104,9 @@ __device__ __forceinline__ void viscous_flux(const Prob& P, R m0, R m1, R m2, co
 
 __device__ __forceinline__ bool in_band(const Prob& P, int idx, int lo, int hi) {
   int p[3] = {idx % P.N[0], (idx / P.N[0]) % P.N[1], idx / (P.N[0] * P.N[1])};
-  for (int l = 0; l < P.ndim; ++l)
-    if (p[l] < P.g[l] + lo || p[l] >= P.g[l] + P.n[l] + hi) return false;
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+    if (l < P.ndim && (p[l] < P.g[l] + lo || p[l] >= P.g[l] + P.n[l] + hi)) return false;
   return true;
 }
 
@@ -205,7 +220,7 @@ k_lad_shear(const Prob* __restrict__ probs, int skip_if_any, int zc) {
     R gl[3][5], D[5][3];
     if (CG) stored_grads(P, idx, gl);
     else e4_grads_zm(P, W, idx, qz, gl);
-    to_physical(P.ndim, mt, gl, D);
+    to_physical<R, false>(P.ndim, mt, gl, D);
     R S2 = R(0);
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) {
@@ -281,7 +296,9 @@ __global__ void __launch_bounds__(256) k_lad_raw(const Prob* __restrict__ probs,
     R cs = sqrt(R(P.gamma) * p * ri);
     R fsw = theta < R(0) ? theta * theta * rcp(theta * theta + om2 + R(1e-32)) : R(0);
     R smu = R(0), sbeta = R(0), skap = R(0);
-    for (int l = 0; l < P.ndim; ++l) {
+    #pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      if (l >= P.ndim) break;
       R dx[3];
       if (P.curvilinear) {
         for (int cc = 0; cc < 3; ++cc) dx[cc] = gx[3 * l + cc];
@@ -490,18 +507,17 @@ __device__ __forceinline__ void lad_node_flux(const Prob& P, const LadNode<R>& s
 }
 
 // F^c + F^v for every active direction at positions -2 .. n+1; gradients recomputed from
-// W (CG: stored gradients), coefficients read at the image of the node; O32 as in gld
-template <typename R, bool CG, bool O32>
+// W (CG: stored gradients), coefficients read at the image of the node
+template <typename R, bool CG>
 __global__ void __launch_bounds__(256) k_lad_nodeflux(const Prob* __restrict__ probs, int coef_buf, int skip_if_any,
                                                       int zc) {
-  using IX = sidx_t<O32>;
   const Prob& P = probs[blockIdx.y];
   if (lad_skip(P, skip_if_any)) return;
   ZCol c;
   if (!zm_column(P, -2, 2, zc, c)) return;
   const R* W = static_cast<const R*>(P.W);
   const R* C = static_cast<const R*>(coef_buf == 0 ? P.CA : P.CB);
-  const IX T = (IX)P.total;
+  const size_t T = P.total;
   const int sz = P.s[2];
   const bool z3 = P.ndim == 3;
   const bool zq = z3 && !CG;
@@ -511,7 +527,7 @@ __global__ void __launch_bounds__(256) k_lad_nodeflux(const Prob* __restrict__ p
   R qz[5][5];   // planes k-2 .. k+2 of the primitives
   if (zq)
     for (int p = 1; p < 5; ++p)
-      for (int q = 0; q < 5; ++q) qz[p][q] = gld<R, O32>(W, (IX)q * T + (IX)(idx + (p - 3) * sz));
+      for (int q = 0; q < 5; ++q) qz[p][q] = W[q * T + idx + (p - 3) * sz];
   R mt[10];
   const bool mplane = P.met_planar;
   if (mplane) load_met(P, idx, mt);   // one plane of metrics serves the whole column
@@ -519,36 +535,39 @@ __global__ void __launch_bounds__(256) k_lad_nodeflux(const Prob* __restrict__ p
     if (zq) {
       for (int p = 0; p < 4; ++p)
         for (int q = 0; q < 5; ++q) qz[p][q] = qz[p + 1][q];
-      for (int q = 0; q < 5; ++q) qz[4][q] = gld<R, O32>(W, (IX)q * T + (IX)(idx + 2 * sz));
+      for (int q = 0; q < 5; ++q) qz[4][q] = W[q * T + idx + 2 * sz];
     }
     if (!mplane) load_met(P, idx, mt);
     R gl[3][5], w[5];
     for (int l = 0; l < 3; ++l)
       for (int q = 0; q < 5; ++q) gl[l][q] = R(0);
     for (int q = 0; q < 5; ++q) {
-      const IX o = (IX)q * T + (IX)idx;
-      w[q] = zq ? qz[2][q] : gld<R, O32>(W, o);
+      const size_t o = q * T + idx;
+      w[q] = zq ? qz[2][q] : W[o];
       if (CG) {
-        for (int l = 0; l < P.ndim; ++l) gl[l][q] = gld<R, O32>(static_cast<const R*>(P.G[l]), o);
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+          if (l < P.ndim) gl[l][q] = static_cast<const R*>(P.G[l])[o];
       } else {
-        gl[0][q] = e4v(gld<R, O32>(W, o - 2), gld<R, O32>(W, o - 1), gld<R, O32>(W, o + 1), gld<R, O32>(W, o + 2));
+        gl[0][q] = e4v(W[o - 2], W[o - 1], W[o + 1], W[o + 2]);
         if (P.ndim > 1) {
-          const IX s1 = (IX)P.s[1];
-          gl[1][q] = e4v(gld<R, O32>(W, o - 2 * s1), gld<R, O32>(W, o - s1), gld<R, O32>(W, o + s1),
-                         gld<R, O32>(W, o + 2 * s1));
+          const size_t s1 = P.s[1];
+          gl[1][q] = e4v(W[o - 2 * s1], W[o - s1], W[o + s1], W[o + 2 * s1]);
         }
         if (z3) gl[2][q] = e4v(qz[0][q], qz[1][q], qz[3][q], qz[4][q]);
       }
     }
-    const IX cidx = (IX)pos_to_idx(P, ci, cj, z3 ? scalar_image(P, 2, k) : k);
-    const R cf[3] = {gld<R, O32>(C, cidx), gld<R, O32>(C, T + cidx), gld<R, O32>(C, 2 * T + cidx)};
+    const size_t cidx = pos_to_idx(P, ci, cj, z3 ? scalar_image(P, 2, k) : k);
+    const R cf[3] = {C[cidx], C[T + cidx], C[2 * T + cidx]};
     LadNode<R> s;
     lad_node_state(P, w, cf, mt, gl, s);
-    for (int l = 0; l < P.ndim; ++l) {
+    #pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      if (l >= P.ndim) break;
       R F[5];
       lad_node_flux(P, s, mt, l, F);
       R* out = static_cast<R*>(P.FL[l]);
-      for (int q = 0; q < 5; ++q) gst<R, O32>(out, (IX)q * T + (IX)idx, F[q]);
+      for (int q = 0; q < 5; ++q) out[q * T + idx] = F[q];
     }
   }
 }
@@ -717,7 +736,9 @@ __global__ void __launch_bounds__(256) k_gbr_viscflux(const Prob* __restrict__ p
     const R ri = rcp(w[0]);
     R mu, kappa;
     transport(P, ri, w[4], mu, kappa);
-    for (int l = 0; l < P.ndim; ++l) {
+    #pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      if (l >= P.ndim) break;
       R F[5];
       viscous_flux(P, mt[3 * l], mt[3 * l + 1], mt[3 * l + 2], w, ri, D, mu, R(0), kappa, F);
       R* out = static_cast<R*>(P.FV[l]);
@@ -762,19 +783,12 @@ template <typename R>
 void launch_lad_nodeflux(const Launch& L, int skip_if_any, int cg) {
   const dim3 grid = zm_grid(L, -2, 2, ZM_TX, ZM_TY);
   const int zb = zm_chunk(L, -2, 2);
-  const bool o32 = sizeof(R) == 4 && !L.o64;
-  if (cg && o32)
-    LG_TIMED(L, KC_LAD_FLUX, hipLaunchKernelGGL((k_lad_nodeflux<R, true, true>), grid, dim3(256), 0, L.stream,
-                                                L.probs, lad_coef_buf(L), skip_if_any, zb));
-  else if (cg)
-    LG_TIMED(L, KC_LAD_FLUX, hipLaunchKernelGGL((k_lad_nodeflux<R, true, false>), grid, dim3(256), 0, L.stream,
-                                                L.probs, lad_coef_buf(L), skip_if_any, zb));
-  else if (o32)
-    LG_TIMED(L, KC_LAD_FLUX, hipLaunchKernelGGL((k_lad_nodeflux<R, false, true>), grid, dim3(256), 0, L.stream,
-                                                L.probs, lad_coef_buf(L), skip_if_any, zb));
+  if (cg)
+    LG_TIMED(L, KC_LAD_FLUX, hipLaunchKernelGGL((k_lad_nodeflux<R, true>), grid, dim3(256), 0, L.stream, L.probs,
+                                                lad_coef_buf(L), skip_if_any, zb));
   else
-    LG_TIMED(L, KC_LAD_FLUX, hipLaunchKernelGGL((k_lad_nodeflux<R, false, false>), grid, dim3(256), 0, L.stream,
-                                                L.probs, lad_coef_buf(L), skip_if_any, zb));
+    LG_TIMED(L, KC_LAD_FLUX, hipLaunchKernelGGL((k_lad_nodeflux<R, false>), grid, dim3(256), 0, L.stream, L.probs,
+                                                lad_coef_buf(L), skip_if_any, zb));
 }
 
 template <typename R>
