@@ -94,24 +94,69 @@ __global__ void __launch_bounds__(256) k_bc_scalar(const Prob* __restrict__ prob
 
 // ------------------------------------------------------------------ primitives + flags
 template <typename R>
+__device__ __forceinline__ void prim_node(const Prob& P, double rho, double m1, double m2, double m3, double E,
+                                          R& r0, R& r1, R& r2, R& r3, R& r4, double& p) {
+  double u = m1 / rho, v = m2 / rho, w = m3 / rho;
+  p = (P.gamma - 1.0) * (E - 0.5 * rho * (u * u + v * v + w * w));
+  r0 = (R)rho;
+  r1 = (R)u;
+  r2 = (R)v;
+  r3 = (R)w;
+  r4 = (R)p;
+}
+
+// PAIR: each lane converts two neighbouring nodes (2t, 2t + 1) with 16-byte state loads and
+// 8-byte (FP32) primitive stores; needs an even node count and 16-byte aligned state
+// (checked on the host).  Otherwise one node per lane.
+template <typename R, bool PAIR>
 __global__ void __launch_bounds__(256) k_prim(const Prob* __restrict__ probs, StateRef ref, int want_flags,
                                               const uint8_t* force) {
   const Prob& P = probs[blockIdx.y];
   const double* Q = ref.state(P);
   R* W = static_cast<R*>(P.W);
   const size_t T = P.total;
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < P.total; idx += gridDim.x * blockDim.x) {
-    double rho = Q[idx];
-    double u = Q[T + idx] / rho, v = Q[2 * T + idx] / rho, w = Q[3 * T + idx] / rho;
-    double p = (P.gamma - 1.0) * (Q[4 * T + idx] - 0.5 * rho * (u * u + v * v + w * w));
-    W[idx] = (R)rho;
-    W[T + idx] = (R)u;
-    W[2 * T + idx] = (R)v;
-    W[3 * T + idx] = (R)w;
-    W[4 * T + idx] = (R)p;
-    if (want_flags) {
-      uint8_t f = force ? (uint8_t)(force[idx] != 0) : (uint8_t)((rho < P.rho_thr) || (p < P.p_thr));
-      P.f[idx] = f;
+  if constexpr (PAIR) {
+    using D2 = double __attribute__((ext_vector_type(2)));
+    using R2 = R __attribute__((ext_vector_type(2)));
+    const int npair = (int)(T / 2);
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < npair; t += gridDim.x * blockDim.x) {
+      const size_t idx = 2 * (size_t)t;
+      D2 q[5];
+      for (int c = 0; c < 5; ++c) q[c] = *reinterpret_cast<const D2*>(Q + c * T + idx);
+      R ra[5], rb[5];
+      double pa, pb;
+      prim_node<R>(P, q[0].x, q[1].x, q[2].x, q[3].x, q[4].x, ra[0], ra[1], ra[2], ra[3], ra[4], pa);
+      prim_node<R>(P, q[0].y, q[1].y, q[2].y, q[3].y, q[4].y, rb[0], rb[1], rb[2], rb[3], rb[4], pb);
+      for (int c = 0; c < 5; ++c) {
+        R2 o;
+        o.x = ra[c];
+        o.y = rb[c];
+        *reinterpret_cast<R2*>(W + c * T + idx) = o;
+      }
+      if (want_flags) {
+        uint8_t fa, fb;
+        if (force) {
+          fa = (uint8_t)(force[idx] != 0);
+          fb = (uint8_t)(force[idx + 1] != 0);
+        } else {
+          fa = (uint8_t)((q[0].x < P.rho_thr) || (pa < P.p_thr));
+          fb = (uint8_t)((q[0].y < P.rho_thr) || (pb < P.p_thr));
+        }
+        P.f[idx] = fa;
+        P.f[idx + 1] = fb;
+      }
+    }
+  } else {
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < P.total; idx += gridDim.x * blockDim.x) {
+      double p;
+      R r[5];
+      prim_node<R>(P, Q[idx], Q[T + idx], Q[2 * T + idx], Q[3 * T + idx], Q[4 * T + idx], r[0], r[1], r[2], r[3],
+                   r[4], p);
+      for (int c = 0; c < 5; ++c) W[c * T + idx] = r[c];
+      if (want_flags) {
+        uint8_t f = force ? (uint8_t)(force[idx] != 0) : (uint8_t)((Q[idx] < P.rho_thr) || (p < P.p_thr));
+        P.f[idx] = f;
+      }
     }
   }
 }
@@ -219,7 +264,9 @@ __global__ void __launch_bounds__(256) k_dt_reduce(const Prob* __restrict__ prob
       double cs = sqrt(P.gamma * p * ri);
       double J = m[9];
       double s = 0.0;
-      for (int l = 0; l < P.ndim; ++l) {
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {   // constant register indices (uniform exit)
+        if (l >= P.ndim) break;
         double x0 = J * m[3 * l], x1 = J * m[3 * l + 1], x2 = J * m[3 * l + 2];
         s += fabs(x0 * u + x1 * v + x2 * w) + cs * sqrt(x0 * x0 + x1 * x1 + x2 * x2);
       }
@@ -428,8 +475,13 @@ void launch_bc_scalar(const Launch& L, int which, int nf, int d) {
 
 template <typename R>
 void launch_prim(const Launch& L, StateRef ref, int want_flags, const uint8_t* force) {
-  LG_TIMED(L, KC_PRIM, hipLaunchKernelGGL(k_prim<R>, grid_for(L.max_total, L.nprob), dim3(256), 0, L.stream,
-                                          L.probs, ref, want_flags, force));
+  // pairs pay off with FP32 primitives (0.80 -> 0.78 ms on the ramp); FP64 runs faster one node per lane
+  if (sizeof(R) == 4 && !L.prim_scalar && (unsigned long long)ref.Qx % 16 == 0)
+    LG_TIMED(L, KC_PRIM, hipLaunchKernelGGL((k_prim<R, true>), grid_for(L.max_total / 2, L.nprob), dim3(256), 0,
+                                            L.stream, L.probs, ref, want_flags, force));
+  else
+    LG_TIMED(L, KC_PRIM, hipLaunchKernelGGL((k_prim<R, false>), grid_for(L.max_total, L.nprob), dim3(256), 0,
+                                            L.stream, L.probs, ref, want_flags, force));
 }
 
 void launch_any_flag(const Launch& L, int interior_only) {

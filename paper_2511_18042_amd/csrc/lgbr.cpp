@@ -417,6 +417,7 @@ void fill_launch(Launch& L, const Prob& P) {
   }
   // 32-bit element offsets address every field of the problem (five FP64 planes)
   if (40LL * P.total >= (1LL << 32)) L.o64 = 1;
+  if (P.total % 2 || ((unsigned long long)P.Q | (unsigned long long)P.Us) % 16) L.prim_scalar = 1;
   L.max_fsteps = std::max(L.max_fsteps, P.fsteps);
   L.max_total = std::max<long long>(L.max_total, P.total);
   L.max_cells = std::max<long long>(L.max_cells, (long long)P.n[0] * P.n[1] * P.n[2]);
