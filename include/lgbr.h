@@ -234,6 +234,14 @@ lg_status lg_get_tuning(const lg_ctx* ctx, int* seg, int* pcr_blocks, int* zc);
  * calls and to batches created afterwards. */
 lg_status lg_set_line_tiles(lg_ctx* ctx, int mask);
 int lg_get_line_tiles(const lg_ctx* ctx);
+/* Memory-access forms of the LAD sweep and the primitive conversion (no effect on results):
+ * by default the FP32 kernels read fields by 32-bit offsets from a scalar base and convert
+ * primitives two nodes per lane, and fall back by themselves to 64-bit addressing and one
+ * node per lane for fields of 2^32 bytes or more, odd node counts or unaligned state.
+ * generic = 1 forces those fallbacks (so that tests can compare the two forms), 0 restores
+ * the default.  Applies to later calls on the context, not to batches.  LG_EINVAL for a
+ * null context or generic outside {0, 1}. */
+lg_status lg_set_generic_access(lg_ctx* ctx, int generic);
 
 /* Synchronises the context's stream and reads its non-physical node count since the
  * last poll (then resets it).  Returns LG_ENONPHYS when the count is non-zero. */

@@ -942,6 +942,14 @@ lg_status lg_set_line_tiles(lg_ctx* c, int mask) {
 
 int lg_get_line_tiles(const lg_ctx* c) { return c ? c->L.tile_mask : -1; }
 
+lg_status lg_set_generic_access(lg_ctx* c, int generic) {
+  if (!c || (generic != 0 && generic != 1)) return LG_EINVAL;
+  c->L.o64 = c->L.prim_scalar = 0;
+  fill_launch(c->L, c->hp);
+  if (generic) c->L.o64 = c->L.prim_scalar = 1;
+  return LG_OK;
+}
+
 lg_status lg_get_tuning(const lg_ctx* c, int* seg, int* pcr_blocks, int* zc) {
   if (!c || !seg || !pcr_blocks || !zc) return LG_EINVAL;
   *seg = lg::sweep_seg(c->L, c->cfg.ndim > 1 ? 1 : 0);

@@ -22,8 +22,8 @@ EXPORTS = ('lg_set_allocator', 'lg_strerror', 'lg_create', 'lg_destroy', 'lg_wor
            'lg_metrics_from_coords', 'cgbr_rhs', 'lad_rhs', 'hybrid_rhs', 'rk3_step', 'lg_rk3_stage',
            'lg_compute_dt', 'lg_batch_create', 'lg_batch_run', 'lg_batch_destroy', 'lg_poll_status',
            'lg_prof_start', 'lg_prof_stop', 'lg_set_tuning', 'lg_get_tuning', 'lg_metrics_planar', 'lad_filter',
-           'lg_set_line_tiles', 'lg_get_line_tiles', 'lg_switch_stats', 'lg_df_create', 'lg_df_random_count',
-           'lg_df_update', 'lg_df_destroy')
+           'lg_set_line_tiles', 'lg_get_line_tiles', 'lg_set_generic_access', 'lg_switch_stats', 'lg_df_create',
+           'lg_df_random_count', 'lg_df_update', 'lg_df_destroy')
 KERNEL_CLASSES = ('bc', 'prim', 'flags', 'grad_e6', 'grad_c4', 'sensor', 'visc', 'lad_node', 'lad_raw', 'gauss',
                   'lad_flux', 'sweep_x', 'sweep_y', 'sweep_z', 'combine', 'dt', 'bc_scalar', 'lad_sweep',
                   'c6_faces', 'filter')
@@ -92,6 +92,7 @@ def load():
         'lg_set_tuning': (I, [P, I, I, I]),
         'lg_set_line_tiles': (I, [P, I]),
         'lg_get_line_tiles': (I, [P]),
+        'lg_set_generic_access': (I, [P, I]),
         'lg_get_tuning': (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
     }
     for name, (res, args) in sig.items():
@@ -241,6 +242,9 @@ class Context:
 
     def get_line_tiles(self):
         return int(self._lib.lg_get_line_tiles(self.handle))
+
+    def set_generic_access(self, generic=True):
+        _check(self._lib.lg_set_generic_access(self.handle, 1 if generic else 0), 'lg_set_generic_access')
 
     def get_tuning(self):
         a, b, z = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
