@@ -256,7 +256,7 @@ def ramp3d(args, variants, cpu):
                            traffic_file=os.path.join(ROOT, 'profiles', 'ramp3d_hybrid_mig4_mixed_hbm_traffic.txt'))
     prof = os.path.join(ROOT, 'profiles', 'ramp3d_hybrid_mig4_mixed_hbm_traffic.txt')
     st, why = profiled_step(prof)
-    if st:   # SURVEY-style whole-step figure: all kernels' HBM bytes over the measured step time
+    if st:   # whole-step figure: every kernel's HBM bytes over the measured step time
         gbs = st['bytes_per_step'] / (ms * 1e-3) / 1e9
         res['hbm_step'] = {'bytes_per_step': st['bytes_per_step'], 'achieved': round(gbs, 1), 'unit': 'GB/s',
                            'frac_of_peak': round(gbs / HBM_PEAK_GBS, 4), 'valu_busy_pct': st['valu_busy_pct'],
