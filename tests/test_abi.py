@@ -83,3 +83,5 @@ def test_strerror_and_argument_errors_without_gpu():
     assert code == lgbr.LG_EINVAL
     assert lib.cgbr_rhs(None, None, None) == lgbr.LG_EINVAL
     assert lib.lg_set_allocator(ctypes.c_void_p(1), None, None) == lgbr.LG_EINVAL
+    assert lib.lg_set_generic_access(None, 1) == lgbr.LG_EINVAL
+    assert lib.lg_set_line_tiles(None, -1) == lgbr.LG_EINVAL
