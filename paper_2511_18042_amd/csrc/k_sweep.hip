@@ -301,33 +301,36 @@ __global__ void __launch_bounds__(256) k_sweep_x(const Prob* __restrict__ probs,
   const Prob& P = probs[blockIdx.y];
   if (gate_skip(P, skip_if_any)) return;
   const int lane = threadIdx.x & 63;
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int n0 = P.n[0];
   const int nseg = (n0 + 62) / 63;
   const int rows = P.n[1] * P.n[2];
-  if (wave >= nseg * rows) return;
-  const int seg = wave % nseg, row = wave / nseg;
-  const int j = row % P.n[1], k = row / P.n[1];
-  const int il = seg * 63 - 1 + lane;  // interface il + 1/2
-  const bool valid = il <= n0 - 1;
-  const int idx = pos_to_idx(P, il + P.g[0], j + P.g[1], k + P.g[2]);
-  R F[5] = {R(0), R(0), R(0), R(0), R(0)};
-  if (valid) interface_flux(P, 0, idx, sel, F);
   double* dQ = ref.deriv(P);
   const size_t T = P.total;
-  double Fp[5];
-  for (int q = 0; q < 5; ++q) Fp[q] = (double)__shfl_up(F[q], 1);
   int bad = 0;
-  if (lane >= 1 && valid) {
-    double J = node_J(P, idx);
-    double Lq[5];
-    for (int q = 0; q < 5; ++q) {
-      double v = -J * ((double)F[q] - Fp[q]);
-      size_t o = q * T + idx;
-      Lq[q] = accumulate ? dQ[o] + v : v;
-      if (!rk) dQ[o] = Lq[q];
+  // waves stride over the (segment, row) items: a capped grid, so that a launch the hybrid
+  // switch skips costs few workgroups (the loop bound is uniform in the wave)
+  for (int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; wave < nseg * rows;
+       wave += (gridDim.x * blockDim.x) >> 6) {
+    const int seg = wave % nseg, row = wave / nseg;
+    const int j = row % P.n[1], k = row / P.n[1];
+    const int il = seg * 63 - 1 + lane;  // interface il + 1/2
+    const bool valid = il <= n0 - 1;
+    const int idx = pos_to_idx(P, il + P.g[0], j + P.g[1], k + P.g[2]);
+    R F[5] = {R(0), R(0), R(0), R(0), R(0)};
+    if (valid) interface_flux(P, 0, idx, sel, F);
+    double Fp[5];
+    for (int q = 0; q < 5; ++q) Fp[q] = (double)__shfl_up(F[q], 1);
+    if (lane >= 1 && valid) {
+      double J = node_J(P, idx);
+      double Lq[5];
+      for (int q = 0; q < 5; ++q) {
+        double v = -J * ((double)F[q] - Fp[q]);
+        size_t o = q * T + idx;
+        Lq[q] = accumulate ? dQ[o] + v : v;
+        if (!rk) dQ[o] = Lq[q];
+      }
+      if (rk && rk_combine_node(P, rr, stage, ca, cb, *P.dt, idx, Lq)) ++bad;
     }
-    if (rk && rk_combine_node(P, rr, stage, ca, cb, *P.dt, idx, Lq)) bad = 1;
   }
   add_bad(P, bad);
 }
@@ -411,6 +414,7 @@ void launch_sweep(const Launch& L, StateRef ref, int d, int sel, int accumulate,
     long long waves = nseg * L.sweep_rows[0];
     long long blocks = (waves + 3) / 4;
     if (blocks < 1) blocks = 1;
+    if (blocks > 16384) blocks = 16384;   // the kernel strides over the rest
     LG_TIMED(L, KC_SWEEP_X, hipLaunchKernelGGL(k_sweep_x<R>, dim3((unsigned)blocks, L.nprob), dim3(256), 0,
                                                L.stream, L.probs, ref, sel, accumulate, skip_if_any, rk, r, stage, a, b));
   } else {
