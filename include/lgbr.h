@@ -114,11 +114,13 @@ typedef struct {
   int lad_scheme;      /* LG_LAD_E4 (the hybrid's LAD, Sec. 5) or LG_LAD_C6 (the
                           stand-alone LAD scheme of Sec. 3: compact sixth-order
                           gradients and interface fluxes; LG_SCHEME_LAD only)          */
-  double filter_alpha; /* alpha_f of the tenth-order implicit filter that ends every
-                          rk3_step of a LG_LAD_C6 context (Alg. 1); 0 <= alpha_f <= 0.5,
-                          0.5 = no filter.  Ignored for LG_LAD_E4.                     */
+  double filter_alpha; /* alpha_f of the tenth-order implicit filter (Sec. 2.1) that
+                          follows the last RK stage wherever that stage ran the LAD-based
+                          solver (Alg. 1 FILTER_CALLS, also in the hybrid's LAD phases,
+                          Alg. 3): LG_SCHEME_LAD with LAD-E4 or LAD-C6, and hybrid stages
+                          that ran LAD; 0 <= alpha_f <= 0.5, 0.5 = no filter          */
   int filter_every_stage; /* 0: filter after the third stage (Alg. 1); 1: after every
-                          stage of rk3_step (an alternative reading)                   */
+                          stage of rk3_step that ran LAD (an alternative reading)      */
 } lg_opts;
 
 typedef struct lg_ctx lg_ctx;
@@ -158,15 +160,15 @@ lg_status cgbr_rhs(lg_ctx* ctx, double* Q, double* dQdt);
  * LAD-C6 on a context created with lad_scheme = LG_LAD_C6. */
 lg_status lad_rhs(lg_ctx* ctx, double* Q, double* dQdt);
 /* FILTER_CALLS of Alg. 1: the implicit low-pass filter (Sec. 2.1; Gaitonde-Visbal,
- * tenth order, alpha_f = opts->filter_alpha)
+ * tenth order, alpha_f = opts->filter_alpha) of the whole field
  *   alpha_f phi^_{i-1} + phi^_i + alpha_f phi^_{i+1} = sum_{k=0}^{5} a_k/2 (phi_{i+k} + phi_{i-k})
  * applied to the conserved state Q in place along xi, eta, zeta in turn.  Before each
  * direction the ghost layers of that direction are refilled with the boundary images;
  * bounded lines filter their interior nodes with the ghost values as known neighbours,
  * periodic lines are cyclic.  Interior nodes and the ghosts of FIXED faces hold the
  * result; other ghosts hold images of intermediate fields.  rk3_step calls it after the
- * third stage on LG_LAD_C6 contexts; lg_rk3_stage does not.  LG_EUNSUPPORTED unless the
- * context is LG_LAD_C6 with alpha_f < 0.5. */
+ * third stage of LG_SCHEME_LAD steps, and in the hybrid's LAD phases (see rk3_step);
+ * lg_rk3_stage does not.  LG_EUNSUPPORTED unless alpha_f < 0.5. */
 lg_status lad_filter(lg_ctx* ctx, double* Q);
 /* dQdt = hybrid right-hand side of Q (Alg. 3, Sec. 5).  flags_in (nullable, uint8 [N])
  * replaces the troubled-cell criterion; flags_out (nullable, uint8 [N]) receives the
@@ -177,9 +179,14 @@ lg_status hybrid_rhs(lg_ctx* ctx, double* Q, double* dQdt, const uint8_t* flags_
 /* One SSP-RK3 step of scheme LG_SCHEME_* on Q in place.  The step size is
  * dt = cfl / max_i sum_l (|xi_l . u| + c |xi_l|) from Q, clipped so that t does not
  * pass t_end; t_inout is a device double that is advanced by dt.  dt stays on the
- * device (no host synchronisation).  LG_SCHEME_LAD on a LG_LAD_C6 context ends the step
- * with lad_filter (Alg. 1) unless filter_alpha = 0.5 (with filter_every_stage, every
- * stage). */
+ * device (no host synchronisation).  Unless filter_alpha = 0.5 the step ends with the
+ * implicit filter where its third stage ran the LAD-based solver (Alg. 1; Alg. 3 runs that
+ * solver in the hybrid's LAD phases): LG_SCHEME_LAD filters the whole field; under the
+ * global hybrid switch the field is filtered when the third stage found no troubled
+ * interior node and left alone when it ran C-GBR (Alg. 2 has no filter); under the
+ * per-cell switch the lines are filtered whole and the nodes in the dilated troubled set
+ * keep their unfiltered values.  The decision is taken on the device from the stage's
+ * troubled-cell reduction.  With filter_every_stage the same follows every stage. */
 lg_status rk3_step(lg_ctx* ctx, int scheme, double* Q, double t_end, double* t_inout);
 
 /* One RK3 stage from given states (for per-stage checks):

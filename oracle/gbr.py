@@ -16,9 +16,14 @@ Readings used here:
   R3  entropy wave (b = 2): when the MP test passes (product <= 1e-20) the
       central linear value is kept, otherwise the MP5 value is used.
   R4  acoustic "Linear" = the upwind GBR linear state.
-  R5  frozen state = arithmetic mean of nodes i and i+1; basis n = xi~/|xi~|,
-      t1 = normalise(n x e_m) with m = argmin |n_m| (lowest index on ties),
-      t2 = n x t1.
+  R5  frozen state of the characteristic transformation = the Roe average of nodes
+      i and i+1 (the same average the HLLC wave speeds of Sec. 2.3 use):
+      rho~ = sqrt(rho_i rho_{i+1}), u~ and H~ weighted by sqrt(rho), c~ from H~ and u~;
+      basis n = xi~/|xi~|, t1 = normalise(n x e_m) with m = argmin |n_m| (lowest index
+      on ties), t2 = n x t1.  (The arithmetic mean of the two nodes, read first, gives
+      sound speeds that mix a dense cold state with a light hot one across strong
+      contacts; the reconstructed acoustic fields then lose positivity on Le Blanc's
+      shock tube within four steps, while the paper runs it stably.)
   R7  Omega = (pressure switch) x (Ducros ratio); the over-bar is the maximum over
       the node and its two neighbours along the sweep; the left state uses node i,
       the right state node i+1; strict "> 0.01".  The Ducros ratio is regularised
@@ -75,6 +80,22 @@ def mp5(vm2, vm1, v0, vp1, vp2, alpha=4.0, eps=1e-20):
     vmax = np.minimum(np.maximum(np.maximum(v0, vp1), vmd), np.maximum(np.maximum(v0, vul), vlc))
     limited = vor + minmod(vmin - vor, vmax - vor)   # median(vor, vmin, vmax)
     return np.where(accept, vor, limited), margin
+
+
+def roe_frozen_state(WL, WR, gamma):
+    """(rho~, c~) of the Roe average of two primitive states (R5)."""
+    rL, rR = WL[0], WR[0]
+    sL, sR = np.sqrt(rL), np.sqrt(rR)
+    wL, wR = sL / (sL + sR), sR / (sL + sR)
+
+    def enthalpy(Wk):
+        q2 = Wk[1] ** 2 + Wk[2] ** 2 + Wk[3] ** 2
+        return gamma / (gamma - 1.0) * Wk[4] / Wk[0] + 0.5 * q2
+
+    u = [wL * WL[m] + wR * WR[m] for m in (1, 2, 3)]
+    H = wL * enthalpy(WL) + wR * enthalpy(WR)
+    c = np.sqrt((gamma - 1.0) * (H - 0.5 * (u[0] ** 2 + u[1] ** 2 + u[2] ** 2)))
+    return sL * sR, c
 
 
 def tangents(n):
@@ -229,9 +250,7 @@ def gbr_interface_flux(W, G, Ob, M, d, gamma, omega_thr=0.01, mp_eps=1e-20, mp_a
     xn = np.sqrt(xt[0] ** 2 + xt[1] ** 2 + xt[2] ** 2)
     n = xt / xn
     t1, t2 = tangents(n)
-    rb = 0.5 * (Ws[0][0] + Ws[1][0])
-    pb = 0.5 * (Ws[0][4] + Ws[1][4])
-    cb = np.sqrt(gamma * pb / rb)
+    rb, cb = roe_frozen_state(Ws[0], Ws[1], gamma)
 
     C = {s: to_characteristic(Ws[s], n, t1, t2, rb, cb) for s in Ws}
     Cp = {s: to_characteristic(Gs[s], n, t1, t2, rb, cb) for s in Gs}

@@ -117,13 +117,18 @@ def filter_direction(Q, d, grid, alpha, coef):
     return np.moveaxis(out.reshape(Qm.shape), 0, ax)
 
 
-def filter_state(Q, grid, alpha=FILTER_ALPHA, order=FILTER_ORDER, gas=None):
+def filter_state(Q, grid, alpha=FILTER_ALPHA, order=FILTER_ORDER, gas=None, keep=None):
     """FILTER_CALLS of Alg. 1 on the conserved state (R29); returns the filtered copy with
-    its ghost layers refilled (isothermal walls need the gas model)."""
+    its ghost layers refilled (isothermal walls need the gas model).
+
+    keep (bool, field shape, optional): nodes that keep their value through every pass
+    (the C-GBR nodes of a per-cell hybrid stage, R35); the lines are still solved whole,
+    and the other nodes take their filtered values."""
     coef = gv_coefficients(alpha, order)
     Q = Q.copy()
     for d in range(grid.ndim):
         gr.fill_ghosts_conserved(Q, grid, gas)
-        Q = filter_direction(Q, d, grid, alpha, coef)
+        out = filter_direction(Q, d, grid, alpha, coef)
+        Q = out if keep is None else np.where(keep[None], Q, out)
     gr.fill_ghosts_conserved(Q, grid, gas)
     return Q

@@ -23,9 +23,15 @@ Readings used here:
   R18  no positivity fallback: rho <= 0, p <= 0 or a non-finite value after a
        stage is reported (non-physical count).
   R24  troubled if rho < rho_thr or p < p_thr (strict).
-  R27-R29  LAD-C6: C6 gradients, compact interface fluxes, tenth-order implicit
-       filter after the third stage (``Opts.lad = 'C6'``; derivatives, lad and
-       implicit_filter modules).
+  R27-R29  LAD-C6: C6 gradients, compact interface fluxes (``Opts.lad = 'C6'``;
+       derivatives and lad modules); the tenth-order implicit filter
+       (implicit_filter module) after the third stage.
+  R35  every stage that ran the LAD-based solver is followed by the filter when it is
+       the step's last (Alg. 1 FILTER_CALLS; Alg. 3 runs that solver in the hybrid's LAD
+       phases; Sec. 2.1: the solver's central schemes, explicit or compact, carry the
+       filter): LAD-E4 and LAD-C6 alike, the global hybrid's LAD stages, and the nodes
+       outside the dilated troubled set of a per-cell hybrid stage.  C-GBR stages are
+       never filtered (Alg. 2).
 """
 from dataclasses import dataclass
 
@@ -77,7 +83,9 @@ def primitives(Q, gamma):
 
 
 def troubled_flags(W, opts):
-    return (W[0] < opts.rho_thr) | (W[4] < opts.p_thr)
+    """R24: rho < rho_thr or p < p_thr (strict); a non-finite density or pressure is
+    troubled too (the comparisons are written so that NaN fails them)."""
+    return ~(W[0] >= opts.rho_thr) | ~(W[4] >= opts.p_thr)
 
 
 def dilate(f, grid, r):
@@ -202,14 +210,33 @@ def nonphysical_count(Q, grid, gamma):
     return int(bad.sum())
 
 
-def uses_filter(opts, scheme):
-    """LAD-C6 steps end with the implicit filter (Alg. 1, R29)."""
-    return scheme == 'lad' and opts.lad == 'C6' and opts.filter_alpha < 0.5
+def stage_filter(U, info, grid, gas, opts, scheme):
+    """FILTER_CALLS after a stage that ran the LAD-based solver (Alg. 1; Alg. 3 calls that
+    solver in the hybrid's LAD phases; Sec. 2.1: the central schemes, explicit or compact,
+    carry the low-pass implicit filter) (R29, R35).
+
+    'lad'            : the whole field is filtered.
+    'hybrid' global  : filtered when the stage found no troubled interior node (it ran
+                       LAD everywhere), left alone otherwise (C-GBR, Alg. 2: no filter).
+    'hybrid' percell : nodes outside the dilated troubled set take the filtered value,
+                       the C-GBR nodes keep theirs.
+    'cgbr'           : never filtered.
+    ``info`` is the stage's RHS diagnostics (troubled flags)."""
+    if not opts.filter_alpha < 0.5 or scheme == 'cgbr':
+        return U
+    if scheme == 'lad':
+        return filter_state(U, grid, opts.filter_alpha, gas=gas)
+    f = info['flags']
+    if opts.hybrid_mode == 'global':
+        return U if f[grid.interior()].any() else filter_state(U, grid, opts.filter_alpha, gas=gas)
+    if not f.any():          # the per-cell form's interface flags come from every node
+        return filter_state(U, grid, opts.filter_alpha, gas=gas)
+    return filter_state(U, grid, opts.filter_alpha, gas=gas, keep=dilate(f, grid, opts.dilate))
 
 
 def rk3_step(Q, t, t_end, grid, gas, opts, scheme, M=None):
-    """One SSP-RK3 step (R8, R17), filtered after the third stage for LAD-C6 (R29; after
-    every stage with ``opts.filter_every_stage``).
+    """One SSP-RK3 step (R8, R17); the third stage is followed by the implicit filter where
+    it ran LAD (R29, R35; after every stage with ``opts.filter_every_stage``).
     Returns (Q_new, t_new, dt, nonphysical_count)."""
     if M is None:
         M = gr.node_metrics(grid)
@@ -217,9 +244,10 @@ def rk3_step(Q, t, t_end, grid, gas, opts, scheme, M=None):
     bad = 0
     U = Q
     for s in range(3):
-        U = rk3_stage(Q, U, dt, s, grid, gas, opts, scheme, M)
-        if (s == 2 or opts.filter_every_stage) and uses_filter(opts, scheme):
-            U = filter_state(U, grid, opts.filter_alpha, gas=gas)
+        info = {} if scheme == 'hybrid' else None
+        U = rk3_stage(Q, U, dt, s, grid, gas, opts, scheme, M, info=info)
+        if s == 2 or opts.filter_every_stage:
+            U = stage_filter(U, info, grid, gas, opts, scheme)
         bad += nonphysical_count(U, grid, gas.gamma)
     return U, t + dt, dt, bad
 

@@ -105,6 +105,12 @@ __device__ __forceinline__ void prim_node(const Prob& P, double rho, double m1, 
   r4 = (R)p;
 }
 
+// Troubled-cell test (Sec. 5): density or pressure below its threshold (strict); a value
+// that is not a number also counts, so that a broken state is never taken for a smooth one.
+__device__ __forceinline__ bool troubled(double rho, double p, const Prob& P) {
+  return !(rho >= P.rho_thr) || !(p >= P.p_thr);
+}
+
 // PAIR: each lane converts two neighbouring nodes (2t, 2t + 1) with 16-byte state loads and
 // 8-byte (FP32) primitive stores; needs an even node count and 16-byte aligned state
 // (checked on the host).  Otherwise one node per lane.
@@ -139,8 +145,8 @@ __global__ void __launch_bounds__(256) k_prim(const Prob* __restrict__ probs, St
           fa = (uint8_t)(force[idx] != 0);
           fb = (uint8_t)(force[idx + 1] != 0);
         } else {
-          fa = (uint8_t)((q[0].x < P.rho_thr) || (pa < P.p_thr));
-          fb = (uint8_t)((q[0].y < P.rho_thr) || (pb < P.p_thr));
+          fa = (uint8_t)troubled(q[0].x, pa, P);
+          fb = (uint8_t)troubled(q[0].y, pb, P);
         }
         P.f[idx] = fa;
         P.f[idx + 1] = fb;
@@ -154,7 +160,7 @@ __global__ void __launch_bounds__(256) k_prim(const Prob* __restrict__ probs, St
                    r[4], p);
       for (int c = 0; c < 5; ++c) W[c * T + idx] = r[c];
       if (want_flags) {
-        uint8_t f = force ? (uint8_t)(force[idx] != 0) : (uint8_t)((Q[idx] < P.rho_thr) || (p < P.p_thr));
+        uint8_t f = force ? (uint8_t)(force[idx] != 0) : (uint8_t)troubled(Q[idx], p, P);
         P.f[idx] = f;
       }
     }

@@ -512,10 +512,24 @@ __device__ __forceinline__ double filt_rhs(const Prob& P, const double w[11]) {
   return v;
 }
 
+// Which filter runs after a stage (host-chosen mode, decided on the device from the stage's
+// troubled-cell reduction): FILT_ALL filters every interior node (LAD scheme); FILT_GLOBAL
+// filters every interior node unless the stage ran C-GBR (global hybrid: any troubled
+// node); FILT_PERCELL keeps the values of the nodes in the dilated troubled set ft when
+// the stage had any troubled node (per-cell hybrid).
+__device__ __forceinline__ bool filt_skip(const Prob& P, int mode) {
+  return mode == FILT_GLOBAL && *P.any_flag != 0;
+}
+__device__ __forceinline__ bool filt_keep(const Prob& P, int mode, size_t node) {
+  return mode == FILT_PERCELL && *P.any_flag != 0 && P.ft[node] != 0;
+}
+
 // One lane per (interior line, conserved variable); in place on the state.
-__global__ void __launch_bounds__(256) k_filter(const Prob* __restrict__ probs, StateRef ref, int d, int mask) {
+__global__ void __launch_bounds__(256) k_filter(const Prob* __restrict__ probs, StateRef ref, int d, int mask,
+                                                int mode) {
   const Prob& P = probs[blockIdx.y];
   if (d >= P.ndim || !(P.falpha < 0.5) || tile_use(P, d, TK_FILTER, mask) || filt_pcr(P, d)) return;
+  if (filt_skip(P, mode)) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int nl = interior_lines(P, d);
   if (t >= 5 * nl) return;
@@ -551,10 +565,10 @@ __global__ void __launch_bounds__(256) k_filter(const Prob* __restrict__ probs, 
         for (int p = 0; p < 10; ++p) w[p] = w[p + 1];
       }
       double y = dprev;
-      phi[(size_t)(g + n - 1) * sd] = y;
+      if (!filt_keep(P, mode, base + (size_t)(g + n - 1) * sd)) phi[(size_t)(g + n - 1) * sd] = y;
       for (int i = n - 2; i >= 0; --i) {
         y = Sq[(size_t)(g + i) * sd] - cp[i] * y;
-        phi[(size_t)(g + i) * sd] = y;
+        if (!filt_keep(P, mode, base + (size_t)(g + i) * sd)) phi[(size_t)(g + i) * sd] = y;
       }
     } else {
       const double* z = tab + 2 * n;
@@ -574,10 +588,10 @@ __global__ void __launch_bounds__(256) k_filter(const Prob* __restrict__ probs, 
       // has read every input it needs)
       const double vy = (y0 - al * dprev) * fac;
       double y = dprev;
-      phi[(size_t)(g + n - 1) * sd] = y - vy * z[n - 1];
+      if (!filt_keep(P, mode, base + (size_t)(g + n - 1) * sd)) phi[(size_t)(g + n - 1) * sd] = y - vy * z[n - 1];
       for (int i = n - 2; i >= 0; --i) {
         y = Sq[(size_t)(g + i) * sd] - cp[i] * y;
-        phi[(size_t)(g + i) * sd] = y - vy * z[i];
+        if (!filt_keep(P, mode, base + (size_t)(g + i) * sd)) phi[(size_t)(g + i) * sd] = y - vy * z[i];
       }
     }
   }
@@ -586,10 +600,11 @@ __global__ void __launch_bounds__(256) k_filter(const Prob* __restrict__ probs, 
 // Contiguous lines: one workgroup per (interior line, variable); the line in LDS, the
 // interior unknowns reduced by PCR, written back in place.
 __global__ void __launch_bounds__(CPCR_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_filter_pcr(const Prob* __restrict__ probs, StateRef ref, int d,
-                                                    int mask) {
+                                                    int mask, int mode) {
   extern __shared__ double lds[];
   const Prob& P = probs[blockIdx.y];
   if (d >= P.ndim || !(P.falpha < 0.5) || tile_use(P, d, TK_FILTER, mask) || !filt_pcr(P, d)) return;
+  if (filt_skip(P, mode)) return;
   const int nlines = interior_lines(P, d);
   const bool periodic = P.bc[d][0] == BC_PERIODIC;
   const int g = P.g[d], n = P.n[d], N = P.N[d], sd = P.s[d];
@@ -600,7 +615,8 @@ __global__ void __launch_bounds__(CPCR_THREADS) __attribute__((amdgpu_waves_per_
   double* r = lds + N;   // interior unknowns
   for (int blk = blockIdx.x; blk < 5 * nlines; blk += gridDim.x) {
     const int line = blk % nlines, q = blk / nlines;
-    double* phi = Q + (size_t)q * T + interior_line_base(P, d, line);
+    const size_t lb0 = interior_line_base(P, d, line);
+    double* phi = Q + (size_t)q * T + lb0;
     for (int p = threadIdx.x; p < N; p += blockDim.x) f[p] = phi[(size_t)p * sd];
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -615,7 +631,8 @@ __global__ void __launch_bounds__(CPCR_THREADS) __attribute__((amdgpu_waves_per_
     }
     __syncthreads();
     pcr_lds(r, n, periodic, P.pcrf[d], P.fsteps);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) phi[(size_t)(g + i) * sd] = r[i];
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+      if (!filt_keep(P, mode, lb0 + (size_t)(g + i) * sd)) phi[(size_t)(g + i) * sd] = r[i];
     __syncthreads();
   }
 }
@@ -647,6 +664,7 @@ struct TileArgs {
   RKRef rr;
   int d, TX, accumulate, rk, stage, mask, skip_if_any;
   double a, b;
+  int keep_ft;   // filter of a per-cell hybrid stage: nodes in the dilated troubled set keep their values
 };
 
 // the LDS index of (variable q, column c, position p) is (q * TX + c) * Lin + p
@@ -918,6 +936,7 @@ k_line_tiles(const Prob* __restrict__ probs, TileArgs A) {
       k = d == 0 ? e - qa * dn.d : qb;
       if (c >= ncol) continue;
       const size_t node = lbase + (size_t)c * P.s[o1] + (size_t)(g + k) * sd;
+      if (filt_keep(P, A.keep_ft, node)) continue;
       for (int q = 0; q < 5; ++q) Q[q * T + node] = buf[(q * TX + c) * Lin + k];
     }
   }
@@ -964,7 +983,7 @@ void launch_grad_c6(const Launch& L, StateRef ref, int d) {
   const SysLaunch sl = sys_launch(L, TK_GRAD6, d);
   if (sl.tiles)
     launch_tiles<R, TK_GRAD6>(L, KC_GRAD_C4, L.max_N[d], L.max_N[o1], L.max_N[o2],
-                              TileArgs{ref, RKRef{nullptr, nullptr, nullptr}, d, 1, 0, 0, 0, L.tile_mask, -1, 0.0, 0.0});
+                              TileArgs{ref, RKRef{nullptr, nullptr, nullptr}, d, 1, 0, 0, 0, L.tile_mask, -1, 0.0, 0.0, 0});
   if (sl.pcr) {
     const unsigned lds = (unsigned)(2 * std::min<long long>(L.max_N[d], 4096) * sizeof(double));
     LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c6_pcr<R>, dim3(pcr_grid(L, 5 * L.lines[d]), L.nprob),
@@ -983,7 +1002,7 @@ void launch_c6_faces(const Launch& L, StateRef ref, int d, int accumulate, const
   if (sl.tiles)
     launch_tiles<R, TK_FACES>(L, KC_C6_FACES, L.max_n[d] + 4, L.max_n[o1], L.max_n[o2],
                               TileArgs{ref, rr ? *rr : RKRef{nullptr, nullptr, nullptr}, d, 1, accumulate, rr ? 1 : 0,
-                                       stage, L.tile_mask, -1, a, b});
+                                       stage, L.tile_mask, -1, a, b, 0});
   if (sl.pcr) {
     const unsigned lds = (unsigned)((2 * std::min<long long>(L.max_n[d], 3990) + 4) * sizeof(double));
     LG_TIMED(L, KC_C6_FACES, hipLaunchKernelGGL(k_c6_faces_pcr<R>, dim3(pcr_grid(L, 5 * L.sweep_rows[d]), L.nprob),
@@ -1000,21 +1019,22 @@ void launch_c6_faces(const Launch& L, StateRef ref, int d, int accumulate, const
   }
 }
 
-void launch_filter(const Launch& L, StateRef ref, int d) {
+void launch_filter(const Launch& L, StateRef ref, int d, int mode) {
   launch_bc_cons(L, ref, d);
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   const SysLaunch sl = sys_launch(L, TK_FILTER, d);
   if (sl.tiles)
     launch_tiles<double, TK_FILTER>(L, KC_FILTER, L.max_N[d], L.max_n[o1], L.max_n[o2],
-                                    TileArgs{ref, RKRef{nullptr, nullptr, nullptr}, d, 1, 0, 0, 0, L.tile_mask, -1, 0.0, 0.0});
+                                    TileArgs{ref, RKRef{nullptr, nullptr, nullptr}, d, 1, 0, 0, 0, L.tile_mask,
+                                             mode == FILT_GLOBAL ? 1 : -1, 0.0, 0.0, mode});
   if (sl.pcr) {
     const unsigned lds = (unsigned)(std::min<long long>(L.max_N[d] + L.max_n[d], 7990) * sizeof(double));
     LG_TIMED(L, KC_FILTER, hipLaunchKernelGGL(k_filter_pcr, dim3(pcr_grid(L, 5 * L.sweep_rows[d]), L.nprob),
-                                              dim3(CPCR_THREADS), lds, L.stream, L.probs, ref, d, L.tile_mask));
+                                              dim3(CPCR_THREADS), lds, L.stream, L.probs, ref, d, L.tile_mask, mode));
   }
   if (sl.thomas)
     LG_TIMED(L, KC_FILTER, hipLaunchKernelGGL(k_filter, dim3(blocks_for(5 * L.sweep_rows[d]), L.nprob), dim3(256), 0,
-                                              L.stream, L.probs, ref, d, L.tile_mask));
+                                              L.stream, L.probs, ref, d, L.tile_mask, mode));
 }
 
 template <typename R>
@@ -1023,7 +1043,7 @@ void launch_grad_c4_tiles(const Launch& L, StateRef ref, int d, int skip_if_any)
   if (L.ctile[TK_GRAD4][d])
     launch_tiles<R, TK_GRAD4>(L, KC_GRAD_C4, L.max_N[d], L.max_N[o1], L.max_N[o2],
                               TileArgs{ref, RKRef{nullptr, nullptr, nullptr}, d, 1, 0, 0, 0, L.tile_mask, skip_if_any,
-                                       0.0, 0.0});
+                                       0.0, 0.0, 0});
 }
 
 template void launch_grad_c4_tiles<float>(const Launch&, StateRef, int, int);

@@ -15,7 +15,7 @@
 //   C^{L,Lin} = C_i + C'_i/2 + C''_i/12,  C^{R,Lin} = C_{i+1} - C'_{i+1}/2 + C''_{i+1}/12,
 //   C''_j = 2 (C_{j+1} - 2 C_j + C_{j-1}) - (C'_{j+1} - C'_{j-1}) / 2.
 // MP5 = Suresh & Huynh (1997), alpha = 4, beta = 4/3.
-// Frozen characteristic state: arithmetic mean of nodes i, i+1; basis n = xi~/|xi~|,
+// Frozen characteristic state: Roe average of nodes i, i+1; basis n = xi~/|xi~|,
 // t1 = normalise(n x e_m) with m = argmin |n_m| (lowest index on ties), t2 = n x t1.
 // Omega = pressure switch x Ducros ratio (theta^2 + eps) / (theta^2 + |omega|^2 + eps),
 // eps = 1e-32, so that a pressure jump in a flow at rest is still detected; over-bar =
@@ -199,10 +199,27 @@ __host__ __device__ __forceinline__ void gbr_flux(const Prob& P, int d, int idx,
     fr.t2[2] = fr.n[0] * fr.t1[1] - fr.n[1] * fr.t1[0];
   }
   const R gamma = (R)P.gamma;
-  R r0 = W[idx], r1 = W[idx + s], p0 = W[4 * T + idx], p1 = W[4 * T + idx + s];
-  fr.rb = R(0.5) * (r0 + r1);
-  R pb = R(0.5) * (p0 + p1);
-  fr.cb = sqrt(gamma * pb / fr.rb);
+  {
+    // frozen state: Roe average of the two nodes (density sqrt(r0 r1); velocity and total
+    // enthalpy weighted by sqrt(rho); sound speed from them)
+    const R r0 = W[idx], r1 = W[idx + s];
+    const R sl = sqrt(r0), sr = sqrt(r1);
+    const R wl = sl / (sl + sr), wr = sr / (sl + sr);
+    R q0 = R(0), q1 = R(0), ub2 = R(0);
+    for (int m = 1; m <= 3; ++m) {
+      const R a = W[m * T + idx], b = W[m * T + idx + s];
+      q0 += a * a;
+      q1 += b * b;
+      const R ub = wl * a + wr * b;
+      ub2 += ub * ub;
+    }
+    const R gg = gamma / (gamma - R(1));
+    const R H0 = gg * W[4 * T + idx] / r0 + R(0.5) * q0;
+    const R H1 = gg * W[4 * T + idx + s] / r1 + R(0.5) * q1;
+    const R Hb = wl * H0 + wr * H1;
+    fr.rb = sl * sr;
+    fr.cb = sqrt((gamma - R(1)) * (Hb - R(0.5) * ub2));
+  }
   fr.k = fr.rb / (R(2) * fr.cb);
 
   R C[6][5], D[4][5];

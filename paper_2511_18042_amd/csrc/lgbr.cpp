@@ -51,9 +51,10 @@ void dev_free(void* p) {
 
 struct Cfg {
   int ndim, precision, grad, hybrid_mode, viscous, dilate;
-  int lad_c6, filter;   // LAD-C6 context; its steps end with the implicit filter
+  int lad_c6;           // the LAD scheme is LAD-C6
+  int filter;           // steps whose last stage ran LAD end with the implicit filter
   double falpha;
-  int filter_all;       // ... or filter after every stage
+  int filter_all;       // ... or every stage that ran LAD is followed by it
 };
 
 }  // namespace
@@ -179,17 +180,28 @@ void enqueue_rhs(const Launch& L, const Cfg& c, int scheme, StateRef ref, const 
   }
 }
 
+// FILTER_CALLS of Alg. 1 after a stage that ran the LAD-based solver: the LAD scheme
+// filters every stage result it is asked to; a hybrid stage filters where it ran LAD,
+// which the device decides from the stage's troubled-cell reduction (the whole field under
+// the global switch when nothing was troubled; the nodes outside the dilated troubled set
+// under the per-cell switch).  C-GBR stages are never filtered (Alg. 2).
+int filter_mode(const Cfg& c, int scheme) {
+  if (!c.filter || scheme == LG_SCHEME_CGBR) return -1;
+  if (scheme == LG_SCHEME_LAD) return lg::FILT_ALL;
+  return c.hybrid_mode == LG_HYB_GLOBAL ? lg::FILT_GLOBAL : lg::FILT_PERCELL;
+}
+
 template <typename R>
 void enqueue_rk3(const Launch& L, const Cfg& c, int scheme, double* Qx, double* tx, double t_end) {
   lg::launch_dt(L, Qx, tx, t_end, 1);
-  const bool filt = scheme == LG_SCHEME_LAD && c.lad_c6 && c.filter;
+  const int fmode = filter_mode(c, scheme);
   for (int s = 0; s < 3; ++s) {
     StateRef ref{s == 0 ? Qx : nullptr, nullptr, s == 0 ? 0 : 1};
     RKRef rr{Qx, nullptr, nullptr};
     enqueue_rhs<R>(L, c, scheme, ref, nullptr, &rr, s);
-    if (filt && (s == 2 || c.filter_all)) {   // FILTER_CALLS (after the last stage, Alg. 1)
+    if (fmode >= 0 && (s == 2 || c.filter_all)) {   // after the last stage (Alg. 1)
       const StateRef out{s == 2 ? Qx : nullptr, nullptr, s == 2 ? 0 : 1};   // the stage result
-      for (int d = 0; d < c.ndim; ++d) lg::launch_filter(L, out, d);
+      for (int d = 0; d < c.ndim; ++d) lg::launch_filter(L, out, d, fmode);
     }
   }
 }
@@ -405,9 +417,9 @@ void fill_launch(Launch& L, const Prob& P) {
     }
     if (periodic && P.n[d] < 128) L.has_short_periodic = 1;
     if (P.bc[d][0] == LG_BC_FIXED || P.bc[d][1] == LG_BC_FIXED) L.has_fixed = 1;
-    if (P.lad_c6) {
+    if (P.lad_c6 || P.falpha < 0.5) {
       for (int k = 0; k < 3; ++k) {
-        if (k == lg::TK_FILTER && !(P.falpha < 0.5)) continue;
+        if (k == lg::TK_FILTER ? !(P.falpha < 0.5) : !P.lad_c6) continue;
         const bool pcr = k == lg::TK_GRAD6 ? lg::c6_grad_pcr(P, d)
                                            : (k == lg::TK_FACES ? lg::c6_face_pcr(P, d) : lg::filt_pcr(P, d));
         if (lg::tile_use(P, d, k, L.tile_mask)) L.ctile[k][d] = 1;
@@ -512,7 +524,7 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
   if (opts->dilate < 0 || opts->dilate > 4 || opts->seg < 0) return LG_EINVAL;
   if (!(opts->cfl > 0.0)) return LG_EINVAL;
   if (opts->lad_scheme != LG_LAD_E4 && opts->lad_scheme != LG_LAD_C6) return LG_EINVAL;
-  if (opts->lad_scheme == LG_LAD_C6 && !(opts->filter_alpha >= 0.0 && opts->filter_alpha <= 0.5)) return LG_EINVAL;
+  if (!(opts->filter_alpha >= 0.0 && opts->filter_alpha <= 0.5)) return LG_EINVAL;
 
   lg_ctx* c = new (std::nothrow) lg_ctx();
   if (!c) return LG_ENOMEM;
@@ -558,8 +570,8 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
   P.grad_c4 = opts->grad == LG_GRAD_C4;
   const int c6 = opts->lad_scheme == LG_LAD_C6;
   P.lad_c6 = c6;
-  P.falpha = c6 ? opts->filter_alpha : 0.5;
-  const int filt = c6 && P.falpha < 0.5;
+  P.falpha = opts->filter_alpha;
+  const int filt = P.falpha < 0.5;
   filter_weights(P.falpha, P.fcoef);
   P.fsteps = filt ? filter_pcr_steps(P.falpha) : 0;
   c->cfg = Cfg{G.ndim, opts->precision, opts->grad, opts->hybrid_mode, gas->viscous, opts->dilate, c6, filt,
@@ -575,7 +587,7 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
   };
   P.W = A(5 * T * rs);
   for (int d = 0; d < G.ndim; ++d) P.G[d] = A(5 * T * rs);
-  if (opts->grad == LG_GRAD_C4 || c6) P.T64 = static_cast<double*>(A(5 * T * sizeof(double)));
+  if (opts->grad == LG_GRAD_C4 || c6 || filt) P.T64 = static_cast<double*>(A(5 * T * sizeof(double)));
   P.Om = A(T * rs);
   P.f = static_cast<uint8_t*>(A(T));
   P.ft = static_cast<uint8_t*>(A(T));
@@ -722,15 +734,33 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
       P.trc[d] = upload(periodic ? cyclic_table(n, a3) : thomas_table(fa, fc));
       P.pcrc[d] = upload(periodic ? pcr_table_ac(pa, pc, true, lg::LG_PCR_STEPS)
                                   : pcr_table_ac(fa, fc, false, lg::LG_PCR_STEPS));
-      if (filt) {
-        const double al = P.falpha;
-        std::vector<double> ka(n, al), kc(n, al);
-        std::vector<double> qa(n, al), qc(n, al);
-        ka[0] = 0.0;
-        kc[n - 1] = 0.0;
-        P.trf[d] = upload(periodic ? cyclic_table(n, al) : thomas_table(ka, kc));
-        P.pcrf[d] = upload(pcr_table_ac(periodic ? qa : ka, periodic ? qc : kc, periodic, P.fsteps));
+    }
+    if (!ok) {
+      lg_destroy(c);
+      return LG_ENOMEM;
+    }
+  }
+  if (filt) {
+    // tables of the implicit filter (every LAD phase ends with it, Alg. 1)
+    for (int d = 0; d < G.ndim && ok; ++d) {
+      const bool periodic = P.bc[d][0] == LG_BC_PERIODIC;
+      const int n = P.n[d];
+      const double al = P.falpha;
+      std::vector<double> ka(n, al), kc(n, al);
+      std::vector<double> qa(n, al), qc(n, al);
+      ka[0] = 0.0;
+      kc[n - 1] = 0.0;
+      const std::vector<double> tri = periodic ? cyclic_table(n, al) : thomas_table(ka, kc);
+      const std::vector<double> pcr = pcr_table_ac(periodic ? qa : ka, periodic ? qc : kc, periodic, P.fsteps);
+      double* t1 = static_cast<double*>(A(tri.size() * sizeof(double)));
+      double* t2 = static_cast<double*>(A(pcr.size() * sizeof(double)));
+      if (!ok || hipMemcpy(t1, tri.data(), tri.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(t2, pcr.data(), pcr.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        lg_destroy(c);
+        return ok ? LG_EHIP : LG_ENOMEM;
       }
+      P.trf[d] = t1;
+      P.pcrf[d] = t2;
     }
     if (!ok) {
       lg_destroy(c);
@@ -883,7 +913,7 @@ lg_status hybrid_rhs(lg_ctx* c, double* Q, double* dQdt, const uint8_t* flags_in
 lg_status lad_filter(lg_ctx* c, double* Q) {
   if (!c || !Q) return LG_EINVAL;
   if (!c->cfg.filter) return LG_EUNSUPPORTED;
-  for (int d = 0; d < c->cfg.ndim; ++d) lg::launch_filter(c->L, StateRef{Q, nullptr, 0}, d);
+  for (int d = 0; d < c->cfg.ndim; ++d) lg::launch_filter(c->L, StateRef{Q, nullptr, 0}, d, lg::FILT_ALL);
   return last_hip();
 }
 

@@ -203,7 +203,8 @@ template <typename R> void launch_grad_c6(const Launch& L, StateRef ref, int d);
 template <typename R>
 void launch_c6_faces(const Launch& L, StateRef ref, int d, int accumulate, const RKRef* rr, int stage, double a,
                      double b);
-void launch_filter(const Launch& L, StateRef ref, int d);
+enum { FILT_ALL = 0, FILT_GLOBAL = 1, FILT_PERCELL = 2 };
+void launch_filter(const Launch& L, StateRef ref, int d, int mode);
 // which kernel solves the lines of each system (shared by the host and the kernels):
 // LDS line tiles when all five variables of one line fit the tile and a periodic line is
 // long enough for the PCR steps; otherwise the policies below

@@ -245,7 +245,10 @@ def test_lad_c6_batch_graph_matches_the_oracle(every):
         ctx.close()
 
 
-def test_lad_c6_context_refuses_the_hybrid_and_e4_refuses_the_filter():
+def test_lad_c6_context_refuses_the_hybrid_and_filter_needs_alpha_below_half():
+    """The hybrid's LAD is LAD-E4 (Sec. 5), so LAD-C6 contexts refuse it; the filter runs on
+    any context with alpha_f < 1/2 (every LAD phase ends with it, Alg. 1) and is refused at
+    alpha_f = 1/2 (no filter)."""
     torch = U.torch_mod()
     c = case_2d_walls()
     ctx, _ = U.gpu_context(c, orhs.Gas(), _opts())
@@ -255,12 +258,9 @@ def test_lad_c6_context_refuses_the_hybrid_and_e4_refuses_the_filter():
         ctx.hybrid_rhs(Qd, dQ)
     assert e.value.code == lgbr.LG_EUNSUPPORTED
     ctx.close()
-    ctx, _ = U.gpu_context(c, orhs.Gas(), orhs.Opts())
-    with pytest.raises(lgbr.LgError) as e:
-        ctx.lad_filter(Qd)
-    assert e.value.code == lgbr.LG_EUNSUPPORTED
-    ctx.close()
-    ctx, _ = U.gpu_context(c, orhs.Gas(), _opts(alpha=0.5))     # alpha_f = 1/2: no filter
-    with pytest.raises(lgbr.LgError):
-        ctx.lad_filter(Qd)
-    ctx.close()
+    for opts in (orhs.Opts(filter_alpha=0.5), _opts(alpha=0.5)):     # alpha_f = 1/2: no filter
+        ctx, _ = U.gpu_context(c, orhs.Gas(), opts)
+        with pytest.raises(lgbr.LgError) as e:
+            ctx.lad_filter(Qd)
+        assert e.value.code == lgbr.LG_EUNSUPPORTED
+        ctx.close()
