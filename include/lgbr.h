@@ -154,6 +154,20 @@ int lg_metrics_planar(const lg_ctx* ctx);
 lg_status lg_metrics_from_coords(const lg_grid* grid, const double* coords, double* node_metrics,
                                  void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): lg_metrics_from_coords with the same arguments,
+ * results and stream ordering, but its [9][N] scratch of inner derivatives lives in a
+ * static device array of 9 * LG_NOALLOC_MAX_NODES doubles (72 MiB) that every GPU the
+ * library runs on holds from library load until the process ends.  No allocation, no
+ * host synchronisation.  Grids whose padded node count N exceeds LG_NOALLOC_MAX_NODES
+ * return LG_EUNSUPPORTED before anything is enqueued.  The scratch is shared by every call
+ * on a GPU and keeps the last call's contents (each call writes all it reads): calls that
+ * overlap on one GPU (different streams, or different host threads without ordering) race;
+ * calls ordered on one stream do not.  The stream must belong to the current device. */
+#define LG_NOALLOC_MAX_NODES (1LL << 20)
+lg_status lg_metrics_from_coords_noalloc(const lg_grid* grid, const double* coords, double* node_metrics,
+                                         void* stream);
+
 /* dQdt = C-GBR right-hand side of Q (Sec. 2.3, Alg. 2). */
 lg_status cgbr_rhs(lg_ctx* ctx, double* Q, double* dQdt);
 /* dQdt = LAD right-hand side of Q (Sec. 2.2, Alg. 1 without the filter): LAD-E4, or

@@ -17,7 +17,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, 'csrc')
 BUILD = os.path.join(PKG, '_build')
 LIB = os.path.join(PKG, 'liblgbr.so')
-SOURCES = ['k_basic.hip', 'k_grad.hip', 'k_lad.hip', 'k_sweep.hip', 'k_compact.hip', 'k_inflow.hip', 'lgbr.cpp']
+SOURCES = ['k_basic.hip', 'k_grad.hip', 'k_lad.hip', 'k_sweep.hip', 'k_compact.hip', 'k_inflow.hip', 'noalloc.hip',
+           'lgbr.cpp']
 ARCH = 'gfx950'
 
 

@@ -23,7 +23,7 @@ EXPORTS = ('lg_set_allocator', 'lg_strerror', 'lg_create', 'lg_destroy', 'lg_wor
            'lg_compute_dt', 'lg_batch_create', 'lg_batch_run', 'lg_batch_destroy', 'lg_poll_status',
            'lg_prof_start', 'lg_prof_stop', 'lg_set_tuning', 'lg_get_tuning', 'lg_metrics_planar', 'lad_filter',
            'lg_set_line_tiles', 'lg_get_line_tiles', 'lg_set_generic_access', 'lg_switch_stats', 'lg_df_create',
-           'lg_df_random_count', 'lg_df_update', 'lg_df_destroy')
+           'lg_df_random_count', 'lg_df_update', 'lg_df_destroy', 'lg_metrics_from_coords_noalloc')
 KERNEL_CLASSES = ('bc', 'prim', 'flags', 'grad_e6', 'grad_c4', 'sensor', 'visc', 'lad_node', 'lad_raw', 'gauss',
                   'lad_flux', 'sweep_x', 'sweep_y', 'sweep_z', 'combine', 'dt', 'bc_scalar', 'lad_sweep',
                   'c6_faces', 'filter')
@@ -71,6 +71,7 @@ def load():
         'lg_workspace_bytes': (S, [P]),
         'lg_metrics_planar': (I, [P]),
         'lg_metrics_from_coords': (I, [ctypes.POINTER(LgGrid), P, P, P]),
+        'lg_metrics_from_coords_noalloc': (I, [ctypes.POINTER(LgGrid), P, P, P]),
         'cgbr_rhs': (I, [P, P, P]),
         'lad_rhs': (I, [P, P, P]),
         'lad_filter': (I, [P, P]),
@@ -160,6 +161,11 @@ def make_opts(grad='E6', precision='fp64', cfl=0.2, omega_thr=0.01, mp_eps=1e-20
 def metrics_from_coords(grid, coords, metrics, stream=None):
     _check(load().lg_metrics_from_coords(ctypes.byref(grid), _ptr(coords), _ptr(metrics), _stream(stream)),
            'lg_metrics_from_coords')
+
+
+def metrics_from_coords_noalloc(grid, coords, metrics, stream=None):
+    _check(load().lg_metrics_from_coords_noalloc(ctypes.byref(grid), _ptr(coords), _ptr(metrics), _stream(stream)),
+           'lg_metrics_from_coords_noalloc')
 
 
 class Context:
