@@ -97,7 +97,7 @@ def filter_lines(cols, g, n, periodic, alpha, coef):
     ab[1, :] = 1.0
     ab[0, 1:] = alpha
     ab[2, :n - 1] = alpha
-    return scipy.linalg.solve_banded((1, 1), ab, rhs)
+    return scipy.linalg.solve_banded((1, 1), ab, rhs, check_finite=False)
 
 
 def filter_direction(Q, d, grid, alpha, coef):

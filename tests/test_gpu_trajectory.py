@@ -16,13 +16,14 @@ per right-hand side (the other GPU tests), not as trajectories.
     by 2e-12; the bounds are 1e-5 and 1e-10 (a stage-ghost or boundary mistake moves it by
     O(dt |L|), about 1e-3);
   * the per-cell switch (an extension beyond the paper's global switch) on the triple point
-    of Sec. 3 (224 x 96) with its density-only criterion: its LAD-E4 stages leave a density
-    dip at the contact that first crosses the threshold about a hundred steps in.  The GPU
-    and the oracle must find the first troubled stage in the same step (give or take one:
-    the dip approaches the threshold smoothly, and the two trajectories differ by the
-    conditioning noted above), and both must stay physical through the window (with the
-    filter of the LAD phases; without it the LAD region beside the C-GBR patches lost
-    positivity near step 190 in earlier readings).
+    of Sec. 3 (224 x 96) with its density-only criterion: its first LAD-E4 steps undershoot
+    the density at the junction of the three states (x = 1, y = 1.5) below the threshold.
+    The GPU and the oracle must find the first troubled stage in the same step (give or
+    take one: the undershoot approaches the threshold smoothly, and the two trajectories
+    differ by the conditioning noted above), and both must stay physical through 40 steps
+    (the per-cell form is marginal there: its unflagged LAD-E4 region meets the shock and
+    the contacts; the oracle's own run loses positivity after about 500 steps, and
+    perturbed starts show that when it does depends on round-off).
 """
 import numpy as np
 import pytest
@@ -101,7 +102,7 @@ def test_percell_switch_first_troubled_step_and_positivity():
     c = cases.triple_point(224, 96)
     gas = orhs.Gas()
     opts = orhs.Opts(rho_thr=c.extra['rho_thr'], hybrid_mode='percell')
-    steps = 130
+    steps = 40
     print('oracle per-cell run', flush=True)
     first_o, bad_o = _oracle_first_troubled(c, gas, opts, steps)
     assert bad_o == 0 and first_o is not None, (first_o, bad_o)
