@@ -230,7 +230,7 @@ enum {
   LG_KC_BC = 0, LG_KC_PRIM, LG_KC_FLAGS, LG_KC_GRAD_E6, LG_KC_GRAD_C4, LG_KC_SENSOR, LG_KC_VISC,
   LG_KC_LAD_NODE, LG_KC_LAD_RAW, LG_KC_GAUSS, LG_KC_LAD_FLUX, LG_KC_SWEEP_X, LG_KC_SWEEP_Y,
   LG_KC_SWEEP_Z, LG_KC_COMBINE, LG_KC_DT, LG_KC_BC_SCALAR, LG_KC_LAD_SWEEP, LG_KC_C6_FACES, LG_KC_FILTER,
-  LG_KC_COUNT
+  LG_KC_GBR_ITEMS, LG_KC_HYB_ASSEMBLE, LG_KC_COUNT
 };
 lg_status lg_prof_start(lg_ctx* ctx, int kernel_class, int max_launches);
 lg_status lg_prof_stop(lg_ctx* ctx, double* ms, int* launches);

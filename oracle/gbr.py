@@ -33,6 +33,12 @@ Readings used here:
       is never detected and the unlimited acoustic states go negative.
   R16 HLLC star flux F*_K = F_K + S_K (Q*_K - Q_K), |xi~| restored on the Roe
       wave speeds, E^K in the star state read as specific total energy.
+  R36 positivity of the reconstructed states: the paper prints no safeguard, yet reports
+      C-GBR stable (Sec. 4.1, stability table) on cases where the characteristic
+      reconstruction, limited field by field, returns a negative density or pressure at a
+      few interfaces (Le Blanc's shock tube, the triple point): there the side whose state
+      is not positive takes its upwind node's primitive state (first order), the other side
+      keeps its reconstruction.
 """
 import numpy as np
 
@@ -203,7 +209,10 @@ def hllc(WL, WR, xt, gamma):
 
         FL, FsL = star_flux(rL, uL, pL, EL, UL, SL)
         FR, FsR = star_flux(rR, uR, pR, ER, UR, SR)
-        return np.where(SL >= 0.0, FL, np.where(Ss >= 0.0, FsL, np.where(SR > 0.0, FsR, FR)))
+        F = np.where(SL >= 0.0, FL, np.where(Ss >= 0.0, FsL, np.where(SR > 0.0, FsR, FR)))
+        # undefined wave speeds (a state without a sound speed) give an undefined flux
+        undefined = np.isnan(SL) | np.isnan(SR) | np.isnan(Ss)
+        return np.where(undefined, np.nan, F)
 
 
 # ---------------------------------------------------------------- sensor
@@ -300,8 +309,19 @@ def gbr_interface_flux(W, G, Ob, M, d, gamma, omega_thr=0.01, mp_eps=1e-20, mp_a
         mm = np.minimum(np.min(mL, axis=0), np.min(mR, axis=0))
         record['margin'] = np.minimum(np.minimum(om, mm), t)
 
-    WL = from_characteristic(CL, n, t1, t2, rb, cb)
-    WR = from_characteristic(CR, n, t1, t2, rb, cb)
+    WL0 = from_characteristic(CL, n, t1, t2, rb, cb)
+    WR0 = from_characteristic(CR, n, t1, t2, rb, cb)
+    # R36: a reconstructed state without positive density and pressure is replaced by its
+    # upwind node's own state (first order on that side)
+    with np.errstate(invalid='ignore'):
+        okL = (WL0[0] > 0.0) & (WL0[4] > 0.0)
+        okR = (WR0[0] > 0.0) & (WR0[4] > 0.0)
+    WL = np.where(okL, WL0, Ws[0])
+    WR = np.where(okR, WR0, Ws[1])
     if record is not None:
+        with np.errstate(divide='ignore', invalid='ignore'):
+            pos = np.minimum(np.minimum(np.abs(WL0[0] / Ws[0][0]), np.abs(WL0[4] / Ws[0][4])),
+                             np.minimum(np.abs(WR0[0] / Ws[1][0]), np.abs(WR0[4] / Ws[1][4])))
+        record['margin'] = np.minimum(record['margin'], np.where(np.isfinite(pos), pos, 0.0))
         record['WL'], record['WR'] = WL, WR
     return hllc(WL, WR, xt, gamma)

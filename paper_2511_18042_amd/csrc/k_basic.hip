@@ -184,6 +184,64 @@ __global__ void __launch_bounds__(256) k_any_flag(const Prob* __restrict__ probs
   if (__any(found) && (threadIdx.x & 63) == 0) atomicOr(P.any_flag, 1);
 }
 
+// ------------------------------------------------------------------ compacted per-cell hybrid
+// After the flag dilation: all_flag starts as any_flag and is cleared by any interior node
+// outside the dilated troubled set; the queue counts restart at zero.
+__global__ void k_hyb_init(const Prob* __restrict__ probs) {
+  const Prob& P = probs[blockIdx.y];
+  if (threadIdx.x == 0) {
+    *P.all_flag = *P.any_flag != 0 ? 1 : 0;
+    for (int d = 0; d < 3; ++d) P.gcount[d] = 0;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_all_flag(const Prob* __restrict__ probs, int zc) {
+  const Prob& P = probs[blockIdx.y];
+  if (*P.any_flag == 0) return;
+  int clear = 0;
+  ZCol c;
+  if (zm_column(P, 0, 0, zc, c)) {
+    int idx = pos_to_idx(P, c.i, c.j, c.k0);
+    for (int k = c.k0; k < c.k1; ++k, idx += P.s[2]) clear |= P.ft[idx] == 0;
+  }
+  if (__any(clear) && (threadIdx.x & 63) == 0) atomicAnd(P.all_flag, 0);
+}
+
+// Work queue of the C-GBR interfaces along d: the interfaces i+1/2 of the interior lines
+// (i from -1 to n-1, stored by their left node) with ft_i | ft_{i+1}, appended in node
+// order with one atomic per wave (ballot + prefix count), so that a queue's neighbouring
+// entries are mostly neighbouring nodes.  Only when some, but not all, interfaces are C-GBR.
+__global__ void __launch_bounds__(256) k_gbr_queue(const Prob* __restrict__ probs, int d) {
+  const Prob& P = probs[blockIdx.y];
+  if (d >= P.ndim || gate_skip(P, GATE_MIXED)) return;
+  int E[3], o[3];
+  for (int l = 0; l < 3; ++l) {
+    E[l] = P.n[l] + (l == d ? 1 : 0);
+    o[l] = P.g[l] - (l == d ? 1 : 0);
+  }
+  const long long tot = (long long)E[0] * E[1] * E[2];
+  const int s = P.s[d];
+  int* q = P.gq + (size_t)d * P.total;
+  const int lane = threadIdx.x & 63;
+  for (long long b0 = (long long)blockIdx.x * blockDim.x; b0 < tot; b0 += (long long)gridDim.x * blockDim.x) {
+    const long long t = b0 + threadIdx.x;
+    int idx = 0, flag = 0;
+    if (t < tot) {
+      const int i = (int)(t % E[0]) + o[0];
+      const int j = (int)((t / E[0]) % E[1]) + o[1];
+      const int k = (int)(t / ((long long)E[0] * E[1])) + o[2];
+      idx = pos_to_idx(P, i, j, k);
+      flag = (P.ft[idx] | P.ft[idx + s]) != 0;
+    }
+    const unsigned long long m = __ballot(flag);
+    const int cnt = __popcll(m);
+    int base = 0;
+    if (lane == 0 && cnt) base = atomicAdd(&P.gcount[d], cnt);
+    base = __shfl(base, 0);
+    if (flag) q[base + __popcll(m & ((1ull << lane) - 1ull))] = idx;
+  }
+}
+
 // Separable box dilation by r nodes along direction d.
 // src/dst: 0 = f, 1 = ftmp, 2 = ft, 3 = fg.
 __device__ __forceinline__ uint8_t* flag_buf(const Prob& P, int b) {
@@ -505,6 +563,18 @@ void launch_dilate(const Launch& L, int ndim, int radius, int first_src, int fin
     LG_TIMED(L, KC_FLAGS, hipLaunchKernelGGL(k_dilate, grid_for(L.max_total, L.nprob), dim3(256), 0, L.stream,
                                              L.probs, d, src, dst, radius));
     src = dst;
+  }
+}
+
+void launch_hyb_queue(const Launch& L, int ndim) {
+  hipLaunchKernelGGL(k_hyb_init, dim3(1, L.nprob), dim3(64), 0, L.stream, L.probs);
+  LG_TIMED(L, KC_FLAGS, hipLaunchKernelGGL(k_all_flag, zm_grid(L, 0, 0, ZM_TX, ZM_TY), dim3(256), 0, L.stream,
+                                           L.probs, zm_chunk(L, 0, 0)));
+  for (int d = 0; d < ndim; ++d) {
+    long long tot = 1;
+    for (int l = 0; l < 3; ++l) tot *= L.max_n[l] + (l == d ? 1 : 0);
+    LG_TIMED(L, KC_FLAGS, hipLaunchKernelGGL(k_gbr_queue, grid_for(tot, L.nprob, 256, 16384), dim3(256), 0,
+                                             L.stream, L.probs, d));
   }
 }
 

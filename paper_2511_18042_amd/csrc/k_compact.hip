@@ -700,7 +700,7 @@ k_line_tiles(const Prob* __restrict__ probs, TileArgs A) {
   const Prob& P = probs[blockIdx.y];
   const int d = A.d, TX = A.TX;
   if (d >= P.ndim || !tile_use(P, d, KIND, A.mask)) return;
-  if (A.skip_if_any >= 0 && P.any_flag && (*P.any_flag != 0) == (A.skip_if_any != 0)) return;
+  if (gate_skip(P, A.skip_if_any)) return;
   int Lin, off, U, la, lb, ba, bb;
   tile_geom(P, d, KIND, Lin, off, U, la, lb, ba, bb);
   if (5 * TX * Lin > TILE_ELEMS || TX > TILE_MAX_TX) return;   // the host sizes TX so that this never holds

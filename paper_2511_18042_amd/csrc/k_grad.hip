@@ -26,7 +26,7 @@
 namespace lg {
 
 __device__ __forceinline__ bool skip_launch(const Prob& P, int skip_if_any) {
-  return skip_if_any >= 0 && P.any_flag && (*P.any_flag != 0) == (skip_if_any != 0);
+  return gate_skip(P, skip_if_any);
 }
 
 template <typename R, int ORDER>

@@ -26,7 +26,7 @@
 namespace lg {
 
 __device__ __forceinline__ bool lad_skip(const Prob& P, int skip_if_any) {
-  return skip_if_any >= 0 && P.any_flag && (*P.any_flag != 0) == (skip_if_any != 0);
+  return gate_skip(P, skip_if_any);
 }
 
 template <typename R>
@@ -661,6 +661,78 @@ __global__ void __launch_bounds__(256) k_lad_sweep(const Prob* __restrict__ prob
   add_bad(P, bad);
 }
 
+// Assembly pass of the compacted per-cell hybrid: the node derivative from the interface
+// fluxes of every direction, where an interface touching the dilated troubled set
+// (ft_i | ft_{i+1}) takes the C-GBR flux the queue pass stored at its left node and every
+// other interface the I4 interpolation of the LAD node fluxes; then dQ/dt or the RK stage.
+// The same z-marching layout as the all-LAD pass (zeta node fluxes in a register queue).
+template <typename R, bool O32>
+__global__ void __launch_bounds__(256) k_hyb_assemble(const Prob* __restrict__ probs, StateRef ref, RKRef rr,
+                                                      int mode, int stage, double a, double b, int zc) {
+  using IX = sidx_t<O32>;
+  const Prob& P = probs[blockIdx.y];
+  if (lad_skip(P, GATE_MIXED)) return;
+  ZCol c;
+  if (!zm_column(P, 0, 0, zc, c)) return;
+  const IX T = (IX)P.total;
+  const int sz = P.s[2];
+  const bool z3 = P.ndim == 3;
+  const R* FLd[3] = {static_cast<const R*>(P.FL[0]), static_cast<const R*>(P.FL[1]),
+                     static_cast<const R*>(P.FL[2])};
+  const R* FGd[3] = {static_cast<const R*>(P.FG[0]), static_cast<const R*>(P.FG[1]),
+                     static_cast<const R*>(P.FG[2])};
+  const uint8_t* ft = P.ft;
+  double* dQ = ref.deriv(P);
+  const double* Un = rr.Un ? rr.Un : P.Q;
+  const double* Us = rr.Us ? rr.Us : (stage == 0 ? Un : P.Us);
+  double* out = rr.out ? rr.out : (stage == 2 ? const_cast<double*>(Un) : P.Us);
+  const double dt = mode ? *P.dt : 0.0;
+  int bad = 0;
+  int idx = pos_to_idx(P, c.i, c.j, c.k0);
+  const bool mplane = P.met_planar;
+  const double Jcol = met64(P, 9, idx);
+  for (int k = c.k0; k < c.k1; ++k, idx += sz) {
+    const double J = mplane ? Jcol : met64(P, 9, idx);
+    const int f0 = ft[idx];
+    double Lq[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int d = 0; d < 3; ++d) {
+      if (d >= P.ndim) break;
+      const int s = P.s[d];
+      const bool gp = (f0 | ft[idx + s]) != 0, gm = (ft[idx - s] | f0) != 0;
+      const R* F = FLd[d];
+      const R* G = FGd[d];
+      for (int q = 0; q < 5; ++q) {
+        const IX o = (IX)q * T + (IX)idx;
+        const IX si = (IX)s;
+        R fp, fm;
+        if (gp) fp = gld<R, O32>(G, o);
+        else fp = i4v(gld<R, O32>(F, o - si), gld<R, O32>(F, o), gld<R, O32>(F, o + si), gld<R, O32>(F, o + 2 * si));
+        if (gm) fm = gld<R, O32>(G, o - si);
+        else fm = i4v(gld<R, O32>(F, o - 2 * si), gld<R, O32>(F, o - si), gld<R, O32>(F, o), gld<R, O32>(F, o + si));
+        Lq[q] = Lq[q] + -J * ((double)fp - (double)fm);
+      }
+    }
+    (void)z3;
+    if (mode == 0) {
+      for (int q = 0; q < 5; ++q) gst<double, O32>(dQ, (IX)q * T + (IX)idx, Lq[q]);
+    } else {
+      double v[5];
+      for (int q = 0; q < 5; ++q) {
+        const IX o = (IX)q * T + (IX)idx;
+        v[q] = a * gld<double, O32>(Un, o) + b * (gld<double, O32>(Us, o) + dt * Lq[q]);
+        gst<double, O32>(out, o, v[q]);
+      }
+      const double rho = v[0];
+      const double ke = 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / rho;
+      const double p = (P.gamma - 1.0) * (v[4] - ke);
+      const bool ok = rho > 0.0 && p > 0.0 && isfinite(rho) && isfinite(p) && isfinite(v[1]) && isfinite(v[2]) &&
+                      isfinite(v[3]);
+      bad += !ok;
+    }
+  }
+  add_bad(P, bad);
+}
+
 // Ghost nodes of the stage result = U^n, as the combination kernel does off the interior.
 // Inside rk3_step (no explicit output) only the ghosts of FIXED faces are copied: every
 // other ghost is rewritten from the interior before the next stage reads it.
@@ -811,6 +883,19 @@ void launch_lad_sweep(const Launch& L, StateRef ref, const RKRef* rr, int stage,
   if (rr) launch_stage_ghosts(L, *rr, stage, skip_if_any);
 }
 
+template <typename R>
+void launch_hyb_assemble(const Launch& L, StateRef ref, const RKRef* rr, int stage, double a, double b) {
+  RKRef r = rr ? *rr : RKRef{nullptr, nullptr, nullptr};
+  const dim3 grid = zm_grid(L, 0, 0, ZM_TX, ZM_TY);
+  if (sizeof(R) == 4 && !L.o64)
+    LG_TIMED(L, KC_HYB_ASSEMBLE, hipLaunchKernelGGL((k_hyb_assemble<R, true>), grid, dim3(256), 0, L.stream, L.probs,
+                                                    ref, r, rr ? 1 : 0, stage, a, b, zm_chunk(L, 0, 0)));
+  else
+    LG_TIMED(L, KC_HYB_ASSEMBLE, hipLaunchKernelGGL((k_hyb_assemble<R, false>), grid, dim3(256), 0, L.stream, L.probs,
+                                                    ref, r, rr ? 1 : 0, stage, a, b, zm_chunk(L, 0, 0)));
+  if (rr) launch_stage_ghosts(L, *rr, stage, GATE_MIXED);
+}
+
 void launch_stage_ghosts(const Launch& L, const RKRef& rr, int stage, int skip_if_any) {
   if (rr.out) {   // an explicit output: every ghost of the result
     LG_TIMED(L, KC_COMBINE, hipLaunchKernelGGL(k_stage_ghosts, g1(L.max_total, L.nprob), dim3(256), 0, L.stream,
@@ -833,6 +918,8 @@ template void launch_lad<float>(const Launch&, int, int);
 template void launch_lad<double>(const Launch&, int, int);
 template void launch_lad_geometry<float>(const Launch&);
 template void launch_lad_geometry<double>(const Launch&);
+template void launch_hyb_assemble<float>(const Launch&, StateRef, const RKRef*, int, double, double);
+template void launch_hyb_assemble<double>(const Launch&, StateRef, const RKRef*, int, double, double);
 template void launch_lad_sweep<float>(const Launch&, StateRef, const RKRef*, int, double, double, int);
 template void launch_lad_sweep<double>(const Launch&, StateRef, const RKRef*, int, double, double, int);
 template void launch_lad_nodeflux<float>(const Launch&, int, int);

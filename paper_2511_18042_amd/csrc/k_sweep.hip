@@ -22,13 +22,16 @@
 // max over the node and its two neighbours along the sweep; the left state uses node i,
 // the right node i+1.
 // Interface metrics: I4 of the node metrics.  The flux difference is formed in FP64.
+// Positivity of the reconstruction: a side whose state has no positive density and pressure
+// falls back to its upwind node's state (the paper prints no safeguard but reports C-GBR
+// stable where the limited characteristic reconstruction returns such states).
 #include "lgbr_dev.h"
 #include "lgbr_kernels.h"
 
 namespace lg {
 
 __device__ __forceinline__ bool sw_skip(const Prob& P, int skip_if_any) {
-  return skip_if_any >= 0 && P.any_flag && (*P.any_flag != 0) == (skip_if_any != 0);
+  return gate_skip(P, skip_if_any);
 }
 
 __device__ __forceinline__ bool band(const Prob& P, int idx, int lo, int hi) {
@@ -273,6 +276,12 @@ __host__ __device__ __forceinline__ void gbr_flux(const Prob& P, int d, int idx,
   R WL[5], WR[5];
   from_char(fr, CL, WL);
   from_char(fr, CR, WR);
+  // a side whose reconstructed density or pressure is not positive takes its upwind node's
+  // own primitive state (first order on that side)
+  if (!(WL[0] > R(0) && WL[4] > R(0)))
+    for (int q = 0; q < 5; ++q) WL[q] = W[q * T + idx];
+  if (!(WR[0] > R(0) && WR[4] > R(0)))
+    for (int q = 0; q < 5; ++q) WR[q] = W[q * T + idx + s];
   hllc(WL, WR, xt, gamma, F);
 }
 
@@ -399,6 +408,45 @@ __global__ void __launch_bounds__(256) k_sweep_s(const Prob* __restrict__ probs,
   add_bad(P, bad);
 }
 
+// ------------------------------------------------------------------ compacted C-GBR interfaces
+// One persistent launch over the work queue of the per-cell hybrid's C-GBR interfaces (all
+// directions, one after the other, each strided over the whole grid): the C-GBR flux of
+// every queued interface (plus the interpolated viscous flux) into FG[d] at its left node.
+// The LAD interfaces are not visited here; the assembly pass forms them from the node fluxes.
+template <typename R>
+__global__ void __launch_bounds__(256) k_gbr_items(const Prob* __restrict__ probs) {
+  const Prob& P = probs[blockIdx.y];
+  if (gate_skip(P, GATE_MIXED)) return;
+  const size_t T = P.total;
+  const int stride = (int)(gridDim.x * blockDim.x);
+  for (int d = 0; d < P.ndim; ++d) {
+    const int cnt = P.gcount[d];
+    const int* q = P.gq + (size_t)d * T;
+    R* FG = static_cast<R*>(P.FG[d]);
+    const int s = P.s[d];
+    for (int it = (int)(blockIdx.x * blockDim.x + threadIdx.x); it < cnt; it += stride) {
+      const int idx = q[it];
+      R F[5];
+      gbr_flux(P, d, idx, F);
+      if (P.viscous) {
+        R Fv[5];
+        i4_flux(static_cast<const R*>(P.FV[d]), T, idx, s, Fv);
+        for (int c = 0; c < 5; ++c) F[c] = F[c] + Fv[c];
+      }
+      for (int c = 0; c < 5; ++c) FG[c * T + idx] = F[c];
+    }
+  }
+}
+
+template <typename R>
+void launch_gbr_items(const Launch& L) {
+  // persistent: a fixed grid that fills the chip (8 workgroups of 4 waves per CU), the
+  // queue lengths are known on the device only
+  const unsigned blocks = L.item_blocks > 0 ? (unsigned)L.item_blocks : 2048u;
+  LG_TIMED(L, KC_GBR_ITEMS, hipLaunchKernelGGL(k_gbr_items<R>, dim3(blocks, L.nprob), dim3(256), 0, L.stream,
+                                               L.probs));
+}
+
 template <typename R>
 void launch_sensor(const Launch& L, int skip_if_any, int region) {
   long long b = (L.max_total + 255) / 256;
@@ -446,6 +494,8 @@ void launch_sweep(const Launch& L, StateRef ref, int d, int sel, int accumulate,
   }
 }
 
+template void launch_gbr_items<float>(const Launch&);
+template void launch_gbr_items<double>(const Launch&);
 template void launch_sensor<float>(const Launch&, int, int);
 template void launch_sensor<double>(const Launch&, int, int);
 template void launch_sweep<float>(const Launch&, StateRef, int, int, int, int, const RKRef*, int, double, double);

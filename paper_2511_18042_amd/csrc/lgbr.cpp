@@ -143,13 +143,19 @@ void enqueue_rhs(const Launch& L, const Cfg& c, int scheme, StateRef ref, const 
     // only needed within three more nodes of those (-> fg), and only the compact lines
     // that cross fg are solved.  With no troubled node at all (any_flag == 0) every
     // interface is LAD and all of this, and the C-GBR inputs, are skipped on the device.
+    // With some: the C-GBR interfaces are compacted into a work queue (one persistent pass
+    // computes their fluxes, an assembly pass forms the node derivatives with the LAD
+    // fluxes of the others); with every interior node troubled, the plain C-GBR sweeps run
+    // and the LAD inputs are skipped.
     lg::launch_any_flag(L, 0);
     lg::launch_switch_count(L);
     lg::launch_dilate(L, c.ndim, c.dilate, 0, 2);
     lg::launch_dilate(L, c.ndim, 3, 2, 3);
+    lg::launch_hyb_queue(L, c.ndim);
     if (c.grad == LG_GRAD_C4) lg::launch_line_lists(L, c.ndim);
     region = 1;
-    skip_gbr = 0;
+    skip_gbr = lg::GATE_ANY;
+    skip_lad = lg::GATE_NOTALL;
   }
   if (sel != lg::SEL_LAD) {
     for (int d = 0; d < c.ndim; ++d) {
@@ -166,17 +172,23 @@ void enqueue_rhs(const Launch& L, const Cfg& c, int scheme, StateRef ref, const 
     lg::launch_lad_nodeflux<R>(L, skip_lad);
   }
   // interfaces: the all-LAD pass (LAD scheme; hybrid with no troubled node), else the
-  // per-direction sweeps that pick C-GBR or LAD per interface; the hybrid decides on the
-  // device, so both are launched and each returns at once when the other applies
+  // per-direction C-GBR sweeps (C-GBR scheme; global hybrid with a troubled node; per-cell
+  // hybrid with every node troubled), else the compacted per-cell pass; the hybrid decides
+  // on the device, so every applicable form is launched and returns at once unless chosen
   const double a = rk ? RK_A[stage] : 0.0, b = rk ? RK_B[stage] : 0.0;
-  const int skip_fused = sel == lg::SEL_LAD ? -1 : 1;
-  const int skip_dir = sel == lg::SEL_GBR ? -1 : 0;
+  const int skip_fused = sel == lg::SEL_LAD ? lg::GATE_NEVER : lg::GATE_NONE;
+  const int skip_dir = sel == lg::SEL_GBR ? lg::GATE_NEVER : (sel == lg::SEL_PERCELL ? lg::GATE_ALL : lg::GATE_ANY);
+  const int sweep_sel = sel == lg::SEL_PERCELL ? lg::SEL_GBR : sel;
   if (sel != lg::SEL_GBR) lg::launch_lad_sweep<R>(L, ref, rk, stage, a, b, skip_fused);
   if (sel != lg::SEL_LAD) {
     // the last direction's sweep forms the RK stage itself
     for (int d = 0; d < c.ndim; ++d)
-      lg::launch_sweep<R>(L, ref, d, sel, d > 0 ? 1 : 0, skip_dir, d == c.ndim - 1 ? rk : nullptr, stage, a, b);
+      lg::launch_sweep<R>(L, ref, d, sweep_sel, d > 0 ? 1 : 0, skip_dir, d == c.ndim - 1 ? rk : nullptr, stage, a, b);
     if (rk) lg::launch_stage_ghosts(L, *rk, stage, skip_dir);
+  }
+  if (sel == lg::SEL_PERCELL) {
+    lg::launch_gbr_items<R>(L);
+    lg::launch_hyb_assemble<R>(L, ref, rk, stage, a, b);
   }
 }
 
@@ -605,7 +617,11 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
     for (int d = 0; d < G.ndim; ++d) P.FV[d] = A(5 * T * rs);
   P.Us = static_cast<double*>(A(5 * T * sizeof(double)));
   P.dQ = static_cast<double*>(A(5 * T * sizeof(double)));
-  double* scal = static_cast<double*>(A(8 * sizeof(double)));
+  if (opts->hybrid_mode == LG_HYB_PERCELL) {   // the compacted C-GBR interface queue and fluxes
+    P.gq = static_cast<int*>(A(3 * T * sizeof(int)));
+    for (int d = 0; d < G.ndim; ++d) P.FG[d] = A(5 * T * rs);
+  }
+  double* scal = static_cast<double*>(A(16 * sizeof(double)));
   if (!ok) {
     lg_destroy(c);
     return LG_ENOMEM;
@@ -621,6 +637,8 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
   P.any_flag = reinterpret_cast<int*>(scal + 4);
   P.lcount = reinterpret_cast<int*>(scal + 5);   // three ints
   P.sw = reinterpret_cast<unsigned*>(scal + 7);   // two counters
+  P.all_flag = reinterpret_cast<int*>(scal + 8);
+  P.gcount = reinterpret_cast<int*>(scal + 9);    // three ints
   P.t_end = 0.0;
   P.met_T = P.total;
   if (G.curvilinear) {
@@ -777,7 +795,7 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
     return LG_EHIP;
   }
   // zero the device scalars and status slots with kernel-free synchronous copies (setup only)
-  double zeros[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double zeros[16] = {0};
   std::vector<int> zslots(lg::STATUS_SLOTS * lg::STATUS_STRIDE, 0);
   if (hipMemcpy(scal, zeros, sizeof(zeros), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(P.status, zslots.data(), zslots.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {

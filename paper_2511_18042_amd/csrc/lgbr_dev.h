@@ -86,6 +86,11 @@ struct Prob {
   int* status;               // non-physical node counts (STATUS_SLOTS slots, see add_bad)
   int* any_flag;             // global hybrid switch: any troubled interior node
   unsigned* sw;              // switching record: [0] hybrid stages, [1] those with a troubled node
+  // compacted per-cell hybrid: work queue of the C-GBR interfaces and their fluxes
+  int* all_flag;             // every interior node lies in the dilated troubled set
+  int* gcount;               // [3] queued C-GBR interfaces per direction
+  int* gq;                   // [3][total] queue: left-node index of each C-GBR interface
+  void* FG[3];               // C-GBR interface fluxes per direction [5][total] R (at the left node)
 };
 
 __host__ __device__ __forceinline__ int pos_to_idx(const Prob& P, int i, int j, int k) {
@@ -121,10 +126,24 @@ __host__ __device__ __forceinline__ double met64(const Prob& P, int c, int idx) 
   return P.cm[c];
 }
 
-// Device-side switch of the hybrid (any_flag = some troubled node): skip = -1 never skips,
-// 1 skips when a troubled node exists, 0 skips when none does.
-__device__ __forceinline__ bool gate_skip(const Prob& P, int skip) {
-  return skip >= 0 && (*P.any_flag != 0) == (skip != 0);
+// Device-side switch of the hybrid.  any_flag: some troubled node; all_flag (per-cell form,
+// valid after the flag dilation): every interior node is in the dilated troubled set, so
+// every interface is C-GBR.  Gate codes of a launch:
+//   GATE_NEVER (-1) always runs;
+//   GATE_ANY   (0)  runs when a troubled node exists (C-GBR inputs, global C-GBR sweeps);
+//   GATE_NONE  (1)  runs when none does (the all-LAD pass);
+//   GATE_NOTALL(2)  runs unless every interface is C-GBR (LAD inputs of the per-cell form);
+//   GATE_ALL   (3)  runs when every interface is C-GBR (plain direction sweeps);
+//   GATE_MIXED (4)  runs when some but not all interfaces are C-GBR (compacted path).
+enum { GATE_NEVER = -1, GATE_ANY = 0, GATE_NONE = 1, GATE_NOTALL = 2, GATE_ALL = 3, GATE_MIXED = 4 };
+__device__ __forceinline__ bool gate_skip(const Prob& P, int gate) {
+  if (gate < 0) return false;
+  const bool any = *P.any_flag != 0;
+  if (gate <= GATE_NONE) return any == (gate == GATE_NONE);
+  const bool all = any && *P.all_flag != 0;
+  if (gate == GATE_NOTALL) return all;
+  if (gate == GATE_ALL) return !all;
+  return !(any && !all);
 }
 
 // Ghost image of position p along d for scalar intermediate fields (even parity; FIXED

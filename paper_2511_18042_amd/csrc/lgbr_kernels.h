@@ -49,7 +49,7 @@ __device__ __forceinline__ bool rk_combine_node(const Prob& P, const RKRef& rr, 
 enum KClass {
   KC_BC = 0, KC_PRIM, KC_FLAGS, KC_GRAD_E6, KC_GRAD_C4, KC_SENSOR, KC_VISC, KC_LAD_NODE, KC_LAD_RAW,
   KC_GAUSS, KC_LAD_FLUX, KC_SWEEP_X, KC_SWEEP_Y, KC_SWEEP_Z, KC_COMBINE, KC_DT, KC_BC_SCALAR, KC_LAD_SWEEP,
-  KC_C6_FACES, KC_FILTER, KC_COUNT
+  KC_C6_FACES, KC_FILTER, KC_GBR_ITEMS, KC_HYB_ASSEMBLE, KC_COUNT
 };
 
 // Event pairs recorded around launches while enabled (never during graph capture).
@@ -92,6 +92,7 @@ struct Launch {
   int seg;                 // nodes per thread in the strided sweeps (0: heuristic)
   int pcr_blocks;          // persistent workgroups of the PCR line solves (0: heuristic)
   int zc;                  // planes per chunk of the z-marching kernels (0: heuristic)
+  int item_blocks;         // persistent workgroups of the compacted C-GBR interface pass (0: 2048)
   Prof* prof;              // optional launch timing (null: off)
 };
 
@@ -126,6 +127,14 @@ template <typename R> void launch_prim(const Launch& L, StateRef ref, int want_f
 void launch_any_flag(const Launch& L, int interior_only);
 void launch_dilate(const Launch& L, int ndim, int radius, int first_src, int final_buf);
 void launch_line_lists(const Launch& L, int ndim);
+// compacted per-cell hybrid: all_flag, then the C-GBR interface queue of each direction;
+// the persistent C-GBR interface pass over the queue; the assembly of the node derivatives
+// (C-GBR interface fluxes from the queue pass, LAD ones from the node fluxes), with the RK
+// stage when rr is given
+void launch_hyb_queue(const Launch& L, int ndim);
+template <typename R> void launch_gbr_items(const Launch& L);
+template <typename R>
+void launch_hyb_assemble(const Launch& L, StateRef ref, const RKRef* rr, int stage, double a, double b);
 void launch_dt(const Launch& L, const double* Qx, double* tx, double t_end, int advance_t);
 void launch_set_dt(const Launch& L, double dt);
 void launch_zero_status(const Launch& L);

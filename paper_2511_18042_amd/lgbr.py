@@ -26,7 +26,7 @@ EXPORTS = ('lg_set_allocator', 'lg_strerror', 'lg_create', 'lg_destroy', 'lg_wor
            'lg_df_random_count', 'lg_df_update', 'lg_df_destroy', 'lg_metrics_from_coords_noalloc')
 KERNEL_CLASSES = ('bc', 'prim', 'flags', 'grad_e6', 'grad_c4', 'sensor', 'visc', 'lad_node', 'lad_raw', 'gauss',
                   'lad_flux', 'sweep_x', 'sweep_y', 'sweep_z', 'combine', 'dt', 'bc_scalar', 'lad_sweep',
-                  'c6_faces', 'filter')
+                  'c6_faces', 'filter', 'gbr_items', 'hyb_assemble')
 LAD_E4, LAD_C6 = 0, 1
 
 
