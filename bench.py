@@ -6,25 +6,28 @@
                     [--variants all|none] [--copy-probe-mib M]
 
 A step is one SSP-RK3 step of the whole hot path (ghost images, primitives, troubled
-flags, gradients, sensor, LAD coefficients, interface fluxes, stage combination and the
-CFL reduction) on synthetic inputs resident in HBM before timing starts.
+flags, gradients, sensor, LAD coefficients, interface fluxes, stage combination, the
+implicit filter after LAD phases and the CFL reduction) on synthetic inputs resident in HBM
+before timing starts.
 
 Headline workload (``value``): the M2.9 24-degree compression-ramp stand-in, 1024 x 384 x
 128 cells on a curvilinear grid (tanh wall clustering, spanwise periodic), viscous
-(Sutherland, Re 2e4, Pr 0.72), per-cell hybrid of LAD-E4 and C-GBR with compact MIG4
-gradients, troubled where p < 0.5 p_inf, the paper's global switch (any troubled node
-puts the whole field on C-GBR), FP32 bulk arithmetic with FP64 state; K steps after W
-warm-up steps.  Also measured on the same grid: FP64, the per-cell switch, the C-GBR and
-LAD forms, and the per-cell hybrid right-hand side with forced troubled-tile fractions of
-0, 5, 17.6, 50 and 100 %.  Further workloads: the 2D triple point (1792 x 768) in a window at t = 0 and one
-from a t = 3 state (reached on the GPU first), and 64 independent four-quadrant Riemann
-problems (128^2 .. 1024^2) advanced 100 hybrid RK3 steps per graph launch, FP32 and FP64,
-default and autotuned launch shapes.
+(Sutherland, Re 2e4, Pr 0.72), hybrid of LAD-E4 and C-GBR with compact MIG4 gradients,
+troubled where p < 0.5 p_inf, the paper's global switch (any troubled node puts the whole
+field on C-GBR for that stage), FP32 bulk arithmetic with FP64 state.  W warm-up steps from
+the initial state (default 150: the first troubled stages come after some 160 steps), six
+steps that find the dominant kernel class, then exactly K timed steps; the LAD share of the
+timed stages is reported beside the paper's 82.4 %.  Also on the same grid: the same window
+in FP64 (with the FP32-bulk error against it), the per-cell switch, the C-GBR and LAD forms
+(median of five timed blocks), and the per-cell hybrid right-hand side with forced troubled
+tiles against the cost-weighted ideal.  Further workloads: the 2D triple point (1792 x 768),
+its FP64 run to t = 5 (LAD share beside the paper's 13.6 %) and a window from t = 3, and 64
+independent four-quadrant Riemann problems advanced 100 hybrid RK3 steps per graph launch.
 
-Each workload reports its dominant kernel's roofline: the kernel class's algorithmic bytes
-per launch over its average launch time from HIP events recorded on the library's stream
-around that class in a timed pass.  The FP64 CPU oracle is timed on a bounded sample on
-this host.
+Each workload reports its dominant kernel's roofline from live HIP-event times of that
+class's launches inside the timed steps (algorithmic bytes per launch over the average
+launch time), and the whole step against the method's algorithmic floor.  The FP64 CPU
+oracle is timed on this host's cores before the GPU is used.
 """
 import argparse
 import json
@@ -45,7 +48,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
     ap.add_argument('--steps', type=int, default=100)
-    ap.add_argument('--warmup', type=int, default=10)
+    ap.add_argument('--warmup', type=int, default=150)
     ap.add_argument('--workload', default='all', choices=['all', 'ramp3d', 'triple_point', 'batch64'])
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--variants', default='all', choices=['all', 'none'])
@@ -123,15 +126,21 @@ class Runner:
     def __init__(self, K, W):
         self.K, self.W = K, W
 
-    def steps(self, ctx, scheme, Q0, K=None, W=None, prof_class=None, t_end=1e30):
+    def steps(self, ctx, scheme, Q0, K=None, W=None, prof_class=None, t_end=1e30, Q=None, t=None):
+        """W untimed steps, then exactly K timed steps (HIP events around the K steps, the
+        stream synchronised on both sides).  prof_class: a kernel class whose launches are
+        bracketed by HIP events during the timed steps (live per-launch times).  Returns
+        (ms per step, per-class (ms, launches) or None, non-physical count, state, t, switch
+        record of the timed steps (hybrid stages, troubled ones))."""
         import torch
         K = self.K if K is None else K
         W = self.W if W is None else W
-        Q = Q0.clone()
-        t = torch.zeros(1, dtype=torch.float64, device='cuda')
+        Q = Q0.clone() if Q is None else Q
+        t = torch.zeros(1, dtype=torch.float64, device='cuda') if t is None else t
         for _ in range(W):
             ctx.rk3_step(scheme, Q, t_end, t)
         torch.cuda.synchronize()
+        ctx.switch_stats(reset=True)
         if prof_class is not None:
             ctx.prof_start(prof_class, 400 * K + 400)
         e0 = torch.cuda.Event(enable_timing=True)
@@ -143,30 +152,86 @@ class Runner:
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / K
         kern = ctx.prof_stop() if prof_class is not None else None
+        sw = ctx.switch_stats(reset=True)
         bad = ctx.poll_status()
-        return ms, kern, bad, Q, float(t.item())
+        return ms, kern, bad, Q, t, sw
 
-    def roofline(self, ctx, scheme, Q0, cells, ndim, gbr_frac, viscous, curv, K=20, traffic_file=None):
-        """Per-class breakdown, then the dominant class timed alone."""
-        planar = ctx.metrics_planar()
-        _, breakdown, _, _, _ = self.steps(ctx, scheme, Q0, K=K, W=2, prof_class=-1)
-        dominant = max(breakdown, key=lambda k: breakdown[k][0])
-        _, kern, _, _, _ = self.steps(ctx, scheme, Q0, K=K, W=2, prof_class=dominant)
-        dom_ms, dom_n = kern[dominant]
-        dom_avg = dom_ms / max(dom_n, 1)
-        algo = algorithmic_bytes(dominant, cells, 4, ndim, gbr_frac, viscous, curv, planar)
-        achieved = algo / (dom_avg * 1e-3) / 1e9
-        roof = {'bound': 'hbm', 'kernel': dominant, 'achieved': round(achieved, 1), 'peak': HBM_PEAK_GBS,
-                'unit': 'GB/s', 'frac': round(achieved / HBM_PEAK_GBS, 4), 'avg_launch_ms': round(dom_avg, 5),
-                'launches': dom_n, 'algorithmic_bytes_per_launch': int(algo), 'traffic': None}
-        if traffic_file:
-            tr, why = profiled_traffic(traffic_file, dominant)
-            roof['traffic'] = tr
-            roof['traffic_source'] = os.path.relpath(traffic_file, ROOT) + ('' if tr else ' (%s)' % why)
-            if tr:
-                roof['traffic_over_algorithmic'] = round(tr / algo, 3)
-        brk = {k: round(v[0] / K, 4) for k, v in sorted(breakdown.items(), key=lambda kv: -kv[1][0])}
-        return roof, brk
+    def median_ms(self, ctx, scheme, Q0, K, W, repeats=5):
+        """Median over ``repeats`` timed blocks of K steps (each after W warm-up steps from Q0)."""
+        import statistics
+        out, bad = [], 0
+        for _ in range(repeats):
+            ms, _, b, Q, _, _ = self.steps(ctx, scheme, Q0, K=K, W=W)
+            del Q
+            out.append(ms)
+            bad += b
+        return statistics.median(out), bad
+
+
+def dominant_class(ctx, scheme, Q, t, steps=6):
+    """Kernel class with the most time over a few steps from the given state (advances it)."""
+    ctx.prof_start(-1, 400 * steps + 400)
+    for _ in range(steps):
+        ctx.rk3_step(scheme, Q, 1e30, t)
+    brk = ctx.prof_stop()
+    ctx.poll_status()
+    ctx.switch_stats(reset=True)
+    return max(brk, key=lambda k: brk[k][0]), {k: round(v[0] / steps, 4) for k, v in
+                                                sorted(brk.items(), key=lambda kv: -kv[1][0])}
+
+
+def live_roofline(kern, dom, cells, ndim, gbr_frac, viscous, curv, planar, traffic_file=None):
+    """Roofline of the dominant class from its live per-launch HIP-event times in the timed
+    steps: algorithmic bytes per launch over the average launch time."""
+    dom_ms, dom_n = kern[dom]
+    dom_avg = dom_ms / max(dom_n, 1)
+    algo = algorithmic_bytes(dom, cells, 4, ndim, gbr_frac, viscous, curv, planar)
+    achieved = algo / (dom_avg * 1e-3) / 1e9
+    roof = {'bound': 'hbm', 'kernel': dom, 'achieved': round(achieved, 1), 'peak': HBM_PEAK_GBS, 'unit': 'GB/s',
+            'frac': round(achieved / HBM_PEAK_GBS, 4), 'avg_launch_ms': round(dom_avg, 5), 'launches': dom_n,
+            'algorithmic_bytes_per_launch': int(algo), 'timing': 'live HIP events around each launch of the '
+            'class on the library stream during the timed steps', 'traffic': None}
+    if traffic_file:
+        tr, why = profiled_traffic(traffic_file, dom)
+        roof['traffic'] = tr
+        roof['traffic_source'] = os.path.relpath(traffic_file, ROOT) + ('' if tr else ' (%s)' % why)
+        if tr:
+            roof['traffic_over_algorithmic'] = round(tr / algo, 3)
+    return roof
+
+
+def step_floor(cells, ms, bytes_per_cell):
+    """The whole RK3 step against the method's algorithmic floor (state read and written
+    once per stage, U^n re-read in stages 2-3, metrics): bytes per cell over the step time."""
+    gbs = bytes_per_cell * cells / (ms * 1e-3) / 1e9
+    return {'bytes_per_cell': bytes_per_cell, 'achieved': round(gbs, 1), 'unit': 'GB/s',
+            'frac': round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def precision_error(Qa, Qb, gamma=1.4):
+    """L1 (mean) and Linf of the primitive variables of two interior states (FP32 bulk
+    against FP64), absolute and relative to the FP64 field's largest magnitude."""
+    import numpy as np
+    A = Qa.double().cpu().numpy()
+    B = Qb.double().cpu().numpy()
+    sl = tuple(slice(5, -5) if A.shape[1 + ax] > 1 else slice(None) for ax in range(3))
+    A, B = A[(slice(None),) + sl], B[(slice(None),) + sl]
+
+    def prim(Q):
+        rho = Q[0]
+        u, v, w = Q[1] / rho, Q[2] / rho, Q[3] / rho
+        p = (gamma - 1.0) * (Q[4] - 0.5 * rho * (u * u + v * v + w * w))
+        return {'rho': rho, 'u': u, 'v': v, 'w': w, 'p': p}
+    pa, pb = prim(A), prim(B)
+    out = {}
+    for k in ('rho', 'u', 'v', 'w', 'p'):
+        scale = float(np.max(np.abs(pb[k])))
+        if scale == 0.0:
+            continue
+        d = np.abs(pa[k] - pb[k])
+        out[k] = {'L1': float(np.mean(d)), 'Linf': float(np.max(d)), 'L1_rel': float(np.mean(d) / scale),
+                  'Linf_rel': float(np.max(d) / scale)}
+    return out
 
 
 def profiled_traffic(path, kclass):
@@ -224,6 +289,9 @@ def flags_of(ctx, Q):
 
 
 # ------------------------------------------------------------------ M2.9 ramp (headline)
+RAMP_FLOOR_B_PER_CELL = 320   # state 3 x (40 + 40) + U^n 2 x 40; metrics: one plane (extruded grid)
+
+
 def ramp3d(args, variants, cpu):
     import torch
     from paper_2511_18042_amd import cases, lgbr
@@ -244,39 +312,66 @@ def ramp3d(args, variants, cpu):
         return lgbr.Context(grid, gas, lgbr.make_opts(precision=precision, cfl=0.2, grad=grad, hybrid_mode=mode,
                                                       p_thr=e['p_thr'], lad=lad), metrics, coords)
 
-    desc = ('M2.9 24-deg ramp stand-in 1024x384x128 curvilinear, viscous, hybrid LAD-E4/MIG4 (global switch), '
-            'p_thr 0.5 p_inf, CFL 0.2')
+    desc = ('M2.9 24-deg ramp stand-in 1024x384x128 curvilinear, viscous, hybrid LAD-E4/MIG4 (global switch, '
+            'LAD phases filtered), p_thr 0.5 p_inf, CFL 0.2')
     res = {'workload': desc, 'cells': cells}
+    traffic = os.path.join(ROOT, 'profiles', 'ramp3d_hybrid_mig4_mixed_hbm_traffic.txt')
+    # headline: W warm-up steps from the initial state, the dominant kernel class over a few
+    # more, then exactly K timed steps with that class's launches timed live
     head = context('mixed')
-    log('ramp3d: headline %d steps' % args.steps)
-    ms, _, bad, Q, t_end = R.steps(head, 'hybrid', Q0)
-    gbr_frac = interface_fraction(flags_of(head, Q), 'global')
-    del Q
-    roof, brk = R.roofline(head, 'hybrid', Q0, cells, 3, gbr_frac, True, True,
-                           traffic_file=os.path.join(ROOT, 'profiles', 'ramp3d_hybrid_mig4_mixed_hbm_traffic.txt'))
-    prof = os.path.join(ROOT, 'profiles', 'ramp3d_hybrid_mig4_mixed_hbm_traffic.txt')
-    st, why = profiled_step(prof)
-    if st:   # whole-step figure: every kernel's HBM bytes over the measured step time
+    log('ramp3d: headline, %d warm-up + %d timed steps' % (args.warmup, args.steps))
+    Q = Q0.clone()
+    t = torch.zeros(1, dtype=torch.float64, device='cuda')
+    for _ in range(args.warmup):
+        head.rk3_step('hybrid', Q, 1e30, t)
+    dom, brk = dominant_class(head, 'hybrid', Q, t)
+    ms, kern, bad, Q, t, sw = R.steps(head, 'hybrid', None, W=0, prof_class=dom, Q=Q, t=t)
+    gbr_stage_share = sw[1] / max(sw[0], 1)
+    planar = head.metrics_planar()
+    roof = live_roofline(kern, dom, cells, 3, gbr_stage_share, True, True, planar, traffic_file=traffic)
+    res.update({'value': mcell(cells, ms), 'ms_per_step': round(ms, 4), 'nonphysical_nodes': bad,
+                'steps_before_window': args.warmup + 6, 'sim_time_end': round(float(t.item()), 6),
+                'stages': {'hybrid': sw[0], 'troubled_cgbr': sw[1], 'lad_share': round(1 - gbr_stage_share, 4),
+                           'paper_lad_share': 0.824},
+                'roofline': roof, 'roofline_step_floor': step_floor(cells, ms, RAMP_FLOOR_B_PER_CELL),
+                'kernel_breakdown_ms_per_step': brk})
+    st, why = profiled_step(traffic)
+    if st:   # whole-step figure: every kernel's counted HBM bytes over the measured step time
         gbs = st['bytes_per_step'] / (ms * 1e-3) / 1e9
         res['hbm_step'] = {'bytes_per_step': st['bytes_per_step'], 'achieved': round(gbs, 1), 'unit': 'GB/s',
                            'frac_of_peak': round(gbs / HBM_PEAK_GBS, 4), 'valu_busy_pct': st['valu_busy_pct'],
-                           'source': os.path.relpath(prof, ROOT)}
+                           'source': os.path.relpath(traffic, ROOT)}
     else:
-        res['hbm_step'] = {'source': os.path.relpath(prof, ROOT) + ' (%s)' % why}
-    res.update({'value': mcell(cells, ms), 'ms_per_step': round(ms, 4), 'nonphysical_nodes': bad,
-                'sim_time_end': round(t_end, 6), 'troubled_interface_fraction': round(gbr_frac, 5),
-                'roofline': roof, 'kernel_breakdown_ms_per_step': brk})
+        res['hbm_step'] = {'source': os.path.relpath(traffic, ROOT) + ' (%s)' % why}
+    Q32 = Q
     head.close()
+    torch.cuda.empty_cache()
     if variants and not args.only_variant:
+        # the same window in FP64: throughput and the FP32-bulk error after the same steps
+        log('ramp3d: FP64 over the same steps')
+        h64 = context('fp64')
+        Q64 = Q0.clone()
+        t64 = torch.zeros(1, dtype=torch.float64, device='cuda')
+        for _ in range(args.warmup + 6):
+            h64.rk3_step('hybrid', Q64, 1e30, t64)
+        ms64, _, bad64, Q64, t64, sw64 = R.steps(h64, 'hybrid', None, W=0, Q=Q64, t=t64)
+        res['fp64_same_window'] = {'ms_per_step': round(ms64, 4), 'mcell_per_s': mcell(cells, ms64),
+                                   'nonphysical_nodes': bad64, 'stages': list(sw64),
+                                   'fp32_speedup': round(ms64 / ms, 3)}
+        res['fp32_vs_fp64_after_window'] = {'steps': args.warmup + 6 + args.steps,
+                                            'error': precision_error(Q32, Q64)}
+        h64.close()
+        del Q64
+        torch.cuda.empty_cache()
         log('ramp3d: forced-flag sweep')
         pc = context('mixed', mode='percell')
-        res['forced_flag_sweep'] = forced_sweep(pc, Q0, tuple(c.shape))
+        res['forced_flag_sweep'] = forced_sweep(pc, Q0, tuple(metrics.shape[1:]))
         pc.close()
+    del Q32
     torch.cuda.empty_cache()
     if variants:
         var = {}
         for vname, prec, scheme, grad, mode, *vv in (
-                ('hybrid_fp64', 'fp64', 'hybrid', 'C4', 'global'),
                 ('hybrid_percell_mixed', 'mixed', 'hybrid', 'C4', 'percell'),
                 ('hybrid_percell_fp64', 'fp64', 'hybrid', 'C4', 'percell'),
                 ('cgbr_mig4_fp64', 'fp64', 'cgbr', 'C4', 'global'),
@@ -291,26 +386,29 @@ def ramp3d(args, variants, cpu):
                 continue
             log('ramp3d: variant ' + vname)
             ctx = context(prec, grad, mode, *vv)
-            vms, _, vbad, _, _ = R.steps(ctx, scheme, Q0, K=min(args.steps, 20), W=3)
-            var[vname] = {'ms_per_step': round(vms, 4), 'mcell_per_s': mcell(cells, vms), 'nonphysical_nodes': vbad}
-            if vname.startswith('lad_c6'):
-                _, kern, _, _, _ = R.steps(ctx, scheme, Q0, K=5, W=1, prof_class=-1)
+            vms, vbad = R.median_ms(ctx, scheme, Q0, K=min(args.steps, 10), W=2)
+            var[vname] = {'ms_per_step': round(vms, 4), 'mcell_per_s': mcell(cells, vms), 'nonphysical_nodes': vbad,
+                          'timing': 'median of 5 blocks of %d steps from the initial state' % min(args.steps, 10)}
+            if vname.startswith('lad_c6') or args.only_variant:
+                _, kern, _, _, _, _ = R.steps(ctx, scheme, Q0, K=5, W=1, prof_class=-1)
                 var[vname]['kernel_breakdown_ms_per_step'] = {
                     k: round(v[0] / 5, 4) for k, v in sorted(kern.items(), key=lambda kv: -kv[1][0])}
             ctx.close()
             torch.cuda.empty_cache()
-        # the paper's per-stage speed-up study: LAD-C6 against MEG6 / MIG4 C-GBR (FP64 there)
         res['variants'] = var
         if args.only_variant:
             return res
-        res['lad_c6_speedup'] = {
-            p: {'over_meg6': round(var['cgbr_meg6_' + p]['ms_per_step'] / var['lad_c6_' + p]['ms_per_step'], 3),
-                'over_mig4': round(var['cgbr_mig4_' + p]['ms_per_step'] / var['lad_c6_' + p]['ms_per_step'], 3),
+        # the paper's per-stage speed-up study: LAD-C6 / LAD-E4 against MEG6 / MIG4 C-GBR (FP64 there)
+        res['lad_speedup'] = {
+            p: {'lad_c6_over_meg6': round(var['cgbr_meg6_' + p]['ms_per_step'] / var['lad_c6_' + p]['ms_per_step'], 3),
+                'lad_c6_over_mig4': round(var['cgbr_mig4_' + p]['ms_per_step'] / var['lad_c6_' + p]['ms_per_step'], 3),
                 'lad_e4_over_meg6': round(var['cgbr_meg6_' + p]['ms_per_step'] / var['lad_e4_' + p]['ms_per_step'], 3),
                 'lad_e4_over_mig4': round(var['cgbr_mig4_' + p]['ms_per_step'] / var['lad_e4_' + p]['ms_per_step'], 3)}
             for p in ('fp64', 'mixed')}
+        res['lad_speedup']['paper_a100_fp64'] = {'lad_c6_over_meg6': '1.17-1.22', 'lad_c6_over_mig4': '1.38-1.43',
+                                                 'lad_e4_over_meg6': '1.9-2.0', 'lad_e4_over_mig4': '2.2-2.3'}
     if cpu:
-        res['cpu_baseline'] = cpu_baseline_ramp()
+        res['cpu_baseline'] = cpu['ramp3d']
     return res
 
 
@@ -349,30 +447,124 @@ def forced_sweep(ctx, Q0, shape):
         full[:flags.shape[0], :flags.shape[1], :flags.shape[2]] = flags[:shape[0], :shape[1], :shape[2]]
         fl = torch.from_numpy(full.astype(np.uint8)).cuda()
         ms = time_rhs(lambda: ctx.hybrid_rhs(Q, dQ, fl, None))
-        out['rhs_ms']['hybrid_%g%%' % (100 * f)] = {'ms': round(ms, 4),
-                                                    'interface_fraction': round(interface_fraction(full), 4)}
+        frac = interface_fraction(full)
+        ideal = (1 - frac) * out['rhs_ms']['lad'] + frac * out['rhs_ms']['cgbr']
+        out['rhs_ms']['hybrid_%g%%' % (100 * f)] = {'ms': round(ms, 4), 'interface_fraction': round(frac, 4),
+                                                    'cost_weighted_ideal_ms': round(ideal, 4),
+                                                    'over_ideal': round(ms / ideal, 3)}
         del fl
     return out
 
 
-def cpu_baseline_ramp():
-    """The FP64 oracle as it stands, one SSP-RK3 step on a 256x192x64 crop of the ramp
-    generator, one host thread."""
+# ------------------------------------------------------------------ oracle on the host cores
+def host_info():
+    model = ''
+    try:
+        for line in open('/proc/cpuinfo'):
+            if line.startswith('model name'):
+                model = line.split(':', 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {'os_cpu_count': os.cpu_count(), 'cpu_model': model}
+
+
+def _oracle_ramp_step(args):
+    """One SSP-RK3 step of the oracle's global hybrid (MIG4, LAD-E4 filtered) on a crop of the
+    ramp generator; returns (cells, seconds)."""
+    nx, ny, nz = args
     from oracle import grid as ogrid, rhs as orhs
     from paper_2511_18042_amd import cases
-    c = cases.ramp3d(256, 192, 64)
+    c = cases.ramp3d(nx, ny, nz)
     e = c.extra
     gas = orhs.Gas(gamma=1.4, Re=e['Re'], Pr=e['Pr'], Mref=e['Mref'], suth=e['suth'], viscous=True)
-    opts = orhs.Opts(grad='C4', p_thr=e['p_thr'])
+    opts = orhs.Opts(grad='C4', p_thr=e['p_thr'], hybrid_mode='global')
     g = ogrid.Grid(c.ndim, c.n, c.bc, c.h, c.coords)
     M = ogrid.node_metrics(g)
-    log('ramp3d: oracle step on the 256x192x64 crop')
     t0 = time.perf_counter()
     orhs.rk3_step(c.Q, 0.0, 1e30, g, gas, opts, 'hybrid', M)
-    s = time.perf_counter() - t0
-    return {'value': round(c.cells / s / 1e6, 4), 'unit': 'Mcell-updates/s', 'cores': 1, 'kind': 'oracle',
-            'sample': ('one SSP-RK3 step of the per-cell hybrid MIG4 RHS on a 256x192x64 crop from the same '
-                       'generator (rate per cell-update, scales linearly with cells); %.1f s' % s)}
+    return c.cells, time.perf_counter() - t0
+
+
+def _oracle_tp_steps(args):
+    """``n`` SSP-RK3 steps of the oracle's global hybrid on the triple point at (nx, ny)."""
+    nx, ny, n = args
+    from oracle import grid as ogrid, rhs as orhs
+    from paper_2511_18042_amd import cases
+    c = cases.triple_point(nx, ny)
+    g = ogrid.Grid(c.ndim, c.n, c.bc, c.h, c.coords)
+    M = ogrid.node_metrics(g)
+    opts = orhs.Opts(rho_thr=c.extra['rho_thr'], hybrid_mode='global')
+    Q, t = c.Q, 0.0
+    t0 = time.perf_counter()
+    for _ in range(n):
+        Q, t, _, _ = orhs.rk3_step(Q, t, 1e30, g, orhs.Gas(), opts, 'hybrid', M)
+    return n * c.cells, time.perf_counter() - t0
+
+
+def _oracle_batch_problem(c):
+    """One SSP-RK3 step of the oracle's global hybrid on one batch problem."""
+    from oracle import grid as ogrid, rhs as orhs
+    g = ogrid.Grid(c.ndim, c.n, c.bc, c.h, c.coords)
+    M = ogrid.node_metrics(g)
+    opts = orhs.Opts(rho_thr=c.extra['rho_thr'], p_thr=c.extra['p_thr'], hybrid_mode='global')
+    t0 = time.perf_counter()
+    orhs.rk3_step(c.Q, 0.0, 1e30, g, orhs.Gas(), opts, 'hybrid', M)
+    return c.cells, time.perf_counter() - t0
+
+
+def _pool_rate(fn, tasks, workers):
+    """Oracle throughput with ``workers`` host processes on independent tasks: total cells
+    over the wall time of the pool (forked before the GPU is touched)."""
+    import multiprocessing as mp
+    t0 = time.perf_counter()
+    with mp.get_context('fork').Pool(workers) as pool:
+        out = pool.map(fn, tasks)
+    wall = time.perf_counter() - t0
+    cells = sum(o[0] for o in out)
+    return cells / wall / 1e6, wall, cells
+
+
+def cpu_baselines(names):
+    """The FP64 oracle as it stands, timed on this host before any GPU work: one thread on a
+    bounded sample, and all host cores (up to 16 worker processes) on independent samples
+    of the same workload.  Rates in cell-updates per second of one RK3 step."""
+    info = host_info()
+    workers = max(1, min(16, os.cpu_count() or 1))
+    out = {}
+    if 'ramp3d' in names:
+        log('cpu baseline: ramp crops')
+        cells, sec = _oracle_ramp_step((128, 96, 32))
+        rate_all, wall, tot = _pool_rate(_oracle_ramp_step, [(128, 96, 32)] * workers, workers)
+        out['ramp3d'] = dict(info, **{
+            'value': round(rate_all, 4), 'unit': 'Mcell-updates/s', 'cores': workers, 'kind': 'oracle',
+            'one_thread': round(cells / sec / 1e6, 4),
+            'sample': ('one SSP-RK3 step of the global hybrid (MIG4 / LAD-E4 filtered) on a 128x96x32 crop of the '
+                       'ramp generator: %.1f s on one thread; %d crops on %d worker processes in %.1f s wall'
+                       % (sec, workers, workers, wall))})
+    if 'triple_point' in names:
+        log('cpu baseline: triple point')
+        cells, sec = _oracle_tp_steps((448, 192, 3))
+        rate_all, wall, _ = _pool_rate(_oracle_tp_steps, [(448, 192, 3)] * workers, workers)
+        out['triple_point'] = dict(info, **{
+            'value': round(rate_all, 4), 'unit': 'Mcell-updates/s', 'cores': workers, 'kind': 'oracle',
+            'one_thread': round(cells / sec / 1e6, 4),
+            'sample': ('three SSP-RK3 steps of the global hybrid on the triple point at 448x192 from t = 0: %.1f s on '
+                       'one thread; %d copies on %d worker processes in %.1f s wall' % (sec, workers, workers, wall))})
+    if 'batch64' in names:
+        log('cpu baseline: batch problems')
+        from paper_2511_18042_amd import cases
+        probs = cases.batch64()
+        small = [c for c in probs if c.cells <= 256 * 256]
+        cells, sec = _oracle_batch_problem(small[0])
+        rate_all, wall, tot = _pool_rate(_oracle_batch_problem, small, workers)
+        out['batch64'] = dict(info, **{
+            'value': round(rate_all, 4), 'unit': 'Mcell-updates/s', 'cores': workers, 'kind': 'oracle',
+            'one_thread': round(cells / sec / 1e6, 4),
+            'sample': ('one SSP-RK3 step of the global hybrid on each of the %d batch problems of at most 256^2 cells '
+                       '(%d cells) on %d worker processes in %.1f s wall; one thread: the first of them alone, %.1f s'
+                       % (len(small), tot, workers, wall, sec))})
+    return out
 
 
 # ------------------------------------------------------------------ 2D triple point
@@ -390,37 +582,62 @@ def triple_point(args, variants, cpu):
         return lgbr.Context(grid, gas, lgbr.make_opts(precision=precision, cfl=0.2, grad=grad, hybrid_mode=mode,
                                                       rho_thr=c.extra['rho_thr'], lad=lad))
 
-    desc = 'triple point 1792x768, hybrid LAD-E4/MEG6 (global switch), rho_thr 0.0625, CFL 0.2'
+    desc = 'triple point 1792x768, hybrid LAD-E4/MEG6 (global switch, LAD phases filtered), rho_thr 0.0625, CFL 0.2'
     res = {'workload': desc, 'cells': cells}
     head = context('mixed')
-    log('triple_point: t=0 window')
-    ms, _, bad, Q, _ = R.steps(head, 'hybrid', Q0)
-    frac0 = interface_fraction(flags_of(head, Q), 'global')
-    del Q
-    roof, brk = R.roofline(head, 'hybrid', Q0, cells, 2, frac0, False, False)
+    log('triple_point: %d warm-up + %d timed steps' % (args.warmup, args.steps))
+    Q = Q0.clone()
+    t = torch.zeros(1, dtype=torch.float64, device='cuda')
+    for _ in range(args.warmup):
+        head.rk3_step('hybrid', Q, 1e30, t)
+    dom, brk = dominant_class(head, 'hybrid', Q, t)
+    ms, kern, bad, Q, t, sw = R.steps(head, 'hybrid', None, W=0, prof_class=dom, Q=Q, t=t)
+    share = sw[1] / max(sw[0], 1)
+    roof = live_roofline(kern, dom, cells, 2, share, False, False, False)
     res.update({'value': mcell(cells, ms), 'ms_per_step': round(ms, 4), 'nonphysical_nodes': bad,
-                'troubled_interface_fraction': round(frac0, 5), 'roofline': roof,
+                'sim_time_end': round(float(t.item()), 6),
+                'stages': {'hybrid': sw[0], 'troubled_cgbr': sw[1], 'lad_share': round(1 - share, 4)},
+                'roofline': roof, 'roofline_step_floor': step_floor(cells, ms, 320),
                 'kernel_breakdown_ms_per_step': brk})
+    Q32 = Q
+    head.close()
     if variants:
-        # the t = 3 state comes from FP64 MEG6 C-GBR, the form that stays positive to t = 5
-        # on this grid (the hybrid's LAD-E4 phases, without the paper's implicit filter, and
-        # the FP32 forms lose positivity earlier)
-        log('triple_point: advancing to t=3 with FP64 MEG6 C-GBR')
-        adv = context('fp64')
-        Q3 = Q0.clone()
-        t = torch.zeros(1, dtype=torch.float64, device='cuda')
-        b = lgbr.Batch([adv], [Q3], [t], [3.0], 500, 'cgbr')
+        log('triple_point: FP64 over the same steps')
+        h64 = context('fp64')
+        Q64 = Q0.clone()
+        t64 = torch.zeros(1, dtype=torch.float64, device='cuda')
+        for _ in range(args.warmup + 6):
+            h64.rk3_step('hybrid', Q64, 1e30, t64)
+        ms64, _, bad64, Q64, t64, sw64 = R.steps(h64, 'hybrid', None, W=0, Q=Q64, t=t64)
+        res['fp64_same_window'] = {'ms_per_step': round(ms64, 4), 'mcell_per_s': mcell(cells, ms64),
+                                   'nonphysical_nodes': bad64, 'stages': list(sw64), 'fp32_speedup': round(ms64 / ms, 3)}
+        res['fp32_vs_fp64_after_window'] = {'steps': args.warmup + 6 + args.steps, 'error': precision_error(Q32, Q64)}
+        # the whole run to t = 5 with the paper's global switch (FP64): its LAD share (Sec. 5
+        # reports 13.6 %) and whether it stays physical
+        log('triple_point: FP64 hybrid run to t = 5')
+        tt = torch.zeros(1, dtype=torch.float64, device='cuda')
+        Qr = Q0.clone()
+        b = lgbr.Batch([h64], [Qr], [tt], [5.0], 500, 'hybrid')
+        h64.switch_stats(reset=True)
         t0 = time.perf_counter()
-        while t.item() < 3.0 and time.perf_counter() - t0 < 120:
+        while tt.item() < 5.0 and time.perf_counter() - t0 < 60:
             b.run()
             torch.cuda.synchronize()
         b.close()
-        w3 = {'t': round(float(t.item()), 6), 'advanced_with': 'cgbr_meg6_fp64',
-              'nonphysical_nodes_to_t3': adv.poll_status()}
-        adv.close()
-        fl3 = flags_of(head, Q3)
-        w3['troubled_interface_fraction'] = {'global': interface_fraction(fl3, 'global'),
-                                             'percell': round(interface_fraction(fl3), 5)}
+        swr = h64.switch_stats(reset=True)
+        res['run_to_t5_fp64'] = {'t': round(float(tt.item()), 6), 'nonphysical_nodes': h64.poll_status(),
+                                 'stages': swr[0], 'lad_share': round(1 - swr[1] / max(swr[0], 1), 4),
+                                 'paper_lad_share': 0.136, 'seconds': round(time.perf_counter() - t0, 2)}
+        Q3 = Q0.clone()
+        t3 = torch.zeros(1, dtype=torch.float64, device='cuda')
+        b = lgbr.Batch([h64], [Q3], [t3], [3.0], 500, 'hybrid')
+        while t3.item() < 3.0:
+            b.run()
+            torch.cuda.synchronize()
+        b.close()
+        h64.close()
+        del Q64, Qr
+        w3 = {'t': round(float(t3.item()), 6), 'advanced_with': 'hybrid_fp64'}
         for vname, prec, scheme, grad, mode, *vv in (
                 ('hybrid_mixed', 'mixed', 'hybrid', 'E6', 'global'),
                 ('hybrid_fp64', 'fp64', 'hybrid', 'E6', 'global'),
@@ -431,15 +648,13 @@ def triple_point(args, variants, cpu):
                 ('lad_e4_mixed', 'mixed', 'lad', 'E6', 'global'),
                 ('lad_c6_mixed', 'mixed', 'lad', 'E6', 'global', 'C6')):
             ctx = context(prec, grad, mode, *vv)
-            vms, _, vbad, _, _ = R.steps(ctx, scheme, Q3, K=min(args.steps, 50), W=3)
+            vms, vbad = R.median_ms(ctx, scheme, Q3, K=min(args.steps, 20), W=2)
             ctx.close()
             w3[vname] = {'ms_per_step': round(vms, 4), 'mcell_per_s': mcell(cells, vms), 'nonphysical_nodes': vbad}
         res['window_t3'] = w3
         var = {}
         for vname, prec, scheme, grad, mode, *vv in (
-                ('hybrid_fp64', 'fp64', 'hybrid', 'E6', 'global'),
                 ('hybrid_percell_mixed', 'mixed', 'hybrid', 'E6', 'percell'),
-                ('hybrid_percell_fp64', 'fp64', 'hybrid', 'E6', 'percell'),
                 ('cgbr_meg6_fp64', 'fp64', 'cgbr', 'E6', 'global'),
                 ('cgbr_meg6_mixed', 'mixed', 'cgbr', 'E6', 'global'),
                 ('cgbr_mig4_fp64', 'fp64', 'cgbr', 'C4', 'global'),
@@ -449,35 +664,13 @@ def triple_point(args, variants, cpu):
                 ('lad_c6_fp64', 'fp64', 'lad', 'E6', 'global', 'C6'),
                 ('lad_c6_mixed', 'mixed', 'lad', 'E6', 'global', 'C6')):
             ctx = context(prec, grad, mode, *vv)
-            vms, _, vbad, _, _ = R.steps(ctx, scheme, Q0, K=min(args.steps, 50), W=3)
+            vms, vbad = R.median_ms(ctx, scheme, Q0, K=min(args.steps, 20), W=2)
             ctx.close()
             var[vname] = {'ms_per_step': round(vms, 4), 'mcell_per_s': mcell(cells, vms), 'nonphysical_nodes': vbad}
         res['variants'] = var
-    head.close()
     if cpu:
-        res['cpu_baseline'] = cpu_baseline_triple()
+        res['cpu_baseline'] = cpu['triple_point']
     return res
-
-
-def cpu_baseline_triple():
-    """The oracle, six SSP-RK3 steps of the full triple point from t = 0, one host thread."""
-    from oracle import grid as ogrid, rhs as orhs
-    from paper_2511_18042_amd import cases
-    c = cases.triple_point()
-    gas = orhs.Gas()
-    opts = orhs.Opts(rho_thr=c.extra['rho_thr'])
-    g = ogrid.Grid(c.ndim, c.n, c.bc, c.h, c.coords)
-    M = ogrid.node_metrics(g)
-    log('triple_point: oracle steps')
-    Q, t, n = c.Q, 0.0, 0
-    t0 = time.perf_counter()
-    while n < 6:
-        Q, t, _, _ = orhs.rk3_step(Q, t, 1e30, g, gas, opts, 'hybrid', M)
-        n += 1
-    s = time.perf_counter() - t0
-    return {'value': round(n * c.cells / s / 1e6, 4), 'unit': 'Mcell-updates/s', 'cores': 1, 'kind': 'oracle',
-            'sample': '%d SSP-RK3 steps of the per-cell hybrid RHS on the full 1792x768 triple point from t=0; '
-                      '%.1f s' % (n, s)}
 
 
 # ------------------------------------------------------------------ 64 problems, one graph
@@ -490,7 +683,8 @@ def batch64(args, variants, cpu):
     cells = int(sum(c.cells for c in probs))
     nsteps = 100
     res = {'workload': '64 four-quadrant Riemann problems, sizes from {128,256,512,1024}^2 (seed 18042), '
-                       'hybrid LAD-E4/MEG6 (global switch per problem), %d RK3 steps per graph launch' % nsteps,
+                       'hybrid LAD-E4/MEG6 (global switch per problem, LAD phases filtered), %d RK3 steps per graph '
+                       'launch' % nsteps,
            'cells': cells, 'problems': len(probs), 'steps_per_launch': nsteps}
     Q0s = [torch.from_numpy(c.Q).cuda() for c in probs]
     big = int(np.argmax([c.cells for c in probs]))
@@ -505,10 +699,12 @@ def batch64(args, variants, cpu):
         return out
 
     def run(ctxs, scheme='hybrid'):
+        """One warm-up launch (nsteps steps), then one timed launch; per-problem
+        non-physical counts over both (a problem counted bad invalidates the row)."""
         Qs = [q.clone() for q in Q0s]
         ts = [torch.zeros(1, dtype=torch.float64, device='cuda') for _ in probs]
         b = lgbr.Batch(ctxs, Qs, ts, [1e30] * len(probs), nsteps, scheme)
-        b.run()                                   # warm-up launch (the first nsteps steps)
+        b.run()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -517,64 +713,56 @@ def batch64(args, variants, cpu):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         b.close()
-        bad = sum(cx.poll_status() for cx in ctxs)
-        return ms / nsteps, bad
+        bad = [cx.poll_status() for cx in ctxs]
+        return ms / nsteps, bad, Qs
 
+    def entry(ms, bad):
+        nbad = sum(1 for v in bad if v)
+        return {'ms_per_step': round(ms, 4), 'mcell_per_s': mcell(cells, ms), 'nonphysical_nodes': int(sum(bad)),
+                'problems_nonphysical': nbad, 'valid': nbad == 0}
+
+    finals = {}
     for precision in (('mixed', 'fp64') if variants else ('mixed',)):
         log('batch64: %s, default launch shapes' % precision)
         ctxs = contexts(precision)
-        ms, bad = run(ctxs)
-        entry = {'ms_per_step': round(ms, 4), 'mcell_per_s': mcell(cells, ms), 'nonphysical_nodes': bad}
+        ms, bad, Qs = run(ctxs)
+        e = entry(ms, bad)
+        finals[precision] = Qs
         if variants:
             log('batch64: %s, autotuning on the largest problem' % precision)
             (zc, seg, pcr), _ = autotune.tune(ctxs[big], Q0s[big], 'hybrid', steps=3, use_cache=False)
             for cx in ctxs:
                 cx.set_tuning(seg, pcr, zc)
-            tms, tbad = run(ctxs)
-            entry['autotuned'] = {'zc': zc, 'seg': seg, 'ms_per_step': round(tms, 4),
-                                  'mcell_per_s': mcell(cells, tms), 'nonphysical_nodes': tbad}
+            tms, tbad, _ = run(ctxs)
+            e['autotuned'] = dict(entry(tms, tbad), zc=zc, seg=seg)
         for cx in ctxs:
             cx.close()
         torch.cuda.empty_cache()
-        res[precision] = entry
+        res[precision] = e
+    if 'fp64' in finals:   # FP32 bulk against FP64 after the same 2 x nsteps steps, over all problems
+        errs = [precision_error(a, b) for a, b in zip(finals['mixed'], finals['fp64'])]
+        w = np.array([c.cells for c in probs], float)
+        res['fp32_vs_fp64_after_%d_steps' % (2 * nsteps)] = {
+            k: {'L1_cell_weighted': float(np.sum(w * [e[k]['L1'] for e in errs]) / w.sum()),
+                'Linf': float(max(e[k]['Linf'] for e in errs))} for k in ('rho', 'u', 'v', 'p')}
+    del finals
     if variants:
         for vname, prec, mode, scheme in (('percell_mixed', 'mixed', 'percell', 'hybrid'),
                                           ('cgbr_meg6_mixed', 'mixed', 'global', 'cgbr'),
                                           ('cgbr_meg6_fp64', 'fp64', 'global', 'cgbr')):
             log('batch64: ' + vname)
             ctxs = contexts(prec, mode)
-            ms, bad = run(ctxs, scheme)
-            res[vname] = {'ms_per_step': round(ms, 4), 'mcell_per_s': mcell(cells, ms), 'nonphysical_nodes': bad}
+            ms, bad, _ = run(ctxs, scheme)
+            res[vname] = entry(ms, bad)
             for cx in ctxs:
                 cx.close()
             torch.cuda.empty_cache()
-    res['value'] = res['mixed']['mcell_per_s']
+    # the batch's throughput is reported only from a row in which every problem stayed physical
+    res['value'] = res['mixed']['mcell_per_s'] if res['mixed']['valid'] else None
     res['ms_per_step'] = res['mixed']['ms_per_step']
     if cpu:
-        res['cpu_baseline'] = cpu_baseline_batch(probs)
+        res['cpu_baseline'] = cpu['batch64']
     return res
-
-
-def cpu_baseline_batch(probs):
-    """The oracle on a bounded sample of the 64 problems: whole problems in draw order until
-    at least 6 M cells, one SSP-RK3 step each, one host thread."""
-    from oracle import grid as ogrid, rhs as orhs
-    gas = orhs.Gas()
-    cells, n, s = 0, 0, 0.0
-    log('batch64: oracle steps')
-    for c in probs:
-        if cells >= 6_000_000:
-            break
-        g = ogrid.Grid(c.ndim, c.n, c.bc, c.h, c.coords)
-        M = ogrid.node_metrics(g)
-        opts = orhs.Opts(rho_thr=c.extra['rho_thr'], p_thr=c.extra['p_thr'])
-        t0 = time.perf_counter()
-        orhs.rk3_step(c.Q, 0.0, 1e30, g, gas, opts, 'hybrid', M)
-        s += time.perf_counter() - t0
-        cells += c.cells
-        n += 1
-    return {'value': round(cells / s / 1e6, 4), 'unit': 'Mcell-updates/s', 'cores': 1, 'kind': 'oracle',
-            'sample': 'one SSP-RK3 step of the first %d problems in draw order (%d cells); %.1f s' % (n, cells, s)}
 
 
 WORKLOADS = {'ramp3d': ramp3d, 'triple_point': triple_point, 'batch64': batch64}
@@ -586,6 +774,9 @@ def main():
         print('bench.py: this build measures one GPU only (one process, one MI355X); '
               '--gpus %d is not supported' % args.gpus, file=sys.stderr)
         sys.exit(2)
+    names = list(WORKLOADS) if args.workload == 'all' else [args.workload]
+    # the oracle runs on the host cores first, before this process touches the GPU
+    cpu = cpu_baselines(names) if not args.no_cpu_baseline else None
     import torch
     torch.cuda.set_device(0)
     if args.copy_probe_mib > 0:
@@ -595,10 +786,9 @@ def main():
         torch.cuda.synchronize()
         del a, b
         torch.cuda.empty_cache()
-    names = list(WORKLOADS) if args.workload == 'all' else [args.workload]
     results = {}
     for nm in names:
-        results[nm] = WORKLOADS[nm](args, args.variants == 'all', not args.no_cpu_baseline)
+        results[nm] = WORKLOADS[nm](args, args.variants == 'all', cpu)
         torch.cuda.empty_cache()
     head = results[names[0]]
     out = {
@@ -616,6 +806,7 @@ def main():
         'data': 'synthetic: seeded generator states',
         'config': {'workload': head['workload'], 'cells': head['cells'], 'parallelism': 'single GPU'},
         'roofline': head.get('roofline'),
+        'roofline_step_floor': head.get('roofline_step_floor'),
         'hbm_step': head.get('hbm_step'),
         'cpu_baseline': head.get('cpu_baseline'),
         'nonphysical_nodes': head.get('nonphysical_nodes'),

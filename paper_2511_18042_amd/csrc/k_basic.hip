@@ -181,7 +181,10 @@ __global__ void __launch_bounds__(256) k_any_flag(const Prob* __restrict__ probs
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < P.total; t += gridDim.x * blockDim.x)
       if (P.f[t]) found = 1;
   }
-  if (__any(found) && (threadIdx.x & 63) == 0) atomicOr(P.any_flag, 1);
+  // one atomic per wave that found a flag, and none once the word is set (many waves find
+  // flags in a troubled field; atomics on one address serialise)
+  if (__any(found) && (threadIdx.x & 63) == 0 && __atomic_load_n(P.any_flag, __ATOMIC_RELAXED) == 0)
+    atomicOr(P.any_flag, 1);
 }
 
 // ------------------------------------------------------------------ compacted per-cell hybrid
@@ -204,14 +207,21 @@ __global__ void __launch_bounds__(256) k_all_flag(const Prob* __restrict__ probs
     int idx = pos_to_idx(P, c.i, c.j, c.k0);
     for (int k = c.k0; k < c.k1; ++k, idx += P.s[2]) clear |= P.ft[idx] == 0;
   }
-  if (__any(clear) && (threadIdx.x & 63) == 0) atomicAnd(P.all_flag, 0);
+  if (__any(clear) && (threadIdx.x & 63) == 0 && __atomic_load_n(P.all_flag, __ATOMIC_RELAXED) != 0)
+    atomicAnd(P.all_flag, 0);
 }
 
 // Work queue of the C-GBR interfaces along d: the interfaces i+1/2 of the interior lines
-// (i from -1 to n-1, stored by their left node) with ft_i | ft_{i+1}, appended in node
-// order with one atomic per wave (ballot + prefix count), so that a queue's neighbouring
-// entries are mostly neighbouring nodes.  Only when some, but not all, interfaces are C-GBR.
+// (i from -1 to n-1, stored by their left node) with ft_i | ft_{i+1}.  Each workgroup scans
+// one chunk of QCHUNK interfaces in node order, collects its entries in LDS (a ballot and a
+// prefix count per wave, one LDS atomic per wave) and appends them with a single global
+// atomic, so that neighbouring queue entries are mostly neighbouring nodes.  Only when some,
+// but not all, interfaces are C-GBR.
+constexpr int QCHUNK = 4096;
+
 __global__ void __launch_bounds__(256) k_gbr_queue(const Prob* __restrict__ probs, int d) {
+  __shared__ int list[QCHUNK];
+  __shared__ int n_loc, base;
   const Prob& P = probs[blockIdx.y];
   if (d >= P.ndim || gate_skip(P, GATE_MIXED)) return;
   int E[3], o[3];
@@ -220,11 +230,14 @@ __global__ void __launch_bounds__(256) k_gbr_queue(const Prob* __restrict__ prob
     o[l] = P.g[l] - (l == d ? 1 : 0);
   }
   const long long tot = (long long)E[0] * E[1] * E[2];
+  const long long c0 = (long long)blockIdx.x * QCHUNK;
+  if (c0 >= tot) return;
   const int s = P.s[d];
-  int* q = P.gq + (size_t)d * P.total;
   const int lane = threadIdx.x & 63;
-  for (long long b0 = (long long)blockIdx.x * blockDim.x; b0 < tot; b0 += (long long)gridDim.x * blockDim.x) {
-    const long long t = b0 + threadIdx.x;
+  if (threadIdx.x == 0) n_loc = 0;
+  __syncthreads();
+  for (int r = 0; r < QCHUNK; r += 256) {
+    const long long t = c0 + r + threadIdx.x;
     int idx = 0, flag = 0;
     if (t < tot) {
       const int i = (int)(t % E[0]) + o[0];
@@ -235,11 +248,16 @@ __global__ void __launch_bounds__(256) k_gbr_queue(const Prob* __restrict__ prob
     }
     const unsigned long long m = __ballot(flag);
     const int cnt = __popcll(m);
-    int base = 0;
-    if (lane == 0 && cnt) base = atomicAdd(&P.gcount[d], cnt);
-    base = __shfl(base, 0);
-    if (flag) q[base + __popcll(m & ((1ull << lane) - 1ull))] = idx;
+    int off = 0;
+    if (lane == 0 && cnt) off = atomicAdd(&n_loc, cnt);
+    off = __shfl(off, 0);
+    if (flag) list[off + __popcll(m & ((1ull << lane) - 1ull))] = idx;
   }
+  __syncthreads();
+  if (threadIdx.x == 0) base = n_loc ? atomicAdd(&P.gcount[d], n_loc) : 0;
+  __syncthreads();
+  int* q = P.gq + (size_t)d * P.total + base;
+  for (int i = threadIdx.x; i < n_loc; i += blockDim.x) q[i] = list[i];
 }
 
 // Separable box dilation by r nodes along direction d.
@@ -573,8 +591,9 @@ void launch_hyb_queue(const Launch& L, int ndim) {
   for (int d = 0; d < ndim; ++d) {
     long long tot = 1;
     for (int l = 0; l < 3; ++l) tot *= L.max_n[l] + (l == d ? 1 : 0);
-    LG_TIMED(L, KC_FLAGS, hipLaunchKernelGGL(k_gbr_queue, grid_for(tot, L.nprob, 256, 16384), dim3(256), 0,
-                                             L.stream, L.probs, d));
+    const unsigned chunks = (unsigned)std::max<long long>(1, (tot + QCHUNK - 1) / QCHUNK);
+    LG_TIMED(L, KC_FLAGS, hipLaunchKernelGGL(k_gbr_queue, dim3(chunks, L.nprob), dim3(256), 0, L.stream, L.probs,
+                                             d));
   }
 }
 

@@ -665,6 +665,7 @@ struct TileArgs {
   int d, TX, accumulate, rk, stage, mask, skip_if_any;
   double a, b;
   int keep_ft;   // filter of a per-cell hybrid stage: nodes in the dilated troubled set keep their values
+  int dense_only;   // MIG4 gradients of a per-cell stage: only when most lines are listed (dense_lines)
 };
 
 // the LDS index of (variable q, column c, position p) is (q * TX + c) * Lin + p
@@ -701,6 +702,7 @@ k_line_tiles(const Prob* __restrict__ probs, TileArgs A) {
   const int d = A.d, TX = A.TX;
   if (d >= P.ndim || !tile_use(P, d, KIND, A.mask)) return;
   if (gate_skip(P, A.skip_if_any)) return;
+  if (A.dense_only && !dense_lines(P, d)) return;
   int Lin, off, U, la, lb, ba, bb;
   tile_geom(P, d, KIND, Lin, off, U, la, lb, ba, bb);
   if (5 * TX * Lin > TILE_ELEMS || TX > TILE_MAX_TX) return;   // the host sizes TX so that this never holds
@@ -1038,16 +1040,16 @@ void launch_filter(const Launch& L, StateRef ref, int d, int mode) {
 }
 
 template <typename R>
-void launch_grad_c4_tiles(const Launch& L, StateRef ref, int d, int skip_if_any) {
+void launch_grad_c4_tiles(const Launch& L, StateRef ref, int d, int skip_if_any, int dense_only) {
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   if (L.ctile[TK_GRAD4][d])
     launch_tiles<R, TK_GRAD4>(L, KC_GRAD_C4, L.max_N[d], L.max_N[o1], L.max_N[o2],
                               TileArgs{ref, RKRef{nullptr, nullptr, nullptr}, d, 1, 0, 0, 0, L.tile_mask, skip_if_any,
-                                       0.0, 0.0, 0});
+                                       0.0, 0.0, 0, dense_only});
 }
 
-template void launch_grad_c4_tiles<float>(const Launch&, StateRef, int, int);
-template void launch_grad_c4_tiles<double>(const Launch&, StateRef, int, int);
+template void launch_grad_c4_tiles<float>(const Launch&, StateRef, int, int, int);
+template void launch_grad_c4_tiles<double>(const Launch&, StateRef, int, int, int);
 template void launch_grad_c6<float>(const Launch&, StateRef, int);
 template void launch_grad_c6<double>(const Launch&, StateRef, int);
 template void launch_c6_faces<float>(const Launch&, StateRef, int, int, const RKRef*, int, double, double);

@@ -98,13 +98,17 @@ __global__ void __launch_bounds__(256) k_grad_c4(const Prob* __restrict__ probs,
   const Prob& P = probs[blockIdx.y];
   if (d >= P.ndim || skip_launch(P, skip_if_any)) return;
   if (use_pcr(P, d)) return;   // done by the PCR kernel
-  if (!region && tile_use(P, d, TK_GRAD4, mask)) return;   // done in LDS tiles
+  // region 1: the listed lines (unless most lines are listed); 2: every line, when most are
+  if (region == 1 && dense_lines(P, d)) return;
+  if (region == 2 && !dense_lines(P, d)) return;
+  const bool listed = region == 1;
+  if (!listed && tile_use(P, d, TK_GRAD4, mask)) return;   // done in LDS tiles
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   const int nlines = P.N[o1] * P.N[o2];
-  const int cnt = region ? P.lcount[d] : nlines;   // compacted list of lines that need solving
+  const int cnt = listed ? P.lcount[d] : nlines;   // compacted list of lines that need solving
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= cnt) return;
-  const int line = region ? P.llist[d][t] : t;
+  const int line = listed ? P.llist[d][t] : t;
   const double* Q = ref.state(P);
   R* G = static_cast<R*>(P.G[d]);
   const size_t T = P.total;
@@ -208,13 +212,17 @@ __global__ void __launch_bounds__(256) k_grad_c4_pcr(const Prob* __restrict__ pr
   const Prob& P = probs[blockIdx.y];
   if (d >= P.ndim || skip_launch(P, skip_if_any)) return;
   if (!use_pcr(P, d)) return;   // the lane-per-line kernel does these
-  if (!region && tile_use(P, d, TK_GRAD4, mask)) return;   // done in LDS tiles
+  // region 1: the listed lines (unless most lines are listed); 2: every line, when most are
+  if (region == 1 && dense_lines(P, d)) return;
+  if (region == 2 && !dense_lines(P, d)) return;
+  const bool listed = region == 1;
+  if (!listed && tile_use(P, d, TK_GRAD4, mask)) return;   // done in LDS tiles
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   const int nlines = P.N[o1] * P.N[o2];
-  const int cnt = region ? P.lcount[d] : nlines;   // compacted list of lines that need solving
+  const int cnt = listed ? P.lcount[d] : nlines;   // compacted list of lines that need solving
   // persistent workgroups walk the (line, primitive) items
   for (int blk = blockIdx.x; blk < 5 * cnt; blk += gridDim.x) {
-  const int line = region ? P.llist[d][blk % cnt] : blk % nlines, q = blk / cnt;
+  const int line = listed ? P.llist[d][blk % cnt] : blk % nlines, q = blk / cnt;
   const bool periodic = P.bc[d][0] == BC_PERIODIC;
   const int g = P.g[d], N = P.N[d], n = P.n[d];
   const int L = periodic ? n : N;
@@ -319,21 +327,41 @@ template <typename R>
 void launch_grad_c4(const Launch& L, StateRef ref, int d, int skip_if_any, int region) {
   // each problem's direction is taken by exactly one kernel: LDS line tiles (region-free
   // launches, tile_use), PCR in LDS with persistent workgroups over the (line, primitive)
-  // items, or one lane per line
-  if (!region) launch_grad_c4_tiles<R>(L, ref, d, skip_if_any);
-  const int mask = region ? 0 : L.tile_mask;
-  if (L.c4_rest_pcr[d] || (region && L.pcr_dir[d])) {
+  // items, or one lane per line.  With a region (per-cell hybrid) the listed lines are
+  // solved, or, when most lines are listed, every line by the region-free kernels (the
+  // device picks one of the two sets).
+  auto full = [&](int reg) {
+    launch_grad_c4_tiles<R>(L, ref, d, skip_if_any, reg == 2);
+    if (L.c4_rest_pcr[d]) {
+      const long long N = std::min<long long>(L.max_N[d], PCR_MAX_LINE);
+      const unsigned lds = (unsigned)(2 * N * sizeof(double));
+      long long blocks = std::min<long long>(5 * L.lines[d], L.pcr_blocks > 0 ? L.pcr_blocks : 16384);
+      LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c4_pcr<R>, dim3((unsigned)blocks, L.nprob), dim3(256), lds,
+                                                 L.stream, L.probs, ref, d, skip_if_any, reg, L.tile_mask));
+    }
+    if (L.c4_rest_thomas[d]) {
+      long long b = (L.lines[d] + 255) / 256;
+      LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c4<R>, dim3((unsigned)b, L.nprob), dim3(256), 0, L.stream,
+                                                 L.probs, ref, d, skip_if_any, reg, L.tile_mask));
+    }
+  };
+  if (!region) {
+    full(0);
+    return;
+  }
+  if (L.pcr_dir[d]) {
     const long long N = std::min<long long>(L.max_N[d], PCR_MAX_LINE);
     const unsigned lds = (unsigned)(2 * N * sizeof(double));
     long long blocks = std::min<long long>(5 * L.lines[d], L.pcr_blocks > 0 ? L.pcr_blocks : 16384);
     LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c4_pcr<R>, dim3((unsigned)blocks, L.nprob), dim3(256), lds,
-                                               L.stream, L.probs, ref, d, skip_if_any, region, mask));
+                                               L.stream, L.probs, ref, d, skip_if_any, 1, 0));
   }
-  if (L.c4_rest_thomas[d] || (region && L.thomas_dir[d])) {
+  if (L.thomas_dir[d]) {
     long long b = (L.lines[d] + 255) / 256;
     LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL(k_grad_c4<R>, dim3((unsigned)b, L.nprob), dim3(256), 0, L.stream,
-                                               L.probs, ref, d, skip_if_any, region, mask));
+                                               L.probs, ref, d, skip_if_any, 1, 0));
   }
+  full(2);
 }
 
 template void launch_grad_explicit<float>(const Launch&, int, int, int, int);

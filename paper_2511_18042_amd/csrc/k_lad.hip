@@ -677,10 +677,7 @@ __global__ void __launch_bounds__(256) k_hyb_assemble(const Prob* __restrict__ p
   const IX T = (IX)P.total;
   const int sz = P.s[2];
   const bool z3 = P.ndim == 3;
-  const R* FLd[3] = {static_cast<const R*>(P.FL[0]), static_cast<const R*>(P.FL[1]),
-                     static_cast<const R*>(P.FL[2])};
-  const R* FGd[3] = {static_cast<const R*>(P.FG[0]), static_cast<const R*>(P.FG[1]),
-                     static_cast<const R*>(P.FG[2])};
+  const R* Fz = static_cast<const R*>(P.FL[2]);
   const uint8_t* ft = P.ft;
   double* dQ = ref.deriv(P);
   const double* Un = rr.Un ? rr.Un : P.Q;
@@ -689,30 +686,57 @@ __global__ void __launch_bounds__(256) k_hyb_assemble(const Prob* __restrict__ p
   const double dt = mode ? *P.dt : 0.0;
   int bad = 0;
   int idx = pos_to_idx(P, c.i, c.j, c.k0);
+  R qz[5][5];   // planes k-2 .. k+2 of the zeta node fluxes
+  if (z3)
+    for (int p = 1; p < 5; ++p)
+      for (int q = 0; q < 5; ++q) qz[p][q] = gld<R, O32>(Fz, (IX)q * T + (IX)(idx + (p - 3) * sz));
+  int fz_m = z3 ? ft[idx - sz] : 0;   // flag of plane k-1
   const bool mplane = P.met_planar;
   const double Jcol = met64(P, 9, idx);
   for (int k = c.k0; k < c.k1; ++k, idx += sz) {
+    if (z3) {
+      for (int p = 0; p < 4; ++p)
+        for (int q = 0; q < 5; ++q) qz[p][q] = qz[p + 1][q];
+      for (int q = 0; q < 5; ++q) qz[4][q] = gld<R, O32>(Fz, (IX)q * T + (IX)(idx + 2 * sz));
+    }
     const double J = mplane ? Jcol : met64(P, 9, idx);
     const int f0 = ft[idx];
     double Lq[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int d = 0; d < 3; ++d) {
+    // xi and eta: the five-point stencil of the node fluxes gives both I4 interfaces
+    for (int d = 0; d < 2; ++d) {
       if (d >= P.ndim) break;
       const int s = P.s[d];
       const bool gp = (f0 | ft[idx + s]) != 0, gm = (ft[idx - s] | f0) != 0;
-      const R* F = FLd[d];
-      const R* G = FGd[d];
+      const R* F = static_cast<const R*>(P.FL[d]);
+      const R* G = static_cast<const R*>(P.FG[d]);
+      const IX si = (IX)s;
       for (int q = 0; q < 5; ++q) {
         const IX o = (IX)q * T + (IX)idx;
-        const IX si = (IX)s;
         R fp, fm;
-        if (gp) fp = gld<R, O32>(G, o);
-        else fp = i4v(gld<R, O32>(F, o - si), gld<R, O32>(F, o), gld<R, O32>(F, o + si), gld<R, O32>(F, o + 2 * si));
-        if (gm) fm = gld<R, O32>(G, o - si);
-        else fm = i4v(gld<R, O32>(F, o - 2 * si), gld<R, O32>(F, o - si), gld<R, O32>(F, o), gld<R, O32>(F, o + si));
+        if (gp && gm) {
+          fp = gld<R, O32>(G, o);
+          fm = gld<R, O32>(G, o - si);
+        } else {
+          const R m2 = gld<R, O32>(F, o - 2 * si), m1 = gld<R, O32>(F, o - si), c0 = gld<R, O32>(F, o),
+                  p1 = gld<R, O32>(F, o + si), p2 = gld<R, O32>(F, o + 2 * si);
+          fp = gp ? gld<R, O32>(G, o) : i4v(m1, c0, p1, p2);
+          fm = gm ? gld<R, O32>(G, o - si) : i4v(m2, m1, c0, p1);
+        }
         Lq[q] = Lq[q] + -J * ((double)fp - (double)fm);
       }
     }
-    (void)z3;
+    if (z3) {
+      const int fz_p = ft[idx + sz];
+      const bool gp = (f0 | fz_p) != 0, gm = (fz_m | f0) != 0;
+      const R* G = static_cast<const R*>(P.FG[2]);
+      for (int q = 0; q < 5; ++q) {
+        const IX o = (IX)q * T + (IX)idx;
+        const R fp = gp ? gld<R, O32>(G, o) : i4v(qz[1][q], qz[2][q], qz[3][q], qz[4][q]);
+        const R fm = gm ? gld<R, O32>(G, o - (IX)sz) : i4v(qz[0][q], qz[1][q], qz[2][q], qz[3][q]);
+        Lq[q] = Lq[q] + -J * ((double)fp - (double)fm);
+      }
+      fz_m = f0;
+    }
     if (mode == 0) {
       for (int q = 0; q < 5; ++q) gst<double, O32>(dQ, (IX)q * T + (IX)idx, Lq[q]);
     } else {

@@ -146,6 +146,14 @@ __device__ __forceinline__ bool gate_skip(const Prob& P, int gate) {
   return !(any && !all);
 }
 
+// Per-cell stages solve the MIG4 lines that cross the C-GBR input region fg (compacted
+// list, lcount[d] lines); when more than half of all lines of d are listed, the region-free
+// kernels solving every line are cheaper, and the device takes them instead.
+__device__ __forceinline__ bool dense_lines(const Prob& P, int d) {
+  const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+  return 2LL * P.lcount[d] > (long long)P.N[o1] * P.N[o2];
+}
+
 // Ghost image of position p along d for scalar intermediate fields (even parity; FIXED
 // faces behave as transmissive): the interior position whose value the ghost holds.
 __device__ __forceinline__ int scalar_image(const Prob& P, int d, int p) {

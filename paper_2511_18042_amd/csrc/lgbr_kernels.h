@@ -184,7 +184,7 @@ inline dim3 zm_grid(const Launch& L, int lo, int hi, int TX, int TY) {
 template <typename R> void launch_grad_explicit(const Launch& L, int d, int order, int skip_if_any, int region);
 template <typename R> void launch_grad_c4(const Launch& L, StateRef ref, int d, int skip_if_any, int region);
 // C4 gradients of whole lines in LDS tiles (region-free launches; see tile_use)
-template <typename R> void launch_grad_c4_tiles(const Launch& L, StateRef ref, int d, int skip_if_any);
+template <typename R> void launch_grad_c4_tiles(const Launch& L, StateRef ref, int d, int skip_if_any, int dense_only);
 // sensor and C-GBR viscous node fluxes
 template <typename R> void launch_sensor(const Launch& L, int skip_if_any, int region);
 template <typename R> void launch_gbr_viscflux(const Launch& L, int skip_if_any, int region);
