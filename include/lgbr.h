@@ -249,8 +249,11 @@ lg_status lg_get_tuning(const lg_ctx* ctx, int* seg, int* pcr_blocks, int* zc);
  * filter, 3 = MIG4 gradients outside per-cell hybrid stages) along direction d.  Where
  * allowed, tiles are used for the contiguous direction and for strided directions with
  * fewer than 32768 lines (bit 12 set: for strided directions whatever their line count);
- * other lines are solved by PCR per (line, variable) or one lane per line.  mask in
- * [0, 8191]; -1 restores the default (4095, all allowed, bit 12 clear).
+ * other lines are solved by PCR per (line, variable) or one lane per line.  The implicit
+ * filter along xi on bounded lines of 128 to 2048 unknowns uses the partition method (one
+ * wave per line and variable: segment solves joined through their end unknowns) unless bit
+ * 13 is set.  mask in [0, 16383]; -1 restores the default (4095: tiles allowed, bits 12
+ * and 13 clear).
  * lg_get_line_tiles returns the mask in effect (-1 for a null context).  Applies to later
  * calls and to batches created afterwards. */
 lg_status lg_set_line_tiles(lg_ctx* ctx, int mask);

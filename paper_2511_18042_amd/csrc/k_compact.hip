@@ -528,7 +528,9 @@ __device__ __forceinline__ bool filt_keep(const Prob& P, int mode, size_t node) 
 __global__ void __launch_bounds__(256) k_filter(const Prob* __restrict__ probs, StateRef ref, int d, int mask,
                                                 int mode) {
   const Prob& P = probs[blockIdx.y];
-  if (d >= P.ndim || !(P.falpha < 0.5) || tile_use(P, d, TK_FILTER, mask) || filt_pcr(P, d)) return;
+  if (d >= P.ndim || !(P.falpha < 0.5) || filt_part_use(P, d, mask) || tile_use(P, d, TK_FILTER, mask) ||
+      filt_pcr(P, d))
+    return;
   if (filt_skip(P, mode)) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int nl = interior_lines(P, d);
@@ -603,7 +605,9 @@ __global__ void __launch_bounds__(CPCR_THREADS) __attribute__((amdgpu_waves_per_
                                                     int mask, int mode) {
   extern __shared__ double lds[];
   const Prob& P = probs[blockIdx.y];
-  if (d >= P.ndim || !(P.falpha < 0.5) || tile_use(P, d, TK_FILTER, mask) || !filt_pcr(P, d)) return;
+  if (d >= P.ndim || !(P.falpha < 0.5) || filt_part_use(P, d, mask) || tile_use(P, d, TK_FILTER, mask) ||
+      !filt_pcr(P, d))
+    return;
   if (filt_skip(P, mode)) return;
   const int nlines = interior_lines(P, d);
   const bool periodic = P.bc[d][0] == BC_PERIODIC;
@@ -634,6 +638,158 @@ __global__ void __launch_bounds__(CPCR_THREADS) __attribute__((amdgpu_waves_per_
     for (int i = threadIdx.x; i < n; i += blockDim.x)
       if (!filt_keep(P, mode, lb0 + (size_t)(g + i) * sd)) phi[(size_t)(g + i) * sd] = r[i];
     __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ filter, partition method
+// Contiguous bounded lines of n interior unknowns (the tridiagonal [a, 1, a] system of the
+// filter with the boundary neighbours moved to the right-hand side), one wave per (line,
+// variable).  The line is staged in LDS with coalesced loads; lane s owns segment s of
+// nseg = min(64, n / 2) segments of length n / nseg or one more, solves its segment system
+// T y = r in registers, and the segments are joined through their first and last unknowns:
+// with u = T^{-1} e_1 and v = T^{-1} e_L (a segment's response to its left and right
+// neighbours, the same for every segment of one length),
+//   x = y - a u B_{s-1} - a v A_{s+1},   A_s = x_first(s), B_s = x_last(s),
+// and eliminating forward (B_{s-1} = gb - Gb A_s) and back (A_s = ga - Ga A_{s+1}) solves
+// the 2 nseg joint unknowns on one lane.  Then every lane corrects its segment, and the line
+// is written back.  Waves of a workgroup work on separate items and synchronise only among
+// their own lanes.
+constexpr int FPART_LMAX = 33;   // longest segment (n <= 2048 with 64 segments)
+constexpr int FPART_WAVES = 4;   // most (line, variable) items in flight per workgroup (one per wave)
+
+// orders the LDS accesses of the lanes of one wave (no other wave takes part)
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ void __launch_bounds__(64 * FPART_WAVES) k_filter_part(const Prob* __restrict__ probs, StateRef ref,
+                                                                  int mode, int nmax, int mask) {
+  extern __shared__ double dyn[];   // per wave: the staged line [nmax + 10], ga, gb, Ga, Gb [64 each]
+  __shared__ double tcp[FPART_LMAX], tinv[FPART_LMAX];
+  __shared__ double tu[2][FPART_LMAX], tv[2][FPART_LMAX];   // segment lengths base and base + 1
+  const Prob& P = probs[blockIdx.y];
+  if (!(P.falpha < 0.5) || !filt_part_use(P, 0, mask) || P.n[0] > nmax || filt_skip(P, mode)) return;
+  const int n = P.n[0], g = P.g[0], N = P.N[0];
+  const int nseg = min(64, n / 2);
+  const int base = n / nseg, extra = n % nseg;   // the first `extra` segments have base + 1
+  const double al = P.falpha;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  // segment factors (they depend on the row index only) and the responses u, v
+  if (threadIdx.x == 0) {
+    double c = 0.0;
+    for (int i = 0; i < base + 1; ++i) {
+      const double den = 1.0 - (i > 0 ? al * c : 0.0);
+      tinv[i] = 1.0 / den;
+      c = al / den;
+      tcp[i] = c;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {   // threads 0 / 1: u for base / base + 1; 2 / 3: v
+    const int which = threadIdx.x & 1, L = base + which;
+    const bool is_u = threadIdx.x < 2;
+    double* out = is_u ? tu[which] : tv[which];
+    double prev = 0.0;
+    for (int i = 0; i < L; ++i) {
+      const double rhs = is_u ? (i == 0 ? 1.0 : 0.0) : (i == L - 1 ? 1.0 : 0.0);
+      prev = (rhs - (i > 0 ? al * prev : 0.0)) * tinv[i];
+      out[i] = prev;
+    }
+    double y = out[L - 1];
+    for (int i = L - 2; i >= 0; --i) {
+      y = out[i] - tcp[i] * y;
+      out[i] = y;
+    }
+  }
+  __syncthreads();
+  double* f = dyn + (size_t)w * (nmax + 10 + 4 * 64);
+  double* ga = f + nmax + 10;
+  double* gb = ga + 64;
+  double* Ga = gb + 64;
+  double* Gb = Ga + 64;
+  const int nlines = interior_lines(P, 0);
+  const size_t T = P.total;
+  double* Q = ref.state(P);
+  const int L = base + (lane < extra ? 1 : 0);
+  const int j0 = lane * base + min(lane, extra);   // first unknown of this lane's segment
+  const int wl = lane < extra ? 1 : 0;             // which u / v table
+  for (int item = blockIdx.x * nw + w; item < 5 * nlines; item += gridDim.x * nw) {
+    const int line = item % nlines, q = item / nlines;
+    const size_t lb = interior_line_base(P, 0, line);
+    double* phi = Q + (size_t)q * T + lb;
+    for (int p = lane; p < N; p += 64) f[p] = phi[p];
+    wave_lds_sync();
+    double y[FPART_LMAX];
+    if (lane < nseg) {
+      double win[11];   // f[g + j - 5 .. g + j + 5] of the current unknown j
+      for (int k = 0; k < 10; ++k) win[k + 1] = f[g + j0 - 5 + k];
+      double prev = 0.0;
+#pragma unroll
+      for (int i = 0; i < FPART_LMAX; ++i) {
+        if (i < L) {
+          const int j = j0 + i;
+#pragma unroll
+          for (int k = 0; k < 10; ++k) win[k] = win[k + 1];
+          win[10] = f[g + j + 5];
+          double r = filt_rhs(P, win);
+          if (j == 0) r = r - al * f[g - 1];
+          if (j == n - 1) r = r - al * f[g + n];
+          prev = (r - (i > 0 ? al * prev : 0.0)) * tinv[i];
+          y[i] = prev;
+        }
+      }
+      const double ylast = prev;   // y_{L-1} = d_{L-1}
+      double v = prev;
+#pragma unroll
+      for (int i = FPART_LMAX - 2; i >= 0; --i) {
+        if (i < L - 1) {
+          v = y[i] - tcp[i] * v;
+          y[i] = v;
+        }
+      }
+      ga[lane] = y[0];
+      gb[lane] = ylast;
+    }
+    wave_lds_sync();
+    if (lane == 0) {
+      double gbp = 0.0, Gbp = 0.0;   // B_{s-1} = gbp - Gbp A_s
+      for (int sg = 0; sg < nseg; ++sg) {
+        const int lw = sg < extra ? 1 : 0, Ls = base + lw;
+        const double u1 = tu[lw][0], uL = tu[lw][Ls - 1], v1 = tv[lw][0], vL = tv[lw][Ls - 1];
+        const double da = 1.0 - al * u1 * Gbp;
+        const double gas = (ga[sg] - al * u1 * gbp) / da;
+        const double Gas = al * v1 / da;
+        const double gbs = gb[sg] - al * uL * gbp + al * uL * Gbp * gas;
+        const double Gbs = al * vL + al * uL * Gbp * Gas;
+        ga[sg] = gas;
+        gb[sg] = gbs;
+        Ga[sg] = Gas;
+        Gb[sg] = Gbs;
+        gbp = gbs;
+        Gbp = Gbs;
+      }
+      double An = 0.0;
+      for (int sg = nseg - 1; sg >= 0; --sg) {
+        const double A = ga[sg] - Ga[sg] * An;
+        gb[sg] = gb[sg] - Gb[sg] * An;
+        ga[sg] = A;
+        An = A;
+      }
+    }
+    wave_lds_sync();
+    if (lane < nseg) {
+      const double Bl = lane > 0 ? gb[lane - 1] : 0.0;
+      const double Ar = lane + 1 < nseg ? ga[lane + 1] : 0.0;
+#pragma unroll
+      for (int i = 0; i < FPART_LMAX; ++i)
+        if (i < L) f[g + j0 + i] = y[i] - al * tu[wl][i] * Bl - al * tv[wl][i] * Ar;
+    }
+    wave_lds_sync();
+    for (int p = lane; p < n; p += 64)
+      if (!filt_keep(P, mode, lb + (size_t)(g + p))) phi[g + p] = f[g + p];
+    wave_lds_sync();   // the next item's staging overwrites f
   }
 }
 
@@ -701,6 +857,7 @@ k_line_tiles(const Prob* __restrict__ probs, TileArgs A) {
   const Prob& P = probs[blockIdx.y];
   const int d = A.d, TX = A.TX;
   if (d >= P.ndim || !tile_use(P, d, KIND, A.mask)) return;
+  if (KIND == TK_FILTER && filt_part_use(P, d, A.mask)) return;   // partition-method kernel
   if (gate_skip(P, A.skip_if_any)) return;
   if (A.dense_only && !dense_lines(P, d)) return;
   int Lin, off, U, la, lb, ba, bb;
@@ -1024,6 +1181,17 @@ void launch_c6_faces(const Launch& L, StateRef ref, int d, int accumulate, const
 void launch_filter(const Launch& L, StateRef ref, int d, int mode) {
   launch_bc_cons(L, ref, d);
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+  if (d == 0 && L.fpart) {
+    // one wave per (line, variable); four waves per workgroup while their staged lines fit
+    // 60 KB of LDS, two otherwise (lines of up to 2048 unknowns)
+    const long long nmax = L.max_n[0];
+    const size_t per_wave = (size_t)(nmax + 10 + 4 * 64) * sizeof(double);
+    const int nw = 4 * per_wave <= 60 * 1024 ? 4 : 2;
+    const long long items = 5 * L.sweep_rows[0];
+    const unsigned blocks = (unsigned)std::max<long long>(1, std::min<long long>((items + nw - 1) / nw, 65536));
+    LG_TIMED(L, KC_FILTER, hipLaunchKernelGGL(k_filter_part, dim3(blocks, L.nprob), dim3(64 * nw), nw * per_wave,
+                                              L.stream, L.probs, ref, mode, (int)nmax, L.tile_mask));
+  }
   const SysLaunch sl = sys_launch(L, TK_FILTER, d);
   if (sl.tiles)
     launch_tiles<double, TK_FILTER>(L, KC_FILTER, L.max_N[d], L.max_n[o1], L.max_n[o2],

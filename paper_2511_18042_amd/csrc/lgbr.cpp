@@ -432,6 +432,10 @@ void fill_launch(Launch& L, const Prob& P) {
     if (P.lad_c6 || P.falpha < 0.5) {
       for (int k = 0; k < 3; ++k) {
         if (k == lg::TK_FILTER ? !(P.falpha < 0.5) : !P.lad_c6) continue;
+        if (k == lg::TK_FILTER && lg::filt_part_use(P, d, L.tile_mask)) {
+          L.fpart = 1;
+          continue;
+        }
         const bool pcr = k == lg::TK_GRAD6 ? lg::c6_grad_pcr(P, d)
                                            : (k == lg::TK_FACES ? lg::c6_face_pcr(P, d) : lg::filt_pcr(P, d));
         if (lg::tile_use(P, d, k, L.tile_mask)) L.ctile[k][d] = 1;
@@ -977,13 +981,15 @@ lg_status lg_set_tuning(lg_ctx* c, int seg, int pcr_blocks, int zc) {
 }
 
 lg_status lg_set_line_tiles(lg_ctx* c, int mask) {
-  if (!c || mask < -1 || mask > (lg::TILE_MASK_ALL | lg::TILE_MASK_FORCE_STRIDED)) return LG_EINVAL;
+  if (!c || mask < -1 || mask > (lg::TILE_MASK_ALL | lg::TILE_MASK_FORCE_STRIDED | lg::TILE_MASK_NO_PART))
+    return LG_EINVAL;
   c->L.tile_mask = mask < 0 ? lg::TILE_MASK_DEFAULT : mask;
   for (int d = 0; d < 3; ++d) {
     for (int k = 0; k < 3; ++k) c->L.cpcr[k][d] = c->L.cthomas[k][d] = 0;
     for (int k = 0; k < 4; ++k) c->L.ctile[k][d] = 0;
     c->L.c4_rest_pcr[d] = c->L.c4_rest_thomas[d] = 0;
   }
+  c->L.fpart = 0;
   fill_launch(c->L, c->hp);
   return LG_OK;
 }

@@ -93,6 +93,7 @@ struct Launch {
   int pcr_blocks;          // persistent workgroups of the PCR line solves (0: heuristic)
   int zc;                  // planes per chunk of the z-marching kernels (0: heuristic)
   int item_blocks;         // persistent workgroups of the compacted C-GBR interface pass (0: 2048)
+  int fpart;               // some problem filters along xi with the partition-method kernel
   Prof* prof;              // optional launch timing (null: off)
 };
 
@@ -220,6 +221,7 @@ void launch_filter(const Launch& L, StateRef ref, int d, int mode);
 enum { TK_GRAD6 = 0, TK_FACES = 1, TK_FILTER = 2, TK_GRAD4 = 3 };
 constexpr int TILE_MASK_ALL = 0xFFF;
 constexpr int TILE_MASK_FORCE_STRIDED = 0x1000;   // tiles on strided directions whatever their line count
+constexpr int TILE_MASK_NO_PART = 0x2000;          // filter along xi without the partition-method kernel
 constexpr int TILE_MASK_DEFAULT = TILE_MASK_ALL;
 constexpr int TILE_ELEMS = 6144;   // doubles per tile (48 KB of LDS)
 // lanes per tile workgroup: contiguous lines take 512 (128 VGPRs, four waves per SIMD);
@@ -260,6 +262,11 @@ __host__ __device__ inline bool c6_grad_pcr(const Prob& P, int d) {
 __host__ __device__ inline bool c6_face_pcr(const Prob& P, int d) {
   const bool periodic = P.bc[d][0] == BC_PERIODIC;
   return d == 0 && P.ndim > 1 && P.n[d] <= 3990 && !(periodic && P.n[d] < (2 << LG_PCR_STEPS));
+}
+// the implicit filter along xi on bounded lines of 128..2048 unknowns: partition method
+// (k_filter_part) unless mask bit 13 turns it off
+__host__ __device__ inline bool filt_part_use(const Prob& P, int d, int mask) {
+  return !(mask & TILE_MASK_NO_PART) && d == 0 && P.bc[0][0] != BC_PERIODIC && P.n[0] >= 128 && P.n[0] <= 2048;
 }
 __host__ __device__ inline bool filt_pcr(const Prob& P, int d) {
   const bool periodic = P.bc[d][0] == BC_PERIODIC;
