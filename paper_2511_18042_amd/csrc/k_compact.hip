@@ -645,17 +645,23 @@ __global__ void __launch_bounds__(CPCR_THREADS) __attribute__((amdgpu_waves_per_
 // Contiguous bounded lines of n interior unknowns (the tridiagonal [a, 1, a] system of the
 // filter with the boundary neighbours moved to the right-hand side), one wave per (line,
 // variable).  The line is staged in LDS with coalesced loads; lane s owns segment s of
-// nseg = min(64, n / 2) segments of length n / nseg or one more, solves its segment system
-// T y = r in registers, and the segments are joined through their first and last unknowns:
-// with u = T^{-1} e_1 and v = T^{-1} e_L (a segment's response to its left and right
-// neighbours, the same for every segment of one length),
-//   x = y - a u B_{s-1} - a v A_{s+1},   A_s = x_first(s), B_s = x_last(s),
-// and eliminating forward (B_{s-1} = gb - Gb A_s) and back (A_s = ga - Ga A_{s+1}) solves
-// the 2 nseg joint unknowns on one lane.  Then every lane corrects its segment, and the line
-// is written back.  Waves of a workgroup work on separate items and synchronise only among
-// their own lanes.
+// nseg = min(64, n / 2) segments of length n / nseg or one more and solves its segment
+// system T y = r in registers.  With u = T^{-1} e_1 and v = T^{-1} e_L (a segment's response
+// to its left and right neighbours, the same for every segment of one length) the solution
+// is x = y - a u B_{s-1} - a v A_{s+1}, where A_s and B_s are the first and last unknowns of
+// segment s.  Eliminating forward, B_{s-1} = gb_{s-1} - Gb_{s-1} A_s, and back,
+// A_s = ga_s - Ga_s A_{s+1}: the factors da_s = 1 - a u1 Gb_{s-1}, Ga_s = a v1 / da_s and
+// Gb_s = a vL + a uL Gb_{s-1} Ga_s do not depend on the data (tables per workgroup), and the
+// data-dependent parts are first-order linear recurrences across the lanes,
+//   gb_s = -(a uL / da_s) gb_{s-1} + yb_s + a uL Gb_{s-1} ya_s / da_s,
+//   A_s = -Ga_s A_{s+1} + ga_s,   ga_s = (ya_s - a u1 gb_{s-1}) / da_s,
+// solved by two wave-wide scans (six shuffle steps each).  Waves of a workgroup work on
+// separate items and synchronise only among their own lanes.
 constexpr int FPART_LMAX = 33;   // longest segment (n <= 2048 with 64 segments)
+constexpr int FPART_LSHORT = 17;  // segments of lines of at most 1088 unknowns (register arrays sized to it)
 constexpr int FPART_WAVES = 4;   // most (line, variable) items in flight per workgroup (one per wave)
+// LDS doubles of one wave's staged line (interior + ghosts, one pad slot per 16)
+__host__ __device__ inline int fpart_lds_slots(int nmax) { return (nmax + 10) + (nmax + 10) / 16 + 1; }
 
 // orders the LDS accesses of the lanes of one wave (no other wave takes part)
 __device__ __forceinline__ void wave_lds_sync() {
@@ -664,19 +670,49 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// inclusive scan of x_s = m_s x_{s-1} + c_s over lanes 0..63 (x_{-1} = 0); returns x_lane
+__device__ __forceinline__ double scan_up(double m, double c, int lane) {
+#pragma unroll
+  for (int k = 1; k < 64; k <<= 1) {
+    const double mp = __shfl_up(m, k), cp = __shfl_up(c, k);
+    if (lane >= k) {
+      c = m * cp + c;
+      m = m * mp;
+    }
+  }
+  return c;
+}
+
+// the same recurrence run from lane 63 down to lane 0: x_s = m_s x_{s+1} + c_s (x_64 = 0)
+__device__ __forceinline__ double scan_down(double m, double c, int lane) {
+#pragma unroll
+  for (int k = 1; k < 64; k <<= 1) {
+    const double mp = __shfl_down(m, k), cp = __shfl_down(c, k);
+    if (lane + k < 64) {
+      c = m * cp + c;
+      m = m * mp;
+    }
+  }
+  return c;
+}
+
+template <int LM>
 __global__ void __launch_bounds__(64 * FPART_WAVES) k_filter_part(const Prob* __restrict__ probs, StateRef ref,
                                                                   int mode, int nmax, int mask) {
-  extern __shared__ double dyn[];   // per wave: the staged line [nmax + 10], ga, gb, Ga, Gb [64 each]
+  extern __shared__ double dyn[];   // per wave: the staged line [nmax + 10]
   __shared__ double tcp[FPART_LMAX], tinv[FPART_LMAX];
   __shared__ double tu[2][FPART_LMAX], tv[2][FPART_LMAX];   // segment lengths base and base + 1
+  __shared__ double tda[64], tGa[64], tGb[64];
   const Prob& P = probs[blockIdx.y];
   if (!(P.falpha < 0.5) || !filt_part_use(P, 0, mask) || P.n[0] > nmax || filt_skip(P, mode)) return;
+  if (P.n[0] / min(64, P.n[0] / 2) + 1 > LM) return;   // segments longer than the register arrays
   const int n = P.n[0], g = P.g[0], N = P.N[0];
   const int nseg = min(64, n / 2);
   const int base = n / nseg, extra = n % nseg;   // the first `extra` segments have base + 1
   const double al = P.falpha;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  // segment factors (they depend on the row index only) and the responses u, v
+  // segment factors (they depend on the row index only), the responses u, v, and the
+  // data-independent elimination factors of the joint unknowns
   if (threadIdx.x == 0) {
     double c = 0.0;
     for (int i = 0; i < base + 1; ++i) {
@@ -704,91 +740,89 @@ __global__ void __launch_bounds__(64 * FPART_WAVES) k_filter_part(const Prob* __
     }
   }
   __syncthreads();
-  double* f = dyn + (size_t)w * (nmax + 10 + 4 * 64);
-  double* ga = f + nmax + 10;
-  double* gb = ga + 64;
-  double* Ga = gb + 64;
-  double* Gb = Ga + 64;
+  if (threadIdx.x == 0) {
+    double Gbp = 0.0;
+    for (int sg = 0; sg < nseg; ++sg) {
+      const int lw = sg < extra ? 1 : 0, Ls = base + lw;
+      const double da = 1.0 - al * tu[lw][0] * Gbp;
+      const double Ga = al * tv[lw][0] / da;
+      tda[sg] = da;
+      tGa[sg] = Ga;
+      tGb[sg] = al * tv[lw][Ls - 1] + al * tu[lw][Ls - 1] * Gbp * Ga;
+      Gbp = tGb[sg];
+    }
+  }
+  __syncthreads();
+  // the staged line, padded by one slot every 16 so that the lanes' segments (16 and more
+  // apart) fall into different LDS banks
+  double* f = dyn + (size_t)w * fpart_lds_slots(nmax);
+  auto F = [f](int p) -> double& { return f[p + (p >> 4)]; };
   const int nlines = interior_lines(P, 0);
   const size_t T = P.total;
   double* Q = ref.state(P);
+  const bool act = lane < nseg;
   const int L = base + (lane < extra ? 1 : 0);
   const int j0 = lane * base + min(lane, extra);   // first unknown of this lane's segment
   const int wl = lane < extra ? 1 : 0;             // which u / v table
+  const double u1 = act ? tu[wl][0] : 0.0, uL = act ? tu[wl][L - 1] : 0.0;
+  const double da = act ? tda[lane] : 1.0, Ga = act ? tGa[lane] : 0.0, Gb = act ? tGb[lane] : 0.0;
+  const double Gbm = act && lane > 0 ? tGb[lane - 1] : 0.0;
   for (int item = blockIdx.x * nw + w; item < 5 * nlines; item += gridDim.x * nw) {
     const int line = item % nlines, q = item / nlines;
     const size_t lb = interior_line_base(P, 0, line);
     double* phi = Q + (size_t)q * T + lb;
-    for (int p = lane; p < N; p += 64) f[p] = phi[p];
+    for (int p = lane; p < N; p += 64) F(p) = phi[p];
     wave_lds_sync();
-    double y[FPART_LMAX];
-    if (lane < nseg) {
-      double win[11];   // f[g + j - 5 .. g + j + 5] of the current unknown j
-      for (int k = 0; k < 10; ++k) win[k + 1] = f[g + j0 - 5 + k];
+    double y[LM];
+    double ya = 0.0, yb = 0.0;
+    if (act) {
+      double win[11];   // the staged values g + j - 5 .. g + j + 5 of the current unknown j
+      for (int k = 0; k < 10; ++k) win[k + 1] = F(g + j0 - 5 + k);
       double prev = 0.0;
 #pragma unroll
-      for (int i = 0; i < FPART_LMAX; ++i) {
+      for (int i = 0; i < LM; ++i) {
         if (i < L) {
           const int j = j0 + i;
 #pragma unroll
           for (int k = 0; k < 10; ++k) win[k] = win[k + 1];
-          win[10] = f[g + j + 5];
+          win[10] = F(g + j + 5);
           double r = filt_rhs(P, win);
-          if (j == 0) r = r - al * f[g - 1];
-          if (j == n - 1) r = r - al * f[g + n];
+          if (j == 0) r = r - al * F(g - 1);
+          if (j == n - 1) r = r - al * F(g + n);
           prev = (r - (i > 0 ? al * prev : 0.0)) * tinv[i];
           y[i] = prev;
         }
       }
-      const double ylast = prev;   // y_{L-1} = d_{L-1}
+      yb = prev;   // y_{L-1} = d_{L-1}
       double v = prev;
 #pragma unroll
-      for (int i = FPART_LMAX - 2; i >= 0; --i) {
+      for (int i = LM - 2; i >= 0; --i) {
         if (i < L - 1) {
           v = y[i] - tcp[i] * v;
           y[i] = v;
         }
       }
-      ga[lane] = y[0];
-      gb[lane] = ylast;
+      ya = y[0];
     }
-    wave_lds_sync();
-    if (lane == 0) {
-      double gbp = 0.0, Gbp = 0.0;   // B_{s-1} = gbp - Gbp A_s
-      for (int sg = 0; sg < nseg; ++sg) {
-        const int lw = sg < extra ? 1 : 0, Ls = base + lw;
-        const double u1 = tu[lw][0], uL = tu[lw][Ls - 1], v1 = tv[lw][0], vL = tv[lw][Ls - 1];
-        const double da = 1.0 - al * u1 * Gbp;
-        const double gas = (ga[sg] - al * u1 * gbp) / da;
-        const double Gas = al * v1 / da;
-        const double gbs = gb[sg] - al * uL * gbp + al * uL * Gbp * gas;
-        const double Gbs = al * vL + al * uL * Gbp * Gas;
-        ga[sg] = gas;
-        gb[sg] = gbs;
-        Ga[sg] = Gas;
-        Gb[sg] = Gbs;
-        gbp = gbs;
-        Gbp = Gbs;
-      }
-      double An = 0.0;
-      for (int sg = nseg - 1; sg >= 0; --sg) {
-        const double A = ga[sg] - Ga[sg] * An;
-        gb[sg] = gb[sg] - Gb[sg] * An;
-        ga[sg] = A;
-        An = A;
-      }
-    }
-    wave_lds_sync();
-    if (lane < nseg) {
-      const double Bl = lane > 0 ? gb[lane - 1] : 0.0;
-      const double Ar = lane + 1 < nseg ? ga[lane + 1] : 0.0;
+    // joint unknowns: gb by a forward scan, then ga, then A by a backward scan, then B
+    const double gbv = scan_up(act ? -al * uL / da : 0.0, act ? yb + al * uL * Gbm * ya / da : 0.0, lane);
+    double gbm = __shfl_up(gbv, 1);
+    if (lane == 0) gbm = 0.0;
+    const double gav = act ? (ya - al * u1 * gbm) / da : 0.0;
+    const double A = scan_down(act ? -Ga : 0.0, gav, lane);
+    double Ap = __shfl_down(A, 1);
+    if (lane + 1 >= nseg) Ap = 0.0;
+    const double B = gbv - Gb * Ap;
+    double Bm = __shfl_up(B, 1);
+    if (lane == 0) Bm = 0.0;
+    if (act) {
 #pragma unroll
-      for (int i = 0; i < FPART_LMAX; ++i)
-        if (i < L) f[g + j0 + i] = y[i] - al * tu[wl][i] * Bl - al * tv[wl][i] * Ar;
+      for (int i = 0; i < LM; ++i)
+        if (i < L) F(g + j0 + i) = y[i] - al * tu[wl][i] * Bm - al * tv[wl][i] * Ap;
     }
     wave_lds_sync();
     for (int p = lane; p < n; p += 64)
-      if (!filt_keep(P, mode, lb + (size_t)(g + p))) phi[g + p] = f[g + p];
+      if (!filt_keep(P, mode, lb + (size_t)(g + p))) phi[g + p] = F(g + p);
     wave_lds_sync();   // the next item's staging overwrites f
   }
 }
@@ -1185,12 +1219,18 @@ void launch_filter(const Launch& L, StateRef ref, int d, int mode) {
     // one wave per (line, variable); four waves per workgroup while their staged lines fit
     // 60 KB of LDS, two otherwise (lines of up to 2048 unknowns)
     const long long nmax = L.max_n[0];
-    const size_t per_wave = (size_t)(nmax + 10 + 4 * 64) * sizeof(double);
+    const size_t per_wave = (size_t)fpart_lds_slots((int)nmax) * sizeof(double);
     const int nw = 4 * per_wave <= 60 * 1024 ? 4 : 2;
     const long long items = 5 * L.sweep_rows[0];
     const unsigned blocks = (unsigned)std::max<long long>(1, std::min<long long>((items + nw - 1) / nw, 65536));
-    LG_TIMED(L, KC_FILTER, hipLaunchKernelGGL(k_filter_part, dim3(blocks, L.nprob), dim3(64 * nw), nw * per_wave,
-                                              L.stream, L.probs, ref, mode, (int)nmax, L.tile_mask));
+    // register arrays sized to the longest segment: short ones when every line has at most
+    // 1088 unknowns (segments of at most 17)
+    if (nmax <= 64 * (FPART_LSHORT - 1))
+      LG_TIMED(L, KC_FILTER, hipLaunchKernelGGL(k_filter_part<FPART_LSHORT>, dim3(blocks, L.nprob), dim3(64 * nw),
+                                                nw * per_wave, L.stream, L.probs, ref, mode, (int)nmax, L.tile_mask));
+    else
+      LG_TIMED(L, KC_FILTER, hipLaunchKernelGGL(k_filter_part<FPART_LMAX>, dim3(blocks, L.nprob), dim3(64 * nw),
+                                                nw * per_wave, L.stream, L.probs, ref, mode, (int)nmax, L.tile_mask));
   }
   const SysLaunch sl = sys_launch(L, TK_FILTER, d);
   if (sl.tiles)
