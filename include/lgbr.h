@@ -225,15 +225,22 @@ void lg_batch_destroy(lg_batch* batch);
  * class (LG_KC_*, or -1 for all classes) issued through this context is bracketed by a
  * pair of HIP events on the context's stream, up to max_launches launches.  lg_prof_stop
  * synchronises the stream and returns, per class, the summed event time in ms and the
- * number of timed launches (arrays of LG_KC_COUNT entries); it also releases the events. */
+ * number of timed launches (arrays of LG_KC_COUNT entries); it also releases the events.
+ * lg_prof_stop_launches does the same and also writes the duration (ms) and class of each
+ * timed launch, in issue order, into each_ms / each_class (host arrays of cap entries;
+ * *n_out = the number written, at most cap).  A launch that the device-side switch turned
+ * into an immediate return is timed like any other; the per-launch durations tell the two
+ * apart.  Both return LG_EINVAL when timing was not started. */
 enum {
   LG_KC_BC = 0, LG_KC_PRIM, LG_KC_FLAGS, LG_KC_GRAD_E6, LG_KC_GRAD_C4, LG_KC_SENSOR, LG_KC_VISC,
   LG_KC_LAD_NODE, LG_KC_LAD_RAW, LG_KC_GAUSS, LG_KC_LAD_FLUX, LG_KC_SWEEP_X, LG_KC_SWEEP_Y,
   LG_KC_SWEEP_Z, LG_KC_COMBINE, LG_KC_DT, LG_KC_BC_SCALAR, LG_KC_LAD_SWEEP, LG_KC_C6_FACES, LG_KC_FILTER,
-  LG_KC_GBR_ITEMS, LG_KC_HYB_ASSEMBLE, LG_KC_COUNT
+  LG_KC_GBR_ITEMS, LG_KC_HYB_ASSEMBLE, LG_KC_FILTER_GUARD, LG_KC_COUNT
 };
 lg_status lg_prof_start(lg_ctx* ctx, int kernel_class, int max_launches);
 lg_status lg_prof_stop(lg_ctx* ctx, double* ms, int* launches);
+lg_status lg_prof_stop_launches(lg_ctx* ctx, double* ms, int* launches, float* each_ms, int* each_class, int cap,
+                                int* n_out);
 
 /* Launch-shape tuning (no effect on results): seg = nodes per lane of the strided
  * interface sweeps (0 = built-in heuristic, else 2..64); pcr_blocks = persistent

@@ -20,8 +20,9 @@ Readings used here:
        flux, otherwise the LAD flux.  The paper's global switch (any troubled
        interior node -> C-GBR everywhere) is kept as mode 'global'.
   R17  Shu-Osher SSP-RK3; flags re-evaluated every stage.
-  R18  no positivity fallback: rho <= 0, p <= 0 or a non-finite value after a
-       stage is reported (non-physical count).
+  R18  no fallback of the state: rho <= 0, p <= 0 or a non-finite value after a
+       stage is reported (non-physical count).  (Reconstructed interface states have
+       one, R36 in the gbr module; the hybrid's filter has one, R37.)
   R24  troubled if rho < rho_thr or p < p_thr (strict).
   R27-R29  LAD-C6: C6 gradients, compact interface fluxes (``Opts.lad = 'C6'``;
        derivatives and lad modules); the tenth-order implicit filter
@@ -32,6 +33,13 @@ Readings used here:
        filter): LAD-E4 and LAD-C6 alike, the global hybrid's LAD stages, and the nodes
        outside the dilated troubled set of a per-cell hybrid stage.  C-GBR stages are
        never filtered (Alg. 2).
+  R37  in a hybrid stage, a node whose filtered state would not be physical (density or
+       pressure not positive, or not finite) keeps its unfiltered state.  The paper's
+       criterion (Sec. 5) hands the troubled cells to C-GBR, which is never filtered; the
+       filter's own ringing at a sharp jump the LAD phase has not yet smoothed (a strong
+       contact at t = 0) is such a cell that only shows after the filter.  Pure LAD runs
+       keep the plain filter, so the paper's LAD-C6 column of the stability table is not
+       altered.
 """
 from dataclasses import dataclass
 
@@ -228,10 +236,27 @@ def stage_filter(U, info, grid, gas, opts, scheme):
         return filter_state(U, grid, opts.filter_alpha, gas=gas)
     f = info['flags']
     if opts.hybrid_mode == 'global':
-        return U if f[grid.interior()].any() else filter_state(U, grid, opts.filter_alpha, gas=gas)
+        if f[grid.interior()].any():
+            return U
+        return physical_or_unfiltered(filter_state(U, grid, opts.filter_alpha, gas=gas), U, grid, gas)
     if not f.any():          # the per-cell form's interface flags come from every node
-        return filter_state(U, grid, opts.filter_alpha, gas=gas)
-    return filter_state(U, grid, opts.filter_alpha, gas=gas, keep=dilate(f, grid, opts.dilate))
+        return physical_or_unfiltered(filter_state(U, grid, opts.filter_alpha, gas=gas), U, grid, gas)
+    return physical_or_unfiltered(filter_state(U, grid, opts.filter_alpha, gas=gas, keep=dilate(f, grid, opts.dilate)),
+                                  U, grid, gas)
+
+
+def physical_or_unfiltered(Uf, U, grid, gas):
+    """R37: interior nodes of the filtered state Uf whose density or pressure is not positive
+    (or not finite) take the unfiltered state U; ghost layers are refilled afterwards."""
+    inner = (slice(None),) + grid.interior()
+    W = primitives(Uf[inner], gas.gamma)
+    bad = (~np.isfinite(Uf[inner]).all(axis=0)) | ~(W[0] > 0.0) | ~(W[4] > 0.0)
+    if not bad.any():
+        return Uf
+    out = Uf.copy()
+    out[inner] = np.where(bad[None], U[inner], Uf[inner])
+    gr.fill_ghosts_conserved(out, grid, gas)
+    return out
 
 
 def rk3_step(Q, t, t_end, grid, gas, opts, scheme, M=None):

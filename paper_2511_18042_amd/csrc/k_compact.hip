@@ -641,6 +641,50 @@ __global__ void __launch_bounds__(CPCR_THREADS) __attribute__((amdgpu_waves_per_
   }
 }
 
+// ------------------------------------------------------------------ filter positivity guard
+// A hybrid stage's filter (the LAD phase's FILTER_CALLS) must not hand the next stage a
+// non-physical node: the filter's ringing at a sharp jump that the LAD stage has not yet
+// smoothed can drive a small density or pressure below zero.  Such a node is troubled in
+// the sense of the hybrid's criterion (Sec. 5) and keeps its unfiltered state: the stage
+// result is saved before the passes (into the time-derivative workspace, free once the
+// stage is combined) and restored after them wherever the filtered density or pressure is
+// not positive or not finite.  The test forms p as the primitives kernel does (FP64).
+__global__ void __launch_bounds__(256) k_filter_save(const Prob* __restrict__ probs, StateRef ref, int mode) {
+  const Prob& P = probs[blockIdx.y];
+  if (!(P.falpha < 0.5) || filt_skip(P, mode)) return;
+  const double* Q = ref.state(P);
+  double* S = P.dQ;
+  const size_t n5 = 5 * (size_t)P.total;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n5; e += (size_t)gridDim.x * blockDim.x)
+    S[e] = Q[e];
+}
+
+__global__ void __launch_bounds__(256) k_filter_guard(const Prob* __restrict__ probs, StateRef ref, int mode) {
+  const Prob& P = probs[blockIdx.y];
+  if (!(P.falpha < 0.5) || filt_skip(P, mode)) return;
+  double* Q = ref.state(P);
+  const double* S = P.dQ;
+  const size_t T = P.total;
+  const double gm1 = P.gamma - 1.0;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < P.total; idx += gridDim.x * blockDim.x) {
+    const int p[3] = {idx % P.N[0], (idx / P.N[0]) % P.N[1], idx / (P.N[0] * P.N[1])};
+    bool inner = true;
+    for (int l = 0; l < 3; ++l)
+      if (l < P.ndim && (p[l] < P.g[l] || p[l] >= P.g[l] + P.n[l])) inner = false;
+    if (!inner) continue;
+    double v[5];
+    bool fin = true;
+    for (int q = 0; q < 5; ++q) {
+      v[q] = Q[q * T + idx];
+      fin = fin && isfinite(v[q]);
+    }
+    const double rho = v[0], u = v[1] / rho, w1 = v[2] / rho, w2 = v[3] / rho;
+    const double pr = gm1 * (v[4] - 0.5 * rho * (u * u + w1 * w1 + w2 * w2));
+    if (fin && rho > 0.0 && pr > 0.0) continue;
+    for (int q = 0; q < 5; ++q) Q[q * T + idx] = S[q * T + idx];
+  }
+}
+
 // ------------------------------------------------------------------ filter, partition method
 // Contiguous bounded lines of n interior unknowns (the tridiagonal [a, 1, a] system of the
 // filter with the boundary neighbours moved to the right-hand side), one wave per (line,
@@ -1210,6 +1254,17 @@ void launch_c6_faces(const Launch& L, StateRef ref, int d, int accumulate, const
       LG_TIMED(L, KC_C6_FACES, hipLaunchKernelGGL((k_c6_faces<R, 1>), dim3(blocks_for(5 * L.sweep_rows[d]), L.nprob),
                                                   dim3(256), 0, L.stream, L.probs, o, d, L.tile_mask));
   }
+}
+
+void launch_filter_save(const Launch& L, StateRef ref, int mode) {
+  const long long work = 5LL * L.max_total;
+  LG_TIMED(L, KC_FILTER_GUARD, hipLaunchKernelGGL(k_filter_save, dim3(blocks_for(std::min(work, 1LL << 24)), L.nprob),
+                                                  dim3(256), 0, L.stream, L.probs, ref, mode));
+}
+
+void launch_filter_guard(const Launch& L, StateRef ref, int mode) {
+  LG_TIMED(L, KC_FILTER_GUARD, hipLaunchKernelGGL(k_filter_guard, dim3(blocks_for(std::min(L.max_total, 1LL << 22)),
+                                                  L.nprob), dim3(256), 0, L.stream, L.probs, ref, mode));
 }
 
 void launch_filter(const Launch& L, StateRef ref, int d, int mode) {

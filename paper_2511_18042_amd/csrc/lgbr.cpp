@@ -213,7 +213,12 @@ void enqueue_rk3(const Launch& L, const Cfg& c, int scheme, double* Qx, double* 
     enqueue_rhs<R>(L, c, scheme, ref, nullptr, &rr, s);
     if (fmode >= 0 && (s == 2 || c.filter_all)) {   // after the last stage (Alg. 1)
       const StateRef out{s == 2 ? Qx : nullptr, nullptr, s == 2 ? 0 : 1};   // the stage result
+      // a hybrid stage keeps the unfiltered state where the filter would leave a
+      // non-physical node (a troubled node, which its C-GBR phases never filter)
+      const bool guard = scheme == LG_SCHEME_HYBRID;
+      if (guard) lg::launch_filter_save(L, out, fmode);
       for (int d = 0; d < c.ndim; ++d) lg::launch_filter(L, out, d, fmode);
+      if (guard) lg::launch_filter_guard(L, out, fmode);
     }
   }
 }
@@ -859,7 +864,13 @@ lg_status lg_prof_start(lg_ctx* c, int kernel_class, int max_launches) {
 }
 
 lg_status lg_prof_stop(lg_ctx* c, double* ms, int* launches) {
-  if (!c || !ms || !launches) return LG_EINVAL;
+  return lg_prof_stop_launches(c, ms, launches, nullptr, nullptr, 0, nullptr);
+}
+
+lg_status lg_prof_stop_launches(lg_ctx* c, double* ms, int* launches, float* each_ms, int* each_class, int cap,
+                                int* n_out) {
+  if (!c || !ms || !launches || cap < 0 || (cap > 0 && (!each_ms || !each_class))) return LG_EINVAL;
+  if (n_out) *n_out = 0;
   for (int k = 0; k < lg::KC_COUNT; ++k) {
     ms[k] = 0.0;
     launches[k] = 0;
@@ -874,6 +885,11 @@ lg_status lg_prof_stop(lg_ctx* c, double* ms, int* launches) {
     }
     ms[c->prof.cls[i]] += t;
     launches[c->prof.cls[i]] += 1;
+    if (i < cap) {
+      each_ms[i] = t;
+      each_class[i] = c->prof.cls[i];
+      if (n_out) *n_out = i + 1;
+    }
   }
   prof_release(c);
   return st;

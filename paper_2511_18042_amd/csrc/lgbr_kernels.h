@@ -49,7 +49,7 @@ __device__ __forceinline__ bool rk_combine_node(const Prob& P, const RKRef& rr, 
 enum KClass {
   KC_BC = 0, KC_PRIM, KC_FLAGS, KC_GRAD_E6, KC_GRAD_C4, KC_SENSOR, KC_VISC, KC_LAD_NODE, KC_LAD_RAW,
   KC_GAUSS, KC_LAD_FLUX, KC_SWEEP_X, KC_SWEEP_Y, KC_SWEEP_Z, KC_COMBINE, KC_DT, KC_BC_SCALAR, KC_LAD_SWEEP,
-  KC_C6_FACES, KC_FILTER, KC_GBR_ITEMS, KC_HYB_ASSEMBLE, KC_COUNT
+  KC_C6_FACES, KC_FILTER, KC_GBR_ITEMS, KC_HYB_ASSEMBLE, KC_FILTER_GUARD, KC_COUNT
 };
 
 // Event pairs recorded around launches while enabled (never during graph capture).
@@ -215,6 +215,10 @@ void launch_c6_faces(const Launch& L, StateRef ref, int d, int accumulate, const
                      double b);
 enum { FILT_ALL = 0, FILT_GLOBAL = 1, FILT_PERCELL = 2 };
 void launch_filter(const Launch& L, StateRef ref, int d, int mode);
+// positivity guard of a hybrid stage's filter: the stage result saved before the passes,
+// nodes the filter made non-physical restored after them
+void launch_filter_save(const Launch& L, StateRef ref, int mode);
+void launch_filter_guard(const Launch& L, StateRef ref, int mode);
 // which kernel solves the lines of each system (shared by the host and the kernels):
 // LDS line tiles when all five variables of one line fit the tile and a periodic line is
 // long enough for the PCR steps; otherwise the policies below

@@ -17,6 +17,20 @@ from oracle import grid as gr, rhs as R  # noqa: E402
 from paper_2511_18042_amd import cases  # noqa: E402
 
 
+def fingerprint(n=400, steps=40):
+    """The oracle's MIG4 C-GBR density after ``steps`` RK3 steps of the same problem on ``n``
+    cells: stored beside the reference so that a test can tell whether the oracle arithmetic
+    that produced it has changed since (a file hash would also change with unrelated edits)."""
+    c = cases.shu_osher(n)
+    g = gr.Grid(c.ndim, c.n, c.bc, c.h)
+    M = gr.node_metrics(g)
+    Q, t = c.Q.copy(), 0.0
+    for _ in range(steps):
+        Q, t, _, _ = R.rk3_step(Q, t, c.t_end, g, R.Gas(gamma=1.4), R.Opts(grad='C4', cfl=0.2), 'cgbr', M)
+    inner = (slice(None),) + g.interior()
+    return R.primitives(Q[inner], 1.4)[0, 0, 0, :]
+
+
 def oracle_hash():
     h = hashlib.sha256()
     for f in sorted(os.listdir(os.path.join(ROOT, 'oracle'))):
@@ -43,7 +57,8 @@ def main():
     inner = (slice(None),) + g.interior()
     W = R.primitives(Q[inner], 1.4)[:, 0, 0, :]
     out = os.path.join(os.path.dirname(os.path.abspath(__file__)), 'shu_osher_ref_%d.npz' % n)
-    np.savez_compressed(out, rho=W[0], u=W[1], p=W[4], t=t, steps=steps, oracle_sha256=oracle_hash())
+    np.savez_compressed(out, rho=W[0], u=W[1], p=W[4], t=t, steps=steps, oracle_sha256=oracle_hash(),
+                        fingerprint_rho=fingerprint())
     print('wrote', out, 'steps', steps)
 
 

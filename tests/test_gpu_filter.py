@@ -112,3 +112,35 @@ def test_lad_e4_rk3_step_is_filtered():
     U.compare(Qd.cpu().numpy(), Qn, g, U.STAGE_RTOL, label='lad-e4 filtered step')
     inner = (slice(None),) + g.interior()
     assert np.max(np.abs(Qn[inner] - Qu[inner])) > 1e-6
+
+
+def case_strong_contact():
+    """Problem 1 of the 64-problem batch at 64 x 64: a density ratio of 17 between quadrants;
+    the filter after the first (LAD) step rings below zero density there."""
+    return cases.batch64(scale=16)[1]
+
+
+@pytest.mark.parametrize('mode', ['global', 'percell'])
+def test_hybrid_filter_positivity_guard(mode):
+    """The hybrid's filter keeps the unfiltered state where it would leave a non-physical
+    node (R37): the GPU step equals the oracle's guarded step, and no node is non-physical."""
+    torch = U.torch_mod()
+    c = case_strong_contact()
+    gas = orhs.Gas()
+    opts = orhs.Opts(grad='E6', hybrid_mode=mode, rho_thr=c.extra['rho_thr'], p_thr=c.extra['p_thr'])
+    g = U.oracle_grid(c)
+    M = ogrid.node_metrics(g)
+    Qn, _, _, bad = orhs.rk3_step(c.Q, 0.0, 1.0, g, gas, opts, 'hybrid', M)
+    assert bad == 0
+    ctx, _ = U.gpu_context(c, gas, opts)
+    Qd = U.dev(c.Q)
+    td = torch.zeros(1, dtype=torch.float64, device='cuda')
+    ctx.rk3_step('hybrid', Qd, 1.0, td)
+    torch.cuda.synchronize()
+    assert ctx.poll_status() == 0
+    ctx.close()
+    out = Qd.cpu().numpy()
+    U.compare(out, Qn, g, U.STAGE_RTOL, label='hybrid guard %s' % mode)
+    inner = (slice(None),) + g.interior()
+    W = orhs.primitives(out[inner], 1.4)
+    assert W[0].min() > 0 and W[4].min() > 0
