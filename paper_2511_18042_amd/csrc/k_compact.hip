@@ -529,7 +529,7 @@ __global__ void __launch_bounds__(256) k_filter(const Prob* __restrict__ probs, 
                                                 int mode) {
   const Prob& P = probs[blockIdx.y];
   if (d >= P.ndim || !(P.falpha < 0.5) || filt_part_use(P, d, mask) || tile_use(P, d, TK_FILTER, mask) ||
-      filt_pcr(P, d))
+      filt_pcr(P, d) || filt_seg_use(P, d, mask))
     return;
   if (filt_skip(P, mode)) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -638,6 +638,128 @@ __global__ void __launch_bounds__(CPCR_THREADS) __attribute__((amdgpu_waves_per_
     for (int i = threadIdx.x; i < n; i += blockDim.x)
       if (!filt_keep(P, mode, lb0 + (size_t)(g + i) * sd)) phi[(size_t)(g + i) * sd] = r[i];
     __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ filter, strided segments
+// Lines along eta / zeta of n <= FSEG_SMAX * FSEG_LM unknowns, bounded or periodic.  A
+// workgroup takes 64 neighbouring lines (consecutive along xi, so every load and store of a
+// wave is one contiguous run) and one variable; wave s holds segment s of all 64 lines,
+// S = ceil(n / FSEG_LM) segments of L = n / S or one more unknowns.  Each lane reads its
+// segment and the five values on either side once, forms the right-hand sides and solves
+// the segment's own [a, 1, a] system T y = r in registers (the forward values overwrite the
+// window slots they no longer need), so the line never goes through FP64 scratch.  With
+// u = T^{-1} e_1 and v = T^{-1} e_L the solution is x = y - a u B_{s-1} - a v A_{s+1}
+// (A_s, B_s: first and last unknown of segment s; bounded lines drop the terms past their
+// ends, periodic lines wrap), so the 2S joint unknowns solve M z = (y_s[0], y_s[L-1])_s.
+// M depends on n, S and a only: its LU factors (no pivoting: M inherits the diagonal
+// dominance of the filter matrix), the segment factors and u, v are host-built tables, and
+// lane t of wave 0 solves the joint system of line t.
+template <int LM>
+__global__ void __launch_bounds__(64 * FSEG_SMAX) k_filter_seg(const Prob* __restrict__ probs, StateRef ref, int d,
+                                                                int mask, int mode) {
+  constexpr int SM = FSEG_SMAX, M2 = 2 * SM;
+  __shared__ double tab[FSEG_TABLE];      // cp, 1 / pivot, u, v, joint LU (host-built, see lgbr.cpp)
+  __shared__ double ends[SM][2][64];      // y_s[0], y_s[L-1] of each line; then A_s, B_s
+  const Prob& P = probs[blockIdx.y];
+  if (d >= P.ndim || !(P.falpha < 0.5) || !filt_seg_use(P, d, mask) || filt_skip(P, mode)) return;
+  const int n = P.n[d], g = P.g[d], sd = P.s[d];
+  const int S = fseg_count(n);
+  const int base = n / S, extra = n % S;   // the first `extra` segments have base + 1
+  const int nlines = interior_lines(P, d);
+  const int q = blockIdx.x % 5, grp = blockIdx.x / 5;
+  if (grp * 64 >= nlines) return;
+  const bool periodic = P.bc[d][0] == BC_PERIODIC;
+  const double al = P.falpha;
+  const int lane = threadIdx.x & 63, s = threadIdx.x >> 6;
+  for (int e = threadIdx.x; e < FSEG_TABLE; e += blockDim.x) tab[e] = P.fsegt[d][e];
+  const double* tcp = tab + FSEG_CP;
+  const double* tinv = tab + FSEG_INV;
+  const int line = grp * 64 + lane;
+  const bool act = s < S && line < nlines;
+  const int L = base + (s < extra ? 1 : 0);
+  const int j0 = s * base + min(s, extra);   // first unknown of this lane's segment
+  const double* tu = tab + FSEG_U + (s < extra ? LM + 1 : 0);
+  const double* tv = tab + FSEG_V + (s < extra ? LM + 1 : 0);
+  double* Q = ref.state(P);
+  const size_t T = P.total;
+  const size_t lb = act ? interior_line_base(P, d, line) : 0;
+  double* phi = Q + (size_t)q * T + lb;
+  auto at = [&](int p) { return phi[(ptrdiff_t)(g + (periodic ? wrap(p, n) : p)) * sd]; };
+  // w[i] = phi_{j0 + i - 5}; after row i, w[i] (no longer read) holds the forward value d_i,
+  // then y_i after the back substitution
+  double w[LM + 10];
+  if (act) {
+#pragma unroll
+    for (int i = 0; i < LM + 10; ++i)
+      if (i < L + 10) w[i] = at(j0 + i - 5);
+  }
+  __syncthreads();   // every lane has read its window before any lane writes a result; tables in LDS
+  double ya = 0.0, yb = 0.0;
+  if (act) {
+    double prev = 0.0;
+#pragma unroll
+    for (int i = 0; i < LM; ++i) {
+      if (i < L) {
+        double r = filt_rhs(P, &w[i]);
+        const int j = j0 + i;
+        if (!periodic && j == 0) r = r - al * w[i + 4];
+        if (!periodic && j == n - 1) r = r - al * w[i + 6];
+        prev = (r - (i > 0 ? al * prev : 0.0)) * tinv[i];
+        w[i] = prev;
+      }
+    }
+    yb = prev;
+    double v = prev;
+#pragma unroll
+    for (int i = LM - 2; i >= 0; --i) {
+      if (i < L - 1) {
+        v = w[i] - tcp[i] * v;
+        w[i] = v;
+      }
+    }
+    ya = w[0];
+    ends[s][0][lane] = ya;
+    ends[s][1][lane] = yb;
+  }
+  __syncthreads();
+  if (s == 0 && line < nlines) {   // L U z = (y_s[0], y_s[L-1])_s, in place in ends
+    const double* lu = tab + FSEG_LU;
+    const int m = 2 * S;
+    double z[M2];
+#pragma unroll
+    for (int r = 0; r < M2; ++r) {
+      if (r < m) {
+        double v = ends[r >> 1][r & 1][lane];
+#pragma unroll
+        for (int c = 0; c < r; ++c) v -= lu[r * M2 + c] * z[c];
+        z[r] = v;
+      }
+    }
+#pragma unroll
+    for (int r = M2 - 1; r >= 0; --r) {
+      if (r < m) {
+        double v = z[r];
+#pragma unroll
+        for (int c = r + 1; c < M2; ++c)
+          if (c < m) v -= lu[r * M2 + c] * z[c];
+        z[r] = v / lu[r * M2 + r];
+        ends[r >> 1][r & 1][lane] = z[r];
+      }
+    }
+  }
+  __syncthreads();
+  if (act) {
+    const int sp = s - 1, sn = s + 1;
+    const double Bm = (periodic || sp >= 0) ? ends[(sp + S) % S][1][lane] : 0.0;
+    const double Ap = (periodic || sn < S) ? ends[sn % S][0][lane] : 0.0;
+#pragma unroll
+    for (int i = 0; i < LM; ++i) {
+      if (i < L) {
+        const size_t node = lb + (size_t)(g + j0 + i) * sd;
+        if (!filt_keep(P, mode, node)) phi[(size_t)(g + j0 + i) * sd] = w[i] - al * tu[i] * Bm - al * tv[i] * Ap;
+      }
+    }
   }
 }
 
@@ -1277,7 +1399,7 @@ void launch_filter(const Launch& L, StateRef ref, int d, int mode) {
     const size_t per_wave = (size_t)fpart_lds_slots((int)nmax) * sizeof(double);
     const int nw = 4 * per_wave <= 60 * 1024 ? 4 : 2;
     const long long items = 5 * L.sweep_rows[0];
-    const unsigned blocks = (unsigned)std::max<long long>(1, std::min<long long>((items + nw - 1) / nw, 65536));
+    const unsigned blocks = (unsigned)std::max<long long>(1, std::min<long long>((items + nw - 1) / nw, 4096));
     // register arrays sized to the longest segment: short ones when every line has at most
     // 1088 unknowns (segments of at most 17)
     if (nmax <= 64 * (FPART_LSHORT - 1))
@@ -1286,6 +1408,12 @@ void launch_filter(const Launch& L, StateRef ref, int d, int mode) {
     else
       LG_TIMED(L, KC_FILTER, hipLaunchKernelGGL(k_filter_part<FPART_LMAX>, dim3(blocks, L.nprob), dim3(64 * nw),
                                                 nw * per_wave, L.stream, L.probs, ref, mode, (int)nmax, L.tile_mask));
+  }
+  if (L.fseg[d] > 0) {
+    // 64 lines x one variable per workgroup, one wave per segment
+    const long long groups = (L.sweep_rows[d] + 63) / 64;
+    LG_TIMED(L, KC_FILTER, hipLaunchKernelGGL(k_filter_seg<FSEG_LM>, dim3((unsigned)(5 * groups), L.nprob),
+                                              dim3(64 * L.fseg[d]), 0, L.stream, L.probs, ref, d, L.tile_mask, mode));
   }
   const SysLaunch sl = sys_launch(L, TK_FILTER, d);
   if (sl.tiles)

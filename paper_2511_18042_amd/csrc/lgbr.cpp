@@ -396,6 +396,69 @@ void append_band_header(std::vector<double>& t, int L, int steps) {
 // T(w) = 1 - (1 - 2 alpha) sin^10(w/2) / (1 + 2 alpha cos w); with
 // sin^10(w/2) = (252 - 420 cos w + 240 cos 2w - 90 cos 3w + 20 cos 4w - 2 cos 5w) / 1024
 // the numerator sum_k a_k cos(k w) gives a_k directly.
+// Tables of k_filter_seg for lines of n unknowns (see k_compact.hip): the forward factors
+// cp_i, 1 / pivot_i of the segment system [a, 1, a] (rows in order, the same for every
+// segment length), the responses u = T^{-1} e_1 and v = T^{-1} e_L for the two segment
+// lengths base and base + 1, and the LU factors (no pivoting) of the joint matrix of the
+// segments' first and last unknowns; layout fseg_offsets() of lgbr_kernels.h.
+std::vector<double> fseg_table(int n, double al, bool periodic) {
+  const int LM = lg::FSEG_LM, M2 = 2 * lg::FSEG_SMAX, S = lg::fseg_count(n);
+  const int base = n / S, extra = n % S;
+  std::vector<double> t(lg::FSEG_TABLE, 0.0);
+  double* tcp = t.data() + lg::FSEG_CP;
+  double* tinv = t.data() + lg::FSEG_INV;
+  double c = 0.0;
+  for (int i = 0; i < base + 1 && i <= LM; ++i) {
+    const double den = 1.0 - (i > 0 ? al * c : 0.0);
+    tinv[i] = 1.0 / den;
+    c = al / den;
+    tcp[i] = c;
+  }
+  for (int which = 0; which < 2; ++which)
+    for (int uv = 0; uv < 2; ++uv) {
+      const int L = base + which;
+      if (L > LM) continue;
+      double* out = t.data() + (uv == 0 ? lg::FSEG_U : lg::FSEG_V) + which * (LM + 1);
+      double prev = 0.0;
+      for (int i = 0; i < L; ++i) {
+        const double rhs = uv == 0 ? (i == 0 ? 1.0 : 0.0) : (i == L - 1 ? 1.0 : 0.0);
+        prev = (rhs - (i > 0 ? al * prev : 0.0)) * tinv[i];
+        out[i] = prev;
+      }
+      double y = out[L - 1];
+      for (int i = L - 2; i >= 0; --i) {
+        y = out[i] - tcp[i] * y;
+        out[i] = y;
+      }
+    }
+  double* lu = t.data() + lg::FSEG_LU;
+  const int m = 2 * S;
+  if (S > lg::FSEG_SMAX) return t;
+  for (int r = 0; r < m; ++r) lu[r * M2 + r] = 1.0;
+  for (int sg = 0; sg < S; ++sg) {
+    const int wl = sg < extra ? 1 : 0, Ls = base + wl;
+    const double* u = t.data() + lg::FSEG_U + wl * (LM + 1);
+    const double* v = t.data() + lg::FSEG_V + wl * (LM + 1);
+    const int sp = sg - 1, sn = sg + 1;
+    const int cpv = 2 * ((sp + S) % S) + 1, cnv = 2 * (sn % S);   // columns of B_{s-1}, A_{s+1}
+    if (periodic || sp >= 0) {
+      lu[(2 * sg) * M2 + cpv] += al * u[0];
+      lu[(2 * sg + 1) * M2 + cpv] += al * u[Ls - 1];
+    }
+    if (periodic || sn < S) {
+      lu[(2 * sg) * M2 + cnv] += al * v[0];
+      lu[(2 * sg + 1) * M2 + cnv] += al * v[Ls - 1];
+    }
+  }
+  for (int k = 0; k < m; ++k)
+    for (int r = k + 1; r < m; ++r) {
+      const double f = lu[r * M2 + k] / lu[k * M2 + k];
+      lu[r * M2 + k] = f;
+      for (int cc = k + 1; cc < m; ++cc) lu[r * M2 + cc] -= f * lu[k * M2 + cc];
+    }
+  return t;
+}
+
 void filter_weights(double al, double a[6]) {
   const double e = (1.0 - 2.0 * al) / 1024.0;
   a[0] = 1.0 - 252.0 * e;
@@ -439,6 +502,10 @@ void fill_launch(Launch& L, const Prob& P) {
         if (k == lg::TK_FILTER ? !(P.falpha < 0.5) : !P.lad_c6) continue;
         if (k == lg::TK_FILTER && lg::filt_part_use(P, d, L.tile_mask)) {
           L.fpart = 1;
+          continue;
+        }
+        if (k == lg::TK_FILTER && lg::filt_seg_use(P, d, L.tile_mask)) {
+          L.fseg[d] = std::max(L.fseg[d], lg::fseg_count(P.n[d]));
           continue;
         }
         const bool pcr = k == lg::TK_GRAD6 ? lg::c6_grad_pcr(P, d)
@@ -788,6 +855,15 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
       }
       P.trf[d] = t1;
       P.pcrf[d] = t2;
+      if (d > 0 && lg::fseg_count(n) <= lg::FSEG_SMAX && n >= 16) {
+        const std::vector<double> fs = fseg_table(n, al, periodic);
+        double* t3 = static_cast<double*>(A(fs.size() * sizeof(double)));
+        if (!ok || hipMemcpy(t3, fs.data(), fs.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+          lg_destroy(c);
+          return ok ? LG_EHIP : LG_ENOMEM;
+        }
+        P.fsegt[d] = t3;
+      }
     }
     if (!ok) {
       lg_destroy(c);
@@ -997,7 +1073,8 @@ lg_status lg_set_tuning(lg_ctx* c, int seg, int pcr_blocks, int zc) {
 }
 
 lg_status lg_set_line_tiles(lg_ctx* c, int mask) {
-  if (!c || mask < -1 || mask > (lg::TILE_MASK_ALL | lg::TILE_MASK_FORCE_STRIDED | lg::TILE_MASK_NO_PART))
+  if (!c || mask < -1 ||
+      mask > (lg::TILE_MASK_ALL | lg::TILE_MASK_FORCE_STRIDED | lg::TILE_MASK_NO_PART | lg::TILE_MASK_NO_SEG))
     return LG_EINVAL;
   c->L.tile_mask = mask < 0 ? lg::TILE_MASK_DEFAULT : mask;
   for (int d = 0; d < 3; ++d) {
@@ -1006,6 +1083,7 @@ lg_status lg_set_line_tiles(lg_ctx* c, int mask) {
     c->L.c4_rest_pcr[d] = c->L.c4_rest_thomas[d] = 0;
   }
   c->L.fpart = 0;
+  for (int d = 0; d < 3; ++d) c->L.fseg[d] = 0;
   fill_launch(c->L, c->hp);
   return LG_OK;
 }

@@ -78,6 +78,7 @@ struct Prob {
   const double* pcrc[3];
   const double* trf[3];  // filter systems
   const double* pcrf[3];
+  const double* fsegt[3]; // filter along eta / zeta by register segments (k_filter_seg tables)
   // device scalars
   double* dt;
   double* t;

@@ -94,6 +94,7 @@ struct Launch {
   int zc;                  // planes per chunk of the z-marching kernels (0: heuristic)
   int item_blocks;         // persistent workgroups of the compacted C-GBR interface pass (0: 2048)
   int fpart;               // some problem filters along xi with the partition-method kernel
+  int fseg[3];             // most segments per line of the problems filtering along d by k_filter_seg (0: none)
   Prof* prof;              // optional launch timing (null: off)
 };
 
@@ -226,6 +227,7 @@ enum { TK_GRAD6 = 0, TK_FACES = 1, TK_FILTER = 2, TK_GRAD4 = 3 };
 constexpr int TILE_MASK_ALL = 0xFFF;
 constexpr int TILE_MASK_FORCE_STRIDED = 0x1000;   // tiles on strided directions whatever their line count
 constexpr int TILE_MASK_NO_PART = 0x2000;          // filter along xi without the partition-method kernel
+constexpr int TILE_MASK_NO_SEG = 0x4000;           // filter along eta / zeta without the register-segment kernel
 constexpr int TILE_MASK_DEFAULT = TILE_MASK_ALL;
 constexpr int TILE_ELEMS = 6144;   // doubles per tile (48 KB of LDS)
 // lanes per tile workgroup: contiguous lines take 512 (128 VGPRs, four waves per SIMD);
@@ -275,6 +277,21 @@ __host__ __device__ inline bool filt_part_use(const Prob& P, int d, int mask) {
 __host__ __device__ inline bool filt_pcr(const Prob& P, int d) {
   const bool periodic = P.bc[d][0] == BC_PERIODIC;
   return d == 0 && P.N[d] <= 4000 && !(periodic && P.n[d] < (2 << P.fsteps));
+}
+// the implicit filter along eta / zeta where the lines would otherwise be solved one lane per
+// line through FP64 scratch: k_filter_seg, segments of at most FSEG_LM unknowns held in
+// registers, at most FSEG_SMAX per line (lines of 16 to 512 unknowns)
+constexpr int FSEG_LM = 64, FSEG_SMAX = 8;
+// host-built tables per direction: cp, 1 / pivot [LM + 1] each, u and v [2][LM + 1] each,
+// the joint LU [2 SMAX][2 SMAX]
+constexpr int FSEG_CP = 0, FSEG_INV = FSEG_LM + 1, FSEG_U = 2 * (FSEG_LM + 1), FSEG_V = 4 * (FSEG_LM + 1),
+              FSEG_LU = 6 * (FSEG_LM + 1), FSEG_TABLE = FSEG_LU + 4 * FSEG_SMAX * FSEG_SMAX;
+__host__ __device__ inline int fseg_count(int n) { return (n + FSEG_LM - 1) / FSEG_LM; }
+__host__ __device__ inline bool filt_seg_use(const Prob& P, int d, int mask) {
+  if ((mask & TILE_MASK_NO_SEG) || d == 0 || d >= P.ndim || !P.fsegt[d] || tile_use(P, d, TK_FILTER, mask))
+    return false;
+  const int S = fseg_count(P.n[d]);
+  return S <= FSEG_SMAX && P.n[d] >= 16;
 }
 
 }  // namespace lg

@@ -144,3 +144,47 @@ def test_hybrid_filter_positivity_guard(mode):
     inner = (slice(None),) + g.interior()
     W = orhs.primitives(out[inner], 1.4)
     assert W[0].min() > 0 and W[4].min() > 0
+
+
+# --- strided directions: register segments joined through their end unknowns (k_filter_seg)
+P_ = cases.PERIODIC
+SEG_ON = 0xFFF & ~((1 << 7) | (1 << 8))      # no line tiles for the filter along eta / zeta
+SEG_OFF = SEG_ON | 0x4000                    # ... and no segment kernel: one lane per line
+
+
+def _strided(n, bc, seed):
+    c = cases.Case(3 if n[2] > 1 else 2, n, bc, h=tuple(1.0 / max(m, 1) for m in n))
+    return cases.random_rough_state(c, seed=seed)
+
+
+STRIDED = {
+    'eta300_walls': lambda: _strided((24, 300, 1), [(RF, T), (T, RF)], 5),          # 5 segments of 60
+    'eta130_fixed': lambda: _strided((16, 130, 1), [(T, T), (FX, T)], 6),           # 3 segments of 43-44
+    'eta70_zeta128': lambda: _strided((20, 70, 128), [(T, T), (RF, T), (P_, P_)], 7),   # 2 x 35; cyclic 2 x 64
+    'eta24_zeta40': lambda: _strided((20, 24, 40), [(T, T), (T, T), (P_, P_)], 8),     # one segment each
+    'eta384_zeta16': lambda: _strided((12, 384, 16), [(T, T), (T, RF), (P_, P_)], 9),  # 6 x 64; cyclic 1 x 16
+}
+
+
+@pytest.mark.parametrize('name', list(STRIDED))
+@pytest.mark.parametrize('alpha', [0.49, 0.3])
+@pytest.mark.parametrize('mask', [-1, SEG_ON, SEG_OFF])
+def test_filter_strided_segments_parity(name, alpha, mask):
+    """The filter along eta and zeta by register segments (k_filter_seg: bounded and
+    periodic lines of 16 to 512 unknowns, one to six segments, FIXED ghosts read and never
+    written) against the oracle, beside the line tiles (default where lines are few) and the
+    one-lane-per-line solves it replaces."""
+    print('filter strided', name, alpha, mask, flush=True)
+    c = STRIDED[name]()
+    gas = orhs.Gas(gamma=c.gamma)
+    g = U.oracle_grid(c)
+    ref = oflt.filter_state(c.Q, g, alpha, gas=gas)
+    ctx, _ = U.gpu_context(c, gas, orhs.Opts(filter_alpha=alpha))
+    ctx.set_line_tiles(mask)
+    Qd = U.dev(c.Q)
+    ctx.lad_filter(Qd)
+    out = Qd.cpu().numpy()
+    ctx.close()
+    U.compare(out, ref, g, U.STAGE_RTOL, label='filter %s %g %d' % (name, alpha, mask))
+    if name == 'eta130_fixed':
+        assert np.array_equal(out[:, :, :5, 5:-5], c.Q[:, :, :5, 5:-5])

@@ -378,3 +378,32 @@ def test_planar_metric_storage_matches_full_storage():
     assert sizes[0] < sizes[1]
     g = U.oracle_grid(c)
     U.compare(outs[1], outs[0], g, 1e-4, label='planar vs perturbed')
+
+
+@pytest.mark.parametrize('scheme,grad', [('hybrid', 'C4'), ('cgbr', 'C4'), ('lad', 'C4')])
+def test_ramp_large_crop_rhs_parity(scheme, grad):
+    """The ramp generator on a 256x192x64 crop: large enough that the library picks, without
+    any forcing switch, the paths of the full 1024x384x128 grid -- one lane per line for the
+    compact solves along zeta (more than 32768 lines), LDS line tiles along xi and eta, the
+    z-chunked stencil kernels -- with the hybrid at 10 % random troubled cells (compacted
+    per-cell path), MIG4 C-GBR and LAD-E4.  FP64 at the RHS gate; the mixed path's error is
+    printed (RHS-REPORT) and bounded by 1e-4 of each variable's max norm."""
+    print('ramp large crop', scheme, grad, flush=True)
+    c, gas = _ramp_case(256, 192, 64)
+    g = U.oracle_grid(c)
+    opts = orhs.Opts(grad=grad, p_thr=c.extra['p_thr'], hybrid_mode='percell')
+    flags = (np.random.default_rng(11).random(g.shape) < 0.1) if scheme == 'hybrid' else None
+    info = {}
+    ref = orhs.rhs(c.Q, g, gas, opts, scheme, info=info, force_flags=flags)
+    inner = (slice(None),) + g.interior()
+    for precision in ('fp64', 'mixed'):
+        ctx, _ = U.gpu_context(c, gas, opts, precision=precision)
+        out = U.gpu_rhs(ctx, c, scheme, flags=flags)
+        ctx.close()
+        if precision == 'fp64':
+            U.compare(out, ref, g, U.RHS_RTOL, U.excused_mask(info, g), label='ramp 256 %s %s' % (scheme, grad))
+        else:
+            rel = [float(np.max(np.abs(out[q][inner[1:]] - ref[q][inner[1:]])) / max(np.max(np.abs(ref[q][inner[1:]])),
+                                                                                 1e-300)) for q in range(5)]
+            print('RHS-REPORT ramp 256x192x64 %s mixed max rel err per variable %s' % (scheme, rel), flush=True)
+            assert max(rel) <= 1e-4
