@@ -58,6 +58,14 @@ def parse():
                     help='with --workload ramp3d: of the config-4 variants run only this one (profiling)')
     ap.add_argument('--copy-probe-mib', type=int, default=0,
                     help='run one plain device copy of this many MiB first (calibrates HBM counters)')
+    ap.add_argument('--profile-summary', default=None, metavar='OUT',
+                    help='write a per-kernel summary of rocprofv3 output (--trace, --fetch, --write csv files) to '
+                         'OUT and exit; no GPU is used')
+    ap.add_argument('--trace', default=None, help='rocprofv3 --kernel-trace csv (with --profile-summary)')
+    ap.add_argument('--fetch', default=None, help='rocprofv3 --pmc FETCH_SIZE csv (with --profile-summary)')
+    ap.add_argument('--write', default=None, help='rocprofv3 --pmc WRITE_SIZE csv (with --profile-summary)')
+    ap.add_argument('--title', default='', help='first line of the summary (with --profile-summary)')
+    ap.add_argument('--commands', default='', help='the commands that made the csv files, ; separated')
     return ap.parse_args()
 
 
@@ -209,10 +217,11 @@ def live_roofline(kern, dom, cells, ndim, gbr_frac, viscous, curv, planar, traff
                       'not averaged' % EXECUTED_FRACTION, 'traffic': None}
     if traffic_file:
         tr, why = profiled_traffic(traffic_file, dom)
-        roof['traffic'] = tr
+        roof['traffic'] = tr['bytes'] if tr else None
         roof['traffic_source'] = os.path.relpath(traffic_file, ROOT) + ('' if tr else ' (%s)' % why)
         if tr:
-            roof['traffic_over_algorithmic'] = round(tr / algo, 3)
+            roof['traffic_over_algorithmic'] = round(tr['bytes'] / algo, 3)
+            roof['profile_avg_launch_ms'] = tr['profile_avg_launch_ms']
     return roof
 
 
@@ -250,49 +259,57 @@ def precision_error(Qa, Qb, gamma=1.4):
     return out
 
 
+def _profile_lines(path):
+    """(KTIME, TRAFFIC) dicts by class of a committed summary written by --profile-summary,
+    or (None, reason) once any library source no longer hashes to what was profiled."""
+    import hashlib
+    if not os.path.exists(path):
+        return None, 'no profile'
+    kt, tr, sha, files = {}, {}, None, None
+    for line in open(path):
+        f = line.split()
+        if len(f) < 2:
+            continue
+        if f[0] == 'SOURCES':
+            kv = dict(x.split('=', 1) for x in f[1:])
+            sha, files = kv['sha256'], kv['files'].split(',')
+        elif f[0] in ('KTIME', 'TRAFFIC'):
+            kv = dict(x.split('=', 1) for x in f[2:])
+            (kt if f[0] == 'KTIME' else tr)[f[1]] = kv
+    if sha is None:
+        return None, 'no SOURCES line'
+    h = hashlib.sha256()
+    for src in files:
+        h.update(open(os.path.join(ROOT, src), 'rb').read())
+    if h.hexdigest() != sha:
+        return None, 'library sources changed since the profile was taken'
+    return (kt, tr), ''
+
+
 def profiled_traffic(path, kclass):
-    """HBM bytes per launch of kernel class kclass from a committed rocprofv3 counter summary
-    (its TRAFFIC line: FETCH_SIZE and WRITE_SIZE in KiB per dispatch and their scales from a
-    copy of known size), or None with the reason: no such line, or the kernel sources no
-    longer hash to what was profiled."""
-    import hashlib
-    if not os.path.exists(path):
-        return None, 'no profile'
-    for line in open(path):
-        f = line.split()
-        if len(f) < 3 or f[0] != 'TRAFFIC' or f[1] != kclass:
-            continue
-        kv = dict(x.split('=', 1) for x in f[2:])
-        h = hashlib.sha256()
-        for src in kv['sources'].split(','):
-            h.update(open(os.path.join(ROOT, src), 'rb').read())
-        if h.hexdigest() != kv['sha256']:
-            return None, 'kernel sources changed since the counters were taken'
-        kib = float(kv['fetch_kib']) * float(kv['fetch_scale']) + float(kv['write_kib']) * float(kv['write_scale'])
-        return int(kib * 1024), ''
-    return None, 'no counters for this kernel'
+    """Counted HBM bytes per executed launch of kernel class kclass (FETCH_SIZE and
+    WRITE_SIZE scaled by a copy of known size) and the profile's own average launch time,
+    from a committed summary; (None, reason) otherwise."""
+    got, why = _profile_lines(path)
+    if got is None:
+        return None, why
+    kt, tr = got
+    if kclass not in tr:
+        return None, 'no counters for this kernel class'
+    return {'bytes': int(float(tr[kclass]['bytes'])),
+            'profile_avg_launch_ms': float(kt[kclass]['avg_ms']) if kclass in kt else None}, ''
 
 
-def profiled_step(path):
-    """Whole-step HBM bytes and VALU-busy % of the workload from a committed counter summary
-    (its STEP line: every kernel of a step, FETCH_SIZE and WRITE_SIZE scaled by the copy of
-    known size), or (None, reason) once any library source no longer hashes to what was
-    profiled."""
-    import hashlib
-    if not os.path.exists(path):
-        return None, 'no profile'
-    for line in open(path):
-        f = line.split()
-        if len(f) < 2 or f[0] != 'STEP':
-            continue
-        kv = dict(x.split('=', 1) for x in f[1:])
-        h = hashlib.sha256()
-        for src in kv['sources'].split(','):
-            h.update(open(os.path.join(ROOT, src), 'rb').read())
-        if h.hexdigest() != kv['sha256']:
-            return None, 'library sources changed since the counters were taken'
-        return {'bytes_per_step': int(float(kv['bytes_per_step'])), 'valu_busy_pct': float(kv['valu_busy_pct'])}, ''
-    return None, 'no STEP line'
+def profiled_step(path, launches_per_step):
+    """Whole-step counted HBM bytes: each class's counted bytes per executed launch times its
+    executed launches per step (measured live); (None, reason) when a class has no counters."""
+    got, why = _profile_lines(path)
+    if got is None:
+        return None, why
+    _, tr = got
+    missing = [k for k in launches_per_step if k not in tr and launches_per_step[k] > 0]
+    total = sum(float(tr[k]['bytes']) * n for k, n in launches_per_step.items() if k in tr)
+    return {'bytes_per_step': int(total), 'classes_without_counters': missing}, ''
 
 
 def flags_of(ctx, Q):
@@ -333,13 +350,20 @@ def mix_window(ctx_lad, ctx_gbr, Q, t, W, K, share=PAPER_GBR_STEP_SHARE, prof=Tr
         for _ in range(6):
             ctx_of(i).rk3_step('hybrid', Q, 1e30, t)
             i += 1
-        tot = {}
+        tot, each = {}, []
         for cx in (ctx_lad, ctx_gbr):
-            for k, v in cx.prof_stop().items():
+            p, e = cx.prof_stop_launches()
+            for k, v in p.items():
                 tot[k] = tot.get(k, 0.0) + v[0]
+            each += e
             cx.poll_status()
         dom = max(tot, key=tot.get)
         brk = {k: round(v / 6, 4) for k, v in sorted(tot.items(), key=lambda kv: -kv[1])}
+        lps = {}   # executed launches per step of each class
+        for k in tot:
+            d = [ms for kk, ms in each if kk == k]
+            lps[k] = sum(1 for ms in d if ms >= EXECUTED_FRACTION * max(d)) / 6.0
+        brk = {'ms_per_step': brk, 'executed_launches_per_step': lps}
     else:
         for _ in range(6):
             ctx_of(i).rk3_step('hybrid', Q, 1e30, t)
@@ -404,7 +428,7 @@ def ramp3d(args, variants, cpu):
     desc = ('M2.9 24-deg ramp stand-in 1024x384x128 curvilinear, viscous, hybrid LAD-E4/MIG4 (global switch, '
             'LAD phases filtered) at the paper stage mix (C-GBR steps forced at 17.6 %), p_thr 0.5 p_inf, CFL 0.2')
     res = {'workload': desc, 'cells': cells}
-    traffic = os.path.join(ROOT, 'profiles', 'ramp3d_hybrid_mig4_mixed_hbm_traffic.txt')
+    traffic = os.path.join(ROOT, 'profiles', 'ramp3d_hybrid_paper_mix_mixed.txt')
     # headline: the hybrid at the paper's stage mix (Sec. 5: LAD 82.4 % of the M2.9 run).  From
     # this generator's state the switch finds no troubled node for thousands of steps (the
     # corner interaction that produces them in the paper develops over a flow-through), so
@@ -414,6 +438,8 @@ def ramp3d(args, variants, cpu):
     # dominant kernel class over six more, then exactly K timed steps with that class's
     # launches timed live on both contexts.  The natural window (the same steps, no forcing)
     # is reported beside it.
+    if args.only_variant:   # one variant alone (profiling): no headline window
+        return ramp3d_variants(args, R, res, context, Q0, cells, variants=True)
     head = context('mixed')
     forced = context('mixed', p_thr=1e30)
     log('ramp3d: headline at the paper stage mix, %d warm-up + %d timed steps' % (args.warmup, args.steps))
@@ -431,7 +457,7 @@ def ramp3d(args, variants, cpu):
                                      'pressure threshold marks every node troubled, at a share of %.3f of the '
                                      'steps spread evenly' % PAPER_GBR_STEP_SHARE},
                 'roofline': roof, 'roofline_step_floor': step_floor(cells, ms, RAMP_FLOOR_B_PER_CELL),
-                'kernel_breakdown_ms_per_step': brk})
+                'kernel_breakdown': brk})
     forced.close()
     # the natural window: the same number of steps from the same input, troubled stages as
     # the switch finds them
@@ -442,11 +468,14 @@ def ramp3d(args, variants, cpu):
                              'hybrid_stages': swn[0], 'cgbr_stages': swn[1],
                              'lad_share': round(1 - swn[1] / max(swn[0], 1), 4)}
     del Qn
-    st, why = profiled_step(traffic)
+    st, why = profiled_step(traffic, brk['executed_launches_per_step'])
     if st:   # whole-step figure: every kernel's counted HBM bytes over the measured step time
         gbs = st['bytes_per_step'] / (ms * 1e-3) / 1e9
         res['hbm_step'] = {'bytes_per_step': st['bytes_per_step'], 'achieved': round(gbs, 1), 'unit': 'GB/s',
-                           'frac_of_peak': round(gbs / HBM_PEAK_GBS, 4), 'valu_busy_pct': st['valu_busy_pct'],
+                           'frac_of_peak': round(gbs / HBM_PEAK_GBS, 4),
+                           'classes_without_counters': st['classes_without_counters'],
+                           'how': 'each class: counted bytes per executed launch (profile) x executed launches per '
+                                  'step (six live-profiled steps of the same mix)',
                            'source': os.path.relpath(traffic, ROOT)}
     else:
         res['hbm_step'] = {'source': os.path.relpath(traffic, ROOT) + ' (%s)' % why}
@@ -476,6 +505,17 @@ def ramp3d(args, variants, cpu):
         pc.close()
     del Q32
     torch.cuda.empty_cache()
+    res = ramp3d_variants(args, R, res, context, Q0, cells, variants)
+    if cpu:
+        res['cpu_baseline'] = cpu['ramp3d']
+    return res
+
+
+def ramp3d_variants(args, R, res, context, Q0, cells, variants):
+    """The config-4 variants (median of five timed blocks from the initial state) and the
+    paper's per-stage LAD / C-GBR speed-up study; with --only-variant, that one alone with
+    its per-class breakdown."""
+    import torch
     if variants:
         var = {}
         for vname, prec, scheme, grad, mode, *vv in (
@@ -514,8 +554,6 @@ def ramp3d(args, variants, cpu):
             for p in ('fp64', 'mixed')}
         res['lad_speedup']['paper_a100_fp64'] = {'lad_c6_over_meg6': '1.17-1.22', 'lad_c6_over_mig4': '1.38-1.43',
                                                  'lad_e4_over_meg6': '1.9-2.0', 'lad_e4_over_mig4': '2.2-2.3'}
-    if cpu:
-        res['cpu_baseline'] = cpu['ramp3d']
     return res
 
 
@@ -875,8 +913,132 @@ def batch64(args, variants, cpu):
 WORKLOADS = {'ramp3d': ramp3d, 'triple_point': triple_point, 'batch64': batch64}
 
 
+# ------------------------------------------------------------------ rocprofv3 summaries
+LIB_SOURCES = ['paper_2511_18042_amd/csrc/' + f for f in ('k_basic.hip', 'k_compact.hip', 'k_grad.hip', 'k_inflow.hip',
+                                                          'k_lad.hip', 'k_sweep.hip', 'lgbr.cpp', 'lgbr_dev.h',
+                                                          'lgbr_kernels.h')] + ['include/lgbr.h']
+
+
+def kernel_class(name):
+    """The library's kernel class (lg_prof_* classes; k_sweep_s serves eta and zeta) of a
+    kernel name as rocprofv3 prints it, or None for kernels outside the library."""
+    import re
+    base = name.split('(')[0].replace('void ', '').strip()
+    if not base.startswith('lg::'):
+        return None
+    k = base[4:]
+    m = re.match(r'k_line_tiles<\w+, (\d)', k)
+    if m:
+        return {0: 'grad_c4', 1: 'c6_faces', 2: 'filter', 3: 'grad_c4'}[int(m.group(1))]
+    table = [('k_bc_cons', 'bc'), ('k_fixed_ghosts', 'combine'), ('k_stage_ghosts', 'combine'), ('k_prim', 'prim'),
+             ('k_zero_any', 'flags'), ('k_any_flag', 'flags'), ('k_all_flag', 'flags'), ('k_switch_count', 'flags'),
+             ('k_dilate', 'flags'), ('k_line_list', 'flags'), ('k_hyb_queue', 'flags'),
+             ('k_grad_explicit', 'grad_e6'), ('k_grad_c4', 'grad_c4'), ('k_grad_c6', 'grad_c4'),
+             ('k_sensor', 'sensor'), ('k_gbr_viscflux', 'visc'), ('k_lad_shear', 'lad_node'),
+             ('k_lad_raw', 'lad_raw'), ('k_gauss', 'gauss'), ('k_lad_nodeflux', 'lad_flux'),
+             ('k_sweep_x', 'sweep_x'), ('k_sweep_s', 'sweep_yz'), ('k_dt_', 'dt'), ('k_lad_sweep', 'lad_sweep'),
+             ('k_c6_faces', 'c6_faces'), ('k_filter_save', 'filter_guard'), ('k_filter_guard', 'filter_guard'),
+             ('k_filter', 'filter'), ('k_gbr_items', 'gbr_items'), ('k_hyb_assemble', 'hyb_assemble'),
+             ('k_bc_scalar', 'bc_scalar')]
+    for pre, cls in table:
+        if k.startswith(pre):
+            return cls
+    return None
+
+
+def _dispatches(path, counter=False):
+    """(kernel name, duration ns, counter value or None) per dispatch of a rocprofv3 csv."""
+    import csv
+    out = []
+    for r in csv.DictReader(open(path)):
+        dur = int(r['End_Timestamp']) - int(r['Start_Timestamp'])
+        out.append((r['Kernel_Name'], dur, float(r['Counter_Value']) if counter else None))
+    return out
+
+
+def _executed(disp):
+    """Per kernel name: the dispatches that did work (at least EXECUTED_FRACTION of that
+    kernel's longest), the others being immediate returns of the hybrid switch."""
+    by = {}
+    for name, dur, val in disp:
+        by.setdefault(name, []).append((dur, val))
+    out = {}
+    for name, v in by.items():
+        top = max(d for d, _ in v)
+        out[name] = ([x for x in v if x[0] >= EXECUTED_FRACTION * top], len(v))
+    return out
+
+
+def profile_summary(a):
+    """Per-kernel and per-class summary of a kernel trace (and optionally FETCH_SIZE /
+    WRITE_SIZE counter runs of the same workload), with machine-readable KTIME / TRAFFIC
+    lines that bench.py reads while the library sources hash to what was profiled."""
+    import hashlib
+    h = hashlib.sha256()
+    for src in LIB_SOURCES:
+        h.update(open(os.path.join(ROOT, src), 'rb').read())
+    sha = h.hexdigest()
+    lines = ['# ' + a.title, '# commands:'] + ['#   ' + c.strip() for c in a.commands.split(';') if c.strip()]
+    lines.append('# a dispatch shorter than %g of its kernel\'s longest is an immediate return of the device-side '
+                 'hybrid switch ("skipped"); averages are over the executed dispatches' % EXECUTED_FRACTION)
+    ex = _executed(_dispatches(a.trace))
+    rows = []
+    for name, (run, n) in ex.items():
+        cls = kernel_class(name)
+        if cls is None:
+            continue
+        tot = sum(d for d, _ in run)
+        rows.append((tot, name.split('(')[0].replace('void ', ''), cls, n, len(run), tot / max(len(run), 1)))
+    rows.sort(reverse=True)
+    lines.append('%-44s %-12s %8s %8s %12s %12s' % ('kernel', 'class', 'calls', 'executed', 'avg exec us',
+                                                    'total ms'))
+    for tot, nm, cls, n, ne, avg in rows:
+        lines.append('%-44s %-12s %8d %8d %12.1f %12.3f' % (nm[:44], cls, n, ne, avg / 1e3, tot / 1e6))
+    cls_t = {}
+    for tot, nm, cls, n, ne, avg in rows:
+        a0 = cls_t.get(cls, (0, 0))
+        cls_t[cls] = (a0[0] + tot, a0[1] + ne)
+    lines.append('# per class (executed dispatches)')
+    for cls, (tot, ne) in sorted(cls_t.items(), key=lambda kv: -kv[1][0]):
+        lines.append('KTIME %s avg_ms=%.5f launches=%d' % (cls, tot / ne / 1e6, ne))
+    if a.fetch and a.write:
+        cal = {}
+        per = {}
+        for kind, path in (('fetch', a.fetch), ('write', a.write)):
+            disp = _dispatches(path, counter=True)
+            for name, dur, val in disp:
+                if name.startswith('__amd_rocclr_copyBuffer') and val > 1e5:
+                    cal[kind] = val
+            for name, (run, n) in _executed(disp).items():
+                cls = kernel_class(name)
+                if cls is None:
+                    continue
+                p = per.setdefault(cls, {'fetch': [0.0, 0], 'write': [0.0, 0]})
+                p[kind][0] += sum(v for _, v in run)
+                p[kind][1] += len(run)
+        copy_kib = float(a.copy_kib)
+        fs = copy_kib / cal['fetch'] if 'fetch' in cal else 1.0
+        ws = copy_kib / cal['write'] if 'write' in cal else 1.0
+        lines.append('# HBM counters: FETCH_SIZE and WRITE_SIZE in KiB per executed dispatch; a plain copy of %d KiB '
+                     'reads FETCH_SIZE %.0f and WRITE_SIZE %.0f: scales %.4f (fetch), %.4f (write)'
+                     % (copy_kib, cal.get('fetch', 0), cal.get('write', 0), fs, ws))
+        for cls, p in sorted(per.items()):
+            fk = p['fetch'][0] / max(p['fetch'][1], 1)
+            wk = p['write'][0] / max(p['write'][1], 1)
+            lines.append('TRAFFIC %s fetch_kib=%.0f write_kib=%.0f fetch_scale=%.4f write_scale=%.4f bytes=%.0f '
+                         'sha256=%s' % (cls, fk, wk, fs, ws, (fk * fs + wk * ws) * 1024, sha))
+    lines.append('SOURCES sha256=%s files=%s' % (sha, ','.join(LIB_SOURCES)))
+    with open(a.profile_summary, 'w') as f:
+        f.write('\n'.join(lines) + '\n')
+    print('\n'.join(lines))
+
+
 def main():
     args = parse()
+    if args.profile_summary:
+        args.copy_kib = args.copy_probe_mib * 1024 if args.copy_probe_mib else 1048576
+        profile_summary(args)
+        return
     if args.gpus != 1:
         print('bench.py: this build measures one GPU only (one process, one MI355X); '
               '--gpus %d is not supported' % args.gpus, file=sys.stderr)
@@ -900,12 +1062,12 @@ def main():
     head = results[names[0]]
     out = {
         'metric': 'Mcell-updates/s per RK3 step (hybrid vs C-GBR, FP32 vs FP64) and % HBM peak',
-        'value': head['value'],
+        'value': head.get('value'),
         'unit': 'Mcell-updates/s',
         'n_gpus': 1,
         'steps': args.steps,
         'warmup': args.warmup,
-        'ms_per_step': head['ms_per_step'],
+        'ms_per_step': head.get('ms_per_step'),
         'higher_is_better': True,
         'scaling': 'weak',
         'vs_baseline': None,

@@ -259,8 +259,10 @@ lg_status lg_get_tuning(const lg_ctx* ctx, int* seg, int* pcr_blocks, int* zc);
  * other lines are solved by PCR per (line, variable) or one lane per line.  The implicit
  * filter along xi on bounded lines of 128 to 2048 unknowns uses the partition method (one
  * wave per line and variable: segment solves joined through their end unknowns) unless bit
- * 13 is set.  mask in [0, 16383]; -1 restores the default (4095: tiles allowed, bits 12
- * and 13 clear).
+ * 13 is set; along eta and zeta, lines of 16 to 512 unknowns that are not in tiles are
+ * solved in register segments of at most 64 unknowns joined the same way (64 lines and one
+ * variable per workgroup) unless bit 14 is set, one lane per line otherwise.  mask in
+ * [0, 32767]; -1 restores the default (4095: tiles allowed, bits 12 to 14 clear).
  * lg_get_line_tiles returns the mask in effect (-1 for a null context).  Applies to later
  * calls and to batches created afterwards. */
 lg_status lg_set_line_tiles(lg_ctx* ctx, int mask);

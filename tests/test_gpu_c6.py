@@ -104,7 +104,7 @@ def test_lad_c6_rhs_parity_fp64(name, tiles):
     ctx.set_line_tiles(TILES[tiles])
     assert ctx.get_line_tiles() == (TILES[tiles] if TILES[tiles] >= 0 else 0xFFF)
     with pytest.raises(lgbr.LgError):
-        ctx.set_line_tiles(0x4000)
+        ctx.set_line_tiles(0x8000)
     assert ctx.get_line_tiles() == (TILES[tiles] if TILES[tiles] >= 0 else 0xFFF)
     out = U.gpu_rhs(ctx, c, 'lad')
     U.compare(out, ref, g, U.RHS_RTOL, label='lad-c6 %s %s' % (name, tiles))
