@@ -324,7 +324,7 @@ __device__ __forceinline__ double node_J(const Prob& P, int idx) { return met64(
 // FP32: capped at 128 registers (four waves per SIMD; a few spill slots): 2.70 -> 2.50 ms on
 // the 1024 x 384 x 128 ramp (the strided sweeps get slower under the same cap).
 template <typename R>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) k_sweep_x(const Prob* __restrict__ probs, StateRef ref, int sel, int accumulate,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1))) k_sweep_x(const Prob* __restrict__ probs, StateRef ref, int sel, int accumulate,
                                                  int skip_if_any, int rk, RKRef rr, int stage, double ca, double cb) {
   const Prob& P = probs[blockIdx.y];
   if (gate_skip(P, skip_if_any)) return;

@@ -97,3 +97,23 @@ def test_every_cell_troubled_equals_cgbr_bitwise():
     ctx.close()
     inner = (slice(None),) + g.interior()
     assert np.array_equal(hyb[inner], cg[inner])
+
+
+@pytest.mark.parametrize('name', ['2d_walls', '3d_curv'])
+@pytest.mark.parametrize('kind', ['scattered', 'tiles50', 'all'])
+def test_compacted_percell_mig4_without_line_tiles(name, kind):
+    """MIG4 per-cell stages with the LDS line tiles off: the listed lines (few troubled cells)
+    go one lane per line, and where most lines are listed every line is solved by the
+    region-free PCR / lane-per-line kernels."""
+    print('compacted no tiles', name, kind, flush=True)
+    c, gas = _case(name)
+    g = U.oracle_grid(c)
+    opts = orhs.Opts(grad='C4', hybrid_mode='percell', C_mu=0.002)
+    flags = _flags(g.shape, c.ndim, kind)
+    info = {}
+    ref = orhs.rhs(c.Q, g, gas, opts, 'hybrid', info=info, force_flags=flags)
+    ctx, _ = U.gpu_context(c, gas, opts)
+    ctx.set_line_tiles(0)
+    out = U.gpu_rhs(ctx, c, 'hybrid', flags=flags)
+    ctx.close()
+    U.compare(out, ref, g, U.RHS_RTOL, U.excused_mask(info, g), label='compacted no tiles %s %s' % (name, kind))
