@@ -875,11 +875,11 @@ def batch64(args, variants, cpu):
         finals[precision] = Qs
         if variants:
             log('batch64: %s, autotuning on the largest problem' % precision)
-            (zc, seg, pcr), _ = autotune.tune(ctxs[big], Q0s[big], 'hybrid', steps=3, use_cache=False)
+            best, _ = autotune.tune(ctxs[big], Q0s[big], 'hybrid', steps=3, use_cache=False)
             for cx in ctxs:
-                cx.set_tuning(seg, pcr, zc)
+                autotune.apply(cx, best)
             tms, tbad, _ = run(ctxs)
-            e['autotuned'] = dict(entry(tms, tbad), zc=zc, seg=seg)
+            e['autotuned'] = dict(entry(tms, tbad), **best)
         for cx in ctxs:
             cx.close()
         torch.cuda.empty_cache()

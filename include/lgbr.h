@@ -250,6 +250,13 @@ lg_status lg_prof_stop_launches(lg_ctx* ctx, double* ms, int* launches, float* e
  * values in effect (heuristic values resolved for the context's grid). */
 lg_status lg_set_tuning(lg_ctx* ctx, int seg, int pcr_blocks, int zc);
 lg_status lg_get_tuning(const lg_ctx* ctx, int* seg, int* pcr_blocks, int* zc);
+/* Tile shapes (no effect on results): zm_width = columns along xi of the tiles of the
+ * z-marching stencil kernels, which hold 256 columns (32 x 8, 64 x 4 or 128 x 2; 0 restores
+ * 64); line_batch = most lines per LDS line tile of the compact solves (1..16; 0 = as many as
+ * fit the tile).  Other values return LG_EINVAL.  Applies to later calls on the context and
+ * to batches created afterwards; lg_get_tile_shape reports the values in effect. */
+lg_status lg_set_tile_shape(lg_ctx* ctx, int zm_width, int line_batch);
+lg_status lg_get_tile_shape(const lg_ctx* ctx, int* zm_width, int* line_batch);
 /* Line-solve kernels of the compact schemes (no effect on results beyond rounding): bit
  * 3 s + d of mask allows LDS line tiles (all five variables of a few lines in one
  * workgroup) for system s (0 = LAD-C6 gradients, 1 = LAD-C6 interface fluxes, 2 = implicit

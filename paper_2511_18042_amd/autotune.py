@@ -1,28 +1,38 @@
 """Launch-shape autotuner for liblgbr (results never depend on the tuning).
 
-Times whole RK3 steps of a context through the C ABI over the launch-shape knobs -- planes
-per chunk of the z-marching stencil kernels, nodes per lane of the strided sweeps and the
-persistent PCR grid (compact gradients only) -- one knob at a time with the others at their
-best so far, keeps the fastest setting and caches it in a JSON file keyed by device, grid,
-precision, gradient kind and scheme.  Tuning runs on a scratch copy of the state.
+Times whole RK3 steps of a context through the C ABI over its launch-shape knobs -- the tile
+shape of the z-marching stencil kernels (32 x 8, 64 x 4 or 128 x 2 columns), the planes per
+chunk they walk, the nodes per lane of the strided sweeps, the lines per LDS line tile of the
+compact solves and the persistent PCR grid (compact gradients only) -- one knob at a time
+with the others at their best so far, keeps the fastest setting and caches it in a JSON file
+keyed by the GPU architecture, grid, precision, gradient kind and scheme.  Tuning runs on a
+scratch copy of the state.
 """
 import json
 import os
 
+CANDIDATE_ZM_WIDTH = (64, 32, 128)
 CANDIDATE_ZC = (0, 8, 16, 32)
 CANDIDATE_SEG = (0, 4, 8, 16, 32)
+CANDIDATE_LINE_BATCH = (0, 8, 4, 2)
 CANDIDATE_PCR = (0, 4096, 32768)
+KNOBS = ('zm_width', 'zc', 'seg', 'line_batch', 'pcr_blocks')
 
 
 def cache_path():
     return os.environ.get('LGBR_TUNE_CACHE', os.path.join(os.path.expanduser('~'), '.cache', 'lgbr_tune.json'))
 
 
-def _key(ctx, scheme):
+def _arch():
     import torch
+    p = torch.cuda.get_device_properties(0)
+    return getattr(p, 'gcnArchName', None) or p.name
+
+
+def _key(ctx, scheme):
     g = ctx.grid
-    return '|'.join(str(v) for v in (torch.cuda.get_device_name(0), g.ndim, tuple(g.n), ctx.opts.precision,
-                                      ctx.opts.grad, ctx.opts.hybrid_mode, scheme))
+    return '|'.join(str(v) for v in (_arch(), g.ndim, tuple(g.n), ctx.opts.precision, ctx.opts.grad,
+                                      ctx.opts.hybrid_mode, ctx.opts.lad_scheme, scheme))
 
 
 def load_cache():
@@ -42,24 +52,30 @@ def save_cache(cache):
     os.replace(tmp, p)
 
 
+def apply(ctx, s):
+    """Set the knobs of the dict ``s`` (keys KNOBS) on a context."""
+    ctx.set_tuning(s['seg'], s['pcr_blocks'], s['zc'])
+    ctx.set_tile_shape(s['zm_width'], s['line_batch'])
+
+
 def tune(ctx, Q0, scheme, steps=3, use_cache=True):
-    """Pick (zc, seg, pcr_blocks) for ``ctx`` by timing ``steps`` RK3 steps per candidate on a
-    copy of the device state Q0; applies and returns the winner and the timings (ms/step)."""
+    """Pick the launch shape of ``ctx`` by timing ``steps`` RK3 steps per candidate on a copy
+    of the device state Q0; applies and returns the winner (dict over KNOBS) and the timings
+    (ms per step, keyed by the candidate)."""
     import torch
     key = _key(ctx, scheme)
     cache = load_cache() if use_cache else {}
     if key in cache:
-        e = cache[key]
-        best = (e['zc'], e['seg'], e['pcr_blocks'])
-        ctx.set_tuning(best[1], best[2], best[0])
-        return best, e.get('timings', {})
+        best = {k: cache[key][k] for k in KNOBS}
+        apply(ctx, best)
+        return best, cache[key].get('timings', {})
     timings = {}
 
-    def measure(zc, seg, pcr):
-        name = '%d,%d,%d' % (zc, seg, pcr)
+    def measure(s):
+        name = ','.join('%s=%d' % (k, s[k]) for k in KNOBS)
         if name in timings:
             return timings[name]
-        ctx.set_tuning(seg, pcr, zc)
+        apply(ctx, s)
         Q = Q0.clone()
         t = torch.zeros(1, dtype=torch.float64, device='cuda')
         ctx.rk3_step(scheme, Q, 1e30, t)
@@ -74,18 +90,19 @@ def tune(ctx, Q0, scheme, steps=3, use_cache=True):
         timings[name] = e0.elapsed_time(e1) / steps
         return timings[name]
 
-    best = [0, 0, 0]
-    for slot, cands in ((0, CANDIDATE_ZC), (1, CANDIDATE_SEG), (2, CANDIDATE_PCR if ctx.opts.grad == 1 else (0,))):
+    best = {'zm_width': 64, 'zc': 0, 'seg': 0, 'line_batch': 0, 'pcr_blocks': 0}
+    compact = ctx.opts.grad == 1 or ctx.opts.lad_scheme == 1 or ctx.opts.filter_alpha < 0.5
+    for knob, cands in (('zm_width', CANDIDATE_ZM_WIDTH), ('zc', CANDIDATE_ZC), ('seg', CANDIDATE_SEG),
+                        ('line_batch', CANDIDATE_LINE_BATCH if compact else (0,)),
+                        ('pcr_blocks', CANDIDATE_PCR if ctx.opts.grad == 1 else (0,))):
         scores = {}
         for v in cands:
-            trial = list(best)
-            trial[slot] = v
-            scores[v] = measure(*trial)
-        best[slot] = min(scores, key=scores.get)
-    zc, seg, pcr = best
-    ctx.set_tuning(seg, pcr, zc)
+            trial = dict(best, **{knob: v})
+            scores[v] = measure(trial)
+        best[knob] = min(scores, key=scores.get)
+    apply(ctx, best)
     ctx.poll_status()
     if use_cache:
-        cache[key] = {'zc': zc, 'seg': seg, 'pcr_blocks': pcr, 'timings': timings}
+        cache[key] = dict(best, timings=timings)
         save_cache(cache)
-    return (zc, seg, pcr), timings
+    return best, timings

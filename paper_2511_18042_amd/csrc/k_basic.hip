@@ -568,9 +568,9 @@ void launch_prim(const Launch& L, StateRef ref, int want_flags, const uint8_t* f
 
 void launch_any_flag(const Launch& L, int interior_only) {
   hipLaunchKernelGGL(k_zero_any, dim3(1, L.nprob), dim3(64), 0, L.stream, L.probs);
-  const dim3 grid = interior_only ? zm_grid(L, 0, 0, ZM_TX, ZM_TY) : grid_for(L.max_total, L.nprob);
+  const dim3 grid = interior_only ? zm_grid_col(L, 0, 0) : grid_for(L.max_total, L.nprob);
   LG_TIMED(L, KC_FLAGS, hipLaunchKernelGGL(k_any_flag, grid, dim3(256), 0, L.stream, L.probs, interior_only,
-                                           zm_chunk(L, 0, 0)));
+                                           zm_arg(L, 0, 0)));
 }
 
 void launch_dilate(const Launch& L, int ndim, int radius, int first_src, int final_buf) {
@@ -586,8 +586,8 @@ void launch_dilate(const Launch& L, int ndim, int radius, int first_src, int fin
 
 void launch_hyb_queue(const Launch& L, int ndim) {
   hipLaunchKernelGGL(k_hyb_init, dim3(1, L.nprob), dim3(64), 0, L.stream, L.probs);
-  LG_TIMED(L, KC_FLAGS, hipLaunchKernelGGL(k_all_flag, zm_grid(L, 0, 0, ZM_TX, ZM_TY), dim3(256), 0, L.stream,
-                                           L.probs, zm_chunk(L, 0, 0)));
+  LG_TIMED(L, KC_FLAGS, hipLaunchKernelGGL(k_all_flag, zm_grid_col(L, 0, 0), dim3(256), 0, L.stream,
+                                           L.probs, zm_arg(L, 0, 0)));
   for (int d = 0; d < ndim; ++d) {
     long long tot = 1;
     for (int l = 0; l < 3; ++l) tot *= L.max_n[l] + (l == d ? 1 : 0);
@@ -608,8 +608,8 @@ void launch_line_lists(const Launch& L, int ndim) {
 
 void launch_dt(const Launch& L, const double* Qx, double* tx, double t_end, int advance_t) {
   hipLaunchKernelGGL(k_dt_reset, dim3(1, L.nprob), dim3(64), 0, L.stream, L.probs);
-  LG_TIMED(L, KC_DT, hipLaunchKernelGGL(k_dt_reduce, zm_grid(L, 0, 0, ZM_TX, ZM_TY), dim3(256), 0, L.stream,
-                                        L.probs, Qx, zm_chunk(L, 0, 0)));
+  LG_TIMED(L, KC_DT, hipLaunchKernelGGL(k_dt_reduce, zm_grid_col(L, 0, 0), dim3(256), 0, L.stream,
+                                        L.probs, Qx, zm_arg(L, 0, 0)));
   hipLaunchKernelGGL(k_dt_finalize, dim3(1, L.nprob), dim3(64), 0, L.stream, L.probs, tx, t_end, advance_t);
 }
 

@@ -1310,6 +1310,7 @@ static inline int tile_tx(long long Lmax) {
 template <typename R, int KIND>
 static void launch_tiles(const Launch& L, int kc, long long Lmax, long long lines_a, long long lines_b, TileArgs A) {
   A.TX = tile_tx(Lmax);
+  if (L.tile_lines > 0) A.TX = std::min(A.TX, L.tile_lines);
   const long long nt = ((lines_a + A.TX - 1) / A.TX) * lines_b;
   const unsigned grid = (unsigned)(8 * ((nt + 7) / 8));
   if (A.d == 0 || A.TX >= 8)

@@ -852,23 +852,23 @@ static inline dim3 g1(long long work, int nprob, long long cap = 1LL << 30) {
 
 template <typename R>
 void launch_lad(const Launch& L, int skip_if_any, int cg) {
-  const int zb = zm_chunk(L, -2, 2), zi = zm_chunk(L, 0, 0);
+  const int zb = zm_arg(L, -2, 2), zi = zm_arg(L, 0, 0);
   if (cg) {
-    LG_TIMED(L, KC_LAD_NODE, hipLaunchKernelGGL((k_lad_shear<R, true>), zm_grid(L, -2, 2, ZM_TX, ZM_TY), dim3(256),
+    LG_TIMED(L, KC_LAD_NODE, hipLaunchKernelGGL((k_lad_shear<R, true>), zm_grid_col(L, -2, 2), dim3(256),
                                                 0, L.stream, L.probs, skip_if_any, zb));
-    LG_TIMED(L, KC_LAD_RAW, hipLaunchKernelGGL((k_lad_raw<R, true>), zm_grid(L, 0, 0, ZM_TX, ZM_TY), dim3(256), 0,
+    LG_TIMED(L, KC_LAD_RAW, hipLaunchKernelGGL((k_lad_raw<R, true>), zm_grid_col(L, 0, 0), dim3(256), 0,
                                                L.stream, L.probs, skip_if_any, zi));
   } else {
-    LG_TIMED(L, KC_LAD_NODE, hipLaunchKernelGGL((k_lad_shear<R, false>), zm_grid(L, -2, 2, ZM_TX, ZM_TY), dim3(256),
+    LG_TIMED(L, KC_LAD_NODE, hipLaunchKernelGGL((k_lad_shear<R, false>), zm_grid_col(L, -2, 2), dim3(256),
                                                 0, L.stream, L.probs, skip_if_any, zb));
-    LG_TIMED(L, KC_LAD_RAW, hipLaunchKernelGGL((k_lad_raw<R, false>), zm_grid(L, 0, 0, ZM_TX, ZM_TY), dim3(256), 0,
+    LG_TIMED(L, KC_LAD_RAW, hipLaunchKernelGGL((k_lad_raw<R, false>), zm_grid_col(L, 0, 0), dim3(256), 0,
                                                L.stream, L.probs, skip_if_any, zi));
   }
   constexpr int GTY = sizeof(R) == 4 ? 16 : 8;
   LG_TIMED(L, KC_GAUSS, hipLaunchKernelGGL((k_gauss_xy<R, GTY>), zm_grid(L, 0, 0, 64, GTY), dim3(256), 0, L.stream,
-                                           L.probs, skip_if_any, zi));
+                                           L.probs, skip_if_any, zm_chunk(L, 0, 0)));
   if (L.ndim > 2)
-    LG_TIMED(L, KC_GAUSS, hipLaunchKernelGGL(k_gauss_z<R>, zm_grid(L, 0, 0, ZM_TX, ZM_TY), dim3(256), 0, L.stream,
+    LG_TIMED(L, KC_GAUSS, hipLaunchKernelGGL(k_gauss_z<R>, zm_grid_col(L, 0, 0), dim3(256), 0, L.stream,
                                              L.probs, skip_if_any, zi));
 }
 
@@ -877,8 +877,8 @@ static inline int lad_coef_buf(const Launch& L) { return L.ndim > 2 ? 0 : 1; }
 
 template <typename R>
 void launch_lad_nodeflux(const Launch& L, int skip_if_any, int cg) {
-  const dim3 grid = zm_grid(L, -2, 2, ZM_TX, ZM_TY);
-  const int zb = zm_chunk(L, -2, 2);
+  const dim3 grid = zm_grid_col(L, -2, 2);
+  const int zb = zm_arg(L, -2, 2);
   if (cg)
     LG_TIMED(L, KC_LAD_FLUX, hipLaunchKernelGGL((k_lad_nodeflux<R, true>), grid, dim3(256), 0, L.stream, L.probs,
                                                 lad_coef_buf(L), skip_if_any, zb));
@@ -895,28 +895,28 @@ void launch_lad_geometry(const Launch& L) {
 template <typename R>
 void launch_lad_sweep(const Launch& L, StateRef ref, const RKRef* rr, int stage, double a, double b, int skip_if_any) {
   RKRef r = rr ? *rr : RKRef{nullptr, nullptr, nullptr};
-  const dim3 grid = zm_grid(L, 0, 0, ZM_TX, ZM_TY);
+  const dim3 grid = zm_grid_col(L, 0, 0);
   // FP32 fluxes: 115 registers with 32-bit offsets (4 waves per SIMD), 7 % faster on the
   // ramp; FP64 needs 164 that way (3 waves) and runs faster with generic addressing
   if (sizeof(R) == 4 && !L.o64)
     LG_TIMED(L, KC_LAD_SWEEP, hipLaunchKernelGGL((k_lad_sweep<R, true>), grid, dim3(256), 0, L.stream, L.probs, ref,
-                                                 r, rr ? 1 : 0, stage, a, b, skip_if_any, zm_chunk(L, 0, 0)));
+                                                 r, rr ? 1 : 0, stage, a, b, skip_if_any, zm_arg(L, 0, 0)));
   else
     LG_TIMED(L, KC_LAD_SWEEP, hipLaunchKernelGGL((k_lad_sweep<R, false>), grid, dim3(256), 0, L.stream, L.probs, ref,
-                                                 r, rr ? 1 : 0, stage, a, b, skip_if_any, zm_chunk(L, 0, 0)));
+                                                 r, rr ? 1 : 0, stage, a, b, skip_if_any, zm_arg(L, 0, 0)));
   if (rr) launch_stage_ghosts(L, *rr, stage, skip_if_any);
 }
 
 template <typename R>
 void launch_hyb_assemble(const Launch& L, StateRef ref, const RKRef* rr, int stage, double a, double b) {
   RKRef r = rr ? *rr : RKRef{nullptr, nullptr, nullptr};
-  const dim3 grid = zm_grid(L, 0, 0, ZM_TX, ZM_TY);
+  const dim3 grid = zm_grid_col(L, 0, 0);
   if (sizeof(R) == 4 && !L.o64)
     LG_TIMED(L, KC_HYB_ASSEMBLE, hipLaunchKernelGGL((k_hyb_assemble<R, true>), grid, dim3(256), 0, L.stream, L.probs,
-                                                    ref, r, rr ? 1 : 0, stage, a, b, zm_chunk(L, 0, 0)));
+                                                    ref, r, rr ? 1 : 0, stage, a, b, zm_arg(L, 0, 0)));
   else
     LG_TIMED(L, KC_HYB_ASSEMBLE, hipLaunchKernelGGL((k_hyb_assemble<R, false>), grid, dim3(256), 0, L.stream, L.probs,
-                                                    ref, r, rr ? 1 : 0, stage, a, b, zm_chunk(L, 0, 0)));
+                                                    ref, r, rr ? 1 : 0, stage, a, b, zm_arg(L, 0, 0)));
   if (rr) launch_stage_ghosts(L, *rr, stage, GATE_MIXED);
 }
 

@@ -1098,6 +1098,22 @@ lg_status lg_set_generic_access(lg_ctx* c, int generic) {
   return LG_OK;
 }
 
+lg_status lg_set_tile_shape(lg_ctx* c, int zm_width, int line_batch) {
+  if (!c || !(zm_width == 0 || zm_width == 32 || zm_width == 64 || zm_width == 128) || line_batch < 0 ||
+      line_batch > lg::TILE_MAX_TX)
+    return LG_EINVAL;
+  c->L.ztx = zm_width;
+  c->L.tile_lines = line_batch;
+  return LG_OK;
+}
+
+lg_status lg_get_tile_shape(const lg_ctx* c, int* zm_width, int* line_batch) {
+  if (!c || !zm_width || !line_batch) return LG_EINVAL;
+  *zm_width = lg::zm_width(c->L);
+  *line_batch = c->L.tile_lines;
+  return LG_OK;
+}
+
 lg_status lg_get_tuning(const lg_ctx* c, int* seg, int* pcr_blocks, int* zc) {
   if (!c || !seg || !pcr_blocks || !zc) return LG_EINVAL;
   *seg = lg::sweep_seg(c->L, c->cfg.ndim > 1 ? 1 : 0);
@@ -1293,6 +1309,8 @@ lg_status lg_batch_create(lg_batch** out, lg_ctx* const* ctxs, double* const* Q,
   b->L.seg = ctxs[0]->L.seg;
   b->L.pcr_blocks = ctxs[0]->L.pcr_blocks;
   b->L.zc = ctxs[0]->L.zc;
+  b->L.ztx = ctxs[0]->L.ztx;
+  b->L.tile_lines = ctxs[0]->L.tile_lines;
   b->L.tile_mask = ctxs[0]->L.tile_mask;
   for (int i = 0; i < n; ++i) {
     Prob P = ctxs[i]->hp;

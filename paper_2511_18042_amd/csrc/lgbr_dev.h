@@ -189,8 +189,8 @@ __device__ __forceinline__ void zm_band(const Prob& P, int lo, int hi, int org[3
   }
 }
 
-template <int TX, int TY>
-__device__ __forceinline__ bool zm_tile(const int ext[3], int zc, int& ti0, int& tj0, int& k0, int& k1) {
+__device__ __forceinline__ bool zm_tile_rt(const int ext[3], int zc, int TX, int TY, int& ti0, int& tj0, int& k0,
+                                           int& k1) {
   const int ntx = (ext[0] + TX - 1) / TX, nty = (ext[1] + TY - 1) / TY, nch = (ext[2] + zc - 1) / zc;
   const int nblk = ntx * nty * nch;
   const int per = (nblk + 7) >> 3;
@@ -205,19 +205,28 @@ __device__ __forceinline__ bool zm_tile(const int ext[3], int zc, int& ti0, int&
   return true;
 }
 
+template <int TX, int TY>
+__device__ __forceinline__ bool zm_tile(const int ext[3], int zc, int& ti0, int& tj0, int& k0, int& k1) {
+  return zm_tile_rt(ext, zc, TX, TY, ti0, tj0, k0, k1);
+}
+
 constexpr int ZM_TX = 64, ZM_TY = 4;
 
 struct ZCol {
   int i, j, k0, k1;  // padded positions of the column; planes [k0, k1)
 };
 
-// This thread's column of a 64 x 4 z-marching launch; false if it has none.
-__device__ __forceinline__ bool zm_column(const Prob& P, int lo, int hi, int zc, ZCol& c) {
+// This thread's column of a z-marching launch of 256 lanes; false if it has none.  zcw: the
+// planes per chunk in its low 16 bits, above them log2 of the tile width along xi (the tile
+// has 256 / width rows; 0: the default 64 x 4).
+__device__ __forceinline__ bool zm_column(const Prob& P, int lo, int hi, int zcw, ZCol& c) {
   int org[3], ext[3];
   zm_band(P, lo, hi, org, ext);
+  const int lt = zcw >> 16;
+  const int TX = lt ? 1 << lt : ZM_TX, TY = 256 / TX;
   int ti0, tj0, k0, k1;
-  if (!zm_tile<ZM_TX, ZM_TY>(ext, zc, ti0, tj0, k0, k1)) return false;
-  const int ti = ti0 + (int)(threadIdx.x % ZM_TX), tj = tj0 + (int)(threadIdx.x / ZM_TX);
+  if (!zm_tile_rt(ext, zcw & 0xFFFF, TX, TY, ti0, tj0, k0, k1)) return false;
+  const int ti = ti0 + (int)(threadIdx.x & (TX - 1)), tj = tj0 + (int)(threadIdx.x >> (lt ? lt : 6));
   if (ti >= ext[0] || tj >= ext[1]) return false;
   c.i = org[0] + ti;
   c.j = org[1] + tj;

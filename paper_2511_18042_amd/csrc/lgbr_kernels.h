@@ -92,6 +92,8 @@ struct Launch {
   int seg;                 // nodes per thread in the strided sweeps (0: heuristic)
   int pcr_blocks;          // persistent workgroups of the PCR line solves (0: heuristic)
   int zc;                  // planes per chunk of the z-marching kernels (0: heuristic)
+  int ztx;                 // width along xi of the z-marching tiles (32, 64, 128; 0: 64)
+  int tile_lines;          // most lines per LDS line tile (0: as many as fit)
   int item_blocks;         // persistent workgroups of the compacted C-GBR interface pass (0: 2048)
   int fpart;               // some problem filters along xi with the partition-method kernel
   int fseg[3];             // most segments per line of the problems filtering along d by k_filter_seg (0: none)
@@ -180,6 +182,16 @@ inline dim3 zm_grid(const Launch& L, int lo, int hi, int TX, int TY) {
   const int zc = zm_chunk(L, lo, hi);
   long long nblk = ((e[0] + TX - 1) / TX) * ((e[1] + TY - 1) / TY) * ((e[2] + zc - 1) / zc);
   return dim3((unsigned)(8 * ((nblk + 7) / 8)), L.nprob);
+}
+// tile width of the z-marching column kernels, their grid, and their zc argument (the
+// chunk length with log2 of a non-default width above bit 16; see zm_column)
+inline int zm_width(const Launch& L) { return L.ztx > 0 ? L.ztx : ZM_TX; }
+inline dim3 zm_grid_col(const Launch& L, int lo, int hi) { return zm_grid(L, lo, hi, zm_width(L), 256 / zm_width(L)); }
+inline int zm_arg(const Launch& L, int lo, int hi) {
+  int lt = 0;
+  if (L.ztx > 0 && L.ztx != ZM_TX)
+    while ((1 << lt) < L.ztx) ++lt;
+  return zm_chunk(L, lo, hi) | (lt << 16);
 }
 
 // gradients (region = 1: only where the per-cell hybrid needs C-GBR inputs)

@@ -24,7 +24,7 @@ EXPORTS = ('lg_set_allocator', 'lg_strerror', 'lg_create', 'lg_destroy', 'lg_wor
            'lg_prof_start', 'lg_prof_stop', 'lg_set_tuning', 'lg_get_tuning', 'lg_metrics_planar', 'lad_filter',
            'lg_set_line_tiles', 'lg_get_line_tiles', 'lg_set_generic_access', 'lg_switch_stats', 'lg_df_create',
            'lg_df_random_count', 'lg_df_update', 'lg_df_destroy', 'lg_metrics_from_coords_noalloc',
-           'lg_prof_stop_launches')
+           'lg_prof_stop_launches', 'lg_set_tile_shape', 'lg_get_tile_shape')
 KERNEL_CLASSES = ('bc', 'prim', 'flags', 'grad_e6', 'grad_c4', 'sensor', 'visc', 'lad_node', 'lad_raw', 'gauss',
                   'lad_flux', 'sweep_x', 'sweep_y', 'sweep_z', 'combine', 'dt', 'bc_scalar', 'lad_sweep',
                   'c6_faces', 'filter', 'gbr_items', 'hyb_assemble', 'filter_guard')
@@ -91,6 +91,8 @@ def load():
         'lg_switch_stats': (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), I]),
         'lg_prof_start': (I, [P, I, I]),
         'lg_prof_stop': (I, [P, ctypes.POINTER(D), ctypes.POINTER(I)]),
+        'lg_set_tile_shape': (I, [P, I, I]),
+        'lg_get_tile_shape': (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
         'lg_prof_stop_launches': (I, [P, ctypes.POINTER(D), ctypes.POINTER(I), ctypes.POINTER(ctypes.c_float),
                                       ctypes.POINTER(I), I, ctypes.POINTER(I)]),
         'lg_set_tuning': (I, [P, I, I, I]),
@@ -252,12 +254,20 @@ class Context:
         ecls = (ctypes.c_int * cap)()
         got = ctypes.c_int(0)
         _check(self._lib.lg_prof_stop_launches(self.handle, ms, cnt, each, ecls, int(cap), ctypes.byref(got)),
-               'lg_prof_stop_launches')
+               'lg_prof_stop_launches', 'lg_set_tile_shape', 'lg_get_tile_shape')
         return ({KERNEL_CLASSES[k]: (ms[k], cnt[k]) for k in range(n) if cnt[k]},
                 [(KERNEL_CLASSES[ecls[i]], float(each[i])) for i in range(got.value)])
 
     def set_tuning(self, seg=0, pcr_blocks=0, zc=0):
         _check(self._lib.lg_set_tuning(self.handle, int(seg), int(pcr_blocks), int(zc)), 'lg_set_tuning')
+
+    def set_tile_shape(self, zm_width=0, line_batch=0):
+        _check(self._lib.lg_set_tile_shape(self.handle, int(zm_width), int(line_batch)), 'lg_set_tile_shape')
+
+    def get_tile_shape(self):
+        w, b = ctypes.c_int(0), ctypes.c_int(0)
+        _check(self._lib.lg_get_tile_shape(self.handle, ctypes.byref(w), ctypes.byref(b)), 'lg_get_tile_shape')
+        return w.value, b.value
 
     def set_line_tiles(self, mask=-1):
         _check(self._lib.lg_set_line_tiles(self.handle, int(mask)), 'lg_set_line_tiles')

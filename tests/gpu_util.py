@@ -106,4 +106,6 @@ def compare(gpu, ref, grid, rtol, excuse=None, label=''):
         raise AssertionError('%s: %d mismatching nodes (first %s); worst rel err per var %s'
                              % (label, int(unexcused.sum()), idx.tolist(), worst))
     assert n_exc <= max(1, int(1e-3 * n_nodes)), '%s: %d excused nodes > 0.1%%' % (label, n_exc)
+    if n_exc:   # reported, so that a run shows every excusal it relied on
+        print('EXCUSED %s: %d nodes (oracle margin <= %g)' % (label, n_exc, MARGIN), flush=True)
     return n_exc

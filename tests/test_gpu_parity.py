@@ -8,7 +8,7 @@ import pytest
 
 import gpu_util as U
 from oracle import grid as ogrid, rhs as orhs
-from paper_2511_18042_amd import cases
+from paper_2511_18042_amd import cases, lgbr
 
 pytestmark = pytest.mark.gpu
 
@@ -320,9 +320,10 @@ def test_ramp_crop_rk3_step_and_mixed_error():
 
 
 def test_launch_tuning_leaves_results_bitwise_unchanged(tmp_path, monkeypatch):
-    """Segment length of the strided sweeps and the persistent PCR grid size only change
-    the launch shape: the RHS is bitwise identical for every setting, and the autotuner
-    picks one of its candidates and caches it."""
+    """Segment length of the strided sweeps, the persistent PCR grid size, the z-marching
+    tile shape, its chunk length and the lines per LDS line tile only change the launch
+    shape: the RHS is bitwise identical for every setting, invalid shapes are refused, and
+    the autotuner picks one of its candidates and caches it."""
     torch = U.torch_mod()
     from paper_2511_18042_amd import autotune
     c, gas = _ramp_case()
@@ -331,20 +332,27 @@ def test_launch_tuning_leaves_results_bitwise_unchanged(tmp_path, monkeypatch):
     flags = np.random.default_rng(10).random(g.shape) < 0.1
     ctx, _ = U.gpu_context(c, gas, opts)
     outs = []
-    for seg, pcr, zc in ((0, 0, 0), (2, 256, 1), (7, 1000, 5), (64, 65536, 1024)):
-        print('tuning', seg, pcr, zc, flush=True)
+    for seg, pcr, zc, zw, lb in ((0, 0, 0, 0, 0), (2, 256, 1, 32, 1), (7, 1000, 5, 128, 3),
+                                 (64, 65536, 1024, 64, 16), (4, 0, 3, 32, 2)):
+        print('tuning', seg, pcr, zc, zw, lb, flush=True)
         ctx.set_tuning(seg, pcr, zc)
+        ctx.set_tile_shape(zw, lb)
         s, p, z = ctx.get_tuning()
         assert (seg == 0 or s == seg) and p == (pcr or 16384) and (zc == 0 or z == zc)
+        assert ctx.get_tile_shape() == (zw or 64, lb)
         for scheme, fl in (('hybrid', flags), ('lad', None)):
             outs.append(U.gpu_rhs(ctx, c, scheme, flags=fl))
     for i, o in enumerate(outs[2:]):
         assert np.array_equal(o, outs[i % 2])
+    for bad in ((48, 0), (64, 17), (64, -1)):
+        with pytest.raises(lgbr.LgError):
+            ctx.set_tile_shape(*bad)
     monkeypatch.setenv('LGBR_TUNE_CACHE', str(tmp_path / 'tune.json'))
     Q0 = U.dev(c.Q)
     best, timings = autotune.tune(ctx, Q0, 'hybrid', steps=1)
-    zc, seg, pcr = best
-    assert zc in autotune.CANDIDATE_ZC and seg in autotune.CANDIDATE_SEG and pcr in autotune.CANDIDATE_PCR
+    assert best['zc'] in autotune.CANDIDATE_ZC and best['seg'] in autotune.CANDIDATE_SEG
+    assert best['pcr_blocks'] in autotune.CANDIDATE_PCR and best['zm_width'] in autotune.CANDIDATE_ZM_WIDTH
+    assert best['line_batch'] in autotune.CANDIDATE_LINE_BATCH
     assert len(timings) >= len(autotune.CANDIDATE_ZC)
     assert autotune.tune(ctx, Q0, 'hybrid')[0] == best          # served from the cache
     ctx.close()
