@@ -74,6 +74,7 @@ enum { LG_FP64 = 0, LG_MIXED = 1 };               /* FP64 everywhere / FP32 bulk
 enum { LG_HYB_PERCELL = 0, LG_HYB_GLOBAL = 1 };   /* hybrid selection (Sec. 5, Alg. 3)   */
 enum { LG_SCHEME_CGBR = 0, LG_SCHEME_LAD = 1, LG_SCHEME_HYBRID = 2 };
 enum { LG_LAD_E4 = 0, LG_LAD_C6 = 1 };            /* central scheme of LG_SCHEME_LAD        */
+enum { LG_RK3 = 0, LG_RK4 = 1 };                  /* time integrator (lg_opts.time_scheme)  */
 
 typedef struct {
   int ndim;            /* 1, 2 or 3 active directions                                 */
@@ -119,8 +120,12 @@ typedef struct {
                           solver (Alg. 1 FILTER_CALLS, also in the hybrid's LAD phases,
                           Alg. 3): LG_SCHEME_LAD with LAD-E4 or LAD-C6, and hybrid stages
                           that ran LAD; 0 <= alpha_f <= 0.5, 0.5 = no filter          */
-  int filter_every_stage; /* 0: filter after the third stage (Alg. 1); 1: after every
+  int filter_every_stage; /* 0: filter after the last stage (Alg. 1); 1: after every
                           stage of rk3_step that ran LAD (an alternative reading)      */
+  int time_scheme;     /* LG_RK3: SSP-RK3 (Sec. 2.3, every scheme); LG_RK4: the classic
+                          four-stage RK4 (Sec. 2.1 names RK4,4 for the LAD solver; LAD-C6
+                          filters in its fourth stage, Sec. 5), LG_SCHEME_LAD steps only:
+                          rk3_step and batches refuse other schemes (LG_EUNSUPPORTED)    */
 } lg_opts;
 
 typedef struct lg_ctx lg_ctx;

@@ -33,6 +33,9 @@ Readings used here:
        filter): LAD-E4 and LAD-C6 alike, the global hybrid's LAD stages, and the nodes
        outside the dilated troubled set of a per-cell hybrid stage.  C-GBR stages are
        never filtered (Alg. 2).
+  R38  LAD-C6 may march with the classic four-stage RK4 (Sec. 2.1 names RK4,4 beside the
+       TVD RK3; Sec. 5 places LAD-C6's filter in the fourth Runge-Kutta stage), the filter
+       after the fourth stage; C-GBR and the hybrid keep SSP-RK3 (Sec. 2.3, Sec. 5).
   R37  in a hybrid stage, a node whose filtered state would not be physical (density or
        pressure not positive, or not finite) keeps its unfiltered state.  The paper's
        criterion (Sec. 5) hands the troubled cells to C-GBR, which is never filtered; the
@@ -80,6 +83,7 @@ class Opts:
     lad: str = 'E4'               # LAD central scheme: 'E4' or 'C6'
     filter_alpha: float = 0.49    # alpha_f of the LAD-C6 filter (0.5: no filter)
     filter_every_stage: bool = False   # R29 alternative: filter after every RK stage
+    time_scheme: str = 'rk3'      # 'rk3' (SSP-RK3) or 'rk4' (classic RK4, the LAD scheme only; R38)
 
 
 def primitives(Q, gamma):
@@ -277,6 +281,47 @@ def rk3_step(Q, t, t_end, grid, gas, opts, scheme, M=None):
     return U, t + dt, dt, bad
 
 
+RK4_NODES = (0.5, 0.5, 1.0)                          # stage s + 1 input: U^n + c_s dt k_s
+RK4_WEIGHTS = (1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0)   # U^{n+1} = U^n + dt sum_s b_s k_s
+
+
+def rk4_stages(Q, dt, grid, gas, opts, scheme, M=None):
+    """The four stages of the classic RK4 (R38) with step dt; the filter follows the fourth
+    stage (after every stage with ``opts.filter_every_stage``).  Returns (U^{n+1},
+    non-physical count over the stage results)."""
+    inner = (slice(None),) + grid.interior()
+    acc = np.zeros_like(Q[inner])
+    U = Q
+    bad = 0
+    for s in range(4):
+        k = rhs(U, grid, gas, opts, scheme, M)
+        acc = acc + (RK4_WEIGHTS[s] * dt) * k[inner]
+        U = Q.copy()
+        U[inner] = Q[inner] + (RK4_NODES[s] * dt * k[inner] if s < 3 else acc)
+        if s == 3 or opts.filter_every_stage:
+            U = stage_filter(U, None, grid, gas, opts, scheme)
+        bad += nonphysical_count(U, grid, gas.gamma)
+    return U, bad
+
+
+def rk4_step(Q, t, t_end, grid, gas, opts, scheme, M=None):
+    """One classic RK4 step (R38: the LAD scheme's alternative integrator, Sec. 2.1) with the
+    time step of R8; returns (Q_new, t_new, dt, nonphysical_count)."""
+    if scheme != 'lad':
+        raise ValueError('RK4 marches the LAD scheme only (R38)')
+    if M is None:
+        M = gr.node_metrics(grid)
+    dt = min(cfl_dt(Q, grid, gas, opts.cfl, M), t_end - t)
+    U, bad = rk4_stages(Q, dt, grid, gas, opts, scheme, M)
+    return U, t + dt, dt, bad
+
+
+def time_step(Q, t, t_end, grid, gas, opts, scheme, M=None):
+    """One step of the integrator ``opts.time_scheme`` names."""
+    f = rk4_step if opts.time_scheme == 'rk4' else rk3_step
+    return f(Q, t, t_end, grid, gas, opts, scheme, M)
+
+
 def run(Q, t_end, grid, gas, opts, scheme, max_steps=10 ** 9):
     """March to t_end; returns (Q, steps, nonphysical_total)."""
     M = gr.node_metrics(grid)
@@ -284,7 +329,7 @@ def run(Q, t_end, grid, gas, opts, scheme, max_steps=10 ** 9):
     steps = 0
     bad = 0
     while t < t_end and steps < max_steps:
-        Q, t, _, b = rk3_step(Q, t, t_end, grid, gas, opts, scheme, M)
+        Q, t, _, b = time_step(Q, t, t_end, grid, gas, opts, scheme, M)
         bad += b
         steps += 1
     return Q, steps, bad

@@ -782,6 +782,43 @@ __global__ void __launch_bounds__(256) k_stage_ghosts(const Prob* __restrict__ p
   }
 }
 
+// Classic RK4 (the LAD scheme's alternative integrator, Sec. 2.1): with k_s the right-hand
+// side of stage s (in the derivative workspace), acc = acc + b_s dt k_s (acc = b_0 dt k_0 at
+// s = 0); s < 3: the next stage input U^n + c_s dt k_s into the stage buffer; s = 3: U^{n+1} =
+// U^n + acc in place of U^n.  Interior nodes; non-physical results are counted.
+__global__ void __launch_bounds__(256) k_rk4_combine(const Prob* __restrict__ probs, const double* Unx, int stage,
+                                                     double b, double c) {
+  const Prob& P = probs[blockIdx.y];
+  const double* Un = Unx ? Unx : P.Q;
+  double* out = stage < 3 ? P.Us : const_cast<double*>(Un);
+  const double* k = P.dQ;
+  double* acc = P.acc;
+  const size_t T = P.total;
+  const double dt = *P.dt;
+  const double bdt = b * dt, cdt = c * dt;
+  int bad = 0;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < P.total; idx += gridDim.x * blockDim.x) {
+    if (!is_interior(P, idx)) continue;
+    double v[5];
+    for (int q = 0; q < 5; ++q) {
+      const size_t o = q * T + idx;
+      const double kq = k[o];
+      const double a = (stage == 0 ? 0.0 : acc[o]) + bdt * kq;
+      if (stage < 3) {
+        acc[o] = a;
+        v[q] = Un[o] + cdt * kq;
+      } else {
+        v[q] = Un[o] + a;
+      }
+      out[o] = v[q];
+    }
+    const double rho = v[0];
+    const double p = (P.gamma - 1.0) * (v[4] - 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / rho);
+    bad += !(rho > 0.0 && p > 0.0 && isfinite(rho) && isfinite(p));
+  }
+  add_bad(P, bad);
+}
+
 // The ghost layers of the FIXED faces along d (all positions of the other directions):
 // the only ghosts a stage inside rk3_step must carry over from U^n.
 // (rr.out null: the stage's own result buffer.)
@@ -849,6 +886,12 @@ static inline dim3 g1(long long work, int nprob, long long cap = 1LL << 30) {
   if (b < 1) b = 1;
   return dim3((unsigned)b, nprob);
 }
+
+void launch_rk4_combine(const Launch& L, double* Un, int stage, double b, double c) {
+  LG_TIMED(L, KC_COMBINE, hipLaunchKernelGGL(k_rk4_combine, g1(L.max_total, L.nprob, 1 << 16), dim3(256), 0, L.stream,
+                                             L.probs, Un, stage, b, c));
+}
+
 
 template <typename R>
 void launch_lad(const Launch& L, int skip_if_any, int cg) {

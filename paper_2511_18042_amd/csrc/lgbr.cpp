@@ -55,6 +55,7 @@ struct Cfg {
   int filter;           // steps whose last stage ran LAD end with the implicit filter
   double falpha;
   int filter_all;       // ... or every stage that ran LAD is followed by it
+  int rk4;              // LAD steps march with the classic RK4
 };
 
 }  // namespace
@@ -201,6 +202,28 @@ int filter_mode(const Cfg& c, int scheme) {
   if (!c.filter || scheme == LG_SCHEME_CGBR) return -1;
   if (scheme == LG_SCHEME_LAD) return lg::FILT_ALL;
   return c.hybrid_mode == LG_HYB_GLOBAL ? lg::FILT_GLOBAL : lg::FILT_PERCELL;
+}
+
+// Classic RK4 (LAD scheme; Sec. 2.1): each stage's right-hand side into the derivative
+// workspace, then the combination (running sum of b_s dt k_s; next stage input U^n + c_s dt
+// k_s), the filter after the fourth stage (Alg. 1).
+const double RK4_B[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+const double RK4_C[3] = {0.5, 0.5, 1.0};
+
+template <typename R>
+void enqueue_rk4(const Launch& L, const Cfg& c, int scheme, double* Qx, double* tx, double t_end) {
+  lg::launch_dt(L, Qx, tx, t_end, 1);
+  const int fmode = filter_mode(c, scheme);
+  for (int s = 0; s < 4; ++s) {
+    const StateRef ref{s == 0 ? Qx : nullptr, nullptr, s == 0 ? 0 : 1};
+    enqueue_rhs<R>(L, c, scheme, ref, nullptr);
+    lg::launch_rk4_combine(L, Qx, s, RK4_B[s], s < 3 ? RK4_C[s] : 0.0);
+    if (s < 3) lg::launch_stage_ghosts(L, RKRef{Qx, nullptr, nullptr}, 0, -1);   // FIXED ghosts of U^n
+    if (fmode >= 0 && (s == 3 || c.filter_all)) {
+      const StateRef out{s == 3 ? Qx : nullptr, nullptr, s == 3 ? 0 : 1};   // the stage result
+      for (int d = 0; d < c.ndim; ++d) lg::launch_filter(L, out, d, fmode);
+    }
+  }
 }
 
 template <typename R>
@@ -612,6 +635,7 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
   if (opts->dilate < 0 || opts->dilate > 4 || opts->seg < 0) return LG_EINVAL;
   if (!(opts->cfl > 0.0)) return LG_EINVAL;
   if (opts->lad_scheme != LG_LAD_E4 && opts->lad_scheme != LG_LAD_C6) return LG_EINVAL;
+  if (opts->time_scheme != LG_RK3 && opts->time_scheme != LG_RK4) return LG_EINVAL;
   if (!(opts->filter_alpha >= 0.0 && opts->filter_alpha <= 0.5)) return LG_EINVAL;
 
   lg_ctx* c = new (std::nothrow) lg_ctx();
@@ -663,7 +687,7 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
   filter_weights(P.falpha, P.fcoef);
   P.fsteps = filt ? filter_pcr_steps(P.falpha) : 0;
   c->cfg = Cfg{G.ndim, opts->precision, opts->grad, opts->hybrid_mode, gas->viscous, opts->dilate, c6, filt,
-               P.falpha, opts->filter_every_stage ? 1 : 0};
+               P.falpha, opts->filter_every_stage ? 1 : 0, opts->time_scheme == LG_RK4 ? 1 : 0};
 
   const size_t T = (size_t)total;
   const size_t rs = opts->precision == LG_MIXED ? sizeof(float) : sizeof(double);
@@ -693,6 +717,7 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
     for (int d = 0; d < G.ndim; ++d) P.FV[d] = A(5 * T * rs);
   P.Us = static_cast<double*>(A(5 * T * sizeof(double)));
   P.dQ = static_cast<double*>(A(5 * T * sizeof(double)));
+  if (opts->time_scheme == LG_RK4) P.acc = static_cast<double*>(A(5 * T * sizeof(double)));
   if (opts->hybrid_mode == LG_HYB_PERCELL) {   // the compacted C-GBR interface queue and fluxes
     P.gq = static_cast<int*>(A(3 * T * sizeof(int)));
     for (int d = 0; d < G.ndim; ++d) P.FG[d] = A(5 * T * rs);
@@ -1035,9 +1060,11 @@ lg_status rk3_step(lg_ctx* c, int scheme, double* Q, double t_end, double* t_ino
   if (!c || !Q || !t_inout) return LG_EINVAL;
   if (scheme < LG_SCHEME_CGBR || scheme > LG_SCHEME_HYBRID) return LG_EINVAL;
   if (scheme == LG_SCHEME_HYBRID && c->cfg.lad_c6) return LG_EUNSUPPORTED;
+  if (c->cfg.rk4 && scheme != LG_SCHEME_LAD) return LG_EUNSUPPORTED;
   return dispatch(c->cfg.precision, [&](auto r) {
     using R = decltype(r);
-    enqueue_rk3<R>(c->L, c->cfg, scheme, Q, t_inout, t_end);
+    if (c->cfg.rk4) enqueue_rk4<R>(c->L, c->cfg, scheme, Q, t_inout, t_end);
+    else enqueue_rk3<R>(c->L, c->cfg, scheme, Q, t_inout, t_end);
   });
 }
 
@@ -1287,12 +1314,13 @@ lg_status lg_batch_create(lg_batch** out, lg_ctx* const* ctxs, double* const* Q,
     if (!ctxs[i]) return LG_EINVAL;
   const Cfg& c0 = ctxs[0]->cfg;
   if (scheme == LG_SCHEME_HYBRID && c0.lad_c6) return LG_EUNSUPPORTED;
+  if (c0.rk4 && scheme != LG_SCHEME_LAD) return LG_EUNSUPPORTED;
   for (int i = 0; i < n; ++i) {
     if (!ctxs[i] || !Q[i] || !t[i]) return LG_EINVAL;
     const Cfg& ci = ctxs[i]->cfg;
     if (ci.ndim != c0.ndim || ci.precision != c0.precision || ci.grad != c0.grad ||
         ci.hybrid_mode != c0.hybrid_mode || ci.viscous != c0.viscous || ci.dilate != c0.dilate ||
-        ci.lad_c6 != c0.lad_c6 || ci.filter != c0.filter || ci.filter_all != c0.filter_all)
+        ci.lad_c6 != c0.lad_c6 || ci.filter != c0.filter || ci.filter_all != c0.filter_all || ci.rk4 != c0.rk4)
       return LG_EINVAL;
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == ctxs[i]) return LG_EINVAL;  // workspaces must not be shared
@@ -1340,8 +1368,14 @@ lg_status lg_batch_create(lg_batch** out, lg_ctx* const* ctxs, double* const* Q,
   if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) st = LG_EHIP;
   if (st == LG_OK) {
     for (int s = 0; s < nsteps; ++s) {
-      if (c0.precision == LG_MIXED) enqueue_rk3<float>(Lc, c0, scheme, nullptr, nullptr, 0.0);
-      else enqueue_rk3<double>(Lc, c0, scheme, nullptr, nullptr, 0.0);
+      if (c0.rk4) {
+        if (c0.precision == LG_MIXED) enqueue_rk4<float>(Lc, c0, scheme, nullptr, nullptr, 0.0);
+        else enqueue_rk4<double>(Lc, c0, scheme, nullptr, nullptr, 0.0);
+      } else if (c0.precision == LG_MIXED) {
+        enqueue_rk3<float>(Lc, c0, scheme, nullptr, nullptr, 0.0);
+      } else {
+        enqueue_rk3<double>(Lc, c0, scheme, nullptr, nullptr, 0.0);
+      }
     }
     if (hipStreamEndCapture(cap, &b->graph) != hipSuccess) st = LG_EHIP;
   }

@@ -44,6 +44,7 @@ struct Prob {
   double* Q;         // conserved state (caller)
   double* dQ;        // time derivative (caller for *_rhs, workspace for rk3)
   double* Us;        // RK stage state (workspace)
+  double* acc;       // classic RK4: sum of b_s dt k_s over the stages so far (workspace; RK4 contexts)
   void* W;           // primitives rho,u,v,w,p          [5][total]  R
   void* G[3];        // d(primitives)/d xi_l             [5][total]  R
   double* T64;       // FP64 scratch of the line solves  [5][total]

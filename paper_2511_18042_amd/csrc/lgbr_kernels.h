@@ -218,6 +218,9 @@ template <typename R>
 void launch_sweep(const Launch& L, StateRef ref, int d, int sel, int accumulate, int skip_if_any,
                   const RKRef* rr = nullptr, int stage = 0, double a = 0.0, double b = 0.0);
 void launch_stage_ghosts(const Launch& L, const RKRef& rr, int stage, int skip_if_any);
+// classic RK4 after stage s's right-hand side (in the derivative workspace): the sum
+// acc += b dt k_s, and U^n + c dt k_s into the stage buffer (s < 3) or U^n + acc into U^n (s = 3)
+void launch_rk4_combine(const Launch& L, double* Un, int stage, double b, double c);
 // LAD-C6: compact sixth-order gradients of the primitives along d; compact interface
 // fluxes along d differenced into dQ/dt (accumulate: add to what earlier directions
 // wrote; rr != nullptr: this is the last direction and it forms the RK stage); one pass

@@ -48,7 +48,8 @@ class LgOpts(ctypes.Structure):
                 ('C_mu', ctypes.c_double), ('C_beta', ctypes.c_double), ('C_kappa', ctypes.c_double),
                 ('hybrid_mode', ctypes.c_int), ('rho_thr', ctypes.c_double), ('p_thr', ctypes.c_double),
                 ('dilate', ctypes.c_int), ('seg', ctypes.c_int), ('lad_scheme', ctypes.c_int),
-                ('filter_alpha', ctypes.c_double), ('filter_every_stage', ctypes.c_int)]
+                ('filter_alpha', ctypes.c_double), ('filter_every_stage', ctypes.c_int),
+                ('time_scheme', ctypes.c_int)]
 
 
 _lib = None
@@ -156,11 +157,14 @@ def make_gas(gamma=1.4, Re=1.0, Pr=0.72, Mref=1.0, suth=110.4 / 108.0, viscous=F
 
 def make_opts(grad='E6', precision='fp64', cfl=0.2, omega_thr=0.01, mp_eps=1e-20, mp_alpha=4.0,
               C_mu=0.0, C_beta=1.75, C_kappa=0.01, hybrid_mode='percell', rho_thr=-1.0, p_thr=-1.0,
-              dilate=3, seg=0, lad='E4', filter_alpha=0.49, filter_every_stage=False):
+              dilate=3, seg=0, lad='E4', filter_alpha=0.49, filter_every_stage=False, time_scheme='rk3'):
+    if time_scheme not in ('rk3', 'rk4'):
+        raise ValueError('time_scheme: rk3 or rk4')
     return LgOpts(GRAD_C4 if grad == 'C4' else GRAD_E6, MIXED if precision == 'mixed' else FP64, cfl,
                   omega_thr, mp_eps, mp_alpha, C_mu, C_beta, C_kappa,
                   HYB_GLOBAL if hybrid_mode == 'global' else HYB_PERCELL, rho_thr, p_thr, dilate, seg,
-                  LAD_C6 if lad == 'C6' else LAD_E4, float(filter_alpha), 1 if filter_every_stage else 0)
+                  LAD_C6 if lad == 'C6' else LAD_E4, float(filter_alpha), 1 if filter_every_stage else 0,
+                  1 if time_scheme == 'rk4' else 0)
 
 
 def metrics_from_coords(grid, coords, metrics, stream=None):

@@ -54,7 +54,7 @@ def gpu_context(c, gas, opts, precision='fp64', stream=None):
                         mp_eps=opts.mp_eps, mp_alpha=opts.mp_alpha, C_mu=opts.C_mu, C_beta=opts.C_beta,
                         C_kappa=opts.C_kappa, hybrid_mode=opts.hybrid_mode, rho_thr=opts.rho_thr,
                         p_thr=opts.p_thr, dilate=opts.dilate, lad=opts.lad, filter_alpha=opts.filter_alpha,
-                        filter_every_stage=opts.filter_every_stage)
+                        filter_every_stage=opts.filter_every_stage, time_scheme=opts.time_scheme)
     return lgbr.Context(g, ga, op, metrics, coords, stream), metrics
 
 

@@ -264,3 +264,54 @@ def test_lad_c6_context_refuses_the_hybrid_and_filter_needs_alpha_below_half():
             ctx.lad_filter(Qd)
         assert e.value.code == lgbr.LG_EUNSUPPORTED
         ctx.close()
+
+
+@pytest.mark.parametrize('name,every', [(n, False) for n in ('2d_walls', '1d_fixed', '3d_curv', '2d_curv')] +
+                         [('2d_walls', True), ('3d_curv', True)])
+@pytest.mark.parametrize('lad', ['C6', 'E4'])
+def test_lad_rk4_step_parity_fp64(name, every, lad):
+    """The classic RK4 (R38): four stages, the filter after the fourth (or after every stage);
+    two steps in a row against the oracle, at 1e-12 of each variable's max norm.  (Cases on
+    which LAD alone stays physical for two steps in the oracle.)"""
+    print('rk4', name, every, lad, flush=True)
+    torch = U.torch_mod()
+    c = CASES[name]()
+    gas = _gas(name, c)
+    opts = orhs.Opts(lad=lad, filter_alpha=0.49, C_mu=0.002, filter_every_stage=every, time_scheme='rk4')
+    g = U.oracle_grid(c)
+    M = ogrid.node_metrics(g)
+    ctx, _ = U.gpu_context(c, gas, opts)
+    Qd = U.dev(c.Q)
+    td = torch.zeros(1, dtype=torch.float64, device='cuda')
+    Q, t = c.Q, 0.0
+    for step in range(2):
+        ctx.rk3_step('lad', Qd, 10.0, td)
+        Q, t, dt, bad = orhs.rk4_step(Q, t, 10.0, g, gas, opts, 'lad', M)
+        torch.cuda.synchronize()
+        assert bad == 0
+        assert abs(td.item() - t) <= 1e-13 * t
+        U.compare(Qd.cpu().numpy(), Q, g, U.STAGE_RTOL, label='lad rk4 %s %s step %d' % (name, lad, step))
+    assert ctx.poll_status() == 0
+    for scheme in ('cgbr', 'hybrid'):   # RK4 marches the LAD scheme only
+        with pytest.raises(lgbr.LgError):
+            ctx.rk3_step(scheme, Qd, 10.0, td)
+    ctx.close()
+
+
+def test_lad_c6_rk4_batch_graph_matches_single_steps():
+    """Graph-captured batches of RK4 steps equal the same steps one call at a time, bitwise."""
+    torch = U.torch_mod()
+    c = case_2d_walls()
+    gas = _gas('2d_walls', c)
+    opts = orhs.Opts(lad='C6', filter_alpha=0.49, time_scheme='rk4')
+    ctx, _ = U.gpu_context(c, gas, opts)
+    Q1, t1 = U.dev(c.Q), torch.zeros(1, dtype=torch.float64, device='cuda')
+    for _ in range(3):
+        ctx.rk3_step('lad', Q1, 10.0, t1)
+    Q2, t2 = U.dev(c.Q), torch.zeros(1, dtype=torch.float64, device='cuda')
+    b = lgbr.Batch([ctx], [Q2], [t2], [10.0], 3, 'lad')
+    b.run()
+    torch.cuda.synchronize()
+    b.close()
+    assert torch.equal(Q1, Q2) and torch.equal(t1, t2)
+    ctx.close()

@@ -6,8 +6,9 @@ Checked against the paper: C-GBR (MEG6 and MIG4) reaches t_end on Sod, Lax, Shu-
 C3; LAD-C6 reaches t_end on Lax and Shu-Osher and diverges on Le Blanc and C3, as the
 paper's LAD-C6 does.  Sod with LAD-C6 is the exception discussed with the readings: with
 the filter after the third stage only (Alg. 1) it diverges; filtering after every stage
-(alpha_f 0.40) it converges.  The 1D runs also report L1 errors against the exact
-solution.
+(alpha_f 0.40) it converges, and so does LAD-C6 marched with the classic RK4 and filtered
+after the fourth stage (R38), which keeps the paper's verdicts on Lax and Shu-Osher as well.
+The 1D runs also report L1 errors against the exact solution.
 """
 import json
 
@@ -18,7 +19,7 @@ import validation_runs as V
 pytestmark = pytest.mark.gpu
 
 SUBSET = ['sod', 'lax', 'le_blanc', 'shu_osher', 'riemann_c3']
-SCHEMES = ['lad_c6', 'lad_c6_every_stage_0.40', 'cgbr_meg6', 'cgbr_mig4']
+SCHEMES = ['lad_c6', 'lad_c6_rk4', 'lad_c6_every_stage_0.40', 'cgbr_meg6', 'cgbr_mig4']
 
 
 def test_stability_table_subset():
@@ -35,5 +36,7 @@ def test_stability_table_subset():
     for case in ('le_blanc', 'riemann_c3'):
         assert rows[case]['lad_c6']['status'] == 'diverged', (case, rows[case]['lad_c6'])
     assert ok('sod', 'lad_c6_every_stage_0.40'), rows['sod']
+    for case in ('sod', 'lax', 'shu_osher'):
+        assert ok(case, 'lad_c6_rk4'), (case, rows[case]['lad_c6_rk4'])
     for case in ('sod', 'lax'):
         assert rows[case]['cgbr_meg6']['L1_rho_exact'] < 0.02

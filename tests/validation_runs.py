@@ -47,9 +47,11 @@ def _extrapolated(c):
     return c
 
 
-# (label, scheme, MEG6 / MIG4 gradients, LAD central scheme[, filter alpha_f, filter every stage])
+# (label, scheme, MEG6 / MIG4 gradients, LAD central scheme[, filter alpha_f, filter every stage,
+# time integrator])
 SCHEMES = [
     ('lad_c6', 'lad', 'E6', 'C6'),
+    ('lad_c6_rk4', 'lad', 'E6', 'C6', 0.49, False, 'rk4'),
     ('lad_c6_every_stage_0.40', 'lad', 'E6', 'C6', 0.40, True),
     ('cgbr_meg6', 'cgbr', 'E6', 'E4'),
     ('cgbr_mig4', 'cgbr', 'C4', 'E4'),
@@ -69,7 +71,7 @@ def exact_l1(c, Q):
     return float(np.abs(rho - ex[0]).mean())
 
 
-def run(c, scheme, grad, lad, alpha=0.49, every=False, precision='fp64', wall=120.0, chunk=200):
+def run(c, scheme, grad, lad, alpha=0.49, every=False, time_scheme='rk3', precision='fp64', wall=120.0, chunk=200):
     """Advance case c to t_end (or until the first non-physical stage, or `wall` seconds)."""
     import torch
     g = lgbr.make_grid(c.ndim, c.n, c.bc, c.h)
@@ -77,7 +79,7 @@ def run(c, scheme, grad, lad, alpha=0.49, every=False, precision='fp64', wall=12
     e = c.extra or {}
     opts = lgbr.make_opts(grad=grad, precision=precision, cfl=0.2, hybrid_mode='global', lad=lad,
                           rho_thr=e.get('rho_thr', -1.0), p_thr=e.get('p_thr', -1.0), filter_alpha=alpha,
-                          filter_every_stage=every)
+                          filter_every_stage=every, time_scheme=time_scheme)
     ctx = lgbr.Context(g, gas, opts)
     Q = torch.from_numpy(np.ascontiguousarray(c.Q)).cuda()
     t = torch.zeros(1, dtype=torch.float64, device='cuda')
