@@ -639,7 +639,7 @@ def _oracle_tp_steps(args):
     c = cases.triple_point(nx, ny)
     g = ogrid.Grid(c.ndim, c.n, c.bc, c.h, c.coords)
     M = ogrid.node_metrics(g)
-    opts = orhs.Opts(rho_thr=c.extra['rho_thr'], hybrid_mode='global')
+    opts = orhs.Opts(rho_thr=c.extra['rho_thr'], p_thr=c.extra['p_thr'], hybrid_mode='global')
     Q, t = c.Q, 0.0
     t0 = time.perf_counter()
     for _ in range(n):
@@ -725,9 +725,10 @@ def triple_point(args, variants, cpu):
 
     def context(precision, grad='E6', mode='global', lad='E4'):
         return lgbr.Context(grid, gas, lgbr.make_opts(precision=precision, cfl=0.2, grad=grad, hybrid_mode=mode,
-                                                      rho_thr=c.extra['rho_thr'], lad=lad))
+                                                      rho_thr=c.extra['rho_thr'], p_thr=c.extra['p_thr'], lad=lad))
 
-    desc = 'triple point 1792x768, hybrid LAD-E4/MEG6 (global switch, LAD phases filtered), rho_thr 0.0625, CFL 0.2'
+    desc = ('triple point 1792x768, hybrid LAD-E4/MEG6 (global switch, LAD phases filtered), rho_thr 0.0625, '
+            'p_thr 0.025, CFL 0.2')
     res = {'workload': desc, 'cells': cells}
     head = context('mixed')
     log('triple_point: %d warm-up + %d timed steps' % (args.warmup, args.steps))
@@ -758,21 +759,29 @@ def triple_point(args, variants, cpu):
                                    'nonphysical_nodes': bad64, 'stages': list(sw64), 'fp32_speedup': round(ms64 / ms, 3)}
         res['fp32_vs_fp64_after_window'] = {'steps': args.warmup + 6 + args.steps, 'error': precision_error(Q32, Q64)}
         # the whole run to t = 5 with the paper's global switch (FP64): its LAD share (Sec. 5
-        # reports 13.6 %) and whether it stays physical
-        log('triple_point: FP64 hybrid run to t = 5')
-        tt = torch.zeros(1, dtype=torch.float64, device='cuda')
-        Qr = Q0.clone()
-        b = lgbr.Batch([h64], [Qr], [tt], [5.0], 500, 'hybrid')
-        h64.switch_stats(reset=True)
-        t0 = time.perf_counter()
-        while tt.item() < 5.0 and time.perf_counter() - t0 < 60:
-            b.run()
-            torch.cuda.synchronize()
-        b.close()
-        swr = h64.switch_stats(reset=True)
-        res['run_to_t5_fp64'] = {'t': round(float(tt.item()), 6), 'nonphysical_nodes': h64.poll_status(),
-                                 'stages': swr[0], 'lad_share': round(1 - swr[1] / max(swr[0], 1), 4),
-                                 'paper_lad_share': 0.136, 'seconds': round(time.perf_counter() - t0, 2)}
+        # reports 13.6 %) and whether it stays physical, with the configured reflective walls
+        # and with the paper's extrapolated walls
+        def run_to_t5(ctx):
+            tt = torch.zeros(1, dtype=torch.float64, device='cuda')
+            Qr = Q0.clone()
+            b = lgbr.Batch([ctx], [Qr], [tt], [5.0], 500, 'hybrid')
+            ctx.switch_stats(reset=True)
+            t0 = time.perf_counter()
+            while tt.item() < 5.0 and time.perf_counter() - t0 < 60:
+                b.run()
+                torch.cuda.synchronize()
+            b.close()
+            swr = ctx.switch_stats(reset=True)
+            return {'t': round(float(tt.item()), 6), 'nonphysical_nodes': ctx.poll_status(), 'stages': swr[0],
+                    'lad_share': round(1 - swr[1] / max(swr[0], 1), 4), 'paper_lad_share': 0.136,
+                    'seconds': round(time.perf_counter() - t0, 2)}
+        log('triple_point: FP64 hybrid runs to t = 5')
+        res['run_to_t5_fp64'] = run_to_t5(h64)
+        gx = lgbr.make_grid(2, c.n, [(cases.TRANSMISSIVE, cases.TRANSMISSIVE)] * 2, c.h)
+        hx = lgbr.Context(gx, gas, lgbr.make_opts(precision='fp64', cfl=0.2, grad='E6', hybrid_mode='global',
+                                                  rho_thr=c.extra['rho_thr'], p_thr=c.extra['p_thr']))
+        res['run_to_t5_fp64_extrapolated_walls'] = run_to_t5(hx)
+        hx.close()
         Q3 = Q0.clone()
         t3 = torch.zeros(1, dtype=torch.float64, device='cuda')
         b = lgbr.Batch([h64], [Q3], [t3], [3.0], 500, 'hybrid')
@@ -781,7 +790,7 @@ def triple_point(args, variants, cpu):
             torch.cuda.synchronize()
         b.close()
         h64.close()
-        del Q64, Qr
+        del Q64
         w3 = {'t': round(float(t3.item()), 6), 'advanced_with': 'hybrid_fp64'}
         for vname, prec, scheme, grad, mode, *vv in (
                 ('hybrid_mixed', 'mixed', 'hybrid', 'E6', 'global'),

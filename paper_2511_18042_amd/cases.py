@@ -148,7 +148,7 @@ def triple_point(nx=1792, ny=768):
     p = np.where(x < 1.0, 1.0, 0.1)
     z = np.zeros_like(x)
     c.Q = conserved(rho, z, z, z, p, c.gamma)
-    c.extra = dict(rho_thr=0.5 * 0.125, p_thr=-1.0)
+    c.extra = dict(rho_thr=0.5 * 0.125, p_thr=0.25 * 0.1)
     return c
 
 

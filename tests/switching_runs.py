@@ -34,7 +34,7 @@ def _triple_point():
     c = cases.triple_point(1792, 768)
     gas = lgbr.make_gas(gamma=c.gamma)
     grid = lgbr.make_grid(2, c.n, c.bc, c.h)
-    opts = dict(grad='E6', precision='fp64', rho_thr=c.extra['rho_thr'], p_thr=-1.0)
+    opts = dict(grad='E6', precision='fp64', rho_thr=c.extra['rho_thr'], p_thr=c.extra['p_thr'])
     return c, gas, grid, opts, None, None, None
 
 
