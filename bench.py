@@ -1015,8 +1015,8 @@ def profile_summary(a):
         per = {}
         for kind, path in (('fetch', a.fetch), ('write', a.write)):
             disp = _dispatches(path, counter=True)
-            for name, dur, val in disp:
-                if name.startswith('__amd_rocclr_copyBuffer') and val > 1e5:
+            for name, dur, val in disp:   # the probe copy is the run's first large copy
+                if name.startswith('__amd_rocclr_copyBuffer') and val > 1e5 and kind not in cal:
                     cal[kind] = val
             for name, (run, n) in _executed(disp).items():
                 cls = kernel_class(name)

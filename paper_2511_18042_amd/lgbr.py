@@ -258,7 +258,7 @@ class Context:
         ecls = (ctypes.c_int * cap)()
         got = ctypes.c_int(0)
         _check(self._lib.lg_prof_stop_launches(self.handle, ms, cnt, each, ecls, int(cap), ctypes.byref(got)),
-               'lg_prof_stop_launches', 'lg_set_tile_shape', 'lg_get_tile_shape')
+               'lg_prof_stop_launches')
         return ({KERNEL_CLASSES[k]: (ms[k], cnt[k]) for k in range(n) if cnt[k]},
                 [(KERNEL_CLASSES[ecls[i]], float(each[i])) for i in range(got.value)])
 

@@ -415,3 +415,24 @@ def test_ramp_large_crop_rhs_parity(scheme, grad):
                                                                                  1e-300)) for q in range(5)]
             print('RHS-REPORT ramp 256x192x64 %s mixed max rel err per variable %s' % (scheme, rel), flush=True)
             assert max(rel) <= 1e-4
+
+
+def test_launch_timing_per_class_and_per_launch():
+    """lg_prof_stop_launches: the per-launch durations add up to the per-class sums, every
+    class of an LAD-E4 RK3 step appears, and timing stopped twice is refused."""
+    torch = U.torch_mod()
+    c = case_2d_walls()
+    gas, opts = orhs.Gas(), _opts('E6', 'global')
+    ctx, _ = U.gpu_context(c, gas, opts)
+    Qd = U.dev(c.Q)
+    td = torch.zeros(1, dtype=torch.float64, device='cuda')
+    ctx.prof_start(-1, 1000)
+    ctx.rk3_step('lad', Qd, 10.0, td)
+    per, each = ctx.prof_stop_launches()
+    assert {'prim', 'lad_raw', 'lad_flux', 'lad_sweep', 'filter', 'dt'} <= set(per)
+    for k, (ms, n) in per.items():
+        d = [x for kk, x in each if kk == k]
+        assert len(d) == n and abs(sum(d) - ms) <= 1e-3 * max(ms, 1e-6) + 1e-6
+    with pytest.raises(lgbr.LgError):
+        ctx.prof_stop_launches()
+    ctx.close()
