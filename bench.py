@@ -294,6 +294,8 @@ def profiled_traffic(path, kclass):
     if got is None:
         return None, why
     kt, tr = got
+    if kclass in ('sweep_y', 'sweep_z') and kclass not in tr:
+        kclass = 'sweep_yz'   # one kernel serves both directions
     if kclass not in tr:
         return None, 'no counters for this kernel class'
     return {'bytes': int(float(tr[kclass]['bytes'])),
@@ -307,8 +309,11 @@ def profiled_step(path, launches_per_step):
     if got is None:
         return None, why
     _, tr = got
-    missing = [k for k in launches_per_step if k not in tr and launches_per_step[k] > 0]
-    total = sum(float(tr[k]['bytes']) * n for k, n in launches_per_step.items() if k in tr)
+
+    def key(k):   # the profile names the strided sweeps of eta and zeta (one kernel) together
+        return 'sweep_yz' if k in ('sweep_y', 'sweep_z') and k not in tr else k
+    missing = [k for k in launches_per_step if key(k) not in tr and launches_per_step[k] > 0]
+    total = sum(float(tr[key(k)]['bytes']) * n for k, n in launches_per_step.items() if key(k) in tr)
     return {'bytes_per_step': int(total), 'classes_without_counters': missing}, ''
 
 
