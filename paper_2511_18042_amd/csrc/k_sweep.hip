@@ -169,20 +169,45 @@ __host__ __device__ __forceinline__ void hllc(const R WL[5], const R WR[5], cons
   }
 }
 
-// C-GBR convective flux at the interface between node idx and idx + s (direction d)
+// The inputs of one C-GBR interface flux between nodes i and i + 1 along d: primitives at
+// offsets -2 .. 3, their d-gradients, Omega and the node metrics of direction d at -1 .. 2,
+// loaded together before the arithmetic.  (A strided sweep that slid this window along its
+// line, loading one node per interface, ran no faster on the 1024 x 384 x 128 ramp: its
+// extra registers halved the waves per SIMD.)
 template <typename R>
-__host__ __device__ __forceinline__ void gbr_flux(const Prob& P, int d, int idx, R F[5]) {
-  const size_t T = P.total;
-  const int s = P.s[d];
+struct GbrWin {
+  R w[6][5], g[4][5], om[4], m[4][3];
+};
+
+template <typename R>
+__host__ __device__ __forceinline__ void gbr_load_w(const Prob& P, int id, R out[5]) {
   const R* W = static_cast<const R*>(P.W);
+  for (int q = 0; q < 5; ++q) out[q] = W[q * P.total + id];
+}
+
+template <typename R>
+__host__ __device__ __forceinline__ void gbr_load_gom(const Prob& P, int d, int id, R g[5], R& om, R m[3]) {
   const R* G = static_cast<const R*>(P.G[d]);
-  const R* Om = static_cast<const R*>(P.Om);
+  for (int q = 0; q < 5; ++q) g[q] = G[q * P.total + id];
+  om = P.viscous ? static_cast<const R*>(P.Om)[id] : R(0);
+  for (int c = 0; c < 3; ++c) m[c] = met<R>(P, 3 * d + c, id);
+}
+
+// the whole window of the interface between idx and idx + s
+template <typename R>
+__host__ __device__ __forceinline__ void gbr_fill(const Prob& P, int d, int idx, GbrWin<R>& wn) {
+  const int s = P.s[d];
+  for (int o = -2; o <= 3; ++o) gbr_load_w(P, idx + o * s, wn.w[o + 2]);
+  for (int o = -1; o <= 2; ++o) gbr_load_gom(P, d, idx + o * s, wn.g[o + 1], wn.om[o + 1], wn.m[o + 1]);
+}
+
+// C-GBR convective flux at the interface between the window's nodes 0 and 1
+template <typename R>
+__host__ __device__ __forceinline__ void gbr_flux_win(const Prob& P, const GbrWin<R>& wn, R F[5]) {
   // interface metrics (I4 of node metrics)
   R xt[3];
   for (int c = 0; c < 3; ++c) {
-    int comp = 3 * d + c;
-    R a0 = met<R>(P, comp, idx - s), a1 = met<R>(P, comp, idx), a2 = met<R>(P, comp, idx + s),
-      a3 = met<R>(P, comp, idx + 2 * s);
+    R a0 = wn.m[0][c], a1 = wn.m[1][c], a2 = wn.m[2][c], a3 = wn.m[3][c];
     xt[c] = (R(7) * (a1 + a2) - (a0 + a3)) / R(12);
   }
   Frame<R> fr;
@@ -205,20 +230,20 @@ __host__ __device__ __forceinline__ void gbr_flux(const Prob& P, int d, int idx,
   {
     // frozen state: Roe average of the two nodes (density sqrt(r0 r1); velocity and total
     // enthalpy weighted by sqrt(rho); sound speed from them)
-    const R r0 = W[idx], r1 = W[idx + s];
+    const R r0 = wn.w[2][0], r1 = wn.w[3][0];
     const R sl = sqrt(r0), sr = sqrt(r1);
     const R wl = sl / (sl + sr), wr = sr / (sl + sr);
     R q0 = R(0), q1 = R(0), ub2 = R(0);
     for (int m = 1; m <= 3; ++m) {
-      const R a = W[m * T + idx], b = W[m * T + idx + s];
+      const R a = wn.w[2][m], b = wn.w[3][m];
       q0 += a * a;
       q1 += b * b;
       const R ub = wl * a + wr * b;
       ub2 += ub * ub;
     }
     const R gg = gamma / (gamma - R(1));
-    const R H0 = gg * W[4 * T + idx] / r0 + R(0.5) * q0;
-    const R H1 = gg * W[4 * T + idx + s] / r1 + R(0.5) * q1;
+    const R H0 = gg * wn.w[2][4] / r0 + R(0.5) * q0;
+    const R H1 = gg * wn.w[3][4] / r1 + R(0.5) * q1;
     const R Hb = wl * H0 + wr * H1;
     fr.rb = sl * sr;
     fr.cb = sqrt((gamma - R(1)) * (Hb - R(0.5) * ub2));
@@ -226,21 +251,15 @@ __host__ __device__ __forceinline__ void gbr_flux(const Prob& P, int d, int idx,
   fr.k = fr.rb / (R(2) * fr.cb);
 
   R C[6][5], D[4][5];
-  for (int o = -2; o <= 3; ++o) {
-    int id = idx + o * s;
-    to_char(fr, W[id], W[T + id], W[2 * T + id], W[3 * T + id], W[4 * T + id], C[o + 2]);
-  }
-  for (int o = -1; o <= 2; ++o) {
-    int id = idx + o * s;
-    to_char(fr, G[id], G[T + id], G[2 * T + id], G[3 * T + id], G[4 * T + id], D[o + 1]);
-  }
+  for (int o = 0; o < 6; ++o) to_char(fr, wn.w[o][0], wn.w[o][1], wn.w[o][2], wn.w[o][3], wn.w[o][4], C[o]);
+  for (int o = 0; o < 4; ++o) to_char(fr, wn.g[o][0], wn.g[o][1], wn.g[o][2], wn.g[o][3], wn.g[o][4], D[o]);
   const R thr = (R)P.omega_thr, eps = (R)P.mp_eps, alpha = (R)P.mp_alpha;
   // inviscid flow: the MP criterion alone governs every field and the Omega sensor is not
   // evaluated (Sec. 2.3); viscous flow: the wave-appropriate rule
   const bool mp_only = !P.viscous;
   bool shockL = false, shockR = false;
   if (!mp_only) {
-    R om_m1 = Om[idx - s], om_0 = Om[idx], om_1 = Om[idx + s], om_2 = Om[idx + 2 * s];
+    R om_m1 = wn.om[0], om_0 = wn.om[1], om_1 = wn.om[2], om_2 = wn.om[3];
     shockL = fmax(fmax(om_m1, om_0), om_1) > thr;
     shockR = fmax(fmax(om_0, om_1), om_2) > thr;
   }
@@ -279,10 +298,18 @@ __host__ __device__ __forceinline__ void gbr_flux(const Prob& P, int d, int idx,
   // a side whose reconstructed density or pressure is not positive takes its upwind node's
   // own primitive state (first order on that side)
   if (!(WL[0] > R(0) && WL[4] > R(0)))
-    for (int q = 0; q < 5; ++q) WL[q] = W[q * T + idx];
+    for (int q = 0; q < 5; ++q) WL[q] = wn.w[2][q];
   if (!(WR[0] > R(0) && WR[4] > R(0)))
-    for (int q = 0; q < 5; ++q) WR[q] = W[q * T + idx + s];
+    for (int q = 0; q < 5; ++q) WR[q] = wn.w[3][q];
   hllc(WL, WR, xt, gamma, F);
+}
+
+// C-GBR convective flux at the interface between node idx and idx + s (direction d)
+template <typename R>
+__host__ __device__ __forceinline__ void gbr_flux(const Prob& P, int d, int idx, R F[5]) {
+  GbrWin<R> wn;
+  gbr_fill(P, d, idx, wn);
+  gbr_flux_win(P, wn, F);
 }
 
 template <typename R>
