@@ -279,13 +279,17 @@ lg_status lg_get_tile_shape(const lg_ctx* ctx, int* zm_width, int* line_batch);
  * calls and to batches created afterwards. */
 lg_status lg_set_line_tiles(lg_ctx* ctx, int mask);
 int lg_get_line_tiles(const lg_ctx* ctx);
-/* Memory-access forms of the LAD sweep and the primitive conversion (no effect on results):
- * by default the FP32 kernels read fields by 32-bit offsets from a scalar base and convert
- * primitives two nodes per lane, and fall back by themselves to 64-bit addressing and one
- * node per lane for fields of 2^32 bytes or more, odd node counts or unaligned state.
- * generic = 1 forces those fallbacks (so that tests can compare the two forms), 0 restores
- * the default.  Applies to later calls on the context, not to batches.  LG_EINVAL for a
- * null context or generic outside {0, 1}. */
+/* Code forms of the LAD kernels and the primitive conversion.  By default the FP32 kernels
+ * read fields by 32-bit offsets from a scalar base and convert primitives two nodes per
+ * lane, and the LAD coefficient kernel (FP32) and node-flux kernel (FP64) take a form
+ * compiled for 3D curvilinear grids whose metrics are planar along zeta; the kernels fall
+ * back by themselves to 64-bit addressing, one node per lane and the general geometry for
+ * fields of 2^32 bytes or more, odd node counts, unaligned state or other grids.  generic
+ * is a bit mask that forces fallbacks so that tests can compare the forms: bit 0 the
+ * addressing and node pairs (results bitwise equal), bit 1 the general geometry (FP64
+ * bitwise equal; FP32 equal to rounding, the compiler fusing and ordering the arithmetic of
+ * the two forms differently); 0 restores the defaults.  Applies to later calls on the
+ * context, not to batches.  LG_EINVAL for a null context or generic outside [0, 3]. */
 lg_status lg_set_generic_access(lg_ctx* ctx, int generic);
 
 /* Synchronises the context's stream and reads its non-physical node count since the

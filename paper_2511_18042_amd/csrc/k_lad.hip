@@ -149,14 +149,15 @@ struct ZQ5 {
 
 // computational E4 derivatives of the 5 primitives at idx; z from the queue (3D)
 template <typename R>
-__device__ __forceinline__ void e4_grads_zm(const Prob& P, const R* W, int idx, const ZQ5<R, 5>& qz, R gl[3][5]) {
+__device__ __forceinline__ void e4_grads_zm(const Prob& P, int nd, const R* W, int idx, const ZQ5<R, 5>& qz,
+                                            R gl[3][5]) {
   const size_t T = P.total;
   for (int l = 0; l < 3; ++l)
     for (int q = 0; q < 5; ++q) gl[l][q] = R(0);
   for (int q = 0; q < 5; ++q) {
     gl[0][q] = e4_at(W + q * T, idx, P.s[0]);
-    if (P.ndim > 1) gl[1][q] = e4_at(W + q * T, idx, P.s[1]);
-    if (P.ndim > 2) gl[2][q] = e4v(qz.v[0][q], qz.v[1][q], qz.v[3][q], qz.v[4][q]);
+    if (nd > 1) gl[1][q] = e4_at(W + q * T, idx, P.s[1]);
+    if (nd > 2) gl[2][q] = e4v(qz.v[0][q], qz.v[1][q], qz.v[3][q], qz.v[4][q]);
   }
 }
 
@@ -207,7 +208,8 @@ k_lad_shear(const Prob* __restrict__ probs, int skip_if_any, int zc) {
   R* S = static_cast<R*>(P.S3);
   const size_t T = P.total;
   const int sz = P.s[2];
-  const bool z3 = P.ndim == 3 && !CG;
+  const int nd = P.ndim;
+  const bool z3 = nd == 3 && !CG;
   int idx = pos_to_idx(P, c.i, c.j, c.k0);
   ZQ5<R, 5> qz;
   if (z3) qz.prime(W, T, idx, sz);
@@ -219,8 +221,8 @@ k_lad_shear(const Prob* __restrict__ probs, int skip_if_any, int zc) {
     if (!mplane) load_met(P, idx, mt);
     R gl[3][5], D[5][3];
     if (CG) stored_grads(P, idx, gl);
-    else e4_grads_zm(P, W, idx, qz, gl);
-    to_physical<R, false>(P.ndim, mt, gl, D);
+    else e4_grads_zm(P, nd, W, idx, qz, gl);
+    to_physical<R, false>(nd, mt, gl, D);
     R S2 = R(0);
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) {
@@ -233,8 +235,23 @@ k_lad_shear(const Prob* __restrict__ probs, int skip_if_any, int zc) {
 }
 
 // ------------------------------------------------------------------ raw coefficients
+// 1 / (|g| + 1e-32), the factor of the regularised unit vector g / (|g| + 1e-32).  In FP32
+// the squares of components below 2^-63 underflow (1e-32 lies below the square root of the
+// normal range) and would leave an unbounded projection: FP32 vectors whose largest
+// component is non-zero and below 2^-60 are normalised in FP64, all others in FP32.
+template <typename R>
+__device__ __forceinline__ R inv_norm_reg(const R g[3]) {
+  if constexpr (sizeof(R) == 4) {
+    const float m = fmaxf(fabsf(g[0]), fmaxf(fabsf(g[1]), fabsf(g[2])));
+    if (m == 0.0f || m >= 0x1p-60f) return 1.0f / (sqrtf(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) + 1e-32f);
+  }
+  return (R)(1.0 / (sqrt((double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2]) + 1e-32));
+}
+
 // at interior nodes; e = p / ((gamma - 1) rho) from W wherever needed
-template <typename R, bool CG>
+// C3P: every problem of the launch is 3D and curvilinear with metrics planar along zeta
+// (branches on the geometry folded at compile time)
+template <typename R, bool CG, bool C3P>
 __global__ void __launch_bounds__(256) k_lad_raw(const Prob* __restrict__ probs, int skip_if_any, int zc) {
   const Prob& P = probs[blockIdx.y];
   if (lad_skip(P, skip_if_any)) return;
@@ -246,7 +263,9 @@ __global__ void __launch_bounds__(256) k_lad_raw(const Prob* __restrict__ probs,
   R* C = static_cast<R*>(P.CA);
   const size_t T = P.total;
   const int sz = P.s[2];
-  const bool z3 = P.ndim == 3;
+  const int nd = C3P ? 3 : P.ndim;
+  const bool curv = C3P || P.curvilinear;
+  const bool z3 = nd == 3;
   const R gm1 = R(P.gamma - 1.0), igm1 = R(1.0 / (P.gamma - 1.0));
   int idx = pos_to_idx(P, c.i, c.j, c.k0);
   ZQ5<R, 5> qz;
@@ -256,9 +275,9 @@ __global__ void __launch_bounds__(256) k_lad_raw(const Prob* __restrict__ probs,
     qs.prime(S, T, idx, sz);
   }
   R mt[10], gx[9];
-  const bool mplane = P.met_planar;
+  const bool mplane = C3P || P.met_planar;
   auto load_gx = [&](int id) {
-    for (int m = 0; m < 9; ++m) gx[m] = P.curvilinear ? GX[(size_t)m * P.met_T + met_idx(P, id)] : R(0);
+    for (int m = 0; m < 9; ++m) gx[m] = curv ? GX[(size_t)m * P.met_T + met_idx(P, id)] : R(0);
   };
   if (mplane) {   // one plane of metrics and grid factors serves the whole column
     load_met(P, idx, mt);
@@ -275,8 +294,8 @@ __global__ void __launch_bounds__(256) k_lad_raw(const Prob* __restrict__ probs,
     }
     R gl[3][5], D[5][3];
     if (CG) stored_grads(P, idx, gl);
-    else e4_grads_zm(P, W, idx, qz, gl);
-    to_physical(P.ndim, mt, gl, D);
+    else e4_grads_zm(P, nd, W, idx, qz, gl);
+    to_physical(nd, mt, gl, D);
     R rho = W[idx], p = W[4 * T + idx];
     R ri = rcp(rho);
     R theta = D[1][0] + D[2][1] + D[3][2];
@@ -287,28 +306,24 @@ __global__ void __launch_bounds__(256) k_lad_raw(const Prob* __restrict__ probs,
       de[j] = (D[4][j] * ri - p * D[0][j] * (ri * ri)) * igm1;
       gr[j] = D[0][j];
     }
-    // regularised unit vectors g / (|g| + 1e-32), formed in FP64: in FP32 the squares of
-    // tiny gradient components underflow (1e-32 is below the square root of its normal
-    // range) and would leave an unbounded projection
-    const double inr = 1.0 / (sqrt((double)gr[0] * gr[0] + (double)gr[1] * gr[1] + (double)gr[2] * gr[2]) + 1e-32);
-    const double ine = 1.0 / (sqrt((double)de[0] * de[0] + (double)de[1] * de[1] + (double)de[2] * de[2]) + 1e-32);
+    const R inr = inv_norm_reg(gr), ine = inv_norm_reg(de);
     R Tt = R(P.gamma * P.Mref * P.Mref) * p * ri;
     R cs = sqrt(R(P.gamma) * p * ri);
     R fsw = theta < R(0) ? theta * theta * rcp(theta * theta + om2 + R(1e-32)) : R(0);
     R smu = R(0), sbeta = R(0), skap = R(0);
     #pragma unroll
     for (int l = 0; l < 3; ++l) {
-      if (l >= P.ndim) break;
+      if (l >= nd) break;
       R dx[3];
-      if (P.curvilinear) {
+      if (curv) {
         for (int cc = 0; cc < 3; ++cc) dx[cc] = gx[3 * l + cc];
       } else {
         dx[0] = dx[1] = dx[2] = R(0);
         dx[l] = (R)P.h[l];
       }
       R dmu2 = dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2];
-      R dbeta = (R)(((double)dx[0] * gr[0] + (double)dx[1] * gr[1] + (double)dx[2] * gr[2]) * inr);
-      R dkap = (R)(fabs((double)dx[0] * de[0] + (double)dx[1] * de[1] + (double)dx[2] * de[2]) * ine);
+      R dbeta = (dx[0] * gr[0] + dx[1] * gr[1] + dx[2] * gr[2]) * inr;
+      R dkap = fabs(dx[0] * de[0] + dx[1] * de[1] + dx[2] * de[2]) * ine;
       R f4S, f4t, f4e;
       if (l < 2) {
         const int s = P.s[l];
@@ -479,10 +494,10 @@ struct LadNode {
 // w: primitives at the node; cf: the (ghost-imaged) coefficients mu*, beta*, kappa* there;
 // gl: computational E4 derivatives; mt: metrics
 template <typename R>
-__device__ __forceinline__ void lad_node_state(const Prob& P, const R w[5], const R cf[3], const R mt[10],
+__device__ __forceinline__ void lad_node_state(const Prob& P, int nd, const R w[5], const R cf[3], const R mt[10],
                                                const R gl[3][5], LadNode<R>& s) {
   for (int q = 0; q < 5; ++q) s.w[q] = w[q];
-  to_physical(P.ndim, mt, gl, s.D);
+  to_physical(nd, mt, gl, s.D);
   s.ri = rcp(s.w[0]);
   R muf, kapf;
   transport(P, s.ri, s.w[4], muf, kapf);
@@ -508,66 +523,76 @@ __device__ __forceinline__ void lad_node_flux(const Prob& P, const LadNode<R>& s
 
 // F^c + F^v for every active direction at positions -2 .. n+1; gradients recomputed from
 // W (CG: stored gradients), coefficients read at the image of the node
-template <typename R, bool CG>
+// C3P: every problem 3D and curvilinear with metrics planar along zeta (as in k_lad_raw)
+template <typename R, bool CG, bool O32, bool C3P>
 __global__ void __launch_bounds__(256) k_lad_nodeflux(const Prob* __restrict__ probs, int coef_buf, int skip_if_any,
                                                       int zc) {
+  using IX = sidx_t<O32>;
   const Prob& P = probs[blockIdx.y];
   if (lad_skip(P, skip_if_any)) return;
   ZCol c;
   if (!zm_column(P, -2, 2, zc, c)) return;
   const R* W = static_cast<const R*>(P.W);
   const R* C = static_cast<const R*>(coef_buf == 0 ? P.CA : P.CB);
-  const size_t T = P.total;
+  const R* MR = static_cast<const R*>(P.MR);
+  const IX T = (IX)P.total;
   const int sz = P.s[2];
-  const bool z3 = P.ndim == 3;
+  const int nd = C3P ? 3 : P.ndim;
+  const bool curv = C3P || P.curvilinear;
+  const bool z3 = nd == 3;
   const bool zq = z3 && !CG;
   const int ci = scalar_image(P, 0, c.i);
-  const int cj = P.ndim > 1 ? scalar_image(P, 1, c.j) : c.j;
+  const int cj = nd > 1 ? scalar_image(P, 1, c.j) : c.j;
   int idx = pos_to_idx(P, c.i, c.j, c.k0);
   R qz[5][5];   // planes k-2 .. k+2 of the primitives
   if (zq)
     for (int p = 1; p < 5; ++p)
-      for (int q = 0; q < 5; ++q) qz[p][q] = W[q * T + idx + (p - 3) * sz];
+      for (int q = 0; q < 5; ++q) qz[p][q] = gld<R, O32>(W, (IX)q * T + (IX)(idx + (p - 3) * sz));
   R mt[10];
-  const bool mplane = P.met_planar;
-  if (mplane) load_met(P, idx, mt);   // one plane of metrics serves the whole column
+  const bool mplane = C3P || P.met_planar;
+  auto load_mt = [&](int id) {
+    const IX mi = (IX)met_idx(P, id), mT = (IX)P.met_T;
+    for (int m = 0; m < 10; ++m) mt[m] = curv ? gld<R, O32>(MR, (IX)m * mT + mi) : (R)P.cm[m];
+  };
+  if (mplane) load_mt(idx);   // one plane of metrics serves the whole column
   for (int k = c.k0; k < c.k1; ++k, idx += sz) {
     if (zq) {
       for (int p = 0; p < 4; ++p)
         for (int q = 0; q < 5; ++q) qz[p][q] = qz[p + 1][q];
-      for (int q = 0; q < 5; ++q) qz[4][q] = W[q * T + idx + 2 * sz];
+      for (int q = 0; q < 5; ++q) qz[4][q] = gld<R, O32>(W, (IX)q * T + (IX)(idx + 2 * sz));
     }
-    if (!mplane) load_met(P, idx, mt);
+    if (!mplane) load_mt(idx);
     R gl[3][5], w[5];
     for (int l = 0; l < 3; ++l)
       for (int q = 0; q < 5; ++q) gl[l][q] = R(0);
     for (int q = 0; q < 5; ++q) {
-      const size_t o = q * T + idx;
-      w[q] = zq ? qz[2][q] : W[o];
+      const IX o = (IX)q * T + (IX)idx;
+      w[q] = zq ? qz[2][q] : gld<R, O32>(W, o);
       if (CG) {
 #pragma unroll
         for (int l = 0; l < 3; ++l)
-          if (l < P.ndim) gl[l][q] = static_cast<const R*>(P.G[l])[o];
+          if (l < nd) gl[l][q] = gld<R, O32>(static_cast<const R*>(P.G[l]), o);
       } else {
-        gl[0][q] = e4v(W[o - 2], W[o - 1], W[o + 1], W[o + 2]);
-        if (P.ndim > 1) {
-          const size_t s1 = P.s[1];
-          gl[1][q] = e4v(W[o - 2 * s1], W[o - s1], W[o + s1], W[o + 2 * s1]);
+        gl[0][q] = e4v(gld<R, O32>(W, o - 2), gld<R, O32>(W, o - 1), gld<R, O32>(W, o + 1), gld<R, O32>(W, o + 2));
+        if (nd > 1) {
+          const IX s1 = (IX)P.s[1];
+          gl[1][q] = e4v(gld<R, O32>(W, o - 2 * s1), gld<R, O32>(W, o - s1), gld<R, O32>(W, o + s1),
+                         gld<R, O32>(W, o + 2 * s1));
         }
         if (z3) gl[2][q] = e4v(qz[0][q], qz[1][q], qz[3][q], qz[4][q]);
       }
     }
-    const size_t cidx = pos_to_idx(P, ci, cj, z3 ? scalar_image(P, 2, k) : k);
-    const R cf[3] = {C[cidx], C[T + cidx], C[2 * T + cidx]};
+    const IX cidx = (IX)pos_to_idx(P, ci, cj, z3 ? scalar_image(P, 2, k) : k);
+    const R cf[3] = {gld<R, O32>(C, cidx), gld<R, O32>(C, T + cidx), gld<R, O32>(C, 2 * T + cidx)};
     LadNode<R> s;
-    lad_node_state(P, w, cf, mt, gl, s);
+    lad_node_state(P, nd, w, cf, mt, gl, s);
     #pragma unroll
     for (int l = 0; l < 3; ++l) {
-      if (l >= P.ndim) break;
+      if (l >= nd) break;
       R F[5];
       lad_node_flux(P, s, mt, l, F);
       R* out = static_cast<R*>(P.FL[l]);
-      for (int q = 0; q < 5; ++q) out[q * T + idx] = F[q];
+      for (int q = 0; q < 5; ++q) gst<R, O32>(out, (IX)q * T + (IX)idx, F[q]);
     }
   }
 }
@@ -899,13 +924,19 @@ void launch_lad(const Launch& L, int skip_if_any, int cg) {
   if (cg) {
     LG_TIMED(L, KC_LAD_NODE, hipLaunchKernelGGL((k_lad_shear<R, true>), zm_grid_col(L, -2, 2), dim3(256),
                                                 0, L.stream, L.probs, skip_if_any, zb));
-    LG_TIMED(L, KC_LAD_RAW, hipLaunchKernelGGL((k_lad_raw<R, true>), zm_grid_col(L, 0, 0), dim3(256), 0,
+    LG_TIMED(L, KC_LAD_RAW, hipLaunchKernelGGL((k_lad_raw<R, true, false>), zm_grid_col(L, 0, 0), dim3(256), 0,
                                                L.stream, L.probs, skip_if_any, zi));
   } else {
     LG_TIMED(L, KC_LAD_NODE, hipLaunchKernelGGL((k_lad_shear<R, false>), zm_grid_col(L, -2, 2), dim3(256),
                                                 0, L.stream, L.probs, skip_if_any, zb));
-    LG_TIMED(L, KC_LAD_RAW, hipLaunchKernelGGL((k_lad_raw<R, false>), zm_grid_col(L, 0, 0), dim3(256), 0,
-                                               L.stream, L.probs, skip_if_any, zi));
+    // the specialised geometry: FP32 1.50x faster on the ramp; FP64 needs 256 registers
+    // that way and runs slower
+    if (sizeof(R) == 4 && !L.geo_generic)
+      LG_TIMED(L, KC_LAD_RAW, hipLaunchKernelGGL((k_lad_raw<R, false, true>), zm_grid_col(L, 0, 0), dim3(256), 0,
+                                                 L.stream, L.probs, skip_if_any, zi));
+    else
+      LG_TIMED(L, KC_LAD_RAW, hipLaunchKernelGGL((k_lad_raw<R, false, false>), zm_grid_col(L, 0, 0), dim3(256), 0,
+                                                 L.stream, L.probs, skip_if_any, zi));
   }
   constexpr int GTY = sizeof(R) == 4 ? 16 : 8;
   LG_TIMED(L, KC_GAUSS, hipLaunchKernelGGL((k_gauss_xy<R, GTY>), zm_grid(L, 0, 0, 64, GTY), dim3(256), 0, L.stream,
@@ -922,12 +953,22 @@ template <typename R>
 void launch_lad_nodeflux(const Launch& L, int skip_if_any, int cg) {
   const dim3 grid = zm_grid_col(L, -2, 2);
   const int zb = zm_arg(L, -2, 2);
+  // FP32: 32-bit element offsets, general geometry (3 % faster on the ramp than generic
+  // addressing, the specialised geometry slower); FP64: generic addressing, the specialised
+  // geometry where it applies (6 % faster)
+  const bool o32 = sizeof(R) == 4 && !L.o64;
   if (cg)
-    LG_TIMED(L, KC_LAD_FLUX, hipLaunchKernelGGL((k_lad_nodeflux<R, true>), grid, dim3(256), 0, L.stream, L.probs,
-                                                lad_coef_buf(L), skip_if_any, zb));
+    LG_TIMED(L, KC_LAD_FLUX, hipLaunchKernelGGL((k_lad_nodeflux<R, true, false, false>), grid, dim3(256), 0,
+                                                L.stream, L.probs, lad_coef_buf(L), skip_if_any, zb));
+  else if (o32)
+    LG_TIMED(L, KC_LAD_FLUX, hipLaunchKernelGGL((k_lad_nodeflux<R, false, true, false>), grid, dim3(256), 0,
+                                                L.stream, L.probs, lad_coef_buf(L), skip_if_any, zb));
+  else if (sizeof(R) == 8 && !L.geo_generic)
+    LG_TIMED(L, KC_LAD_FLUX, hipLaunchKernelGGL((k_lad_nodeflux<R, false, false, true>), grid, dim3(256), 0,
+                                                L.stream, L.probs, lad_coef_buf(L), skip_if_any, zb));
   else
-    LG_TIMED(L, KC_LAD_FLUX, hipLaunchKernelGGL((k_lad_nodeflux<R, false>), grid, dim3(256), 0, L.stream, L.probs,
-                                                lad_coef_buf(L), skip_if_any, zb));
+    LG_TIMED(L, KC_LAD_FLUX, hipLaunchKernelGGL((k_lad_nodeflux<R, false, false, false>), grid, dim3(256), 0,
+                                                L.stream, L.probs, lad_coef_buf(L), skip_if_any, zb));
 }
 
 template <typename R>

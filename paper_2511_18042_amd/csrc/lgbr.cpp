@@ -540,6 +540,7 @@ void fill_launch(Launch& L, const Prob& P) {
   }
   // 32-bit element offsets address every field of the problem (five FP64 planes)
   if (40LL * P.total >= (1LL << 32)) L.o64 = 1;
+  if (!(P.ndim == 3 && P.curvilinear && P.met_planar)) L.geo_generic = 1;
   if (P.total % 2 || ((unsigned long long)P.Q | (unsigned long long)P.Us) % 16) L.prim_scalar = 1;
   L.max_fsteps = std::max(L.max_fsteps, P.fsteps);
   L.max_total = std::max<long long>(L.max_total, P.total);
@@ -1118,10 +1119,11 @@ lg_status lg_set_line_tiles(lg_ctx* c, int mask) {
 int lg_get_line_tiles(const lg_ctx* c) { return c ? c->L.tile_mask : -1; }
 
 lg_status lg_set_generic_access(lg_ctx* c, int generic) {
-  if (!c || (generic != 0 && generic != 1)) return LG_EINVAL;
-  c->L.o64 = c->L.prim_scalar = 0;
+  if (!c || generic < 0 || generic > 3) return LG_EINVAL;
+  c->L.o64 = c->L.prim_scalar = c->L.geo_generic = 0;
   fill_launch(c->L, c->hp);
-  if (generic) c->L.o64 = c->L.prim_scalar = 1;
+  if (generic & 1) c->L.o64 = c->L.prim_scalar = 1;
+  if (generic & 2) c->L.geo_generic = 1;
   return LG_OK;
 }
 

@@ -280,7 +280,10 @@ class Context:
         return int(self._lib.lg_get_line_tiles(self.handle))
 
     def set_generic_access(self, generic=True):
-        _check(self._lib.lg_set_generic_access(self.handle, 1 if generic else 0), 'lg_set_generic_access')
+        """generic: True (every fallback), False (the defaults) or the bit mask of
+        lg_set_generic_access (1 addressing and node pairs, 2 general geometry)."""
+        mask = (3 if generic else 0) if isinstance(generic, bool) else int(generic)
+        _check(self._lib.lg_set_generic_access(self.handle, mask), 'lg_set_generic_access')
 
     def get_tuning(self):
         a, b, z = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
