@@ -281,10 +281,11 @@ lg_status lg_set_line_tiles(lg_ctx* ctx, int mask);
 int lg_get_line_tiles(const lg_ctx* ctx);
 /* Code forms of the LAD kernels and the primitive conversion.  By default the FP32 kernels
  * read fields by 32-bit offsets from a scalar base and convert primitives two nodes per
- * lane, and the LAD coefficient kernel (FP32) and node-flux kernel (FP64) take a form
- * compiled for 3D curvilinear grids whose metrics are planar along zeta; the kernels fall
- * back by themselves to 64-bit addressing, one node per lane and the general geometry for
- * fields of 2^32 bytes or more, odd node counts, unaligned state or other grids.  generic
+ * lane, and the LAD coefficient kernel (FP32), node-flux kernel (FP64) and the C-GBR
+ * direction sweeps (viscous problems) take a form compiled for 3D curvilinear grids whose
+ * metrics are planar along zeta; the kernels fall back by themselves to 64-bit addressing,
+ * one node per lane and the general form for fields of 2^32 bytes or more, odd node
+ * counts, unaligned state, other grids or inviscid problems.  generic
  * is a bit mask that forces fallbacks so that tests can compare the forms: bit 0 the
  * addressing and node pairs (results bitwise equal), bit 1 the general geometry (FP64
  * bitwise equal; FP32 equal to rounding, the compiler fusing and ordering the arithmetic of

@@ -185,24 +185,39 @@ __host__ __device__ __forceinline__ void gbr_load_w(const Prob& P, int id, R out
   for (int q = 0; q < 5; ++q) out[q] = W[q * P.total + id];
 }
 
-template <typename R>
-__host__ __device__ __forceinline__ void gbr_load_gom(const Prob& P, int d, int id, R g[5], R& om, R m[3]) {
+// C3V: the problem is known to be 3D, curvilinear with metrics planar along zeta, and
+// viscous (branches on these folded at compile time); false: read from the descriptor.
+// id: the node; mid: its index in the metric arrays (met_idx)
+template <typename R, bool C3V = false>
+__host__ __device__ __forceinline__ void gbr_load_gom(const Prob& P, int d, int id, int mid, R g[5], R& om, R m[3]) {
   const R* G = static_cast<const R*>(P.G[d]);
   for (int q = 0; q < 5; ++q) g[q] = G[q * P.total + id];
-  om = P.viscous ? static_cast<const R*>(P.Om)[id] : R(0);
-  for (int c = 0; c < 3; ++c) m[c] = met<R>(P, 3 * d + c, id);
+  om = (C3V || P.viscous) ? static_cast<const R*>(P.Om)[id] : R(0);
+  const R* M = static_cast<const R*>(P.MR);
+  for (int c = 0; c < 3; ++c)
+    m[c] = (C3V || P.curvilinear) ? M[(size_t)(3 * d + c) * P.met_T + mid] : (R)P.cm[3 * d + c];
 }
 
-// the whole window of the interface between idx and idx + s
-template <typename R>
-__host__ __device__ __forceinline__ void gbr_fill(const Prob& P, int d, int idx, GbrWin<R>& wn) {
-  const int s = P.s[d];
+// Step of the metric index along direction d: the node step, or 0 along zeta where the
+// metrics are stored for one plane.  Every node of a window lies in its interface's row
+// (all interior and ghost positions of the other two directions), so its metric index is
+// the interface node's plus a multiple of this step, without a division.
+template <bool C3V = false>
+__host__ __device__ __forceinline__ int met_step(const Prob& P, int d) {
+  return ((C3V || P.met_planar) && d == 2) ? 0 : P.s[d];
+}
+
+// the whole window of the interface between idx and idx + s (mi = met_idx(P, idx))
+template <typename R, bool C3V = false>
+__host__ __device__ __forceinline__ void gbr_fill(const Prob& P, int d, int idx, int mi, GbrWin<R>& wn) {
+  const int s = P.s[d], ms = met_step<C3V>(P, d);
   for (int o = -2; o <= 3; ++o) gbr_load_w(P, idx + o * s, wn.w[o + 2]);
-  for (int o = -1; o <= 2; ++o) gbr_load_gom(P, d, idx + o * s, wn.g[o + 1], wn.om[o + 1], wn.m[o + 1]);
+  for (int o = -1; o <= 2; ++o)
+    gbr_load_gom<R, C3V>(P, d, idx + o * s, mi + o * ms, wn.g[o + 1], wn.om[o + 1], wn.m[o + 1]);
 }
 
 // C-GBR convective flux at the interface between the window's nodes 0 and 1
-template <typename R>
+template <typename R, bool C3V = false>
 __host__ __device__ __forceinline__ void gbr_flux_win(const Prob& P, const GbrWin<R>& wn, R F[5]) {
   // interface metrics (I4 of node metrics)
   R xt[3];
@@ -256,7 +271,7 @@ __host__ __device__ __forceinline__ void gbr_flux_win(const Prob& P, const GbrWi
   const R thr = (R)P.omega_thr, eps = (R)P.mp_eps, alpha = (R)P.mp_alpha;
   // inviscid flow: the MP criterion alone governs every field and the Omega sensor is not
   // evaluated (Sec. 2.3); viscous flow: the wave-appropriate rule
-  const bool mp_only = !P.viscous;
+  const bool mp_only = !(C3V || P.viscous);
   bool shockL = false, shockR = false;
   if (!mp_only) {
     R om_m1 = wn.om[0], om_0 = wn.om[1], om_1 = wn.om[2], om_2 = wn.om[3];
@@ -304,12 +319,13 @@ __host__ __device__ __forceinline__ void gbr_flux_win(const Prob& P, const GbrWi
   hllc(WL, WR, xt, gamma, F);
 }
 
-// C-GBR convective flux at the interface between node idx and idx + s (direction d)
-template <typename R>
-__host__ __device__ __forceinline__ void gbr_flux(const Prob& P, int d, int idx, R F[5]) {
+// C-GBR convective flux at the interface between node idx and idx + s (direction d;
+// mi = met_idx(P, idx))
+template <typename R, bool C3V = false>
+__host__ __device__ __forceinline__ void gbr_flux(const Prob& P, int d, int idx, int mi, R F[5]) {
   GbrWin<R> wn;
-  gbr_fill(P, d, idx, wn);
-  gbr_flux_win(P, wn, F);
+  gbr_fill<R, C3V>(P, d, idx, mi, wn);
+  gbr_flux_win<R, C3V>(P, wn, F);
 }
 
 template <typename R>
@@ -320,8 +336,8 @@ __host__ __device__ __forceinline__ void i4_flux(const R* Fn, size_t T, int idx,
   }
 }
 
-template <typename R>
-__device__ __forceinline__ void interface_flux(const Prob& P, int d, int idx, int sel, R F[5]) {
+template <typename R, bool C3V = false>
+__device__ __forceinline__ void interface_flux(const Prob& P, int d, int idx, int mi, int sel, R F[5]) {
   const int s = P.s[d];
   const size_t T = P.total;
   bool gbr;
@@ -330,8 +346,8 @@ __device__ __forceinline__ void interface_flux(const Prob& P, int d, int idx, in
   else if (sel == SEL_PERCELL) gbr = *P.any_flag != 0 && (P.ft[idx] | P.ft[idx + s]) != 0;
   else gbr = *P.any_flag != 0;
   if (gbr) {
-    gbr_flux(P, d, idx, F);
-    if (P.viscous) {
+    gbr_flux<R, C3V>(P, d, idx, mi, F);
+    if (C3V || P.viscous) {
       R Fv[5];
       i4_flux(static_cast<const R*>(P.FV[d]), T, idx, s, Fv);
       for (int q = 0; q < 5; ++q) F[q] = F[q] + Fv[q];
@@ -341,7 +357,11 @@ __device__ __forceinline__ void interface_flux(const Prob& P, int d, int idx, in
   }
 }
 
-__device__ __forceinline__ double node_J(const Prob& P, int idx) { return met64(P, 9, idx); }
+// J at the node whose metric index is mi
+template <bool C3V = false>
+__device__ __forceinline__ double node_J(const Prob& P, int mi) {
+  return (C3V || P.curvilinear) ? P.M64[(size_t)9 * P.met_T + mi] : P.cm[9];
+}
 
 // ------------------------------------------------------------------ x sweep: one wave per
 // row segment of 63 nodes; lane t computes the interface left of node (seg*63 + t - 1) + 1
@@ -350,7 +370,7 @@ __device__ __forceinline__ double node_J(const Prob& P, int idx) { return met64(
 // derivative and forms the RK stage result at once (the combination kernel's work).
 // FP32: capped at 128 registers (four waves per SIMD; a few spill slots): 2.70 -> 2.50 ms on
 // the 1024 x 384 x 128 ramp (the strided sweeps get slower under the same cap).
-template <typename R>
+template <typename R, bool C3V>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1))) k_sweep_x(const Prob* __restrict__ probs, StateRef ref, int sel, int accumulate,
                                                  int skip_if_any, int rk, RKRef rr, int stage, double ca, double cb) {
   const Prob& P = probs[blockIdx.y];
@@ -371,12 +391,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     const int il = seg * 63 - 1 + lane;  // interface il + 1/2
     const bool valid = il <= n0 - 1;
     const int idx = pos_to_idx(P, il + P.g[0], j + P.g[1], k + P.g[2]);
+    const int mi = (C3V || P.met_planar) ? pos_to_idx(P, il + P.g[0], j + P.g[1], 0) : idx;
     R F[5] = {R(0), R(0), R(0), R(0), R(0)};
-    if (valid) interface_flux(P, 0, idx, sel, F);
+    if (valid) interface_flux<R, C3V>(P, 0, idx, mi, sel, F);
     double Fp[5];
     for (int q = 0; q < 5; ++q) Fp[q] = (double)__shfl_up(F[q], 1);
     if (lane >= 1 && valid) {
-      double J = node_J(P, idx);
+      double J = node_J<C3V>(P, mi);
       double Lq[5];
       for (int q = 0; q < 5; ++q) {
         double v = -J * ((double)F[q] - Fp[q]);
@@ -392,12 +413,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
 
 // ------------------------------------------------------------------ strided sweeps: one
 // lane per line segment of `seg` nodes, sliding along the line.
-template <typename R>
+template <typename R, bool C3V>
 __global__ void __launch_bounds__(256) k_sweep_s(const Prob* __restrict__ probs, StateRef ref, int d, int sel,
                                                  int accumulate, int seg, int skip_if_any, int rk, RKRef rr, int stage,
                                                  double ca, double cb) {
   const Prob& P = probs[blockIdx.y];
-  if (d >= P.ndim || gate_skip(P, skip_if_any)) return;
+  if (d >= (C3V ? 3 : P.ndim) || gate_skip(P, skip_if_any)) return;
   const int o2 = d == 1 ? 2 : 1;
   const int na = P.n[0], nb = P.n[o2], nd = P.n[d];
   const int nch = (nd + seg - 1) / seg;
@@ -411,18 +432,19 @@ __global__ void __launch_bounds__(256) k_sweep_s(const Prob* __restrict__ probs,
   pos[o2] = b + P.g[o2];
   pos[d] = start - 1 + P.g[d];
   int idx = pos_to_idx(P, pos[0], pos[1], pos[2]);
-  const int s = P.s[d];
+  int mi = (C3V || P.met_planar) ? pos_to_idx(P, pos[0], pos[1], 0) : idx;
+  const int s = P.s[d], ms = met_step<C3V>(P, d);
   const size_t T = P.total;
   double* dQ = ref.deriv(P);
   const double dt = rk ? *P.dt : 0.0;
   int bad = 0;
   // one flux evaluation site: interface p + 1/2 at node p, for p = start - 1 .. end - 1
   double Fp[5];
-  for (int p = start - 1; p < end; ++p, idx += s) {
+  for (int p = start - 1; p < end; ++p, idx += s, mi += ms) {
     R F[5];
-    interface_flux(P, d, idx, sel, F);
+    interface_flux<R, C3V>(P, d, idx, mi, sel, F);
     if (p >= start) {
-      const double J = node_J(P, idx);
+      const double J = node_J<C3V>(P, mi);
       double Lq[5];
       for (int q = 0; q < 5; ++q) {
         const double v = -J * ((double)F[q] - Fp[q]);
@@ -456,7 +478,7 @@ __global__ void __launch_bounds__(256) k_gbr_items(const Prob* __restrict__ prob
     for (int it = (int)(blockIdx.x * blockDim.x + threadIdx.x); it < cnt; it += stride) {
       const int idx = q[it];
       R F[5];
-      gbr_flux(P, d, idx, F);
+      gbr_flux(P, d, idx, met_idx(P, idx), F);
       if (P.viscous) {
         R Fv[5];
         i4_flux(static_cast<const R*>(P.FV[d]), T, idx, s, Fv);
@@ -503,23 +525,36 @@ void launch_sweep(const Launch& L, StateRef ref, int d, int sel, int accumulate,
                   int stage, double a, double b) {
   const RKRef r = rr ? *rr : RKRef{nullptr, nullptr, nullptr};
   const int rk = rr ? 1 : 0;
+  // every problem 3D, curvilinear with metrics planar along zeta, and viscous
+  const bool c3v = !L.geo_generic && !L.inviscid;
   if (d == 0) {
     long long nseg = (L.max_n[0] + 62) / 63;
     long long waves = nseg * L.sweep_rows[0];
     long long blocks = (waves + 3) / 4;
     if (blocks < 1) blocks = 1;
     if (blocks > 16384) blocks = 16384;   // the kernel strides over the rest
-    LG_TIMED(L, KC_SWEEP_X, hipLaunchKernelGGL(k_sweep_x<R>, dim3((unsigned)blocks, L.nprob), dim3(256), 0,
-                                               L.stream, L.probs, ref, sel, accumulate, skip_if_any, rk, r, stage, a, b));
+    if (c3v)
+      LG_TIMED(L, KC_SWEEP_X, hipLaunchKernelGGL((k_sweep_x<R, true>), dim3((unsigned)blocks, L.nprob), dim3(256), 0,
+                                                 L.stream, L.probs, ref, sel, accumulate, skip_if_any, rk, r, stage, a,
+                                                 b));
+    else
+      LG_TIMED(L, KC_SWEEP_X, hipLaunchKernelGGL((k_sweep_x<R, false>), dim3((unsigned)blocks, L.nprob), dim3(256),
+                                                 0, L.stream, L.probs, ref, sel, accumulate, skip_if_any, rk, r, stage,
+                                                 a, b));
   } else {
     const int seg = sweep_seg(L, d);
     long long nch = (L.max_n[d] + seg - 1) / seg;
     long long work = nch * L.sweep_rows[d];
     long long blocks = (work + 255) / 256;
     if (blocks < 1) blocks = 1;
-    LG_TIMED(L, d == 1 ? KC_SWEEP_Y : KC_SWEEP_Z,
-             hipLaunchKernelGGL(k_sweep_s<R>, dim3((unsigned)blocks, L.nprob), dim3(256), 0, L.stream, L.probs, ref,
-                                d, sel, accumulate, seg, skip_if_any, rk, r, stage, a, b));
+    if (c3v)
+      LG_TIMED(L, d == 1 ? KC_SWEEP_Y : KC_SWEEP_Z,
+               hipLaunchKernelGGL((k_sweep_s<R, true>), dim3((unsigned)blocks, L.nprob), dim3(256), 0, L.stream,
+                                  L.probs, ref, d, sel, accumulate, seg, skip_if_any, rk, r, stage, a, b));
+    else
+      LG_TIMED(L, d == 1 ? KC_SWEEP_Y : KC_SWEEP_Z,
+               hipLaunchKernelGGL((k_sweep_s<R, false>), dim3((unsigned)blocks, L.nprob), dim3(256), 0, L.stream,
+                                  L.probs, ref, d, sel, accumulate, seg, skip_if_any, rk, r, stage, a, b));
   }
 }
 

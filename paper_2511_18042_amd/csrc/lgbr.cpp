@@ -541,6 +541,7 @@ void fill_launch(Launch& L, const Prob& P) {
   // 32-bit element offsets address every field of the problem (five FP64 planes)
   if (40LL * P.total >= (1LL << 32)) L.o64 = 1;
   if (!(P.ndim == 3 && P.curvilinear && P.met_planar)) L.geo_generic = 1;
+  if (!P.viscous) L.inviscid = 1;
   if (P.total % 2 || ((unsigned long long)P.Q | (unsigned long long)P.Us) % 16) L.prim_scalar = 1;
   L.max_fsteps = std::max(L.max_fsteps, P.fsteps);
   L.max_total = std::max<long long>(L.max_total, P.total);

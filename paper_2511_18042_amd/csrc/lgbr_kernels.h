@@ -80,6 +80,7 @@ struct Launch {
   int has_fixed;           // some problem has a FIXED face (caller-owned ghosts)
   int o64;                 // some problem's fields need 64-bit offsets (5 FP64 planes >= 2^32 B)
   int geo_generic;         // some problem is not 3D curvilinear with metrics planar along zeta
+  int inviscid;            // some problem is inviscid
   int prim_scalar;         // some problem rules out two nodes per lane in k_prim (odd count, alignment)
   int pcr_dir[3];          // some problem solves its lines along d by PCR
   int thomas_dir[3];       // some problem solves its lines along d one lane per line

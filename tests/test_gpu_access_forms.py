@@ -1,11 +1,12 @@
 """The kernels' default code forms against their fallbacks.
 
 The defaults are 32-bit offsets from scalar bases in the FP32 LAD sweep and node fluxes, two
-nodes per lane in the primitive conversion, and forms of the LAD coefficient kernel (FP32)
-and node-flux kernel (FP64) compiled for 3D curvilinear grids with metrics planar along
-zeta. The kernels fall back by themselves to 64-bit addressing, one node per lane and the
-general geometry for fields of 2^32 bytes or more, odd node counts, unaligned state or other
-grids, and lg_set_generic_access forces those fallbacks (bit 0 addressing, bit 1 geometry).
+nodes per lane in the primitive conversion, and forms of the LAD coefficient kernel (FP32),
+node-flux kernel (FP64) and C-GBR direction sweeps (viscous problems) compiled for 3D
+curvilinear grids with metrics planar along zeta. The kernels fall back by themselves to
+64-bit addressing, one node per lane and the general form for fields of 2^32 bytes or more,
+odd node counts, unaligned state, other grids or inviscid problems, and
+lg_set_generic_access forces those fallbacks (bit 0 addressing, bit 1 geometry).
 On the compression-ramp crop (3D, curvilinear, extruded along zeta) right-hand sides and
 RK3 steps must be bitwise equal across the addressing forms, and across the geometry forms
 in FP64; the FP32 geometry forms differ by rounding only (the compiler fuses and orders the
