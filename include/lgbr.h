@@ -61,7 +61,7 @@ typedef enum {
 /* boundary conditions (the per-case boundary treatments of Sec. 3) */
 enum {
   LG_BC_PERIODIC = 0,          /* periodic images                                      */
-  LG_BC_TRANSMISSIVE = 1,      /* zeroth-order extrapolation ("extrapolated outflow")  */
+  LG_BC_TRANSMISSIVE = 1,      /* zeroth-order extrapolation of every variable        */
   LG_BC_REFLECTIVE = 2,        /* mirror, normal momentum negated (inviscid wall)      */
   LG_BC_NOSLIP_ADIABATIC = 3,  /* mirror, all momentum negated (no-slip adiabatic wall)*/
   LG_BC_FIXED = 4,             /* ghosts owned by the caller (inflow at the IC state)  */

@@ -1,7 +1,7 @@
 """First derivatives along one computational direction (oracle; test infrastructure only).
 
 Paper: Sec. 2.3 (MEG6 uses explicit sixth-order gradients, MIG4 implicit fourth-order
-gradients obtained by "solving several 1D tridiagonal matrices", Sec. 4.2) and the
+gradients, one tridiagonal solve per line and primitive, Sec. 4.2) and the
 LAD-E4 variant of Sec. 4.2 / Sec. 5 (explicit fourth-order central differences).
 Unit computational spacing (Delta xi = 1, Sec. 2.2).
 

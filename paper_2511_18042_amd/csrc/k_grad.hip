@@ -1,8 +1,8 @@
 // Gradients of the primitives along one computational direction.
 //
 // Paper: Sec. 2.3 -- MEG6 reconstructs from explicit sixth-order gradients, MIG4 from
-// implicit fourth-order (compact) gradients, which requires "solving several 1D
-// tridiagonal matrices" (Sec. 4.2).  Unit computational spacing (Sec. 2.2).
+// implicit fourth-order (compact) gradients, which cost one tridiagonal solve per line
+// and primitive (Sec. 4.2).  Unit computational spacing (Sec. 2.2).
 //
 //   E6: f'_i = [45 (f_{i+1}-f_{i-1}) - 9 (f_{i+2}-f_{i-2}) + (f_{i+3}-f_{i-3})] / 60
 //   C4: f'_{i-1}/4 + f'_i + f'_{i+1}/4 = 3 (f_{i+1} - f_{i-1}) / 4
