@@ -993,6 +993,157 @@ __global__ void __launch_bounds__(64 * FPART_WAVES) k_filter_part(const Prob* __
   }
 }
 
+// ------------------------------------------------------------------ C4 gradients, partition method
+// MIG4 gradients along xi on bounded lines (Sec. 2.3; the C4 rows of k_grad.hip).  The
+// one-sided end rows of the padded line of N nodes decouple, so rows 1 .. N-2 form the
+// [1/4, 1, 1/4] system of M = N - 2 unknowns with the two end values moved to the
+// right-hand side: the system k_filter_part solves with a = alpha_f, solved the same way
+// here with a = 1/4 (segments per lane, joint unknowns by two wave-wide scans).  One wave
+// per (line, primitive) over every line of the direction; the five primitives of a line are
+// consecutive items, so their staging reads of the state share the cache.  Region-free
+// launches only (every line; in a per-cell stage, when most lines are listed).
+template <typename R, int LM>
+__global__ void __launch_bounds__(64 * FPART_WAVES) k_grad_c4_part(const Prob* __restrict__ probs, StateRef ref,
+                                                                   int nmax, int skip_if_any, int dense_only,
+                                                                   int mask) {
+  extern __shared__ double dyn[];   // per wave: the staged line [nmax + 10]
+  __shared__ double tcp[FPART_LMAX], tinv[FPART_LMAX];
+  __shared__ double tu[2][FPART_LMAX], tv[2][FPART_LMAX];   // segment lengths base and base + 1
+  __shared__ double tda[64], tGa[64], tGb[64];
+  const Prob& P = probs[blockIdx.y];
+  if (!c4_part_use(P, 0, mask) || P.n[0] > nmax || gate_skip(P, skip_if_any)) return;
+  if (dense_only && !dense_lines(P, 0)) return;
+  const int N = P.N[0], M = N - 2;
+  const int nseg = min(64, M / 2);
+  const int base = M / nseg, extra = M % nseg;   // the first `extra` segments have base + 1
+  if (base + 1 > LM) return;   // segments longer than the register arrays
+  const double al = 0.25;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  // segment factors, the responses u = T^{-1} e_1 and v = T^{-1} e_L, and the
+  // data-independent elimination factors of the joint unknowns (as in k_filter_part)
+  if (threadIdx.x == 0) {
+    double c = 0.0;
+    for (int i = 0; i < base + 1; ++i) {
+      const double den = 1.0 - (i > 0 ? al * c : 0.0);
+      tinv[i] = 1.0 / den;
+      c = al / den;
+      tcp[i] = c;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {   // threads 0 / 1: u for base / base + 1; 2 / 3: v
+    const int which = threadIdx.x & 1, L = base + which;
+    const bool is_u = threadIdx.x < 2;
+    double* out = is_u ? tu[which] : tv[which];
+    double prev = 0.0;
+    for (int i = 0; i < L; ++i) {
+      const double rhs = is_u ? (i == 0 ? 1.0 : 0.0) : (i == L - 1 ? 1.0 : 0.0);
+      prev = (rhs - (i > 0 ? al * prev : 0.0)) * tinv[i];
+      out[i] = prev;
+    }
+    double y = out[L - 1];
+    for (int i = L - 2; i >= 0; --i) {
+      y = out[i] - tcp[i] * y;
+      out[i] = y;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double Gbp = 0.0;
+    for (int sg = 0; sg < nseg; ++sg) {
+      const int lw = sg < extra ? 1 : 0, Ls = base + lw;
+      const double da = 1.0 - al * tu[lw][0] * Gbp;
+      const double Ga = al * tv[lw][0] / da;
+      tda[sg] = da;
+      tGa[sg] = Ga;
+      tGb[sg] = al * tv[lw][Ls - 1] + al * tu[lw][Ls - 1] * Gbp * Ga;
+      Gbp = tGb[sg];
+    }
+  }
+  __syncthreads();
+  double* f = dyn + (size_t)w * fpart_lds_slots(nmax);
+  auto F = [f](int p) -> double& { return f[p + (p >> 4)]; };
+  const int nlines = P.N[1] * P.N[2];
+  const size_t T = P.total;
+  const double* Q = ref.state(P);
+  R* G = static_cast<R*>(P.G[0]);
+  const double gm1 = P.gamma - 1.0;
+  const bool act = lane < nseg;
+  const int L = base + (lane < extra ? 1 : 0);
+  const int j0 = lane * base + min(lane, extra);   // first unknown of this lane's segment
+  const int wl = lane < extra ? 1 : 0;             // which u / v table
+  const double u1 = act ? tu[wl][0] : 0.0, uL = act ? tu[wl][L - 1] : 0.0;
+  const double da = act ? tda[lane] : 1.0, Ga = act ? tGa[lane] : 0.0, Gb = act ? tGb[lane] : 0.0;
+  const double Gbm = act && lane > 0 ? tGb[lane - 1] : 0.0;
+  for (int item = blockIdx.x * nw + w; item < 5 * nlines; item += gridDim.x * nw) {
+    const int line = item / 5, q = item % 5;
+    const size_t lb = (size_t)(line % P.N[1]) * P.s[1] + (size_t)(line / P.N[1]) * P.s[2];
+    for (int p = lane; p < N; p += 64) {
+      double v;
+      prims_q<1>(Q, T, lb + (size_t)p, gm1, q, &v);
+      F(p) = v;
+    }
+    wave_lds_sync();
+    // the decoupled end rows (second-order one-sided)
+    const double d0 = (-3.0 * F(0) + 4.0 * F(1) - F(2)) / 2.0;
+    const double dN = (3.0 * F(N - 1) - 4.0 * F(N - 2) + F(N - 3)) / 2.0;
+    double y[LM];
+    double ya = 0.0, yb = 0.0;
+    if (act) {
+      // unknown j is row j + 1: 3 (f_{j+2} - f_j) / 4, less a / 4 times a known end value
+      double fm = F(j0), f0 = F(j0 + 1);
+      double prev = 0.0;
+#pragma unroll
+      for (int i = 0; i < LM; ++i) {
+        if (i < L) {
+          const int j = j0 + i;
+          const double fp = F(j + 2);
+          double r = 0.75 * (fp - fm);
+          if (j == 0) r = r - al * d0;
+          if (j == M - 1) r = r - al * dN;
+          prev = (r - (i > 0 ? al * prev : 0.0)) * tinv[i];
+          y[i] = prev;
+          fm = f0;
+          f0 = fp;
+        }
+      }
+      yb = prev;
+      double v = prev;
+#pragma unroll
+      for (int i = LM - 2; i >= 0; --i) {
+        if (i < L - 1) {
+          v = y[i] - tcp[i] * v;
+          y[i] = v;
+        }
+      }
+      ya = y[0];
+    }
+    const double gbv = scan_up(act ? -al * uL / da : 0.0, act ? yb + al * uL * Gbm * ya / da : 0.0, lane);
+    double gbm = __shfl_up(gbv, 1);
+    if (lane == 0) gbm = 0.0;
+    const double gav = act ? (ya - al * u1 * gbm) / da : 0.0;
+    const double A = scan_down(act ? -Ga : 0.0, gav, lane);
+    double Ap = __shfl_down(A, 1);
+    if (lane + 1 >= nseg) Ap = 0.0;
+    const double B = gbv - Gb * Ap;
+    double Bm = __shfl_up(B, 1);
+    if (lane == 0) Bm = 0.0;
+    wave_lds_sync();   // every lane has read its window before the solution overwrites it
+    if (act) {
+#pragma unroll
+      for (int i = 0; i < LM; ++i)
+        if (i < L) F(1 + j0 + i) = y[i] - al * tu[wl][i] * Bm - al * tv[wl][i] * Ap;
+    }
+    if (lane == 0) {
+      F(0) = d0;
+      F(N - 1) = dN;
+    }
+    wave_lds_sync();
+    for (int p = lane; p < N; p += 64) G[(size_t)q * T + lb + (size_t)p] = (R)F(p);
+    wave_lds_sync();   // the next item's staging overwrites f
+  }
+}
+
 // ------------------------------------------------------------------ line tiles
 // One workgroup holds all five variables of TX neighbouring lines of one direction in LDS
 // (TX * 5 * positions <= TILE_ELEMS doubles), forms the right-hand sides there, reduces
@@ -1440,8 +1591,32 @@ void launch_grad_c4_tiles(const Launch& L, StateRef ref, int d, int skip_if_any,
                                        0.0, 0.0, 0, dense_only});
 }
 
+template <typename R>
+void launch_grad_c4_part(const Launch& L, StateRef ref, int skip_if_any, int dense_only) {
+  if (!L.c4part) return;
+  // one wave per (line, primitive); four waves per workgroup while their staged lines fit
+  // 60 KB of LDS, two otherwise
+  const long long nmax = L.max_n[0];
+  const size_t per_wave = (size_t)fpart_lds_slots((int)nmax) * sizeof(double);
+  const int nw = 4 * per_wave <= 60 * 1024 ? 4 : 2;
+  const long long items = 5 * L.lines[0];
+  const unsigned blocks = (unsigned)std::max<long long>(1, std::min<long long>((items + nw - 1) / nw, 4096));
+  // register arrays sized to the longest segment: short ones when every line has at most
+  // 1088 unknowns (segments of at most 17)
+  if (nmax + 8 <= 64 * (FPART_LSHORT - 1))
+    LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL((k_grad_c4_part<R, FPART_LSHORT>), dim3(blocks, L.nprob),
+                                               dim3(64 * nw), nw * per_wave, L.stream, L.probs, ref, (int)nmax,
+                                               skip_if_any, dense_only, L.tile_mask));
+  else
+    LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL((k_grad_c4_part<R, FPART_LMAX>), dim3(blocks, L.nprob),
+                                               dim3(64 * nw), nw * per_wave, L.stream, L.probs, ref, (int)nmax,
+                                               skip_if_any, dense_only, L.tile_mask));
+}
+
 template void launch_grad_c4_tiles<float>(const Launch&, StateRef, int, int, int);
 template void launch_grad_c4_tiles<double>(const Launch&, StateRef, int, int, int);
+template void launch_grad_c4_part<float>(const Launch&, StateRef, int, int);
+template void launch_grad_c4_part<double>(const Launch&, StateRef, int, int);
 template void launch_grad_c6<float>(const Launch&, StateRef, int);
 template void launch_grad_c6<double>(const Launch&, StateRef, int);
 template void launch_c6_faces<float>(const Launch&, StateRef, int, int, const RKRef*, int, double, double);

@@ -514,7 +514,8 @@ void fill_launch(Launch& L, const Prob& P) {
     if (pcr) L.pcr_dir[d] = 1;
     else L.thomas_dir[d] = 1;
     if (P.grad_c4) {
-      if (lg::tile_use(P, d, lg::TK_GRAD4, L.tile_mask)) L.ctile[lg::TK_GRAD4][d] = 1;
+      if (lg::c4_part_use(P, d, L.tile_mask)) L.c4part = 1;
+      else if (lg::tile_use(P, d, lg::TK_GRAD4, L.tile_mask)) L.ctile[lg::TK_GRAD4][d] = 1;
       else if (pcr) L.c4_rest_pcr[d] = 1;
       else L.c4_rest_thomas[d] = 1;
     }
@@ -1111,7 +1112,7 @@ lg_status lg_set_line_tiles(lg_ctx* c, int mask) {
     for (int k = 0; k < 4; ++k) c->L.ctile[k][d] = 0;
     c->L.c4_rest_pcr[d] = c->L.c4_rest_thomas[d] = 0;
   }
-  c->L.fpart = 0;
+  c->L.fpart = c->L.c4part = 0;
   for (int d = 0; d < 3; ++d) c->L.fseg[d] = 0;
   fill_launch(c->L, c->hp);
   return LG_OK;

@@ -98,6 +98,7 @@ struct Launch {
   int tile_lines;          // most lines per LDS line tile (0: as many as fit)
   int item_blocks;         // persistent workgroups of the compacted C-GBR interface pass (0: 2048)
   int fpart;               // some problem filters along xi with the partition-method kernel
+  int c4part;              // some problem solves its MIG4 gradients along xi by the partition method
   int fseg[3];             // most segments per line of the problems filtering along d by k_filter_seg (0: none)
   Prof* prof;              // optional launch timing (null: off)
 };
@@ -199,8 +200,10 @@ inline int zm_arg(const Launch& L, int lo, int hi) {
 // gradients (region = 1: only where the per-cell hybrid needs C-GBR inputs)
 template <typename R> void launch_grad_explicit(const Launch& L, int d, int order, int skip_if_any, int region);
 template <typename R> void launch_grad_c4(const Launch& L, StateRef ref, int d, int skip_if_any, int region);
-// C4 gradients of whole lines in LDS tiles (region-free launches; see tile_use)
+// C4 gradients of whole lines in LDS tiles (region-free launches; see tile_use), and along xi
+// by the partition method (see c4_part_use)
 template <typename R> void launch_grad_c4_tiles(const Launch& L, StateRef ref, int d, int skip_if_any, int dense_only);
+template <typename R> void launch_grad_c4_part(const Launch& L, StateRef ref, int skip_if_any, int dense_only);
 // sensor and C-GBR viscous node fluxes
 template <typename R> void launch_sensor(const Launch& L, int skip_if_any, int region);
 template <typename R> void launch_gbr_viscflux(const Launch& L, int skip_if_any, int region);
@@ -243,7 +246,7 @@ void launch_filter_guard(const Launch& L, StateRef ref, int mode);
 enum { TK_GRAD6 = 0, TK_FACES = 1, TK_FILTER = 2, TK_GRAD4 = 3 };
 constexpr int TILE_MASK_ALL = 0xFFF;
 constexpr int TILE_MASK_FORCE_STRIDED = 0x1000;   // tiles on strided directions whatever their line count
-constexpr int TILE_MASK_NO_PART = 0x2000;          // filter along xi without the partition-method kernel
+constexpr int TILE_MASK_NO_PART = 0x2000;          // no partition-method kernels along xi (filter, MIG4 gradients)
 constexpr int TILE_MASK_NO_SEG = 0x4000;           // filter along eta / zeta without the register-segment kernel
 constexpr int TILE_MASK_DEFAULT = TILE_MASK_ALL;
 constexpr int TILE_ELEMS = 6144;   // doubles per tile (48 KB of LDS)
@@ -267,8 +270,15 @@ __host__ __device__ inline bool tile_ok(const Prob& P, int d, int kind) {
 // 142 k lines, 2.5 ms one lane per line vs 4.4 ms in tiles; a 1792 x 768 plane has only
 // 1802 eta lines, far too few lanes)
 constexpr long long TILE_FEW_LINES = 32768;
+// MIG4 gradients along xi on bounded lines of 128..2048 unknowns (the padded line less its
+// two decoupled end rows): partition method (k_grad_c4_part) unless mask bit 13 turns it off
+__host__ __device__ inline bool c4_part_use(const Prob& P, int d, int mask) {
+  return !(mask & TILE_MASK_NO_PART) && d == 0 && P.bc[0][0] != BC_PERIODIC && P.N[0] - 2 >= 128 &&
+         P.N[0] - 2 <= 2048;
+}
 __host__ __device__ inline bool tile_use(const Prob& P, int d, int kind, int mask) {
   if (!((mask >> (3 * kind + d)) & 1) || !tile_ok(P, d, kind)) return false;
+  if (kind == TK_GRAD4 && c4_part_use(P, d, mask)) return false;
   if (d == 0 || (mask & TILE_MASK_FORCE_STRIDED)) return true;
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   const bool all_nodes = kind == TK_GRAD6 || kind == TK_GRAD4;
