@@ -763,6 +763,145 @@ __global__ void __launch_bounds__(64 * FSEG_SMAX) k_filter_seg(const Prob* __res
   }
 }
 
+// ------------------------------------------------------------------ C4 gradients, strided segments
+// MIG4 gradients along eta / zeta (Sec. 2.3; the C4 rows of k_grad.hip) in register
+// segments, as k_filter_seg filters: 64 neighbouring lines (consecutive along xi) and one
+// primitive per workgroup, wave s segment s of every line, the segments joined through the
+// LU of their first and last unknowns (host tables for a = 1/4).  A bounded line of N nodes
+// has one-sided end rows that decouple: its unknowns are rows 1 .. N-2, the two end values
+// moved to the right-hand side.  A periodic line's unknowns are its n interior nodes
+// (cyclic), and its ghosts take the periodic images.  Right-hand sides 3 (f_{i+1} -
+// f_{i-1}) / 4 from FP64 primitives formed from the state; the gradients go to G in the bulk
+// type.  Region-free launches only (every line; in a per-cell stage, when most lines are
+// listed).
+template <typename R, int LM>
+__global__ void __launch_bounds__(64 * FSEG_SMAX) k_grad_c4_seg(const Prob* __restrict__ probs, StateRef ref, int d,
+                                                                 int skip_if_any, int dense_only, int mask) {
+  constexpr int SM = FSEG_SMAX, M2 = 2 * SM;
+  __shared__ double tab[FSEG_TABLE];      // cp, 1 / pivot, u, v, joint LU (host-built)
+  __shared__ double ends[SM][2][64];      // y_s[0], y_s[L-1] of each line; then A_s, B_s
+  const Prob& P = probs[blockIdx.y];
+  if (!c4_seg_use(P, d, mask) || gate_skip(P, skip_if_any)) return;
+  if (dense_only && !dense_lines(P, d)) return;
+  const bool periodic = P.bc[d][0] == BC_PERIODIC;
+  const int N = P.N[d], n = P.n[d], g = P.g[d], sd = P.s[d];
+  const int m = c4_seg_unknowns(P, d);
+  const int S = fseg_count(m);
+  const int base = m / S, extra = m % S;   // the first `extra` segments have base + 1
+  const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+  const int nlines = P.N[o1] * P.N[o2];
+  const int q = blockIdx.x % 5, grp = blockIdx.x / 5;
+  if (grp * 64 >= nlines) return;
+  const double al = 0.25;
+  const int lane = threadIdx.x & 63, s = threadIdx.x >> 6;
+  for (int e = threadIdx.x; e < FSEG_TABLE; e += blockDim.x) tab[e] = P.c4segt[d][e];
+  const double* tcp = tab + FSEG_CP;
+  const double* tinv = tab + FSEG_INV;
+  const int line = grp * 64 + lane;
+  const bool act = s < S && line < nlines;
+  const int L = base + (s < extra ? 1 : 0);
+  const int j0 = s * base + min(s, extra);   // first unknown of this lane's segment
+  const double* tu = tab + FSEG_U + (s < extra ? LM + 1 : 0);
+  const double* tv = tab + FSEG_V + (s < extra ? LM + 1 : 0);
+  const double* Q = ref.state(P);
+  R* G = static_cast<R*>(P.G[d]);
+  const size_t T = P.total;
+  const double gm1 = P.gamma - 1.0;
+  const size_t lb = act ? (size_t)(line % P.N[o1]) * P.s[o1] + (size_t)(line / P.N[o1]) * P.s[o2] : 0;
+  // line position of window slot i: the rows j0 .. j0 + L + 1 around this segment's rows
+  // j0 + 1 .. j0 + L (bounded), the interior nodes j0 - 1 .. j0 + L wrapped (periodic)
+  auto pos = [&](int i) { return periodic ? g + wrap(j0 + i - 1, n) : j0 + i; };
+  // w[i] = f at pos(i); after row i, w[i] (no longer read) holds the forward value, then y_i
+  double w[LM + 2];
+  double d0 = 0.0, dN = 0.0;   // the decoupled end rows of a bounded line
+  if (act) {
+#pragma unroll
+    for (int i = 0; i < LM + 2; ++i)
+      if (i < L + 2) prims_q<1>(Q, T, lb + (size_t)pos(i) * sd, gm1, q, &w[i]);
+    if (!periodic && s == 0) d0 = (-3.0 * w[0] + 4.0 * w[1] - w[2]) / 2.0;
+  }
+  __syncthreads();   // tables in LDS
+  double ya = 0.0, yb = 0.0;
+  if (act) {
+    double prev = 0.0;
+#pragma unroll
+    for (int i = 0; i < LM; ++i) {
+      if (i < L) {
+        double r = 0.75 * (w[i + 2] - w[i]);
+        const int j = j0 + i;
+        if (!periodic && j == 0) r = r - al * d0;
+        if (!periodic && j == m - 1) {   // rows N-3 .. N-1 are slots i .. i + 2 here
+          dN = (3.0 * w[i + 2] - 4.0 * w[i + 1] + w[i]) / 2.0;
+          r = r - al * dN;
+        }
+        prev = (r - (i > 0 ? al * prev : 0.0)) * tinv[i];
+        w[i] = prev;
+      }
+    }
+    yb = prev;
+    double v = prev;
+#pragma unroll
+    for (int i = LM - 2; i >= 0; --i) {
+      if (i < L - 1) {
+        v = w[i] - tcp[i] * v;
+        w[i] = v;
+      }
+    }
+    ya = w[0];
+    ends[s][0][lane] = ya;
+    ends[s][1][lane] = yb;
+  }
+  __syncthreads();
+  if (s == 0 && line < nlines) {   // L U z = (y_s[0], y_s[L-1])_s, in place in ends
+    const double* lu = tab + FSEG_LU;
+    const int m2 = 2 * S;
+    double z[M2];
+#pragma unroll
+    for (int r = 0; r < M2; ++r) {
+      if (r < m2) {
+        double v = ends[r >> 1][r & 1][lane];
+#pragma unroll
+        for (int c = 0; c < r; ++c) v -= lu[r * M2 + c] * z[c];
+        z[r] = v;
+      }
+    }
+#pragma unroll
+    for (int r = M2 - 1; r >= 0; --r) {
+      if (r < m2) {
+        double v = z[r];
+#pragma unroll
+        for (int c = r + 1; c < M2; ++c)
+          if (c < m2) v -= lu[r * M2 + c] * z[c];
+        z[r] = v / lu[r * M2 + r];
+        ends[r >> 1][r & 1][lane] = z[r];
+      }
+    }
+  }
+  __syncthreads();
+  if (act) {
+    const int sp = s - 1, sn = s + 1;
+    const double Bm = (periodic || sp >= 0) ? ends[(sp + S) % S][1][lane] : 0.0;
+    const double Ap = (periodic || sn < S) ? ends[sn % S][0][lane] : 0.0;
+    R* Gl = G + (size_t)q * T + lb;
+#pragma unroll
+    for (int i = 0; i < LM; ++i) {
+      if (i < L) {
+        const int j = j0 + i;
+        const R x = (R)(w[i] - al * tu[i] * Bm - al * tv[i] * Ap);
+        if (periodic) {
+          Gl[(size_t)(g + j) * sd] = x;
+          if (j < g) Gl[(size_t)(g + n + j) * sd] = x;            // ghost images past the end
+          if (j >= n - g) Gl[(size_t)(j - (n - g)) * sd] = x;     // ... and before the start
+        } else {
+          Gl[(size_t)(j + 1) * sd] = x;
+        }
+      }
+    }
+    if (!periodic && s == 0) Gl[0] = (R)d0;
+    if (!periodic && s == S - 1) Gl[(size_t)(N - 1) * sd] = (R)dN;
+  }
+}
+
 // ------------------------------------------------------------------ filter positivity guard
 // A hybrid stage's filter (the LAD phase's FILTER_CALLS) must not hand the next stage a
 // non-physical node: the filter's ringing at a sharp jump that the LAD stage has not yet
@@ -1615,8 +1754,20 @@ void launch_grad_c4_part(const Launch& L, StateRef ref, int skip_if_any, int den
 
 template void launch_grad_c4_tiles<float>(const Launch&, StateRef, int, int, int);
 template void launch_grad_c4_tiles<double>(const Launch&, StateRef, int, int, int);
+template <typename R>
+void launch_grad_c4_seg(const Launch& L, StateRef ref, int d, int skip_if_any, int dense_only) {
+  if (L.c4seg[d] <= 0) return;
+  // 64 lines x one primitive per workgroup, one wave per segment
+  const long long groups = (L.lines[d] + 63) / 64;
+  LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL((k_grad_c4_seg<R, FSEG_LM>), dim3((unsigned)(5 * groups), L.nprob),
+                                             dim3(64 * L.c4seg[d]), 0, L.stream, L.probs, ref, d, skip_if_any,
+                                             dense_only, L.tile_mask));
+}
+
 template void launch_grad_c4_part<float>(const Launch&, StateRef, int, int);
 template void launch_grad_c4_part<double>(const Launch&, StateRef, int, int);
+template void launch_grad_c4_seg<float>(const Launch&, StateRef, int, int, int);
+template void launch_grad_c4_seg<double>(const Launch&, StateRef, int, int, int);
 template void launch_grad_c6<float>(const Launch&, StateRef, int);
 template void launch_grad_c6<double>(const Launch&, StateRef, int);
 template void launch_c6_faces<float>(const Launch&, StateRef, int, int, const RKRef*, int, double, double);

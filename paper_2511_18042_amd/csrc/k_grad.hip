@@ -104,6 +104,7 @@ __global__ void __launch_bounds__(256) k_grad_c4(const Prob* __restrict__ probs,
   const bool listed = region == 1;
   if (!listed && tile_use(P, d, TK_GRAD4, mask)) return;   // done in LDS tiles
   if (!listed && c4_part_use(P, d, mask)) return;          // done by the partition method
+  if (!listed && c4_seg_use(P, d, mask)) return;           // done in register segments
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   const int nlines = P.N[o1] * P.N[o2];
   const int cnt = listed ? P.lcount[d] : nlines;   // compacted list of lines that need solving
@@ -219,6 +220,7 @@ __global__ void __launch_bounds__(256) k_grad_c4_pcr(const Prob* __restrict__ pr
   const bool listed = region == 1;
   if (!listed && tile_use(P, d, TK_GRAD4, mask)) return;   // done in LDS tiles
   if (!listed && c4_part_use(P, d, mask)) return;          // done by the partition method
+  if (!listed && c4_seg_use(P, d, mask)) return;           // done in register segments
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   const int nlines = P.N[o1] * P.N[o2];
   const int cnt = listed ? P.lcount[d] : nlines;   // compacted list of lines that need solving
@@ -335,6 +337,7 @@ void launch_grad_c4(const Launch& L, StateRef ref, int d, int skip_if_any, int r
   auto full = [&](int reg) {
     launch_grad_c4_tiles<R>(L, ref, d, skip_if_any, reg == 2);
     if (d == 0) launch_grad_c4_part<R>(L, ref, skip_if_any, reg == 2);
+    else launch_grad_c4_seg<R>(L, ref, d, skip_if_any, reg == 2);
     if (L.c4_rest_pcr[d]) {
       const long long N = std::min<long long>(L.max_N[d], PCR_MAX_LINE);
       const unsigned lds = (unsigned)(2 * N * sizeof(double));

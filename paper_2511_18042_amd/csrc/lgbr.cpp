@@ -516,6 +516,8 @@ void fill_launch(Launch& L, const Prob& P) {
     if (P.grad_c4) {
       if (lg::c4_part_use(P, d, L.tile_mask)) L.c4part = 1;
       else if (lg::tile_use(P, d, lg::TK_GRAD4, L.tile_mask)) L.ctile[lg::TK_GRAD4][d] = 1;
+      else if (lg::c4_seg_use(P, d, L.tile_mask))
+        L.c4seg[d] = std::max(L.c4seg[d], lg::fseg_count(lg::c4_seg_unknowns(P, d)));
       else if (pcr) L.c4_rest_pcr[d] = 1;
       else L.c4_rest_thomas[d] = 1;
     }
@@ -824,6 +826,17 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
         return ok ? LG_EHIP : LG_ENOMEM;
       }
       P.pcr[d] = pd;
+      const bool periodic = P.bc[d][0] == LG_BC_PERIODIC;
+      const int m = periodic ? P.n[d] : P.N[d] - 2;   // unknowns (c4_seg_unknowns)
+      if (d > 0 && lg::fseg_count(m) <= lg::FSEG_SMAX && m >= 16) {
+        const std::vector<double> cs = fseg_table(m, 0.25, periodic);
+        double* t3 = static_cast<double*>(A(cs.size() * sizeof(double)));
+        if (!ok || hipMemcpy(t3, cs.data(), cs.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+          lg_destroy(c);
+          return ok ? LG_EHIP : LG_ENOMEM;
+        }
+        P.c4segt[d] = t3;
+      }
     }
   }
   if (c6) {
@@ -1113,7 +1126,7 @@ lg_status lg_set_line_tiles(lg_ctx* c, int mask) {
     c->L.c4_rest_pcr[d] = c->L.c4_rest_thomas[d] = 0;
   }
   c->L.fpart = c->L.c4part = 0;
-  for (int d = 0; d < 3; ++d) c->L.fseg[d] = 0;
+  for (int d = 0; d < 3; ++d) c->L.fseg[d] = c->L.c4seg[d] = 0;
   fill_launch(c->L, c->hp);
   return LG_OK;
 }

@@ -80,6 +80,7 @@ struct Prob {
   const double* trf[3];  // filter systems
   const double* pcrf[3];
   const double* fsegt[3]; // filter along eta / zeta by register segments (k_filter_seg tables)
+  const double* c4segt[3];  // MIG4 gradients along eta / zeta by register segments (k_grad_c4_seg tables)
   // device scalars
   double* dt;
   double* t;

@@ -99,6 +99,7 @@ struct Launch {
   int item_blocks;         // persistent workgroups of the compacted C-GBR interface pass (0: 2048)
   int fpart;               // some problem filters along xi with the partition-method kernel
   int c4part;              // some problem solves its MIG4 gradients along xi by the partition method
+  int c4seg[3];            // most segments per line of the problems solving MIG4 gradients along d in k_grad_c4_seg (0: none)
   int fseg[3];             // most segments per line of the problems filtering along d by k_filter_seg (0: none)
   Prof* prof;              // optional launch timing (null: off)
 };
@@ -204,6 +205,7 @@ template <typename R> void launch_grad_c4(const Launch& L, StateRef ref, int d, 
 // by the partition method (see c4_part_use)
 template <typename R> void launch_grad_c4_tiles(const Launch& L, StateRef ref, int d, int skip_if_any, int dense_only);
 template <typename R> void launch_grad_c4_part(const Launch& L, StateRef ref, int skip_if_any, int dense_only);
+template <typename R> void launch_grad_c4_seg(const Launch& L, StateRef ref, int d, int skip_if_any, int dense_only);
 // sensor and C-GBR viscous node fluxes
 template <typename R> void launch_sensor(const Launch& L, int skip_if_any, int region);
 template <typename R> void launch_gbr_viscflux(const Launch& L, int skip_if_any, int region);
@@ -319,6 +321,19 @@ __host__ __device__ inline bool filt_seg_use(const Prob& P, int d, int mask) {
     return false;
   const int S = fseg_count(P.n[d]);
   return S <= FSEG_SMAX && P.n[d] >= 16;
+}
+// MIG4 gradients along eta / zeta in register segments (k_grad_c4_seg, tables of the same
+// layout for a = 1/4): bounded lines (their N - 2 unknowns between the decoupled end rows)
+// and periodic lines (n interior unknowns) of 16 to 512 unknowns that the LDS tiles do not
+// take, outside the listed lines of per-cell stages, unless mask bit 14 is set
+__host__ __device__ inline int c4_seg_unknowns(const Prob& P, int d) {
+  return P.bc[d][0] == BC_PERIODIC ? P.n[d] : P.N[d] - 2;
+}
+__host__ __device__ inline bool c4_seg_use(const Prob& P, int d, int mask) {
+  if ((mask & TILE_MASK_NO_SEG) || d == 0 || d >= P.ndim || !P.c4segt[d] || tile_use(P, d, TK_GRAD4, mask))
+    return false;
+  const int m = c4_seg_unknowns(P, d);
+  return fseg_count(m) <= FSEG_SMAX && m >= 16;
 }
 
 }  // namespace lg
