@@ -601,7 +601,8 @@ __global__ void __launch_bounds__(256) k_lad_nodeflux(const Prob* __restrict__ p
 // dQ/dt = -J sum_l (F_{l,+1/2} - F_{l,-1/2}) with F = I4 of the node fluxes (fourth-order
 // midpoint interpolation), the differences in FP64 in the order xi, eta, zeta; mode 0
 // stores it, mode 1 forms the RK stage a U^n + b (U^s + dt L) in place of the combination
-// kernel (interior nodes; non-physical results are counted).
+// kernel (interior nodes; non-physical results are counted), and with rr.save_dq also
+// writes it to dQ/dt, the copy the filter guard restores from.
 template <typename R>
 __device__ __forceinline__ R i4v(R m1, R c0, R p1, R p2) {
   return (R(7) * (c0 + p1) - (m1 + p2)) * R(1.0 / 12.0);
@@ -674,6 +675,7 @@ __global__ void __launch_bounds__(256) k_lad_sweep(const Prob* __restrict__ prob
         const IX o = (IX)q * T + (IX)idx;
         v[q] = a * gld<double, O32>(Un, o) + b * (gld<double, O32>(Us, o) + dt * Lq[q]);
         gst<double, O32>(out, o, v[q]);
+        if (rr.save_dq) gst<double, O32>(P.dQ, o, v[q]);
       }
       const double rho = v[0];
       const double ke = 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / rho;

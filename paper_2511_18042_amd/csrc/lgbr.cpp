@@ -232,14 +232,17 @@ void enqueue_rk3(const Launch& L, const Cfg& c, int scheme, double* Qx, double* 
   const int fmode = filter_mode(c, scheme);
   for (int s = 0; s < 3; ++s) {
     StateRef ref{s == 0 ? Qx : nullptr, nullptr, s == 0 ? 0 : 1};
-    RKRef rr{Qx, nullptr, nullptr};
+    // a hybrid stage keeps the unfiltered state where the filter would leave a
+    // non-physical node (a troubled node, which its C-GBR phases never filter); under the
+    // global switch the last stage is filtered only where it ran all-LAD, and that pass
+    // leaves the copy the guard restores from
+    const bool guard = scheme == LG_SCHEME_HYBRID && fmode >= 0 && (s == 2 || c.filter_all);
+    const bool fused_save = guard && fmode == lg::FILT_GLOBAL && s == 2;
+    RKRef rr{Qx, nullptr, nullptr, fused_save ? 1 : 0};
     enqueue_rhs<R>(L, c, scheme, ref, nullptr, &rr, s);
     if (fmode >= 0 && (s == 2 || c.filter_all)) {   // after the last stage (Alg. 1)
       const StateRef out{s == 2 ? Qx : nullptr, nullptr, s == 2 ? 0 : 1};   // the stage result
-      // a hybrid stage keeps the unfiltered state where the filter would leave a
-      // non-physical node (a troubled node, which its C-GBR phases never filter)
-      const bool guard = scheme == LG_SCHEME_HYBRID;
-      if (guard) lg::launch_filter_save(L, out, fmode);
+      if (guard && !fused_save) lg::launch_filter_save(L, out, fmode);
       for (int d = 0; d < c.ndim; ++d) lg::launch_filter(L, out, d, fmode);
       if (guard) lg::launch_filter_guard(L, out, fmode);
     }

@@ -21,6 +21,7 @@ struct RKRef {
   const double* Un;
   const double* Us;
   double* out;
+  int save_dq;   // the all-LAD pass also copies the stage result into dQ/dt (the filter guard's copy)
 };
 
 // Stage result at interior node idx: out = a U^n + b (U^s + dt L); true if non-physical
