@@ -93,40 +93,36 @@ __global__ void __launch_bounds__(256) k_bc_scalar(const Prob* __restrict__ prob
 }
 
 // ------------------------------------------------------------------ primitives + flags
-template <typename R>
-__device__ __forceinline__ void prim_node(const Prob& P, double rho, double m1, double m2, double m3, double E,
-                                          R& r0, R& r1, R& r2, R& r3, R& r4, double& p) {
-  double u = m1 / rho, v = m2 / rho, w = m3 / rho;
-  p = (P.gamma - 1.0) * (E - 0.5 * rho * (u * u + v * v + w * w));
-  r0 = (R)rho;
-  r1 = (R)u;
-  r2 = (R)v;
-  r3 = (R)w;
-  r4 = (R)p;
-}
-
-// Troubled-cell test (Sec. 5): density or pressure below its threshold (strict); a value
-// that is not a number also counts, so that a broken state is never taken for a smooth one.
-__device__ __forceinline__ bool troubled(double rho, double p, const Prob& P) {
-  return !(rho >= P.rho_thr) || !(p >= P.p_thr);
-}
-
 // PAIR: each lane converts two neighbouring nodes (2t, 2t + 1) with 16-byte state loads and
 // 8-byte (FP32) primitive stores; needs an even node count and 16-byte aligned state
 // (checked on the host).  Otherwise one node per lane.
+// ghosts: 0 converts every node; 1 the ghost nodes only (the previous stage's all-LAD pass
+// wrote the interior primitives and flags with the stage result); 2 the ghost nodes only if
+// that pass ran, i.e. the previous stage of the global hybrid found no troubled node (its
+// any_flag, not yet reset for this stage), every node otherwise.
+__device__ __forceinline__ bool interior_node(const Prob& P, int idx) {
+  const int p[3] = {idx % P.N[0], (idx / P.N[0]) % P.N[1], idx / (P.N[0] * P.N[1])};
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+    if (l < P.ndim && (p[l] < P.g[l] || p[l] >= P.g[l] + P.n[l])) return false;
+  return true;
+}
+
 template <typename R, bool PAIR>
 __global__ void __launch_bounds__(256) k_prim(const Prob* __restrict__ probs, StateRef ref, int want_flags,
-                                              const uint8_t* force) {
+                                              const uint8_t* force, int ghosts) {
   const Prob& P = probs[blockIdx.y];
   const double* Q = ref.state(P);
   R* W = static_cast<R*>(P.W);
   const size_t T = P.total;
+  const bool skip_in = ghosts == 1 || (ghosts == 2 && *P.any_flag == 0);
   if constexpr (PAIR) {
     using D2 = double __attribute__((ext_vector_type(2)));
     using R2 = R __attribute__((ext_vector_type(2)));
     const int npair = (int)(T / 2);
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < npair; t += gridDim.x * blockDim.x) {
       const size_t idx = 2 * (size_t)t;
+      if (skip_in && interior_node(P, (int)idx) && interior_node(P, (int)idx + 1)) continue;
       D2 q[5];
       for (int c = 0; c < 5; ++c) q[c] = *reinterpret_cast<const D2*>(Q + c * T + idx);
       R ra[5], rb[5];
@@ -154,6 +150,7 @@ __global__ void __launch_bounds__(256) k_prim(const Prob* __restrict__ probs, St
     }
   } else {
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < P.total; idx += gridDim.x * blockDim.x) {
+      if (skip_in && interior_node(P, idx)) continue;
       double p;
       R r[5];
       prim_node<R>(P, Q[idx], Q[T + idx], Q[2 * T + idx], Q[3 * T + idx], Q[4 * T + idx], r[0], r[1], r[2], r[3],
@@ -556,14 +553,14 @@ void launch_bc_scalar(const Launch& L, int which, int nf, int d) {
 }
 
 template <typename R>
-void launch_prim(const Launch& L, StateRef ref, int want_flags, const uint8_t* force) {
+void launch_prim(const Launch& L, StateRef ref, int want_flags, const uint8_t* force, int ghosts) {
   // pairs pay off with FP32 primitives (0.80 -> 0.78 ms on the ramp); FP64 runs faster one node per lane
   if (sizeof(R) == 4 && !L.prim_scalar && (unsigned long long)ref.Qx % 16 == 0)
     LG_TIMED(L, KC_PRIM, hipLaunchKernelGGL((k_prim<R, true>), grid_for(L.max_total / 2, L.nprob), dim3(256), 0,
-                                            L.stream, L.probs, ref, want_flags, force));
+                                            L.stream, L.probs, ref, want_flags, force, ghosts));
   else
     LG_TIMED(L, KC_PRIM, hipLaunchKernelGGL((k_prim<R, false>), grid_for(L.max_total, L.nprob), dim3(256), 0,
-                                            L.stream, L.probs, ref, want_flags, force));
+                                            L.stream, L.probs, ref, want_flags, force, ghosts));
 }
 
 void launch_any_flag(const Launch& L, int interior_only) {
@@ -646,8 +643,8 @@ void launch_convert(const double* src, R* dst, size_t n, hipStream_t s) {
 
 template void launch_bc_scalar<float>(const Launch&, int, int, int);
 template void launch_bc_scalar<double>(const Launch&, int, int, int);
-template void launch_prim<float>(const Launch&, StateRef, int, const uint8_t*);
-template void launch_prim<double>(const Launch&, StateRef, int, const uint8_t*);
+template void launch_prim<float>(const Launch&, StateRef, int, const uint8_t*, int);
+template void launch_prim<double>(const Launch&, StateRef, int, const uint8_t*, int);
 template void launch_convert<float>(const double*, float*, size_t, hipStream_t);
 template void launch_convert<double>(const double*, double*, size_t, hipStream_t);
 

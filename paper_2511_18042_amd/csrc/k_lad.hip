@@ -602,7 +602,8 @@ __global__ void __launch_bounds__(256) k_lad_nodeflux(const Prob* __restrict__ p
 // midpoint interpolation), the differences in FP64 in the order xi, eta, zeta; mode 0
 // stores it, mode 1 forms the RK stage a U^n + b (U^s + dt L) in place of the combination
 // kernel (interior nodes; non-physical results are counted), and with rr.save_dq also
-// writes it to dQ/dt, the copy the filter guard restores from.
+// writes it to dQ/dt, the copy the filter guard restores from; with rr.prim_out also its
+// primitives (and troubled flags), which the next stage would otherwise convert.
 template <typename R>
 __device__ __forceinline__ R i4v(R m1, R c0, R p1, R p2) {
   return (R(7) * (c0 + p1) - (m1 + p2)) * R(1.0 / 12.0);
@@ -676,6 +677,14 @@ __global__ void __launch_bounds__(256) k_lad_sweep(const Prob* __restrict__ prob
         v[q] = a * gld<double, O32>(Un, o) + b * (gld<double, O32>(Us, o) + dt * Lq[q]);
         gst<double, O32>(out, o, v[q]);
         if (rr.save_dq) gst<double, O32>(P.dQ, o, v[q]);
+      }
+      if (rr.prim_out) {   // the next stage's primitives (and troubled flags) at this node
+        double pp;
+        R w[5];
+        prim_node<R>(P, v[0], v[1], v[2], v[3], v[4], w[0], w[1], w[2], w[3], w[4], pp);
+        R* W = static_cast<R*>(P.W);
+        for (int q = 0; q < 5; ++q) gst<R, O32>(W, (IX)q * T + (IX)idx, w[q]);
+        if (rr.prim_out == 2) P.f[idx] = (uint8_t)troubled(v[0], pp, P);
       }
       const double rho = v[0];
       const double ke = 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / rho;

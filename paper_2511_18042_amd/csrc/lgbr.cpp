@@ -115,15 +115,16 @@ void enqueue_rhs_c6(const Launch& L, const Cfg& c, StateRef ref, const RKRef* rk
 }
 
 template <typename R>
+// prim_ghosts: the k_prim mode (0 every node; 1 / 2 the ghosts only, see k_basic.hip)
 void enqueue_rhs(const Launch& L, const Cfg& c, int scheme, StateRef ref, const uint8_t* force,
-                 const RKRef* rk = nullptr, int stage = 0) {
+                 const RKRef* rk = nullptr, int stage = 0, int prim_ghosts = 0) {
   if (scheme == LG_SCHEME_LAD && c.lad_c6) {
     enqueue_rhs_c6<R>(L, c, ref, rk, stage);
     return;
   }
   for (int d = 0; d < c.ndim; ++d) lg::launch_bc_cons(L, ref, d);
   const bool hyb = scheme == LG_SCHEME_HYBRID;
-  lg::launch_prim<R>(L, ref, hyb ? 1 : 0, force);
+  lg::launch_prim<R>(L, ref, hyb ? 1 : 0, force, force ? 0 : prim_ghosts);
   int sel, skip_gbr = -1, skip_lad = -1;
   if (scheme == LG_SCHEME_CGBR) {
     sel = lg::SEL_GBR;
@@ -238,8 +239,15 @@ void enqueue_rk3(const Launch& L, const Cfg& c, int scheme, double* Qx, double* 
     // leaves the copy the guard restores from
     const bool guard = scheme == LG_SCHEME_HYBRID && fmode >= 0 && (s == 2 || c.filter_all);
     const bool fused_save = guard && fmode == lg::FILT_GLOBAL && s == 2;
-    RKRef rr{Qx, nullptr, nullptr, fused_save ? 1 : 0};
-    enqueue_rhs<R>(L, c, scheme, ref, nullptr, &rr, s);
+    // the all-LAD pass of stages 1 and 2 also converts its result for the next stage (not
+    // when a filter follows the stage, nor where LAD-C6 forms the stage in its face solves)
+    const bool lad_e4 = scheme == LG_SCHEME_LAD && !c.lad_c6;
+    const bool global = scheme == LG_SCHEME_HYBRID && c.hybrid_mode == LG_HYB_GLOBAL;
+    const bool fuse_prim = !c.filter_all && (lad_e4 || global);
+    const int prim_out = fuse_prim && s < 2 ? (global ? 2 : 1) : 0;
+    const int prim_ghosts = fuse_prim && s > 0 ? (global ? 2 : 1) : 0;
+    RKRef rr{Qx, nullptr, nullptr, fused_save ? 1 : 0, prim_out};
+    enqueue_rhs<R>(L, c, scheme, ref, nullptr, &rr, s, prim_ghosts);
     if (fmode >= 0 && (s == 2 || c.filter_all)) {   // after the last stage (Alg. 1)
       const StateRef out{s == 2 ? Qx : nullptr, nullptr, s == 2 ? 0 : 1};   // the stage result
       if (guard && !fused_save) lg::launch_filter_save(L, out, fmode);

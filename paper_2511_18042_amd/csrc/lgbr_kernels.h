@@ -21,8 +21,29 @@ struct RKRef {
   const double* Un;
   const double* Us;
   double* out;
-  int save_dq;   // the all-LAD pass also copies the stage result into dQ/dt (the filter guard's copy)
+  int save_dq;    // the all-LAD pass also copies the stage result into dQ/dt (the filter guard's copy)
+  int prim_out;   // the all-LAD pass also writes the primitives of the stage result (1), and its
+                  // troubled flags (2), at interior nodes: the next stage converts the ghosts only
 };
+
+// Primitives of one node in the bulk type, p in FP64 (the conversion of k_prim)
+template <typename R>
+__device__ __forceinline__ void prim_node(const Prob& P, double rho, double m1, double m2, double m3, double E,
+                                          R& r0, R& r1, R& r2, R& r3, R& r4, double& p) {
+  double u = m1 / rho, v = m2 / rho, w = m3 / rho;
+  p = (P.gamma - 1.0) * (E - 0.5 * rho * (u * u + v * v + w * w));
+  r0 = (R)rho;
+  r1 = (R)u;
+  r2 = (R)v;
+  r3 = (R)w;
+  r4 = (R)p;
+}
+
+// Troubled-cell test (Sec. 5): density or pressure below its threshold (strict); a value
+// that is not a number also counts, so that a broken state is never taken for a smooth one.
+__device__ __forceinline__ bool troubled(double rho, double p, const Prob& P) {
+  return !(rho >= P.rho_thr) || !(p >= P.p_thr);
+}
 
 // Stage result at interior node idx: out = a U^n + b (U^s + dt L); true if non-physical
 // (rho <= 0, p <= 0 or not finite).  U^s may alias out (each node reads before it writes).
@@ -132,7 +153,8 @@ inline void prof_end(const Launch& L, int k) {
 
 void launch_bc_cons(const Launch& L, StateRef ref, int d);
 template <typename R> void launch_bc_scalar(const Launch& L, int which, int nf, int d);
-template <typename R> void launch_prim(const Launch& L, StateRef ref, int want_flags, const uint8_t* force);
+template <typename R>
+void launch_prim(const Launch& L, StateRef ref, int want_flags, const uint8_t* force, int ghosts = 0);
 void launch_any_flag(const Launch& L, int interior_only);
 void launch_dilate(const Launch& L, int ndim, int radius, int first_src, int final_buf);
 void launch_line_lists(const Launch& L, int ndim);
