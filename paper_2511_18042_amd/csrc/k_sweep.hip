@@ -80,8 +80,8 @@ __global__ void __launch_bounds__(256) k_sensor(const Prob* __restrict__ probs, 
 
 // ------------------------------------------------------------------ pieces of the GBR flux
 template <typename R>
-__host__ __device__ __forceinline__ R mp5(R vm2, R vm1, R v0, R vp1, R vp2, R alpha, R eps) {
-  R vor = (R(2) * vm2 - R(13) * vm1 + R(47) * v0 + R(27) * vp1 - R(3) * vp2) / R(60);
+__device__ __forceinline__ R mp5(R vm2, R vm1, R v0, R vp1, R vp2, R alpha, R eps) {
+  R vor = bdiv(R(2) * vm2 - R(13) * vm1 + R(47) * v0 + R(27) * vp1 - R(3) * vp2, R(60));
   R vmp = v0 + minmod2(vp1 - v0, alpha * (v0 - vm1));
   if ((vor - v0) * (vor - vmp) <= eps) return vor;
   R djm1 = vm2 - R(2) * vm1 + v0;
@@ -105,19 +105,19 @@ struct Frame {
 };
 
 template <typename R>
-__host__ __device__ __forceinline__ void to_char(const Frame<R>& f, R r, R u, R v, R w, R p, R C[5]) {
+__device__ __forceinline__ void to_char(const Frame<R>& f, R r, R u, R v, R w, R p, R C[5]) {
   R un = f.n[0] * u + f.n[1] * v + f.n[2] * w;
-  R pc = p / (R(2) * f.cb * f.cb);
+  R pc = bdiv(p, R(2) * f.cb * f.cb);
   C[0] = -f.k * un + pc;
-  C[1] = r - p / (f.cb * f.cb);
+  C[1] = r - bdiv(p, f.cb * f.cb);
   C[2] = f.t1[0] * u + f.t1[1] * v + f.t1[2] * w;
   C[3] = f.t2[0] * u + f.t2[1] * v + f.t2[2] * w;
   C[4] = f.k * un + pc;
 }
 
 template <typename R>
-__host__ __device__ __forceinline__ void from_char(const Frame<R>& f, const R C[5], R Wo[5]) {
-  R un = (f.cb / f.rb) * (C[4] - C[0]);
+__device__ __forceinline__ void from_char(const Frame<R>& f, const R C[5], R Wo[5]) {
+  R un = bdiv(f.cb, f.rb) * (C[4] - C[0]);
   Wo[0] = C[0] + C[1] + C[4];
   Wo[1] = f.n[0] * un + f.t1[0] * C[2] + f.t2[0] * C[3];
   Wo[2] = f.n[1] * un + f.t1[1] * C[2] + f.t2[1] * C[3];
@@ -126,25 +126,25 @@ __host__ __device__ __forceinline__ void from_char(const Frame<R>& f, const R C[
 }
 
 template <typename R>
-__host__ __device__ __forceinline__ void hllc(const R WL[5], const R WR[5], const R xt[3], R gamma, R F[5]) {
+__device__ __forceinline__ void hllc(const R WL[5], const R WR[5], const R xt[3], R gamma, R F[5]) {
   R xn2 = xt[0] * xt[0] + xt[1] * xt[1] + xt[2] * xt[2];
   R xn = sqrt(xn2);
   R rL = WL[0], pL = WL[4], rR = WR[0], pR = WR[4];
-  R EL = pL / (gamma - R(1)) + R(0.5) * rL * (WL[1] * WL[1] + WL[2] * WL[2] + WL[3] * WL[3]);
-  R ER = pR / (gamma - R(1)) + R(0.5) * rR * (WR[1] * WR[1] + WR[2] * WR[2] + WR[3] * WR[3]);
-  R HL = (EL + pL) / rL, HR = (ER + pR) / rR;
-  R cL = sqrt(gamma * pL / rL), cR = sqrt(gamma * pR / rR);
+  R EL = bdiv(pL, gamma - R(1)) + R(0.5) * rL * (WL[1] * WL[1] + WL[2] * WL[2] + WL[3] * WL[3]);
+  R ER = bdiv(pR, gamma - R(1)) + R(0.5) * rR * (WR[1] * WR[1] + WR[2] * WR[2] + WR[3] * WR[3]);
+  R HL = bdiv(EL + pL, rL), HR = bdiv(ER + pR, rR);
+  R cL = sqrt(bdiv(gamma * pL, rL)), cR = sqrt(bdiv(gamma * pR, rR));
   R UL = xt[0] * WL[1] + xt[1] * WL[2] + xt[2] * WL[3];
   R UR = xt[0] * WR[1] + xt[1] * WR[2] + xt[2] * WR[3];
-  R Rr = sqrt(rR / rL);
+  R Rr = sqrt(bdiv(rR, rL));
   R ub[3];
-  for (int m = 0; m < 3; ++m) ub[m] = (WL[1 + m] + Rr * WR[1 + m]) / (R(1) + Rr);
-  R Hb = (HL + Rr * HR) / (R(1) + Rr);
+  for (int m = 0; m < 3; ++m) ub[m] = bdiv(WL[1 + m] + Rr * WR[1 + m], R(1) + Rr);
+  R Hb = bdiv(HL + Rr * HR, R(1) + Rr);
   R cb = sqrt((gamma - R(1)) * (Hb - R(0.5) * (ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2])));
   R Ub = xt[0] * ub[0] + xt[1] * ub[1] + xt[2] * ub[2];
   R SL = fmin(UL - cL * xn, Ub - cb * xn);
   R SR = fmax(UR + cR * xn, Ub + cb * xn);
-  R Ss = (rR * UR * (SR - UR) - rL * UL * (SL - UL) + (pL - pR) * xn2) / (rR * (SR - UR) - rL * (SL - UL));
+  R Ss = bdiv(rR * UR * (SR - UR) - rL * UL * (SL - UL) + (pL - pR) * xn2, rR * (SR - UR) - rL * (SL - UL));
   // pick the side whose flux (or star flux) is needed:
   // S_L >= 0 -> F_L; S* >= 0 -> F*_L; S_R > 0 -> F*_R; else F_R
   bool left = (SL >= R(0)) || (Ss >= R(0));
@@ -157,11 +157,11 @@ __host__ __device__ __forceinline__ void hllc(const R WL[5], const R WR[5], cons
   F[4] = (E + p) * U;
   bool star = left ? !(SL >= R(0)) : (SR > R(0));
   if (star) {
-    R fac = rho * (S - U) / (S - Ss);
+    R fac = bdiv(rho * (S - U), S - Ss);
     R Qs[5], Qk[5];
     Qs[0] = fac;
-    for (int m = 0; m < 3; ++m) Qs[1 + m] = fac * (Wk[1 + m] + xt[m] * (Ss - U) / xn2);
-    Qs[4] = fac * (E / rho + (Ss - U) * (Ss / xn2 + p / (rho * (S - U))));
+    for (int m = 0; m < 3; ++m) Qs[1 + m] = fac * (Wk[1 + m] + bdiv(xt[m] * (Ss - U), xn2));
+    Qs[4] = fac * (bdiv(E, rho) + (Ss - U) * (bdiv(Ss, xn2) + bdiv(p, rho * (S - U))));
     Qk[0] = rho;
     for (int m = 0; m < 3; ++m) Qk[1 + m] = rho * Wk[1 + m];
     Qk[4] = E;
@@ -218,16 +218,16 @@ __host__ __device__ __forceinline__ void gbr_fill(const Prob& P, int d, int idx,
 
 // C-GBR convective flux at the interface between the window's nodes 0 and 1
 template <typename R, bool C3V = false>
-__host__ __device__ __forceinline__ void gbr_flux_win(const Prob& P, const GbrWin<R>& wn, R F[5]) {
+__device__ __forceinline__ void gbr_flux_win(const Prob& P, const GbrWin<R>& wn, R F[5]) {
   // interface metrics (I4 of node metrics)
   R xt[3];
   for (int c = 0; c < 3; ++c) {
     R a0 = wn.m[0][c], a1 = wn.m[1][c], a2 = wn.m[2][c], a3 = wn.m[3][c];
-    xt[c] = (R(7) * (a1 + a2) - (a0 + a3)) / R(12);
+    xt[c] = bdiv(R(7) * (a1 + a2) - (a0 + a3), R(12));
   }
   Frame<R> fr;
   R xn = sqrt(xt[0] * xt[0] + xt[1] * xt[1] + xt[2] * xt[2]);
-  for (int c = 0; c < 3; ++c) fr.n[c] = xt[c] / xn;
+  for (int c = 0; c < 3; ++c) fr.n[c] = bdiv(xt[c], xn);
   {
     R a0 = fabs(fr.n[0]), a1 = fabs(fr.n[1]), a2 = fabs(fr.n[2]);
     int m = (a0 <= a1 && a0 <= a2) ? 0 : (a1 <= a2 ? 1 : 2);
@@ -236,7 +236,7 @@ __host__ __device__ __forceinline__ void gbr_flux_win(const Prob& P, const GbrWi
     else if (m == 1) { t[0] = -fr.n[2]; t[1] = R(0); t[2] = fr.n[0]; }
     else { t[0] = fr.n[1]; t[1] = -fr.n[0]; t[2] = R(0); }
     R tn = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
-    for (int c = 0; c < 3; ++c) fr.t1[c] = t[c] / tn;
+    for (int c = 0; c < 3; ++c) fr.t1[c] = bdiv(t[c], tn);
     fr.t2[0] = fr.n[1] * fr.t1[2] - fr.n[2] * fr.t1[1];
     fr.t2[1] = fr.n[2] * fr.t1[0] - fr.n[0] * fr.t1[2];
     fr.t2[2] = fr.n[0] * fr.t1[1] - fr.n[1] * fr.t1[0];
@@ -247,7 +247,7 @@ __host__ __device__ __forceinline__ void gbr_flux_win(const Prob& P, const GbrWi
     // enthalpy weighted by sqrt(rho); sound speed from them)
     const R r0 = wn.w[2][0], r1 = wn.w[3][0];
     const R sl = sqrt(r0), sr = sqrt(r1);
-    const R wl = sl / (sl + sr), wr = sr / (sl + sr);
+    const R wl = bdiv(sl, sl + sr), wr = bdiv(sr, sl + sr);
     R q0 = R(0), q1 = R(0), ub2 = R(0);
     for (int m = 1; m <= 3; ++m) {
       const R a = wn.w[2][m], b = wn.w[3][m];
@@ -256,14 +256,14 @@ __host__ __device__ __forceinline__ void gbr_flux_win(const Prob& P, const GbrWi
       const R ub = wl * a + wr * b;
       ub2 += ub * ub;
     }
-    const R gg = gamma / (gamma - R(1));
-    const R H0 = gg * wn.w[2][4] / r0 + R(0.5) * q0;
-    const R H1 = gg * wn.w[3][4] / r1 + R(0.5) * q1;
+    const R gg = bdiv(gamma, gamma - R(1));
+    const R H0 = bdiv(gg * wn.w[2][4], r0) + R(0.5) * q0;
+    const R H1 = bdiv(gg * wn.w[3][4], r1) + R(0.5) * q1;
     const R Hb = wl * H0 + wr * H1;
     fr.rb = sl * sr;
     fr.cb = sqrt((gamma - R(1)) * (Hb - R(0.5) * ub2));
   }
-  fr.k = fr.rb / (R(2) * fr.cb);
+  fr.k = bdiv(fr.rb, R(2) * fr.cb);
 
   R C[6][5], D[4][5];
   for (int o = 0; o < 6; ++o) to_char(fr, wn.w[o][0], wn.w[o][1], wn.w[o][2], wn.w[o][3], wn.w[o][4], C[o]);
@@ -286,8 +286,8 @@ __host__ __device__ __forceinline__ void gbr_flux_win(const Prob& P, const GbrWi
     R dm1 = D[0][b], d0 = D[1][b], d1 = D[2][b], d2 = D[3][b];
     R c2i = R(2) * (c1 - R(2) * c0 + cm1) - R(0.5) * (d1 - dm1);
     R c2p = R(2) * (c2 - R(2) * c1 + c0) - R(0.5) * (d2 - d0);
-    R Llin = c0 + R(0.5) * d0 + c2i / R(12);
-    R Rlin = c1 - R(0.5) * d1 + c2p / R(12);
+    R Llin = c0 + R(0.5) * d0 + bdiv(c2i, R(12));
+    R Rlin = c1 - R(0.5) * d1 + bdiv(c2p, R(12));
     R cc = R(0.5) * (Llin + Rlin);
     bool useL, useR;  // use MP5?
     R Lalt, Ralt;     // value otherwise
@@ -322,7 +322,7 @@ __host__ __device__ __forceinline__ void gbr_flux_win(const Prob& P, const GbrWi
 // C-GBR convective flux at the interface between node idx and idx + s (direction d;
 // mi = met_idx(P, idx))
 template <typename R, bool C3V = false>
-__host__ __device__ __forceinline__ void gbr_flux(const Prob& P, int d, int idx, int mi, R F[5]) {
+__device__ __forceinline__ void gbr_flux(const Prob& P, int d, int idx, int mi, R F[5]) {
   GbrWin<R> wn;
   gbr_fill<R, C3V>(P, d, idx, mi, wn);
   gbr_flux_win<R, C3V>(P, wn, F);

@@ -282,6 +282,18 @@ __device__ __forceinline__ double rcp<double>(double x) {
   return 1.0 / x;
 }
 
+// a / b in the bulk type of the C-GBR flux: FP64 divides (correctly rounded); FP32
+// multiplies by the hardware reciprocal (within 1 ulp, one instruction against the ten of
+// a correctly rounded division), which the FP32 bulk's own accuracy allows
+template <typename R>
+__device__ __forceinline__ R bdiv(R a, R b) {
+  return a / b;
+}
+template <>
+__device__ __forceinline__ float bdiv<float>(float a, float b) {
+  return a * __builtin_amdgcn_rcpf(b);
+}
+
 template <typename R>
 __host__ __device__ __forceinline__ R sgn(R a) {
   return a > R(0) ? R(1) : (a < R(0) ? R(-1) : R(0));
