@@ -1740,9 +1740,9 @@ void launch_grad_c4_part(const Launch& L, StateRef ref, int skip_if_any, int den
   const int nw = 4 * per_wave <= 60 * 1024 ? 4 : 2;
   const long long items = 5 * L.lines[0];
   const unsigned blocks = (unsigned)std::max<long long>(1, std::min<long long>((items + nw - 1) / nw, 4096));
-  // register arrays sized to the longest segment: short ones when every line has at most
-  // 1088 unknowns (segments of at most 17)
-  if (nmax + 8 <= 64 * (FPART_LSHORT - 1))
+  // register arrays sized to the longest segment: short ones when every line has fewer
+  // than 64 * 17 unknowns (the n + 8 between its end rows; segments of at most 17)
+  if ((nmax + 8) / 64 + 1 <= FPART_LSHORT)
     LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL((k_grad_c4_part<R, FPART_LSHORT>), dim3(blocks, L.nprob),
                                                dim3(64 * nw), nw * per_wave, L.stream, L.probs, ref, (int)nmax,
                                                skip_if_any, dense_only, L.tile_mask));
