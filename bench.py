@@ -73,11 +73,14 @@ def log(msg):
     print('[bench] ' + msg, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kclass, nodes, rs, ndim, gbr_frac, viscous, curv, planar=False):
+def algorithmic_bytes(kclass, nodes, rs, ndim, gbr_frac, viscous, curv, planar=False, global_hybrid=False):
     """Minimum bytes one launch of a kernel class moves (every input read once, every
     output written once) for ``nodes`` interior nodes; rs = bytes of the bulk real type,
     curv: node metrics (9 components + J) are fields rather than constants; planar: they
-    (and the LAD grid factors) are stored for one plane only, so they add nothing per node."""
+    (and the LAD grid factors) are stored for one plane only, so they add nothing per node.
+    global_hybrid: the all-LAD pass of an RK3 step of the global hybrid also writes the
+    primitives and troubled flags of its result in stages 1 and 2, and the filter guard's
+    FP64 copy of it in stage 3 (the mean over the three launches)."""
     vis = 5 * rs if viscous else 0
     per_node_geom = curv and not planar
     met = 10 * rs if per_node_geom else 0
@@ -95,6 +98,8 @@ def algorithmic_bytes(kclass, nodes, rs, ndim, gbr_frac, viscous, curv, planar=F
         per = 5 * rs + 3 * rs + met + 5 * ndim * rs          # W, coefficients, metrics -> F_l
     elif kclass == 'lad_sweep':
         per = 5 * ndim * rs + (8 if per_node_geom else 0) + 120   # F_l, J, U^n, U^s -> stage result
+        if global_hybrid:
+            per += (2 * (5 * rs + 1) + 40) / 3.0
     elif kclass == 'grad_e6':
         per = 10 * rs
     elif kclass == 'grad_c4':
@@ -197,7 +202,7 @@ def dominant_class(ctx, scheme, Q, t, steps=6):
 EXECUTED_FRACTION = 0.25   # a launch shorter than this share of its class's longest one returned at once
 
 
-def live_roofline(kern, dom, cells, ndim, gbr_frac, viscous, curv, planar, traffic_file=None):
+def live_roofline(kern, dom, cells, ndim, gbr_frac, viscous, curv, planar, traffic_file=None, global_hybrid=False):
     """Roofline of the dominant class from its live per-launch HIP-event times in the timed
     steps: algorithmic bytes per launch over the average duration of the launches that did
     the work.  Launches the device-side hybrid switch turned into immediate returns (a few
@@ -207,7 +212,7 @@ def live_roofline(kern, dom, cells, ndim, gbr_frac, viscous, curv, planar, traff
     top = max(dur)
     run = [ms for ms in dur if ms >= EXECUTED_FRACTION * top]
     dom_avg = sum(run) / len(run)
-    algo = algorithmic_bytes(dom, cells, 4, ndim, gbr_frac, viscous, curv, planar)
+    algo = algorithmic_bytes(dom, cells, 4, ndim, gbr_frac, viscous, curv, planar, global_hybrid)
     achieved = algo / (dom_avg * 1e-3) / 1e9
     roof = {'bound': 'hbm', 'kernel': dom, 'achieved': round(achieved, 1), 'peak': HBM_PEAK_GBS, 'unit': 'GB/s',
             'frac': round(achieved / HBM_PEAK_GBS, 4), 'avg_launch_ms': round(dom_avg, 5), 'launches': len(run),
@@ -452,7 +457,7 @@ def ramp3d(args, variants, cpu):
     t = torch.zeros(1, dtype=torch.float64, device='cuda')
     ms, kern, bad, sw, dom, brk, n_gbr = mix_window(head, forced, Q, t, args.warmup, args.steps)
     planar = head.metrics_planar()
-    roof = live_roofline(kern, dom, cells, 3, 1.0, True, True, planar, traffic_file=traffic)
+    roof = live_roofline(kern, dom, cells, 3, 1.0, True, True, planar, traffic_file=traffic, global_hybrid=True)
     res.update({'value': mcell(cells, ms), 'ms_per_step': round(ms, 4), 'nonphysical_nodes': bad,
                 'steps_before_window': args.warmup + 6, 'sim_time_end': round(float(t.item()), 6),
                 'stage_mix': {'forced_cgbr_steps': n_gbr, 'steps': args.steps, 'hybrid_stages': sw[0],
@@ -744,7 +749,7 @@ def triple_point(args, variants, cpu):
     dom, brk = dominant_class(head, 'hybrid', Q, t)
     ms, kern, bad, Q, t, sw = R.steps(head, 'hybrid', None, W=0, prof_class=dom, Q=Q, t=t)
     share = sw[1] / max(sw[0], 1)
-    roof = live_roofline(kern, dom, cells, 2, 1.0, False, False, False)
+    roof = live_roofline(kern, dom, cells, 2, 1.0, False, False, False, global_hybrid=True)
     res.update({'value': mcell(cells, ms), 'ms_per_step': round(ms, 4), 'nonphysical_nodes': bad,
                 'sim_time_end': round(float(t.item()), 6),
                 'stages': {'hybrid': sw[0], 'troubled_cgbr': sw[1], 'lad_share': round(1 - share, 4)},
