@@ -195,7 +195,9 @@ lg_status lad_filter(lg_ctx* ctx, double* Q);
  * LAD is LAD-E4). */
 lg_status hybrid_rhs(lg_ctx* ctx, double* Q, double* dQdt, const uint8_t* flags_in, uint8_t* flags_out);
 
-/* One SSP-RK3 step of scheme LG_SCHEME_* on Q in place.  The step size is
+/* One time step of scheme LG_SCHEME_* on Q in place: the three-stage SSP-RK3 of Sec. 2.3,
+ * or the classic four-stage RK4 of Sec. 2.1 when time_scheme = LG_RK4 (LG_SCHEME_LAD only;
+ * the filter then follows the fourth stage).  The step size is
  * dt = cfl / max_i sum_l (|xi_l . u| + c |xi_l|) from Q, clipped so that t does not
  * pass t_end; t_inout is a device double that is advanced by dt.  dt stays on the
  * device (no host synchronisation).  Unless filter_alpha = 0.5 the step ends with the
@@ -204,8 +206,10 @@ lg_status hybrid_rhs(lg_ctx* ctx, double* Q, double* dQdt, const uint8_t* flags_
  * global hybrid switch the field is filtered when the third stage found no troubled
  * interior node and left alone when it ran C-GBR (Alg. 2 has no filter); under the
  * per-cell switch the lines are filtered whole and the nodes in the dilated troubled set
- * keep their unfiltered values.  The decision is taken on the device from the stage's
- * troubled-cell reduction.  With filter_every_stage the same follows every stage. */
+ * keep their unfiltered values.  In the hybrid, a node whose filtered density or pressure
+ * is not positive (or not finite) keeps its unfiltered state.  The decision is taken on the
+ * device from the stage's troubled-cell reduction.  With filter_every_stage the same
+ * follows every stage. */
 lg_status rk3_step(lg_ctx* ctx, int scheme, double* Q, double t_end, double* t_inout);
 
 /* One RK3 stage from given states (for per-stage checks):
