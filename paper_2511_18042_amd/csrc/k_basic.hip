@@ -226,20 +226,21 @@ __global__ void __launch_bounds__(256) k_gbr_queue(const Prob* __restrict__ prob
     E[l] = P.n[l] + (l == d ? 1 : 0);
     o[l] = P.g[l] - (l == d ? 1 : 0);
   }
-  const long long tot = (long long)E[0] * E[1] * E[2];
-  const long long c0 = (long long)blockIdx.x * QCHUNK;
+  // interface counts stay below the node count, which int node indices already bound
+  const int tot = E[0] * E[1] * E[2];
+  const int c0 = (int)blockIdx.x * QCHUNK;
   if (c0 >= tot) return;
   const int s = P.s[d];
   const int lane = threadIdx.x & 63;
   if (threadIdx.x == 0) n_loc = 0;
   __syncthreads();
   for (int r = 0; r < QCHUNK; r += 256) {
-    const long long t = c0 + r + threadIdx.x;
+    const int t = c0 + r + (int)threadIdx.x;
     int idx = 0, flag = 0;
     if (t < tot) {
-      const int i = (int)(t % E[0]) + o[0];
-      const int j = (int)((t / E[0]) % E[1]) + o[1];
-      const int k = (int)(t / ((long long)E[0] * E[1])) + o[2];
+      const int i = t % E[0] + o[0];
+      const int j = (t / E[0]) % E[1] + o[1];
+      const int k = t / (E[0] * E[1]) + o[2];
       idx = pos_to_idx(P, i, j, k);
       flag = (P.ft[idx] | P.ft[idx + s]) != 0;
     }
@@ -263,13 +264,15 @@ __device__ __forceinline__ uint8_t* flag_buf(const Prob& P, int b) {
   return b == 0 ? P.f : (b == 1 ? P.ftmp : (b == 2 ? P.ft : P.fg));
 }
 
+// RR > 0: the radius is RR, and only its window is read; RR = 0: any radius up to 7.
+template <int RR>
 __global__ void __launch_bounds__(256) k_dilate(const Prob* __restrict__ probs, int d, int src, int dst, int radius) {
   const Prob& P = probs[blockIdx.y];
   if (d >= P.ndim || *P.any_flag == 0) return;   // nothing flagged: consumers check any_flag
   const uint8_t* in = flag_buf(P, src);
   uint8_t* out = flag_buf(P, dst);
-  const int r = radius, Nd = P.N[d], sd = P.s[d];
-  constexpr int RMAX = 7;
+  const int r = RR > 0 ? RR : radius, Nd = P.N[d], sd = P.s[d];
+  constexpr int RMAX = RR > 0 ? RR : 7;
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < P.total; idx += gridDim.x * blockDim.x) {
     const int c = (idx / sd) % Nd;
     uint8_t v[2 * RMAX + 1];
@@ -575,8 +578,12 @@ void launch_dilate(const Launch& L, int ndim, int radius, int first_src, int fin
   int src = first_src;
   for (int d = 0; d < ndim; ++d) {
     int dst = ((ndim - 1 - d) % 2 == 0) ? final_buf : 1;
-    LG_TIMED(L, KC_FLAGS, hipLaunchKernelGGL(k_dilate, grid_for(L.max_total, L.nprob), dim3(256), 0, L.stream,
-                                             L.probs, d, src, dst, radius));
+    if (radius == 3)   // the hybrid's radius: a window of seven loads instead of fifteen
+      LG_TIMED(L, KC_FLAGS, hipLaunchKernelGGL(k_dilate<3>, grid_for(L.max_total, L.nprob), dim3(256), 0, L.stream,
+                                               L.probs, d, src, dst, radius));
+    else
+      LG_TIMED(L, KC_FLAGS, hipLaunchKernelGGL(k_dilate<0>, grid_for(L.max_total, L.nprob), dim3(256), 0, L.stream,
+                                               L.probs, d, src, dst, radius));
     src = dst;
   }
 }
