@@ -1059,7 +1059,7 @@ def main():
         profile_summary(args)
         return
     if args.gpus != 1:
-        print('bench.py: this build measures one GPU only (one process, one MI355X); '
+        print('bench.py: the benchmark runs on one GPU only (one process, one MI355X); '
               '--gpus %d is not supported' % args.gpus, file=sys.stderr)
         sys.exit(2)
     names = list(WORKLOADS) if args.workload == 'all' else [args.workload]
