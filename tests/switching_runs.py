@@ -7,8 +7,9 @@ on the GPU, for the two cases the paper reports:
   * the M2.9 ramp stand-in (1024 x 384 x 128, MIG4 / LAD-E4, troubled where p < p_inf / 2,
     FP32 bulk) for a fixed number of steps, with the adiabatic wall of the headline workload,
     with the isothermal wall at 1.14 T_aw, and with that wall and the digital-filter inflow
-    (a new time-correlated plane before every step, cases.ramp_df_inflow) (paper: LAD 82.4 %
-    of one flow-through, 1.67x faster than MEG6 C-GBR).
+    (a new time-correlated plane before every step, cases.ramp_df_inflow), and at half the
+    resolution in every direction for one whole flow-through (paper: LAD 82.4 % of one
+    flow-through, 1.67x faster than MEG6 C-GBR).
 
 Every RK3 step reads the context's switching record (lg_switch_stats: hybrid stages and
 those with a troubled node).  A step counts as LAD or C-GBR by its stages; a step whose
@@ -38,9 +39,11 @@ def _triple_point():
     return c, gas, grid, opts, None, None, None
 
 
-def _ramp(wall, df=False):
+def _ramp(wall, df=False, half=False, precision='mixed'):
     import torch
-    c = cases.ramp3d(wall=wall)
+    # half: every spacing doubled (512 x 192 x 64, first cell at 0.004 delta), run for one
+    # flow-through (t = Lx / U = 26.2) instead of a fixed number of steps
+    c = cases.ramp3d(512, 192, 64, y1=0.004, wall=wall) if half else cases.ramp3d(wall=wall)
     inflow = cases.ramp_df_inflow(c) if df else None
     e = c.extra
     gas = lgbr.make_gas(gamma=1.4, Re=e['Re'], Pr=e['Pr'], Mref=e['Mref'], suth=e['suth'], viscous=True)
@@ -49,9 +52,9 @@ def _ramp(wall, df=False):
     metrics = torch.zeros((10,) + tuple(c.shape), dtype=torch.float64, device='cuda')
     lgbr.metrics_from_coords(grid, coords, metrics)
     c.coords = None
-    opts = dict(grad='C4', precision='mixed', rho_thr=-1.0, p_thr=e['p_thr'])
+    opts = dict(grad='C4', precision=precision, rho_thr=-1.0, p_thr=e['p_thr'])
     c.extra['df_inflow'] = inflow
-    return c, gas, grid, opts, metrics, coords, 1e30
+    return c, gas, grid, opts, metrics, coords, 26.2 if half else 1e30
 
 
 CASES = {
@@ -60,6 +63,10 @@ CASES = {
     'ramp_isothermal': (lambda: _ramp('isothermal'), 'MIG4 / LAD-E4, FP32 bulk, wall at 1.14 T_aw', 82.4),
     'ramp_isothermal_df': (lambda: _ramp('isothermal', df=True),
                            'MIG4 / LAD-E4, FP32 bulk, wall at 1.14 T_aw, digital-filter inflow', 82.4),
+    'ramp_half_flowthrough': (lambda: _ramp('adiabatic', half=True),
+                              'MIG4 / LAD-E4, FP32 bulk, adiabatic wall, 512 x 192 x 64, one flow-through', 82.4),
+    'ramp_half_flowthrough_fp64': (lambda: _ramp('adiabatic', half=True, precision='fp64'),
+                                   'MIG4 / LAD-E4, FP64, adiabatic wall, 512 x 192 x 64, one flow-through', 82.4),
 }
 
 
@@ -81,7 +88,7 @@ def run(name, wall=120.0, ramp_steps=2000):
     build, desc, paper_lad = CASES[name]
     c, gas, grid, o, metrics, coords, t_end = build()
     t_end = c.t_end if t_end is None else t_end
-    max_steps = ramp_steps if name.startswith('ramp') else 10 ** 7
+    max_steps = ramp_steps if name.startswith('ramp') and 'flowthrough' not in name else 10 ** 7
     ctx = lgbr.Context(grid, gas, lgbr.make_opts(cfl=0.2, hybrid_mode='global', **o), metrics, coords)
     Q0 = torch.from_numpy(np.ascontiguousarray(c.Q)).cuda()
     Q = Q0.clone()
