@@ -348,7 +348,7 @@ __device__ __forceinline__ bool face_emit_q(const Prob& P, const FaceOut& o, dou
 template <typename R, int NQ>
 __global__ void __launch_bounds__(256) k_c6_faces(const Prob* __restrict__ probs, FaceOut o, int d, int mask) {
   const Prob& P = probs[blockIdx.y];
-  if (d >= P.ndim || tile_use(P, d, TK_FACES, mask) || c6_face_pcr(P, d)) return;
+  if (d >= P.ndim || tile_use(P, d, TK_FACES, mask) || c6_face_pcr(P, d) || c6f_part_use(P, d, mask)) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int nl = interior_lines(P, d);
   if (t >= (5 / NQ) * nl) return;
@@ -457,7 +457,7 @@ __global__ void __launch_bounds__(CPCR_THREADS) __attribute__((amdgpu_waves_per_
                                                       int mask) {
   extern __shared__ double lds[];
   const Prob& P = probs[blockIdx.y];
-  if (d >= P.ndim || tile_use(P, d, TK_FACES, mask) || !c6_face_pcr(P, d)) return;
+  if (d >= P.ndim || tile_use(P, d, TK_FACES, mask) || !c6_face_pcr(P, d) || c6f_part_use(P, d, mask)) return;
   const int nlines = interior_lines(P, d);
   const bool periodic = P.bc[d][0] == BC_PERIODIC;
   const int g = P.g[d], n = P.n[d], sd = P.s[d];
@@ -1283,6 +1283,153 @@ __global__ void __launch_bounds__(64 * FPART_WAVES) k_grad_c4_part(const Prob* _
   }
 }
 
+// ------------------------------------------------------------------ C6 faces, partition method
+// LAD-C6 interface fluxes along xi (Sec. 3) on bounded lines of 129 to 2049 nodes: the
+// n - 1 interior faces form the [1/3, 1, 1/3] system with the two I4 boundary faces on the
+// right-hand side (the system k_c6_faces_pcr reduces), solved as k_filter_part solves the
+// filter's with a = 1/3: one wave per (line, flux component), the line's node fluxes staged
+// in LDS, segments per lane joined by two wave-wide scans.  The faces go back to LDS and
+// each node's derivative -J (F_{i+1/2} - F_{i-1/2}) to dQ/dt.  Xi is the first of two or
+// three directions here, so the derivative is written, not accumulated, and never forms
+// the RK stage (as in k_c6_faces_pcr).
+template <typename R, int LM>
+__global__ void __launch_bounds__(64 * FPART_WAVES) k_c6_faces_part(const Prob* __restrict__ probs, StateRef ref,
+                                                                    int nmax, int mask) {
+  extern __shared__ double dyn[];   // per wave: the staged node fluxes [nmax + 4]
+  __shared__ double tcp[FPART_LMAX], tinv[FPART_LMAX];
+  __shared__ double tu[2][FPART_LMAX], tv[2][FPART_LMAX];   // segment lengths base and base + 1
+  __shared__ double tda[64], tGa[64], tGb[64];
+  const Prob& P = probs[blockIdx.y];
+  if (!c6f_part_use(P, 0, mask) || P.n[0] > nmax) return;
+  const int n = P.n[0], g = P.g[0], M = n - 1;
+  const int nseg = min(64, M / 2);
+  const int base = M / nseg, extra = M % nseg;   // the first `extra` segments have base + 1
+  if (base + 1 > LM) return;   // segments longer than the register arrays
+  const double al = C6_ALPHA;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  // segment factors, the responses u = T^{-1} e_1 and v = T^{-1} e_L, and the
+  // data-independent elimination factors of the joint unknowns (as in k_filter_part)
+  if (threadIdx.x == 0) {
+    double c = 0.0;
+    for (int i = 0; i < base + 1; ++i) {
+      const double den = 1.0 - (i > 0 ? al * c : 0.0);
+      tinv[i] = 1.0 / den;
+      c = al / den;
+      tcp[i] = c;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {   // threads 0 / 1: u for base / base + 1; 2 / 3: v
+    const int which = threadIdx.x & 1, L = base + which;
+    const bool is_u = threadIdx.x < 2;
+    double* out = is_u ? tu[which] : tv[which];
+    double prev = 0.0;
+    for (int i = 0; i < L; ++i) {
+      const double rhs = is_u ? (i == 0 ? 1.0 : 0.0) : (i == L - 1 ? 1.0 : 0.0);
+      prev = (rhs - (i > 0 ? al * prev : 0.0)) * tinv[i];
+      out[i] = prev;
+    }
+    double y = out[L - 1];
+    for (int i = L - 2; i >= 0; --i) {
+      y = out[i] - tcp[i] * y;
+      out[i] = y;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double Gbp = 0.0;
+    for (int sg = 0; sg < nseg; ++sg) {
+      const int lw = sg < extra ? 1 : 0, Ls = base + lw;
+      const double da = 1.0 - al * tu[lw][0] * Gbp;
+      const double Ga = al * tv[lw][0] / da;
+      tda[sg] = da;
+      tGa[sg] = Ga;
+      tGb[sg] = al * tv[lw][Ls - 1] + al * tu[lw][Ls - 1] * Gbp * Ga;
+      Gbp = tGb[sg];
+    }
+  }
+  __syncthreads();
+  double* f = dyn + (size_t)w * fpart_lds_slots(nmax);
+  auto F = [f](int p) -> double& { return f[p + (p >> 4)]; };   // p = node position + 2
+  const int nlines = interior_lines(P, 0);
+  const size_t T = P.total;
+  const R* FL = static_cast<const R*>(P.FL[0]);
+  double* dQ = ref.deriv(P);
+  const bool act = lane < nseg;
+  const int L = base + (lane < extra ? 1 : 0);
+  const int j0 = lane * base + min(lane, extra);   // first face of this lane's segment
+  const int wl = lane < extra ? 1 : 0;             // which u / v table
+  const double u1 = act ? tu[wl][0] : 0.0, uL = act ? tu[wl][L - 1] : 0.0;
+  const double da = act ? tda[lane] : 1.0, Ga = act ? tGa[lane] : 0.0, Gb = act ? tGb[lane] : 0.0;
+  const double Gbm = act && lane > 0 ? tGb[lane - 1] : 0.0;
+  for (int item = blockIdx.x * nw + w; item < 5 * nlines; item += gridDim.x * nw) {
+    const int line = item / 5, q = item % 5;
+    const size_t lb = interior_line_base(P, 0, line);
+    const R* Fq = FL + (size_t)q * T + lb;
+    for (int p = lane; p < n + 4; p += 64) F(p) = (double)Fq[g - 2 + p];
+    wave_lds_sync();
+    // boundary faces (I4 of the node fluxes)
+    const double lo = (7.0 * (F(1) + F(2)) - (F(0) + F(3))) / 12.0;
+    const double hi = (7.0 * (F(n + 1) + F(n + 2)) - (F(n) + F(n + 3))) / 12.0;
+    double y[LM];
+    double ya = 0.0, yb = 0.0;
+    if (act) {
+      // face k between nodes k and k + 1: C6 interpolation of the nodes k - 1 .. k + 2
+      double fm1 = F(j0 + 1), f0 = F(j0 + 2), f1 = F(j0 + 3);
+      double prev = 0.0;
+#pragma unroll
+      for (int i = 0; i < LM; ++i) {
+        if (i < L) {
+          const int k = j0 + i;
+          const double f2 = F(k + 4);
+          double r = C6F_A * (f0 + f1) + C6F_B * (fm1 + f2);
+          if (k == 0) r = r - al * lo;
+          if (k == M - 1) r = r - al * hi;
+          prev = (r - (i > 0 ? al * prev : 0.0)) * tinv[i];
+          y[i] = prev;
+          fm1 = f0;
+          f0 = f1;
+          f1 = f2;
+        }
+      }
+      yb = prev;
+      double v = prev;
+#pragma unroll
+      for (int i = LM - 2; i >= 0; --i) {
+        if (i < L - 1) {
+          v = y[i] - tcp[i] * v;
+          y[i] = v;
+        }
+      }
+      ya = y[0];
+    }
+    const double gbv = scan_up(act ? -al * uL / da : 0.0, act ? yb + al * uL * Gbm * ya / da : 0.0, lane);
+    double gbm = __shfl_up(gbv, 1);
+    if (lane == 0) gbm = 0.0;
+    const double gav = act ? (ya - al * u1 * gbm) / da : 0.0;
+    const double A = scan_down(act ? -Ga : 0.0, gav, lane);
+    double Ap = __shfl_down(A, 1);
+    if (lane + 1 >= nseg) Ap = 0.0;
+    const double B = gbv - Gb * Ap;
+    double Bm = __shfl_up(B, 1);
+    if (lane == 0) Bm = 0.0;
+    wave_lds_sync();   // every lane has read its window before the faces overwrite it
+    if (act) {
+#pragma unroll
+      for (int i = 0; i < LM; ++i)
+        if (i < L) F(j0 + i) = y[i] - al * tu[wl][i] * Bm - al * tv[wl][i] * Ap;   // face j0 + i
+    }
+    wave_lds_sync();
+    for (int i = lane; i < n; i += 64) {
+      const double fp = i < M ? F(i) : hi;
+      const double fm = i > 0 ? F(i - 1) : lo;
+      const size_t idx = lb + (size_t)(g + i);
+      dQ[(size_t)q * T + idx] = -met64(P, 9, (int)idx) * (fp - fm);
+    }
+    wave_lds_sync();   // the next item's staging overwrites f
+  }
+}
+
 // ------------------------------------------------------------------ line tiles
 // One workgroup holds all five variables of TX neighbouring lines of one direction in LDS
 // (TX * 5 * positions <= TILE_ELEMS doubles), forms the right-hand sides there, reduces
@@ -1649,6 +1796,22 @@ void launch_c6_faces(const Launch& L, StateRef ref, int d, int accumulate, const
                      double b) {
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   const SysLaunch sl = sys_launch(L, TK_FACES, d);
+  if (d == 0 && L.c6fpart && !accumulate && !rr) {
+    // one wave per (line, component), as the C4 partition kernel
+    const long long nmax = L.max_n[0];
+    const size_t per_wave = (size_t)fpart_lds_slots((int)nmax) * sizeof(double);
+    const int nw = 4 * per_wave <= 60 * 1024 ? 4 : 2;
+    const long long items = 5 * L.sweep_rows[0];
+    const unsigned blocks = (unsigned)std::max<long long>(1, std::min<long long>((items + nw - 1) / nw, 4096));
+    if ((nmax - 1) / 64 + 1 <= FPART_LSHORT)
+      LG_TIMED(L, KC_C6_FACES, hipLaunchKernelGGL((k_c6_faces_part<R, FPART_LSHORT>), dim3(blocks, L.nprob),
+                                                  dim3(64 * nw), nw * per_wave, L.stream, L.probs, ref, (int)nmax,
+                                                  L.tile_mask));
+    else
+      LG_TIMED(L, KC_C6_FACES, hipLaunchKernelGGL((k_c6_faces_part<R, FPART_LMAX>), dim3(blocks, L.nprob),
+                                                  dim3(64 * nw), nw * per_wave, L.stream, L.probs, ref, (int)nmax,
+                                                  L.tile_mask));
+  }
   if (sl.tiles)
     launch_tiles<R, TK_FACES>(L, KC_C6_FACES, L.max_n[d] + 4, L.max_n[o1], L.max_n[o2],
                               TileArgs{ref, rr ? *rr : RKRef{nullptr, nullptr, nullptr}, d, 1, accumulate, rr ? 1 : 0,

@@ -541,6 +541,10 @@ void fill_launch(Launch& L, const Prob& P) {
           L.fpart = 1;
           continue;
         }
+        if (k == lg::TK_FACES && lg::c6f_part_use(P, d, L.tile_mask)) {
+          L.c6fpart = 1;
+          continue;
+        }
         if (k == lg::TK_FILTER && lg::filt_seg_use(P, d, L.tile_mask)) {
           L.fseg[d] = std::max(L.fseg[d], lg::fseg_count(P.n[d]));
           continue;
@@ -1136,7 +1140,7 @@ lg_status lg_set_line_tiles(lg_ctx* c, int mask) {
     for (int k = 0; k < 4; ++k) c->L.ctile[k][d] = 0;
     c->L.c4_rest_pcr[d] = c->L.c4_rest_thomas[d] = 0;
   }
-  c->L.fpart = c->L.c4part = 0;
+  c->L.fpart = c->L.c4part = c->L.c6fpart = 0;
   for (int d = 0; d < 3; ++d) c->L.fseg[d] = c->L.c4seg[d] = 0;
   fill_launch(c->L, c->hp);
   return LG_OK;
