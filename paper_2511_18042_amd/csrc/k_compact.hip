@@ -348,7 +348,9 @@ __device__ __forceinline__ bool face_emit_q(const Prob& P, const FaceOut& o, dou
 template <typename R, int NQ>
 __global__ void __launch_bounds__(256) k_c6_faces(const Prob* __restrict__ probs, FaceOut o, int d, int mask) {
   const Prob& P = probs[blockIdx.y];
-  if (d >= P.ndim || tile_use(P, d, TK_FACES, mask) || c6_face_pcr(P, d) || c6f_part_use(P, d, mask)) return;
+  if (d >= P.ndim || tile_use(P, d, TK_FACES, mask) || c6_face_pcr(P, d) || c6f_part_use(P, d, mask) ||
+      c6f_seg_use(P, d, mask))
+    return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int nl = interior_lines(P, d);
   if (t >= (5 / NQ) * nl) return;
@@ -900,6 +902,198 @@ __global__ void __launch_bounds__(64 * FSEG_SMAX) k_grad_c4_seg(const Prob* __re
     if (!periodic && s == 0) Gl[0] = (R)d0;
     if (!periodic && s == S - 1) Gl[(size_t)(N - 1) * sd] = (R)dN;
   }
+}
+
+// ------------------------------------------------------------------ C6 interface fluxes, strided segments
+// LAD-C6 interface fluxes along eta / zeta (the [1/3, 1, 1/3] face system of k_c6_faces) in
+// register segments, as k_filter_seg filters: 64 neighbouring lines (consecutive along xi)
+// and one flux component per workgroup, wave s segment s of every line, the segments
+// joined through the LU of their first and last faces (host tables for a = 1/3).  A
+// bounded line's unknowns are its n - 1 interior faces (face j between nodes j and j + 1),
+// the fourth-order boundary faces moved to the right-hand side; a periodic line's are its
+// n faces.  Each segment then emits -J D for its own nodes j0 .. j0 + L - 1 (D = right
+// face - left face; the left face of node j0 is the previous segment's last face, the low
+// boundary face, or the periodic image), the last segment of a bounded line also node
+// n - 1, into dQ/dt (accumulated after the first direction), or, in the last direction of
+// an RK stage, the stage combination of its component (a U^n + b (U^s + dt L)); the
+// non-physical count of the stage result then takes its own pass (k_c6_seg_check), since it
+// needs the five components of a node together.  Region-free stages only.
+template <typename R, int LM, bool RK>
+__global__ void __launch_bounds__(64 * C6FSEG_SMAX) k_c6_faces_seg(const Prob* __restrict__ probs, StateRef ref, int d,
+                                                                  int accumulate, int mask, RKRef rr, int stage,
+                                                                  double a, double b) {
+  constexpr int SM = C6FSEG_SMAX, M2 = 2 * SM, M2T = 2 * FSEG_SMAX;   // joint unknowns; table row stride
+  __shared__ double tab[FSEG_TABLE];      // cp, 1 / pivot, u, v, joint LU (host-built)
+  __shared__ double ends[SM][2][64];      // y_s[0], y_s[L-1] of each line; then A_s, B_s
+  const Prob& P = probs[blockIdx.y];
+  if (!c6f_seg_use(P, d, mask)) return;
+  const bool periodic = P.bc[d][0] == BC_PERIODIC;
+  const int n = P.n[d], g = P.g[d], sd = P.s[d];
+  const int m = c6f_seg_unknowns(P, d);
+  const int S = fseg_count(m);
+  const int base = m / S, extra = m % S;   // the first `extra` segments have base + 1
+  const int nlines = interior_lines(P, d);
+  const int q = blockIdx.x % 5, grp = blockIdx.x / 5;
+  if (grp * 64 >= nlines) return;
+  const double al = C6_ALPHA;
+  const int lane = threadIdx.x & 63, s = threadIdx.x >> 6;
+  for (int e = threadIdx.x; e < FSEG_TABLE; e += blockDim.x) tab[e] = P.c6fsegt[d][e];
+  const double* tcp = tab + FSEG_CP;
+  const double* tinv = tab + FSEG_INV;
+  const int line = grp * 64 + lane;
+  const bool act = s < S && line < nlines;
+  const int L = base + (s < extra ? 1 : 0);
+  const int j0 = s * base + min(s, extra);   // first face of this lane's segment
+  const double* tu = tab + FSEG_U + (s < extra ? LM + 1 : 0);
+  const double* tv = tab + FSEG_V + (s < extra ? LM + 1 : 0);
+  const size_t T = P.total;
+  const size_t lb = act ? interior_line_base(P, d, line) : 0;
+  const R* F = static_cast<const R*>(P.FL[d]) + (size_t)q * T + lb;
+  auto at = [&](int p) { return (double)F[(ptrdiff_t)(g + (periodic ? wrap(p, n) : p)) * sd]; };
+  // w[i] = F at node j0 + i - 1 (faces j0 + i use nodes j0 + i - 1 .. j0 + i + 2); after row
+  // i, w[i] (no longer read) holds the forward value, then y_i, then the face
+  double w[LM + 3];
+  double lo = 0.0, hi = 0.0;   // boundary faces of a bounded line
+  if (act) {
+#pragma unroll
+    for (int i = 0; i < LM + 3; ++i)
+      if (i < L + 3) w[i] = at(j0 + i - 1);
+    if (!periodic && s == 0) lo = (7.0 * (w[0] + w[1]) - (at(-2) + w[2])) / 12.0;
+    if (!periodic && s == S - 1) {   // nodes n - 2 .. n are slots L .. L + 2
+#pragma unroll
+      for (int i = 0; i < LM; ++i)
+        if (i == L - 1) hi = (7.0 * (w[i + 2] + w[i + 3]) - (w[i + 1] + at(n + 1))) / 12.0;
+    }
+  }
+  __syncthreads();   // tables in LDS
+  if (act) {
+    double prev = 0.0;
+#pragma unroll
+    for (int i = 0; i < LM; ++i) {
+      if (i < L) {
+        double r = C6F_A * (w[i + 1] + w[i + 2]) + C6F_B * (w[i] + w[i + 3]);
+        const int j = j0 + i;
+        if (!periodic && j == 0) r = r - al * lo;
+        if (!periodic && j == m - 1) r = r - al * hi;
+        prev = (r - (i > 0 ? al * prev : 0.0)) * tinv[i];
+        w[i] = prev;
+      }
+    }
+    double v = prev;
+#pragma unroll
+    for (int i = LM - 2; i >= 0; --i) {
+      if (i < L - 1) {
+        v = w[i] - tcp[i] * v;
+        w[i] = v;
+      }
+    }
+    ends[s][0][lane] = w[0];
+    ends[s][1][lane] = prev;
+  }
+  __syncthreads();
+  if (s == 0 && line < nlines) {   // L U z = (y_s[0], y_s[L-1])_s, in place in ends
+    const double* lu = tab + FSEG_LU;
+    const int m2 = 2 * S;
+    double z[M2];
+#pragma unroll
+    for (int r = 0; r < M2; ++r) {
+      if (r < m2) {
+        double v = ends[r >> 1][r & 1][lane];
+#pragma unroll
+        for (int c = 0; c < r; ++c) v -= lu[r * M2T + c] * z[c];
+        z[r] = v;
+      }
+    }
+#pragma unroll
+    for (int r = M2 - 1; r >= 0; --r) {
+      if (r < m2) {
+        double v = z[r];
+#pragma unroll
+        for (int c = r + 1; c < M2; ++c)
+          if (c < m2) v -= lu[r * M2T + c] * z[c];
+        z[r] = v / lu[r * M2T + r];
+        ends[r >> 1][r & 1][lane] = z[r];
+      }
+    }
+  }
+  __syncthreads();
+  if (act) {
+    const int sp = s - 1, sn = s + 1;
+    const double Bm = (periodic || sp >= 0) ? ends[(sp + S) % S][1][lane] : 0.0;
+    const double Ap = (periodic || sn < S) ? ends[sn % S][0][lane] : 0.0;
+    double* dQ = ref.deriv(P) + (size_t)q * T + lb;
+    // the RK stage's arrays (as rk_combine_node): U^n, U^s and the result, this component
+    const double* Un = (rr.Un ? rr.Un : P.Q) + (size_t)q * T + lb;
+    const double* Us = RK ? (rr.Us ? rr.Us + (size_t)q * T + lb : (stage == 0 ? Un : P.Us + (size_t)q * T + lb)) : Un;
+    double* out = rr.out ? rr.out + (size_t)q * T + lb
+                         : (stage == 2 ? const_cast<double*>(Un) : P.Us + (size_t)q * T + lb);
+    const double dt = RK ? *P.dt : 0.0;
+    double left = sp >= 0 ? Bm : (periodic ? ends[S - 1][1][lane] : lo);
+    // eight nodes at a time: their loads are all in flight before the stores
+    constexpr int CH = 8;
+#pragma unroll
+    for (int c = 0; c < LM; c += CH) {
+      if (c < L) {
+        double Jv[CH], dv[CH], un[CH], us[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          if (c + u < L) {
+            const size_t o = (size_t)(g + j0 + c + u) * sd;
+            Jv[u] = met64(P, 9, (int)(lb + o));
+            dv[u] = accumulate ? dQ[o] : 0.0;
+            if (RK) {
+              un[u] = Un[o];
+              us[u] = Us[o];
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          if (c + u < L) {
+            const double x = w[c + u] - al * tu[c + u] * Bm - al * tv[c + u] * Ap;
+            const double Lv = dv[u] - Jv[u] * (x - left);
+            const size_t o = (size_t)(g + j0 + c + u) * sd;
+            if (RK) out[o] = a * un[u] + b * (us[u] + dt * Lv);
+            else dQ[o] = Lv;
+            left = x;
+          }
+        }
+      }
+    }
+    if (!periodic && s == S - 1) {   // node n - 1: the high boundary face on its right
+      const size_t o = (size_t)(g + n - 1) * sd;
+      const double Lv = (accumulate ? dQ[o] : 0.0) - met64(P, 9, (int)(lb + o)) * (hi - left);
+      if (RK) out[o] = a * Un[o] + b * (Us[o] + dt * Lv);
+      else dQ[o] = Lv;
+    }
+  }
+}
+
+// Non-physical count of an RK stage whose last direction k_c6_faces_seg combined: interior
+// nodes of the result, tested as rk_combine_node tests them.
+__global__ void __launch_bounds__(256) k_c6_seg_check(const Prob* __restrict__ probs, RKRef rr, int stage, int mask) {
+  const Prob& P = probs[blockIdx.y];
+  if (!c6f_seg_use(P, P.ndim - 1, mask)) return;
+  const size_t T = P.total;
+  const double* Un = rr.Un ? rr.Un : P.Q;
+  const double* out = rr.out ? rr.out : (stage == 2 ? Un : P.Us);
+  const int n0 = P.n[0], n1 = P.n[1], rows = n1 * P.n[2];
+  int bad = 0;
+  for (int r = blockIdx.x; r < rows; r += gridDim.x) {   // one xi row of interior nodes per step
+    const int row0 = (P.g[1] + r % n1) * P.s[1] + (P.g[2] + r / n1) * P.s[2] + P.g[0];
+    for (int i = threadIdx.x; i < n0; i += blockDim.x) {
+      const int idx = row0 + i;
+      double v[5];
+      for (int q = 0; q < 5; ++q) v[q] = out[(size_t)q * T + idx];
+      const double rho = v[0];
+      const double ke = 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / rho;
+      const double p = (P.gamma - 1.0) * (v[4] - ke);
+      const bool ok = rho > 0.0 && p > 0.0 && isfinite(rho) && isfinite(p) && isfinite(v[1]) && isfinite(v[2]) &&
+                      isfinite(v[3]);
+      bad += !ok;
+    }
+  }
+  add_bad(P, bad);
 }
 
 // ------------------------------------------------------------------ filter positivity guard
@@ -1811,6 +2005,24 @@ void launch_c6_faces(const Launch& L, StateRef ref, int d, int accumulate, const
       LG_TIMED(L, KC_C6_FACES, hipLaunchKernelGGL((k_c6_faces_part<R, FPART_LMAX>), dim3(blocks, L.nprob),
                                                   dim3(64 * nw), nw * per_wave, L.stream, L.probs, ref, (int)nmax,
                                                   L.tile_mask));
+  }
+  if (d > 0 && L.c6fseg[d] > 0) {
+    // 64 lines x one component per workgroup, one wave per segment; where this is the last
+    // direction of an RK stage, the combination in the same pass and the non-physical count
+    // in its own
+    const long long groups = (L.sweep_rows[d] + 63) / 64;
+    const dim3 grid((unsigned)(5 * groups), L.nprob), block(64 * L.c6fseg[d]);
+    if (rr)
+      LG_TIMED(L, KC_C6_FACES, hipLaunchKernelGGL((k_c6_faces_seg<R, FSEG_LM, true>), grid, block, 0, L.stream,
+                                                  L.probs, ref, d, accumulate, L.tile_mask, *rr, stage, a, b));
+    else
+      LG_TIMED(L, KC_C6_FACES, hipLaunchKernelGGL((k_c6_faces_seg<R, FSEG_LM, false>), grid, block, 0, L.stream,
+                                                  L.probs, ref, d, accumulate, L.tile_mask,
+                                                  RKRef{nullptr, nullptr, nullptr}, stage, a, b));
+    if (rr)
+      LG_TIMED(L, KC_COMBINE, hipLaunchKernelGGL(k_c6_seg_check,
+                                                 dim3((unsigned)std::min<long long>(L.sweep_rows[0], 1 << 16), L.nprob),
+                                                 dim3(256), 0, L.stream, L.probs, *rr, stage, L.tile_mask));
   }
   if (sl.tiles)
     launch_tiles<R, TK_FACES>(L, KC_C6_FACES, L.max_n[d] + 4, L.max_n[o1], L.max_n[o2],

@@ -545,6 +545,10 @@ void fill_launch(Launch& L, const Prob& P) {
           L.c6fpart = 1;
           continue;
         }
+        if (k == lg::TK_FACES && lg::c6f_seg_use(P, d, L.tile_mask)) {
+          L.c6fseg[d] = std::max(L.c6fseg[d], lg::fseg_count(lg::c6f_seg_unknowns(P, d)));
+          continue;
+        }
         if (k == lg::TK_FILTER && lg::filt_seg_use(P, d, L.tile_mask)) {
           L.fseg[d] = std::max(L.fseg[d], lg::fseg_count(P.n[d]));
           continue;
@@ -884,6 +888,8 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
       P.trc[d] = upload(periodic ? cyclic_table(n, a3) : thomas_table(fa, fc));
       P.pcrc[d] = upload(periodic ? pcr_table_ac(pa, pc, true, lg::LG_PCR_STEPS)
                                   : pcr_table_ac(fa, fc, false, lg::LG_PCR_STEPS));
+      const int mf = periodic ? n : n - 1;   // faces solved (c6f_seg_unknowns)
+      if (d > 0 && lg::fseg_count(mf) <= lg::C6FSEG_SMAX && mf >= 16) P.c6fsegt[d] = upload(fseg_table(mf, a3, periodic));
     }
     if (!ok) {
       lg_destroy(c);
@@ -1141,7 +1147,7 @@ lg_status lg_set_line_tiles(lg_ctx* c, int mask) {
     c->L.c4_rest_pcr[d] = c->L.c4_rest_thomas[d] = 0;
   }
   c->L.fpart = c->L.c4part = c->L.c6fpart = 0;
-  for (int d = 0; d < 3; ++d) c->L.fseg[d] = c->L.c4seg[d] = 0;
+  for (int d = 0; d < 3; ++d) c->L.fseg[d] = c->L.c4seg[d] = c->L.c6fseg[d] = 0;
   fill_launch(c->L, c->hp);
   return LG_OK;
 }

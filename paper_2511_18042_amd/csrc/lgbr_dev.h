@@ -81,6 +81,7 @@ struct Prob {
   const double* pcrf[3];
   const double* fsegt[3]; // filter along eta / zeta by register segments (k_filter_seg tables)
   const double* c4segt[3];  // MIG4 gradients along eta / zeta by register segments (k_grad_c4_seg tables)
+  const double* c6fsegt[3]; // LAD-C6 interface fluxes along eta / zeta by register segments (k_c6_faces_seg tables)
   // device scalars
   double* dt;
   double* t;

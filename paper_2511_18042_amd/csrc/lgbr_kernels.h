@@ -123,6 +123,7 @@ struct Launch {
   int c4part;              // some problem solves its MIG4 gradients along xi by the partition method
   int c6fpart;             // some problem solves its LAD-C6 faces along xi by the partition method
   int c4seg[3];            // most segments per line of the problems solving MIG4 gradients along d in k_grad_c4_seg (0: none)
+  int c6fseg[3];           // most segments per line of the problems solving LAD-C6 faces along d in k_c6_faces_seg (0: none)
   int fseg[3];             // most segments per line of the problems filtering along d by k_filter_seg (0: none)
   Prof* prof;              // optional launch timing (null: off)
 };
@@ -273,7 +274,7 @@ enum { TK_GRAD6 = 0, TK_FACES = 1, TK_FILTER = 2, TK_GRAD4 = 3 };
 constexpr int TILE_MASK_ALL = 0xFFF;
 constexpr int TILE_MASK_FORCE_STRIDED = 0x1000;   // tiles on strided directions whatever their line count
 constexpr int TILE_MASK_NO_PART = 0x2000;          // no partition-method kernels along xi (filter, MIG4 gradients)
-constexpr int TILE_MASK_NO_SEG = 0x4000;           // filter along eta / zeta without the register-segment kernel
+constexpr int TILE_MASK_NO_SEG = 0x4000;           // no register-segment kernels along eta / zeta (filter, MIG4 gradients, LAD-C6 faces)
 constexpr int TILE_MASK_DEFAULT = TILE_MASK_ALL;
 constexpr int TILE_ELEMS = 6144;   // doubles per tile (48 KB of LDS)
 // lanes per tile workgroup: contiguous lines take 512 (128 VGPRs, four waves per SIMD);
@@ -366,6 +367,22 @@ __host__ __device__ inline bool c4_seg_use(const Prob& P, int d, int mask) {
     return false;
   const int m = c4_seg_unknowns(P, d);
   return fseg_count(m) <= FSEG_SMAX && m >= 16;
+}
+// LAD-C6 interface fluxes along eta / zeta in register segments (k_c6_faces_seg, tables of
+// the same layout for a = 1/3): the n - 1 interior faces of a bounded line between its
+// fourth-order boundary faces, or the n faces of a periodic line, 16 to 256 of them (at most
+// four segments: with two waves per SIMD at the kernel's register count, two workgroups
+// share a CU; six-segment workgroups, alone on their CU, were slower than one lane per line),
+// where the LDS tiles do not take the direction, unless mask bit 14 is set
+constexpr int C6FSEG_SMAX = 4;
+__host__ __device__ inline int c6f_seg_unknowns(const Prob& P, int d) {
+  return P.bc[d][0] == BC_PERIODIC ? P.n[d] : P.n[d] - 1;
+}
+__host__ __device__ inline bool c6f_seg_use(const Prob& P, int d, int mask) {
+  if ((mask & TILE_MASK_NO_SEG) || d == 0 || d >= P.ndim || !P.c6fsegt[d] || tile_use(P, d, TK_FACES, mask))
+    return false;
+  const int m = c6f_seg_unknowns(P, d);
+  return fseg_count(m) <= C6FSEG_SMAX && m >= 16;
 }
 
 }  // namespace lg
