@@ -149,7 +149,7 @@ __device__ __forceinline__ double c6_grad_rhs(int i, int N, double m2, double m1
 template <typename R, int NQ>
 __global__ void __launch_bounds__(320) k_grad_c6(const Prob* __restrict__ probs, StateRef ref, int d, int mask) {
   const Prob& P = probs[blockIdx.y];
-  if (d >= P.ndim || tile_use(P, d, TK_GRAD6, mask) || c6_grad_pcr(P, d)) return;
+  if (d >= P.ndim || tile_use(P, d, TK_GRAD6, mask) || c6_grad_pcr(P, d) || c6g_part_use(P, d, mask)) return;
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   // NQ = 5: one lane per line; NQ = 1: a workgroup of five waves solves the five primitives
   // of 64 lines, wave w primitive w (the waves share the state's cache lines)
@@ -243,7 +243,7 @@ __global__ void __launch_bounds__(CPCR_THREADS) __attribute__((amdgpu_waves_per_
                                                      int mask) {
   extern __shared__ double lds[];
   const Prob& P = probs[blockIdx.y];
-  if (d >= P.ndim || tile_use(P, d, TK_GRAD6, mask) || !c6_grad_pcr(P, d)) return;
+  if (d >= P.ndim || tile_use(P, d, TK_GRAD6, mask) || !c6_grad_pcr(P, d) || c6g_part_use(P, d, mask)) return;
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   const int nlines = P.N[o1] * P.N[o2];
   const bool periodic = P.bc[d][0] == BC_PERIODIC;
@@ -1326,31 +1326,41 @@ __global__ void __launch_bounds__(64 * FPART_WAVES) k_filter_part(const Prob* __
   }
 }
 
-// ------------------------------------------------------------------ C4 gradients, partition method
-// MIG4 gradients along xi on bounded lines (Sec. 2.3; the C4 rows of k_grad.hip).  The
-// one-sided end rows of the padded line of N nodes decouple, so rows 1 .. N-2 form the
-// [1/4, 1, 1/4] system of M = N - 2 unknowns with the two end values moved to the
-// right-hand side: the system k_filter_part solves with a = alpha_f, solved the same way
-// here with a = 1/4 (segments per lane, joint unknowns by two wave-wide scans).  One wave
-// per (line, primitive) over every line of the direction; the five primitives of a line are
-// consecutive items, so their staging reads of the state share the cache.  Region-free
-// launches only (every line; in a per-cell stage, when most lines are listed).
-template <typename R, int LM>
-__global__ void __launch_bounds__(64 * FPART_WAVES) k_grad_c4_part(const Prob* __restrict__ probs, StateRef ref,
-                                                                   int nmax, int skip_if_any, int dense_only,
-                                                                   int mask) {
+// ------------------------------------------------------------------ C4 / C6 gradients, partition method
+// MIG4 gradients along xi on bounded lines (Sec. 2.3; the C4 rows of k_grad.hip), and the
+// LAD-C6 gradients (Sec. 3; the rows of k_grad_c6).  The one-sided end rows of the padded
+// line of N nodes decouple, so rows 1 .. N-2 form a system of M = N - 2 unknowns with the
+// two end values moved to the right-hand side.  C4: the [1/4, 1, 1/4] system, which
+// k_filter_part solves with a = alpha_f, solved the same way here (segments per lane, joint
+// unknowns by two wave-wide scans).  C6: the [1/3, 1, 1/3] system T except that the first
+// row's upper and the last row's lower neighbour carry 1/4 (the C4 rows next to the ends),
+// T' = T - (e_0 e_1^T + e_{M-1} e_{M-2}^T) / 12; the scans solve T y = r, and the
+// Sherman-Morrison-Woodbury identity gives x = y + (c_0 z_0 + c_M z_M) / 12, with z_0 =
+// T^{-1} e_0, z_M = T^{-1} e_{M-1} (its mirror image) and (c_0, c_M) = (I - W)^{-1}
+// (y_1, y_{M-2}) for W = [z_0 z_M] rows 1 and M-2 / 12.  z_0 decays by 0.38 per row, so
+// its first 64 entries and the 2x2 inverse (host tables) carry the correction to FP64
+// precision.  One wave per (line, primitive) over every line of the direction; the five
+// primitives of a line are consecutive items, so their staging reads of the state share
+// the cache.  Region-free launches only (every line; in a per-cell stage, when most lines
+// are listed).
+template <typename R, int LM, bool C6>
+__global__ void __launch_bounds__(64 * FPART_WAVES) k_grad_part(const Prob* __restrict__ probs, StateRef ref,
+                                                                int nmax, int skip_if_any, int dense_only,
+                                                                int mask) {
   extern __shared__ double dyn[];   // per wave: the staged line [nmax + 10]
   __shared__ double tcp[FPART_LMAX], tinv[FPART_LMAX];
   __shared__ double tu[2][FPART_LMAX], tv[2][FPART_LMAX];   // segment lengths base and base + 1
   __shared__ double tda[64], tGa[64], tGb[64];
   const Prob& P = probs[blockIdx.y];
-  if (!c4_part_use(P, 0, mask) || P.n[0] > nmax || gate_skip(P, skip_if_any)) return;
+  if (!(C6 ? c6g_part_use(P, 0, mask) : c4_part_use(P, 0, mask)) || P.n[0] > nmax || gate_skip(P, skip_if_any))
+    return;
   if (dense_only && !dense_lines(P, 0)) return;
   const int N = P.N[0], M = N - 2;
   const int nseg = min(64, M / 2);
   const int base = M / nseg, extra = M % nseg;   // the first `extra` segments have base + 1
   if (base + 1 > LM) return;   // segments longer than the register arrays
-  const double al = 0.25;
+  const double al = C6 ? C6_ALPHA : 0.25;   // the system solved by the scans
+  constexpr double ae = 0.25;                // coupling of rows 1 and N-2 to the end values
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
   // segment factors, the responses u = T^{-1} e_1 and v = T^{-1} e_L, and the
   // data-independent elimination factors of the joint unknowns (as in k_filter_part)
@@ -1423,19 +1433,22 @@ __global__ void __launch_bounds__(64 * FPART_WAVES) k_grad_c4_part(const Prob* _
     double y[LM];
     double ya = 0.0, yb = 0.0;
     if (act) {
-      // unknown j is row j + 1: 3 (f_{j+2} - f_j) / 4, less a / 4 times a known end value
-      double fm = F(j0), f0 = F(j0 + 1);
+      // unknown j is row j + 1: 3 (f_{j+2} - f_j) / 4 (C4, and the C6 rows next to the
+      // ends, less 1/4 times the end value), else C6_A (f_{j+2} - f_j) + C6_B (f_{j+3} - f_{j-1})
+      double fa = C6 && j0 > 0 ? F(j0 - 1) : 0.0, fm = F(j0), f0 = F(j0 + 1);
       double prev = 0.0;
 #pragma unroll
       for (int i = 0; i < LM; ++i) {
         if (i < L) {
           const int j = j0 + i;
           const double fp = F(j + 2);
-          double r = 0.75 * (fp - fm);
-          if (j == 0) r = r - al * d0;
-          if (j == M - 1) r = r - al * dN;
+          const double fe = C6 && j + 3 < N ? F(j + 3) : 0.0;
+          double r = C6 && j > 0 && j < M - 1 ? C6_A * (fp - fm) + C6_B * (fe - fa) : 0.75 * (fp - fm);
+          if (j == 0) r = r - ae * d0;
+          if (j == M - 1) r = r - ae * dN;
           prev = (r - (i > 0 ? al * prev : 0.0)) * tinv[i];
           y[i] = prev;
+          fa = fm;
           fm = f0;
           f0 = fp;
         }
@@ -1472,6 +1485,16 @@ __global__ void __launch_bounds__(64 * FPART_WAVES) k_grad_c4_part(const Prob* _
       F(N - 1) = dN;
     }
     wave_lds_sync();
+    if (C6) {   // x = y + (c_0 z_0 + c_M z_M) / 12 on the first and last 64 unknowns
+      const double* zt = P.c6gz;
+      const double y1 = F(2), yM = F(M - 1);   // unknowns 1 and M-2
+      const double c0 = (zt[64] * y1 + zt[65] * yM) / 12.0, cM = (zt[66] * y1 + zt[67] * yM) / 12.0;
+      const double z = zt[lane];
+      wave_lds_sync();   // every lane has read y_1 and y_{M-2}
+      F(1 + lane) = F(1 + lane) + c0 * z;     // unknown lane
+      F(M - lane) = F(M - lane) + cM * z;     // unknown M - 1 - lane
+      wave_lds_sync();
+    }
     for (int p = lane; p < N; p += 64) G[(size_t)q * T + lb + (size_t)p] = (R)F(p);
     wave_lds_sync();   // the next item's staging overwrites f
   }
@@ -1968,10 +1991,14 @@ static inline SysLaunch sys_launch(const Launch& L, int kind, int d) {
   return SysLaunch{L.ctile[kind][d], L.cpcr[kind][d], L.cthomas[kind][d]};
 }
 
+template <typename R, bool C6>
+static void launch_grad_part(const Launch& L, StateRef ref, int skip_if_any, int dense_only);
+
 template <typename R>
 void launch_grad_c6(const Launch& L, StateRef ref, int d) {
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   const SysLaunch sl = sys_launch(L, TK_GRAD6, d);
+  if (d == 0 && L.c6gpart) launch_grad_part<R, true>(L, ref, -1, 0);
   if (sl.tiles)
     launch_tiles<R, TK_GRAD6>(L, KC_GRAD_C4, L.max_N[d], L.max_N[o1], L.max_N[o2],
                               TileArgs{ref, RKRef{nullptr, nullptr, nullptr}, d, 1, 0, 0, 0, L.tile_mask, -1, 0.0, 0.0, 0});
@@ -2105,9 +2132,8 @@ void launch_grad_c4_tiles(const Launch& L, StateRef ref, int d, int skip_if_any,
                                        0.0, 0.0, 0, dense_only});
 }
 
-template <typename R>
-void launch_grad_c4_part(const Launch& L, StateRef ref, int skip_if_any, int dense_only) {
-  if (!L.c4part) return;
+template <typename R, bool C6>
+static void launch_grad_part(const Launch& L, StateRef ref, int skip_if_any, int dense_only) {
   // one wave per (line, primitive); four waves per workgroup while their staged lines fit
   // 60 KB of LDS, two otherwise
   const long long nmax = L.max_n[0];
@@ -2118,13 +2144,18 @@ void launch_grad_c4_part(const Launch& L, StateRef ref, int skip_if_any, int den
   // register arrays sized to the longest segment: short ones when every line has fewer
   // than 64 * 17 unknowns (the n + 8 between its end rows; segments of at most 17)
   if ((nmax + 8) / 64 + 1 <= FPART_LSHORT)
-    LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL((k_grad_c4_part<R, FPART_LSHORT>), dim3(blocks, L.nprob),
+    LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL((k_grad_part<R, FPART_LSHORT, C6>), dim3(blocks, L.nprob),
                                                dim3(64 * nw), nw * per_wave, L.stream, L.probs, ref, (int)nmax,
                                                skip_if_any, dense_only, L.tile_mask));
   else
-    LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL((k_grad_c4_part<R, FPART_LMAX>), dim3(blocks, L.nprob),
+    LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL((k_grad_part<R, FPART_LMAX, C6>), dim3(blocks, L.nprob),
                                                dim3(64 * nw), nw * per_wave, L.stream, L.probs, ref, (int)nmax,
                                                skip_if_any, dense_only, L.tile_mask));
+}
+
+template <typename R>
+void launch_grad_c4_part(const Launch& L, StateRef ref, int skip_if_any, int dense_only) {
+  if (L.c4part) launch_grad_part<R, false>(L, ref, skip_if_any, dense_only);
 }
 
 template void launch_grad_c4_tiles<float>(const Launch&, StateRef, int, int, int);

@@ -493,6 +493,35 @@ std::vector<double> fseg_table(int n, double al, bool periodic) {
   return t;
 }
 
+// The partition solve of the LAD-C6 gradients along xi (k_grad_part) solves the constant
+// [1/3, 1, 1/3] system T of the M unknowns between the end rows and corrects for the 1/4
+// neighbours of the first and last rows: z_0 = T^{-1} e_0 (entries 0..63; the rest fall
+// below 1e-26 of the first) and (I - W)^{-1}, W = [[z_0[1], z_M[1]], [z_0[M-2], z_M[M-2]]] / 12
+// with z_M the mirror image of z_0.
+std::vector<double> c6_grad_woodbury_table(int M) {
+  const double a = 1.0 / 3.0;
+  std::vector<double> cp(M), z(M);
+  double den = 1.0;
+  z[0] = 1.0;   // forward elimination of e_0
+  cp[0] = a;
+  for (int i = 1; i < M; ++i) {
+    den = 1.0 - a * cp[i - 1];
+    cp[i] = a / den;
+    z[i] = (0.0 - a * z[i - 1]) / den;
+  }
+  for (int i = M - 2; i >= 0; --i) z[i] = z[i] - cp[i] * z[i + 1];
+  std::vector<double> t(68, 0.0);
+  for (int i = 0; i < 64; ++i) t[i] = z[i];
+  const double w00 = z[1] / 12.0, w01 = z[M - 2] / 12.0;   // z_M[1] = z_0[M-2], z_M[M-2] = z_0[1]
+  const double m00 = 1.0 - w00, m01 = -w01, m10 = -w01, m11 = 1.0 - w00;
+  const double det = m00 * m11 - m01 * m10;
+  t[64] = m11 / det;
+  t[65] = -m01 / det;
+  t[66] = -m10 / det;
+  t[67] = m00 / det;
+  return t;
+}
+
 void filter_weights(double al, double a[6]) {
   const double e = (1.0 - 2.0 * al) / 1024.0;
   a[0] = 1.0 - 252.0 * e;
@@ -539,6 +568,10 @@ void fill_launch(Launch& L, const Prob& P) {
         if (k == lg::TK_FILTER ? !(P.falpha < 0.5) : !P.lad_c6) continue;
         if (k == lg::TK_FILTER && lg::filt_part_use(P, d, L.tile_mask)) {
           L.fpart = 1;
+          continue;
+        }
+        if (k == lg::TK_GRAD6 && lg::c6g_part_use(P, d, L.tile_mask)) {
+          L.c6gpart = 1;
           continue;
         }
         if (k == lg::TK_FACES && lg::c6f_part_use(P, d, L.tile_mask)) {
@@ -888,6 +921,7 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
       P.trc[d] = upload(periodic ? cyclic_table(n, a3) : thomas_table(fa, fc));
       P.pcrc[d] = upload(periodic ? pcr_table_ac(pa, pc, true, lg::LG_PCR_STEPS)
                                   : pcr_table_ac(fa, fc, false, lg::LG_PCR_STEPS));
+      if (d == 0 && !periodic && N - 2 >= 128 && N - 2 <= 2048) P.c6gz = upload(c6_grad_woodbury_table(N - 2));
       const int mf = periodic ? n : n - 1;   // faces solved (c6f_seg_unknowns)
       if (d > 0 && lg::fseg_count(mf) <= lg::C6FSEG_SMAX && mf >= 16) P.c6fsegt[d] = upload(fseg_table(mf, a3, periodic));
     }
@@ -1146,7 +1180,7 @@ lg_status lg_set_line_tiles(lg_ctx* c, int mask) {
     for (int k = 0; k < 4; ++k) c->L.ctile[k][d] = 0;
     c->L.c4_rest_pcr[d] = c->L.c4_rest_thomas[d] = 0;
   }
-  c->L.fpart = c->L.c4part = c->L.c6fpart = 0;
+  c->L.fpart = c->L.c4part = c->L.c6fpart = c->L.c6gpart = 0;
   for (int d = 0; d < 3; ++d) c->L.fseg[d] = c->L.c4seg[d] = c->L.c6fseg[d] = 0;
   fill_launch(c->L, c->hp);
   return LG_OK;

@@ -122,6 +122,7 @@ struct Launch {
   int fpart;               // some problem filters along xi with the partition-method kernel
   int c4part;              // some problem solves its MIG4 gradients along xi by the partition method
   int c6fpart;             // some problem solves its LAD-C6 faces along xi by the partition method
+  int c6gpart;             // some problem solves its LAD-C6 gradients along xi by the partition method
   int c4seg[3];            // most segments per line of the problems solving MIG4 gradients along d in k_grad_c4_seg (0: none)
   int c6fseg[3];           // most segments per line of the problems solving LAD-C6 faces along d in k_c6_faces_seg (0: none)
   int fseg[3];             // most segments per line of the problems filtering along d by k_filter_seg (0: none)
@@ -310,10 +311,17 @@ __host__ __device__ inline bool c6f_part_use(const Prob& P, int d, int mask) {
   return !(mask & TILE_MASK_NO_PART) && d == 0 && P.ndim > 1 && P.bc[0][0] != BC_PERIODIC && P.n[0] - 1 >= 128 &&
          P.n[0] - 1 <= 2048;
 }
+// LAD-C6 gradients along xi on bounded lines of 130..2050 nodes (the N - 2 unknowns between
+// the decoupled end rows): partition method (k_grad_part) unless mask bit 13 turns it off
+__host__ __device__ inline bool c6g_part_use(const Prob& P, int d, int mask) {
+  return !(mask & TILE_MASK_NO_PART) && d == 0 && P.c6gz && P.bc[0][0] != BC_PERIODIC && P.N[0] - 2 >= 128 &&
+         P.N[0] - 2 <= 2048;
+}
 __host__ __device__ inline bool tile_use(const Prob& P, int d, int kind, int mask) {
   if (!((mask >> (3 * kind + d)) & 1) || !tile_ok(P, d, kind)) return false;
   if (kind == TK_GRAD4 && c4_part_use(P, d, mask)) return false;
   if (kind == TK_FACES && c6f_part_use(P, d, mask)) return false;
+  if (kind == TK_GRAD6 && c6g_part_use(P, d, mask)) return false;
   if (d == 0 || (mask & TILE_MASK_FORCE_STRIDED)) return true;
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   const bool all_nodes = kind == TK_GRAD6 || kind == TK_GRAD4;

@@ -1,14 +1,20 @@
-"""LAD-C6 interface fluxes along xi by the partition method (k_c6_faces_part: bounded lines
-of 129 to 2049 nodes of 2D and 3D problems, the n - 1 interior faces of the [alpha, 1, alpha]
-system with the two fourth-order boundary faces on its right-hand side; segments per lane
-joined through their end unknowns), against the oracle's banded solve, through LAD-C6
-right-hand sides (FP64, the RHS tolerance of the other parity tests), beside the kernels it
-replaces (LDS line tiles, PCR or one lane per line: mask bit 13).
+"""LAD-C6 along xi by the partition method, against the oracle's banded solves, through
+LAD-C6 right-hand sides (FP64, the RHS tolerance of the other parity tests), beside the
+kernels it replaces (LDS line tiles, PCR or one lane per line: mask bit 13):
+  * interface fluxes (k_c6_faces_part: bounded lines of 129 to 2049 nodes of 2D and 3D
+    problems, the n - 1 interior faces of the [1/3, 1, 1/3] system with the two
+    fourth-order boundary faces on its right-hand side; segments per lane joined through
+    their end unknowns);
+  * gradients (k_grad_part: padded lines of 130 to 2050 nodes, the N - 2 unknowns between
+    the decoupled end rows; the constant system by the same scans, the 1/4 neighbours of
+    its first and last rows by a Woodbury correction).
 
-Cases: the shortest line it takes (129 nodes: 128 faces, two per segment), 300 nodes with
-reflective and transmissive walls, 1030 nodes with a FIXED inflow face, 2049 nodes (the
-longest register arrays), a 3D curvilinear block with a periodic zeta, and a periodic line
-of 200 nodes and a 1D line, which stay on the other kernels."""
+Cases: the shortest lines they take (120 nodes: 128 gradient unknowns, 119 faces, which stay
+on the tiles; 129 nodes: 128 faces), 300 nodes with reflective and transmissive walls, 1030
+nodes with a FIXED inflow face, 2038 nodes (2046 gradient unknowns) and 2049 (2048 faces,
+gradients on the PCR kernel), a 3D curvilinear block with a periodic zeta, a 1D line (its
+gradients only: 1D faces stay on the PCR kernel) and a periodic line of 200 nodes, which
+stays on the other kernels."""
 import numpy as np
 import pytest
 
@@ -35,15 +41,17 @@ def _curv3d():
 
 
 CASES = {
+    'x120': lambda: _case(2, (120, 8, 1), [(RF, T), (T, T)], 40),
     'x129': lambda: _case(2, (129, 8, 1), [(T, T), (RF, T)], 41),
     'x300_walls': lambda: _case(2, (300, 12, 1), [(RF, T), (T, RF)], 42),
     'x1030_fixed': lambda: _case(2, (1030, 6, 1), [(FX, T), (T, T)], 43),
+    'x2038': lambda: _case(2, (2038, 5, 1), [(RF, FX), (T, T)], 49),
     'x2049': lambda: _case(2, (2049, 5, 1), [(T, RF), (T, T)], 44),
     'x160_3d_curv': _curv3d,
     'x200_periodic': lambda: _case(2, (200, 8, 1), [(P, P), (T, T)], 45),
     'x300_1d': lambda: _case(1, (300, 1, 1), [(T, RF)], 47),
 }
-UNCHANGED = ('x200_periodic', 'x300_1d')   # stay on the other kernels
+UNCHANGED = ('x200_periodic',)   # periodic lines stay on the other kernels
 
 
 def _gas(c):
@@ -53,8 +61,8 @@ def _gas(c):
 
 
 @pytest.mark.parametrize('name', list(CASES))
-def test_c6_face_partition_parity_fp64(name):
-    print('c6 face partition', name, flush=True)
+def test_c6_partition_parity_fp64(name):
+    print('c6 partition', name, flush=True)
     c = CASES[name]()
     gas = _gas(c)
     opts = orhs.Opts(lad='C6', filter_alpha=0.49, C_mu=0.002)
@@ -66,7 +74,7 @@ def test_c6_face_partition_parity_fp64(name):
         ctx.set_line_tiles(mask)
         out = U.gpu_rhs(ctx, c, 'lad')
         ctx.close()
-        U.compare(out, ref, g, U.RHS_RTOL, label='c6 face part %s mask %d' % (name, mask))
+        U.compare(out, ref, g, U.RHS_RTOL, label='c6 part %s mask %d' % (name, mask))
         outs.append(out)
     inner = (slice(None),) + g.interior()
     a, b = outs[0][inner], outs[1][inner]
@@ -80,7 +88,7 @@ def test_c6_face_partition_parity_fp64(name):
 
 
 @pytest.mark.parametrize('precision', ['fp64', 'mixed'])
-def test_c6_face_partition_rk3_steps(precision):
+def test_c6_partition_rk3_steps(precision):
     """Two RK3 steps (three stages and the filter each) with and without the partition
     kernel on 300 x 12 nodes of near-square cells (LAD alone loses positivity within a step
     on the stretched cells of the RHS cases); FP64 also against the oracle's steps."""
