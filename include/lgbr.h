@@ -272,13 +272,16 @@ lg_status lg_get_tile_shape(const lg_ctx* ctx, int* zm_width, int* line_batch);
  * filter, 3 = MIG4 gradients outside per-cell hybrid stages) along direction d.  Where
  * allowed, tiles are used for the contiguous direction and for strided directions with
  * fewer than 32768 lines (bit 12 set: for strided directions whatever their line count);
- * other lines are solved by PCR per (line, variable) or one lane per line.  The implicit
- * filter along xi on bounded lines of 128 to 2048 unknowns, and the MIG4 gradients along xi
- * on bounded lines of 130 to 2050 nodes outside the listed lines of per-cell stages, use the
- * partition method (one wave per line and variable: segment solves joined through their
- * end unknowns) unless bit 13 is set; along eta and zeta, lines of 16 to 512 unknowns that are not in tiles are
- * solved in register segments of at most 64 unknowns joined the same way (64 lines and one
- * variable per workgroup) unless bit 14 is set, one lane per line otherwise.  mask in
+ * other lines are solved by PCR per (line, variable) or one lane per line.  Along xi the
+ * implicit filter on bounded lines of 128 to 2048 unknowns, the MIG4 gradients (outside the
+ * listed lines of per-cell stages) and the LAD-C6 gradients on bounded lines of 130 to 2050
+ * nodes, and the LAD-C6 interface fluxes on bounded lines of 129 to 2049 nodes of 2D and 3D
+ * grids use the partition method (one wave per line and variable: segment solves joined
+ * through their end unknowns) unless bit 13 is set.  Along eta and zeta, lines that are not
+ * in tiles are solved in register segments of at most 64 unknowns joined the same way (64
+ * lines and one variable per workgroup) unless bit 14 is set: the filter and the MIG4
+ * gradients on lines of 16 to 512 unknowns, the LAD-C6 interface fluxes on lines of 16 to
+ * 256 faces; one lane per line otherwise.  mask in
  * [0, 32767]; -1 restores the default (4095: tiles allowed, bits 12 to 14 clear).
  * lg_get_line_tiles returns the mask in effect (-1 for a null context).  Applies to later
  * calls and to batches created afterwards. */
