@@ -149,7 +149,9 @@ __device__ __forceinline__ double c6_grad_rhs(int i, int N, double m2, double m1
 template <typename R, int NQ>
 __global__ void __launch_bounds__(320) k_grad_c6(const Prob* __restrict__ probs, StateRef ref, int d, int mask) {
   const Prob& P = probs[blockIdx.y];
-  if (d >= P.ndim || tile_use(P, d, TK_GRAD6, mask) || c6_grad_pcr(P, d) || c6g_part_use(P, d, mask)) return;
+  if (d >= P.ndim || tile_use(P, d, TK_GRAD6, mask) || c6_grad_pcr(P, d) || c6g_part_use(P, d, mask) ||
+      c6g_seg_use(P, d, mask))
+    return;
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   // NQ = 5: one lane per line; NQ = 1: a workgroup of five waves solves the five primitives
   // of 64 lines, wave w primitive w (the waves share the state's cache lines)
@@ -243,7 +245,9 @@ __global__ void __launch_bounds__(CPCR_THREADS) __attribute__((amdgpu_waves_per_
                                                      int mask) {
   extern __shared__ double lds[];
   const Prob& P = probs[blockIdx.y];
-  if (d >= P.ndim || tile_use(P, d, TK_GRAD6, mask) || !c6_grad_pcr(P, d) || c6g_part_use(P, d, mask)) return;
+  if (d >= P.ndim || tile_use(P, d, TK_GRAD6, mask) || !c6_grad_pcr(P, d) || c6g_part_use(P, d, mask) ||
+      c6g_seg_use(P, d, mask))
+    return;
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   const int nlines = P.N[o1] * P.N[o2];
   const bool periodic = P.bc[d][0] == BC_PERIODIC;
@@ -775,28 +779,30 @@ __global__ void __launch_bounds__(64 * FSEG_SMAX) k_filter_seg(const Prob* __res
 // (cyclic), and its ghosts take the periodic images.  Right-hand sides 3 (f_{i+1} -
 // f_{i-1}) / 4 from FP64 primitives formed from the state; the gradients go to G in the bulk
 // type.  Region-free launches only (every line; in a per-cell stage, when most lines are
-// listed).
-template <typename R, int LM>
+// listed).  C6: the LAD-C6 gradients of periodic lines, the cyclic [1/3, 1, 1/3] system with
+// the sixth-order right-hand side (tables for a = 1/3).
+template <typename R, int LM, bool C6>
 __global__ void __launch_bounds__(64 * FSEG_SMAX) k_grad_c4_seg(const Prob* __restrict__ probs, StateRef ref, int d,
                                                                  int skip_if_any, int dense_only, int mask) {
   constexpr int SM = FSEG_SMAX, M2 = 2 * SM;
   __shared__ double tab[FSEG_TABLE];      // cp, 1 / pivot, u, v, joint LU (host-built)
   __shared__ double ends[SM][2][64];      // y_s[0], y_s[L-1] of each line; then A_s, B_s
   const Prob& P = probs[blockIdx.y];
-  if (!c4_seg_use(P, d, mask) || gate_skip(P, skip_if_any)) return;
+  if (!(C6 ? c6g_seg_use(P, d, mask) : c4_seg_use(P, d, mask)) || gate_skip(P, skip_if_any)) return;
   if (dense_only && !dense_lines(P, d)) return;
-  const bool periodic = P.bc[d][0] == BC_PERIODIC;
+  const bool periodic = C6 || P.bc[d][0] == BC_PERIODIC;   // C6: periodic lines only
   const int N = P.N[d], n = P.n[d], g = P.g[d], sd = P.s[d];
-  const int m = c4_seg_unknowns(P, d);
+  const int m = C6 ? n : c4_seg_unknowns(P, d);
   const int S = fseg_count(m);
   const int base = m / S, extra = m % S;   // the first `extra` segments have base + 1
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   const int nlines = P.N[o1] * P.N[o2];
   const int q = blockIdx.x % 5, grp = blockIdx.x / 5;
   if (grp * 64 >= nlines) return;
-  const double al = 0.25;
+  const double al = C6 ? C6_ALPHA : 0.25;
   const int lane = threadIdx.x & 63, s = threadIdx.x >> 6;
-  for (int e = threadIdx.x; e < FSEG_TABLE; e += blockDim.x) tab[e] = P.c4segt[d][e];
+  const double* tsrc = C6 ? P.c6gsegt[d] : P.c4segt[d];
+  for (int e = threadIdx.x; e < FSEG_TABLE; e += blockDim.x) tab[e] = tsrc[e];
   const double* tcp = tab + FSEG_CP;
   const double* tinv = tab + FSEG_INV;
   const int line = grp * 64 + lane;
@@ -812,14 +818,15 @@ __global__ void __launch_bounds__(64 * FSEG_SMAX) k_grad_c4_seg(const Prob* __re
   const size_t lb = act ? (size_t)(line % P.N[o1]) * P.s[o1] + (size_t)(line / P.N[o1]) * P.s[o2] : 0;
   // line position of window slot i: the rows j0 .. j0 + L + 1 around this segment's rows
   // j0 + 1 .. j0 + L (bounded), the interior nodes j0 - 1 .. j0 + L wrapped (periodic)
-  auto pos = [&](int i) { return periodic ? g + wrap(j0 + i - 1, n) : j0 + i; };
+  constexpr int WX = C6 ? 4 : 2;   // window slots beyond the segment's rows
+  auto pos = [&](int i) { return periodic ? g + wrap(j0 + i - WX / 2, n) : j0 + i; };
   // w[i] = f at pos(i); after row i, w[i] (no longer read) holds the forward value, then y_i
-  double w[LM + 2];
+  double w[LM + WX];
   double d0 = 0.0, dN = 0.0;   // the decoupled end rows of a bounded line
   if (act) {
 #pragma unroll
-    for (int i = 0; i < LM + 2; ++i)
-      if (i < L + 2) prims_q<1>(Q, T, lb + (size_t)pos(i) * sd, gm1, q, &w[i]);
+    for (int i = 0; i < LM + WX; ++i)
+      if (i < L + WX) prims_q<1>(Q, T, lb + (size_t)pos(i) * sd, gm1, q, &w[i]);
     if (!periodic && s == 0) d0 = (-3.0 * w[0] + 4.0 * w[1] - w[2]) / 2.0;
   }
   __syncthreads();   // tables in LDS
@@ -829,7 +836,7 @@ __global__ void __launch_bounds__(64 * FSEG_SMAX) k_grad_c4_seg(const Prob* __re
 #pragma unroll
     for (int i = 0; i < LM; ++i) {
       if (i < L) {
-        double r = 0.75 * (w[i + 2] - w[i]);
+        double r = C6 ? C6_A * (w[i + 3] - w[i + 1]) + C6_B * (w[i + 4] - w[i]) : 0.75 * (w[i + 2] - w[i]);
         const int j = j0 + i;
         if (!periodic && j == 0) r = r - al * d0;
         if (!periodic && j == m - 1) {   // rows N-3 .. N-1 are slots i .. i + 2 here
@@ -1999,6 +2006,12 @@ void launch_grad_c6(const Launch& L, StateRef ref, int d) {
   const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
   const SysLaunch sl = sys_launch(L, TK_GRAD6, d);
   if (d == 0 && L.c6gpart) launch_grad_part<R, true>(L, ref, -1, 0);
+  if (d > 0 && L.c6gseg[d] > 0) {   // periodic lines in register segments: 64 lines x one primitive per workgroup
+    const long long groups = (L.lines[d] + 63) / 64;
+    LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL((k_grad_c4_seg<R, FSEG_LM, true>), dim3((unsigned)(5 * groups), L.nprob),
+                                               dim3(64 * L.c6gseg[d]), 0, L.stream, L.probs, ref, d, -1, 0,
+                                               L.tile_mask));
+  }
   if (sl.tiles)
     launch_tiles<R, TK_GRAD6>(L, KC_GRAD_C4, L.max_N[d], L.max_N[o1], L.max_N[o2],
                               TileArgs{ref, RKRef{nullptr, nullptr, nullptr}, d, 1, 0, 0, 0, L.tile_mask, -1, 0.0, 0.0, 0});
@@ -2165,7 +2178,7 @@ void launch_grad_c4_seg(const Launch& L, StateRef ref, int d, int skip_if_any, i
   if (L.c4seg[d] <= 0) return;
   // 64 lines x one primitive per workgroup, one wave per segment
   const long long groups = (L.lines[d] + 63) / 64;
-  LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL((k_grad_c4_seg<R, FSEG_LM>), dim3((unsigned)(5 * groups), L.nprob),
+  LG_TIMED(L, KC_GRAD_C4, hipLaunchKernelGGL((k_grad_c4_seg<R, FSEG_LM, false>), dim3((unsigned)(5 * groups), L.nprob),
                                              dim3(64 * L.c4seg[d]), 0, L.stream, L.probs, ref, d, skip_if_any,
                                              dense_only, L.tile_mask));
 }

@@ -578,6 +578,10 @@ void fill_launch(Launch& L, const Prob& P) {
           L.c6fpart = 1;
           continue;
         }
+        if (k == lg::TK_GRAD6 && lg::c6g_seg_use(P, d, L.tile_mask)) {
+          L.c6gseg[d] = std::max(L.c6gseg[d], lg::fseg_count(P.n[d]));
+          continue;
+        }
         if (k == lg::TK_FACES && lg::c6f_seg_use(P, d, L.tile_mask)) {
           L.c6fseg[d] = std::max(L.c6fseg[d], lg::fseg_count(lg::c6f_seg_unknowns(P, d)));
           continue;
@@ -922,6 +926,8 @@ lg_status lg_create(lg_ctx** out, const lg_grid* grid, const double* node_metric
       P.pcrc[d] = upload(periodic ? pcr_table_ac(pa, pc, true, lg::LG_PCR_STEPS)
                                   : pcr_table_ac(fa, fc, false, lg::LG_PCR_STEPS));
       if (d == 0 && !periodic && N - 2 >= 128 && N - 2 <= 2048) P.c6gz = upload(c6_grad_woodbury_table(N - 2));
+      if (d > 0 && periodic && lg::fseg_count(n) <= lg::C6FSEG_SMAX && n >= 16)
+        P.c6gsegt[d] = upload(fseg_table(n, a3, true));
       const int mf = periodic ? n : n - 1;   // faces solved (c6f_seg_unknowns)
       if (d > 0 && lg::fseg_count(mf) <= lg::C6FSEG_SMAX && mf >= 16) P.c6fsegt[d] = upload(fseg_table(mf, a3, periodic));
     }
@@ -1181,7 +1187,7 @@ lg_status lg_set_line_tiles(lg_ctx* c, int mask) {
     c->L.c4_rest_pcr[d] = c->L.c4_rest_thomas[d] = 0;
   }
   c->L.fpart = c->L.c4part = c->L.c6fpart = c->L.c6gpart = 0;
-  for (int d = 0; d < 3; ++d) c->L.fseg[d] = c->L.c4seg[d] = c->L.c6fseg[d] = 0;
+  for (int d = 0; d < 3; ++d) c->L.fseg[d] = c->L.c4seg[d] = c->L.c6fseg[d] = c->L.c6gseg[d] = 0;
   fill_launch(c->L, c->hp);
   return LG_OK;
 }

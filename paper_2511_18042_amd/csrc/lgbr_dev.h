@@ -83,6 +83,7 @@ struct Prob {
   const double* c4segt[3];  // MIG4 gradients along eta / zeta by register segments (k_grad_c4_seg tables)
   const double* c6fsegt[3]; // LAD-C6 interface fluxes along eta / zeta by register segments (k_c6_faces_seg tables)
   const double* c6gz;       // LAD-C6 gradients along xi by the partition method: z_0 [64], (I - W)^{-1} [4]
+  const double* c6gsegt[3]; // LAD-C6 gradients of periodic eta / zeta lines by register segments (k_grad_c4_seg tables)
   // device scalars
   double* dt;
   double* t;

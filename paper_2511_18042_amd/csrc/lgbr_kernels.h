@@ -125,6 +125,7 @@ struct Launch {
   int c6gpart;             // some problem solves its LAD-C6 gradients along xi by the partition method
   int c4seg[3];            // most segments per line of the problems solving MIG4 gradients along d in k_grad_c4_seg (0: none)
   int c6fseg[3];           // most segments per line of the problems solving LAD-C6 faces along d in k_c6_faces_seg (0: none)
+  int c6gseg[3];           // most segments per line of the problems solving LAD-C6 gradients along d in k_grad_c4_seg (0: none)
   int fseg[3];             // most segments per line of the problems filtering along d by k_filter_seg (0: none)
   Prof* prof;              // optional launch timing (null: off)
 };
@@ -385,6 +386,15 @@ __host__ __device__ inline bool c4_seg_use(const Prob& P, int d, int mask) {
 constexpr int C6FSEG_SMAX = 4;
 __host__ __device__ inline int c6f_seg_unknowns(const Prob& P, int d) {
   return P.bc[d][0] == BC_PERIODIC ? P.n[d] : P.n[d] - 1;
+}
+// LAD-C6 gradients of periodic eta / zeta lines of 16 to 256 interior nodes in register
+// segments (k_grad_c4_seg with the cyclic [1/3, 1, 1/3] tables), where the LDS tiles do not
+// take the direction, unless mask bit 14 is set
+__host__ __device__ inline bool c6g_seg_use(const Prob& P, int d, int mask) {
+  if ((mask & TILE_MASK_NO_SEG) || d == 0 || d >= P.ndim || !P.c6gsegt[d] || P.bc[d][0] != BC_PERIODIC ||
+      tile_use(P, d, TK_GRAD6, mask))
+    return false;
+  return fseg_count(P.n[d]) <= C6FSEG_SMAX && P.n[d] >= 16;
 }
 __host__ __device__ inline bool c6f_seg_use(const Prob& P, int d, int mask) {
   if ((mask & TILE_MASK_NO_SEG) || d == 0 || d >= P.ndim || !P.c6fsegt[d] || tile_use(P, d, TK_FACES, mask))

@@ -11,7 +11,9 @@ faces along eta and zeta.
 Cases: one segment (44 faces), three with a FIXED face, four (250 faces, and 256: the
 longest line), periodic lines of 16 (one segment wrapping onto itself) and 200 faces, a 3D
 curvilinear block with bounded eta and periodic zeta lines of 17 faces, and lines of 15 and
-299 faces, which stay on the lane-per-line kernel."""
+299 faces, which stay on the lane-per-line kernel.  The LAD-C6 gradients of periodic lines
+of 16 to 256 nodes take the same register segments (the cyclic [1/3, 1, 1/3] system); they
+are checked the same way, with the tiles of the gradients turned off too."""
 import numpy as np
 import pytest
 
@@ -146,3 +148,57 @@ def test_c6_face_segments_rk3_mixed():
     rel = _rel(outs[0][inner], outs[1][inner])
     print('mixed rk3 segments vs one lane per line', rel.tolist(), flush=True)
     assert rel.max() <= 1e-5
+
+
+# LAD-C6 gradients of periodic eta / zeta lines in register segments (k_grad_c4_seg with the
+# cyclic [1/3, 1, 1/3] tables): no LDS tiles for the gradients and faces along eta / zeta
+GSEG_ON = 0xFFF & ~((1 << 1) | (1 << 2) | (1 << 4) | (1 << 5))
+GSEG_OFF = GSEG_ON | 0x4000
+
+
+@pytest.mark.parametrize('name', ['y16_periodic', 'y200_periodic', '3d_curv', 'y300'])
+def test_c6_gradient_segments_rhs_fp64(name):
+    """Periodic lines of 16 (one segment wrapping onto itself), 200 (four) and 17 nodes (the
+    3D block's zeta); the bounded 300-node line stays on one lane per line."""
+    print('c6 gradient segments rhs', name, flush=True)
+    c = CASES[name]()
+    gas, opts = _gas(c), _opts()
+    g = U.oracle_grid(c)
+    ref = orhs.rhs(c.Q, g, gas, opts, 'lad')
+    outs = []
+    for mask in (GSEG_ON, GSEG_OFF):
+        ctx, _ = U.gpu_context(c, gas, opts)
+        ctx.set_line_tiles(mask)
+        out = U.gpu_rhs(ctx, c, 'lad')
+        ctx.close()
+        U.compare(out, ref, g, U.RHS_RTOL, label='c6 gradient seg %s mask %#x' % (name, mask))
+        outs.append(out)
+    inner = (slice(None),) + g.interior()
+    rel = _rel(outs[0][inner], outs[1][inner])
+    print('gradient segments vs one lane per line', rel.tolist(), flush=True)
+    assert rel.max() <= 1e-11
+
+
+def test_c6_gradient_segments_rk3_fp64():
+    """Two RK3 steps of the 3D block with the gradient and face segments (ghost images of
+    the periodic zeta gradients included) against the oracle."""
+    torch = U.torch_mod()
+    c = CASES['3d_curv']()
+    gas, opts = _gas(c), _opts()
+    g = U.oracle_grid(c)
+    M = ogrid.node_metrics(g)
+    Q, t = c.Q, 0.0
+    for _ in range(2):
+        Q, t, dt, bad = orhs.rk3_step(Q, t, 10.0, g, gas, opts, 'lad', M)
+        assert bad == 0
+    ctx, _ = U.gpu_context(c, gas, opts)
+    ctx.set_line_tiles(GSEG_ON)
+    Qd = U.dev(c.Q)
+    td = torch.zeros(1, dtype=torch.float64, device='cuda')
+    for _ in range(2):
+        ctx.rk3_step('lad', Qd, 10.0, td)
+    torch.cuda.synchronize()
+    assert ctx.poll_status() == 0
+    assert abs(td.item() - t) <= 1e-13 * t
+    U.compare(Qd.cpu().numpy(), Q, g, U.STAGE_RTOL, label='c6 gradient seg rk3')
+    ctx.close()
