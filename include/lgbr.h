@@ -281,7 +281,8 @@ lg_status lg_get_tile_shape(const lg_ctx* ctx, int* zm_width, int* line_batch);
  * in tiles are solved in register segments of at most 64 unknowns joined the same way (64
  * lines and one variable per workgroup) unless bit 14 is set: the filter and the MIG4
  * gradients on lines of 16 to 512 unknowns, the LAD-C6 interface fluxes on lines of 16 to
- * 256 faces; one lane per line otherwise.  mask in
+ * 256 faces and the LAD-C6 gradients on periodic lines of 16 to 256 nodes; one lane per
+ * line otherwise.  mask in
  * [0, 32767]; -1 restores the default (4095: tiles allowed, bits 12 to 14 clear).
  * lg_get_line_tiles returns the mask in effect (-1 for a null context).  Applies to later
  * calls and to batches created afterwards. */
