@@ -953,7 +953,8 @@ def kernel_class(name):
              ('k_zero_any', 'flags'), ('k_any_flag', 'flags'), ('k_all_flag', 'flags'), ('k_switch_count', 'flags'),
              ('k_dilate', 'flags'), ('k_line_list', 'flags'), ('k_hyb_queue', 'flags'),
              ('k_grad_explicit', 'grad_e6'), ('k_grad_c4', 'grad_c4'), ('k_grad_c6', 'grad_c4'),
-             ('k_grad_part', 'grad_c4'), ('k_c6_seg_check', 'combine'),
+             ('k_grad_part', 'grad_c4'), ('k_c6_seg_check', 'combine'), ('k_rk4_combine', 'combine'),
+             ('k_gbr_queue', 'flags'),
              ('k_sensor', 'sensor'), ('k_gbr_viscflux', 'visc'), ('k_lad_shear', 'lad_node'),
              ('k_lad_raw', 'lad_raw'), ('k_gauss', 'gauss'), ('k_lad_nodeflux', 'lad_flux'),
              ('k_sweep_x', 'sweep_x'), ('k_sweep_s', 'sweep_yz'), ('k_dt_', 'dt'), ('k_lad_sweep', 'lad_sweep'),
